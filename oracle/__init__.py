@@ -1,0 +1,191 @@
+"""CPU oracle for the (alpha,beta)-core method -- TEST INFRASTRUCTURE.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path never calls it.
+
+The arithmetic lives in ``abcore_oracle.c`` (plain sequential C, no shared
+code with the device library); this module marshals arrays and adds the
+compositions the paper defines in terms of those routines:
+
+* ``compute``      -- Problem 1 (Sec. III): vertex set of the (alpha,beta)-core.
+* ``core_numbers`` -- Definition 2.
+* ``components``   -- connected components (Sec. V preprocessing).
+* ``gfq_stream``   -- Problem 2 (Sec. III) / GFQ (Sec. V): after each edge
+  update, membership of the updated edge's endpoints in the core of the
+  updated graph, by full recomputation on that graph.
+* ``pack``         -- the membership bitmask layout (bit x of word x // 32,
+  least significant bit first; unified ids, lower vertex v is nU + v).
+
+Every function here has a pin in ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build() -> str:
+    """Compile ``abcore_oracle.c`` into ``liboracle.so`` (always recompiles)."""
+    global _lib
+    tmp = _LIB_PATH + ".tmp"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
+                    os.path.join(_HERE, "abcore_oracle.c"), "-o", tmp], check=True)
+    os.replace(tmp, _LIB_PATH)
+    _lib = None
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.or_build_csr.restype = ctypes.c_int64
+    lib.or_build_csr.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, vp, vp, vp, vp]
+    lib.or_peel.restype = ctypes.c_int
+    lib.or_peel.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_int64,
+                            ctypes.c_int64, vp, vp]
+    lib.or_core_numbers.restype = ctypes.c_int
+    lib.or_core_numbers.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+    lib.or_components.restype = ctypes.c_int
+    lib.or_components.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class Graph:
+    """Host CSR of a bipartite graph in unified ids (upper first)."""
+
+    def __init__(self, n_upper: int, n_lower: int, eu, ev):
+        eu = np.ascontiguousarray(eu, np.int32)
+        ev = np.ascontiguousarray(ev, np.int32)
+        self.n_upper = int(n_upper)
+        self.n_lower = int(n_lower)
+        self.n = self.n_upper + self.n_lower
+        self.off = np.zeros(self.n + 1, np.int64)
+        cols = np.zeros(max(1, 2 * len(eu)), np.int32)
+        md = _load().or_build_csr(self.n_upper, self.n_lower, len(eu), _ptr(eu), _ptr(ev),
+                                  _ptr(self.off), _ptr(cols))
+        if md < 0:
+            raise ValueError("edge id out of range")
+        self.m = int(md)
+        self.cols = cols[: 2 * self.m].copy()
+
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.off)
+
+    def edges(self):
+        """Distinct edges as (upper index, lower index), sorted."""
+        u = np.repeat(np.arange(self.n_upper, dtype=np.int32),
+                      np.diff(self.off[: self.n_upper + 1]))
+        v = self.cols[: self.m] - self.n_upper
+        return u, v.astype(np.int32)
+
+
+def peel(g: Graph, alpha: int, beta: int):
+    """(alpha,beta)-core membership (bool per unified id) and peel stats."""
+    member = np.zeros(max(1, g.n), np.uint8)
+    st = np.zeros(4, np.int64)
+    rc = _load().or_peel(g.n_upper, g.n_lower, _ptr(g.off), _ptr(g.cols), int(alpha),
+                         int(beta), _ptr(member), _ptr(st))
+    if rc != 0:
+        raise MemoryError("oracle peel failed")
+    stats = dict(removed=int(st[0]), removed_degree_sum=int(st[1]), m_peeled=int(st[2]),
+                 rounds=int(st[3]))
+    return member[: g.n].astype(bool), stats
+
+
+def compute(g: Graph, alpha: int, beta: int) -> np.ndarray:
+    return peel(g, alpha, beta)[0]
+
+
+def core_numbers(g: Graph) -> np.ndarray:
+    core = np.zeros(max(1, g.n), np.int32)
+    if _load().or_core_numbers(g.n_upper, g.n_lower, _ptr(g.off), _ptr(g.cols),
+                               _ptr(core)) != 0:
+        raise MemoryError("oracle core numbers failed")
+    return core[: g.n]
+
+
+def components(g: Graph) -> np.ndarray:
+    comp = np.zeros(max(1, g.n), np.int32)
+    if _load().or_components(g.n_upper, g.n_lower, _ptr(g.off), _ptr(g.cols),
+                             _ptr(comp)) != 0:
+        raise MemoryError("oracle components failed")
+    return comp[: g.n]
+
+
+def pack(member: np.ndarray) -> np.ndarray:
+    """Membership bitmask: bit (x % 32) of word x // 32, LSB first, padding 0."""
+    member = np.asarray(member, bool)
+    nwords = (len(member) + 31) // 32
+    bits = np.zeros(nwords * 32, np.uint8)
+    bits[: len(member)] = member
+    return np.packbits(bits, bitorder="little").view("<u4").astype(np.uint32)
+
+
+def unpack(words: np.ndarray, n: int) -> np.ndarray:
+    b = np.unpackbits(np.asarray(words, "<u4").view(np.uint8), bitorder="little")
+    return b[:n].astype(bool)
+
+
+def gfq_stream(n_upper: int, n_lower: int, eu, ev, updates, check_only=None):
+    """GFQ by recomputation (Problem 2 of Sec. III; procedure of Sec. V).
+
+    ``updates`` holds arrays u, v, op (+1 insert, -1 delete), alpha, beta.
+    Updates are cumulative: query i is answered on the graph after updates
+    0..i.  An insertion of a present edge or a deletion of an absent edge is
+    rejected and leaves the graph unchanged (status 'EEXIST' / 'ENOENT').
+    Returns per-update (status, answer, endpoint_bits) where answer is
+    member(u) and member(nU + v) in the (alpha,beta)-core of the updated graph
+    and endpoint_bits = member(u) | member(nU + v) << 1.
+    ``check_only`` (optional set of indices) limits the recomputations to those
+    updates; the others are applied without a peel and reported as None.
+    """
+    nL = int(n_lower)
+    present = set((int(a) * nL + int(b)) for a, b in zip(np.asarray(eu), np.asarray(ev)))
+    out = []
+    for i in range(len(updates["u"])):
+        u, v, op = int(updates["u"][i]), int(updates["v"][i]), int(updates["op"][i])
+        key = u * nL + v
+        if op > 0:
+            if key in present:
+                out.append(("EEXIST", None, None))
+                continue
+            present.add(key)
+        else:
+            if key not in present:
+                out.append(("ENOENT", None, None))
+                continue
+            present.discard(key)
+        if check_only is not None and i not in check_only:
+            out.append(("OK", None, None))
+            continue
+        keys = np.fromiter(present, np.int64, len(present))
+        g = Graph(n_upper, n_lower, (keys // nL).astype(np.int32), (keys % nL).astype(np.int32))
+        member = compute(g, int(updates["alpha"][i]), int(updates["beta"][i]))
+        bu, bv = bool(member[u]), bool(member[n_upper + v])
+        out.append(("OK", bu and bv, int(bu) | (int(bv) << 1)))
+    return out
+
+
+def timed_peel(g: Graph, alpha: int, beta: int):
+    """Wall-clock seconds of one oracle peel (single thread) and its stats."""
+    t0 = time.perf_counter()
+    _, stats = peel(g, alpha, beta)
+    return time.perf_counter() - t0, stats

@@ -1,0 +1,57 @@
+"""Brute-force definitions used to pin the oracle on tiny graphs.
+
+These enumerate vertex subsets directly from Definition 1 and Definition 2 of
+the paper; they are exponential and only run for n <= 14.
+"""
+from __future__ import annotations
+
+
+def adjacency_masks(n_upper, n_lower, edges):
+    n = n_upper + n_lower
+    adj = [0] * n
+    for u, v in edges:
+        adj[u] |= 1 << (n_upper + v)
+        adj[n_upper + v] |= 1 << u
+    return adj
+
+
+def feasible(S, adj, n_upper, alpha, beta):
+    """Every upper member has >= alpha neighbours in S, lower >= beta."""
+    x = S
+    while x:
+        low = x & -x
+        i = low.bit_length() - 1
+        thr = alpha if i < n_upper else beta
+        if bin(adj[i] & S).count("1") < thr:
+            return False
+        x ^= low
+    return True
+
+
+def core_by_enumeration(n_upper, n_lower, edges, alpha, beta):
+    """Definition 1: the union of all feasible vertex subsets (feasibility is
+    closed under union, so the union is the unique maximal one)."""
+    n = n_upper + n_lower
+    adj = adjacency_masks(n_upper, n_lower, edges)
+    union = 0
+    for S in range(1, 1 << n):
+        if S | union == union:
+            continue  # adds nothing new
+        if feasible(S, adj, n_upper, alpha, beta):
+            union |= S
+    return [bool(union >> i & 1) for i in range(n)]
+
+
+def core_numbers_by_enumeration(n_upper, n_lower, edges):
+    """Definition 2: largest delta with the vertex in the (delta,delta)-core."""
+    n = n_upper + n_lower
+    core = [0] * n
+    delta = 1
+    while True:
+        mem = core_by_enumeration(n_upper, n_lower, edges, delta, delta)
+        if not any(mem):
+            return core
+        for i in range(n):
+            if mem[i]:
+                core[i] = delta
+        delta += 1
