@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark: (alpha,beta)-core peeling on one MI355X.
+
+Workload: seeded Chung-Lu bipartite graph with |U| = 1,000,000,
+|L| = 500,000, 20,000,000 distinct edges, degree-distribution exponent 2.1 on
+both layers, expected degrees capped at 50,000; query (alpha,beta) = (10,10).
+One step = one GCC query (Algorithm 1: scan, peel rounds, bitmask pack) on
+the resident graph.  GCC+ (Algorithm 2) on the same query and its core-number
+preprocessing are timed separately and reported as extra fields, like the
+paper's Table II separates preprocessing from query time.
+
+Metric: edges peeled per second = (m - |E(core)|) / step time, with the
+numerator taken from the CPU oracle so it does not depend on the GPU code.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def _cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return platform.processor()
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="approximate CPU time spent on the oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--peel-mode", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import bigraph_gen
+    import paper_2606_07148_amd as pkg
+
+    if not os.path.exists(pkg.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    pkg.load()
+
+    spec = bigraph_gen.CONFIGS[2]
+    alpha = beta = 10
+    nU, nL = spec["n_upper"], spec["n_lower"]
+    n = nU + nL
+    t0 = time.perf_counter()
+    eu, ev = bigraph_gen.make_graph(spec)
+    gen_s = time.perf_counter() - t0
+    print(f"# generated {len(eu)} edges in {gen_s:.1f}s", file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    deu = torch.from_numpy(eu).cuda()
+    dev = torch.from_numpy(ev).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = pkg.abcore_build_csr(nU, nL, deu, dev)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    del deu, dev
+    if args.peel_mode:
+        pkg.abcore_set_option(g, pkg.ABCORE_OPT_PEEL_MODE, args.peel_mode)
+
+    # --- oracle: numerators of the metric and the CPU baseline ------------
+    import oracle
+    ref = oracle.Graph(nU, nL, eu, ev)
+    deg = ref.degrees()
+    reps, cpu_t = 0, 0.0
+    stats_o = None
+    member = None
+    while True:
+        t0 = time.perf_counter()
+        member, stats_o = oracle.peel(ref, alpha, beta)
+        cpu_t += time.perf_counter() - t0
+        reps += 1
+        if args.no_cpu_baseline or cpu_t >= args.cpu_seconds:
+            break
+    m_peeled = stats_o["m_peeled"]
+    removed = stats_o["removed"]
+    sum_deg_removed = stats_o["removed_degree_sum"]
+    want = oracle.pack(member)
+
+    # --- GPU: GCC timed region -------------------------------------------
+    out = torch.empty(max(1, g.nwords), dtype=torch.int32, device="cuda")
+    for _ in range(args.warmup):
+        pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)[: len(want)]
+    parity = bool(np.array_equal(got, want))
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_TIMING, 1)
+    pkg.abcore_peel_timing(g, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    peel_ms, peel_launches = pkg.abcore_peel_timing(g, reset=True)
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_TIMING, 0)
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = m_peeled / (ms_per_step / 1e3)
+
+    # algorithmic bytes of the peel phase for one query: offsets (16 B) and
+    # row (4 B per entry) of every removed vertex, plus one 4-byte
+    # read-modify-write per peeled edge endpoint decrement (8 B)
+    peel_bytes = 16 * removed + 4 * sum_deg_removed + 8 * m_peeled
+    step_bytes = 8 * n + n // 8 + peel_bytes
+    launches_per_step = peel_launches / args.steps
+    avg_launch_s = peel_ms / 1e3 / max(1, peel_launches)
+    bytes_per_launch = peel_bytes / max(1e-9, launches_per_step)
+    achieved = bytes_per_launch / avg_launch_s / 1e9 if peel_ms > 0 else 0.0
+
+    # --- GCC+ (Algorithm 2): preprocessing + query ------------------------
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, max_core = pkg.abcore_core_numbers(g)
+    torch.cuda.synchronize()
+    prep_ms = (time.perf_counter() - t0) * 1e3
+    for _ in range(args.warmup):
+        pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC_PLUS, out=out)
+    torch.cuda.synchronize()
+    plus_parity = bool(np.array_equal(out.cpu().numpy().view(np.uint32)[: len(want)], want))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC_PLUS, out=out)
+    torch.cuda.synchronize()
+    plus_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    result = {
+        "metric": "edges peeled/sec",
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic: seeded Chung-Lu bipartite graph (bigraph_gen config 2)",
+        "config": {
+            "workload": "chung-lu |U|=1,000,000 |L|=500,000 m=20,000,000 gamma=2.1/2.1 "
+                        "cap=50,000; (alpha,beta)=(10,10); GCC",
+            "n_upper": nU, "n_lower": nL, "m": int(ref.m), "alpha": alpha, "beta": beta,
+            "algo": "GCC", "seed": spec["seed"],
+            "edge_sha256": bigraph_gen.edge_hash(eu, ev),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "peel_round_kernel<GCC>",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_launch": bytes_per_launch,
+            "avg_launch_us": avg_launch_s * 1e6,
+            "launches_per_step": launches_per_step,
+        },
+        "parity": parity,
+        "m_peeled": m_peeled,
+        "removed": removed,
+        "rounds": stats_o["rounds"],
+        "step_algorithmic_bytes": step_bytes,
+        "step_gbs": step_bytes / (ms_per_step / 1e3) / 1e9,
+        "input_edges_per_s": ref.m / (ms_per_step / 1e3),
+        "gcc_plus": {"ms_per_query": plus_ms, "parity": plus_parity,
+                     "edges_peeled_per_s": m_peeled / (plus_ms / 1e3),
+                     "core_preprocessing_ms": prep_ms, "max_core": max_core},
+        "build_s": build_s,
+    }
+    if not args.no_cpu_baseline:
+        per = cpu_t / reps
+        result["cpu_baseline"] = {
+            "value": m_peeled / per, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} single-threaded oracle peels of the full config-2 graph at "
+                      f"(10,10), {per * 1e3:.1f} ms each (CSR build excluded)",
+            "host_cpu": _cpu_model(), "host_nproc": os.cpu_count(),
+        }
+    print(json.dumps(result), flush=True)
+    g.destroy()
+    return 0 if (parity and plus_parity) else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,164 @@
+/*
+ * abcore.h -- C ABI of libabcore, (alpha,beta)-core computation and
+ * on-the-fly edge queries on bipartite graphs, for AMD Instinct MI355X
+ * (gfx950).  Method: Feng et al., "Efficient (alpha,beta)-core Computation
+ * and On-the-fly Query at Billion Scale with GPUs".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Vertices use unified ids (Sec. IV-A): upper vertex u is id u in
+ *    [0, n_upper); lower vertex v is id n_upper + v.  Edge endpoints in the
+ *    API are given per layer: u in [0, n_upper), v in [0, n_lower).
+ *  - Membership bitmasks are arrays of ceil(n/32) uint32 words in DEVICE
+ *    memory owned by the caller; bit (x % 32) of word x / 32 (least
+ *    significant bit first) is 1 iff vertex x belongs to the result.  Padding
+ *    bits past n are written as 0.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it; calls documented as synchronous also wait for it.
+ *  - Every entry point returns an abcore_status and never throws.  On any
+ *    error no state changes: a rejected update is not applied.  The message
+ *    of the last error of the calling thread is abcore_last_error().
+ *  - A handle is not thread-safe: calls on one handle must be serialised by
+ *    the caller.  Handles own all of their device memory.
+ *  - All arithmetic is integer; results are exact and independent of thread
+ *    scheduling (the (alpha,beta)-core is unique, Definition 1).
+ */
+#ifndef ABCORE_H
+#define ABCORE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct abcore_graph_s *abcore_graph;
+
+typedef enum {
+  ABCORE_OK = 0,
+  ABCORE_EINVAL = 1,  /* bad argument: null pointer, id out of range, alpha or beta 0 */
+  ABCORE_ENOMEM = 2,  /* device or host allocation failed */
+  ABCORE_EDEVICE = 3, /* a HIP call failed */
+  ABCORE_ENOENT = 4,  /* deletion of an edge that is not present */
+  ABCORE_EEXIST = 5,  /* insertion of an edge that is already present */
+  ABCORE_EBUSY = 6    /* no admission slot free (serving) */
+} abcore_status;
+
+/* Algorithms of Sec. IV. */
+enum { ABCORE_GCC = 0, ABCORE_GCC_PLUS = 1 };
+
+/* Counters of one computation (filled when a stats pointer is passed; that
+ * forces a synchronisation of the stream). */
+typedef struct {
+  int64_t removed;        /* vertices removed by peeling (|R|) */
+  int64_t rounds;         /* peel rounds (frontier generations) */
+  int64_t entries_read;   /* adjacency entries read by the peel */
+  int64_t initial;        /* vertices in the first frontier (scan phase) */
+  int64_t uncertain;      /* GCC+: vertices with delta_l <= core < delta_q */
+  int64_t launches;       /* kernels launched for the peel phase */
+} abcore_stats;
+
+/* One edge update for the on-the-fly query (Problem 2, Sec. III). */
+typedef struct {
+  int32_t u;  /* upper index in [0, n_upper) */
+  int32_t v;  /* lower index in [0, n_lower) */
+  int32_t op; /* +1 insertion, -1 deletion */
+} abcore_edge_update;
+
+/* Message describing the last error on this thread ("" if none). */
+const char *abcore_last_error(void);
+
+/* Graph construction (Sec. III: CSR storage; Sec. IV-A: unified ids).
+ * d_eu, d_ev: DEVICE arrays of m int32 endpoints (u in [0,n_upper), v in
+ * [0,n_lower)), read during the call and not retained.  Duplicate pairs are
+ * removed (the edge set E is a set).  Builds one CSR over unified ids holding
+ * both adjacencies, rows sorted ascending.  Requires n_upper, n_lower >= 0,
+ * n_upper + n_lower < 2^31 and m < 2^31.  Synchronous.
+ * out: receives the handle.  out_m_distinct (nullable): distinct edge count.
+ * Errors: EINVAL (null pointer, negative size, id out of range), ENOMEM,
+ * EDEVICE. */
+abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *d_eu,
+                               const int32_t *d_ev, int64_t m, void *stream,
+                               abcore_graph *out, int64_t *out_m_distinct);
+
+/* Releases every resource of the handle.  NULL is accepted. */
+abcore_status abcore_destroy(abcore_graph g);
+
+/* Sizes: n_upper, n_lower and the current number of distinct edges. */
+abcore_status abcore_graph_info(abcore_graph g, int32_t *n_upper, int32_t *n_lower,
+                                int64_t *m);
+
+/* Copies the current CSR to DEVICE buffers: d_off (n+1 int64) and d_cols
+ * (2m int32), rows sorted ascending, edges inserted after the build included
+ * and deleted ones left out.  Either pointer may be NULL to only query
+ * *out_entries (= 2m).  Synchronous. */
+abcore_status abcore_export_csr(abcore_graph g, int64_t *d_off, int32_t *d_cols,
+                                int64_t *out_entries, void *stream);
+
+/* Problem 1 of Sec. III: the vertex set of the (alpha,beta)-core
+ * (Definition 1).  algo = ABCORE_GCC runs the scan and peel phases of
+ * Algorithm 1 (Sec. IV-A); ABCORE_GCC_PLUS runs Algorithm 2 (Sec. IV-B):
+ * core-number classification by Lemma 1, then the peel restricted to the
+ * vertices with min(alpha,beta) <= core < max(alpha,beta), whose degrees
+ * count only neighbours with core >= min(alpha,beta).  GCC+ computes and
+ * caches the core numbers on first use (abcore_core_numbers).
+ * alpha, beta >= 1 (EINVAL otherwise).  d_bitmask: DEVICE, ceil(n/32)
+ * words, every word written.  stats: nullable.  Asynchronous on `stream`
+ * unless stats is requested. */
+abcore_status abcore_compute(abcore_graph g, uint32_t alpha, uint32_t beta, int32_t algo,
+                             uint32_t *d_bitmask, abcore_stats *stats, void *stream);
+
+/* Core numbers (Definition 2): core(x) = largest delta with x in the
+ * (delta,delta)-core, 0 for isolated vertices.  Computed once per graph
+ * version and cached for GCC+.  d_core: DEVICE n int32, or NULL to only fill
+ * the cache.  max_core (nullable): largest core number (delta of Table I).
+ * Synchronous. */
+abcore_status abcore_core_numbers(abcore_graph g, int32_t *d_core, int32_t *max_core,
+                                  void *stream);
+
+/* Connected-component labels (GFQ preprocessing, Sec. V): label = smallest
+ * unified id in the component.  Maintained under updates by abcore_query.
+ * d_comp: DEVICE n int32 or NULL (only compute the labels).  Synchronous. */
+abcore_status abcore_components(abcore_graph g, int32_t *d_comp, void *stream);
+
+/* Problem 2 of Sec. III / GFQ (Sec. V).  Applies the update permanently,
+ * updates the component labels (union on insertion, re-labelling of the old
+ * component on deletion), peels only the component(s) holding u and v, and
+ * answers whether both endpoints belong to the (alpha,beta)-core of the
+ * updated graph (for an insertion this is membership of the edge, the core
+ * being an induced subgraph).  h_answer: HOST int32, 1 or 0.
+ * h_endpoint_bits (nullable, HOST): bit0 = u in core, bit1 = v in core.
+ * Errors: EINVAL (ids, op, alpha/beta 0), EEXIST (insertion of a present
+ * edge), ENOENT (deletion of an absent edge); the graph is unchanged on
+ * error.  Synchronous. */
+abcore_status abcore_query(abcore_graph g, abcore_edge_update upd, uint32_t alpha,
+                           uint32_t beta, int32_t *h_answer, uint32_t *h_endpoint_bits,
+                           void *stream);
+
+/* Tuning knobs (non-negative values; 0 restores the default).
+ *   ABCORE_OPT_PEEL_MODE : 1 = one kernel per peel round, host-checked in
+ *                          batches; 2 = persistent asynchronous worklist.
+ *   ABCORE_OPT_GRID      : workgroups per peel launch.
+ *   ABCORE_OPT_ROUNDS_PER_SYNC : round kernels enqueued between checks.
+ *   ABCORE_OPT_TIMING    : 1 = record a HIP event pair on the caller's stream
+ *                          around every launch (or batch of launches) of the
+ *                          peel kernel; read with abcore_peel_timing. */
+enum {
+  ABCORE_OPT_PEEL_MODE = 1,
+  ABCORE_OPT_GRID = 2,
+  ABCORE_OPT_ROUNDS_PER_SYNC = 3,
+  ABCORE_OPT_TIMING = 4
+};
+abcore_status abcore_set_option(abcore_graph g, int32_t option, int64_t value);
+
+/* Peel-kernel GPU time recorded while ABCORE_OPT_TIMING is on: *ms = summed
+ * elapsed time of the recorded event pairs, *launches = peel-kernel launches
+ * they bracket.  Waits for the recorded events.  reset != 0 clears both. */
+abcore_status abcore_peel_timing(abcore_graph g, double *ms, int64_t *launches,
+                                 int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABCORE_H */

@@ -1,0 +1,230 @@
+"""Python binding of libabcore: (alpha,beta)-core computation (GCC, GCC+) and
+on-the-fly edge queries (GFQ) on MI355X.
+
+Argument marshalling only: every step runs in the HIP kernels of
+``libabcore.so`` (built by ``paper_2606_07148_amd.build``).  Device buffers
+are torch CUDA tensors; the stream is torch's current stream unless given.
+Importing this package does not require a GPU, but every call does, and the
+package raises ``ImportError`` when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libabcore.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "abcore.h")
+
+ABCORE_GCC = 0
+ABCORE_GCC_PLUS = 1
+ABCORE_OPT_PEEL_MODE = 1
+ABCORE_OPT_GRID = 2
+ABCORE_OPT_ROUNDS_PER_SYNC = 3
+ABCORE_OPT_TIMING = 4
+
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOENT", 5: "EEXIST",
+          6: "EBUSY"}
+
+
+class AbcoreError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class abcore_stats(ctypes.Structure):
+    _fields_ = [("removed", ctypes.c_int64), ("rounds", ctypes.c_int64),
+                ("entries_read", ctypes.c_int64), ("initial", ctypes.c_int64),
+                ("uncertain", ctypes.c_int64), ("launches", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class abcore_edge_update(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_int32), ("v", ctypes.c_int32), ("op", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """The loaded library; ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libabcore.so not built ({LIB_PATH}); run "
+                          "`python -m paper_2606_07148_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    P = ctypes.POINTER
+    sig = {
+        "abcore_last_error": (ctypes.c_char_p, []),
+        "abcore_build_csr": (i32, [i32, i32, vp, vp, i64, vp, P(vp), P(i64)]),
+        "abcore_destroy": (i32, [vp]),
+        "abcore_graph_info": (i32, [vp, P(i32), P(i32), P(i64)]),
+        "abcore_export_csr": (i32, [vp, vp, vp, P(i64), vp]),
+        "abcore_compute": (i32, [vp, u32, u32, i32, vp, P(abcore_stats), vp]),
+        "abcore_core_numbers": (i32, [vp, vp, P(i32), vp]),
+        "abcore_components": (i32, [vp, vp, vp]),
+        "abcore_query": (i32, [vp, abcore_edge_update, u32, u32, P(i32), P(u32), vp]),
+        "abcore_set_option": (i32, [vp, i32, i64]),
+        "abcore_peel_timing": (i32, [vp, P(ctypes.c_double), P(i64), i32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def declared_symbols() -> list:
+    """Function names declared in include/abcore.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(abcore_[a-z_]+)\s*\(", text)))
+
+
+def _check(status: int):
+    if status != 0:
+        msg = load().abcore_last_error().decode(errors="replace")
+        raise AbcoreError(status, msg)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else None
+
+
+class Graph:
+    """Owns one abcore_graph handle."""
+
+    def __init__(self, handle, n_upper, n_lower, m):
+        self._h = handle
+        self.n_upper = n_upper
+        self.n_lower = n_lower
+        self.n = n_upper + n_lower
+        self.m = m
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("graph destroyed")
+        return self._h
+
+    @property
+    def nwords(self) -> int:
+        return (self.n + 31) // 32
+
+    def destroy(self):
+        if self._h is not None:
+            load().abcore_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def refresh(self):
+        nu, nl, m = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(load().abcore_graph_info(self.handle, ctypes.byref(nu), ctypes.byref(nl),
+                                        ctypes.byref(m)))
+        self.m = int(m.value)
+        return self
+
+
+def abcore_build_csr(n_upper: int, n_lower: int, eu, ev, stream=None) -> Graph:
+    """Build the device CSR from int32 CUDA tensors of endpoints."""
+    import torch
+    assert eu.dtype == torch.int32 and ev.dtype == torch.int32
+    assert eu.is_cuda and ev.is_cuda and eu.numel() == ev.numel()
+    eu = eu.contiguous()
+    ev = ev.contiguous()
+    h = ctypes.c_void_p()
+    md = ctypes.c_int64()
+    _check(load().abcore_build_csr(int(n_upper), int(n_lower), _ptr(eu), _ptr(ev),
+                                   int(eu.numel()), _stream(stream), ctypes.byref(h),
+                                   ctypes.byref(md)))
+    return Graph(h, int(n_upper), int(n_lower), int(md.value))
+
+
+def abcore_destroy(g: Graph) -> None:
+    g.destroy()
+
+
+def abcore_set_option(g: Graph, option: int, value: int) -> None:
+    _check(load().abcore_set_option(g.handle, int(option), int(value)))
+
+
+def abcore_peel_timing(g: Graph, reset: bool = True):
+    """(GPU milliseconds, launches) of the peel kernels recorded with
+    ABCORE_OPT_TIMING on."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(load().abcore_peel_timing(g.handle, ctypes.byref(ms), ctypes.byref(n), int(reset)))
+    return float(ms.value), int(n.value)
+
+
+def abcore_export_csr(g: Graph, stream=None):
+    """(off int64[n+1], cols int32[2m]) CUDA tensors of the current graph."""
+    import torch
+    ent = ctypes.c_int64()
+    _check(load().abcore_export_csr(g.handle, None, None, ctypes.byref(ent), None))
+    off = torch.empty(g.n + 1, dtype=torch.int64, device="cuda")
+    cols = torch.empty(max(1, int(ent.value)), dtype=torch.int32, device="cuda")
+    _check(load().abcore_export_csr(g.handle, _ptr(off), _ptr(cols), ctypes.byref(ent),
+                                    _stream(stream)))
+    return off, cols[: int(ent.value)]
+
+
+def abcore_compute(g: Graph, alpha: int, beta: int, algo: int = ABCORE_GCC, out=None,
+                   stats: bool = False, stream=None):
+    """Membership bitmask (int32 CUDA tensor of ceil(n/32) words, bit order
+    LSB-first) of the (alpha,beta)-core; with stats=True also the counters."""
+    import torch
+    if out is None:
+        out = torch.empty(max(1, g.nwords), dtype=torch.int32, device="cuda")
+    st = abcore_stats() if stats else None
+    _check(load().abcore_compute(g.handle, int(alpha), int(beta), int(algo), _ptr(out),
+                                 ctypes.byref(st) if st is not None else None,
+                                 _stream(stream)))
+    return (out, st.as_dict()) if stats else out
+
+
+def abcore_core_numbers(g: Graph, stream=None):
+    """(core int32 CUDA tensor[n], max core number)."""
+    import torch
+    core = torch.empty(max(1, g.n), dtype=torch.int32, device="cuda")
+    mx = ctypes.c_int32()
+    _check(load().abcore_core_numbers(g.handle, _ptr(core), ctypes.byref(mx), _stream(stream)))
+    return core[: g.n], int(mx.value)
+
+
+def abcore_components(g: Graph, stream=None):
+    import torch
+    comp = torch.empty(max(1, g.n), dtype=torch.int32, device="cuda")
+    _check(load().abcore_components(g.handle, _ptr(comp), _stream(stream)))
+    return comp[: g.n]
+
+
+def abcore_query(g: Graph, u: int, v: int, op: int, alpha: int, beta: int, stream=None):
+    """Apply one edge update and return (answer, endpoint_bits)."""
+    ans = ctypes.c_int32()
+    bits = ctypes.c_uint32()
+    upd = abcore_edge_update(int(u), int(v), int(op))
+    _check(load().abcore_query(g.handle, upd, int(alpha), int(beta), ctypes.byref(ans),
+                               ctypes.byref(bits), _stream(stream)))
+    g.m += int(op)
+    return bool(ans.value), int(bits.value)

@@ -1,0 +1,171 @@
+// Device construction of the unified CSR (Sec. III: CSR storage; Sec. IV-A:
+// contiguous ids, upper first).  Pairs are keyed (u*nL + v), radix-sorted
+// and deduplicated (E is a set); the sorted keys give the upper rows
+// directly, a second sort on (v*nU + u) gives the lower rows.  Both sorts use
+// rocPRIM's device radix sort through hipCUB; the build is preprocessing and
+// is not part of the timed peel.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+
+#include "abcore_internal.h"
+
+namespace abc {
+
+namespace {
+
+__global__ void validate_kernel(const int32_t *__restrict__ eu, const int32_t *__restrict__ ev,
+                                int64_t m, int32_t nU, int32_t nL, int32_t *bad) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int found = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    const int32_t u = eu[i], v = ev[i];
+    found |= (u < 0 || u >= nU || v < 0 || v >= nL);
+  }
+  if (__ballot(found) != 0 && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
+}
+
+__global__ void make_keys_kernel(const int32_t *__restrict__ eu, const int32_t *__restrict__ ev,
+                                 int64_t m, int32_t nL, uint64_t *__restrict__ keys) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
+    keys[i] = (uint64_t)(uint32_t)eu[i] * (uint64_t)nL + (uint64_t)(uint32_t)ev[i];
+}
+
+// Upper side: unique key i = (u, v) -> cols[i] = nU + v; degree counts; and
+// the transposed key (v*nU + u) for the lower rows.
+__global__ void upper_rows_kernel(const uint64_t *__restrict__ ukeys, int64_t md, int32_t nU,
+                                  int32_t nL, int32_t *__restrict__ cols,
+                                  int32_t *__restrict__ deg, uint64_t *__restrict__ tkeys) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < md; i += stride) {
+    const uint64_t k = ukeys[i];
+    const int32_t u = (int32_t)(k / (uint64_t)nL);
+    const int32_t v = (int32_t)(k % (uint64_t)nL);
+    cols[i] = nU + v;
+    atomicAdd(&deg[u], 1);
+    atomicAdd(&deg[(int64_t)nU + v], 1);
+    tkeys[i] = (uint64_t)(uint32_t)v * (uint64_t)nU + (uint64_t)(uint32_t)u;
+  }
+}
+
+__global__ void lower_rows_kernel(const uint64_t *__restrict__ lkeys, int64_t md, int32_t nU,
+                                  int32_t *__restrict__ cols) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < md; i += stride)
+    cols[md + i] = (int32_t)(lkeys[i] % (uint64_t)nU);
+}
+
+__global__ void widen_kernel(const int32_t *__restrict__ deg, int64_t n,
+                             int64_t *__restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += stride)
+    out[i] = i < n ? (int64_t)deg[i] : 0;
+}
+
+int bits_for(uint64_t maxkey) {
+  int b = 0;
+  while (b < 64 && (maxkey >> b) != 0) ++b;
+  return std::max(b, 1);
+}
+
+}  // namespace
+
+// Builds off/cols/deg0 of g (already sized: g.nU, g.nL, g.n set; arrays not
+// yet allocated).  Returns a status and sets the error message.
+abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, int64_t m,
+                               hipStream_t s) {
+#define BCHK(x)                                                                     \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess) {                                                         \
+      set_error("CSR build: %s failed: %s", #x, hipGetErrorString(e_));             \
+      status = (e_ == hipErrorOutOfMemory) ? ABCORE_ENOMEM : ABCORE_EDEVICE;        \
+      goto done;                                                                    \
+    }                                                                               \
+  } while (0)
+  abcore_status status = ABCORE_OK;
+  const int grid = std::max(1, std::min(g.cu_count * 8, (int)((m + 255) / 256)));
+  int32_t *d_bad = nullptr;
+  uint64_t *k0 = nullptr, *k1 = nullptr;
+  int *d_nsel = nullptr;
+  void *temp = nullptr;
+  size_t temp_bytes = 0, need = 0;
+  int64_t *deg64 = nullptr;
+  int32_t h_bad = 0;
+  int h_nsel = 0;
+  int64_t md = 0;
+  const int ubits = bits_for((uint64_t)std::max(g.nU, 1) * (uint64_t)std::max(g.nL, 1) - 1);
+  const int lbits = ubits;
+
+  BCHK(hipMalloc(&g.off, sizeof(int64_t) * (g.n + 1)));
+  BCHK(hipMalloc(&g.deg0, sizeof(int32_t) * std::max<int64_t>(g.n, 1)));
+  BCHK(hipMemsetAsync(g.deg0, 0, sizeof(int32_t) * std::max<int64_t>(g.n, 1), s));
+  if (m > 0) {
+    BCHK(hipMalloc(&d_bad, sizeof(int32_t)));
+    BCHK(hipMemsetAsync(d_bad, 0, sizeof(int32_t), s));
+    validate_kernel<<<grid, 256, 0, s>>>(eu, ev, m, g.nU, g.nL, d_bad);
+    BCHK(hipGetLastError());
+    BCHK(hipMemcpyAsync(&h_bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BCHK(hipStreamSynchronize(s));
+    if (h_bad) {
+      set_error("abcore_build_csr: edge endpoint out of range");
+      status = ABCORE_EINVAL;
+      goto done;
+    }
+    BCHK(hipMalloc(&k0, sizeof(uint64_t) * m));
+    BCHK(hipMalloc(&k1, sizeof(uint64_t) * m));
+    BCHK(hipMalloc(&d_nsel, sizeof(int)));
+    make_keys_kernel<<<grid, 256, 0, s>>>(eu, ev, m, g.nL, k0);
+    BCHK(hipGetLastError());
+    // temp storage large enough for the sort and the unique selection
+    BCHK(hipcub::DeviceRadixSort::SortKeys(nullptr, need, k0, k1, (int)m, 0, ubits, s));
+    temp_bytes = std::max(temp_bytes, need);
+    BCHK(hipcub::DeviceSelect::Unique(nullptr, need, k1, k0, d_nsel, (int)m, s));
+    temp_bytes = std::max(temp_bytes, need);
+    BCHK(hipMalloc(&temp, std::max<size_t>(temp_bytes, 16)));
+    BCHK(hipcub::DeviceRadixSort::SortKeys(temp, temp_bytes, k0, k1, (int)m, 0, ubits, s));
+    BCHK(hipcub::DeviceSelect::Unique(temp, temp_bytes, k1, k0, d_nsel, (int)m, s));
+    BCHK(hipMemcpyAsync(&h_nsel, d_nsel, sizeof(int), hipMemcpyDeviceToHost, s));
+    BCHK(hipStreamSynchronize(s));
+    md = h_nsel;
+  }
+  g.m_csr = md;
+  g.m = md;
+  BCHK(hipMalloc(&g.cols, sizeof(int32_t) * std::max<int64_t>(2 * md, 1)));
+  if (md > 0) {
+    const int gridm = std::max(1, std::min(g.cu_count * 8, (int)((md + 255) / 256)));
+    upper_rows_kernel<<<gridm, 256, 0, s>>>(k0, md, g.nU, g.nL, g.cols, g.deg0, k1);
+    BCHK(hipGetLastError());
+    BCHK(hipcub::DeviceRadixSort::SortKeys(temp, temp_bytes, k1, k0, (int)md, 0, lbits, s));
+    lower_rows_kernel<<<gridm, 256, 0, s>>>(k0, md, g.nU, g.cols);
+    BCHK(hipGetLastError());
+  }
+  BCHK(hipMalloc(&deg64, sizeof(int64_t) * (g.n + 1)));
+  {
+    const int gridn = std::max(1, std::min(g.cu_count * 8, (int)((g.n + 256) / 256)));
+    widen_kernel<<<gridn, 256, 0, s>>>(g.deg0, g.n, deg64);
+    BCHK(hipGetLastError());
+    need = 0;
+    BCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, deg64, g.off, (int)(g.n + 1), s));
+    if (need > temp_bytes) {
+      BCHK(hipFree(temp));
+      temp = nullptr;
+      temp_bytes = need;
+      BCHK(hipMalloc(&temp, temp_bytes));
+    }
+    BCHK(hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, deg64, g.off, (int)(g.n + 1), s));
+  }
+  BCHK(hipStreamSynchronize(s));
+done:
+  if (d_bad) (void)hipFree(d_bad);
+  if (k0) (void)hipFree(k0);
+  if (k1) (void)hipFree(k1);
+  if (d_nsel) (void)hipFree(d_nsel);
+  if (temp) (void)hipFree(temp);
+  if (deg64) (void)hipFree(deg64);
+  return status;
+#undef BCHK
+}
+
+}  // namespace abc

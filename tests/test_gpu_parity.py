@@ -1,0 +1,266 @@
+"""GPU parity: the HIP path against the CPU oracle, bit for bit.
+
+Every comparison is exact (integer membership); inputs are seeded synthetic
+graphs from bigraph_gen.
+"""
+import numpy as np
+import pytest
+
+import bigraph_gen
+import oracle
+from tests.gpu_util import bits_np, ensure_built, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+pkg = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    global pkg
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ensure_built()
+    import paper_2606_07148_amd as p
+    pkg = p
+    yield
+
+
+def _make(nU, nL, eu, ev):
+    g = pkg.abcore_build_csr(nU, nL, to_dev(eu), to_dev(ev))
+    ref = oracle.Graph(nU, nL, eu, ev)
+    return g, ref
+
+
+def _check_core(g, ref, a, b, algo, tag="", tombstones=False):
+    bits, st = pkg.abcore_compute(g, a, b, algo, stats=True)
+    mem, ost = oracle.peel(ref, a, b)
+    want = oracle.pack(mem)
+    got = bits_np(bits)[: len(want)]
+    assert np.array_equal(got, want), f"{tag} ({a},{b}) algo={algo}: bitmask differs"
+    if algo == pkg.ABCORE_GCC:
+        assert st["removed"] == ost["removed"], (tag, a, b)
+        assert st["rounds"] == ost["rounds"], (tag, a, b)
+        # after deletions the peel also reads the tombstoned entries of removed rows
+        if tombstones:
+            assert st["entries_read"] >= ost["removed_degree_sum"], (tag, a, b)
+        else:
+            assert st["entries_read"] == ost["removed_degree_sum"], (tag, a, b)
+    return st, ost
+
+
+# ------------------------------------------------------------------ build --
+
+
+def test_build_matches_oracle_csr():
+    spec = bigraph_gen.CONFIGS[1]
+    nU, nL = spec["n_upper"], spec["n_lower"]
+    eu, ev = bigraph_gen.make_graph(spec)
+    rng = np.random.default_rng(0)
+    dup = rng.choice(len(eu), 5000, replace=False)
+    eu2 = np.concatenate([eu, eu[dup]])
+    ev2 = np.concatenate([ev, ev[dup]])
+    perm = rng.permutation(len(eu2))
+    eu2, ev2 = eu2[perm], ev2[perm]
+    say("build: config 1 shuffled with 5000 duplicates")
+    g, ref = _make(nU, nL, eu2, ev2)
+    assert g.m == ref.m == len(eu)
+    off, cols = pkg.abcore_export_csr(g)
+    assert np.array_equal(off.cpu().numpy(), ref.off)
+    assert np.array_equal(cols.cpu().numpy(), ref.cols)
+    g.destroy()
+
+
+def test_build_rejects_out_of_range():
+    say("build: out-of-range endpoint")
+    with pytest.raises(pkg.AbcoreError) as e:
+        pkg.abcore_build_csr(4, 4, to_dev([0, 4]), to_dev([0, 1]))
+    assert e.value.name == "EINVAL"
+
+
+# ------------------------------------------------------------ computation --
+
+
+def test_config1_gcc_and_gccplus():
+    spec = bigraph_gen.CONFIGS[1]
+    eu, ev = bigraph_gen.make_graph(spec)
+    g, ref = _make(spec["n_upper"], spec["n_lower"], eu, ev)
+    say("config 1: (3,2) GCC / GCC+")
+    _check_core(g, ref, 3, 2, pkg.ABCORE_GCC, "c1")
+    _check_core(g, ref, 3, 2, pkg.ABCORE_GCC_PLUS, "c1")
+    for a, b in [(1, 1), (2, 2), (5, 3), (3, 5), (10, 14), (14, 10), (13, 27), (40, 40)]:
+        say("config 1:", a, b)
+        _check_core(g, ref, a, b, pkg.ABCORE_GCC, "c1")
+        _check_core(g, ref, a, b, pkg.ABCORE_GCC_PLUS, "c1")
+    g.destroy()
+
+
+@pytest.mark.parametrize("seed", [101, 102, 103])
+def test_chung_lu_small_grid(seed):
+    nU, nL, m = 30_000, 20_000, 400_000
+    eu, ev = bigraph_gen.chung_lu(nU, nL, m, 2.1, 2.1, 5000, seed)
+    g, ref = _make(nU, nL, eu, ev)
+    for a, b in [(1, 1), (2, 3), (3, 2), (5, 5), (4, 9), (9, 4), (12, 30), (30, 12), (64, 64),
+                 (1000, 1)]:
+        say("chung-lu", seed, a, b)
+        for algo in (pkg.ABCORE_GCC, pkg.ABCORE_GCC_PLUS):
+            _check_core(g, ref, a, b, algo, f"cl{seed}")
+    g.destroy()
+
+
+def test_repeat_runs_identical():
+    eu, ev = bigraph_gen.chung_lu(50_000, 30_000, 600_000, 2.1, 2.1, 8000, 7)
+    g = pkg.abcore_build_csr(50_000, 30_000, to_dev(eu), to_dev(ev))
+    say("repeatability (6,6) x 5")
+    first = bits_np(pkg.abcore_compute(g, 6, 6)).copy()
+    for _ in range(4):
+        assert np.array_equal(bits_np(pkg.abcore_compute(g, 6, 6)), first)
+    g.destroy()
+
+
+# ----------------------------------------------------------- core numbers --
+
+
+@pytest.mark.parametrize("seed", [201, 202])
+def test_core_numbers(seed):
+    nU, nL, m = 40_000, 25_000, 500_000
+    eu, ev = bigraph_gen.chung_lu(nU, nL, m, 2.1, 2.3, 6000, seed)
+    g, ref = _make(nU, nL, eu, ev)
+    say("core numbers", seed)
+    core, mx = pkg.abcore_core_numbers(g)
+    want = oracle.core_numbers(ref)
+    assert np.array_equal(core.cpu().numpy(), want)
+    assert mx == int(want.max())
+    g.destroy()
+
+
+def test_components():
+    nU, nL, m = 20_000, 20_000, 15_000  # sparse: many components
+    eu, ev = bigraph_gen.uniform(nU, nL, m, 301)
+    g, ref = _make(nU, nL, eu, ev)
+    say("components")
+    comp = pkg.abcore_components(g).cpu().numpy()
+    assert np.array_equal(comp, oracle.components(ref))
+    g.destroy()
+
+
+# ------------------------------------------------------------- edge cases --
+
+
+def test_edge_cases():
+    # no edges: nothing survives for alpha, beta >= 1
+    say("edge: empty edge set")
+    g = pkg.abcore_build_csr(5, 7, to_dev([]), to_dev([]))
+    assert g.m == 0
+    assert not bits_np(pkg.abcore_compute(g, 1, 1)).any()
+    assert not bits_np(pkg.abcore_compute(g, 2, 1, pkg.ABCORE_GCC_PLUS)).any()
+    core, mx = pkg.abcore_core_numbers(g)
+    assert mx == 0 and not core.cpu().numpy().any()
+    g.destroy()
+    # a star with a 50,000-degree hub plus a K_{3,3}
+    say("edge: 50k hub star")
+    hub_v = np.arange(50_000, dtype=np.int32)
+    eu = np.concatenate([np.zeros(50_000, np.int32), np.repeat(np.arange(1, 4), 3)])
+    ev = np.concatenate([hub_v, np.tile(np.arange(50_000, 50_003), 3)])
+    g, ref = _make(4, 50_003, eu, ev)
+    for a, b in [(1, 1), (2, 1), (1, 2), (3, 3), (4, 1), (50_000, 1), (50_001, 1)]:
+        for algo in (pkg.ABCORE_GCC, pkg.ABCORE_GCC_PLUS):
+            _check_core(g, ref, a, b, algo, "star")
+    g.destroy()
+    # complete bipartite K_{40,70}
+    say("edge: K_{40,70}")
+    eu = np.repeat(np.arange(40, dtype=np.int32), 70)
+    ev = np.tile(np.arange(70, dtype=np.int32), 40)
+    g, ref = _make(40, 70, eu, ev)
+    for a, b in [(70, 40), (71, 40), (70, 41), (1, 1), (35, 20)]:
+        for algo in (pkg.ABCORE_GCC, pkg.ABCORE_GCC_PLUS):
+            _check_core(g, ref, a, b, algo, "K")
+    g.destroy()
+    # a long path: one vertex per end per round
+    say("edge: path of 3001 vertices")
+    L = 3001
+    pos = np.arange(L - 1)
+    u = np.where(pos % 2 == 0, pos // 2, (pos + 1) // 2).astype(np.int32)
+    v = np.where(pos % 2 == 0, pos // 2, pos // 2).astype(np.int32)
+    g, ref = _make((L + 1) // 2, L // 2, u, v)
+    st, ost = _check_core(g, ref, 2, 2, pkg.ABCORE_GCC, "path")
+    assert st["rounds"] == (L + 1) // 2
+    g.destroy()
+
+
+# -------------------------------------------------------------------- GFQ --
+
+
+def test_gfq_stream_matches_recomputation():
+    spec = dict(kind="chung_lu", n_upper=3000, n_lower=2000, m=12_000, gamma_upper=2.1,
+                gamma_lower=2.1, cap=400, seed=401)
+    eu, ev = bigraph_gen.make_graph(spec)
+    ups = bigraph_gen.update_stream(spec, eu, ev, 300, 1401, qlo=1, qhi=6)
+    g = pkg.abcore_build_csr(spec["n_upper"], spec["n_lower"], to_dev(eu), to_dev(ev))
+    want = oracle.gfq_stream(spec["n_upper"], spec["n_lower"], eu, ev, ups)
+    say("gfq: 300 updates")
+    for i in range(len(ups["u"])):
+        ans, bits = pkg.abcore_query(g, ups["u"][i], ups["v"][i], ups["op"][i],
+                                     ups["alpha"][i], ups["beta"][i])
+        st, wans, wbits = want[i]
+        assert st == "OK"
+        assert (ans, bits) == (wans, wbits), f"update {i}"
+    # the graph after the stream equals the oracle's final graph
+    off, cols = pkg.abcore_export_csr(g)
+    nL = spec["n_lower"]
+    keys = set((int(a) * nL + int(b)) for a, b in zip(eu, ev))
+    for i in range(len(ups["u"])):
+        k = int(ups["u"][i]) * nL + int(ups["v"][i])
+        (keys.add if ups["op"][i] > 0 else keys.discard)(k)
+    kk = np.array(sorted(keys), np.int64)
+    ref = oracle.Graph(spec["n_upper"], nL, (kk // nL).astype(np.int32),
+                       (kk % nL).astype(np.int32))
+    assert np.array_equal(off.cpu().numpy(), ref.off)
+    assert np.array_equal(cols.cpu().numpy(), ref.cols)
+    # components and the whole-graph computation on the updated graph
+    assert np.array_equal(pkg.abcore_components(g).cpu().numpy(), oracle.components(ref))
+    for algo in (pkg.ABCORE_GCC, pkg.ABCORE_GCC_PLUS):
+        _check_core(g, ref, 2, 3, algo, "after-stream", tombstones=True)
+    core, _ = pkg.abcore_core_numbers(g)
+    assert np.array_equal(core.cpu().numpy(), oracle.core_numbers(ref))
+    g.destroy()
+
+
+def test_gfq_errors_leave_graph_unchanged():
+    eu = np.array([0, 0, 1], np.int32)
+    ev = np.array([0, 1, 1], np.int32)
+    g = pkg.abcore_build_csr(3, 3, to_dev(eu), to_dev(ev))
+    say("gfq: error statuses")
+    off0, cols0 = [t.cpu().numpy() for t in pkg.abcore_export_csr(g)]
+    for (u, v, op, name) in [(0, 0, 1, "EEXIST"), (2, 2, -1, "ENOENT"), (3, 0, 1, "EINVAL"),
+                             (0, 0, 2, "EINVAL")]:
+        with pytest.raises(pkg.AbcoreError) as e:
+            pkg.abcore_query(g, u, v, op, 1, 1)
+        assert e.value.name == name
+        off1, cols1 = [t.cpu().numpy() for t in pkg.abcore_export_csr(g)]
+        assert np.array_equal(off0, off1) and np.array_equal(cols0, cols1)
+    # insert, delete, re-insert the same pair (CSR edge and inserted edge)
+    assert pkg.abcore_query(g, 0, 0, -1, 1, 1) == (False, 1)  # (0,0) gone; v0 isolated
+    assert pkg.abcore_query(g, 0, 0, 1, 1, 1) == (True, 3)
+    assert pkg.abcore_query(g, 2, 2, 1, 1, 1) == (True, 3)
+    assert pkg.abcore_query(g, 2, 2, -1, 1, 1) == (False, 0)
+    assert pkg.abcore_query(g, 2, 2, 1, 1, 1) == (True, 3)
+    g.destroy()
+
+
+# ------------------------------------------------------- full-size config 2 --
+
+
+def test_config2_full_size():
+    spec = bigraph_gen.CONFIGS[2]
+    nU, nL = spec["n_upper"], spec["n_lower"]
+    say("config 2: generating 20M edges")
+    eu, ev = bigraph_gen.make_graph(spec)
+    g, ref = _make(nU, nL, eu, ev)
+    for a, b in [(10, 10), (5, 20), (20, 5), (2, 2)]:
+        say("config 2:", a, b)
+        _check_core(g, ref, a, b, pkg.ABCORE_GCC, "c2")
+        _check_core(g, ref, a, b, pkg.ABCORE_GCC_PLUS, "c2")
+    core, mx = pkg.abcore_core_numbers(g)
+    assert np.array_equal(core.cpu().numpy(), oracle.core_numbers(ref))
+    g.destroy()
