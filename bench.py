@@ -112,28 +112,56 @@ def main() -> int:
     torch.cuda.synchronize()
     got = out.cpu().numpy().view(np.uint32)[: len(want)]
     parity = bool(np.array_equal(got, want))
+    _, gst = pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out, stats=True)
     pkg.abcore_set_option(g, pkg.ABCORE_OPT_TIMING, 1)
-    pkg.abcore_peel_timing(g, reset=True)
+    for kind in range(4):
+        pkg.abcore_kernel_timing(g, kind, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    peel_ms, peel_launches = pkg.abcore_peel_timing(g, reset=True)
+    ktime = {kind: pkg.abcore_kernel_timing(g, kind, reset=True) for kind in range(4)}
     pkg.abcore_set_option(g, pkg.ABCORE_OPT_TIMING, 0)
     ms_per_step = elapsed * 1e3 / args.steps
     value = m_peeled / (ms_per_step / 1e3)
 
-    # algorithmic bytes of the peel phase for one query: offsets (16 B) and
-    # row (4 B per entry) of every removed vertex, plus one 4-byte
-    # read-modify-write per peeled edge endpoint decrement (8 B)
-    peel_bytes = 16 * removed + 4 * sum_deg_removed + 8 * m_peeled
-    step_bytes = 8 * n + n // 8 + peel_bytes
-    launches_per_step = peel_launches / args.steps
-    avg_launch_s = peel_ms / 1e3 / max(1, peel_launches)
-    bytes_per_launch = peel_bytes / max(1e-9, launches_per_step)
-    achieved = bytes_per_launch / avg_launch_s / 1e9 if peel_ms > 0 else 0.0
+    # algorithmic bytes per query of each kernel, from the oracle's sets:
+    # F0 = scan frontier, A1 = its complement, R = removed vertices
+    thr = np.where(np.arange(n) < nU, alpha, beta)
+    f0 = deg < thr
+    removed_mask = ~member
+    lower = nU + ev.astype(np.int64)
+    upper = eu.astype(np.int64)
+    pulled = bool(gst["pulled"])
+    if pulled:
+        a1 = ~f0
+        r2 = removed_mask & a1
+        touch_r2 = r2[upper] | r2[lower]
+        touch_f0 = f0[upper] | f0[lower]
+        m2 = int(np.count_nonzero(touch_r2 & ~touch_f0))
+        push_bytes = 16 * int(r2.sum()) + 4 * int(deg[r2].sum()) + 8 * m2
+        pull_bytes = 20 * int(a1.sum()) + 4 * int(deg[a1].sum()) + n // 8
+    else:
+        push_bytes = 16 * removed + 4 * sum_deg_removed + 8 * m_peeled
+        pull_bytes = 0
+    scan_bytes = 8 * n + 4 * int(f0.sum()) + (n // 8 if pulled else 0)
+    pack_bytes = 4 * n + n // 8
+    kinfo = {}
+    names = {0: "peel_persistent_kernel<GCC>", 1: "pull_round_kernel", 2: "scan_gcc_kernel",
+             3: "pack_kernel"}
+    kbytes = {0: push_bytes, 1: pull_bytes, 2: scan_bytes, 3: pack_bytes}
+    for kind, (ms, launches) in ktime.items():
+        if launches == 0:
+            continue
+        per_launch_s = ms / 1e3 / launches
+        bpl = kbytes[kind] * args.steps / launches
+        kinfo[names[kind]] = {"avg_launch_us": per_launch_s * 1e6, "launches_per_step":
+                              launches / args.steps, "bytes_per_launch": bpl,
+                              "achieved_GBs": bpl / per_launch_s / 1e9 if per_launch_s > 0 else 0}
+    dom = max(kinfo, key=lambda k: kinfo[k]["avg_launch_us"] * kinfo[k]["launches_per_step"])
+    step_bytes = scan_bytes + pull_bytes + push_bytes + pack_bytes
 
     # --- GCC+ (Algorithm 2): preprocessing + query ------------------------
     torch.cuda.synchronize()
@@ -173,16 +201,17 @@ def main() -> int:
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "peel_round_kernel<GCC>",
-            "achieved": achieved,
+            "kernel": dom,
+            "achieved": kinfo[dom]["achieved_GBs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "frac": kinfo[dom]["achieved_GBs"] / HBM_PEAK_GBS,
             "traffic": None,
-            "bytes_per_launch": bytes_per_launch,
-            "avg_launch_us": avg_launch_s * 1e6,
-            "launches_per_step": launches_per_step,
+            "bytes_per_launch": kinfo[dom]["bytes_per_launch"],
+            "avg_launch_us": kinfo[dom]["avg_launch_us"],
         },
+        "kernels": kinfo,
+        "gpu_stats": gst,
         "parity": parity,
         "m_peeled": m_peeled,
         "removed": removed,

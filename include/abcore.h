@@ -50,12 +50,13 @@ enum { ABCORE_GCC = 0, ABCORE_GCC_PLUS = 1 };
 /* Counters of one computation (filled when a stats pointer is passed; that
  * forces a synchronisation of the stream). */
 typedef struct {
-  int64_t removed;        /* vertices removed by peeling (|R|) */
+  int64_t removed;        /* vertices outside the result (|V| - |core|) */
   int64_t rounds;         /* peel rounds (frontier generations) */
   int64_t entries_read;   /* adjacency entries read by the peel */
   int64_t initial;        /* vertices in the first frontier (scan phase) */
   int64_t uncertain;      /* GCC+: vertices with delta_l <= core < delta_q */
   int64_t launches;       /* kernels launched for the peel phase */
+  int64_t pulled;         /* 1 if the first round ran in pull form */
 } abcore_stats;
 
 /* One edge update for the on-the-fly query (Problem 2, Sec. III). */
@@ -137,25 +138,42 @@ abcore_status abcore_query(abcore_graph g, abcore_edge_update upd, uint32_t alph
 
 /* Tuning knobs (non-negative values; 0 restores the default).
  *   ABCORE_OPT_PEEL_MODE : 1 = one kernel per peel round, host-checked in
- *                          batches; 2 = persistent asynchronous worklist.
+ *                          batches; 2 = all rounds in one cooperative launch
+ *                          with a grid barrier between rounds (default when
+ *                          the device reports co-residency).
  *   ABCORE_OPT_GRID      : workgroups per peel launch.
  *   ABCORE_OPT_ROUNDS_PER_SYNC : round kernels enqueued between checks.
  *   ABCORE_OPT_TIMING    : 1 = record a HIP event pair on the caller's stream
  *                          around every launch (or batch of launches) of the
- *                          peel kernel; read with abcore_peel_timing. */
+ *                          GCC kernels; read with abcore_kernel_timing.
+ *   ABCORE_OPT_PULL      : first GCC round in pull form: 0 = decided on the
+ *                          device from the scan frontier, 1 = never, 2 = always. */
 enum {
   ABCORE_OPT_PEEL_MODE = 1,
   ABCORE_OPT_GRID = 2,
   ABCORE_OPT_ROUNDS_PER_SYNC = 3,
-  ABCORE_OPT_TIMING = 4
+  ABCORE_OPT_TIMING = 4,
+  ABCORE_OPT_PULL = 5
 };
 abcore_status abcore_set_option(abcore_graph g, int32_t option, int64_t value);
 
-/* Peel-kernel GPU time recorded while ABCORE_OPT_TIMING is on: *ms = summed
- * elapsed time of the recorded event pairs, *launches = peel-kernel launches
- * they bracket.  Waits for the recorded events.  reset != 0 clears both. */
-abcore_status abcore_peel_timing(abcore_graph g, double *ms, int64_t *launches,
-                                 int32_t reset);
+/* Kernel kinds timed while ABCORE_OPT_TIMING is on: the push peel rounds
+ * (Algorithm 1, peel phase), the pull-form first round, the scan phase and
+ * the bitmask pack. */
+enum {
+  ABCORE_KERNEL_PEEL = 0,
+  ABCORE_KERNEL_PULL = 1,
+  ABCORE_KERNEL_SCAN = 2,
+  ABCORE_KERNEL_PACK = 3
+};
+
+/* GPU time of one kernel kind recorded while ABCORE_OPT_TIMING is on:
+ * *ms = summed elapsed time of its event pairs (recorded on the stream the
+ * kernel is launched on), *launches = launches they bracket.  Waits for the
+ * recorded events.  reset != 0 clears the records of that kind.
+ * EINVAL for an unknown kind. */
+abcore_status abcore_kernel_timing(abcore_graph g, int32_t kernel, double *ms,
+                                   int64_t *launches, int32_t reset);
 
 #ifdef __cplusplus
 }

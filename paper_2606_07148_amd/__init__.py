@@ -23,6 +23,7 @@ ABCORE_OPT_PEEL_MODE = 1
 ABCORE_OPT_GRID = 2
 ABCORE_OPT_ROUNDS_PER_SYNC = 3
 ABCORE_OPT_TIMING = 4
+ABCORE_OPT_PULL = 5
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOENT", 5: "EEXIST",
           6: "EBUSY"}
@@ -38,7 +39,8 @@ class AbcoreError(RuntimeError):
 class abcore_stats(ctypes.Structure):
     _fields_ = [("removed", ctypes.c_int64), ("rounds", ctypes.c_int64),
                 ("entries_read", ctypes.c_int64), ("initial", ctypes.c_int64),
-                ("uncertain", ctypes.c_int64), ("launches", ctypes.c_int64)]
+                ("uncertain", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("pulled", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -73,7 +75,7 @@ def load():
         "abcore_components": (i32, [vp, vp, vp]),
         "abcore_query": (i32, [vp, abcore_edge_update, u32, u32, P(i32), P(u32), vp]),
         "abcore_set_option": (i32, [vp, i32, i64]),
-        "abcore_peel_timing": (i32, [vp, P(ctypes.c_double), P(i64), i32]),
+        "abcore_kernel_timing": (i32, [vp, i32, P(ctypes.c_double), P(i64), i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -168,12 +170,19 @@ def abcore_set_option(g: Graph, option: int, value: int) -> None:
     _check(load().abcore_set_option(g.handle, int(option), int(value)))
 
 
-def abcore_peel_timing(g: Graph, reset: bool = True):
-    """(GPU milliseconds, launches) of the peel kernels recorded with
+ABCORE_KERNEL_PEEL = 0
+ABCORE_KERNEL_PULL = 1
+ABCORE_KERNEL_SCAN = 2
+ABCORE_KERNEL_PACK = 3
+
+
+def abcore_kernel_timing(g: Graph, kernel: int, reset: bool = True):
+    """(GPU milliseconds, launches) of one kernel kind recorded with
     ABCORE_OPT_TIMING on."""
     ms = ctypes.c_double()
     n = ctypes.c_int64()
-    _check(load().abcore_peel_timing(g.handle, ctypes.byref(ms), ctypes.byref(n), int(reset)))
+    _check(load().abcore_kernel_timing(g.handle, int(kernel), ctypes.byref(ms), ctypes.byref(n),
+                                       int(reset)))
     return float(ms.value), int(n.value)
 
 

@@ -13,11 +13,27 @@
 namespace abc {
 
 constexpr int kWave = 64;
-constexpr int kBlock = 256;
+constexpr int kBlock = 256;             // flat kernels (scan, classify, pack)
 constexpr int kWavesPerBlock = kBlock / kWave;
-// Per-wave local queue (LDS) used to batch frontier pushes, Sec. IV-A's
-// warp-local queue sized for a 64-lane wavefront.
-constexpr int kLocalQueue = 512;
+constexpr int kPeelBlock = 512;         // peel kernels: 8 waves per workgroup
+constexpr int kPeelWaves = kPeelBlock / kWave;
+constexpr int kPullBlock = 1024;        // pull round: one workgroup per CU
+constexpr int kPullWaves = kPullBlock / kWave;
+// Per-wave frontier buffer in LDS (the warp-local queue of Algorithm 1,
+// sized for a 64-lane wavefront); flushed per workgroup at round ends.
+constexpr int kLocalQueue = 256;
+constexpr int kPullLocalQueue = 128;
+// Row piece length (entries) for load balancing over skewed degrees.
+constexpr int kPiece = 64;
+
+// Spread append counters: workgroup b appends to sub-queue b % kSub, each
+// with its own counter on its own 64-byte line.  Same-address device-scope
+// atomics serialise (about 11 ns each on MI355X), so no counter may take
+// more than a few dozen increments per launch.
+constexpr int kSub = 16;
+constexpr int kPad = 16;      // int32 words per 64-byte line
+constexpr int kGroups = 16;   // grid-barrier / last-workgroup groups
+constexpr int kMaxBlocks = 4096;
 
 // GCC+ class encoding in the working degree array (Sec. IV-B, Lemma 1):
 // certain members are never decremented, certain non-members never counted.
@@ -26,29 +42,52 @@ constexpr int32_t kDegOut = -1;
 // Largest usable threshold: kDegIn must stay above every threshold.
 constexpr int32_t kMaxThreshold = 0x7FFFFFFE;
 
-// Peel bookkeeping shared by every multi-round computation.  One instance
-// lives in device memory per handle.  The queue Q is append-only for the
-// whole computation (each vertex enters it at most once), so a round is the
-// index range [lo, hi) of Q; the last workgroup of a round launch advances
-// the range to the items appended during that round.
+// Hierarchical arrival counters: workgroups arrive on their group's line,
+// the last of each group on the top line.
+struct Arrival {
+  uint32_t group[kGroups][kPad];
+  uint32_t top[kPad];
+  uint32_t gen[kPad];  // grid barrier generation (persistent kernels)
+};
+
+// Peel bookkeeping shared by every multi-round computation (one instance in
+// device memory per handle).  Each vertex enters the frontier queues at most
+// once per computation (twice for GCC+: uncertain list, then frontier), so
+// the queues are append-only and a round is the ranges [lo[j], hi[j]) of the
+// kSub sub-queues.  Whoever completes a round (the last workgroup of a
+// launch, or the last arrival of a grid barrier) advances the ranges to the
+// items appended meanwhile.
 struct PeelState {
-  int32_t tail;       // append cursor into Q (atomic)
-  int32_t lo, hi;     // current round = Q[lo, hi)
-  int32_t rounds;     // non-empty rounds executed
-  uint32_t finished;  // workgroups done in the current launch
-  int32_t k;          // core decomposition: current level
-  int32_t next_k;     // core decomposition: level of the next scan
-  int32_t alive_cur;  // core decomposition: entries in the current alive list
-  int32_t alive_next; // core decomposition: entries written to the next list
-  int32_t alive_sel;  // which alive buffer is current (0/1)
-  int32_t min_alive;  // smallest degree among kept vertices of the last scan
-  int32_t done;       // computation finished
-  int32_t max_core;   // largest level with removals
-  int32_t status;     // device-side status for updates (0 ok)
-  int32_t aux0, aux1; // small results (uncertain count, labels, answer bits)
-  int32_t first;      // size of the initial frontier (scan phase)
-  int64_t entries;    // adjacency entries read by peel rounds
-  int64_t launches;   // round/step launches that did work
+  int32_t tail[kSub][kPad];  // append cursors
+  int32_t lo[kSub];
+  int32_t hi[kSub];
+  Arrival arr;
+  int32_t rounds;       // non-empty rounds completed
+  int32_t first;        // size of the initial frontier
+  int32_t k;            // core decomposition: current level
+  int32_t next_k;       // core decomposition: level of the next scan
+  int32_t alive_cur;    // core decomposition: entries in the current alive list
+  int32_t alive_sel;    // which alive list is current (0/1)
+  int32_t kept;         // core decomposition: live vertices after the last scan
+  int32_t compact;      // core decomposition: compact the alive list next
+  int32_t done;         // computation finished
+  int32_t max_core;     // largest level with removals
+  int32_t status;       // device-side status for updates (0 ok)
+  int32_t aux0, aux1;   // small results (uncertain count, labels, answer bits)
+  int32_t pulled;       // first round ran in pull form
+  int32_t abort_flag;   // a grid barrier exceeded its spin limit
+  int32_t pad0;
+  int64_t launches;     // launches that did work
+};
+
+// Per-workgroup partial results, one slot line per workgroup (no atomics).
+enum PartField : int {
+  kPartEntries = 0,   // adjacency entries read
+  kPartF0 = 1,        // initial-frontier vertices
+  kPartF0Deg = 2,     // their degree sum
+  kPartKept = 3,      // core decomposition: kept vertices of the last scan
+  kPartMin = 4,       // core decomposition: smallest kept degree
+  kPartFields = 8
 };
 
 // Dynamic edge storage for updates after the build (Sec. V).  Deleted CSR
@@ -74,69 +113,97 @@ struct Graph {
   int32_t *cols = nullptr;  // 2*m_csr
   int32_t *deg0 = nullptr;  // current degree of every vertex
   int32_t *deg = nullptr;   // working degree (per computation)
-  int32_t *queue = nullptr; // n + padding
-  int32_t *list = nullptr;  // n: scratch vertex list (uncertain set, alive lists)
-  int32_t *list2 = nullptr; // n: second alive list
+  int32_t *queue = nullptr; // kSub sub-queues of qcap entries
+  int64_t qcap = 0;
+  uint32_t *alive_bits = nullptr;  // n bits: alive after the scan (pull round)
+  int32_t *list = nullptr;  // n: alive list 0 (core decomposition)
+  int32_t *list2 = nullptr; // n: alive list 1
+  int64_t *part = nullptr;  // kMaxBlocks * kPartFields
   PeelState *state = nullptr;
   PeelState *h_state = nullptr;  // pinned host mirror
+  int64_t *h_part = nullptr;     // pinned host mirror of part
   int32_t *core = nullptr;  // cached core numbers
   bool core_valid = false;
   int32_t max_core = 0;
+  // Rows longer than kPiece entries are split into pieces of kPiece entries
+  // so that no wave batch walks a hub alone (fixed by the offsets, so built
+  // once per handle).  Pieces are ordered by row; upper rows come first.
+  int32_t *piece_row = nullptr;    // npieces
+  int64_t *piece_start = nullptr;  // npieces: absolute position in cols
+  int32_t *piece_first = nullptr;  // n: first piece of a split row, else -1
+  int32_t *heavy_rows = nullptr;   // nheavy: the split rows, ascending
+  int64_t npieces = 0, npieces_upper = 0;
+  int64_t nheavy = 0, nheavy_upper = 0;
   int32_t *comp = nullptr;  // component labels
   bool comp_valid = false;
   int32_t *parent = nullptr; // union-find scratch
-  bool has_tombstones = false;
   Delta delta;
   int version = 0;
-  // options
-  int peel_mode = 1;
-  int grid = 0;            // 0 = derived from the device
-  int rounds_per_sync = 16;
+  // device facts and options
   int cu_count = 256;
-  // peel-kernel timing (ABCORE_OPT_TIMING)
+  size_t lds_per_block = 65536;
+  int peel_mode = 2;        // 1 = round kernels, 2 = persistent (cooperative)
+  int pull_mode = 0;        // 0 = auto, 1 = never, 2 = always
+  int grid = 0;             // 0 = derived from the device
+  int rounds_per_sync = 16;
+  int persistent_grid = 0;  // co-resident workgroups of the persistent kernels
+  int kcore_grid = 0;
+  // kernel timing (ABCORE_OPT_TIMING): event pairs per kernel kind
   bool timing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;  // recorded pairs
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events[4];
   std::vector<hipEvent_t> event_pool;
-  int64_t timed_launches = 0;
+  int64_t timed_launches[4] = {0, 0, 0, 0};
 };
 
 // Peel flavours.
 enum PeelKind : int { kGCC = 0, kGCCPlus = 1, kKCore = 2 };
 
-// Parameters of a peel round, passed by value to kernels.
+// Parameters of a peel, passed by value to kernels.
 struct PeelArgs {
   const int64_t *off;
   const int32_t *cols;
   int32_t *deg;
   int32_t *queue;
+  int64_t qcap;
   PeelState *st;
+  int64_t *part;
   const int32_t *ins_head;  // nullable
   const int32_t *ins_next;
   const int32_t *ins_other;
   int32_t *core;            // kKCore: output core numbers
+  const int32_t *piece_row;
+  const int64_t *piece_start;
+  const int32_t *piece_first;
   int32_t nU;
-  int32_t thrU, thrL;       // thresholds (kKCore: k + 1 read from st)
+  int32_t thrU, thrL;
 };
 
 void set_error(const char *fmt, ...);
+PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL);
 
 // Launchers (defined in the .hip files).
-hipError_t launch_init_state(PeelState *st, hipStream_t s);
-hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s);
+hipError_t launch_init_state(Graph &g, hipStream_t s);
+hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, bool want_bits,
+                           hipStream_t s);
+hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s);
 hipError_t launch_scan_component_of(Graph &g, int32_t thrU, int32_t thrL, int32_t x,
                                     int32_t y, hipStream_t s);
 hipError_t launch_peel_rounds(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
                               int rounds, hipStream_t s);
+hipError_t launch_peel_persistent(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
+                                  hipStream_t s);
 hipError_t launch_pack(Graph &g, int32_t thrU, int32_t thrL, uint32_t *bits,
                        hipStream_t s);
 hipError_t launch_pack_from_core(Graph &g, int32_t k, uint32_t *bits, hipStream_t s);
-hipError_t launch_classify(Graph &g, int32_t thrU, int32_t thrL, int32_t dl, int32_t dq,
-                           hipStream_t s);
+hipError_t launch_classify(Graph &g, int32_t dl, int32_t dq, hipStream_t s);
 hipError_t launch_restricted_init(Graph &g, int32_t thrU, int32_t thrL, int32_t dl,
                                   hipStream_t s);
 hipError_t launch_kcore_init(Graph &g, hipStream_t s);
+hipError_t launch_kcore_persistent(Graph &g, hipStream_t s);
 hipError_t launch_kcore_steps(Graph &g, int steps, hipStream_t s);
 hipError_t launch_cc(Graph &g, int32_t only_label, hipStream_t s);
+hipError_t query_persistent_grids(Graph &g);
+abcore_status build_pieces(Graph &g, hipStream_t s);
 
 int peel_grid(const Graph &g);
 

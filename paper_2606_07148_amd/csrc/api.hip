@@ -27,6 +27,7 @@ hipError_t launch_update(Graph &g, int32_t u, int32_t v, int32_t op, int64_t slo
 hipError_t launch_answer(Graph &g, int32_t x, int32_t y, int32_t thrU, int32_t thrL,
                          hipStream_t s);
 hipError_t launch_export(Graph &g, int64_t *out_off, int32_t *out_cols, hipStream_t s);
+hipError_t prepare_pull_kernel(Graph &g);
 
 namespace {
 
@@ -39,6 +40,12 @@ namespace {
     }                                                                              \
   } while (0)
 
+#define TRY(x)                                 \
+  do {                                         \
+    abcore_status s_ = (x);                    \
+    if (s_ != ABCORE_OK) return s_;            \
+  } while (0)
+
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 inline int32_t clamp_thr(uint32_t t) {
@@ -48,26 +55,31 @@ inline int32_t clamp_thr(uint32_t t) {
 void free_graph(Graph *g) {
   if (!g) return;
   (void)hipSetDevice(g->device);
-  for (auto &pr : g->events) {
-    (void)hipEventDestroy(pr.first);
-    (void)hipEventDestroy(pr.second);
-  }
+  for (auto &ev : g->events)
+    for (auto &pr : ev) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
   for (hipEvent_t e : g->event_pool) (void)hipEventDestroy(e);
-  void *bufs[] = {g->off,    g->cols,   g->deg0,       g->deg,        g->queue,
-                  g->list,   g->list2,  g->state,      g->core,       g->comp,
-                  g->parent, g->delta.head, g->delta.next, g->delta.other};
+  void *bufs[] = {g->off,        g->cols,        g->deg0,        g->deg,
+                  g->queue,      g->list,        g->list2,       g->state,
+                  g->core,       g->comp,        g->parent,      g->delta.head,
+                  g->delta.next, g->delta.other, g->alive_bits,  g->part,
+                  g->piece_row,  g->piece_start, g->piece_first, g->heavy_rows};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   if (g->h_state) (void)hipHostFree(g->h_state);
+  if (g->h_part) (void)hipHostFree(g->h_part);
   delete g;
 }
 
-abcore_status ensure(int32_t **p, int64_t count) {
+template <class T>
+abcore_status ensure(T **p, int64_t count) {
   if (*p) return ABCORE_OK;
-  hipError_t e = hipMalloc(p, sizeof(int32_t) * std::max<int64_t>(count, 1));
+  hipError_t e = hipMalloc(p, sizeof(T) * std::max<int64_t>(count, 1));
   if (e != hipSuccess) {
     *p = nullptr;
-    set_error("device allocation of %lld words failed: %s", (long long)count,
+    set_error("device allocation of %lld elements failed: %s", (long long)count,
               hipGetErrorString(e));
     return ABCORE_ENOMEM;
   }
@@ -83,9 +95,10 @@ hipError_t take_event(Graph &g, hipEvent_t *e) {
   return hipEventCreate(e);
 }
 
-// Records an event pair around `launch` when timing is on.
+// Records an event pair of kernel kind `kind` around `launch` when timing
+// is on (kinds: ABCORE_KERNEL_PEEL, _PULL, _SCAN, _PACK).
 template <class F>
-hipError_t timed(Graph &g, hipStream_t s, int64_t nlaunch, F launch) {
+hipError_t timed(Graph &g, int kind, hipStream_t s, int64_t nlaunch, F launch) {
   if (!g.timing) return launch();
   hipEvent_t a, b;
   hipError_t e = take_event(g, &a);
@@ -94,31 +107,59 @@ hipError_t timed(Graph &g, hipStream_t s, int64_t nlaunch, F launch) {
   if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
   if ((e = launch()) != hipSuccess) return e;
   if ((e = hipEventRecord(b, s)) != hipSuccess) return e;
-  g.events.emplace_back(a, b);
-  g.timed_launches += nlaunch;
+  g.events[kind].emplace_back(a, b);
+  g.timed_launches[kind] += nlaunch;
   return hipSuccess;
 }
 
 abcore_status read_state(Graph &g, hipStream_t s) {
   CHK(hipMemcpyAsync(g.h_state, g.state, sizeof(PeelState), hipMemcpyDeviceToHost, s));
   CHK(hipStreamSynchronize(s));
+  if (g.h_state->abort_flag) {
+    set_error("a grid barrier exceeded its spin limit; the result is invalid");
+    return ABCORE_EDEVICE;
+  }
   return ABCORE_OK;
 }
 
-// Runs peel rounds until the frontier is empty.  Round kernels are enqueued
-// in growing batches (4, 8, 16, ... up to rounds_per_sync); a launch after
-// convergence returns immediately.
-abcore_status run_rounds(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, hipStream_t s,
-                         int64_t *launches) {
+int64_t sum_part(Graph &g, int field, hipStream_t s, abcore_status *st) {
+  hipError_t e = hipMemcpyAsync(g.h_part, g.part, sizeof(int64_t) * kMaxBlocks * kPartFields,
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    set_error("reading partial sums failed: %s", hipGetErrorString(e));
+    *st = ABCORE_EDEVICE;
+    return 0;
+  }
+  int64_t t = 0;
+  for (int b = 0; b < kMaxBlocks; ++b) t += g.h_part[(int64_t)b * kPartFields + field];
+  *st = ABCORE_OK;
+  return t;
+}
+
+// Runs the peel rounds of the current frontier to completion.  Persistent
+// mode: one cooperative launch, no host involvement.  Round mode: round
+// kernels in growing batches (4, 8, 16, ...), checking convergence between
+// batches; a launch after convergence returns immediately.
+abcore_status run_peel(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, hipStream_t s,
+                       int64_t *launches) {
+  if (g.peel_mode == 2) {
+    CHK(timed(g, ABCORE_KERNEL_PEEL, s, 1,
+              [&] { return launch_peel_persistent(g, kind, thrU, thrL, s); }));
+    *launches += 1;
+    return ABCORE_OK;
+  }
   // every non-empty round removes at least one vertex
   const int64_t max_launches = g.n + 4 * (int64_t)std::max(4, g.rounds_per_sync) + 8;
   int batch = 4;
   for (int64_t done = 0; done < max_launches; done += batch) {
-    CHK(timed(g, s, batch, [&] { return launch_peel_rounds(g, kind, thrU, thrL, batch, s); }));
+    CHK(timed(g, ABCORE_KERNEL_PEEL, s, batch,
+              [&] { return launch_peel_rounds(g, kind, thrU, thrL, batch, s); }));
     *launches += batch;
-    abcore_status st = read_state(g, s);
-    if (st != ABCORE_OK) return st;
-    if (g.h_state->lo >= g.h_state->hi) return ABCORE_OK;
+    TRY(read_state(g, s));
+    bool empty = true;
+    for (int j = 0; j < kSub; ++j) empty &= g.h_state->lo[j] >= g.h_state->hi[j];
+    if (empty) return ABCORE_OK;
     batch = std::min(batch * 2, std::max(4, g.rounds_per_sync));
   }
   set_error("peel did not converge");
@@ -127,33 +168,43 @@ abcore_status run_rounds(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, hi
 
 abcore_status compute_core(Graph &g, hipStream_t s) {
   if (g.core_valid) return ABCORE_OK;
-  abcore_status st;
-  if ((st = ensure(&g.core, g.n)) != ABCORE_OK) return st;
-  if ((st = ensure(&g.list, g.n)) != ABCORE_OK) return st;
-  if ((st = ensure(&g.list2, g.n)) != ABCORE_OK) return st;
+  TRY(ensure(&g.core, g.n));
+  TRY(ensure(&g.list, g.n));
+  TRY(ensure(&g.list2, g.n));
   CHK(launch_kcore_init(g, s));
-  // each step either removes a vertex or raises the level past a live degree
-  const int64_t max_steps = 3 * g.n + 256;
-  int batch = 8;
-  for (int64_t done = 0; done < max_steps; done += batch) {
-    CHK(launch_kcore_steps(g, batch, s));
-    if ((st = read_state(g, s)) != ABCORE_OK) return st;
-    if (g.h_state->done) {
-      g.max_core = g.h_state->max_core;
-      g.core_valid = true;
-      return ABCORE_OK;
+  if (g.peel_mode == 2) {
+    CHK(launch_kcore_persistent(g, s));
+    TRY(read_state(g, s));
+    if (!g.h_state->done) {
+      set_error("core decomposition did not finish");
+      return ABCORE_EDEVICE;
     }
-    batch = std::min(batch * 2, 64);
+  } else {
+    // each step removes a vertex, raises the level past a live degree, or
+    // compacts the alive list after a scan
+    const int64_t max_steps = 4 * g.n + 256;
+    int batch = 8;
+    int64_t done = 0;
+    for (; done < max_steps; done += batch) {
+      CHK(launch_kcore_steps(g, batch, s));
+      TRY(read_state(g, s));
+      if (g.h_state->done) break;
+      batch = std::min(batch * 2, 64);
+    }
+    if (done >= max_steps) {
+      set_error("core decomposition did not converge");
+      return ABCORE_EDEVICE;
+    }
   }
-  set_error("core decomposition did not converge");
-  return ABCORE_EDEVICE;
+  g.max_core = g.h_state->max_core;
+  g.core_valid = true;
+  return ABCORE_OK;
 }
 
 abcore_status compute_components(Graph &g, hipStream_t s) {
   if (g.comp_valid) return ABCORE_OK;
-  abcore_status st;
-  if ((st = ensure(&g.comp, g.n)) != ABCORE_OK) return st;
-  if ((st = ensure(&g.parent, g.n)) != ABCORE_OK) return st;
+  TRY(ensure(&g.comp, g.n));
+  TRY(ensure(&g.parent, g.n));
   if (g.n > 0) CHK(launch_cc(g, -1, s));
   CHK(hipStreamSynchronize(s));
   g.comp_valid = true;
@@ -163,8 +214,7 @@ abcore_status compute_components(Graph &g, hipStream_t s) {
 abcore_status ensure_delta(Graph &g, hipStream_t s) {
   Delta &d = g.delta;
   if (d.head == nullptr) {
-    abcore_status st = ensure(&d.head, g.n);
-    if (st != ABCORE_OK) return st;
+    TRY(ensure(&d.head, g.n));
     CHK(hipMemsetAsync(d.head, 0xFF, sizeof(int32_t) * std::max<int64_t>(g.n, 1), s));
   }
   if (d.count < d.cap) return ABCORE_OK;
@@ -207,7 +257,7 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
     return ABCORE_EINVAL;
   }
   *out = nullptr;
-  if (n_upper < 0 || n_lower < 0 || m < 0 || (int64_t)n_upper + n_lower >= 0x7FFFFFFFLL ||
+  if (n_upper < 0 || n_lower < 0 || m < 0 || (int64_t)n_upper + n_lower >= 0x3FFFFFFFLL ||
       m >= 0x7FFFFFFFLL || (m > 0 && (!d_eu || !d_ev))) {
     set_error("abcore_build_csr: invalid sizes or null edge arrays");
     return ABCORE_EINVAL;
@@ -226,23 +276,42 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
       break;
     }
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, g->device) == hipSuccess && prop.multiProcessorCount > 0)
-      g->cu_count = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) {
+      if (prop.multiProcessorCount > 0) g->cu_count = prop.multiProcessorCount;
+      if (prop.sharedMemPerBlock > 0) g->lds_per_block = prop.sharedMemPerBlock;
+    }
     g->nU = n_upper;
     g->nL = n_lower;
     g->n = (int64_t)n_upper + n_lower;
     st = build_csr_device(*g, d_eu, d_ev, m, s);
     if (st != ABCORE_OK) break;
+    st = build_pieces(*g, s);
+    if (st != ABCORE_OK) break;
+    // every vertex enters the queues at most twice per computation
+    g->qcap = 2 * g->n + kLocalQueue;
     if ((st = ensure(&g->deg, g->n)) != ABCORE_OK) break;
-    if ((st = ensure(&g->queue, g->n + kLocalQueue)) != ABCORE_OK) break;
+    if ((st = ensure(&g->queue, (int64_t)kSub * g->qcap)) != ABCORE_OK) break;
+    if ((st = ensure(&g->alive_bits, (g->n + 31) / 32 + 1)) != ABCORE_OK) break;
+    if ((st = ensure(&g->part, (int64_t)kMaxBlocks * kPartFields)) != ABCORE_OK) break;
     hipError_t e = hipMalloc(&g->state, sizeof(PeelState));
     if (e == hipSuccess) e = hipHostMalloc(&g->h_state, sizeof(PeelState));
+    if (e == hipSuccess)
+      e = hipHostMalloc(&g->h_part, sizeof(int64_t) * kMaxBlocks * kPartFields);
     if (e != hipSuccess) {
       set_error("abcore_build_csr: state allocation failed: %s", hipGetErrorString(e));
       st = ABCORE_ENOMEM;
       break;
     }
     memset(g->h_state, 0, sizeof(PeelState));
+    if (query_persistent_grids(*g) != hipSuccess || g->persistent_grid <= 0 ||
+        g->kcore_grid <= 0)
+      g->peel_mode = 1;  // no co-residency information: one kernel per round
+    (void)prepare_pull_kernel(*g);
+    if (launch_init_state(*g, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+      set_error("abcore_build_csr: state initialisation failed");
+      st = ABCORE_EDEVICE;
+      break;
+    }
   } while (0);
   if (st != ABCORE_OK) {
     free_graph(g);
@@ -293,20 +362,27 @@ abcore_status abcore_set_option(abcore_graph h, int32_t option, int64_t value) {
   }
   switch (option) {
     case ABCORE_OPT_PEEL_MODE:
-      if (value > 1) {
+      if (value > 2 || (value == 2 && g->persistent_grid <= 0)) {
         set_error("abcore_set_option: peel mode %lld not available", (long long)value);
         return ABCORE_EINVAL;
       }
-      g->peel_mode = value == 0 ? 1 : (int)value;
+      g->peel_mode = value == 0 ? (g->persistent_grid > 0 ? 2 : 1) : (int)value;
       return ABCORE_OK;
     case ABCORE_OPT_GRID:
-      g->grid = (int)std::min<int64_t>(value, 1 << 20);
+      g->grid = (int)std::min<int64_t>(value, kMaxBlocks);
+      return ABCORE_OK;
+    case ABCORE_OPT_ROUNDS_PER_SYNC:
+      g->rounds_per_sync = value == 0 ? 16 : (int)std::min<int64_t>(value, 4096);
       return ABCORE_OK;
     case ABCORE_OPT_TIMING:
       g->timing = value != 0;
       return ABCORE_OK;
-    case ABCORE_OPT_ROUNDS_PER_SYNC:
-      g->rounds_per_sync = value == 0 ? 16 : (int)std::min<int64_t>(value, 4096);
+    case ABCORE_OPT_PULL:
+      if (value > 2) {
+        set_error("abcore_set_option: pull mode %lld unknown", (long long)value);
+        return ABCORE_EINVAL;
+      }
+      g->pull_mode = (int)value;
       return ABCORE_OK;
     default:
       set_error("abcore_set_option: unknown option %d", option);
@@ -314,29 +390,31 @@ abcore_status abcore_set_option(abcore_graph h, int32_t option, int64_t value) {
   }
 }
 
-abcore_status abcore_peel_timing(abcore_graph h, double *ms, int64_t *launches, int32_t reset) {
+abcore_status abcore_kernel_timing(abcore_graph h, int32_t kernel, double *ms,
+                                   int64_t *launches, int32_t reset) {
   Graph *g = reinterpret_cast<Graph *>(h);
-  if (!g) {
-    set_error("abcore_peel_timing: null handle");
+  if (!g || kernel < 0 || kernel > 3) {
+    set_error("abcore_kernel_timing: null handle or unknown kernel kind");
     return ABCORE_EINVAL;
   }
   CHK(hipSetDevice(g->device));
   double total = 0.0;
-  for (auto &pr : g->events) {
+  auto &ev = g->events[kernel];
+  for (auto &pr : ev) {
     CHK(hipEventSynchronize(pr.second));
     float t = 0.f;
     CHK(hipEventElapsedTime(&t, pr.first, pr.second));
     total += t;
   }
   if (ms) *ms = total;
-  if (launches) *launches = g->timed_launches;
+  if (launches) *launches = g->timed_launches[kernel];
   if (reset) {
-    for (auto &pr : g->events) {
+    for (auto &pr : ev) {
       g->event_pool.push_back(pr.first);
       g->event_pool.push_back(pr.second);
     }
-    g->events.clear();
-    g->timed_launches = 0;
+    ev.clear();
+    g->timed_launches[kernel] = 0;
   }
   return ABCORE_OK;
 }
@@ -350,8 +428,7 @@ abcore_status abcore_core_numbers(abcore_graph h, int32_t *d_core, int32_t *max_
   }
   CHK(hipSetDevice(g->device));
   hipStream_t s = as_stream(stream);
-  abcore_status st = compute_core(*g, s);
-  if (st != ABCORE_OK) return st;
+  TRY(compute_core(*g, s));
   if (d_core && g->n > 0)
     CHK(hipMemcpyAsync(d_core, g->core, sizeof(int32_t) * g->n, hipMemcpyDeviceToDevice, s));
   CHK(hipStreamSynchronize(s));
@@ -367,8 +444,7 @@ abcore_status abcore_components(abcore_graph h, int32_t *d_comp, void *stream) {
   }
   CHK(hipSetDevice(g->device));
   hipStream_t s = as_stream(stream);
-  abcore_status st = compute_components(*g, s);
-  if (st != ABCORE_OK) return st;
+  TRY(compute_components(*g, s));
   if (d_comp && g->n > 0)
     CHK(hipMemcpyAsync(d_comp, g->comp, sizeof(int32_t) * g->n, hipMemcpyDeviceToDevice, s));
   CHK(hipStreamSynchronize(s));
@@ -393,37 +469,56 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
   CHK(hipSetDevice(g->device));
   hipStream_t s = as_stream(stream);
   const int32_t thrU = clamp_thr(alpha), thrL = clamp_thr(beta);
-  int64_t launches = 0, uncertain = 0;
-  abcore_status st = ABCORE_OK;
+  int64_t launches = 0;
   if (algo == ABCORE_GCC) {
-    CHK(launch_init_state(g->state, s));
-    CHK(launch_scan_gcc(*g, thrU, thrL, s));
-    if ((st = run_rounds(*g, kGCC, thrU, thrL, s, &launches)) != ABCORE_OK) return st;
-    CHK(launch_pack(*g, thrU, thrL, d_bitmask, s));
+    const bool pull = g->pull_mode != 1;
+    CHK(launch_init_state(*g, s));
+    CHK(timed(*g, ABCORE_KERNEL_SCAN, s, 1,
+              [&] { return launch_scan_gcc(*g, thrU, thrL, pull, s); }));
+    if (pull)
+      CHK(timed(*g, ABCORE_KERNEL_PULL, s, 1,
+                [&] { return launch_pull_round(*g, thrU, thrL, s); }));
+    TRY(run_peel(*g, kGCC, thrU, thrL, s, &launches));
+    CHK(timed(*g, ABCORE_KERNEL_PACK, s, 1,
+              [&] { return launch_pack(*g, thrU, thrL, d_bitmask, s); }));
   } else {
-    if ((st = compute_core(*g, s)) != ABCORE_OK) return st;
+    TRY(compute_core(*g, s));
     const int32_t dl = std::min(thrU, thrL), dq = std::max(thrU, thrL);
-    CHK(launch_init_state(g->state, s));
+    CHK(launch_init_state(*g, s));
     if (dl == dq) {
       CHK(launch_pack_from_core(*g, dl, d_bitmask, s));
     } else {
-      if ((st = ensure(&g->list, g->n)) != ABCORE_OK) return st;
-      CHK(launch_classify(*g, thrU, thrL, dl, dq, s));
+      CHK(launch_classify(*g, dl, dq, s));
       CHK(launch_restricted_init(*g, thrU, thrL, dl, s));
-      if ((st = run_rounds(*g, kGCCPlus, thrU, thrL, s, &launches)) != ABCORE_OK) return st;
+      TRY(run_peel(*g, kGCCPlus, thrU, thrL, s, &launches));
       CHK(launch_pack(*g, thrU, thrL, d_bitmask, s));
     }
   }
   if (stats) {
-    if ((st = read_state(*g, s)) != ABCORE_OK) return st;
+    TRY(read_state(*g, s));
+    abcore_status st = ABCORE_OK;
+    const int64_t entries = sum_part(*g, kPartEntries, s, &st);
+    if (st != ABCORE_OK) return st;
     const PeelState &p = *g->h_state;
-    if (algo == ABCORE_GCC_PLUS) uncertain = p.aux0;
-    stats->removed = p.tail;
+    // queue items count pieces of split rows, so removals are counted from
+    // the result: every vertex outside the core
+    const int64_t nwords = (g->n + 31) / 32;
+    std::vector<uint32_t> words((size_t)std::max<int64_t>(nwords, 1));
+    if (nwords > 0) {
+      CHK(hipMemcpyAsync(words.data(), d_bitmask, sizeof(uint32_t) * nwords,
+                         hipMemcpyDeviceToHost, s));
+      CHK(hipStreamSynchronize(s));
+    }
+    int64_t members = 0;
+    for (int64_t i = 0; i < nwords; ++i) members += __builtin_popcount(words[i]);
+    const bool plus = algo == ABCORE_GCC_PLUS;
+    stats->removed = g->n - members;
     stats->rounds = p.rounds;
-    stats->entries_read = p.entries;
+    stats->entries_read = entries;
     stats->initial = p.first;
-    stats->uncertain = uncertain;
+    stats->uncertain = plus ? p.aux0 : 0;
     stats->launches = launches;
+    stats->pulled = p.pulled;
   }
   return ABCORE_OK;
 }
@@ -447,13 +542,12 @@ abcore_status abcore_query(abcore_graph h, abcore_edge_update upd, uint32_t alph
   }
   CHK(hipSetDevice(g->device));
   hipStream_t s = as_stream(stream);
-  abcore_status st;
-  if ((st = compute_components(*g, s)) != ABCORE_OK) return st;
-  if ((st = ensure_delta(*g, s)) != ABCORE_OK) return st;
+  TRY(compute_components(*g, s));
+  TRY(ensure_delta(*g, s));
   // 1. apply the update (validated on the device before any write)
-  CHK(launch_init_state(g->state, s));
+  CHK(launch_init_state(*g, s));
   CHK(launch_update(*g, upd.u, upd.v, upd.op, g->delta.count, s));
-  if ((st = read_state(*g, s)) != ABCORE_OK) return st;
+  TRY(read_state(*g, s));
   const int32_t ustat = g->h_state->status;
   if (ustat == -(int32_t)ABCORE_EEXIST) {
     set_error("abcore_query: edge (%d, %d) already present", upd.u, upd.v);
@@ -479,11 +573,11 @@ abcore_status abcore_query(abcore_graph h, abcore_edge_update upd, uint32_t alph
   // 3. scoped peel: Algorithm 1 on the component(s) of u and v only
   const int32_t thrU = clamp_thr(alpha), thrL = clamp_thr(beta);
   int64_t launches = 0;
-  CHK(launch_init_state(g->state, s));
+  CHK(launch_init_state(*g, s));
   CHK(launch_scan_component_of(*g, thrU, thrL, x, y, s));
-  if ((st = run_rounds(*g, kGCC, thrU, thrL, s, &launches)) != ABCORE_OK) return st;
+  TRY(run_peel(*g, kGCC, thrU, thrL, s, &launches));
   CHK(launch_answer(*g, x, y, thrU, thrL, s));
-  if ((st = read_state(*g, s)) != ABCORE_OK) return st;
+  TRY(read_state(*g, s));
   const int32_t bits = g->h_state->aux0;
   *h_answer = (bits & 3) == 3 ? 1 : 0;
   if (h_endpoint_bits) *h_endpoint_bits = (uint32_t)bits;

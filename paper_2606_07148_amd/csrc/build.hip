@@ -63,6 +63,44 @@ __global__ void widen_kernel(const int32_t *__restrict__ deg, int64_t n,
     out[i] = i < n ? (int64_t)deg[i] : 0;
 }
 
+// Piece counts of every row (rows longer than kPiece entries are split) and
+// split-row flags, each followed by a zero so an exclusive scan yields the
+// totals in the last slot.
+__global__ void count_pieces_kernel(const int64_t *__restrict__ off, int64_t n,
+                                    int64_t *__restrict__ np, int64_t *__restrict__ hv) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= n; x += stride) {
+    const int64_t d = x < n ? off[x + 1] - off[x] : 0;
+    np[x] = d > kPiece ? (d + kPiece - 1) / kPiece : 0;
+    hv[x] = d > kPiece ? 1 : 0;
+  }
+}
+
+__global__ void fill_pieces_kernel(const int64_t *__restrict__ off, int64_t n,
+                                   const int64_t *__restrict__ first,
+                                   const int64_t *__restrict__ hfirst,
+                                   int32_t *__restrict__ piece_row,
+                                   int64_t *__restrict__ piece_start,
+                                   int32_t *__restrict__ piece_first,
+                                   int32_t *__restrict__ heavy_rows) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
+    const int64_t d = off[x + 1] - off[x];
+    if (d > kPiece) {
+      const int64_t f = first[x];
+      const int64_t np = (d + kPiece - 1) / kPiece;
+      piece_first[x] = (int32_t)f;
+      heavy_rows[hfirst[x]] = (int32_t)x;
+      for (int64_t k = 0; k < np; ++k) {
+        piece_row[f + k] = (int32_t)x;
+        piece_start[f + k] = off[x] + k * kPiece;
+      }
+    } else {
+      piece_first[x] = -1;
+    }
+  }
+}
+
 int bits_for(uint64_t maxkey) {
   int b = 0;
   while (b < 64 && (maxkey >> b) != 0) ++b;
@@ -166,6 +204,60 @@ done:
   if (deg64) (void)hipFree(deg64);
   return status;
 #undef BCHK
+}
+
+// Splits rows longer than kPiece entries into pieces (see Graph).
+abcore_status build_pieces(Graph &g, hipStream_t s) {
+#define PCHK(x)                                                                     \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess) {                                                         \
+      set_error("piece build: %s failed: %s", #x, hipGetErrorString(e_));           \
+      status = (e_ == hipErrorOutOfMemory) ? ABCORE_ENOMEM : ABCORE_EDEVICE;        \
+      goto done;                                                                    \
+    }                                                                               \
+  } while (0)
+  abcore_status status = ABCORE_OK;
+  int64_t *np = nullptr, *hv = nullptr, *first = nullptr, *hfirst = nullptr;
+  void *temp = nullptr;
+  size_t temp_bytes = 0;
+  int64_t h_tot[4] = {0, 0, 0, 0};
+  const int grid = std::max(1, std::min(g.cu_count * 8, (int)((g.n + 256) / 256)));
+  PCHK(hipMalloc(&np, sizeof(int64_t) * (g.n + 1)));
+  PCHK(hipMalloc(&hv, sizeof(int64_t) * (g.n + 1)));
+  PCHK(hipMalloc(&first, sizeof(int64_t) * (g.n + 1)));
+  PCHK(hipMalloc(&hfirst, sizeof(int64_t) * (g.n + 1)));
+  count_pieces_kernel<<<grid, 256, 0, s>>>(g.off, g.n, np, hv);
+  PCHK(hipGetLastError());
+  PCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, temp_bytes, np, first, (int)(g.n + 1), s));
+  PCHK(hipMalloc(&temp, std::max<size_t>(temp_bytes, 16)));
+  PCHK(hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, np, first, (int)(g.n + 1), s));
+  PCHK(hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, hv, hfirst, (int)(g.n + 1), s));
+  PCHK(hipMemcpyAsync(&h_tot[0], first + g.n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  PCHK(hipMemcpyAsync(&h_tot[1], first + g.nU, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  PCHK(hipMemcpyAsync(&h_tot[2], hfirst + g.n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  PCHK(hipMemcpyAsync(&h_tot[3], hfirst + g.nU, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  PCHK(hipStreamSynchronize(s));
+  g.npieces = h_tot[0];
+  g.npieces_upper = h_tot[1];
+  g.nheavy = h_tot[2];
+  g.nheavy_upper = h_tot[3];
+  PCHK(hipMalloc(&g.piece_row, sizeof(int32_t) * std::max<int64_t>(g.npieces, 1)));
+  PCHK(hipMalloc(&g.piece_start, sizeof(int64_t) * std::max<int64_t>(g.npieces, 1)));
+  PCHK(hipMalloc(&g.piece_first, sizeof(int32_t) * std::max<int64_t>(g.n, 1)));
+  PCHK(hipMalloc(&g.heavy_rows, sizeof(int32_t) * std::max<int64_t>(g.nheavy, 1)));
+  fill_pieces_kernel<<<grid, 256, 0, s>>>(g.off, g.n, first, hfirst, g.piece_row, g.piece_start,
+                                          g.piece_first, g.heavy_rows);
+  PCHK(hipGetLastError());
+  PCHK(hipStreamSynchronize(s));
+done:
+  if (np) (void)hipFree(np);
+  if (hv) (void)hipFree(hv);
+  if (first) (void)hipFree(first);
+  if (hfirst) (void)hipFree(hfirst);
+  if (temp) (void)hipFree(temp);
+  return status;
+#undef PCHK
 }
 
 }  // namespace abc

@@ -9,6 +9,18 @@
 // spread over the wave).  A neighbour is decremented with one device-scope
 // atomic; the unique decrement that takes it from its threshold to one below
 // enqueues it (every vertex enters the queue at most once).
+//
+// Rounds run either inside one cooperatively launched kernel separated by a
+// grid barrier (no host involvement), or one kernel per round.  The first
+// round of GCC may run in pull form: every vertex that survived the scan
+// recounts its surviving neighbours from an LDS-staged bitmap, which replaces
+// the scan frontier's atomic decrements (most of a power-law peel) by one
+// streaming pass over the surviving rows.
+//
+// Same-address device-scope atomics and single-thread chains of coherent
+// loads are the expensive operations here (about 11 ns and 1 us each), so
+// appends are aggregated per workgroup, partial results live in per-workgroup
+// slots, and round bookkeeping is done by a whole wave in parallel.
 #include <algorithm>
 
 #include "abcore_internal.h"
@@ -16,140 +28,322 @@
 
 namespace abc {
 
+constexpr int kScanBlock = 512;
+constexpr int kScanChunk = 4096;  // vertices per workgroup chunk (4 per thread, 2 passes)
+
 // ---------------------------------------------------------------- state --
 
-__global__ void init_state_kernel(PeelState *st) {
-  PeelState z = {};
-  z.min_alive = 0x7FFFFFFF;
-  *st = z;
+__global__ void init_state_kernel(int32_t *st_words, int nwords, int64_t *part, int nparts) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x)
+    st_words[i] = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nparts; i += gridDim.x * blockDim.x)
+    part[i] = 0;
 }
 
-hipError_t launch_init_state(PeelState *st, hipStream_t s) {
-  init_state_kernel<<<1, 1, 0, s>>>(st);
+hipError_t launch_init_state(Graph &g, hipStream_t s) {
+  static_assert(sizeof(PeelState) % 4 == 0, "state must be whole words");
+  init_state_kernel<<<8, 256, 0, s>>>(reinterpret_cast<int32_t *>(g.state),
+                                      (int)(sizeof(PeelState) / 4), g.part,
+                                      kMaxBlocks * kPartFields);
   return hipGetLastError();
 }
 
 int peel_grid(const Graph &g) {
-  if (g.grid > 0) return g.grid;
-  return g.cu_count * 8;  // 8 workgroups of 4 waves per CU: 32 waves per CU
+  if (g.grid > 0) return std::min(g.grid, kMaxBlocks);
+  return std::min(g.cu_count * 4, kMaxBlocks);  // 4 workgroups of 8 waves per CU
 }
+
+static int flat_grid(const Graph &g, int64_t items, int per_block) {
+  int64_t b = (items + per_block - 1) / per_block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, std::min(g.cu_count * 8, kMaxBlocks)));
+}
+
+static int scan_grid(const Graph &g) {
+  int64_t chunks = (g.n + kScanChunk - 1) / kScanChunk;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(chunks, std::min(g.cu_count * 4, kMaxBlocks)));
+}
+
+PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL) {
+  PeelArgs a;
+  a.off = g.off;
+  a.cols = g.cols;
+  a.deg = g.deg;
+  a.queue = g.queue;
+  a.qcap = g.qcap;
+  a.st = g.state;
+  a.part = g.part;
+  a.ins_head = g.delta.count > 0 ? g.delta.head : nullptr;
+  a.ins_next = g.delta.next;
+  a.ins_other = g.delta.other;
+  a.core = g.core;
+  a.piece_row = g.piece_row;
+  a.piece_start = g.piece_start;
+  a.piece_first = g.piece_first;
+  a.nU = g.nU;
+  a.thrU = thrU;
+  a.thrL = thrL;
+  return a;
+}
+
+// Queue items: a vertex id x >= 0 (its whole row), or -(p + 2) for piece p
+// of a split row (kPiece entries of it).
+__device__ __forceinline__ int32_t piece_item(int32_t p) { return -(p + 2); }
+
+// Row, entry range and "first piece" flag of an item (x < 0 with x != -1 is
+// a piece; -1 is an empty lane).
+__device__ __forceinline__ void decode_item(const PeelArgs &a, int32_t x, int32_t &row,
+                                            int64_t &s, int &d, bool &first) {
+  row = -1;
+  s = 0;
+  d = 0;
+  first = false;
+  if (x >= 0) {
+    row = x;
+    s = a.off[x];
+    d = (int)(a.off[x + 1] - s);
+    first = true;
+  } else if (x < -1) {
+    const int32_t p = -x - 2;
+    row = a.piece_row[p];
+    s = a.piece_start[p];
+    const int64_t rs = a.off[row], re = a.off[row + 1];
+    d = (int)(min(s + kPiece, re) - s);
+    first = s == rs;
+  }
+}
+
+// Appends removed vertices; a split row is appended as its pieces so that
+// several waves share it.  Whole wave, uniform flow.
+__device__ __forceinline__ void push_removed(const PeelArgs &a, LocalQueue &lq, bool pred,
+                                             int32_t w) {
+  const int32_t pf = pred ? a.piece_first[w] : -1;
+  lq.push(pred && pf < 0, w);
+  if (__ballot(pf >= 0)) {
+    int np = 0;
+    if (pf >= 0) np = (int)((a.off[w + 1] - a.off[w] + kPiece - 1) / kPiece);
+    for (int k = 0; __ballot(k < np); ++k) lq.push(k < np, piece_item(pf + k));
+  }
+}
+
+// Adds a workgroup total to its partial slot (block-exclusive, no atomics).
+__device__ __forceinline__ void add_part(int64_t *part, int field, int64_t v, int64_t *s_acc) {
+  const int64_t w = wave_sum64(v);
+  if (threadIdx.x == 0) *s_acc = 0;
+  __syncthreads();
+  if (lane_id() == 0 && w != 0) atomicAdd((unsigned long long *)s_acc, (unsigned long long)w);
+  __syncthreads();
+  if (threadIdx.x == 0 && *s_acc != 0) part[(int64_t)blockIdx.x * kPartFields + field] += *s_acc;
+}
+
+// Collects a workgroup's appended vertices of one chunk in LDS and appends
+// them to its sub-queue with one atomic.
+struct ScanCollector {
+  int32_t buf[kScanChunk];
+  int count;
+  int base;
+
+  // up to 4 items per thread; the whole workgroup calls in uniform flow
+  __device__ __forceinline__ void append(const int32_t *items, int cnt) {
+    const int incl = wave_incl_scan(cnt);
+    int b = 0;
+    if (lane_id() == kWave - 1 && incl > 0) b = atomicAdd(&count, incl);
+    b = __shfl(b, kWave - 1, kWave);
+    int pos = b + incl - cnt;
+    for (int j = 0; j < cnt; ++j) buf[pos + j] = items[j];
+  }
+
+  __device__ __forceinline__ void flush(int32_t *q, int32_t *tail) {
+    __syncthreads();
+    const int c = count;
+    if (threadIdx.x == 0) base = c > 0 ? atomicAdd(tail, c) : 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < c; i += blockDim.x) q[base + i] = buf[i];
+    __syncthreads();
+    if (threadIdx.x == 0) count = 0;
+    __syncthreads();
+  }
+};
 
 // ----------------------------------------------------------- scan phase --
 // Algorithm 1, scan phase: deg <- deg0 for every vertex and every vertex
 // below its threshold (alpha for upper ids, beta for lower ids: a range check
 // on the unified id) is appended to the frontier.  Four vertices per thread
-// with 16-byte loads; one queue atomic per workgroup tile.
+// with 16-byte loads.  Optionally writes the survivor bitmap used by a
+// pull-form first round, and per-workgroup sums of the frontier size and
+// degree (the push/pull decision).
 
-__global__ __launch_bounds__(kBlock) void scan_gcc_kernel(const int32_t *__restrict__ deg0,
-                                                          int32_t *__restrict__ deg,
-                                                          int32_t *__restrict__ q,
-                                                          PeelState *st, int64_t n,
-                                                          int32_t nU, int32_t thrU,
-                                                          int32_t thrL) {
-  __shared__ int s_wsum[kWavesPerBlock + 1];
-  const int64_t tile = (int64_t)kBlock * 4;
-  for (int64_t base = (int64_t)blockIdx.x * tile; base < n; base += (int64_t)gridDim.x * tile) {
-    const int64_t x0 = base + (int64_t)threadIdx.x * 4;
-    int32_t d[4] = {0, 0, 0, 0};
-    bool p[4] = {false, false, false, false};
-    if (x0 + 3 < n) {
-      int4 v = *reinterpret_cast<const int4 *>(deg0 + x0);
-      *reinterpret_cast<int4 *>(deg + x0) = v;
-      d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+__global__ __launch_bounds__(kScanBlock) void scan_gcc_kernel(PeelArgs a,
+                                                              const int32_t *__restrict__ deg0,
+                                                              uint32_t *__restrict__ bits,
+                                                              int64_t n) {
+  __shared__ ScanCollector col;
+  __shared__ int64_t s_acc;
+  if (threadIdx.x == 0) col.count = 0;
+  __syncthreads();
+  const int sub = blockIdx.x % kSub;
+  int32_t *q = a.queue + (int64_t)sub * a.qcap;
+  int64_t f0 = 0, f0deg = 0;
+  for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < n;
+       cb += (int64_t)gridDim.x * kScanChunk) {
+    for (int t = 0; t < kScanChunk; t += kScanBlock * 4) {
+      const int64_t x0 = cb + t + (int64_t)threadIdx.x * 4;
+      int32_t d[4] = {0, 0, 0, 0};
+      bool p[4] = {false, false, false, false};
+      uint32_t alive = 0;
+      if (x0 + 3 < n) {
+        int4 v = *reinterpret_cast<const int4 *>(deg0 + x0);
+        *reinterpret_cast<int4 *>(a.deg + x0) = v;
+        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) p[j] = d[j] < ((x0 + j) < nU ? thrU : thrL);
-    } else {
+        for (int j = 0; j < 4; ++j) {
+          p[j] = d[j] < ((x0 + j) < a.nU ? a.thrU : a.thrL);
+          alive |= (uint32_t)(!p[j]) << j;
+        }
+      } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        int64_t x = x0 + j;
-        if (x < n) {
-          d[j] = deg0[x];
-          deg[x] = d[j];
-          p[j] = d[j] < (x < nU ? thrU : thrL);
+        for (int j = 0; j < 4; ++j) {
+          int64_t x = x0 + j;
+          if (x < n) {
+            d[j] = deg0[x];
+            a.deg[x] = d[j];
+            p[j] = d[j] < (x < a.nU ? a.thrU : a.thrL);
+            alive |= (uint32_t)(!p[j]) << j;
+          }
         }
       }
-    }
-    int cnt = (int)p[0] + (int)p[1] + (int)p[2] + (int)p[3];
-    int pos = block_reserve(cnt, &st->tail, s_wsum);
+      if (bits != nullptr) {
+        // eight consecutive threads hold the 32 vertices of one bitmap word
+        uint32_t w = alive << (4 * (lane_id() & 7));
+        w |= __shfl_xor(w, 1, kWave);
+        w |= __shfl_xor(w, 2, kWave);
+        w |= __shfl_xor(w, 4, kWave);
+        if ((lane_id() & 7) == 0 && x0 < n) bits[x0 / 32] = w;
+      }
+      int32_t items[4];
+      int cnt = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (p[j]) q[pos++] = (int32_t)(x0 + j);
+      for (int j = 0; j < 4; ++j) {
+        if (p[j]) {
+          items[cnt++] = (int32_t)(x0 + j);
+          f0deg += d[j];
+        }
+      }
+      f0 += cnt;
+      col.append(items, cnt);
+    }
+    col.flush(q, &a.st->tail[sub][0]);
   }
-  if (last_block_done(&st->finished)) {
-    st->lo = 0;
-    st->hi = atomicAdd(&st->tail, 0);
-    st->first = st->hi;
-    st->rounds = 0;
-    st->finished = 0;
-  }
+  add_part(a.part, kPartF0, f0, &s_acc);
+  add_part(a.part, kPartF0Deg, f0deg, &s_acc);
+  if (last_block_done<false>(a.st)) start_rounds_wave(a.st);
 }
 
-hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s) {
-  int64_t tiles = (g.n + kBlock * 4 - 1) / (kBlock * 4);
-  int grid = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), (int64_t)g.cu_count * 8);
-  scan_gcc_kernel<<<grid, kBlock, 0, s>>>(g.deg0, g.deg, g.queue, g.state, g.n, g.nU, thrU,
-                                          thrL);
+hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, bool want_bits,
+                           hipStream_t s) {
+  PeelArgs a = make_args(g, thrU, thrL);
+  scan_gcc_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, g.deg0,
+                                                      want_bits ? g.alive_bits : nullptr, g.n);
   return hipGetLastError();
 }
 
 // GFQ (Sec. V): the scan restricted to the affected component(s); vertices of
 // other components keep stale degrees and are never reached by the peel.
-__global__ __launch_bounds__(kBlock) void scan_component_kernel(
-    const int32_t *__restrict__ deg0, const int32_t *__restrict__ comp,
-    int32_t *__restrict__ deg, int32_t *__restrict__ q, PeelState *st, int64_t n, int32_t nU,
-    int32_t thrU, int32_t thrL, int32_t vx, int32_t vy) {
-  __shared__ int s_wsum[kWavesPerBlock + 1];
+// The labels are read on the device from the endpoints x and y, after the
+// component maintenance of the update has run on the same stream.
+__global__ __launch_bounds__(kScanBlock) void scan_component_kernel(
+    PeelArgs a, const int32_t *__restrict__ deg0, const int32_t *__restrict__ comp, int64_t n,
+    int32_t vx, int32_t vy) {
+  __shared__ ScanCollector col;
+  if (threadIdx.x == 0) col.count = 0;
+  __syncthreads();
   const int32_t c1 = comp[vx], c2 = comp[vy];
-  const int64_t tile = (int64_t)kBlock * 4;
-  for (int64_t base = (int64_t)blockIdx.x * tile; base < n; base += (int64_t)gridDim.x * tile) {
-    const int64_t x0 = base + (int64_t)threadIdx.x * 4;
-    bool p[4] = {false, false, false, false};
-    if (x0 + 3 < n) {
-      int4 c = *reinterpret_cast<const int4 *>(comp + x0);
-      int cc[4] = {c.x, c.y, c.z, c.w};
+  const int sub = blockIdx.x % kSub;
+  int32_t *q = a.queue + (int64_t)sub * a.qcap;
+  for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < n;
+       cb += (int64_t)gridDim.x * kScanChunk) {
+    for (int t = 0; t < kScanChunk; t += kScanBlock * 4) {
+      const int64_t x0 = cb + t + (int64_t)threadIdx.x * 4;
+      int32_t cc[4] = {-1, -1, -1, -1};
+      if (x0 + 3 < n) {
+        int4 c = *reinterpret_cast<const int4 *>(comp + x0);
+        cc[0] = c.x; cc[1] = c.y; cc[2] = c.z; cc[3] = c.w;
+      } else {
+        for (int j = 0; j < 4; ++j)
+          if (x0 + j < n) cc[j] = comp[x0 + j];
+      }
+      int32_t items[4];
+      int cnt = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        if (cc[j] == c1 || cc[j] == c2) {
-          int32_t d = deg0[x0 + j];
-          deg[x0 + j] = d;
-          p[j] = d < ((x0 + j) < nU ? thrU : thrL);
+        if (x0 + j < n && (cc[j] == c1 || cc[j] == c2)) {
+          const int32_t d = deg0[x0 + j];
+          a.deg[x0 + j] = d;
+          if (d < ((x0 + j) < a.nU ? a.thrU : a.thrL)) items[cnt++] = (int32_t)(x0 + j);
         }
       }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        int64_t x = x0 + j;
-        if (x < n && (comp[x] == c1 || comp[x] == c2)) {
-          int32_t d = deg0[x];
-          deg[x] = d;
-          p[j] = d < (x < nU ? thrU : thrL);
-        }
-      }
+      col.append(items, cnt);
     }
-    int cnt = (int)p[0] + (int)p[1] + (int)p[2] + (int)p[3];
-    int pos = block_reserve(cnt, &st->tail, s_wsum);
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (p[j]) q[pos++] = (int32_t)(x0 + j);
+    col.flush(q, &a.st->tail[sub][0]);
   }
-  if (last_block_done(&st->finished)) {
-    st->lo = 0;
-    st->hi = atomicAdd(&st->tail, 0);
-    st->first = st->hi;
-    st->rounds = 0;
-    st->finished = 0;
-  }
+  if (last_block_done<false>(a.st)) start_rounds_wave(a.st);
 }
 
-// Labels are read on the device from the endpoints x and y, after the
-// component maintenance of the update has run on the same stream.
 hipError_t launch_scan_component_of(Graph &g, int32_t thrU, int32_t thrL, int32_t x, int32_t y,
                                     hipStream_t s) {
-  int64_t tiles = (g.n + kBlock * 4 - 1) / (kBlock * 4);
-  int grid = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), (int64_t)g.cu_count * 8);
-  scan_component_kernel<<<grid, kBlock, 0, s>>>(g.deg0, g.comp, g.deg, g.queue, g.state, g.n,
-                                                g.nU, thrU, thrL, x, y);
+  PeelArgs a = make_args(g, thrU, thrL);
+  scan_component_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, g.deg0, g.comp, g.n, x, y);
   return hipGetLastError();
+}
+
+// ------------------------------------------------- edge-balanced walking --
+// Lane L of step s of a wave batch handles entry s*64+L of the concatenated
+// adjacency lists of the batch's vertices.  The owner of an entry is found
+// by a binary search over the wave's inclusive degree prefix, in registers
+// through cross-lane reads.
+struct BatchWalk {
+  int incl, excl, total;
+  int s_lo, s_hi;
+
+  __device__ __forceinline__ void init(int64_t s, int d) {
+    incl = wave_incl_scan(d);
+    total = __shfl(incl, kWave - 1, kWave);
+    excl = incl - d;
+    s_lo = (int)(uint32_t)(uint64_t)s;
+    s_hi = (int)((uint64_t)s >> 32);
+  }
+  // For entry kk (< total): owner lane j and the entry's position in cols.
+  __device__ __forceinline__ int64_t locate(int kk, int &j) const {
+    j = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+      int v = __shfl(incl, j + step - 1, kWave);
+      if (v <= kk) j += step;
+    }
+    const int ex = __shfl(excl, j, kWave);
+    const uint32_t lo32 = (uint32_t)__shfl(s_lo, j, kWave);
+    const uint32_t hi32 = (uint32_t)__shfl(s_hi, j, kWave);
+    return (int64_t)(((uint64_t)hi32 << 32) | lo32) + (kk - ex);
+  }
+};
+
+// Adds, for every owner lane, the number of its entries of this step whose
+// flag is set (entries of one owner are contiguous lanes of the step).
+__device__ __forceinline__ void segmented_count(int32_t *cnt, int j, bool act, bool ok,
+                                                int nact) {
+  const int jprev = __shfl_up(j, 1, kWave);
+  const bool start = act && (lane_id() == 0 || jprev != j);
+  const uint64_t starts = __ballot(start);
+  const uint64_t okm = __ballot(ok);
+  if (start) {
+    const int L = lane_id();
+    const uint64_t le = L == 63 ? ~0ull : ((1ull << (L + 1)) - 1);
+    const uint64_t rest = starts & ~le;
+    const int end = rest ? __builtin_ctzll(rest) : nact;
+    const uint64_t upto = end >= 64 ? ~0ull : ((1ull << end) - 1);
+    const uint64_t from = (1ull << L) - 1;
+    cnt[j] += __popcll(okm & upto & ~from);
+  }
+  __builtin_amdgcn_wave_barrier();
 }
 
 // ----------------------------------------------------------- peel phase --
@@ -160,64 +354,67 @@ hipError_t launch_scan_component_of(Graph &g, int32_t thrU, int32_t thrL, int32_
 // is already removed or queued -- no atomic is needed.  GCC+ certain members
 // (kDegIn) are skipped; certain non-members (kDegOut) fail the threshold test.
 template <int KIND>
-__device__ __forceinline__ bool peel_visit(const PeelArgs &a, int32_t w, int32_t thrU,
-                                           int32_t thrL, int32_t level) {
+__device__ __forceinline__ bool peel_visit(const PeelArgs &a, int32_t w, int32_t level) {
   if (w < 0) return false;  // deleted edge
-  const int32_t t = (KIND == kKCore) ? level + 1 : (w < a.nU ? thrU : thrL);
+  const int32_t t = (KIND == kKCore) ? level + 1 : (w < a.nU ? a.thrU : a.thrL);
   const int32_t dw = a.deg[w];
   if (dw < t) return false;
   if (KIND == kGCCPlus && dw == kDegIn) return false;
-  const int32_t old = atomicSub(&a.deg[w], 1);
-  if (old != t) return false;
-  if (KIND == kKCore) a.core[w] = level;
-  return true;
+  return atomicSub(&a.deg[w], 1) == t;
 }
 
-// Processes up to 64 removed vertices (x < 0 marks an empty lane) with
-// edge-balanced lanes: lane L of step s handles entry s*64+L of the
-// concatenated adjacency lists.  The owner of an entry is found by a
-// binary search over the wave's inclusive degree prefix (all in registers
-// via cross-lane reads).
+// Steps of 64 entries whose loads a wave issues together: each step is a
+// chain of dependent accesses (entry, degree, atomic), so independent steps
+// are interleaved to keep several in flight per wave.
+constexpr int kUnroll = 4;
+
+// Removes up to 64 queue items (vertices or pieces of split rows; -1 marks
+// an empty lane).
 template <int KIND>
-__device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t thrU,
-                                           int32_t thrL, int32_t level, LocalQueue &lq,
-                                           int64_t &entries) {
-  int64_t s = 0;
-  int d = 0;
-  if (x >= 0) {
-    s = a.off[x];
-    d = (int)(a.off[x + 1] - s);
-  }
-  const int incl = wave_incl_scan(d);
-  const int total = __shfl(incl, kWave - 1, kWave);
-  const int excl = incl - d;
-  const int s_lo = (int)(uint32_t)(uint64_t)s;
-  const int s_hi = (int)((uint64_t)s >> 32);
+__device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t level,
+                                           LocalQueue &lq, int64_t &entries) {
+  int32_t row;
+  int64_t s;
+  int d;
+  bool first;
+  decode_item(a, x, row, s, d, first);
+  BatchWalk bw;
+  bw.init(s, d);
   entries += d;
-  for (int base = 0; base < total; base += kWave) {
-    const int k = base + lane_id();
-    const int kk = k < total ? k : total - 1;
-    int j = 0;
+  for (int base = 0; base < bw.total; base += kUnroll * kWave) {
+    int32_t w[kUnroll];
 #pragma unroll
-    for (int step = 32; step > 0; step >>= 1) {
-      int v = __shfl(incl, j + step - 1, kWave);
-      if (v <= kk) j += step;
+    for (int u = 0; u < kUnroll; ++u) {
+      const int k = base + u * kWave + lane_id();
+      int j;
+      const int64_t pos = bw.locate(k < bw.total ? k : bw.total - 1, j);
+      w[u] = k < bw.total ? a.cols[pos] : -1;
     }
-    const int ex = __shfl(excl, j, kWave);
-    const uint32_t lo32 = (uint32_t)__shfl(s_lo, j, kWave);
-    const uint32_t hi32 = (uint32_t)__shfl(s_hi, j, kWave);
-    const int64_t start = (int64_t)(((uint64_t)hi32 << 32) | lo32);
-    bool push = false;
-    int32_t w = -1;
-    if (k < total) {
-      w = a.cols[start + (kk - ex)];
-      push = peel_visit<KIND>(a, w, thrU, thrL, level);
+    int32_t t[kUnroll], dw[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      t[u] = (KIND == kKCore) ? level + 1 : (w[u] < a.nU ? a.thrU : a.thrL);
+      dw[u] = w[u] >= 0 ? a.deg[w[u]] : -1;
     }
-    lq.push(push, w, a.queue, &a.st->tail);
+    bool push[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      // the plain load is a filter: degrees only decrease, so a stale value
+      // is never below the true one
+      bool live = w[u] >= 0 && dw[u] >= t[u];
+      if (KIND == kGCCPlus) live = live && dw[u] != kDegIn;
+      push[u] = live && atomicSub(&a.deg[w[u]], 1) == t[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (KIND == kKCore && push[u]) st_agent(&a.core[w[u]], level);
+      push_removed(a, lq, push[u], w[u]);
+    }
   }
   if (a.ins_head != nullptr) {
-    // edges inserted after the build: short per-vertex lists
-    int e = x >= 0 ? a.ins_head[x] : -1;
+    // edges inserted after the build: short per-vertex lists, walked once
+    // per row (by its first piece)
+    int e = (row >= 0 && first) ? a.ins_head[row] : -1;
     while (__ballot(e >= 0)) {
       bool push = false;
       int32_t w = -1;
@@ -225,70 +422,83 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
         w = a.ins_other[e];
         e = a.ins_next[e];
         entries += 1;
-        push = peel_visit<KIND>(a, w, thrU, thrL, level);
+        push = peel_visit<KIND>(a, w, level);
+        if (KIND == kKCore && push) st_agent(&a.core[w], level);
       }
-      lq.push(push, w, a.queue, &a.st->tail);
+      push_removed(a, lq, push, w);
     }
   }
 }
 
-// Adds the workgroup's adjacency-entry count to the state (stats).
-__device__ __forceinline__ void add_entries(int64_t entries, PeelState *st, int64_t *s_acc) {
-  int64_t w = wave_sum64(entries);
-  if (threadIdx.x == 0) *s_acc = 0;
-  __syncthreads();
-  if (lane_id() == 0 && w != 0) atomicAdd((unsigned long long *)s_acc, (unsigned long long)w);
-  __syncthreads();
-  if (threadIdx.x == 0 && *s_acc != 0)
-    atomicAdd((unsigned long long *)&st->entries, (unsigned long long)*s_acc);
-}
-
-// One round: the vertices Q[lo, hi) are removed.  The last workgroup to
-// finish advances the round to the items appended meanwhile.  Launched in
-// batches; launches after convergence return at once.
+// The work of one round over the current view; called by every thread.
 template <int KIND>
-__global__ __launch_bounds__(kBlock) void peel_round_kernel(PeelArgs a) {
-  __shared__ int32_t s_lq[kWavesPerBlock][kLocalQueue];
-  __shared__ int64_t s_acc;
-  PeelState *st = a.st;
-  const int32_t lo = st->lo, hi = st->hi;
-  if (lo >= hi) return;
-  const int32_t level = (KIND == kKCore) ? st->k : 0;
-  LocalQueue lq{s_lq[wave_in_block()], 0};
-  int64_t entries = 0;
-  const int gw = blockIdx.x * kWavesPerBlock + wave_in_block();
-  const int nw = gridDim.x * kWavesPerBlock;
-  for (int64_t b = (int64_t)lo + (int64_t)gw * kWave; b < hi; b += (int64_t)nw * kWave) {
-    const int64_t i = b + lane_id();
-    const int32_t x = i < hi ? a.queue[i] : -1;
-    peel_batch<KIND>(a, x, a.thrU, a.thrL, level, lq, entries);
-  }
-  lq.flush(a.queue, &st->tail);
-  add_entries(entries, st, &s_acc);
-  if (last_block_done(&st->finished)) {
-    st->lo = hi;
-    st->hi = atomicAdd(&st->tail, 0);
-    st->rounds += 1;
-    st->launches += 1;
-    st->finished = 0;
+__device__ __forceinline__ void peel_round_body(const PeelArgs &a, const RangeView &v,
+                                                int32_t level, LocalQueue &lq,
+                                                int64_t &entries) {
+  const int32_t total = v.pre[kSub];
+  const int waves = blockDim.x / kWave;
+  const int gw = blockIdx.x * waves + wave_in_block();
+  const int nw = gridDim.x * waves;
+  for (int64_t b = (int64_t)gw * kWave; b < total; b += (int64_t)nw * kWave) {
+    const int32_t i = (int32_t)(b + lane_id());
+    const int32_t x = i < total ? view_item(v, a.queue, a.qcap, i) : -1;
+    peel_batch<KIND>(a, x, level, lq, entries);
   }
 }
 
-static PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL) {
-  PeelArgs a;
-  a.off = g.off;
-  a.cols = g.cols;
-  a.deg = g.deg;
-  a.queue = g.queue;
-  a.st = g.state;
-  a.ins_head = g.delta.count > 0 ? g.delta.head : nullptr;
-  a.ins_next = g.delta.next;
-  a.ins_other = g.delta.other;
-  a.core = g.core;
-  a.nU = g.nU;
-  a.thrU = thrU;
-  a.thrL = thrL;
-  return a;
+// One round per launch; the last workgroup advances the round.  Launches
+// after convergence return at once.
+template <int KIND>
+__global__ __launch_bounds__(kPeelBlock) void peel_round_kernel(PeelArgs a) {
+  __shared__ int32_t s_lq[kPeelWaves][kLocalQueue];
+  __shared__ RangeView s_view;
+  __shared__ int s_cnt[kPeelWaves + 1];
+  __shared__ int64_t s_acc;
+  load_view(s_view, a.st);
+  if (s_view.pre[kSub] == 0) return;
+  LocalQueue lq = make_lq(s_lq[wave_in_block()], kLocalQueue, a);
+  int64_t entries = 0;
+  peel_round_body<KIND>(a, s_view, 0, lq, entries);
+  block_flush(lq, s_cnt);
+  add_part(a.part, kPartEntries, entries, &s_acc);
+  if (last_block_done<false>(a.st)) {
+    advance_round_wave(a.st);
+    if (lane_id() == 0) atomicAdd((unsigned long long *)&a.st->launches, 1ull);
+  }
+}
+
+// All rounds in one cooperative launch, separated by grid barriers.  Every
+// non-empty round removes a vertex, so more than max_rounds rounds can only
+// come from a fault; the loop then flags an abort instead of running on.
+// Queue items cross workgroups through agent-scope stores and loads and the
+// degrees only through atomics (plus stale-safe filter loads), so the
+// barriers need no cache write-back or invalidation.
+template <int KIND>
+__global__ __launch_bounds__(kPeelBlock) void peel_persistent_kernel(PeelArgs a,
+                                                                     int64_t max_rounds) {
+  __shared__ int32_t s_lq[kPeelWaves][kLocalQueue];
+  __shared__ RangeView s_view;
+  __shared__ int s_cnt[kPeelWaves + 1];
+  __shared__ int s_abort;
+  __shared__ int64_t s_acc;
+  LocalQueue lq = make_lq(s_lq[wave_in_block()], kLocalQueue, a);
+  int64_t entries = 0;
+  for (int64_t it = 0;; ++it) {
+    if (threadIdx.x == 0) s_abort = ld_agent(&a.st->abort_flag);
+    load_view(s_view, a.st);
+    if (s_view.pre[kSub] == 0 || s_abort) break;
+    if (it > max_rounds) {
+      if (threadIdx.x == 0) st_agent(&a.st->abort_flag, 1);
+      break;
+    }
+    peel_round_body<KIND>(a, s_view, 0, lq, entries);
+    block_flush(lq, s_cnt);
+    grid_sync<false>(a.st, [&] {
+      advance_round_wave(a.st);
+      if (lane_id() == 0) atomicAdd((unsigned long long *)&a.st->launches, 1ull);
+    });
+  }
+  add_part(a.part, kPartEntries, entries, &s_acc);
 }
 
 hipError_t launch_peel_rounds(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, int rounds,
@@ -297,10 +507,247 @@ hipError_t launch_peel_rounds(Graph &g, PeelKind kind, int32_t thrU, int32_t thr
   const int grid = peel_grid(g);
   for (int r = 0; r < rounds; ++r) {
     if (kind == kGCC)
-      peel_round_kernel<kGCC><<<grid, kBlock, 0, s>>>(a);
+      peel_round_kernel<kGCC><<<grid, kPeelBlock, 0, s>>>(a);
     else
-      peel_round_kernel<kGCCPlus><<<grid, kBlock, 0, s>>>(a);
+      peel_round_kernel<kGCCPlus><<<grid, kPeelBlock, 0, s>>>(a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_peel_persistent(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
+                                  hipStream_t s) {
+  PeelArgs a = make_args(g, thrU, thrL);
+  int64_t max_rounds = g.n + 2;
+  void *args[] = {&a, &max_rounds};
+  const void *fn = kind == kGCC ? reinterpret_cast<const void *>(&peel_persistent_kernel<kGCC>)
+                                : reinterpret_cast<const void *>(&peel_persistent_kernel<kGCCPlus>);
+  return hipLaunchCooperativeKernel(fn, dim3(g.persistent_grid), dim3(kPeelBlock), args, 0, s);
+}
+
+// ------------------------------------------------------ pull first round --
+// The first peel round in pull form.  After the scan, every vertex that
+// survived it counts its neighbours that survived it (bitmap lookups), which
+// is exactly its degree after the removal of the scan frontier; those now
+// below their threshold form the second frontier.  The frontier of the scan
+// itself is then never walked.  Upper rows look up lower vertices and lower
+// rows upper vertices, so each phase stages one layer's bitmap in LDS when
+// it fits.  Rows longer than kPiece are counted piece by piece (balanced
+// batches); a row's pieces add their counts to its degree atomically, the
+// first piece also removing the degree the scan wrote, and a separate fixup
+// kernel queues the split rows that end below their threshold.  Chosen on
+// the device from the scan's frontier degree sum.
+
+struct PullShared {
+  int32_t lq[kPullWaves][kPullLocalQueue];
+  int32_t cnt[kPullWaves][kWave];
+  int s_cnt[kPullWaves + 1];
+  int decide;
+  int64_t acc;
+};
+
+__device__ __forceinline__ uint32_t test_bit(const uint32_t *w, int64_t base_word, int32_t v) {
+  return (w[(v >> 5) - base_word] >> (v & 31)) & 1u;
+}
+
+// Counts, for every lane's row range [s, s+d), the entries whose neighbour
+// has its bit set (LDS-staged or global bitmap); result in cnt[lane].
+__device__ __forceinline__ void pull_count(const PeelArgs &a, const uint32_t *lk, int64_t lk_base,
+                                           int64_t s, int d, int32_t *cnt, int64_t &entries) {
+  cnt[lane_id()] = 0;
+  __builtin_amdgcn_wave_barrier();
+  BatchWalk bw;
+  bw.init(s, d);
+  entries += d;
+  for (int base = 0; base < bw.total; base += kUnroll * kWave) {
+    int32_t w[kUnroll];
+    int jj[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int k = base + u * kWave + lane_id();
+      const int64_t pos = bw.locate(k < bw.total ? k : bw.total - 1, jj[u]);
+      w[u] = k < bw.total ? a.cols[pos] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int k = base + u * kWave + lane_id();
+      const bool ok = w[u] >= 0 && test_bit(lk, lk_base, w[u]);
+      segmented_count(cnt, jj[u], k < bw.total, ok, min(kWave, bw.total - base - u * kWave));
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int delta_alive(const PeelArgs &a, const uint32_t *gbits, int32_t x,
+                                           int64_t &entries) {
+  int extra = 0;
+  for (int e = a.ins_head[x]; e >= 0; e = a.ins_next[e]) {
+    const int32_t w = a.ins_other[e];
+    if (w >= 0) {
+      ++entries;
+      extra += (gbits[w >> 5] >> (w & 31)) & 1u;
+    }
+  }
+  return extra;
+}
+
+__global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
+    PeelArgs a, const uint32_t *__restrict__ gbits, const int32_t *__restrict__ deg0, int64_t n,
+    int scan_blocks, int mode, int use_lds, int64_t total_entries, int64_t npieces,
+    int64_t npieces_upper) {
+  extern __shared__ uint32_t s_bits[];
+  __shared__ PullShared sh;
+  if (wave_in_block() == 0) {
+    // the scan's frontier degree sum, from its per-workgroup slots
+    const int64_t f0deg = wave_sum_strided(a.part + kPartF0Deg, scan_blocks, kPartFields);
+    const int64_t rest = total_entries - f0deg;
+    // pull pays one streaming read per surviving entry instead of one atomic
+    // per frontier entry: worth it when the frontier carries a sizeable share
+    const bool pull = mode == 2 || (mode == 0 && f0deg > 0 &&
+                                    (use_lds ? f0deg * 16 >= rest : f0deg * 2 >= rest));
+    if (lane_id() == 0) sh.decide = pull ? 1 : 0;
+  }
+  __syncthreads();
+  if (!sh.decide) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(&a.st->pulled, 1);
+  LocalQueue lq = make_lq(sh.lq[wave_in_block()], kPullLocalQueue, a);
+  int32_t *cnt = sh.cnt[wave_in_block()];
+  int64_t entries = 0;
+  const int waves = blockDim.x / kWave;
+  const int gw = blockIdx.x * waves + wave_in_block();
+  const int nw = gridDim.x * waves;
+  for (int phase = 0; phase < 2; ++phase) {
+    // phase 0: upper rows (neighbours are lower ids), phase 1: lower rows
+    const int64_t lo = phase == 0 ? 0 : a.nU, hi = phase == 0 ? a.nU : n;
+    const int64_t plo = phase == 0 ? 0 : npieces_upper, phi = phase == 0 ? npieces_upper : npieces;
+    const int64_t nb_lo = phase == 0 ? a.nU : 0, nb_hi = phase == 0 ? n : a.nU;
+    if (lo >= hi) continue;
+    const uint32_t *lk = gbits;
+    int64_t lk_base = 0;
+    if (use_lds) {
+      const int64_t w0 = nb_lo >> 5;
+      const int64_t w1 = nb_hi > nb_lo ? ((nb_hi - 1) >> 5) : w0;
+      __syncthreads();
+      for (int64_t i = threadIdx.x; i <= w1 - w0; i += blockDim.x) s_bits[i] = gbits[w0 + i];
+      __syncthreads();
+      lk = s_bits;
+      lk_base = w0;
+    }
+    // rows of at most kPiece entries
+    for (int64_t b = lo + (int64_t)gw * kWave; b < hi; b += (int64_t)nw * kWave) {
+      const int64_t xi = b + lane_id();
+      const bool valid = xi < hi;
+      const int32_t x = valid ? (int32_t)xi : -1;
+      int64_t s = 0, e = 0;
+      uint32_t word = 0;
+      if (valid) {
+        word = gbits[xi >> 5];
+        s = a.off[x];
+        e = a.off[x + 1];
+      }
+      const bool light = valid && e - s <= kPiece;
+      const bool alive = light && ((word >> (xi & 31)) & 1u);
+      pull_count(a, lk, lk_base, s, alive ? (int)(e - s) : 0, cnt, entries);
+      bool push = false;
+      if (alive) {
+        int32_t c = cnt[lane_id()];
+        if (a.ins_head != nullptr) c += delta_alive(a, gbits, x, entries);
+        a.deg[x] = c;
+        push = c < (x < a.nU ? a.thrU : a.thrL);
+      }
+      lq.push(push, x);
+      __builtin_amdgcn_wave_barrier();
+    }
+    // pieces of longer rows
+    for (int64_t b = plo + (int64_t)gw * kWave; b < phi; b += (int64_t)nw * kWave) {
+      const int64_t pi = b + lane_id();
+      int32_t row = -1;
+      int64_t s = 0;
+      int d = 0;
+      bool first = false;
+      if (pi < phi) {
+        row = a.piece_row[pi];
+        s = a.piece_start[pi];
+        const int64_t rs = a.off[row], re = a.off[row + 1];
+        const bool alive = (gbits[row >> 5] >> (row & 31)) & 1u;
+        d = alive ? (int)(min(s + kPiece, re) - s) : 0;
+        first = alive && s == rs;
+        if (!alive) row = -1;
+      }
+      pull_count(a, lk, lk_base, s, d, cnt, entries);
+      if (row >= 0) {
+        int32_t c = cnt[lane_id()];
+        if (first) {
+          if (a.ins_head != nullptr) c += delta_alive(a, gbits, row, entries);
+          c -= deg0[row];  // the scan wrote deg[row] = deg0[row]
+        }
+        if (c != 0) atomicAdd(&a.deg[row], c);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  block_flush(lq, sh.s_cnt);
+  add_part(a.part, kPartEntries, entries, &sh.acc);
+}
+
+// After a pull round: queues the split rows that ended below their threshold
+// and starts the next round.  Does nothing when the first round was pushed.
+__global__ __launch_bounds__(kPeelBlock) void pull_fixup_kernel(
+    PeelArgs a, const uint32_t *__restrict__ gbits, const int32_t *__restrict__ heavy_rows,
+    int64_t nheavy) {
+  __shared__ int32_t s_lq[kPeelWaves][kLocalQueue];
+  __shared__ int s_cnt[kPeelWaves + 1];
+  if (ld_agent(&a.st->pulled) == 0) return;
+  LocalQueue lq = make_lq(s_lq[wave_in_block()], kLocalQueue, a);
+  const int waves = blockDim.x / kWave;
+  const int gw = blockIdx.x * waves + wave_in_block();
+  const int nw = gridDim.x * waves;
+  for (int64_t b = (int64_t)gw * kWave; b < nheavy; b += (int64_t)nw * kWave) {
+    const int64_t i = b + lane_id();
+    bool push = false;
+    int32_t x = -1;
+    if (i < nheavy) x = heavy_rows[i];
+    if (x >= 0 && ((gbits[x >> 5] >> (x & 31)) & 1u))
+      push = a.deg[x] < (x < a.nU ? a.thrU : a.thrL);
+    push_removed(a, lq, push, x);
+  }
+  block_flush(lq, s_cnt);
+  if (last_block_done<false>(a.st)) {
+    advance_round_wave(a.st);
+    if (lane_id() == 0) atomicAdd((unsigned long long *)&a.st->launches, 1ull);
+  }
+}
+
+// Allows the pull kernel to stage a layer bitmap as large as the device's
+// per-workgroup LDS permits.
+hipError_t prepare_pull_kernel(Graph &g) {
+  const int dyn = (int)std::max<int64_t>(0, (int64_t)g.lds_per_block - (int64_t)sizeof(PullShared));
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&pull_round_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+}
+
+bool pull_uses_lds(const Graph &g) {
+  const int64_t words_upper = g.nU > 0 ? ((int64_t)g.nU - 1) / 32 + 1 : 0;
+  const int64_t words_lower = g.nL > 0 ? ((g.n - 1) >> 5) - (g.nU >> 5) + 1 : 0;
+  const int64_t need = 4 * std::max(words_upper, words_lower);
+  return (size_t)need + sizeof(PullShared) + 1024 <= g.lds_per_block;
+}
+
+hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s) {
+  if (g.pull_mode == 1) return hipSuccess;
+  PeelArgs a = make_args(g, thrU, thrL);
+  const int64_t words_upper = g.nU > 0 ? ((int64_t)g.nU - 1) / 32 + 1 : 0;
+  const int64_t words_lower = g.nL > 0 ? ((g.n - 1) >> 5) - (g.nU >> 5) + 1 : 0;
+  const bool use_lds = pull_uses_lds(g);
+  const size_t dyn = use_lds ? (size_t)(4 * std::max(words_upper, words_lower)) : 0;
+  const int64_t total_entries = 2 * g.m;
+  pull_round_kernel<<<g.cu_count, kPullBlock, dyn, s>>>(
+      a, g.alive_bits, g.deg0, g.n, scan_grid(g), g.pull_mode, use_lds ? 1 : 0, total_entries,
+      g.npieces, g.npieces_upper);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  pull_fixup_kernel<<<flat_grid(g, std::max<int64_t>(g.nheavy, 1), kPeelBlock), kPeelBlock, 0, s>>>(
+      a, g.alive_bits, g.heavy_rows, g.nheavy);
   return hipGetLastError();
 }
 
@@ -328,10 +775,8 @@ __global__ __launch_bounds__(kBlock) void pack_kernel(const int32_t *__restrict_
 hipError_t launch_pack(Graph &g, int32_t thrU, int32_t thrL, uint32_t *bits, hipStream_t s) {
   const int64_t nwords = (g.n + 31) / 32;
   if (nwords == 0) return hipSuccess;
-  int64_t waves = (nwords * 32 + kWave - 1) / kWave;
-  int grid = (int)std::min<int64_t>((waves + kWavesPerBlock - 1) / kWavesPerBlock,
-                                    (int64_t)g.cu_count * 8);
-  pack_kernel<<<grid, kBlock, 0, s>>>(g.deg, g.n, g.nU, thrU, thrL, bits, nwords);
+  pack_kernel<<<flat_grid(g, nwords * 32, kBlock), kBlock, 0, s>>>(g.deg, g.n, g.nU, thrU, thrL,
+                                                                  bits, nwords);
   return hipGetLastError();
 }
 
@@ -356,87 +801,87 @@ __global__ __launch_bounds__(kBlock) void pack_from_core_kernel(const int32_t *_
 hipError_t launch_pack_from_core(Graph &g, int32_t k, uint32_t *bits, hipStream_t s) {
   const int64_t nwords = (g.n + 31) / 32;
   if (nwords == 0) return hipSuccess;
-  int64_t waves = (nwords * 32 + kWave - 1) / kWave;
-  int grid = (int)std::min<int64_t>((waves + kWavesPerBlock - 1) / kWavesPerBlock,
-                                    (int64_t)g.cu_count * 8);
-  pack_from_core_kernel<<<grid, kBlock, 0, s>>>(g.core, g.n, k, bits, nwords);
+  pack_from_core_kernel<<<flat_grid(g, nwords * 32, kBlock), kBlock, 0, s>>>(g.core, g.n, k, bits,
+                                                                            nwords);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------- GCC+ init --
 // Algorithm 2's classification by Lemma 1 with delta_l = min(alpha,beta) and
 // delta_q = max(alpha,beta): core < delta_l -> out, core >= delta_q -> in,
-// otherwise uncertain (collected in g.list, count in st->aux0).
+// otherwise uncertain.  Uncertain vertices are appended to the queues; the
+// next kernel consumes them as its items.
 
-__global__ __launch_bounds__(kBlock) void classify_kernel(const int32_t *__restrict__ core,
-                                                          int32_t *__restrict__ deg,
-                                                          int32_t *__restrict__ unc,
-                                                          PeelState *st, int64_t n, int32_t dl,
-                                                          int32_t dq) {
-  __shared__ int s_wsum[kWavesPerBlock + 1];
-  const int64_t tile = (int64_t)kBlock * 4;
-  for (int64_t base = (int64_t)blockIdx.x * tile; base < n; base += (int64_t)gridDim.x * tile) {
-    const int64_t x0 = base + (int64_t)threadIdx.x * 4;
-    bool p[4] = {false, false, false, false};
-    int32_t c[4] = {0, 0, 0, 0};
-    const bool full = x0 + 3 < n;
-    if (full) {
-      int4 v = *reinterpret_cast<const int4 *>(core + x0);
-      c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
-    } else {
-      for (int j = 0; j < 4; ++j)
-        if (x0 + j < n) c[j] = core[x0 + j];
-    }
-    int32_t dv[4];
+__global__ __launch_bounds__(kScanBlock) void classify_kernel(PeelArgs a, int64_t n, int32_t dl,
+                                                              int32_t dq) {
+  __shared__ ScanCollector col;
+  if (threadIdx.x == 0) col.count = 0;
+  __syncthreads();
+  const int sub = blockIdx.x % kSub;
+  int32_t *q = a.queue + (int64_t)sub * a.qcap;
+  for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < n;
+       cb += (int64_t)gridDim.x * kScanChunk) {
+    for (int t = 0; t < kScanChunk; t += kScanBlock * 4) {
+      const int64_t x0 = cb + t + (int64_t)threadIdx.x * 4;
+      int32_t c[4] = {0, 0, 0, 0};
+      const bool full = x0 + 3 < n;
+      if (full) {
+        int4 v = *reinterpret_cast<const int4 *>(a.core + x0);
+        c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+      } else {
+        for (int j = 0; j < 4; ++j)
+          if (x0 + j < n) c[j] = a.core[x0 + j];
+      }
+      int32_t dv[4];
+      int32_t items[4];
+      int cnt = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      dv[j] = c[j] < dl ? kDegOut : (c[j] >= dq ? kDegIn : 0);
-      p[j] = (x0 + j < n) && c[j] >= dl && c[j] < dq;
+      for (int j = 0; j < 4; ++j) {
+        dv[j] = c[j] < dl ? kDegOut : (c[j] >= dq ? kDegIn : 0);
+        if ((x0 + j < n) && c[j] >= dl && c[j] < dq) items[cnt++] = (int32_t)(x0 + j);
+      }
+      if (full) {
+        *reinterpret_cast<int4 *>(a.deg + x0) = make_int4(dv[0], dv[1], dv[2], dv[3]);
+      } else {
+        for (int j = 0; j < 4; ++j)
+          if (x0 + j < n) a.deg[x0 + j] = dv[j];
+      }
+      col.append(items, cnt);
     }
-    if (full) {
-      *reinterpret_cast<int4 *>(deg + x0) = make_int4(dv[0], dv[1], dv[2], dv[3]);
-    } else {
-      for (int j = 0; j < 4; ++j)
-        if (x0 + j < n) deg[x0 + j] = dv[j];
-    }
-    int cnt = (int)p[0] + (int)p[1] + (int)p[2] + (int)p[3];
-    int pos = block_reserve(cnt, &st->aux0, s_wsum);
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (p[j]) unc[pos++] = (int32_t)(x0 + j);
+    col.flush(q, &a.st->tail[sub][0]);
+  }
+  if (last_block_done<false>(a.st)) {
+    start_rounds_wave(a.st);
+    if (lane_id() == 0) st_agent(&a.st->aux0, ld_agent(&a.st->first));  // uncertain count
   }
 }
 
-hipError_t launch_classify(Graph &g, int32_t thrU, int32_t thrL, int32_t dl, int32_t dq,
-                           hipStream_t s) {
-  (void)thrU;
-  (void)thrL;
-  int64_t tiles = (g.n + kBlock * 4 - 1) / (kBlock * 4);
-  int grid = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), (int64_t)g.cu_count * 8);
-  classify_kernel<<<grid, kBlock, 0, s>>>(g.core, g.deg, g.list, g.state, g.n, dl, dq);
+hipError_t launch_classify(Graph &g, int32_t dl, int32_t dq, hipStream_t s) {
+  PeelArgs a = make_args(g, 0, 0);
+  classify_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, g.n, dl, dq);
   return hipGetLastError();
 }
 
 // Degree of every uncertain vertex inside G[{core >= delta_l}] -- the
 // (alpha,beta)-core lies inside the (delta_l,delta_l)-core, so neighbours with
 // smaller core numbers never count -- and the initial frontier of GCC+.
-// Edge-balanced like the peel; per-vertex counts accumulate in LDS.
-__global__ __launch_bounds__(kBlock) void restricted_init_kernel(PeelArgs a,
-                                                                 const int32_t *__restrict__ unc,
-                                                                 int32_t dl) {
-  __shared__ int32_t s_lq[kWavesPerBlock][kLocalQueue];
-  __shared__ int32_t s_cnt[kWavesPerBlock][kWave];
+__global__ __launch_bounds__(kPeelBlock) void restricted_init_kernel(PeelArgs a, int32_t dl) {
+  __shared__ int32_t s_lq[kPeelWaves][kLocalQueue];
+  __shared__ int32_t s_cnt_own[kPeelWaves][kWave];
+  __shared__ RangeView s_view;
+  __shared__ int s_cnt[kPeelWaves + 1];
   __shared__ int64_t s_acc;
-  PeelState *st = a.st;
-  const int32_t nunc = st->aux0;
-  LocalQueue lq{s_lq[wave_in_block()], 0};
-  int32_t *cnt = s_cnt[wave_in_block()];
+  load_view(s_view, a.st);
+  LocalQueue lq = make_lq(s_lq[wave_in_block()], kLocalQueue, a);
+  int32_t *cnt = s_cnt_own[wave_in_block()];
   int64_t entries = 0;
-  const int gw = blockIdx.x * kWavesPerBlock + wave_in_block();
-  const int nw = gridDim.x * kWavesPerBlock;
-  for (int64_t b = (int64_t)gw * kWave; b < nunc; b += (int64_t)nw * kWave) {
-    const int64_t i = b + lane_id();
-    const int32_t x = i < nunc ? unc[i] : -1;
+  const int32_t total = s_view.pre[kSub];
+  const int waves = blockDim.x / kWave;
+  const int gw = blockIdx.x * waves + wave_in_block();
+  const int nw = gridDim.x * waves;
+  for (int64_t b = (int64_t)gw * kWave; b < total; b += (int64_t)nw * kWave) {
+    const int32_t i = (int32_t)(b + lane_id());
+    const int32_t x = i < total ? view_item(s_view, a.queue, a.qcap, i) : -1;
     int64_t s = 0;
     int d = 0;
     if (x >= 0) {
@@ -445,28 +890,25 @@ __global__ __launch_bounds__(kBlock) void restricted_init_kernel(PeelArgs a,
     }
     cnt[lane_id()] = 0;
     __builtin_amdgcn_wave_barrier();
-    const int incl = wave_incl_scan(d);
-    const int total = __shfl(incl, kWave - 1, kWave);
-    const int excl = incl - d;
-    const int s_lo = (int)(uint32_t)(uint64_t)s;
-    const int s_hi = (int)((uint64_t)s >> 32);
+    BatchWalk bw;
+    bw.init(s, d);
     entries += d;
-    for (int base = 0; base < total; base += kWave) {
-      const int k = base + lane_id();
-      const int kk = k < total ? k : total - 1;
-      int j = 0;
+    for (int base = 0; base < bw.total; base += kUnroll * kWave) {
+      int32_t w[kUnroll], cw[kUnroll];
+      int jj[kUnroll];
 #pragma unroll
-      for (int step = 32; step > 0; step >>= 1) {
-        int v = __shfl(incl, j + step - 1, kWave);
-        if (v <= kk) j += step;
+      for (int u = 0; u < kUnroll; ++u) {
+        const int k = base + u * kWave + lane_id();
+        const int64_t pos = bw.locate(k < bw.total ? k : bw.total - 1, jj[u]);
+        w[u] = k < bw.total ? a.cols[pos] : -1;
       }
-      const int ex = __shfl(excl, j, kWave);
-      const uint32_t lo32 = (uint32_t)__shfl(s_lo, j, kWave);
-      const uint32_t hi32 = (uint32_t)__shfl(s_hi, j, kWave);
-      const int64_t start = (int64_t)(((uint64_t)hi32 << 32) | lo32);
-      if (k < total) {
-        const int32_t w = a.cols[start + (kk - ex)];
-        if (w >= 0 && a.core[w] >= dl) atomicAdd(&cnt[j], 1);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) cw[u] = w[u] >= 0 ? a.core[w[u]] : -1;
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int k = base + u * kWave + lane_id();
+        segmented_count(cnt, jj[u], k < bw.total, w[u] >= 0 && cw[u] >= dl,
+                        min(kWave, bw.total - base - u * kWave));
       }
     }
     int extra = 0;
@@ -476,44 +918,53 @@ __global__ __launch_bounds__(kBlock) void restricted_init_kernel(PeelArgs a,
         if (w >= 0 && a.core[w] >= dl) ++extra;
       }
     }
-    __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     bool push = false;
     if (x >= 0) {
       const int32_t dx = cnt[lane_id()] + extra;
       a.deg[x] = dx;
       push = dx < (x < a.nU ? a.thrU : a.thrL);
     }
-    lq.push(push, x, a.queue, &st->tail);
+    lq.push(push, x);
     __builtin_amdgcn_wave_barrier();
   }
-  lq.flush(a.queue, &st->tail);
-  add_entries(entries, st, &s_acc);
-  if (last_block_done(&st->finished)) {
-    st->lo = 0;
-    st->hi = atomicAdd(&st->tail, 0);
-    st->first = st->hi;
-    st->rounds = 0;
-    st->finished = 0;
+  block_flush(lq, s_cnt);
+  add_part(a.part, kPartEntries, entries, &s_acc);
+  if (last_block_done<false>(a.st)) {
+    advance_round_wave(a.st);
+    // the uncertain list is not a round: the frontier starts the count
+    const int j = lane_id();
+    int32_t f = 0;
+    if (j < kSub) f = ld_agent(&a.st->hi[j]) - ld_agent(&a.st->lo[j]);
+    f = wave_sum(f);
+    if (j == 0) {
+      st_agent(&a.st->first, f);
+      st_agent(&a.st->rounds, 0);
+    }
   }
 }
 
 hipError_t launch_restricted_init(Graph &g, int32_t thrU, int32_t thrL, int32_t dl,
                                   hipStream_t s) {
   PeelArgs a = make_args(g, thrU, thrL);
-  restricted_init_kernel<<<peel_grid(g), kBlock, 0, s>>>(a, g.list, dl);
+  restricted_init_kernel<<<peel_grid(g), kPeelBlock, 0, s>>>(a, dl);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------- core numbers --
 // Level-synchronous k-core peeling (Definition 2; a (k,k)-core is the k-core
-// of G taken as an ordinary graph).  Each launch performs one step:
-//  - if the current round Q[lo,hi) is non-empty, it is peeled at level k
-//    (threshold k+1; a vertex crossing to k gets core number k);
-//  - otherwise a scan advances to the next level: every live vertex with
-//    degree <= k' gets core k' and is queued, the alive list is compacted,
-//    and when nothing was queued the smallest live degree gives the next
-//    level directly (empty levels are skipped).
+// of G taken as an ordinary graph).  Phases:
+//  - round: the current frontier is peeled at level k (threshold k+1; a
+//    vertex crossing to k gets core number k);
+//  - scan (frontier empty): every live vertex of the alive list with degree
+//    <= k' gets core k' and is queued; when nothing was queued the smallest
+//    live degree gives the next level directly (empty levels are skipped);
+//  - compaction (right after a scan that left under half the list alive):
+//    the list is rewritten without dead vertices, each workgroup at the
+//    offset given by the kept counts of the workgroups before it.
+// The persistent kernel loops over phases with grid barriers; the step
+// kernel performs one phase per launch.
 
 __global__ void kcore_init_kernel(const int32_t *__restrict__ deg0, int32_t *__restrict__ deg,
                                   int32_t *__restrict__ core, int32_t *__restrict__ alive,
@@ -534,105 +985,249 @@ __global__ void kcore_init_kernel(const int32_t *__restrict__ deg0, int32_t *__r
 }
 
 hipError_t launch_kcore_init(Graph &g, hipStream_t s) {
-  hipError_t e = launch_init_state(g.state, s);
+  hipError_t e = launch_init_state(g, s);
   if (e != hipSuccess) return e;
-  int grid = (int)std::min<int64_t>((g.n + kBlock - 1) / kBlock + 1, (int64_t)g.cu_count * 8);
-  kcore_init_kernel<<<grid, kBlock, 0, s>>>(g.deg0, g.deg, g.core, g.list, g.state, g.n);
+  kcore_init_kernel<<<flat_grid(g, g.n, kBlock), kBlock, 0, s>>>(g.deg0, g.deg, g.core, g.list,
+                                                                 g.state, g.n);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kBlock) void kcore_step_kernel(PeelArgs a, int32_t *alive0,
-                                                            int32_t *alive1) {
-  __shared__ int32_t s_lq[kWavesPerBlock][kLocalQueue];
-  __shared__ int64_t s_acc;
-  __shared__ int s_wsum[kWavesPerBlock + 1];
-  __shared__ int s_min;
-  PeelState *st = a.st;
-  if (st->done) return;
-  const int32_t lo = st->lo, hi = st->hi;
-  if (lo < hi) {
-    const int32_t level = st->k;
-    LocalQueue lq{s_lq[wave_in_block()], 0};
-    int64_t entries = 0;
-    const int gw = blockIdx.x * kWavesPerBlock + wave_in_block();
-    const int nw = gridDim.x * kWavesPerBlock;
-    for (int64_t b = (int64_t)lo + (int64_t)gw * kWave; b < hi; b += (int64_t)nw * kWave) {
-      const int64_t i = b + lane_id();
-      const int32_t x = i < hi ? a.queue[i] : -1;
-      peel_batch<kKCore>(a, x, 0, 0, level, lq, entries);
+struct KCoreShared {
+  int32_t lq[kPeelWaves][kLocalQueue];
+  RangeView view;
+  int s_cnt[kPeelWaves + 1];
+  int s_wsum[kPeelWaves + 1];
+  int phase;   // 0 done, 1 round, 2 scan, 3 compaction
+  int level, next_k, cur, sel;
+  int s_min;
+  int64_t acc;
+  int64_t offset;
+};
+
+// Reads the phase from the state (all threads).  Written only when a phase
+// completes, i.e. before the barrier (or kernel boundary) preceding this.
+__device__ __forceinline__ void kcore_read_phase(KCoreShared &sh, PeelState *st) {
+  load_view(sh.view, st);
+  if (threadIdx.x == 0) {
+    const bool abort = ld_agent(&st->abort_flag) != 0;
+    // a compaction runs right after its scan, before any round of the new
+    // level can change which vertices are live: its offsets come from the
+    // scan's kept counts
+    if (abort || st->done)
+      sh.phase = 0;
+    else if (st->compact)
+      sh.phase = 3;
+    else if (sh.view.pre[kSub] > 0)
+      sh.phase = 1;
+    else
+      sh.phase = 2;
+    sh.level = st->k;
+    sh.next_k = st->next_k;
+    sh.cur = st->alive_cur;
+    sh.sel = st->alive_sel;
+  }
+  __syncthreads();
+}
+
+// Work of one phase (whole grid).
+__device__ void kcore_phase(const PeelArgs &a, KCoreShared &sh, LocalQueue &lq,
+                            int32_t *alive0, int32_t *alive1, int64_t &entries) {
+  if (sh.phase == 1) {
+    peel_round_body<kKCore>(a, sh.view, sh.level, lq, entries);
+    block_flush(lq, sh.s_cnt);
+    return;
+  }
+  const int32_t cur = sh.cur;
+  const int32_t *A = sh.sel ? alive1 : alive0;
+  int32_t *N = sh.sel ? alive0 : alive1;
+  const int64_t chunk = ((int64_t)cur + gridDim.x - 1) / gridDim.x;
+  const int64_t c0 = std::min<int64_t>((int64_t)blockIdx.x * chunk, cur);
+  const int64_t c1 = std::min<int64_t>(c0 + chunk, cur);
+  const int64_t span = (c1 - c0 + blockDim.x - 1) / blockDim.x * blockDim.x;
+  if (sh.phase == 2) {
+    const int32_t kn = sh.next_k;
+    int kept = 0, mn = 0x7FFFFFFF;
+    for (int64_t t = threadIdx.x; t < span; t += blockDim.x) {
+      const int64_t i = c0 + t;
+      bool push = false;
+      int32_t x = -1;
+      if (i < c1) {
+        x = A[i];
+        if (a.core[x] < 0) {
+          const int32_t d = a.deg[x];
+          if (d <= kn) {
+            a.core[x] = kn;
+            push = true;
+          } else {
+            ++kept;
+            mn = min(mn, d);
+          }
+        }
+      }
+      lq.push(push, x);
     }
-    lq.flush(a.queue, &st->tail);
-    add_entries(entries, st, &s_acc);
-    if (last_block_done(&st->finished)) {
-      st->lo = hi;
-      st->hi = atomicAdd(&st->tail, 0);
-      st->rounds += 1;
-      st->launches += 1;
-      st->finished = 0;
+    block_flush(lq, sh.s_cnt);
+    const int wk = wave_sum(kept);
+    const int wm = wave_min(mn);
+    if (threadIdx.x == 0) {
+      sh.acc = 0;
+      sh.s_min = 0x7FFFFFFF;
+    }
+    __syncthreads();
+    if (lane_id() == 0) {
+      atomicAdd((unsigned long long *)&sh.acc, (unsigned long long)wk);
+      atomicMin(&sh.s_min, wm);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      a.part[(int64_t)blockIdx.x * kPartFields + kPartKept] = sh.acc;
+      a.part[(int64_t)blockIdx.x * kPartFields + kPartMin] = sh.s_min;
     }
     return;
   }
-  // scan step at level kn
-  const int32_t kn = st->next_k;
-  const int32_t cur = st->alive_cur;
-  const int32_t *alive = st->alive_sel ? alive1 : alive0;
-  int32_t *next = st->alive_sel ? alive0 : alive1;
-  if (threadIdx.x == 0) s_min = 0x7FFFFFFF;
+  // compaction: offset = kept counts of the preceding workgroups
+  if (wave_in_block() == 0) {
+    const int64_t o = wave_sum_strided(a.part + kPartKept, (int)blockIdx.x, kPartFields);
+    if (lane_id() == 0) sh.offset = o;
+  }
   __syncthreads();
-  int local_min = 0x7FFFFFFF;
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  const int64_t span = ((int64_t)cur + kBlock - 1) / kBlock * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < span; i += stride) {
+  int64_t o = sh.offset;
+  for (int64_t t = threadIdx.x; t < span; t += blockDim.x) {
+    const int64_t i = c0 + t;
     int32_t x = -1;
-    bool push = false, keep = false;
-    if (i < cur) {
-      x = alive[i];
-      if (a.core[x] < 0) {
-        const int32_t d = a.deg[x];
-        if (d <= kn) {
-          a.core[x] = kn;
-          push = true;
-        } else {
-          keep = true;
-          local_min = min(local_min, d);
-        }
+    bool keep = false;
+    if (i < c1) {
+      x = A[i];
+      keep = a.core[x] < 0;
+    }
+    int incl = wave_incl_scan((int)keep);
+    if (lane_id() == kWave - 1) sh.s_wsum[wave_in_block()] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+        int v = sh.s_wsum[w];
+        sh.s_wsum[w] = tot;
+        tot += v;
+      }
+      sh.s_wsum[kPeelWaves] = tot;
+    }
+    __syncthreads();
+    if (keep) N[o + sh.s_wsum[wave_in_block()] + incl - 1] = x;
+    o += sh.s_wsum[kPeelWaves];
+    __syncthreads();
+  }
+}
+
+// Completes a phase: the 64 lanes of one wave, with every write of the phase
+// visible.
+__device__ void kcore_complete(const PeelArgs &a, int phase, int nblocks) {
+  PeelState *st = a.st;
+  const int lane = lane_id();
+  if (phase == 1) {
+    advance_round_wave(st);
+  } else if (phase == 2) {
+    const int32_t kn = st->next_k;
+    const int64_t kept = wave_sum_strided(a.part + kPartKept, nblocks, kPartFields);
+    const int32_t mn =
+        (int32_t)wave_min_strided(a.part + kPartMin, nblocks, kPartFields, 0x7FFFFFFF);
+    int32_t after = 0;
+    if (lane < kSub) after = ld_agent(&st->tail[lane][0]) - ld_agent(&st->hi[lane]);
+    after = wave_sum(after);
+    advance_round_wave(st);  // the scan's pushes become the level's first round
+    if (lane == 0) {
+      const bool pushed = after > 0;
+      st->k = kn;
+      if (pushed) st->max_core = kn;
+      st->next_k = pushed ? kn + 1 : max(kn + 1, mn);
+      st->kept = (int32_t)kept;
+      if (kept == 0) {
+        st->alive_cur = 0;
+        st->done = 1;
+      } else {
+        st->compact = kept * 2 < st->alive_cur ? 1 : 0;
       }
     }
-    int pos = block_reserve((int)push, &st->tail, s_wsum);
-    if (push) a.queue[pos] = x;
-    pos = block_reserve((int)keep, &st->alive_next, s_wsum);
-    if (keep) next[pos] = x;
+  } else if (phase == 3) {
+    if (lane == 0) {
+      st->alive_sel ^= 1;
+      st->alive_cur = st->kept;
+      st->compact = 0;
+    }
   }
-  local_min = wave_min(local_min);
-  if (lane_id() == 0) atomicMin(&s_min, local_min);
-  __syncthreads();
-  if (threadIdx.x == 0 && s_min != 0x7FFFFFFF) atomicMin(&st->min_alive, s_min);
-  if (last_block_done(&st->finished)) {
-    const int32_t tail = atomicAdd(&st->tail, 0);
-    const int32_t kept = atomicAdd(&st->alive_next, 0);
-    const int32_t mn = atomicAdd(&st->min_alive, 0);
-    const bool pushed = tail > hi;
-    st->k = kn;
-    st->lo = hi;
-    st->hi = tail;
-    if (pushed) st->max_core = kn;
-    st->alive_cur = kept;
-    st->alive_next = 0;
-    st->alive_sel ^= 1;
-    st->min_alive = 0x7FFFFFFF;
-    st->next_k = pushed ? kn + 1 : max(kn + 1, mn);
-    st->done = kept == 0;
-    st->launches += 1;
-    st->finished = 0;
+  if (lane == 0) atomicAdd((unsigned long long *)&st->launches, 1ull);
+}
+
+// Each phase removes a vertex, raises the level past a live degree, or
+// compacts the list after a scan, so max_phases (4n + 1024) bounds a correct
+// run; beyond it the loop flags an abort.
+__global__ __launch_bounds__(kPeelBlock) void kcore_persistent_kernel(PeelArgs a, int32_t *alive0,
+                                                                      int32_t *alive1,
+                                                                      int64_t max_phases) {
+  __shared__ KCoreShared sh;
+  LocalQueue lq = make_lq(sh.lq[wave_in_block()], kLocalQueue, a);
+  int64_t entries = 0;
+  for (int64_t it = 0;; ++it) {
+    kcore_read_phase(sh, a.st);
+    const int phase = sh.phase;
+    if (phase == 0) break;
+    if (it > max_phases) {
+      if (threadIdx.x == 0) st_agent(&a.st->abort_flag, 1);
+      break;
+    }
+    kcore_phase(a, sh, lq, alive0, alive1, entries);
+    grid_sync(a.st, [&] { kcore_complete(a, phase, (int)gridDim.x); });
   }
+  add_part(a.part, kPartEntries, entries, &sh.acc);
+}
+
+__global__ __launch_bounds__(kPeelBlock) void kcore_step_kernel(PeelArgs a, int32_t *alive0,
+                                                                int32_t *alive1) {
+  __shared__ KCoreShared sh;
+  LocalQueue lq = make_lq(sh.lq[wave_in_block()], kLocalQueue, a);
+  int64_t entries = 0;
+  kcore_read_phase(sh, a.st);
+  const int phase = sh.phase;
+  if (phase == 0) return;
+  kcore_phase(a, sh, lq, alive0, alive1, entries);
+  // the completion reads other workgroups' kept counts: release them first
+  if (last_block_done<true>(a.st)) kcore_complete(a, phase, (int)gridDim.x);
+}
+
+hipError_t launch_kcore_persistent(Graph &g, hipStream_t s) {
+  PeelArgs a = make_args(g, 0, 0);
+  int32_t *l0 = g.list, *l1 = g.list2;
+  int64_t max_phases = 4 * g.n + 1024;
+  void *args[] = {&a, &l0, &l1, &max_phases};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&kcore_persistent_kernel),
+                                    dim3(g.kcore_grid), dim3(kPeelBlock), args, 0, s);
 }
 
 hipError_t launch_kcore_steps(Graph &g, int steps, hipStream_t s) {
   PeelArgs a = make_args(g, 0, 0);
   const int grid = peel_grid(g);
-  for (int r = 0; r < steps; ++r)
-    kcore_step_kernel<<<grid, kBlock, 0, s>>>(a, g.list, g.list2);
+  for (int r = 0; r < steps; ++r) kcore_step_kernel<<<grid, kPeelBlock, 0, s>>>(a, g.list, g.list2);
   return hipGetLastError();
+}
+
+// Co-resident workgroup counts for the cooperative kernels.
+hipError_t query_persistent_grids(Graph &g) {
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void *>(&peel_persistent_kernel<kGCC>), kPeelBlock, 0);
+  if (e != hipSuccess) return e;
+  int per_cu2 = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu2, reinterpret_cast<const void *>(&peel_persistent_kernel<kGCCPlus>), kPeelBlock, 0);
+  if (e != hipSuccess) return e;
+  int per_cu3 = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu3, reinterpret_cast<const void *>(&kcore_persistent_kernel), kPeelBlock, 0);
+  if (e != hipSuccess) return e;
+  const int pc = std::max(1, std::min({per_cu, per_cu2, 2}));
+  g.persistent_grid = std::min(kMaxBlocks, g.cu_count * pc);
+  g.kcore_grid = std::min(kMaxBlocks, g.cu_count * std::max(1, std::min(per_cu3, 2)));
+  return hipSuccess;
 }
 
 }  // namespace abc

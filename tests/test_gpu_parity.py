@@ -41,12 +41,24 @@ def _check_core(g, ref, a, b, algo, tag="", tombstones=False):
     if algo == pkg.ABCORE_GCC:
         assert st["removed"] == ost["removed"], (tag, a, b)
         assert st["rounds"] == ost["rounds"], (tag, a, b)
-        # after deletions the peel also reads the tombstoned entries of removed rows
-        if tombstones:
+        # a push peel reads exactly the rows of removed vertices; a pull first
+        # round reads the surviving rows instead; after deletions the peel
+        # also reads tombstoned entries
+        if st["pulled"]:
+            pass
+        elif tombstones:
             assert st["entries_read"] >= ost["removed_degree_sum"], (tag, a, b)
         else:
             assert st["entries_read"] == ost["removed_degree_sum"], (tag, a, b)
     return st, ost
+
+
+MODES = [(2, 0), (2, 1), (2, 2), (1, 1), (1, 2)]  # (peel mode, pull mode)
+
+
+def _set_mode(g, peel, pull):
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_PEEL_MODE, peel)
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_PULL, pull)
 
 
 # ------------------------------------------------------------------ build --
@@ -81,12 +93,15 @@ def test_build_rejects_out_of_range():
 # ------------------------------------------------------------ computation --
 
 
-def test_config1_gcc_and_gccplus():
+@pytest.mark.parametrize("peel,pull", MODES)
+def test_config1_gcc_and_gccplus(peel, pull):
     spec = bigraph_gen.CONFIGS[1]
     eu, ev = bigraph_gen.make_graph(spec)
     g, ref = _make(spec["n_upper"], spec["n_lower"], eu, ev)
-    say("config 1: (3,2) GCC / GCC+")
-    _check_core(g, ref, 3, 2, pkg.ABCORE_GCC, "c1")
+    _set_mode(g, peel, pull)
+    say("config 1: (3,2) GCC / GCC+, mode", peel, pull)
+    st, _ = _check_core(g, ref, 3, 2, pkg.ABCORE_GCC, "c1")
+    assert st["pulled"] == (1 if pull == 2 else 0) or pull == 0
     _check_core(g, ref, 3, 2, pkg.ABCORE_GCC_PLUS, "c1")
     for a, b in [(1, 1), (2, 2), (5, 3), (3, 5), (10, 14), (14, 10), (13, 27), (40, 40)]:
         say("config 1:", a, b)
@@ -95,14 +110,16 @@ def test_config1_gcc_and_gccplus():
     g.destroy()
 
 
-@pytest.mark.parametrize("seed", [101, 102, 103])
-def test_chung_lu_small_grid(seed):
+@pytest.mark.parametrize("seed,peel,pull", [(101, 2, 0), (102, 2, 2), (103, 1, 1),
+                                            (104, 2, 1), (105, 1, 2)])
+def test_chung_lu_small_grid(seed, peel, pull):
     nU, nL, m = 30_000, 20_000, 400_000
     eu, ev = bigraph_gen.chung_lu(nU, nL, m, 2.1, 2.1, 5000, seed)
     g, ref = _make(nU, nL, eu, ev)
+    _set_mode(g, peel, pull)
     for a, b in [(1, 1), (2, 3), (3, 2), (5, 5), (4, 9), (9, 4), (12, 30), (30, 12), (64, 64),
                  (1000, 1)]:
-        say("chung-lu", seed, a, b)
+        say("chung-lu", seed, a, b, "mode", peel, pull)
         for algo in (pkg.ABCORE_GCC, pkg.ABCORE_GCC_PLUS):
             _check_core(g, ref, a, b, algo, f"cl{seed}")
     g.destroy()
@@ -121,12 +138,13 @@ def test_repeat_runs_identical():
 # ----------------------------------------------------------- core numbers --
 
 
-@pytest.mark.parametrize("seed", [201, 202])
-def test_core_numbers(seed):
+@pytest.mark.parametrize("seed,peel", [(201, 2), (202, 1), (203, 2)])
+def test_core_numbers(seed, peel):
     nU, nL, m = 40_000, 25_000, 500_000
     eu, ev = bigraph_gen.chung_lu(nU, nL, m, 2.1, 2.3, 6000, seed)
     g, ref = _make(nU, nL, eu, ev)
-    say("core numbers", seed)
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_PEEL_MODE, peel)
+    say("core numbers", seed, "mode", peel)
     core, mx = pkg.abcore_core_numbers(g)
     want = oracle.core_numbers(ref)
     assert np.array_equal(core.cpu().numpy(), want)
@@ -175,6 +193,19 @@ def test_edge_cases():
     for a, b in [(70, 40), (71, 40), (70, 41), (1, 1), (35, 20)]:
         for algo in (pkg.ABCORE_GCC, pkg.ABCORE_GCC_PLUS):
             _check_core(g, ref, a, b, algo, "K")
+    g.destroy()
+    # a hub that crosses its threshold during the rounds (its row is split
+    # into pieces when queued): 100 private degree-1 neighbours, 100 shared
+    # with a second upper vertex
+    say("edge: hub crossing in a later round")
+    eu = np.concatenate([np.zeros(200, np.int32), np.ones(100, np.int32)])
+    ev = np.concatenate([np.arange(200), np.arange(100, 200)]).astype(np.int32)
+    g, ref = _make(2, 200, eu, ev)
+    for peel, pull in MODES:
+        _set_mode(g, peel, pull)
+        for a, b in [(101, 2), (150, 2), (1, 2), (100, 2), (2, 2)]:
+            _check_core(g, ref, a, b, pkg.ABCORE_GCC, "hub")
+            _check_core(g, ref, a, b, pkg.ABCORE_GCC_PLUS, "hub")
     g.destroy()
     # a long path: one vertex per end per round
     say("edge: path of 3001 vertices")
