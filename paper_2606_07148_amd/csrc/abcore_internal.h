@@ -59,6 +59,8 @@ struct Arrival {
 // items appended meanwhile.
 struct PeelState {
   int32_t tail[kSub][kPad];  // append cursors
+  int32_t head[kSub][kPad];  // asynchronous peel: next slot to claim
+  int32_t consumed[kSub][kPad];  // asynchronous peel: slots processed
   int32_t lo[kSub];
   int32_t hi[kSub];
   Arrival arr;
@@ -142,7 +144,8 @@ struct Graph {
   // device facts and options
   int cu_count = 256;
   size_t lds_per_block = 65536;
-  int peel_mode = 2;        // 1 = round kernels, 2 = persistent (cooperative)
+  int peel_mode = 3;        // 1 = round kernels, 2 = rounds in one cooperative
+                            // launch, 3 = asynchronous worklist
   int pull_mode = 0;        // 0 = auto, 1 = never, 2 = always
   int grid = 0;             // 0 = derived from the device
   int rounds_per_sync = 16;
@@ -192,6 +195,8 @@ hipError_t launch_peel_rounds(Graph &g, PeelKind kind, int32_t thrU, int32_t thr
                               int rounds, hipStream_t s);
 hipError_t launch_peel_persistent(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
                                   hipStream_t s);
+hipError_t launch_peel_async(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
+                             hipStream_t s);
 hipError_t launch_pack(Graph &g, int32_t thrU, int32_t thrL, uint32_t *bits,
                        hipStream_t s);
 hipError_t launch_pack_from_core(Graph &g, int32_t k, uint32_t *bits, hipStream_t s);

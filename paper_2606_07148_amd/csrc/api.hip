@@ -143,6 +143,12 @@ int64_t sum_part(Graph &g, int field, hipStream_t s, abcore_status *st) {
 // batches; a launch after convergence returns immediately.
 abcore_status run_peel(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, hipStream_t s,
                        int64_t *launches) {
+  if (g.peel_mode == 3) {
+    CHK(timed(g, ABCORE_KERNEL_PEEL, s, 1,
+              [&] { return launch_peel_async(g, kind, thrU, thrL, s); }));
+    *launches += 1;
+    return ABCORE_OK;
+  }
   if (g.peel_mode == 2) {
     CHK(timed(g, ABCORE_KERNEL_PEEL, s, 1,
               [&] { return launch_peel_persistent(g, kind, thrU, thrL, s); }));
@@ -172,7 +178,7 @@ abcore_status compute_core(Graph &g, hipStream_t s) {
   TRY(ensure(&g.list, g.n));
   TRY(ensure(&g.list2, g.n));
   CHK(launch_kcore_init(g, s));
-  if (g.peel_mode == 2) {
+  if (g.peel_mode >= 2 && g.kcore_grid > 0) {
     CHK(launch_kcore_persistent(g, s));
     TRY(read_state(g, s));
     if (!g.h_state->done) {
@@ -287,13 +293,21 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
     if (st != ABCORE_OK) break;
     st = build_pieces(*g, s);
     if (st != ABCORE_OK) break;
-    // every vertex enters the queues at most twice per computation
-    g->qcap = 2 * g->n + kLocalQueue;
+    // per computation a vertex enters the queues at most twice (GCC+: as
+    // uncertain, then as removed) and a split row once more as its pieces
+    g->qcap = 2 * g->n + g->npieces + kLocalQueue;
     if ((st = ensure(&g->deg, g->n)) != ABCORE_OK) break;
     if ((st = ensure(&g->queue, (int64_t)kSub * g->qcap)) != ABCORE_OK) break;
+    if (hipMemsetAsync(g->queue, 0xFF, sizeof(int32_t) * kSub * g->qcap, s) != hipSuccess) {
+      set_error("abcore_build_csr: queue initialisation failed");
+      st = ABCORE_EDEVICE;
+      break;
+    }
     if ((st = ensure(&g->alive_bits, (g->n + 31) / 32 + 1)) != ABCORE_OK) break;
     if ((st = ensure(&g->part, (int64_t)kMaxBlocks * kPartFields)) != ABCORE_OK) break;
     hipError_t e = hipMalloc(&g->state, sizeof(PeelState));
+    // the state is read (queue tails) by the first initialisation: zero it
+    if (e == hipSuccess) e = hipMemsetAsync(g->state, 0, sizeof(PeelState), s);
     if (e == hipSuccess) e = hipHostMalloc(&g->h_state, sizeof(PeelState));
     if (e == hipSuccess)
       e = hipHostMalloc(&g->h_part, sizeof(int64_t) * kMaxBlocks * kPartFields);
@@ -303,9 +317,11 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
       break;
     }
     memset(g->h_state, 0, sizeof(PeelState));
-    if (query_persistent_grids(*g) != hipSuccess || g->persistent_grid <= 0 ||
-        g->kcore_grid <= 0)
-      g->peel_mode = 1;  // no co-residency information: one kernel per round
+    if (query_persistent_grids(*g) != hipSuccess) {
+      // no co-residency information: the cooperative kernels are not used
+      g->persistent_grid = 0;
+      g->kcore_grid = 0;
+    }
     (void)prepare_pull_kernel(*g);
     if (launch_init_state(*g, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
       set_error("abcore_build_csr: state initialisation failed");
@@ -362,11 +378,11 @@ abcore_status abcore_set_option(abcore_graph h, int32_t option, int64_t value) {
   }
   switch (option) {
     case ABCORE_OPT_PEEL_MODE:
-      if (value > 2 || (value == 2 && g->persistent_grid <= 0)) {
+      if (value > 3 || (value == 2 && g->persistent_grid <= 0)) {
         set_error("abcore_set_option: peel mode %lld not available", (long long)value);
         return ABCORE_EINVAL;
       }
-      g->peel_mode = value == 0 ? (g->persistent_grid > 0 ? 2 : 1) : (int)value;
+      g->peel_mode = value == 0 ? 3 : (int)value;
       return ABCORE_OK;
     case ABCORE_OPT_GRID:
       g->grid = (int)std::min<int64_t>(value, kMaxBlocks);
@@ -513,7 +529,9 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
     for (int64_t i = 0; i < nwords; ++i) members += __builtin_popcount(words[i]);
     const bool plus = algo == ABCORE_GCC_PLUS;
     stats->removed = g->n - members;
-    stats->rounds = p.rounds;
+    // the asynchronous peel has no rounds
+    stats->rounds = (g->peel_mode == 3 && !(algo == ABCORE_GCC_PLUS && thrU == thrL)) ? -1
+                                                                                     : p.rounds;
     stats->entries_read = entries;
     stats->initial = p.first;
     stats->uncertain = plus ? p.aux0 : 0;

@@ -40,8 +40,25 @@ __global__ void init_state_kernel(int32_t *st_words, int nwords, int64_t *part, 
     part[i] = 0;
 }
 
+// Queue slots not yet written hold kEmpty (the asynchronous peel waits on
+// them); the previous computation's used prefixes [0, tail) are cleared
+// before its state is reset.
+constexpr int32_t kEmpty = -1;
+
+__global__ void queue_reset_kernel(int32_t *queue, int64_t qcap, const PeelState *st) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int j = 0; j < kSub; ++j) {
+    // clamped: the range can never leave the sub-queue whatever the state holds
+    const int64_t t = min(max((int64_t)st->tail[j][0], (int64_t)0), qcap);
+    int32_t *q = queue + (int64_t)j * qcap;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < t; i += stride)
+      q[i] = kEmpty;
+  }
+}
+
 hipError_t launch_init_state(Graph &g, hipStream_t s) {
   static_assert(sizeof(PeelState) % 4 == 0, "state must be whole words");
+  queue_reset_kernel<<<g.cu_count, 256, 0, s>>>(g.queue, g.qcap, g.state);
   init_state_kernel<<<8, 256, 0, s>>>(reinterpret_cast<int32_t *>(g.state),
                                       (int)(sizeof(PeelState) / 4), g.part,
                                       kMaxBlocks * kPartFields);
@@ -522,6 +539,124 @@ hipError_t launch_peel_persistent(Graph &g, PeelKind kind, int32_t thrU, int32_t
   const void *fn = kind == kGCC ? reinterpret_cast<const void *>(&peel_persistent_kernel<kGCC>)
                                 : reinterpret_cast<const void *>(&peel_persistent_kernel<kGCCPlus>);
   return hipLaunchCooperativeKernel(fn, dim3(g.persistent_grid), dim3(kPeelBlock), args, 0, s);
+}
+
+// --------------------------------------------------- asynchronous worklist --
+// The peel without rounds: since the core does not depend on the order of
+// removals (Definition 1 fixes a unique result), a removed vertex can be
+// processed as soon as it is queued.  Each workgroup is bound to one
+// sub-queue; its waves claim 64 slots at a time, process the items as they
+// are written (a slot holds kEmpty until then) and append what they remove to
+// the same sub-queue, whose claimed-but-unwritten slots always belong to a
+// waiting wave of that sub-queue.  Termination: every queued item has been
+// processed, read as sum(done) == sum(tail) with all `done` read before any
+// `tail` (an item's appends precede its `done` increment), which means no item
+// was in flight and none can be appended any more.  Needs no co-residency:
+// a wave only waits on slots that an already running wave has reserved.
+
+__global__ void async_prepare_kernel(PeelState *st) {
+  const int j = threadIdx.x;
+  if (j < kSub) {
+    const int32_t lo = ld_agent(&st->lo[j]);
+    st_agent(&st->head[j][0], lo);
+    st_agent(&st->consumed[j][0], lo);
+  }
+}
+
+__device__ __forceinline__ bool quiescent(PeelState *st) {
+  const int j = lane_id();
+  int32_t d = 0, t = 0;
+  if (j < kSub) d = ld_agent(&st->consumed[j][0]);
+  const int dsum = wave_sum(d);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  if (j < kSub) t = ld_agent(&st->tail[j][0]);
+  const int tsum = wave_sum(t);
+  return dsum == tsum;
+}
+
+// Polls of one waiting wave before it declares a hang (each poll takes at
+// least a few microseconds, so this is seconds: far beyond any legitimate
+// wait of a peel).
+constexpr uint32_t kAsyncSpinLimit = 1u << 21;
+
+template <int KIND>
+__global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
+  __shared__ int32_t s_lq[kPeelWaves][kLocalQueue];
+  __shared__ int64_t s_acc;
+  LocalQueue lq = make_lq(s_lq[wave_in_block()], kLocalQueue, a);
+  const int j = blockIdx.x % kSub;
+  int32_t *head = &a.st->head[j][0];
+  int32_t *consumed = &a.st->consumed[j][0];
+  int64_t entries = 0;
+  uint32_t idle = 0;
+  bool finished = false;
+  while (!finished) {
+    int base = 0;
+    if (lane_id() == 0) base = atomicAdd(head, kWave);
+    base = __shfl(base, 0, kWave);
+    const int64_t slot = (int64_t)base + lane_id();
+    // slots past the capacity are never written and never read: such a lane
+    // stays pending, so its wave ends through the termination test
+    bool pending = true;
+    while (__ballot(pending)) {
+      int32_t item = kEmpty;
+      if (pending && slot < a.qcap) item = ld_agent(&lq.q[slot]);
+      const bool ready = pending && item != kEmpty;
+      const uint64_t rmask = __ballot(ready);
+      if (rmask) {
+        peel_batch<KIND>(a, ready ? item : -1, 0, lq, entries);
+        // local continuation: the wave removes what its batch just queued
+        // (64 at a time, last in first out) instead of a round trip through
+        // the sub-queue; only an overflowing local queue shares work.  The
+        // batch counts as consumed after all of it, so termination cannot
+        // be declared while these items are in flight.
+        while (lq.count > 0) {
+          const int take = min(lq.count, kWave);
+          __builtin_amdgcn_wave_barrier();
+          const int32_t xi = lane_id() < take ? lq.buf[lq.count - take + lane_id()] : -1;
+          __builtin_amdgcn_wave_barrier();
+          lq.count -= take;
+          peel_batch<KIND>(a, xi, 0, lq, entries);
+        }
+        lq.flush();
+        // the appends are visible before the items count as processed
+        __builtin_amdgcn_s_waitcnt(0);
+        if (lane_id() == 0) atomicAdd(consumed, (int)__popcll(rmask));
+        pending = pending && !ready;
+        idle = 0;
+        continue;
+      }
+      // waiting: poll the own slots with growing back-off (the counters share
+      // lines with the producers' atomics), test for termination every
+      // fourth poll, and give up after the spin limit (an abort, reported)
+      ++idle;
+      if ((idle & 3) == 0 && (quiescent(a.st) || ld_agent(&a.st->abort_flag))) {
+        finished = true;
+        break;
+      }
+      if (idle > kAsyncSpinLimit) {
+        if (lane_id() == 0) st_agent(&a.st->abort_flag, 1);
+        finished = true;
+        break;
+      }
+      for (uint32_t k = 0; k < min(idle, 16u); ++k) __builtin_amdgcn_s_sleep(4);
+    }
+  }
+  add_part(a.part, kPartEntries, entries, &s_acc);
+}
+
+hipError_t launch_peel_async(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
+                             hipStream_t s) {
+  PeelArgs a = make_args(g, thrU, thrL);
+  async_prepare_kernel<<<1, 64, 0, s>>>(g.state);
+  const int grid = peel_grid(g);
+  if (kind == kGCC)
+    peel_async_kernel<kGCC><<<grid, kPeelBlock, 0, s>>>(a);
+  else
+    peel_async_kernel<kGCCPlus><<<grid, kPeelBlock, 0, s>>>(a);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------ pull first round --
