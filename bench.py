@@ -149,8 +149,9 @@ def main() -> int:
     scan_bytes = 8 * n + 4 * int(f0.sum()) + (n // 8 if pulled else 0)
     pack_bytes = 4 * n + n // 8
     kinfo = {}
-    names = {0: "peel_persistent_kernel<GCC>", 1: "pull_round_kernel", 2: "scan_gcc_kernel",
-             3: "pack_kernel"}
+    peel_name = {1: "peel_round_kernel<GCC>", 2: "peel_persistent_kernel<GCC>"}.get(
+        args.peel_mode, "peel_async_kernel<GCC>")
+    names = {0: peel_name, 1: "pull_round_kernel", 2: "scan_gcc_kernel", 3: "pack_kernel"}
     kbytes = {0: push_bytes, 1: pull_bytes, 2: scan_bytes, 3: pack_bytes}
     for kind, (ms, launches) in ktime.items():
         if launches == 0:

@@ -139,8 +139,12 @@ abcore_status abcore_query(abcore_graph g, abcore_edge_update upd, uint32_t alph
 /* Tuning knobs (non-negative values; 0 restores the default).
  *   ABCORE_OPT_PEEL_MODE : 1 = one kernel per peel round, host-checked in
  *                          batches; 2 = all rounds in one cooperative launch
- *                          with a grid barrier between rounds (default when
- *                          the device reports co-residency).
+ *                          with a grid barrier between rounds; 3 (default) =
+ *                          asynchronous worklist: one launch, no rounds,
+ *                          waves take queued vertices as soon as they are
+ *                          appended (stats.rounds is then -1).  Modes 2 and 3
+ *                          fall back to 1 when the device reports no
+ *                          co-residency of the grid.
  *   ABCORE_OPT_GRID      : workgroups per peel launch.
  *   ABCORE_OPT_ROUNDS_PER_SYNC : round kernels enqueued between checks.
  *   ABCORE_OPT_TIMING    : 1 = record a HIP event pair on the caller's stream

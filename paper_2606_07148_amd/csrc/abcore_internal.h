@@ -151,6 +151,7 @@ struct Graph {
   int rounds_per_sync = 16;
   int persistent_grid = 0;  // co-resident workgroups of the persistent kernels
   int kcore_grid = 0;
+  int async_grid = 0;       // co-resident workgroups of the asynchronous peel
   // kernel timing (ABCORE_OPT_TIMING): event pairs per kernel kind
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events[4];

@@ -321,6 +321,8 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
       // no co-residency information: the cooperative kernels are not used
       g->persistent_grid = 0;
       g->kcore_grid = 0;
+      g->async_grid = 0;
+      g->peel_mode = 1;
     }
     (void)prepare_pull_kernel(*g);
     if (launch_init_state(*g, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
@@ -378,11 +380,11 @@ abcore_status abcore_set_option(abcore_graph h, int32_t option, int64_t value) {
   }
   switch (option) {
     case ABCORE_OPT_PEEL_MODE:
-      if (value > 3 || (value == 2 && g->persistent_grid <= 0)) {
+      if (value > 3 || (value >= 2 && g->persistent_grid <= 0)) {
         set_error("abcore_set_option: peel mode %lld not available", (long long)value);
         return ABCORE_EINVAL;
       }
-      g->peel_mode = value == 0 ? 3 : (int)value;
+      g->peel_mode = value != 0 ? (int)value : g->persistent_grid > 0 ? 3 : 1;
       return ABCORE_OK;
     case ABCORE_OPT_GRID:
       g->grid = (int)std::min<int64_t>(value, kMaxBlocks);

@@ -551,17 +551,10 @@ hipError_t launch_peel_persistent(Graph &g, PeelKind kind, int32_t thrU, int32_t
 // waiting wave of that sub-queue.  Termination: every queued item has been
 // processed, read as sum(done) == sum(tail) with all `done` read before any
 // `tail` (an item's appends precede its `done` increment), which means no item
-// was in flight and none can be appended any more.  Needs no co-residency:
-// a wave only waits on slots that an already running wave has reserved.
-
-__global__ void async_prepare_kernel(PeelState *st) {
-  const int j = threadIdx.x;
-  if (j < kSub) {
-    const int32_t lo = ld_agent(&st->lo[j]);
-    st_agent(&st->head[j][0], lo);
-    st_agent(&st->consumed[j][0], lo);
-  }
-}
+// was in flight and none can be appended any more.  Waiting waves end only
+// at termination, so every sub-queue needs a running workgroup: the grid is
+// kept within the co-resident capacity, which places the first kSub
+// workgroups on the device together.
 
 __device__ __forceinline__ bool quiescent(PeelState *st) {
   const int j = lane_id();
@@ -650,8 +643,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
 hipError_t launch_peel_async(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
                              hipStream_t s) {
   PeelArgs a = make_args(g, thrU, thrL);
-  async_prepare_kernel<<<1, 64, 0, s>>>(g.state);
-  const int grid = peel_grid(g);
+  const int grid = std::max(kSub, std::min(peel_grid(g), g.async_grid));
   if (kind == kGCC)
     peel_async_kernel<kGCC><<<grid, kPeelBlock, 0, s>>>(a);
   else
@@ -1359,6 +1351,14 @@ hipError_t query_persistent_grids(Graph &g) {
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
       &per_cu3, reinterpret_cast<const void *>(&kcore_persistent_kernel), kPeelBlock, 0);
   if (e != hipSuccess) return e;
+  int per_cu4 = 0, per_cu5 = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu4, reinterpret_cast<const void *>(&peel_async_kernel<kGCC>), kPeelBlock, 0);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu5, reinterpret_cast<const void *>(&peel_async_kernel<kGCCPlus>), kPeelBlock, 0);
+  if (e != hipSuccess) return e;
+  g.async_grid = std::min(kMaxBlocks, g.cu_count * std::max(1, std::min({per_cu4, per_cu5, 4})));
   const int pc = std::max(1, std::min({per_cu, per_cu2, 2}));
   g.persistent_grid = std::min(kMaxBlocks, g.cu_count * pc);
   g.kcore_grid = std::min(kMaxBlocks, g.cu_count * std::max(1, std::min(per_cu3, 2)));

@@ -189,6 +189,8 @@ __device__ __forceinline__ void advance_round_wave(PeelState *st) {
   if (j < kSub) {
     st_agent(&st->lo[j], h);
     st_agent(&st->hi[j], t);
+    st_agent(&st->head[j][0], h);  // the asynchronous peel starts at lo
+    st_agent(&st->consumed[j][0], h);
   }
   if (j == 0 && prev > 0) bump(&st->rounds);
 }
@@ -201,6 +203,8 @@ __device__ __forceinline__ void start_rounds_wave(PeelState *st) {
     t = ld_agent(&st->tail[j][0]);
     st_agent(&st->lo[j], 0);
     st_agent(&st->hi[j], t);
+    st_agent(&st->head[j][0], 0);
+    st_agent(&st->consumed[j][0], 0);
   }
   const int tot = wave_sum(t);
   if (j == 0) {
