@@ -39,6 +39,34 @@ def _cpu_model() -> str:
     return platform.processor()
 
 
+def _kernel_source_hash() -> str:
+    """SHA-256 over the kernel sources, sorted by name (name, then content)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "paper_2606_07148_amd", "csrc", "*"))):
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _counter_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed hardware-counter
+    summary, or None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "gcc_chung_lu_1M_500k_20M_a10_b10.md")
+    try:
+        text = open(path).read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(block)
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_sha256") != _kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["traffic_bytes"]
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -48,6 +76,10 @@ def main() -> int:
                     help="approximate CPU time spent on the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--peel-mode", type=int, default=0)
+    ap.add_argument("--gcc-only", action="store_true",
+                    help="skip GCC+ and its core-number preprocessing")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one device copy of MIB MiB (hardware-counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -75,6 +107,16 @@ def main() -> int:
     print(f"# generated {len(eu)} edges in {gen_s:.1f}s", file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # give the scale between counted and moved bytes
+        words = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(words, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     deu = torch.from_numpy(eu).cuda()
     dev = torch.from_numpy(ev).cuda()
     torch.cuda.synchronize()
@@ -113,18 +155,23 @@ def main() -> int:
     got = out.cpu().numpy().view(np.uint32)[: len(want)]
     parity = bool(np.array_equal(got, want))
     _, gst = pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out, stats=True)
-    pkg.abcore_set_option(g, pkg.ABCORE_OPT_TIMING, 1)
-    for kind in range(4):
-        pkg.abcore_kernel_timing(g, kind, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    ktime = {kind: pkg.abcore_kernel_timing(g, kind, reset=True) for kind in range(4)}
-    pkg.abcore_set_option(g, pkg.ABCORE_OPT_TIMING, 0)
     ms_per_step = elapsed * 1e3 / args.steps
+    # per-kernel durations: the same steps again with an event pair around
+    # every launch, on the stream the kernels run on
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_TIMING, 1)
+    for kind in range(5):
+        pkg.abcore_kernel_timing(g, kind, reset=True)
+    for _ in range(args.steps):
+        pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out)
+    torch.cuda.synchronize()
+    ktime = {kind: pkg.abcore_kernel_timing(g, kind, reset=True) for kind in range(5)}
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_TIMING, 0)
     value = m_peeled / (ms_per_step / 1e3)
 
     # algorithmic bytes per query of each kernel, from the oracle's sets:
@@ -149,10 +196,13 @@ def main() -> int:
     scan_bytes = 8 * n + 4 * int(f0.sum()) + (n // 8 if pulled else 0)
     pack_bytes = 4 * n + n // 8
     kinfo = {}
-    peel_name = {1: "peel_round_kernel<GCC>", 2: "peel_persistent_kernel<GCC>"}.get(
-        args.peel_mode, "peel_async_kernel<GCC>")
-    names = {0: peel_name, 1: "pull_round_kernel", 2: "scan_gcc_kernel", 3: "pack_kernel"}
-    kbytes = {0: push_bytes, 1: pull_bytes, 2: scan_bytes, 3: pack_bytes}
+    peel_name = {1: "peel_round_kernel<0>", 2: "peel_persistent_kernel<0>"}.get(
+        args.peel_mode, "peel_async_kernel<0>")  # <0> = the GCC instantiation
+    names = {0: peel_name, 1: "pull_round_kernel", 2: "scan_gcc_kernel", 3: "pack_kernel",
+             4: "pull_fixup_kernel"}
+    # fixup: split rows (more than 64 entries): row id, deg0 and deg read
+    fixup_bytes = 12 * int(np.count_nonzero(deg > 64)) if pulled else 0
+    kbytes = {0: push_bytes, 1: pull_bytes, 2: scan_bytes, 3: pack_bytes, 4: fixup_bytes}
     for kind, (ms, launches) in ktime.items():
         if launches == 0:
             continue
@@ -162,23 +212,29 @@ def main() -> int:
                               launches / args.steps, "bytes_per_launch": bpl,
                               "achieved_GBs": bpl / per_launch_s / 1e9 if per_launch_s > 0 else 0}
     dom = max(kinfo, key=lambda k: kinfo[k]["avg_launch_us"] * kinfo[k]["launches_per_step"])
-    step_bytes = scan_bytes + pull_bytes + push_bytes + pack_bytes
+    step_bytes = scan_bytes + pull_bytes + push_bytes + pack_bytes + fixup_bytes
 
     # --- GCC+ (Algorithm 2): preprocessing + query ------------------------
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, max_core = pkg.abcore_core_numbers(g)
-    torch.cuda.synchronize()
-    prep_ms = (time.perf_counter() - t0) * 1e3
-    for _ in range(args.warmup):
-        pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC_PLUS, out=out)
-    torch.cuda.synchronize()
-    plus_parity = bool(np.array_equal(out.cpu().numpy().view(np.uint32)[: len(want)], want))
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC_PLUS, out=out)
-    torch.cuda.synchronize()
-    plus_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    gcc_plus = None
+    plus_parity = True
+    if not args.gcc_only:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, max_core = pkg.abcore_core_numbers(g)
+        torch.cuda.synchronize()
+        prep_ms = (time.perf_counter() - t0) * 1e3
+        for _ in range(args.warmup):
+            pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC_PLUS, out=out)
+        torch.cuda.synchronize()
+        plus_parity = bool(np.array_equal(out.cpu().numpy().view(np.uint32)[: len(want)], want))
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC_PLUS, out=out)
+        torch.cuda.synchronize()
+        plus_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        gcc_plus = {"ms_per_query": plus_ms, "parity": plus_parity,
+                    "edges_peeled_per_s": m_peeled / (plus_ms / 1e3),
+                    "core_preprocessing_ms": prep_ms, "max_core": max_core}
 
     result = {
         "metric": "edges peeled/sec",
@@ -207,7 +263,7 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": kinfo[dom]["achieved_GBs"] / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": _counter_traffic(dom),
             "bytes_per_launch": kinfo[dom]["bytes_per_launch"],
             "avg_launch_us": kinfo[dom]["avg_launch_us"],
         },
@@ -220,9 +276,7 @@ def main() -> int:
         "step_algorithmic_bytes": step_bytes,
         "step_gbs": step_bytes / (ms_per_step / 1e3) / 1e9,
         "input_edges_per_s": ref.m / (ms_per_step / 1e3),
-        "gcc_plus": {"ms_per_query": plus_ms, "parity": plus_parity,
-                     "edges_peeled_per_s": m_peeled / (plus_ms / 1e3),
-                     "core_preprocessing_ms": prep_ms, "max_core": max_core},
+        "gcc_plus": gcc_plus,
         "build_s": build_s,
     }
     if not args.no_cpu_baseline:

@@ -161,14 +161,16 @@ enum {
 };
 abcore_status abcore_set_option(abcore_graph g, int32_t option, int64_t value);
 
-/* Kernel kinds timed while ABCORE_OPT_TIMING is on: the push peel rounds
- * (Algorithm 1, peel phase), the pull-form first round, the scan phase and
- * the bitmask pack. */
+/* Kernel kinds timed while ABCORE_OPT_TIMING is on: the push peel
+ * (Algorithm 1, peel phase), the pull-form first round, the scan phase, the
+ * bitmask pack and the pull round's completion (split rows below threshold
+ * queued, round range advanced). */
 enum {
   ABCORE_KERNEL_PEEL = 0,
   ABCORE_KERNEL_PULL = 1,
   ABCORE_KERNEL_SCAN = 2,
-  ABCORE_KERNEL_PACK = 3
+  ABCORE_KERNEL_PACK = 3,
+  ABCORE_KERNEL_FIXUP = 4
 };
 
 /* GPU time of one kernel kind recorded while ABCORE_OPT_TIMING is on:

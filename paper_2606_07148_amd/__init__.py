@@ -174,6 +174,7 @@ ABCORE_KERNEL_PEEL = 0
 ABCORE_KERNEL_PULL = 1
 ABCORE_KERNEL_SCAN = 2
 ABCORE_KERNEL_PACK = 3
+ABCORE_KERNEL_FIXUP = 4
 
 
 def abcore_kernel_timing(g: Graph, kernel: int, reset: bool = True):

@@ -154,9 +154,10 @@ struct Graph {
   int async_grid = 0;       // co-resident workgroups of the asynchronous peel
   // kernel timing (ABCORE_OPT_TIMING): event pairs per kernel kind
   bool timing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> events[4];
+  static constexpr int kKernelKinds = 5;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events[kKernelKinds];
   std::vector<hipEvent_t> event_pool;
-  int64_t timed_launches[4] = {0, 0, 0, 0};
+  int64_t timed_launches[kKernelKinds] = {0, 0, 0, 0, 0};
 };
 
 // Peel flavours.
@@ -190,6 +191,7 @@ hipError_t launch_init_state(Graph &g, hipStream_t s);
 hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, bool want_bits,
                            hipStream_t s);
 hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s);
+hipError_t launch_pull_fixup(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s);
 hipError_t launch_scan_component_of(Graph &g, int32_t thrU, int32_t thrL, int32_t x,
                                     int32_t y, hipStream_t s);
 hipError_t launch_peel_rounds(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,

@@ -96,7 +96,7 @@ hipError_t take_event(Graph &g, hipEvent_t *e) {
 }
 
 // Records an event pair of kernel kind `kind` around `launch` when timing
-// is on (kinds: ABCORE_KERNEL_PEEL, _PULL, _SCAN, _PACK).
+// is on (kinds: ABCORE_KERNEL_PEEL, _PULL, _SCAN, _PACK, _FIXUP).
 template <class F>
 hipError_t timed(Graph &g, int kind, hipStream_t s, int64_t nlaunch, F launch) {
   if (!g.timing) return launch();
@@ -411,7 +411,7 @@ abcore_status abcore_set_option(abcore_graph h, int32_t option, int64_t value) {
 abcore_status abcore_kernel_timing(abcore_graph h, int32_t kernel, double *ms,
                                    int64_t *launches, int32_t reset) {
   Graph *g = reinterpret_cast<Graph *>(h);
-  if (!g || kernel < 0 || kernel > 3) {
+  if (!g || kernel < 0 || kernel >= Graph::kKernelKinds) {
     set_error("abcore_kernel_timing: null handle or unknown kernel kind");
     return ABCORE_EINVAL;
   }
@@ -493,9 +493,12 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
     CHK(launch_init_state(*g, s));
     CHK(timed(*g, ABCORE_KERNEL_SCAN, s, 1,
               [&] { return launch_scan_gcc(*g, thrU, thrL, pull, s); }));
-    if (pull)
+    if (pull) {
       CHK(timed(*g, ABCORE_KERNEL_PULL, s, 1,
                 [&] { return launch_pull_round(*g, thrU, thrL, s); }));
+      CHK(timed(*g, ABCORE_KERNEL_FIXUP, s, 1,
+                [&] { return launch_pull_fixup(*g, thrU, thrL, s); }));
+    }
     TRY(run_peel(*g, kGCC, thrU, thrL, s, &launches));
     CHK(timed(*g, ABCORE_KERNEL_PACK, s, 1,
               [&] { return launch_pack(*g, thrU, thrL, d_bitmask, s); }));

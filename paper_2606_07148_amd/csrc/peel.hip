@@ -871,8 +871,13 @@ hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s
   pull_round_kernel<<<g.cu_count, kPullBlock, dyn, s>>>(
       a, g.alive_bits, g.deg0, g.n, scan_grid(g), g.pull_mode, use_lds ? 1 : 0, total_entries,
       g.npieces, g.npieces_upper);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+// Must follow launch_pull_round on the same stream (it completes that round).
+hipError_t launch_pull_fixup(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s) {
+  if (g.pull_mode == 1) return hipSuccess;
+  PeelArgs a = make_args(g, thrU, thrL);
   pull_fixup_kernel<<<flat_grid(g, std::max<int64_t>(g.nheavy, 1), kPeelBlock), kPeelBlock, 0, s>>>(
       a, g.alive_bits, g.heavy_rows, g.nheavy);
   return hipGetLastError();
