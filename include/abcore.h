@@ -109,6 +109,34 @@ abcore_status abcore_export_csr(abcore_graph g, int64_t *d_off, int32_t *d_cols,
 abcore_status abcore_compute(abcore_graph g, uint32_t alpha, uint32_t beta, int32_t algo,
                              uint32_t *d_bitmask, abcore_stats *stats, void *stream);
 
+/* Batch of q queries (thresholds h_alpha[i], h_beta[i], HOST arrays of q
+ * values >= 1) computed in one call.  Result i is written to d_bitmasks +
+ * i * ceil(n/32) (DEVICE, q * ceil(n/32) words, every word written) and equals
+ * abcore_compute(g, h_alpha[i], h_beta[i], ...) bit for bit.
+ * Method: the cores are nested -- the (a,b)-core lies inside the
+ * (a',b')-core whenever a' <= a and b' <= b, the property behind Lemma 1's
+ * proof (Sec. IV-B).  Each query starts from the final degrees and
+ * survivors of a query it dominates and peels only the difference
+ * (Algorithm 1's scan and peel on that state); equal queries share one
+ * computation.  The plan is abcore_batch_plan's.  The working degrees need
+ * `states` buffers of n int32, allocated on first use and kept by the handle
+ * (ENOMEM if they do not fit).  In the default peel mode the whole batch is
+ * captured into one HIP graph, cached for the same thresholds, output pointer
+ * and graph version, and replayed.  Synchronous.
+ * Errors: EINVAL (null pointer, q < 0, a threshold 0), ENOMEM, EDEVICE. */
+abcore_status abcore_compute_batch(abcore_graph g, const uint32_t *h_alpha,
+                                   const uint32_t *h_beta, int32_t q, uint32_t *d_bitmasks,
+                                   void *stream);
+
+/* The plan abcore_compute_batch follows, on the host only (no device call).
+ * h_parent[i] (nullable, HOST q int32): the query whose final state query i
+ * starts from (it is dominated: alpha and beta both <=), or -1 to start from
+ * the graph; equal queries name the first of them.  h_order (nullable, HOST
+ * q int32): execution order, parents first.  out_states (nullable): number
+ * of n-int32 degree buffers the plan needs.  Errors: EINVAL. */
+abcore_status abcore_batch_plan(const uint32_t *h_alpha, const uint32_t *h_beta, int32_t q,
+                                int32_t *h_parent, int32_t *h_order, int32_t *out_states);
+
 /* Core numbers (Definition 2): core(x) = largest delta with x in the
  * (delta,delta)-core, 0 for isolated vertices.  Computed once per graph
  * version and cached for GCC+.  d_core: DEVICE n int32, or NULL to only fill

@@ -114,6 +114,12 @@ def compute(g: Graph, alpha: int, beta: int) -> np.ndarray:
     return peel(g, alpha, beta)[0]
 
 
+def batch(g: Graph, alphas, betas) -> np.ndarray:
+    """Bitmasks of several queries: one independent peel per query (the
+    batch must equal the queries computed one at a time)."""
+    return np.stack([pack(compute(g, a, b)) for a, b in zip(alphas, betas)])
+
+
 def core_numbers(g: Graph) -> np.ndarray:
     core = np.zeros(max(1, g.n), np.int32)
     if _load().or_core_numbers(g.n_upper, g.n_lower, _ptr(g.off), _ptr(g.cols),

@@ -76,6 +76,8 @@ def load():
         "abcore_query": (i32, [vp, abcore_edge_update, u32, u32, P(i32), P(u32), vp]),
         "abcore_set_option": (i32, [vp, i32, i64]),
         "abcore_kernel_timing": (i32, [vp, i32, P(ctypes.c_double), P(i64), i32]),
+        "abcore_compute_batch": (i32, [vp, P(u32), P(u32), i32, vp, vp]),
+        "abcore_batch_plan": (i32, [P(u32), P(u32), i32, P(i32), P(i32), P(i32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -211,6 +213,38 @@ def abcore_compute(g: Graph, alpha: int, beta: int, algo: int = ABCORE_GCC, out=
                                  ctypes.byref(st) if st is not None else None,
                                  _stream(stream)))
     return (out, st.as_dict()) if stats else out
+
+
+def _u32_array(values):
+    vals = [int(x) for x in values]
+    return (ctypes.c_uint32 * max(1, len(vals)))(*vals), len(vals)
+
+
+def abcore_compute_batch(g: Graph, alphas, betas, out=None, stream=None):
+    """Bitmasks of q queries: int32 CUDA tensor (q, ceil(n/32)); row i is the
+    (alphas[i], betas[i])-core."""
+    import torch
+    a, q = _u32_array(alphas)
+    b, qb = _u32_array(betas)
+    if q != qb:
+        raise ValueError("alphas and betas differ in length")
+    if out is None:
+        out = torch.empty((q, max(1, g.nwords)), dtype=torch.int32, device="cuda")
+    _check(load().abcore_compute_batch(g.handle, a, b, q, _ptr(out), _stream(stream)))
+    return out
+
+
+def abcore_batch_plan(alphas, betas):
+    """(parent list, execution order, degree buffers needed) of a batch."""
+    a, q = _u32_array(alphas)
+    b, qb = _u32_array(betas)
+    if q != qb:
+        raise ValueError("alphas and betas differ in length")
+    parent = (ctypes.c_int32 * max(1, q))()
+    order = (ctypes.c_int32 * max(1, q))()
+    states = ctypes.c_int32()
+    _check(load().abcore_batch_plan(a, b, q, parent, order, ctypes.byref(states)))
+    return list(parent)[:q], list(order)[:q], int(states.value)
 
 
 def abcore_core_numbers(g: Graph, stream=None):

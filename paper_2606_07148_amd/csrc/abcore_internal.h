@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include <string>
@@ -105,6 +106,27 @@ struct Delta {
   int64_t count = 0;         // pairs used
 };
 
+// Execution plan of a batch of queries (make_batch_plan).
+struct BatchPlan {
+  std::vector<int32_t> order;   // execution order (query indices)
+  std::vector<int32_t> parent;  // query whose final state seeds it, -1 = the graph
+  std::vector<uint8_t> dup;     // 1: same thresholds as parent, bitmask copied
+  std::vector<uint8_t> copy;    // 1: starts from a copy of the parent's state
+  std::vector<int32_t> slot;    // state buffer (-1 for duplicates)
+  int nslots = 0;
+};
+BatchPlan make_batch_plan(const int32_t *tu, const int32_t *tl, int32_t q);
+
+// A captured batch of nested queries, replayed while the same batch is
+// asked for again on an unchanged graph.
+struct BatchCache {
+  std::vector<int32_t> key;  // thresholds of the queries, then options
+  uint32_t *bits = nullptr;  // output the graph writes
+  int version = -1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct Graph {
   int device = 0;
   int32_t nU = 0, nL = 0;
@@ -152,6 +174,10 @@ struct Graph {
   int persistent_grid = 0;  // co-resident workgroups of the persistent kernels
   int kcore_grid = 0;
   int async_grid = 0;       // co-resident workgroups of the asynchronous peel
+  // batched queries: working-degree states (n int32 each) and the cache
+  std::vector<int32_t *> slots;
+  BatchCache batch;
+  hipStream_t capture_stream = nullptr;
   // kernel timing (ABCORE_OPT_TIMING): event pairs per kernel kind
   bool timing = false;
   static constexpr int kKernelKinds = 5;
@@ -187,9 +213,13 @@ void set_error(const char *fmt, ...);
 PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL);
 
 // Launchers (defined in the .hip files).
-hipError_t launch_init_state(Graph &g, hipStream_t s);
+// keep_abort: leave the abort flag as it is (several computations in one
+// sequence report a spin-limit abort of any of them)
+hipError_t launch_init_state(Graph &g, hipStream_t s, bool keep_abort = false);
 hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, bool want_bits,
                            hipStream_t s);
+hipError_t launch_scan_nested(Graph &g, int32_t pU, int32_t pL, int32_t thrU, int32_t thrL,
+                              hipStream_t s);
 hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s);
 hipError_t launch_pull_fixup(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s);
 hipError_t launch_scan_component_of(Graph &g, int32_t thrU, int32_t thrL, int32_t x,

@@ -61,6 +61,11 @@ void free_graph(Graph *g) {
       (void)hipEventDestroy(pr.second);
     }
   for (hipEvent_t e : g->event_pool) (void)hipEventDestroy(e);
+  if (g->batch.exec) (void)hipGraphExecDestroy(g->batch.exec);
+  if (g->batch.graph) (void)hipGraphDestroy(g->batch.graph);
+  if (g->capture_stream) (void)hipStreamDestroy(g->capture_stream);
+  for (int32_t *p : g->slots)
+    if (p) (void)hipFree(p);
   void *bufs[] = {g->off,        g->cols,        g->deg0,        g->deg,
                   g->queue,      g->list,        g->list2,       g->state,
                   g->core,       g->comp,        g->parent,      g->delta.head,
@@ -246,7 +251,171 @@ abcore_status ensure_delta(Graph &g, hipStream_t s) {
   return ABCORE_OK;
 }
 
+// ------------------------------------------------------------- batches --
+// Runs the nested sequence of a batch plan on stream s (every launch is
+// stream-ordered with no host read, so the sequence can be captured).
+// Working degrees of query i live in slot plan.slot[i]; g.deg is restored on
+// every exit.
+abcore_status run_batch(Graph &g, const BatchPlan &plan, const int32_t *tu, const int32_t *tl,
+                        uint32_t *bits, hipStream_t s) {
+  struct Restore {
+    Graph &g;
+    int32_t *deg;
+    ~Restore() { g.deg = deg; }
+  } restore{g, g.deg};
+  const int64_t words = (g.n + 31) / 32;
+  const bool pull = g.pull_mode != 1;
+  int64_t launches = 0;
+  CHK(launch_init_state(g, s));  // clears the abort flag once for the batch
+  for (int32_t i : plan.order) {
+    uint32_t *out = bits + (int64_t)i * words;
+    const int32_t p = plan.parent[i];
+    if (plan.dup[i]) {
+      if (words > 0)
+        CHK(hipMemcpyAsync(out, bits + (int64_t)p * words, sizeof(uint32_t) * words,
+                           hipMemcpyDeviceToDevice, s));
+      continue;
+    }
+    g.deg = g.slots[plan.slot[i]];
+    if (p < 0) {
+      CHK(launch_init_state(g, s, true));
+      CHK(launch_scan_gcc(g, tu[i], tl[i], pull, s));
+      if (pull) {
+        CHK(launch_pull_round(g, tu[i], tl[i], s));
+        CHK(launch_pull_fixup(g, tu[i], tl[i], s));
+      }
+    } else {
+      if (plan.copy[i] && g.n > 0)
+        CHK(hipMemcpyAsync(g.deg, g.slots[plan.slot[p]], sizeof(int32_t) * g.n,
+                           hipMemcpyDeviceToDevice, s));
+      CHK(launch_init_state(g, s, true));
+      CHK(launch_scan_nested(g, tu[p], tl[p], tu[i], tl[i], s));
+    }
+    TRY(run_peel(g, kGCC, tu[i], tl[i], s, &launches));
+    CHK(launch_pack(g, tu[i], tl[i], out, s));
+  }
+  return ABCORE_OK;
+}
+
+abcore_status ensure_slots(Graph &g, int n_slots) {
+  while ((int)g.slots.size() < n_slots) {
+    int32_t *p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(int32_t) * std::max<int64_t>(g.n, 1));
+    if (e != hipSuccess) {
+      set_error("batch: allocation of degree state %d failed: %s", (int)g.slots.size(),
+                hipGetErrorString(e));
+      return ABCORE_ENOMEM;
+    }
+    g.slots.push_back(p);
+  }
+  return ABCORE_OK;
+}
+
+void drop_batch_cache(Graph &g) {
+  if (g.batch.exec) (void)hipGraphExecDestroy(g.batch.exec);
+  if (g.batch.graph) (void)hipGraphDestroy(g.batch.graph);
+  g.batch = BatchCache();
+}
+
 }  // namespace
+
+// Plan of a batch of queries (host only).  Query i computes the core for
+// thresholds (tu[i], tl[i]).  The (a,b)-core is contained in the (a',b')-core
+// whenever a' <= a and b' <= b (the nesting that the proof of Lemma 1 uses),
+// so a query can start from the final state of any query it dominates and
+// peel only the difference.  Queries are taken in lexicographic order of
+// (tu, tl), a topological order of dominance; each picks as parent the
+// dominated earlier query with the largest tu + tl (the smallest core it
+// can expect), among the last kPlanWindow distinct ones.  Equal queries copy
+// the bitmask of the first.  The tree runs depth first, the child with the
+// largest subtree last: that child continues in its parent's state buffer,
+// the others start from a copy, and a buffer returns to the pool when the
+// chain using it ends at a leaf.
+BatchPlan make_batch_plan(const int32_t *tu, const int32_t *tl, int32_t q) {
+  constexpr int kPlanWindow = 4096;
+  BatchPlan plan;
+  plan.parent.assign(q, -1);
+  plan.dup.assign(q, 0);
+  plan.copy.assign(q, 0);
+  plan.slot.assign(q, -1);
+  std::vector<int32_t> idx(q);
+  for (int32_t i = 0; i < q; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
+    return tu[a] != tu[b] ? tu[a] < tu[b] : tl[a] < tl[b];
+  });
+  std::vector<int32_t> reps;  // distinct queries in sorted order
+  std::vector<std::vector<int32_t>> dups(q);
+  for (int32_t k = 0; k < q; ++k) {
+    const int32_t i = idx[k];
+    if (!reps.empty() && tu[reps.back()] == tu[i] && tl[reps.back()] == tl[i]) {
+      plan.parent[i] = reps.back();
+      plan.dup[i] = 1;
+      dups[reps.back()].push_back(i);
+      continue;
+    }
+    int32_t best = -1;
+    int64_t best_score = -1;
+    const int lo = std::max(0, (int)reps.size() - kPlanWindow);
+    for (int r = (int)reps.size() - 1; r >= lo; --r) {
+      const int32_t j = reps[r];
+      if (tu[j] <= tu[i] && tl[j] <= tl[i]) {
+        const int64_t score = (int64_t)tu[j] + tl[j];
+        if (score > best_score) {
+          best_score = score;
+          best = j;
+        }
+      }
+    }
+    plan.parent[i] = best;
+    reps.push_back(i);
+  }
+  // children and subtree sizes (a parent precedes its children in reps)
+  std::vector<std::vector<int32_t>> kids(q);
+  std::vector<int64_t> size(q, 1);
+  std::vector<int32_t> roots;
+  for (int32_t i : reps) {
+    if (plan.parent[i] >= 0)
+      kids[plan.parent[i]].push_back(i);
+    else
+      roots.push_back(i);
+  }
+  for (auto it = reps.rbegin(); it != reps.rend(); ++it)
+    if (plan.parent[*it] >= 0) size[plan.parent[*it]] += size[*it];
+  for (int32_t i : reps)
+    std::stable_sort(kids[i].begin(), kids[i].end(),
+                     [&](int32_t a, int32_t b) { return size[a] < size[b]; });
+  // depth-first order and buffer assignment
+  std::vector<int32_t> free_slots;
+  auto take = [&]() {
+    if (!free_slots.empty()) {
+      const int32_t s = free_slots.back();
+      free_slots.pop_back();
+      return s;
+    }
+    return (int32_t)plan.nslots++;
+  };
+  std::vector<int32_t> stack;
+  for (auto it = roots.rbegin(); it != roots.rend(); ++it) stack.push_back(*it);
+  while (!stack.empty()) {
+    const int32_t i = stack.back();
+    stack.pop_back();
+    const int32_t p = plan.parent[i];
+    if (p < 0) {
+      plan.slot[i] = take();
+    } else if (kids[p].back() == i) {
+      plan.slot[i] = plan.slot[p];
+    } else {
+      plan.slot[i] = take();
+      plan.copy[i] = 1;
+    }
+    plan.order.push_back(i);
+    for (int32_t d : dups[i]) plan.order.push_back(d);
+    if (kids[i].empty()) free_slots.push_back(plan.slot[i]);
+    for (auto it = kids[i].rbegin(); it != kids[i].rend(); ++it) stack.push_back(*it);
+  }
+  return plan;
+}
+
 }  // namespace abc
 
 using namespace abc;
@@ -544,6 +713,100 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
     stats->pulled = p.pulled;
   }
   return ABCORE_OK;
+}
+
+static abcore_status batch_thresholds(const uint32_t *h_alpha, const uint32_t *h_beta,
+                                      int32_t q, std::vector<int32_t> &tu,
+                                      std::vector<int32_t> &tl) {
+  if (q < 0 || (q > 0 && (!h_alpha || !h_beta))) {
+    set_error("batch: negative count or null threshold array");
+    return ABCORE_EINVAL;
+  }
+  tu.resize(q);
+  tl.resize(q);
+  for (int32_t i = 0; i < q; ++i) {
+    if (h_alpha[i] < 1 || h_beta[i] < 1) {
+      set_error("batch: query %d has alpha or beta 0", i);
+      return ABCORE_EINVAL;
+    }
+    tu[i] = clamp_thr(h_alpha[i]);
+    tl[i] = clamp_thr(h_beta[i]);
+  }
+  return ABCORE_OK;
+}
+
+abcore_status abcore_batch_plan(const uint32_t *h_alpha, const uint32_t *h_beta, int32_t q,
+                                int32_t *h_parent, int32_t *h_order, int32_t *out_states) {
+  std::vector<int32_t> tu, tl;
+  TRY(batch_thresholds(h_alpha, h_beta, q, tu, tl));
+  BatchPlan plan = make_batch_plan(tu.data(), tl.data(), q);
+  for (int32_t i = 0; i < q; ++i) {
+    if (h_parent) h_parent[i] = plan.parent[i];
+    if (h_order) h_order[i] = plan.order[i];
+  }
+  if (out_states) *out_states = plan.nslots;
+  return ABCORE_OK;
+}
+
+abcore_status abcore_compute_batch(abcore_graph h, const uint32_t *h_alpha,
+                                   const uint32_t *h_beta, int32_t q, uint32_t *d_bitmasks,
+                                   void *stream) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (!g || (q > 0 && g->n > 0 && !d_bitmasks)) {
+    set_error("abcore_compute_batch: null handle or bitmask array");
+    return ABCORE_EINVAL;
+  }
+  std::vector<int32_t> tu, tl;
+  TRY(batch_thresholds(h_alpha, h_beta, q, tu, tl));
+  if (q == 0 || g->n == 0) return ABCORE_OK;
+  CHK(hipSetDevice(g->device));
+  hipStream_t s = as_stream(stream);
+  BatchPlan plan = make_batch_plan(tu.data(), tl.data(), q);
+  TRY(ensure_slots(*g, plan.nslots));
+  // the sequence has no host reads in the asynchronous peel mode: it is
+  // captured once into a HIP graph and replayed for the same batch
+  if (g->peel_mode != 3) {
+    TRY(run_batch(*g, plan, tu.data(), tl.data(), d_bitmasks, s));
+    return read_state(*g, s);
+  }
+  std::vector<int32_t> key;
+  key.reserve(2 * (size_t)q + 8);
+  key.insert(key.end(), tu.begin(), tu.end());
+  key.insert(key.end(), tl.begin(), tl.end());
+  key.push_back(q);
+  key.push_back(g->pull_mode);
+  key.push_back(g->grid);
+  key.push_back(g->delta.count > 0 ? 1 : 0);
+  BatchCache &c = g->batch;
+  if (!(c.exec && c.bits == d_bitmasks && c.version == g->version && c.key == key)) {
+    drop_batch_cache(*g);
+    if (!g->capture_stream) CHK(hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking));
+    const bool timing = g->timing;
+    g->timing = false;
+    CHK(hipStreamBeginCapture(g->capture_stream, hipStreamCaptureModeThreadLocal));
+    abcore_status st = run_batch(*g, plan, tu.data(), tl.data(), d_bitmasks, g->capture_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(g->capture_stream, &graph);
+    g->timing = timing;
+    if (st != ABCORE_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    CHK(e);
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      CHK(e);
+    }
+    c.graph = graph;
+    c.exec = exec;
+    c.bits = d_bitmasks;
+    c.version = g->version;
+    c.key = std::move(key);
+  }
+  CHK(hipGraphLaunch(c.exec, s));
+  return read_state(*g, s);
 }
 
 abcore_status abcore_query(abcore_graph h, abcore_edge_update upd, uint32_t alpha,

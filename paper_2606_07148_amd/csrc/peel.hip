@@ -33,9 +33,10 @@ constexpr int kScanChunk = 4096;  // vertices per workgroup chunk (4 per thread,
 
 // ---------------------------------------------------------------- state --
 
-__global__ void init_state_kernel(int32_t *st_words, int nwords, int64_t *part, int nparts) {
+__global__ void init_state_kernel(int32_t *st_words, int nwords, int64_t *part, int nparts,
+                                  int keep_word) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x)
-    st_words[i] = 0;
+    if (i != keep_word) st_words[i] = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nparts; i += gridDim.x * blockDim.x)
     part[i] = 0;
 }
@@ -56,12 +57,14 @@ __global__ void queue_reset_kernel(int32_t *queue, int64_t qcap, const PeelState
   }
 }
 
-hipError_t launch_init_state(Graph &g, hipStream_t s) {
+hipError_t launch_init_state(Graph &g, hipStream_t s, bool keep_abort) {
   static_assert(sizeof(PeelState) % 4 == 0, "state must be whole words");
+  static_assert(offsetof(PeelState, abort_flag) % 4 == 0, "abort flag must be a word");
   queue_reset_kernel<<<g.cu_count, 256, 0, s>>>(g.queue, g.qcap, g.state);
+  const int keep = keep_abort ? (int)(offsetof(PeelState, abort_flag) / 4) : -1;
   init_state_kernel<<<8, 256, 0, s>>>(reinterpret_cast<int32_t *>(g.state),
                                       (int)(sizeof(PeelState) / 4), g.part,
-                                      kMaxBlocks * kPartFields);
+                                      kMaxBlocks * kPartFields, keep);
   return hipGetLastError();
 }
 
@@ -260,6 +263,59 @@ hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, bool want_bits,
   PeelArgs a = make_args(g, thrU, thrL);
   scan_gcc_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, g.deg0,
                                                       want_bits ? g.alive_bits : nullptr, g.n);
+  return hipGetLastError();
+}
+
+// Scan of a nested query.  The working degrees hold the final state of a
+// query (pU, pL) that the new query (thrU, thrL) dominates (pU <= thrU and
+// pL <= thrL).  Its core contains the new core (the nesting of cores that
+// Lemma 1's proof rests on), and a survivor's degree is exactly its degree
+// inside it: every removed neighbour decremented it once (the filter never
+// skips a vertex at or above its threshold).  Vertices the earlier query
+// removed hold degrees below their old threshold and stay out; survivors
+// below the new threshold form the frontier.
+__global__ __launch_bounds__(kScanBlock) void scan_nested_kernel(PeelArgs a, int32_t pU,
+                                                                 int32_t pL, int64_t n) {
+  __shared__ ScanCollector col;
+  __shared__ int64_t s_acc;
+  if (threadIdx.x == 0) col.count = 0;
+  __syncthreads();
+  const int sub = blockIdx.x % kSub;
+  int32_t *q = a.queue + (int64_t)sub * a.qcap;
+  int64_t f0 = 0;
+  for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < n;
+       cb += (int64_t)gridDim.x * kScanChunk) {
+    for (int t = 0; t < kScanChunk; t += kScanBlock * 4) {
+      const int64_t x0 = cb + t + (int64_t)threadIdx.x * 4;
+      int32_t d[4] = {-1, -1, -1, -1};
+      if (x0 + 3 < n) {
+        const int4 v = *reinterpret_cast<const int4 *>(a.deg + x0);
+        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+      } else {
+        for (int j = 0; j < 4; ++j)
+          if (x0 + j < n) d[j] = a.deg[x0 + j];
+      }
+      int32_t items[4];
+      int cnt = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool up = (x0 + j) < a.nU;
+        if (x0 + j < n && d[j] >= (up ? pU : pL) && d[j] < (up ? a.thrU : a.thrL))
+          items[cnt++] = (int32_t)(x0 + j);
+      }
+      f0 += cnt;
+      col.append(items, cnt);
+    }
+    col.flush(q, &a.st->tail[sub][0]);
+  }
+  add_part(a.part, kPartF0, f0, &s_acc);
+  if (last_block_done<false>(a.st)) start_rounds_wave(a.st);
+}
+
+hipError_t launch_scan_nested(Graph &g, int32_t pU, int32_t pL, int32_t thrU, int32_t thrL,
+                              hipStream_t s) {
+  PeelArgs a = make_args(g, thrU, thrL);
+  scan_nested_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, pU, pL, g.n);
   return hipGetLastError();
 }
 
