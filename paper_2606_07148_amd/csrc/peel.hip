@@ -607,10 +607,11 @@ hipError_t launch_peel_persistent(Graph &g, PeelKind kind, int32_t thrU, int32_t
 // waiting wave of that sub-queue.  Termination: every queued item has been
 // processed, read as sum(done) == sum(tail) with all `done` read before any
 // `tail` (an item's appends precede its `done` increment), which means no item
-// was in flight and none can be appended any more.  Waiting waves end only
-// at termination, so every sub-queue needs a running workgroup: the grid is
-// kept within the co-resident capacity, which places the first kSub
-// workgroups on the device together.
+// was in flight and none can be appended any more.  A waiting wave also
+// steals: it claims exactly the appended-but-unclaimed slots of another
+// sub-queue (compare-and-swap on that head, never past its tail), so items
+// never wait for a workgroup of their own sub-queue to be resident, and
+// several peels can share the device without any co-residency assumption.
 
 __device__ __forceinline__ bool quiescent(PeelState *st) {
   const int j = lane_id();
@@ -630,6 +631,49 @@ __device__ __forceinline__ bool quiescent(PeelState *st) {
 // wait of a peel).
 constexpr uint32_t kAsyncSpinLimit = 1u << 21;
 
+// Removes one batch of up to 64 items and, last in first out, everything
+// the batch removes while it fits the wave's local buffer (local
+// continuation: no round trip through the sub-queue; only an overflowing
+// buffer shares work), then appends the rest and counts the batch as
+// processed.  The count follows the appends, so termination cannot be
+// declared while any of this is in flight.
+template <int KIND>
+__device__ __forceinline__ void async_batch(const PeelArgs &a, int32_t item, int nitems,
+                                            LocalQueue &lq, int32_t *consumed,
+                                            int64_t &entries) {
+  peel_batch<KIND>(a, item, 0, lq, entries);
+  while (lq.count > 0) {
+    const int take = min(lq.count, kWave);
+    __builtin_amdgcn_wave_barrier();
+    const int32_t xi = lane_id() < take ? lq.buf[lq.count - take + lane_id()] : -1;
+    __builtin_amdgcn_wave_barrier();
+    lq.count -= take;
+    peel_batch<KIND>(a, xi, 0, lq, entries);
+  }
+  lq.flush();
+  __builtin_amdgcn_s_waitcnt(0);
+  if (lane_id() == 0) atomicAdd(consumed, nitems);
+}
+
+// Claims up to 64 appended, unclaimed slots of sub-queue v (none past its
+// tail); returns the count claimed, base in *base.  Wave-uniform.
+__device__ __forceinline__ int steal_claim(PeelState *st, int v, int *base) {
+  int b = 0, c = 0;
+  if (lane_id() == 0) {
+    const int h = ld_agent(&st->head[v][0]);
+    const int t = ld_agent(&st->tail[v][0]);
+    if (h < t) {
+      const int want = min(t - h, kWave);
+      if (atomicCAS(&st->head[v][0], h, h + want) == h) {
+        b = h;
+        c = want;
+      }
+    }
+  }
+  *base = __shfl(b, 0, kWave);
+  return __shfl(c, 0, kWave);
+}
+
 template <int KIND>
 __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
   __shared__ int32_t s_lq[kPeelWaves][kLocalQueue];
@@ -639,7 +683,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
   int32_t *head = &a.st->head[j][0];
   int32_t *consumed = &a.st->consumed[j][0];
   int64_t entries = 0;
-  uint32_t idle = 0;
+  uint32_t idle = 0, victim = 0;
   bool finished = false;
   while (!finished) {
     int base = 0;
@@ -655,31 +699,38 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
       const bool ready = pending && item != kEmpty;
       const uint64_t rmask = __ballot(ready);
       if (rmask) {
-        peel_batch<KIND>(a, ready ? item : -1, 0, lq, entries);
-        // local continuation: the wave removes what its batch just queued
-        // (64 at a time, last in first out) instead of a round trip through
-        // the sub-queue; only an overflowing local queue shares work.  The
-        // batch counts as consumed after all of it, so termination cannot
-        // be declared while these items are in flight.
-        while (lq.count > 0) {
-          const int take = min(lq.count, kWave);
-          __builtin_amdgcn_wave_barrier();
-          const int32_t xi = lane_id() < take ? lq.buf[lq.count - take + lane_id()] : -1;
-          __builtin_amdgcn_wave_barrier();
-          lq.count -= take;
-          peel_batch<KIND>(a, xi, 0, lq, entries);
-        }
-        lq.flush();
-        // the appends are visible before the items count as processed
-        __builtin_amdgcn_s_waitcnt(0);
-        if (lane_id() == 0) atomicAdd(consumed, (int)__popcll(rmask));
+        async_batch<KIND>(a, ready ? item : -1, (int)__popcll(rmask), lq, consumed, entries);
         pending = pending && !ready;
         idle = 0;
         continue;
       }
-      // waiting: poll the own slots with growing back-off (the counters share
-      // lines with the producers' atomics), test for termination every
-      // fourth poll, and give up after the spin limit (an abort, reported)
+      // nothing in the own slots: steal from another sub-queue (one victim
+      // per poll, in rotation)
+      victim = victim % (kSub - 1) + 1;
+      int sbase;
+      const int taken = steal_claim(a.st, (j + (int)victim) % kSub, &sbase);
+      if (taken > 0) {
+        const int32_t *vq = a.queue + (int64_t)((j + (int)victim) % kSub) * a.qcap;
+        // the slots are reserved by appenders that are running: wait for
+        // their stores (bounded like every other wait)
+        int32_t sitem = -1;
+        if (lane_id() < taken) {
+          uint32_t spin = 0;
+          do {
+            sitem = ld_agent(&vq[sbase + lane_id()]);
+          } while (sitem == kEmpty && ++spin < kAsyncSpinLimit);
+          if (sitem == kEmpty) {
+            st_agent(&a.st->abort_flag, 1);
+            sitem = -1;
+          }
+        }
+        async_batch<KIND>(a, sitem, taken, lq, consumed, entries);
+        idle = 0;
+        continue;
+      }
+      // waiting: poll with growing back-off (the counters share lines with
+      // the producers' atomics), test for termination every fourth poll,
+      // and give up after the spin limit (an abort, reported)
       ++idle;
       if ((idle & 3) == 0 && (quiescent(a.st) || ld_agent(&a.st->abort_flag))) {
         finished = true;
@@ -699,7 +750,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
 hipError_t launch_peel_async(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
                              hipStream_t s) {
   PeelArgs a = make_args(g, thrU, thrL);
-  const int grid = std::max(kSub, std::min(peel_grid(g), g.async_grid));
+  const int grid = std::max(1, std::min(peel_grid(g), g.async_grid));
   if (kind == kGCC)
     peel_async_kernel<kGCC><<<grid, kPeelBlock, 0, s>>>(a);
   else

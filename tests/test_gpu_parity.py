@@ -139,6 +139,23 @@ def test_repeat_runs_identical():
     g.destroy()
 
 
+@pytest.mark.parametrize("grid", [1, 3, 17])
+def test_async_small_grids(grid):
+    """The asynchronous peel with fewer workgroups than sub-queues: items of
+    sub-queues without a workgroup of their own are taken by stealing."""
+    nU, nL, m = 30_000, 20_000, 400_000
+    eu, ev = bigraph_gen.chung_lu(nU, nL, m, 2.1, 2.1, 5000, 77 + grid)
+    g, ref = _make(nU, nL, eu, ev)
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_GRID, grid)
+    say("async peel, grid", grid)
+    for (a, b) in [(4, 4), (9, 3), (2, 12)]:
+        for pull in (1, 2):
+            pkg.abcore_set_option(g, pkg.ABCORE_OPT_PULL, pull)
+            _check_core(g, ref, a, b, pkg.ABCORE_GCC, f"grid{grid}")
+        _check_core(g, ref, a, b, pkg.ABCORE_GCC_PLUS, f"grid{grid}")
+    g.destroy()
+
+
 # ----------------------------------------------------------- core numbers --
 
 
