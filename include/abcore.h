@@ -41,7 +41,8 @@ typedef enum {
   ABCORE_EDEVICE = 3, /* a HIP call failed */
   ABCORE_ENOENT = 4,  /* deletion of an edge that is not present */
   ABCORE_EEXIST = 5,  /* insertion of an edge that is already present */
-  ABCORE_EBUSY = 6    /* no admission slot free (serving) */
+  ABCORE_EBUSY = 6,   /* no admission slot free, or the handle is serving */
+  ABCORE_EAGAIN = 7   /* abcore_poll: the request has not finished yet */
 } abcore_status;
 
 /* Algorithms of Sec. IV. */
@@ -163,6 +164,56 @@ abcore_status abcore_components(abcore_graph g, int32_t *d_comp, void *stream);
 abcore_status abcore_query(abcore_graph g, abcore_edge_update upd, uint32_t alpha,
                            uint32_t beta, int32_t *h_answer, uint32_t *h_endpoint_bits,
                            void *stream);
+
+/* ---- Serving: a stream of on-the-fly queries (Problem 2, Sec. V) -------
+ * Requests are the calls abcore_query would get, in submission order; each
+ * result equals what abcore_query returns when the requests are applied one
+ * at a time in ticket order (answer, endpoint bits, or the EEXIST/ENOENT
+ * rejection of an update that does not apply to the graph as the earlier
+ * requests left it).  A worker thread of the library takes the admitted
+ * requests in windows: it applies a window's updates in order (each at its
+ * own graph version: deletions keep their version, insertions take new
+ * edge slots), then peels each valid query's component(s) (GFQ's scoped
+ * Algorithm 1) on its own device working set, all working sets running
+ * concurrently on separate streams.  A new window starts as soon as working
+ * sets free up, while earlier queries still run.  Component labels only
+ * merge while serving (a stale label's component is a superset of the
+ * current ones, which keeps the scoped peel exact).  While a handle serves,
+ * every other entry point except abcore_graph_info and abcore_kernel_timing
+ * returns EBUSY. */
+
+/* Starts the engine (abcore_submit starts it with defaults if needed).
+ * max_inflight: admitted-but-unfinished requests allowed (0 = 1024);
+ * device_slots: concurrent device working sets, n + 16 * (2n + pieces)
+ * int32 each (0 = 8, at most 256); window: most updates per window (0 = 64,
+ * at most 64).  Computes the component labels if needed.  Synchronous.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+abcore_status abcore_serve_start(abcore_graph g, int64_t max_inflight, int32_t device_slots,
+                                 int32_t window);
+
+/* Admits one request: the update (u, v, op) and the (alpha,beta) membership
+ * question on the updated graph.  *ticket receives its number (consecutive
+ * from 0 per handle).  EBUSY when max_inflight requests are admitted and
+ * unfinished (retry later); EINVAL for ids out of range, op not +1/-1 or a
+ * threshold 0 (the request is not admitted); EDEVICE once the engine failed.
+ * Thread-safe with abcore_poll. */
+abcore_status abcore_submit(abcore_graph g, abcore_edge_update upd, uint32_t alpha,
+                            uint32_t beta, uint64_t *ticket);
+
+/* Result of a ticket.  ABCORE_OK: *answer (1 if both endpoints are in the
+ * core of the graph after that update), *endpoint_bits (bit0 u, bit1 v) and
+ * *t_done_ns (steady-clock nanoseconds, CLOCK_MONOTONIC, when the engine saw
+ * it finish) are written (each pointer nullable) and the result is released.
+ * EEXIST / ENOENT: the update was rejected (graph unchanged by it).
+ * EAGAIN: not finished yet, or already taken.  EINVAL: a ticket never
+ * issued.  EDEVICE: the engine failed.  Thread-safe with abcore_submit. */
+abcore_status abcore_poll(abcore_graph g, uint64_t ticket, int32_t *answer,
+                          uint32_t *endpoint_bits, uint64_t *t_done_ns);
+
+/* Waits for every admitted request to finish, stops the worker and frees the
+ * working sets (unpolled results stay available).  counters (nullable, HOST
+ * int64[3]): windows run, requests answered, requests rejected. */
+abcore_status abcore_serve_stop(abcore_graph g, int64_t *counters);
 
 /* Tuning knobs (non-negative values; 0 restores the default).
  *   ABCORE_OPT_PEEL_MODE : 1 = one kernel per peel round, host-checked in

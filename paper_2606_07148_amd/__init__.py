@@ -26,7 +26,7 @@ ABCORE_OPT_TIMING = 4
 ABCORE_OPT_PULL = 5
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOENT", 5: "EEXIST",
-          6: "EBUSY"}
+          6: "EBUSY", 7: "EAGAIN"}
 
 
 class AbcoreError(RuntimeError):
@@ -78,6 +78,10 @@ def load():
         "abcore_kernel_timing": (i32, [vp, i32, P(ctypes.c_double), P(i64), i32]),
         "abcore_compute_batch": (i32, [vp, P(u32), P(u32), i32, vp, vp]),
         "abcore_batch_plan": (i32, [P(u32), P(u32), i32, P(i32), P(i32), P(i32)]),
+        "abcore_serve_start": (i32, [vp, i64, i32, i32]),
+        "abcore_submit": (i32, [vp, abcore_edge_update, u32, u32, P(ctypes.c_uint64)]),
+        "abcore_poll": (i32, [vp, ctypes.c_uint64, P(i32), P(u32), P(ctypes.c_uint64)]),
+        "abcore_serve_stop": (i32, [vp, P(i64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -245,6 +249,60 @@ def abcore_batch_plan(alphas, betas):
     states = ctypes.c_int32()
     _check(load().abcore_batch_plan(a, b, q, parent, order, ctypes.byref(states)))
     return list(parent)[:q], list(order)[:q], int(states.value)
+
+
+def abcore_serve_start(g: Graph, max_inflight: int = 0, device_slots: int = 0,
+                       window: int = 0):
+    """Starts the serving engine of the handle (0 = library defaults)."""
+    _check(load().abcore_serve_start(g.handle, int(max_inflight), int(device_slots),
+                                     int(window)))
+
+
+def abcore_submit(g: Graph, u: int, v: int, op: int, alpha: int, beta: int) -> int:
+    """Admits one request; returns its ticket.  AbcoreError EBUSY when the
+    admission limit is reached."""
+    t = ctypes.c_uint64()
+    _check(load().abcore_submit(g.handle, abcore_edge_update(int(u), int(v), int(op)),
+                                int(alpha), int(beta), ctypes.byref(t)))
+    return int(t.value)
+
+
+def abcore_try_submit(g: Graph, u: int, v: int, op: int, alpha: int, beta: int):
+    """Like abcore_submit, but None instead of an EBUSY error."""
+    t = ctypes.c_uint64()
+    st = load().abcore_submit(g.handle, abcore_edge_update(int(u), int(v), int(op)),
+                              int(alpha), int(beta), ctypes.byref(t))
+    if st == 6:
+        return None
+    _check(st)
+    return int(t.value)
+
+
+def abcore_poll(g: Graph, ticket: int):
+    """None while the request runs; else a dict with status ("OK", "EEXIST",
+    "ENOENT", ...), answer, bits and t_done_ns (time.monotonic_ns clock)."""
+    ans = ctypes.c_int32()
+    bits = ctypes.c_uint32()
+    t = ctypes.c_uint64()
+    st = load().abcore_poll(g.handle, int(ticket), ctypes.byref(ans), ctypes.byref(bits),
+                            ctypes.byref(t))
+    if st == 7:
+        return None
+    if st not in (0, 4, 5):
+        _check(st)
+    return {"status": STATUS[st], "answer": bool(ans.value), "bits": int(bits.value),
+            "t_done_ns": int(t.value)}
+
+
+def abcore_serve_stop(g: Graph) -> dict:
+    """Drains and stops the engine; returns its counters."""
+    c = (ctypes.c_int64 * 3)()
+    _check(load().abcore_serve_stop(g.handle, c))
+    info_u, info_l, m = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check(load().abcore_graph_info(g.handle, ctypes.byref(info_u), ctypes.byref(info_l),
+                                    ctypes.byref(m)))
+    g.m = int(m.value)
+    return {"windows": int(c[0]), "answered": int(c[1]), "rejected": int(c[2])}
 
 
 def abcore_core_numbers(g: Graph, stream=None):

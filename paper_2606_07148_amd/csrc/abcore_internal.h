@@ -106,6 +106,8 @@ struct Delta {
   int64_t count = 0;         // pairs used
 };
 
+struct Server;  // serving engine (serve.hip)
+
 // Execution plan of a batch of queries (make_batch_plan).
 struct BatchPlan {
   std::vector<int32_t> order;   // execution order (query indices)
@@ -174,6 +176,13 @@ struct Graph {
   int persistent_grid = 0;  // co-resident workgroups of the persistent kernels
   int kcore_grid = 0;
   int async_grid = 0;       // co-resident workgroups of the asynchronous peel
+  // serving: versions of deletions (per base entry, per inserted pair) and
+  // the count of applied served updates; the engine while it runs
+  int32_t *del_ver = nullptr;
+  int32_t *pair_del_ver = nullptr;
+  int64_t pair_del_cap = 0;
+  int32_t upd_version = 0;
+  Server *server = nullptr;
   // batched queries: working-degree states (n int32 each) and the cache
   std::vector<int32_t *> slots;
   BatchCache batch;
@@ -184,6 +193,20 @@ struct Graph {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events[kKernelKinds];
   std::vector<hipEvent_t> event_pool;
   int64_t timed_launches[kKernelKinds] = {0, 0, 0, 0, 0};
+};
+
+// Serving: at most kWindowMax updates per window, hence at most kCorrMax
+// degree corrections for one query's view.
+constexpr int kWindowMax = 64;
+constexpr int kCorrMax = 2 * kWindowMax;
+
+// Outcome of one served update (update_window_kernel).
+struct WindowRecord {
+  int32_t status;       // 0, -ABCORE_EEXIST or -ABCORE_ENOENT
+  int32_t version;      // version of the graph after it (valid updates)
+  int32_t pairs_after;  // inserted pairs allocated after it
+  int32_t label_u, label_v;  // component labels of the endpoints before the window
+  int32_t pad[3];
 };
 
 // Peel flavours.
@@ -205,6 +228,15 @@ struct PeelArgs {
   const int32_t *piece_row;
   const int64_t *piece_start;
   const int32_t *piece_first;
+  // Versioned view (served queries, whose updates are applied while older
+  // queries still peel): a tombstoned entry at position p is still an edge of
+  // this query iff del_ver[p] > ver; inserted pair j exists iff
+  // j < pair_limit and it is live or pair_del_ver[j] > ver.  del_ver ==
+  // nullptr: the current graph.
+  const int32_t *del_ver;
+  const int32_t *pair_del_ver;
+  int32_t ver;
+  int32_t pair_limit;
   int32_t nU;
   int32_t thrU, thrL;
 };
@@ -216,6 +248,10 @@ PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL);
 // keep_abort: leave the abort flag as it is (several computations in one
 // sequence report a spin-limit abort of any of them)
 hipError_t launch_init_state(Graph &g, hipStream_t s, bool keep_abort = false);
+// The same for another working set (queue of g.qcap per sub-queue, state,
+// partial sums) than the handle's own.
+hipError_t launch_init_workspace(Graph &g, int32_t *queue, PeelState *state, int64_t *part,
+                                 hipStream_t s, bool keep_abort = false);
 hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, bool want_bits,
                            hipStream_t s);
 hipError_t launch_scan_nested(Graph &g, int32_t pU, int32_t pL, int32_t thrU, int32_t thrL,
@@ -224,6 +260,11 @@ hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s
 hipError_t launch_pull_fixup(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s);
 hipError_t launch_scan_component_of(Graph &g, int32_t thrU, int32_t thrL, int32_t x,
                                     int32_t y, hipStream_t s);
+hipError_t launch_scan_component_view(Graph &g, const PeelArgs &a, int32_t x, int32_t y,
+                                      const int32_t *corr_x, const int32_t *corr_d, int ncorr,
+                                      hipStream_t s);
+hipError_t launch_peel_async_args(Graph &g, PeelKind kind, const PeelArgs &a, int grid,
+                                  hipStream_t s);
 hipError_t launch_peel_rounds(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
                               int rounds, hipStream_t s);
 hipError_t launch_peel_persistent(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
@@ -242,6 +283,11 @@ hipError_t launch_kcore_steps(Graph &g, int steps, hipStream_t s);
 hipError_t launch_cc(Graph &g, int32_t only_label, hipStream_t s);
 hipError_t query_persistent_grids(Graph &g);
 abcore_status build_pieces(Graph &g, hipStream_t s);
+hipError_t launch_answer_view(const PeelArgs &a, int32_t x, int32_t y, hipStream_t s);
+hipError_t launch_update_window(Graph &g, const int32_t *d_upd, int w, WindowRecord *d_rec,
+                                hipStream_t s);
+hipError_t launch_relabel(Graph &g, int32_t from, int32_t to, hipStream_t s);
+void set_error(const char *fmt, ...);
 
 int peel_grid(const Graph &g);
 

@@ -28,6 +28,67 @@ hipError_t launch_answer(Graph &g, int32_t x, int32_t y, int32_t thrU, int32_t t
                          hipStream_t s);
 hipError_t launch_export(Graph &g, int64_t *out_off, int32_t *out_cols, hipStream_t s);
 hipError_t prepare_pull_kernel(Graph &g);
+bool serving(const Graph &g);
+abcore_status serve_start(Graph &g, int64_t max_inflight, int32_t slots, int32_t window);
+abcore_status serve_stop(Graph &g);
+void destroy_server(Graph &g);
+abcore_status serve_submit(Graph &g, const abcore_edge_update &upd, int32_t thrU, int32_t thrL,
+                           uint64_t *ticket);
+abcore_status serve_poll(Graph &g, uint64_t ticket, int32_t *answer, uint32_t *bits,
+                         uint64_t *t_done);
+void serve_counters(const Graph &g, int64_t *out);
+
+// Storage for edges inserted after the build: the per-vertex list heads and
+// room for at least min_cap pairs (doubling), with a deletion version per
+// pair (0 for pairs present before serving, so their tombstones hold for
+// every served version).  Synchronous; moves the pair arrays.
+abcore_status grow_delta(Graph &g, int64_t min_cap, hipStream_t s) {
+  Delta &d = g.delta;
+  hipError_t e = hipSuccess;
+  if (d.head == nullptr) {
+    e = hipMalloc(&d.head, sizeof(int32_t) * std::max<int64_t>(g.n, 1));
+    if (e == hipSuccess)
+      e = hipMemsetAsync(d.head, 0xFF, sizeof(int32_t) * std::max<int64_t>(g.n, 1), s);
+    if (e != hipSuccess) {
+      if (d.head) (void)hipFree(d.head);
+      d.head = nullptr;
+      set_error("delta allocation failed: %s", hipGetErrorString(e));
+      return ABCORE_ENOMEM;
+    }
+  }
+  if (min_cap <= d.cap && min_cap <= g.pair_del_cap) return ABCORE_OK;
+  int64_t ncap = std::max<int64_t>(1024, d.cap);
+  while (ncap < min_cap) ncap *= 2;
+  int32_t *nn = nullptr, *no = nullptr, *nv = nullptr;
+  e = hipMalloc(&nn, sizeof(int32_t) * 2 * ncap);
+  if (e == hipSuccess) e = hipMalloc(&no, sizeof(int32_t) * 2 * ncap);
+  if (e == hipSuccess) e = hipMalloc(&nv, sizeof(int32_t) * ncap);
+  if (e == hipSuccess) e = hipMemsetAsync(nv, 0, sizeof(int32_t) * ncap, s);
+  if (e == hipSuccess && d.count > 0) {
+    e = hipMemcpyAsync(nn, d.next, sizeof(int32_t) * 2 * d.count, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(no, d.other, sizeof(int32_t) * 2 * d.count, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && g.pair_del_ver)
+      e = hipMemcpyAsync(nv, g.pair_del_ver, sizeof(int32_t) * d.count, hipMemcpyDeviceToDevice,
+                         s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    for (void *p : {(void *)nn, (void *)no, (void *)nv})
+      if (p) (void)hipFree(p);
+    set_error("delta growth failed: %s", hipGetErrorString(e));
+    return ABCORE_ENOMEM;
+  }
+  if (d.next) (void)hipFree(d.next);
+  if (d.other) (void)hipFree(d.other);
+  if (g.pair_del_ver) (void)hipFree(g.pair_del_ver);
+  d.next = nn;
+  d.other = no;
+  g.pair_del_ver = nv;
+  d.cap = ncap;
+  g.pair_del_cap = ncap;
+  return ABCORE_OK;
+}
 
 namespace {
 
@@ -55,6 +116,9 @@ inline int32_t clamp_thr(uint32_t t) {
 void free_graph(Graph *g) {
   if (!g) return;
   (void)hipSetDevice(g->device);
+  destroy_server(*g);
+  if (g->del_ver) (void)hipFree(g->del_ver);
+  if (g->pair_del_ver) (void)hipFree(g->pair_del_ver);
   for (auto &ev : g->events)
     for (auto &pr : ev) {
       (void)hipEventDestroy(pr.first);
@@ -223,32 +287,7 @@ abcore_status compute_components(Graph &g, hipStream_t s) {
 }
 
 abcore_status ensure_delta(Graph &g, hipStream_t s) {
-  Delta &d = g.delta;
-  if (d.head == nullptr) {
-    TRY(ensure(&d.head, g.n));
-    CHK(hipMemsetAsync(d.head, 0xFF, sizeof(int32_t) * std::max<int64_t>(g.n, 1), s));
-  }
-  if (d.count < d.cap) return ABCORE_OK;
-  const int64_t ncap = std::max<int64_t>(1024, d.cap * 2);
-  int32_t *nn = nullptr, *no = nullptr;
-  CHK(hipMalloc(&nn, sizeof(int32_t) * 2 * ncap));
-  hipError_t e = hipMalloc(&no, sizeof(int32_t) * 2 * ncap);
-  if (e != hipSuccess) {
-    (void)hipFree(nn);
-    set_error("delta growth failed: %s", hipGetErrorString(e));
-    return ABCORE_ENOMEM;
-  }
-  if (d.count > 0) {
-    CHK(hipMemcpyAsync(nn, d.next, sizeof(int32_t) * 2 * d.count, hipMemcpyDeviceToDevice, s));
-    CHK(hipMemcpyAsync(no, d.other, sizeof(int32_t) * 2 * d.count, hipMemcpyDeviceToDevice, s));
-  }
-  CHK(hipStreamSynchronize(s));
-  if (d.next) (void)hipFree(d.next);
-  if (d.other) (void)hipFree(d.other);
-  d.next = nn;
-  d.other = no;
-  d.cap = ncap;
-  return ABCORE_OK;
+  return grow_delta(g, g.delta.count + 1, s);
 }
 
 // ------------------------------------------------------------- batches --
@@ -420,6 +459,11 @@ BatchPlan make_batch_plan(const int32_t *tu, const int32_t *tl, int32_t q) {
 
 using namespace abc;
 
+static abcore_status busy_error(const char *fn) {
+  set_error("%s: the handle is serving (abcore_serve_stop first)", fn);
+  return ABCORE_EBUSY;
+}
+
 extern "C" {
 
 const char *abcore_last_error(void) { return g_error; }
@@ -530,6 +574,7 @@ abcore_status abcore_graph_info(abcore_graph h, int32_t *n_upper, int32_t *n_low
 abcore_status abcore_export_csr(abcore_graph h, int64_t *d_off, int32_t *d_cols,
                                 int64_t *out_entries, void *stream) {
   Graph *g = reinterpret_cast<Graph *>(h);
+  if (g && serving(*g)) return busy_error(__func__);
   if (!g) {
     set_error("abcore_export_csr: null handle");
     return ABCORE_EINVAL;
@@ -543,6 +588,7 @@ abcore_status abcore_export_csr(abcore_graph h, int64_t *d_off, int32_t *d_cols,
 
 abcore_status abcore_set_option(abcore_graph h, int32_t option, int64_t value) {
   Graph *g = reinterpret_cast<Graph *>(h);
+  if (g && serving(*g)) return busy_error(__func__);
   if (!g || value < 0) {
     set_error("abcore_set_option: null handle or negative value");
     return ABCORE_EINVAL;
@@ -609,6 +655,7 @@ abcore_status abcore_kernel_timing(abcore_graph h, int32_t kernel, double *ms,
 abcore_status abcore_core_numbers(abcore_graph h, int32_t *d_core, int32_t *max_core,
                                   void *stream) {
   Graph *g = reinterpret_cast<Graph *>(h);
+  if (g && serving(*g)) return busy_error(__func__);
   if (!g) {
     set_error("abcore_core_numbers: null handle");
     return ABCORE_EINVAL;
@@ -625,6 +672,7 @@ abcore_status abcore_core_numbers(abcore_graph h, int32_t *d_core, int32_t *max_
 
 abcore_status abcore_components(abcore_graph h, int32_t *d_comp, void *stream) {
   Graph *g = reinterpret_cast<Graph *>(h);
+  if (g && serving(*g)) return busy_error(__func__);
   if (!g) {
     set_error("abcore_components: null handle");
     return ABCORE_EINVAL;
@@ -641,6 +689,7 @@ abcore_status abcore_components(abcore_graph h, int32_t *d_comp, void *stream) {
 abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int32_t algo,
                              uint32_t *d_bitmask, abcore_stats *stats, void *stream) {
   Graph *g = reinterpret_cast<Graph *>(h);
+  if (g && serving(*g)) return busy_error(__func__);
   if (!g || (!d_bitmask && g->n > 0)) {
     set_error("abcore_compute: null handle or bitmask");
     return ABCORE_EINVAL;
@@ -752,6 +801,7 @@ abcore_status abcore_compute_batch(abcore_graph h, const uint32_t *h_alpha,
                                    const uint32_t *h_beta, int32_t q, uint32_t *d_bitmasks,
                                    void *stream) {
   Graph *g = reinterpret_cast<Graph *>(h);
+  if (g && serving(*g)) return busy_error(__func__);
   if (!g || (q > 0 && g->n > 0 && !d_bitmasks)) {
     set_error("abcore_compute_batch: null handle or bitmask array");
     return ABCORE_EINVAL;
@@ -813,6 +863,7 @@ abcore_status abcore_query(abcore_graph h, abcore_edge_update upd, uint32_t alph
                            uint32_t beta, int32_t *h_answer, uint32_t *h_endpoint_bits,
                            void *stream) {
   Graph *g = reinterpret_cast<Graph *>(h);
+  if (g && serving(*g)) return busy_error(__func__);
   if (!g || !h_answer) {
     set_error("abcore_query: null handle or answer pointer");
     return ABCORE_EINVAL;
@@ -868,6 +919,60 @@ abcore_status abcore_query(abcore_graph h, abcore_edge_update upd, uint32_t alph
   *h_answer = (bits & 3) == 3 ? 1 : 0;
   if (h_endpoint_bits) *h_endpoint_bits = (uint32_t)bits;
   return ABCORE_OK;
+}
+
+abcore_status abcore_serve_start(abcore_graph h, int64_t max_inflight, int32_t device_slots,
+                                 int32_t window) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (!g || max_inflight < 0 || device_slots < 0 || window < 0 || device_slots > 256) {
+    set_error("abcore_serve_start: null handle or bad sizes");
+    return ABCORE_EINVAL;
+  }
+  if (serving(*g)) return ABCORE_OK;
+  CHK(hipSetDevice(g->device));
+  hipStream_t s = nullptr;
+  TRY(compute_components(*g, s));
+  TRY(ensure_delta(*g, s));
+  CHK(hipStreamSynchronize(s));
+  return serve_start(*g, max_inflight > 0 ? max_inflight : 1024,
+                     device_slots > 0 ? device_slots : 8, window > 0 ? window : kWindowMax);
+}
+
+abcore_status abcore_submit(abcore_graph h, abcore_edge_update upd, uint32_t alpha,
+                            uint32_t beta, uint64_t *ticket) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (!g || !ticket) {
+    set_error("abcore_submit: null handle or ticket");
+    return ABCORE_EINVAL;
+  }
+  if (upd.u < 0 || upd.u >= g->nU || upd.v < 0 || upd.v >= g->nL ||
+      (upd.op != 1 && upd.op != -1) || alpha < 1 || beta < 1) {
+    set_error("abcore_submit: endpoint out of range, op not +1/-1, or alpha/beta 0");
+    return ABCORE_EINVAL;
+  }
+  if (!serving(*g)) TRY(abcore_serve_start(h, 0, 0, 0));
+  return serve_submit(*g, upd, clamp_thr(alpha), clamp_thr(beta), ticket);
+}
+
+abcore_status abcore_poll(abcore_graph h, uint64_t ticket, int32_t *answer,
+                          uint32_t *endpoint_bits, uint64_t *t_done_ns) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (!g) {
+    set_error("abcore_poll: null handle");
+    return ABCORE_EINVAL;
+  }
+  return serve_poll(*g, ticket, answer, endpoint_bits, t_done_ns);
+}
+
+abcore_status abcore_serve_stop(abcore_graph h, int64_t *counters) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (!g) {
+    set_error("abcore_serve_stop: null handle");
+    return ABCORE_EINVAL;
+  }
+  abcore_status st = serve_stop(*g);
+  if (counters) serve_counters(*g, counters);
+  return st;
 }
 
 }  // extern "C"

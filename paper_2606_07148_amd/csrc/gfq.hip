@@ -220,6 +220,90 @@ __global__ void update_kernel(int64_t *off, int32_t *cols, int64_t m_csr, int32_
   (void)m_csr;
 }
 
+// A window of served updates, applied in order on a single thread (the order
+// of the stream: each update is validated against the graph after the
+// previous ones).  Append-only, so that queries of earlier versions still
+// peeling see their own graph: a deleted base entry gets its deletion
+// version in del_ver before it is tombstoned, a deleted inserted pair in
+// pair_del_ver, and an insertion always takes a new pair (pairs are
+// numbered in insertion order; a query sees pairs below its limit).  Each
+// record: status (0, -EEXIST, -ENOENT), version (valid updates count up from
+// ver_base), pairs after the update, labels of the endpoints before the
+// window.
+__global__ void update_window_kernel(const int64_t *off, int32_t *cols, int32_t *deg0,
+                                     const int32_t *comp, int32_t *ins_head, int32_t *ins_next,
+                                     int32_t *ins_other, int32_t *del_ver,
+                                     int32_t *pair_del_ver, int32_t pair_base,
+                                     int32_t ver_base, int32_t nU, const int32_t *upd, int w,
+                                     WindowRecord *rec) {
+  int32_t ver = ver_base, pairs = pair_base;
+  for (int i = 0; i < w; ++i) {
+    const int32_t x = upd[3 * i], y = nU + upd[3 * i + 1], op = upd[3 * i + 2];
+    WindowRecord r;
+    r.label_u = comp[x];
+    r.label_v = comp[y];
+    int64_t jx = -1, jy = -1;
+    {
+      const int64_t a = off[x], b = off[x + 1];
+      const int64_t p = row_find(cols, a, b, y);
+      if (p < b) {
+        const int32_t c = cols[p];
+        if ((c < 0 ? ~c : c) == y) jx = p;
+      }
+    }
+    const bool csr_live = jx >= 0 && cols[jx] >= 0;
+    if (csr_live) jy = row_find(cols, off[y], off[y + 1], x);
+    int32_t ex = -1;  // live inserted half-edge of the pair in row x
+    for (int32_t e = pairs > 0 ? ins_head[x] : -1; e >= 0; e = ins_next[e])
+      if (ins_other[e] == y) {
+        ex = e;
+        break;
+      }
+    const bool present = csr_live || ex >= 0;
+    r.status = 0;
+    r.version = -1;
+    if (op > 0 && present) {
+      r.status = -(int32_t)ABCORE_EEXIST;
+    } else if (op < 0 && !present) {
+      r.status = -(int32_t)ABCORE_ENOENT;
+    } else if (op > 0) {
+      const int32_t v = ++ver;
+      const int32_t hx = 2 * pairs, hy = 2 * pairs + 1;
+      ins_other[hx] = y;
+      ins_other[hy] = x;
+      pair_del_ver[pairs] = 0x7FFFFFFF;
+      ins_next[hx] = ins_head[x];
+      ins_next[hy] = ins_head[y];
+      __threadfence();  // the pair is complete before the lists point to it
+      astore(&ins_head[x], hx);
+      astore(&ins_head[y], hy);
+      ++pairs;
+      deg0[x] += 1;
+      deg0[y] += 1;
+      r.version = v;
+    } else {
+      const int32_t v = ++ver;
+      if (csr_live) {
+        del_ver[jx] = v;
+        del_ver[jy] = v;
+        __threadfence();  // the version is visible before the tombstone
+        astore(&cols[jx], ~y);
+        astore(&cols[jy], ~x);
+      } else {
+        pair_del_ver[ex >> 1] = v;
+        __threadfence();
+        astore(&ins_other[ex], ~y);
+        astore(&ins_other[ex ^ 1], ~x);
+      }
+      deg0[x] -= 1;
+      deg0[y] -= 1;
+      r.version = v;
+    }
+    r.pairs_after = pairs;
+    rec[i] = r;
+  }
+}
+
 // Membership of the two endpoints after the scoped peel.
 __global__ void answer_kernel(const int32_t *deg, int32_t x, int32_t y, int32_t thrU,
                               int32_t thrL, PeelState *st) {
@@ -294,6 +378,20 @@ hipError_t launch_update(Graph &g, int32_t u, int32_t v, int32_t op, int64_t slo
 hipError_t launch_answer(Graph &g, int32_t x, int32_t y, int32_t thrU, int32_t thrL,
                          hipStream_t s) {
   answer_kernel<<<1, 1, 0, s>>>(g.deg, x, y, thrU, thrL, g.state);
+  return hipGetLastError();
+}
+
+hipError_t launch_answer_view(const PeelArgs &a, int32_t x, int32_t y, hipStream_t s) {
+  answer_kernel<<<1, 1, 0, s>>>(a.deg, x, y, a.thrU, a.thrL, a.st);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_window(Graph &g, const int32_t *d_upd, int w, WindowRecord *d_rec,
+                                hipStream_t s) {
+  update_window_kernel<<<1, 1, 0, s>>>(g.off, g.cols, g.deg0, g.comp, g.delta.head,
+                                       g.delta.next, g.delta.other, g.del_ver, g.pair_del_ver,
+                                       (int32_t)g.delta.count, g.upd_version, g.nU, d_upd, w,
+                                       d_rec);
   return hipGetLastError();
 }
 

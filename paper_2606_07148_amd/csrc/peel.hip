@@ -57,15 +57,20 @@ __global__ void queue_reset_kernel(int32_t *queue, int64_t qcap, const PeelState
   }
 }
 
-hipError_t launch_init_state(Graph &g, hipStream_t s, bool keep_abort) {
+hipError_t launch_init_workspace(Graph &g, int32_t *queue, PeelState *state, int64_t *part,
+                                  hipStream_t s, bool keep_abort) {
   static_assert(sizeof(PeelState) % 4 == 0, "state must be whole words");
   static_assert(offsetof(PeelState, abort_flag) % 4 == 0, "abort flag must be a word");
-  queue_reset_kernel<<<g.cu_count, 256, 0, s>>>(g.queue, g.qcap, g.state);
+  queue_reset_kernel<<<g.cu_count, 256, 0, s>>>(queue, g.qcap, state);
   const int keep = keep_abort ? (int)(offsetof(PeelState, abort_flag) / 4) : -1;
-  init_state_kernel<<<8, 256, 0, s>>>(reinterpret_cast<int32_t *>(g.state),
-                                      (int)(sizeof(PeelState) / 4), g.part,
+  init_state_kernel<<<8, 256, 0, s>>>(reinterpret_cast<int32_t *>(state),
+                                      (int)(sizeof(PeelState) / 4), part,
                                       kMaxBlocks * kPartFields, keep);
   return hipGetLastError();
+}
+
+hipError_t launch_init_state(Graph &g, hipStream_t s, bool keep_abort) {
+  return launch_init_workspace(g, g.queue, g.state, g.part, s, keep_abort);
 }
 
 int peel_grid(const Graph &g) {
@@ -99,6 +104,10 @@ PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL) {
   a.piece_row = g.piece_row;
   a.piece_start = g.piece_start;
   a.piece_first = g.piece_first;
+  a.del_ver = nullptr;
+  a.pair_del_ver = nullptr;
+  a.ver = 0x7FFFFFFF;
+  a.pair_limit = 0x7FFFFFFF;
   a.nU = g.nU;
   a.thrU = thrU;
   a.thrL = thrL;
@@ -323,11 +332,34 @@ hipError_t launch_scan_nested(Graph &g, int32_t pU, int32_t pL, int32_t thrU, in
 // other components keep stale degrees and are never reached by the peel.
 // The labels are read on the device from the endpoints x and y, after the
 // component maintenance of the update has run on the same stream.
+// Served queries pass degree corrections (corr_x[i] gains corr_d[i]): the
+// updates applied after the query's own, undone for its view.  They sit in
+// an LDS hash table probed per scanned vertex.
+constexpr int kCorrHash = 256;  // > 2 * kCorrMax, power of two
+
 __global__ __launch_bounds__(kScanBlock) void scan_component_kernel(
     PeelArgs a, const int32_t *__restrict__ deg0, const int32_t *__restrict__ comp, int64_t n,
-    int32_t vx, int32_t vy) {
+    int32_t vx, int32_t vy, const int32_t *__restrict__ corr_x,
+    const int32_t *__restrict__ corr_d, int ncorr) {
   __shared__ ScanCollector col;
+  __shared__ int32_t h_key[kCorrHash];
+  __shared__ int32_t h_val[kCorrHash];
   if (threadIdx.x == 0) col.count = 0;
+  for (int i = threadIdx.x; i < kCorrHash; i += blockDim.x) h_key[i] = -1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < ncorr; ++i) {
+      const int32_t key = corr_x[i];
+      uint32_t hsl = ((uint32_t)key * 2654435761u) >> 24;
+      while (h_key[hsl & (kCorrHash - 1)] != -1 && h_key[hsl & (kCorrHash - 1)] != key) ++hsl;
+      hsl &= kCorrHash - 1;
+      if (h_key[hsl] == -1) {
+        h_key[hsl] = key;
+        h_val[hsl] = 0;
+      }
+      h_val[hsl] += corr_d[i];
+    }
+  }
   __syncthreads();
   const int32_t c1 = comp[vx], c2 = comp[vy];
   const int sub = blockIdx.x % kSub;
@@ -349,7 +381,20 @@ __global__ __launch_bounds__(kScanBlock) void scan_component_kernel(
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (x0 + j < n && (cc[j] == c1 || cc[j] == c2)) {
-          const int32_t d = deg0[x0 + j];
+          int32_t d = deg0[x0 + j];
+          if (ncorr > 0) {
+            const int32_t key = (int32_t)(x0 + j);
+            uint32_t hsl = ((uint32_t)key * 2654435761u) >> 24;
+            while (true) {
+              const int32_t k = h_key[hsl & (kCorrHash - 1)];
+              if (k == key) {
+                d += h_val[hsl & (kCorrHash - 1)];
+                break;
+              }
+              if (k == -1) break;
+              ++hsl;
+            }
+          }
           a.deg[x0 + j] = d;
           if (d < ((x0 + j) < a.nU ? a.thrU : a.thrL)) items[cnt++] = (int32_t)(x0 + j);
         }
@@ -364,7 +409,17 @@ __global__ __launch_bounds__(kScanBlock) void scan_component_kernel(
 hipError_t launch_scan_component_of(Graph &g, int32_t thrU, int32_t thrL, int32_t x, int32_t y,
                                     hipStream_t s) {
   PeelArgs a = make_args(g, thrU, thrL);
-  scan_component_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, g.deg0, g.comp, g.n, x, y);
+  scan_component_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, g.deg0, g.comp, g.n, x, y,
+                                                            nullptr, nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_component_view(Graph &g, const PeelArgs &a, int32_t x, int32_t y,
+                                      const int32_t *corr_x, const int32_t *corr_d, int ncorr,
+                                      hipStream_t s) {
+  if (ncorr < 0 || ncorr > kCorrMax) return hipErrorInvalidValue;
+  scan_component_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, g.deg0, g.comp, g.n, x, y,
+                                                            corr_x, corr_d, ncorr);
   return hipGetLastError();
 }
 
@@ -462,6 +517,9 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
       int j;
       const int64_t pos = bw.locate(k < bw.total ? k : bw.total - 1, j);
       w[u] = k < bw.total ? a.cols[pos] : -1;
+      // an entry deleted after this query's version is still its edge
+      if (a.del_ver != nullptr && k < bw.total && w[u] < 0 && ld_agent(&a.del_ver[pos]) > a.ver)
+        w[u] = ~w[u];
     }
     int32_t t[kUnroll], dw[kUnroll];
 #pragma unroll
@@ -492,8 +550,22 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
       bool push = false;
       int32_t w = -1;
       if (e >= 0) {
-        w = a.ins_other[e];
-        e = a.ins_next[e];
+        if (a.del_ver == nullptr) {
+          w = a.ins_other[e];
+          e = a.ins_next[e];
+        } else {
+          // pairs at or past the limit were inserted after this query's
+          // version, possibly while it runs: read coherently and skip them
+          const int pair = e >> 1;
+          if (pair >= a.pair_limit) {
+            w = -1;
+            e = ld_agent(&a.ins_next[e]);
+          } else {
+            w = a.ins_other[e];
+            if (w < 0 && ld_agent(&a.pair_del_ver[pair]) > a.ver) w = ~w;
+            e = a.ins_next[e];
+          }
+        }
         entries += 1;
         push = peel_visit<KIND>(a, w, level);
         if (KIND == kKCore && push) st_agent(&a.core[w], level);
@@ -747,15 +819,21 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
   add_part(a.part, kPartEntries, entries, &s_acc);
 }
 
-hipError_t launch_peel_async(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
-                             hipStream_t s) {
-  PeelArgs a = make_args(g, thrU, thrL);
-  const int grid = std::max(1, std::min(peel_grid(g), g.async_grid));
+hipError_t launch_peel_async_args(Graph &g, PeelKind kind, const PeelArgs &a, int grid,
+                                  hipStream_t s) {
+  (void)g;
+  grid = std::max(1, grid);
   if (kind == kGCC)
     peel_async_kernel<kGCC><<<grid, kPeelBlock, 0, s>>>(a);
   else
     peel_async_kernel<kGCCPlus><<<grid, kPeelBlock, 0, s>>>(a);
   return hipGetLastError();
+}
+
+hipError_t launch_peel_async(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
+                             hipStream_t s) {
+  PeelArgs a = make_args(g, thrU, thrL);
+  return launch_peel_async_args(g, kind, a, std::min(peel_grid(g), g.async_grid), s);
 }
 
 // ------------------------------------------------------ pull first round --

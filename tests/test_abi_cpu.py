@@ -38,3 +38,8 @@ def test_null_handle_and_bad_arguments_rejected(lib):
     assert lib.abcore_core_numbers(None, None, None, None) == EINVAL
     assert lib.abcore_components(None, None, None) == EINVAL
     assert lib.abcore_graph_info(None, None, None, None) == EINVAL
+    t = ctypes.c_uint64()
+    assert lib.abcore_serve_start(None, 0, 0, 0) == EINVAL
+    assert lib.abcore_submit(None, upd, 1, 1, ctypes.byref(t)) == EINVAL
+    assert lib.abcore_poll(None, 0, None, None, None) == EINVAL
+    assert lib.abcore_serve_stop(None, None) == EINVAL
