@@ -128,6 +128,138 @@ def bench_batch(args, pkg, torch, np, bigraph_gen) -> dict:
     }
 
 
+def _pct(values, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(values, np.float64), q)) if len(values) else None
+
+
+def _drive(pkg, g, ups, lo, hi, sched_ns=None):
+    """Submits requests lo..hi-1 of the stream in order (at their scheduled
+    steady-clock times when given, else as fast as admission allows) and
+    polls them; returns (results in order, submit times, wall seconds)."""
+    n = hi - lo
+    res = [None] * n
+    t_sub = [0] * n
+    waiting = []
+    i = 0
+    t0 = time.monotonic_ns()
+    while i < n or waiting:
+        if i < n and (sched_ns is None or time.monotonic_ns() >= sched_ns[i]):
+            k = lo + i
+            t = pkg.abcore_try_submit(g, ups["u"][k], ups["v"][k], ups["op"][k],
+                                      ups["alpha"][k], ups["beta"][k])
+            if t is not None:
+                t_sub[i] = time.monotonic_ns()
+                waiting.append((i, t))
+                i += 1
+                continue
+        still = []
+        for j, t in waiting:
+            r = pkg.abcore_poll(g, t)
+            if r is None:
+                still.append((j, t))
+            else:
+                res[j] = r
+        waiting = still
+    return res, t_sub, (time.monotonic_ns() - t0) / 1e9
+
+
+def bench_serve(args, pkg, torch, np, bigraph_gen) -> dict:
+    """Serving on-the-fly queries: Chung-Lu |U|=20M |L|=10M m=500M gamma=2.1
+    cap 50k; a stream of edge updates (70% insertions of new edges, 30%
+    deletions of present ones), each asking (alpha,beta)-membership with
+    alpha, beta log-uniform in [2,64].  Sequential abcore_query (one at a
+    time) against the serving loop, closed loop (as fast as admitted) and
+    open loop (Poisson arrivals at fractions of the closed-loop rate);
+    latency = completion - scheduled arrival.  Every served answer is
+    compared with the sequential answer of the same request."""
+    spec = bigraph_gen.CONFIGS[5]
+    nU, nL = spec["n_upper"], spec["n_lower"]
+    t0 = time.perf_counter()
+    eu, ev = bigraph_gen.make_graph(spec)
+    ups = bigraph_gen.update_stream(spec, eu, ev, args.serve_requests, spec["seed"] + 1000)
+    print(f"# serving graph and stream generated in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    handles = []
+    for _ in range(2):
+        deu = torch.from_numpy(eu).cuda()
+        dev = torch.from_numpy(ev).cuda()
+        handles.append(pkg.abcore_build_csr(nU, nL, deu, dev))
+        del deu, dev
+    del eu, ev
+    torch.cuda.empty_cache()
+    g_seq, g_srv = handles
+    pkg.abcore_components(g_seq)
+    total = len(ups["u"])
+    # sequential: one abcore_query at a time
+    seq = []
+    t_seq = []
+    for k in range(total):
+        t1 = time.perf_counter()
+        try:
+            a, b = pkg.abcore_query(g_seq, ups["u"][k], ups["v"][k], ups["op"][k],
+                                    ups["alpha"][k], ups["beta"][k])
+            seq.append(("OK", a, b))
+        except pkg.AbcoreError as e:
+            seq.append((e.name, None, None))
+        t_seq.append(time.perf_counter() - t1)
+    seq_qps = total / sum(t_seq)
+    pkg.abcore_serve_start(g_srv, args.serve_inflight, args.serve_slots, 0)
+    phases = []
+    served = []
+    # closed loop: the first part of the stream as fast as admission allows
+    n_closed = total // 3
+    res, t_sub, wall = _drive(pkg, g_srv, ups, 0, n_closed)
+    lat = [(r["t_done_ns"] - s) / 1e6 for r, s in zip(res, t_sub)]
+    closed_qps = n_closed / wall
+    phases.append({"mode": "closed", "requests": n_closed, "queries_per_s": closed_qps,
+                   "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99)})
+    served += res
+    # open loop at fractions of the closed-loop rate: Poisson arrivals
+    lo = n_closed
+    fracs = [0.25, 0.5, 0.8, 0.95]
+    per = (total - n_closed) // len(fracs)
+    for f in fracs:
+        hi = lo + per
+        lam = f * closed_qps
+        gaps = np.asarray(ups["gap"][lo:hi], np.float64) / lam
+        start = time.monotonic_ns() + 1_000_000
+        sched = (start + np.cumsum(gaps) * 1e9).astype(np.int64).tolist()
+        res, t_sub, wall = _drive(pkg, g_srv, ups, lo, hi, sched)
+        lat = [(r["t_done_ns"] - s) / 1e6 for r, s in zip(res, sched)]
+        phases.append({"mode": "open", "rate_fraction": f, "offered_per_s": lam,
+                       "requests": hi - lo, "queries_per_s": (hi - lo) / wall,
+                       "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99)})
+        served += res
+        lo = hi
+    counters = pkg.abcore_serve_stop(g_srv)
+    n_cmp = len(served)
+    mismatch = 0
+    for r, w in zip(served, seq[:n_cmp]):
+        if r["status"] != w[0] or (w[0] == "OK" and (r["answer"], r["bits"]) != (w[1], w[2])):
+            mismatch += 1
+    for h in handles:
+        h.destroy()
+    return {
+        "workload": "chung-lu |U|=20,000,000 |L|=10,000,000 m=500,000,000 gamma=2.1/2.1 "
+                    "cap=50,000; update stream 70% insertions / 30% deletions, "
+                    "(alpha,beta) log-uniform in [2,64] (seed 1005), prefix of "
+                    f"{total} requests",
+        "requests": total,
+        "sequential_queries_per_s": seq_qps,
+        "sequential_p50_ms": _pct([t * 1e3 for t in t_seq], 50),
+        "sequential_p99_ms": _pct([t * 1e3 for t in t_seq], 99),
+        "served_closed_loop_queries_per_s": closed_qps,
+        "speedup_vs_sequential": closed_qps / seq_qps,
+        "phases": phases,
+        "device_slots": args.serve_slots,
+        "max_inflight": args.serve_inflight,
+        "windows": counters["windows"],
+        "answers_equal_sequential": mismatch == 0,
+        "mismatches": mismatch,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +273,10 @@ def main() -> int:
                     help="skip GCC+ and its core-number preprocessing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-query section")
     ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-inflight", type=int, default=64)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device copy of MIB MiB (hardware-counter scale)")
     args = ap.parse_args()
@@ -303,6 +439,10 @@ def main() -> int:
     if not args.no_batch:
         batch = bench_batch(args, pkg, torch, np, bigraph_gen)
 
+    serve = None
+    if not args.no_serve:
+        serve = bench_serve(args, pkg, torch, np, bigraph_gen)
+
     result = {
         "metric": "edges peeled/sec",
         "value": value,
@@ -345,6 +485,7 @@ def main() -> int:
         "input_edges_per_s": ref.m / (ms_per_step / 1e3),
         "gcc_plus": gcc_plus,
         "batch": batch,
+        "serve": serve,
         "build_s": build_s,
     }
     if not args.no_cpu_baseline:
@@ -357,7 +498,8 @@ def main() -> int:
         }
     print(json.dumps(result), flush=True)
     g.destroy()
-    ok = parity and plus_parity and (batch is None or batch["parity_vs_sequential"])
+    ok = (parity and plus_parity and (batch is None or batch["parity_vs_sequential"])
+          and (serve is None or serve["answers_equal_sequential"]))
     return 0 if ok else 1
 
 

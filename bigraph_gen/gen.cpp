@@ -20,6 +20,8 @@
 #include <cstring>
 #include <vector>
 #include <unordered_map>
+#include <unordered_set>
+#include <parallel/algorithm>
 #include <omp.h>
 
 namespace {
@@ -296,14 +298,18 @@ int64_t bg_update_stream(int32_t nU, int32_t nL, int64_t m, const int32_t* eu,
   // the tables depend only on the graph parameters, so inserts follow the
   // graph's own degree weights
   if (!make_tables(nU, nL, m, gU, gL, cap, graph_seed, t)) return -1;
+  // present: the current edge keys (deletions draw a uniform position and
+  // swap the last key into it).  Membership: the sorted base keys, minus the
+  // deleted base keys, plus the inserted keys still present.
   std::vector<uint64_t> present(m);
-  std::unordered_map<uint64_t, int64_t> where;
-  where.reserve((size_t)(m + count) * 2);
-  for (int64_t i = 0; i < m; ++i) {
-    uint64_t k = (uint64_t)eu[i] * (uint64_t)nL + (uint64_t)ev[i];
-    present[i] = k;
-    where.emplace(k, i);
-  }
+  for (int64_t i = 0; i < m; ++i) present[i] = (uint64_t)eu[i] * (uint64_t)nL + (uint64_t)ev[i];
+  std::vector<uint64_t> base(present);
+  __gnu_parallel::sort(base.begin(), base.end());
+  std::unordered_set<uint64_t> base_deleted, inserted;
+  auto is_present = [&](uint64_t k) {
+    if (inserted.count(k)) return true;
+    return std::binary_search(base.begin(), base.end(), k) && !base_deleted.count(k);
+  };
   const uint64_t key = stream_key(seed, TAG_UPDATES);
   const uint64_t akey = stream_key(seed, TAG_ARRIVALS);
   const double la = std::log((double)qlo), lb = std::log((double)qhi + 1.0);
@@ -320,18 +326,16 @@ int64_t bg_update_stream(int32_t nU, int32_t nL, int64_t m, const int32_t* eu,
         ctr += 4;
         k = (uint64_t)u * (uint64_t)nL + (uint64_t)v;
         if (++guard > 1000000) return -5;
-      } while (where.count(k));
-      where.emplace(k, (int64_t)present.size());
+      } while (is_present(k));
+      inserted.insert(k);
       present.push_back(k);
       out_u[j] = u; out_v[j] = v; out_op[j] = 1;
     } else {
       int64_t pos = (int64_t)bounded(draw(key, ctr++), (uint64_t)present.size());
       uint64_t k = present[pos];
-      uint64_t last = present.back();
-      present[pos] = last;
-      where[last] = pos;
+      present[pos] = present.back();
       present.pop_back();
-      where.erase(k);
+      if (!inserted.erase(k)) base_deleted.insert(k);
       out_u[j] = (int32_t)(k / (uint64_t)nL);
       out_v[j] = (int32_t)(k % (uint64_t)nL);
       out_op[j] = -1;
