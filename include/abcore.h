@@ -230,13 +230,16 @@ abcore_status abcore_serve_stop(abcore_graph g, int64_t *counters);
  *                          around every launch (or batch of launches) of the
  *                          GCC kernels; read with abcore_kernel_timing.
  *   ABCORE_OPT_PULL      : first GCC round in pull form: 0 = decided on the
- *                          device from the scan frontier, 1 = never, 2 = always. */
+ *                          device from the scan frontier, 1 = never, 2 = always.
+ *   ABCORE_OPT_CLAIM     : queue slots a wave of the asynchronous peel takes
+ *                          at a time, 1..64 (0 = 16). */
 enum {
   ABCORE_OPT_PEEL_MODE = 1,
   ABCORE_OPT_GRID = 2,
   ABCORE_OPT_ROUNDS_PER_SYNC = 3,
   ABCORE_OPT_TIMING = 4,
-  ABCORE_OPT_PULL = 5
+  ABCORE_OPT_PULL = 5,
+  ABCORE_OPT_CLAIM = 6
 };
 abcore_status abcore_set_option(abcore_graph g, int32_t option, int64_t value);
 

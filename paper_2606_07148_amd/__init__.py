@@ -24,6 +24,7 @@ ABCORE_OPT_GRID = 2
 ABCORE_OPT_ROUNDS_PER_SYNC = 3
 ABCORE_OPT_TIMING = 4
 ABCORE_OPT_PULL = 5
+ABCORE_OPT_CLAIM = 6
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOENT", 5: "EEXIST",
           6: "EBUSY", 7: "EAGAIN"}

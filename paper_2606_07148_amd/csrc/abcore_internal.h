@@ -35,6 +35,10 @@ constexpr int kSub = 16;
 constexpr int kPad = 16;      // int32 words per 64-byte line
 constexpr int kGroups = 16;   // grid-barrier / last-workgroup groups
 constexpr int kMaxBlocks = 4096;
+// Queue slots an asynchronous-peel wave claims at a time.  Fewer than 64
+// spreads a small frontier over more waves (the batch's entries are still
+// spread over all 64 lanes).
+constexpr int kDefaultClaim = 16;
 
 // GCC+ class encoding in the working degree array (Sec. IV-B, Lemma 1):
 // certain members are never decremented, certain non-members never counted.
@@ -173,6 +177,7 @@ struct Graph {
   int pull_mode = 0;        // 0 = auto, 1 = never, 2 = always
   int grid = 0;             // 0 = derived from the device
   int rounds_per_sync = 16;
+  int claim = kDefaultClaim;  // slots a wave of the asynchronous peel claims
   int persistent_grid = 0;  // co-resident workgroups of the persistent kernels
   int kcore_grid = 0;
   int async_grid = 0;       // co-resident workgroups of the asynchronous peel
@@ -237,6 +242,7 @@ struct PeelArgs {
   const int32_t *pair_del_ver;
   int32_t ver;
   int32_t pair_limit;
+  int32_t claim;  // asynchronous peel: slots per claim, 1..64
   int32_t nU;
   int32_t thrU, thrL;
 };

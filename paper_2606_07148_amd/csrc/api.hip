@@ -617,6 +617,13 @@ abcore_status abcore_set_option(abcore_graph h, int32_t option, int64_t value) {
       }
       g->pull_mode = (int)value;
       return ABCORE_OK;
+    case ABCORE_OPT_CLAIM:
+      if (value > kWave) {
+        set_error("abcore_set_option: claim %lld above %d", (long long)value, kWave);
+        return ABCORE_EINVAL;
+      }
+      g->claim = value == 0 ? kDefaultClaim : (int)value;
+      return ABCORE_OK;
     default:
       set_error("abcore_set_option: unknown option %d", option);
       return ABCORE_EINVAL;

@@ -108,6 +108,7 @@ PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL) {
   a.pair_del_ver = nullptr;
   a.ver = 0x7FFFFFFF;
   a.pair_limit = 0x7FFFFFFF;
+  a.claim = g.claim;
   a.nU = g.nU;
   a.thrU = thrU;
   a.thrL = thrL;
@@ -494,7 +495,10 @@ __device__ __forceinline__ bool peel_visit(const PeelArgs &a, int32_t w, int32_t
 // Steps of 64 entries whose loads a wave issues together: each step is a
 // chain of dependent accesses (entry, degree, atomic), so independent steps
 // are interleaved to keep several in flight per wave.
-constexpr int kUnroll = 4;
+#ifndef ABC_UNROLL
+#define ABC_UNROLL 4
+#endif
+constexpr int kUnroll = ABC_UNROLL;
 
 // Removes up to 64 queue items (vertices or pieces of split rows; -1 marks
 // an empty lane).
@@ -702,6 +706,18 @@ __device__ __forceinline__ bool quiescent(PeelState *st) {
 // least a few microseconds, so this is seconds: far beyond any legitimate
 // wait of a peel).
 constexpr uint32_t kAsyncSpinLimit = 1u << 21;
+#ifndef ABC_QMASK
+#define ABC_QMASK 3
+#endif
+#ifndef ABC_BACKOFF
+#define ABC_BACKOFF 16
+#endif
+#ifndef ABC_SLEEP
+#define ABC_SLEEP 4
+#endif
+#ifndef ABC_STEAL_EVERY
+#define ABC_STEAL_EVERY 1
+#endif
 
 // Removes one batch of up to 64 items and, last in first out, everything
 // the batch removes while it fits the wave's local buffer (local
@@ -729,13 +745,13 @@ __device__ __forceinline__ void async_batch(const PeelArgs &a, int32_t item, int
 
 // Claims up to 64 appended, unclaimed slots of sub-queue v (none past its
 // tail); returns the count claimed, base in *base.  Wave-uniform.
-__device__ __forceinline__ int steal_claim(PeelState *st, int v, int *base) {
+__device__ __forceinline__ int steal_claim(PeelState *st, int v, int max_take, int *base) {
   int b = 0, c = 0;
   if (lane_id() == 0) {
     const int h = ld_agent(&st->head[v][0]);
     const int t = ld_agent(&st->tail[v][0]);
     if (h < t) {
-      const int want = min(t - h, kWave);
+      const int want = min(t - h, max_take);
       if (atomicCAS(&st->head[v][0], h, h + want) == h) {
         b = h;
         c = want;
@@ -757,14 +773,15 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
   int64_t entries = 0;
   uint32_t idle = 0, victim = 0;
   bool finished = false;
+  const int claim = a.claim;
   while (!finished) {
     int base = 0;
-    if (lane_id() == 0) base = atomicAdd(head, kWave);
+    if (lane_id() == 0) base = atomicAdd(head, claim);
     base = __shfl(base, 0, kWave);
     const int64_t slot = (int64_t)base + lane_id();
     // slots past the capacity are never written and never read: such a lane
     // stays pending, so its wave ends through the termination test
-    bool pending = true;
+    bool pending = lane_id() < claim;
     while (__ballot(pending)) {
       int32_t item = kEmpty;
       if (pending && slot < a.qcap) item = ld_agent(&lq.q[slot]);
@@ -779,8 +796,10 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
       // nothing in the own slots: steal from another sub-queue (one victim
       // per poll, in rotation)
       victim = victim % (kSub - 1) + 1;
-      int sbase;
-      const int taken = steal_claim(a.st, (j + (int)victim) % kSub, &sbase);
+      int sbase = 0;
+      const int taken = (idle % ABC_STEAL_EVERY) == 0
+                            ? steal_claim(a.st, (j + (int)victim) % kSub, claim, &sbase)
+                            : 0;
       if (taken > 0) {
         const int32_t *vq = a.queue + (int64_t)((j + (int)victim) % kSub) * a.qcap;
         // the slots are reserved by appenders that are running: wait for
@@ -804,7 +823,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
       // the producers' atomics), test for termination every fourth poll,
       // and give up after the spin limit (an abort, reported)
       ++idle;
-      if ((idle & 3) == 0 && (quiescent(a.st) || ld_agent(&a.st->abort_flag))) {
+      if ((idle & ABC_QMASK) == 0 && (quiescent(a.st) || ld_agent(&a.st->abort_flag))) {
         finished = true;
         break;
       }
@@ -813,7 +832,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
         finished = true;
         break;
       }
-      for (uint32_t k = 0; k < min(idle, 16u); ++k) __builtin_amdgcn_s_sleep(4);
+      for (uint32_t k = 0; k < min(idle, (uint32_t)ABC_BACKOFF); ++k) __builtin_amdgcn_s_sleep(ABC_SLEEP);
     }
   }
   add_part(a.part, kPartEntries, entries, &s_acc);
@@ -849,9 +868,23 @@ hipError_t launch_peel_async(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL
 // kernel queues the split rows that end below their threshold.  Chosen on
 // the device from the scan's frontier degree sum.
 
+// Rows of at most kLightRow entries are counted thread per row (up to
+// kLightRow independent loads in flight per lane); longer rows of at most
+// kPiece entries and the pieces of split rows are counted by 16-lane groups,
+// each group four chunks of up to 64 entries at a time (16 loads per lane in
+// flight, each load 64 contiguous bytes per group).
+constexpr int kLightRow = 16;
+
+struct ChunkDesc {
+  int64_t s;      // first entry
+  int32_t d;      // entries
+  int32_t owner;  // lane that receives the count
+};
+
 struct PullShared {
   int32_t lq[kPullWaves][kPullLocalQueue];
   int32_t cnt[kPullWaves][kWave];
+  ChunkDesc desc[kPullWaves][kWave];
   int s_cnt[kPullWaves + 1];
   int decide;
   int64_t acc;
@@ -861,29 +894,65 @@ __device__ __forceinline__ uint32_t test_bit(const uint32_t *w, int64_t base_wor
   return (w[(v >> 5) - base_word] >> (v & 31)) & 1u;
 }
 
-// Counts, for every lane's row range [s, s+d), the entries whose neighbour
-// has its bit set (LDS-staged or global bitmap); result in cnt[lane].
-__device__ __forceinline__ void pull_count(const PeelArgs &a, const uint32_t *lk, int64_t lk_base,
-                                           int64_t s, int d, int32_t *cnt, int64_t &entries) {
-  cnt[lane_id()] = 0;
+// Neighbours with their bit set in the row [s, s+d), d <= kLightRow (deleted
+// entries are negative and never count).
+__device__ __forceinline__ int count_row_thread(const PeelArgs &a, const uint32_t *lk,
+                                                int64_t lk_base, int64_t s, int d) {
+  int32_t w[kLightRow];
+#pragma unroll
+  for (int j = 0; j < kLightRow; ++j) w[j] = j < d ? a.cols[s + j] : -1;
+  int c = 0;
+#pragma unroll
+  for (int j = 0; j < kLightRow; ++j) c += w[j] >= 0 ? (int)test_bit(lk, lk_base, w[j]) : 0;
+  return c;
+}
+
+// Counts, for every lane with pred, the neighbours with their bit set in its
+// chunk [s, s+d) (d <= 64); the count lands in cnt[lane].  Whole wave.
+__device__ __forceinline__ void count_chunks(const PeelArgs &a, const uint32_t *lk,
+                                             int64_t lk_base, bool pred, int64_t s, int d,
+                                             ChunkDesc *desc, int32_t *cnt) {
+  const uint64_t m = __ballot(pred);
+  const int total = __popcll(m);
+  if (total == 0) return;
+  if (pred) {
+    ChunkDesc &cd = desc[__popcll(m & lanemask_lt())];
+    cd.s = s;
+    cd.d = d;
+    cd.owner = lane_id();
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  BatchWalk bw;
-  bw.init(s, d);
-  entries += d;
-  for (int base = 0; base < bw.total; base += kUnroll * kWave) {
-    int32_t w[kUnroll];
-    int jj[kUnroll];
+  const int grp = lane_id() >> 4, l = lane_id() & 15;
+  for (int base = 0; base < total; base += 16) {
+    int64_t cs[4];
+    int cdn[4], own[4];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int k = base + u * kWave + lane_id();
-      const int64_t pos = bw.locate(k < bw.total ? k : bw.total - 1, jj[u]);
-      w[u] = k < bw.total ? a.cols[pos] : -1;
+    for (int r = 0; r < 4; ++r) {
+      const int i = base + grp * 4 + r;
+      const bool ok = i < total;
+      cs[r] = ok ? desc[i].s : 0;
+      cdn[r] = ok ? desc[i].d : 0;
+      own[r] = ok ? desc[i].owner : -1;
     }
+    int32_t w[4][4];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int k = base + u * kWave + lane_id();
-      const bool ok = w[u] >= 0 && test_bit(lk, lk_base, w[u]);
-      segmented_count(cnt, jj[u], k < bw.total, ok, min(kWave, bw.total - base - u * kWave));
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = l + 16 * j;
+        w[r][j] = k < cdn[r] ? a.cols[cs[r] + k] : -1;
+      }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int c = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) c += w[r][j] >= 0 ? (int)test_bit(lk, lk_base, w[r][j]) : 0;
+      c += __shfl_xor(c, 8, 16);
+      c += __shfl_xor(c, 4, 16);
+      c += __shfl_xor(c, 2, 16);
+      c += __shfl_xor(c, 1, 16);
+      if (l == 0 && own[r] >= 0) cnt[own[r]] = c;
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -924,6 +993,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
   if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(&a.st->pulled, 1);
   LocalQueue lq = make_lq(sh.lq[wave_in_block()], kPullLocalQueue, a);
   int32_t *cnt = sh.cnt[wave_in_block()];
+  ChunkDesc *desc = sh.desc[wave_in_block()];
   int64_t entries = 0;
   const int waves = blockDim.x / kWave;
   const int gw = blockIdx.x * waves + wave_in_block();
@@ -945,24 +1015,27 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
       lk = s_bits;
       lk_base = w0;
     }
-    // rows of at most kPiece entries
+    // rows of at most kPiece entries, 64 consecutive vertices per wave
     for (int64_t b = lo + (int64_t)gw * kWave; b < hi; b += (int64_t)nw * kWave) {
       const int64_t xi = b + lane_id();
-      const bool valid = xi < hi;
-      const int32_t x = valid ? (int32_t)xi : -1;
-      int64_t s = 0, e = 0;
-      uint32_t word = 0;
-      if (valid) {
-        word = gbits[xi >> 5];
+      const int32_t x = xi < hi ? (int32_t)xi : -1;
+      int64_t s = 0;
+      int d = 0;
+      bool alive = false;
+      if (x >= 0) {
+        alive = (gbits[xi >> 5] >> (xi & 31)) & 1u;
         s = a.off[x];
-        e = a.off[x + 1];
+        d = (int)(a.off[x + 1] - s);
+        alive = alive && d <= kPiece;  // split rows are counted by their pieces
       }
-      const bool light = valid && e - s <= kPiece;
-      const bool alive = light && ((word >> (xi & 31)) & 1u);
-      pull_count(a, lk, lk_base, s, alive ? (int)(e - s) : 0, cnt, entries);
+      int c = 0;
+      if (alive && d <= kLightRow) c = count_row_thread(a, lk, lk_base, s, d);
+      const bool grouped = alive && d > kLightRow;
+      count_chunks(a, lk, lk_base, grouped, s, d, desc, cnt);
+      if (grouped) c = cnt[lane_id()];
       bool push = false;
       if (alive) {
-        int32_t c = cnt[lane_id()];
+        entries += d;
         if (a.ins_head != nullptr) c += delta_alive(a, gbits, x, entries);
         a.deg[x] = c;
         push = c < (x < a.nU ? a.thrU : a.thrL);
@@ -970,31 +1043,45 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
       lq.push(push, x);
       __builtin_amdgcn_wave_barrier();
     }
-    // pieces of longer rows
+    // pieces of longer rows: per-piece counts summed per row inside the
+    // wave (a row's pieces are consecutive), one atomic per row and wave
     for (int64_t b = plo + (int64_t)gw * kWave; b < phi; b += (int64_t)nw * kWave) {
       const int64_t pi = b + lane_id();
       int32_t row = -1;
       int64_t s = 0;
       int d = 0;
-      bool first = false;
+      bool first = false, alive = false;
       if (pi < phi) {
         row = a.piece_row[pi];
         s = a.piece_start[pi];
         const int64_t rs = a.off[row], re = a.off[row + 1];
-        const bool alive = (gbits[row >> 5] >> (row & 31)) & 1u;
-        d = alive ? (int)(min(s + kPiece, re) - s) : 0;
-        first = alive && s == rs;
-        if (!alive) row = -1;
+        alive = (gbits[row >> 5] >> (row & 31)) & 1u;
+        d = (int)(min(s + kPiece, re) - s);
+        first = s == rs;
       }
-      pull_count(a, lk, lk_base, s, d, cnt, entries);
-      if (row >= 0) {
-        int32_t c = cnt[lane_id()];
+      count_chunks(a, lk, lk_base, alive, s, d, desc, cnt);
+      int c = 0;
+      if (alive) {
+        entries += d;
+        c = cnt[lane_id()];
         if (first) {
           if (a.ins_head != nullptr) c += delta_alive(a, gbits, row, entries);
           c -= deg0[row];  // the scan wrote deg[row] = deg0[row]
         }
-        if (c != 0) atomicAdd(&a.deg[row], c);
       }
+      // segmented sum over lanes of equal rows (dead rows contribute 0)
+      const int32_t key = alive ? row : -1;
+      const int incl = wave_incl_scan(c);
+      const int32_t prev_key = __shfl_up(key, 1, kWave);
+      const int32_t next_key = __shfl_down(key, 1, kWave);
+      const bool head = lane_id() == 0 || prev_key != key;
+      const bool tail = lane_id() == kWave - 1 || next_key != key;
+      const uint64_t heads = __ballot(head);
+      const uint64_t le = lane_id() == kWave - 1 ? ~0ull : ((1ull << (lane_id() + 1)) - 1);
+      const int start = 63 - __builtin_clzll(heads & le);
+      const int before = __shfl(incl, start > 0 ? start - 1 : 0, kWave);
+      const int total = incl - (start > 0 ? before : 0);
+      if (tail && key >= 0 && total != 0) atomicAdd(&a.deg[key], total);
       __builtin_amdgcn_wave_barrier();
     }
   }

@@ -275,6 +275,10 @@ def test_gfq_stream_matches_recomputation():
     assert np.array_equal(pkg.abcore_components(g).cpu().numpy(), oracle.components(ref))
     for algo in (pkg.ABCORE_GCC, pkg.ABCORE_GCC_PLUS):
         _check_core(g, ref, 2, 3, algo, "after-stream", tombstones=True)
+    for pull in (1, 2, 0):  # pull form over tombstones and inserted edges too
+        pkg.abcore_set_option(g, pkg.ABCORE_OPT_PULL, pull)
+        for ab in [(2, 3), (3, 2), (1, 1), (4, 4)]:
+            _check_core(g, ref, *ab, pkg.ABCORE_GCC, f"after-stream pull{pull}", tombstones=True)
     core, _ = pkg.abcore_core_numbers(g)
     assert np.array_equal(core.cpu().numpy(), oracle.core_numbers(ref))
     g.destroy()
