@@ -232,7 +232,7 @@ abcore_status abcore_serve_stop(abcore_graph g, int64_t *counters);
  *   ABCORE_OPT_PULL      : first GCC round in pull form: 0 = decided on the
  *                          device from the scan frontier, 1 = never, 2 = always.
  *   ABCORE_OPT_CLAIM     : queue slots a wave of the asynchronous peel takes
- *                          at a time, 1..64 (0 = 16). */
+ *                          at a time, 1..64 (0 = 32). */
 enum {
   ABCORE_OPT_PEEL_MODE = 1,
   ABCORE_OPT_GRID = 2,
@@ -242,6 +242,19 @@ enum {
   ABCORE_OPT_CLAIM = 6
 };
 abcore_status abcore_set_option(abcore_graph g, int32_t option, int64_t value);
+
+/* Autotuner of the peel's work mapping for this graph: times the query
+ * (alpha, beta) with algorithm algo (3 runs after a warm run, median) for
+ * every pair of asynchronous-peel grid size (1/2, 3/4, 1, 3/2, 2, 3
+ * workgroups of 8 waves per compute unit, within the co-resident capacity)
+ * and claim size (64, 32, 16 queue slots per wave), then sets ABCORE_OPT_GRID
+ * and ABCORE_OPT_CLAIM to the fastest.  out_grid, out_claim, out_ms
+ * (nullable): the choice and its time in milliseconds.  Results of every
+ * computation stay exact whatever the choice.  Synchronous.
+ * Errors: EINVAL, ENOMEM, EDEVICE, EBUSY (serving). */
+abcore_status abcore_autotune(abcore_graph g, uint32_t alpha, uint32_t beta, int32_t algo,
+                              int32_t *out_grid, int32_t *out_claim, double *out_ms,
+                              void *stream);
 
 /* Kernel kinds timed while ABCORE_OPT_TIMING is on: the push peel
  * (Algorithm 1, peel phase), the pull-form first round, the scan phase, the

@@ -83,6 +83,7 @@ def load():
         "abcore_submit": (i32, [vp, abcore_edge_update, u32, u32, P(ctypes.c_uint64)]),
         "abcore_poll": (i32, [vp, ctypes.c_uint64, P(i32), P(u32), P(ctypes.c_uint64)]),
         "abcore_serve_stop": (i32, [vp, P(i64)]),
+        "abcore_autotune": (i32, [vp, u32, u32, i32, P(i32), P(i32), P(ctypes.c_double), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -250,6 +251,15 @@ def abcore_batch_plan(alphas, betas):
     states = ctypes.c_int32()
     _check(load().abcore_batch_plan(a, b, q, parent, order, ctypes.byref(states)))
     return list(parent)[:q], list(order)[:q], int(states.value)
+
+
+def abcore_autotune(g: Graph, alpha: int, beta: int, algo: int = ABCORE_GCC, stream=None):
+    """Picks and sets the asynchronous-peel grid and claim size for this
+    graph; returns (grid, claim, best ms)."""
+    gr, cl, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(load().abcore_autotune(g.handle, int(alpha), int(beta), int(algo), ctypes.byref(gr),
+                                  ctypes.byref(cl), ctypes.byref(ms), _stream(stream)))
+    return int(gr.value), int(cl.value), float(ms.value)
 
 
 def abcore_serve_start(g: Graph, max_inflight: int = 0, device_slots: int = 0,

@@ -38,7 +38,7 @@ constexpr int kMaxBlocks = 4096;
 // Queue slots an asynchronous-peel wave claims at a time.  Fewer than 64
 // spreads a small frontier over more waves (the batch's entries are still
 // spread over all 64 lanes).
-constexpr int kDefaultClaim = 16;
+constexpr int kDefaultClaim = 32;
 
 // GCC+ class encoding in the working degree array (Sec. IV-B, Lemma 1):
 // certain members are never decremented, certain non-members never counted.
@@ -296,5 +296,7 @@ hipError_t launch_relabel(Graph &g, int32_t from, int32_t to, hipStream_t s);
 void set_error(const char *fmt, ...);
 
 int peel_grid(const Graph &g);
+int wide_grid(const Graph &g);
+int async_peel_grid(const Graph &g);
 
 }  // namespace abc

@@ -982,4 +982,74 @@ abcore_status abcore_serve_stop(abcore_graph h, int64_t *counters) {
   return st;
 }
 
+abcore_status abcore_autotune(abcore_graph h, uint32_t alpha, uint32_t beta, int32_t algo,
+                              int32_t *out_grid, int32_t *out_claim, double *out_ms,
+                              void *stream) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (g && serving(*g)) return busy_error(__func__);
+  if (!g || alpha < 1 || beta < 1 || (algo != ABCORE_GCC && algo != ABCORE_GCC_PLUS)) {
+    set_error("abcore_autotune: null handle, threshold 0 or unknown algorithm");
+    return ABCORE_EINVAL;
+  }
+  CHK(hipSetDevice(g->device));
+  hipStream_t s = as_stream(stream);
+  const int64_t words = std::max<int64_t>(1, (g->n + 31) / 32);
+  uint32_t *bits = nullptr;
+  CHK(hipMalloc(&bits, sizeof(uint32_t) * words));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  const int saved_grid = g->grid, saved_claim = g->claim;
+  const bool saved_timing = g->timing;
+  g->timing = false;
+  abcore_status st = he == hipSuccess ? ABCORE_OK : ABCORE_EDEVICE;
+  const int cu = g->cu_count;
+  const int grids[] = {cu / 2, (3 * cu) / 4, cu, (3 * cu) / 2, 2 * cu, 3 * cu};
+  const int claims[] = {64, 32, 16};
+  int best_grid = saved_grid, best_claim = saved_claim;
+  double best = 1e30;
+  for (int gi = 0; gi < 6 && st == ABCORE_OK; ++gi) {
+    if (grids[gi] < 1 || (g->async_grid > 0 && grids[gi] > g->async_grid)) continue;
+    for (int ci = 0; ci < 3 && st == ABCORE_OK; ++ci) {
+      g->grid = grids[gi];
+      g->claim = claims[ci];
+      st = abcore_compute(h, alpha, beta, algo, bits, nullptr, stream);  // warm
+      double t[3];
+      for (int r = 0; r < 3 && st == ABCORE_OK; ++r) {
+        if (hipEventRecord(e0, s) != hipSuccess) st = ABCORE_EDEVICE;
+        if (st == ABCORE_OK) st = abcore_compute(h, alpha, beta, algo, bits, nullptr, stream);
+        float ms = 0.f;
+        if (st == ABCORE_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                                hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          st = ABCORE_EDEVICE;
+        t[r] = ms;
+      }
+      if (st != ABCORE_OK) break;
+      std::sort(t, t + 3);
+      if (t[1] < best) {
+        best = t[1];
+        best_grid = grids[gi];
+        best_claim = claims[ci];
+      }
+    }
+  }
+  g->timing = saved_timing;
+  if (st == ABCORE_OK && read_state(*g, s) != ABCORE_OK) st = ABCORE_EDEVICE;
+  if (st == ABCORE_OK) {
+    g->grid = best_grid;
+    g->claim = best_claim;
+    if (out_grid) *out_grid = best_grid;
+    if (out_claim) *out_claim = best_claim;
+    if (out_ms) *out_ms = best;
+  } else {
+    g->grid = saved_grid;
+    g->claim = saved_claim;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(bits);
+  return st;
+}
+
 }  // extern "C"

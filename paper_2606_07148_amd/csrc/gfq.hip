@@ -356,7 +356,7 @@ int small_grid(const Graph &g, int64_t items) {
 hipError_t launch_cc(Graph &g, int32_t label, hipStream_t s) {
   const int32_t *head = g.delta.count > 0 ? g.delta.head : nullptr;
   uf_init_kernel<<<small_grid(g, g.n), 256, 0, s>>>(g.parent, g.comp, label, g.n);
-  uf_union_kernel<<<peel_grid(g), kBlock, 0, s>>>(g.off, g.cols, g.comp, label, g.parent, head,
+  uf_union_kernel<<<wide_grid(g), kBlock, 0, s>>>(g.off, g.cols, g.comp, label, g.parent, head,
                                                   g.delta.next, g.delta.other, g.nU);
   uf_label_kernel<<<small_grid(g, g.n), 256, 0, s>>>(g.parent, g.comp, label, g.n);
   return hipGetLastError();

@@ -75,7 +75,19 @@ hipError_t launch_init_state(Graph &g, hipStream_t s, bool keep_abort) {
 
 int peel_grid(const Graph &g) {
   if (g.grid > 0) return std::min(g.grid, kMaxBlocks);
+  return wide_grid(g);
+}
+
+int wide_grid(const Graph &g) {
   return std::min(g.cu_count * 4, kMaxBlocks);  // 4 workgroups of 8 waves per CU
+}
+
+// Asynchronous peel: one workgroup of 8 waves per CU unless set (measured
+// best or near-best on power-law graphs of 20M-200M edges; abcore_autotune
+// picks per graph).
+int async_peel_grid(const Graph &g) {
+  const int want = g.grid > 0 ? g.grid : g.cu_count;
+  return std::max(1, std::min(want, g.async_grid > 0 ? g.async_grid : want));
 }
 
 static int flat_grid(const Graph &g, int64_t items, int per_block) {
@@ -852,7 +864,7 @@ hipError_t launch_peel_async_args(Graph &g, PeelKind kind, const PeelArgs &a, in
 hipError_t launch_peel_async(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
                              hipStream_t s) {
   PeelArgs a = make_args(g, thrU, thrL);
-  return launch_peel_async_args(g, kind, a, std::min(peel_grid(g), g.async_grid), s);
+  return launch_peel_async_args(g, kind, a, async_peel_grid(g), s);
 }
 
 // ------------------------------------------------------ pull first round --
@@ -1352,7 +1364,7 @@ __global__ __launch_bounds__(kPeelBlock) void restricted_init_kernel(PeelArgs a,
 hipError_t launch_restricted_init(Graph &g, int32_t thrU, int32_t thrL, int32_t dl,
                                   hipStream_t s) {
   PeelArgs a = make_args(g, thrU, thrL);
-  restricted_init_kernel<<<peel_grid(g), kPeelBlock, 0, s>>>(a, dl);
+  restricted_init_kernel<<<wide_grid(g), kPeelBlock, 0, s>>>(a, dl);
   return hipGetLastError();
 }
 

@@ -237,7 +237,7 @@ bool run_window(Graph &g, Server &S, const std::vector<Request> &win) {
   g.version += 1;
   SCHK(hipEventRecord(S.applied, S.main));
   S.windows += 1;
-  const int grid = std::max(1, g.async_grid / std::max<int>(1, (int)S.slots.size()));
+  const int grid = std::max(1, async_peel_grid(g) / std::max<int>(1, (int)S.slots.size()));
   size_t next_slot = 0;
   for (int i = 0; i < w; ++i) {
     const WindowRecord &r = S.h_rec[i];

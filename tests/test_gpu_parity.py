@@ -156,6 +156,19 @@ def test_async_small_grids(grid):
     g.destroy()
 
 
+def test_autotune_keeps_results_exact():
+    nU, nL, m = 40_000, 25_000, 500_000
+    eu, ev = bigraph_gen.chung_lu(nU, nL, m, 2.1, 2.1, 6000, 91)
+    g, ref = _make(nU, nL, eu, ev)
+    say("autotune")
+    for algo in (pkg.ABCORE_GCC, pkg.ABCORE_GCC_PLUS):
+        grid, claim, ms = pkg.abcore_autotune(g, 6, 9, algo)
+        assert grid >= 1 and claim in (16, 32, 64) and ms > 0
+        for ab in [(6, 9), (2, 2), (12, 4)]:
+            _check_core(g, ref, *ab, algo, f"tuned grid{grid} claim{claim}")
+    g.destroy()
+
+
 # ----------------------------------------------------------- core numbers --
 
 
