@@ -268,7 +268,15 @@ hipError_t launch_scan_component_of(Graph &g, int32_t thrU, int32_t thrL, int32_
                                     int32_t y, hipStream_t s);
 hipError_t launch_scan_component_view(Graph &g, const PeelArgs &a, int32_t x, int32_t y,
                                       const int32_t *corr_x, const int32_t *corr_d, int ncorr,
-                                      hipStream_t s);
+                                      uint32_t *bits, hipStream_t s);
+// Pull-form first round for any working set: bits are the scan's survivors;
+// corr_x/corr_d (ncorr entries, nullable) the degree corrections the scan
+// applied (served views).
+hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
+                                  const int32_t *corr_x, const int32_t *corr_d, int ncorr,
+                                  hipStream_t s);
+hipError_t launch_pull_fixup_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
+                                  hipStream_t s);
 hipError_t launch_peel_async_args(Graph &g, PeelKind kind, const PeelArgs &a, int grid,
                                   hipStream_t s);
 hipError_t launch_peel_rounds(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,

@@ -919,6 +919,10 @@ abcore_status abcore_query(abcore_graph h, abcore_edge_update upd, uint32_t alph
   int64_t launches = 0;
   CHK(launch_init_state(*g, s));
   CHK(launch_scan_component_of(*g, thrU, thrL, x, y, s));
+  if (g->pull_mode != 1) {  // the first round in pull form when the frontier is heavy
+    CHK(launch_pull_round(*g, thrU, thrL, s));
+    CHK(launch_pull_fixup(*g, thrU, thrL, s));
+  }
   TRY(run_peel(*g, kGCC, thrU, thrL, s, &launches));
   CHK(launch_answer(*g, x, y, thrU, thrL, s));
   TRY(read_state(*g, s));

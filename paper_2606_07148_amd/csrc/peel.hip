@@ -127,6 +127,15 @@ PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL) {
   return a;
 }
 
+// Versioned view of an entry w loaded from position pos: an entry deleted
+// after the query's version is still its edge.  Applied after a group of
+// loads so that the loads stay in flight together (a.del_ver is uniform).
+__device__ __forceinline__ int32_t view_col(const PeelArgs &a, bool valid, int64_t pos,
+                                            int32_t w) {
+  if (valid && w < 0 && ld_agent(&a.del_ver[pos]) > a.ver) return ~w;
+  return w;
+}
+
 // Queue items: a vertex id x >= 0 (its whole row), or -(p + 2) for piece p
 // of a split row (kPiece entries of it).
 __device__ __forceinline__ int32_t piece_item(int32_t p) { return -(p + 2); }
@@ -353,8 +362,9 @@ constexpr int kCorrHash = 256;  // > 2 * kCorrMax, power of two
 __global__ __launch_bounds__(kScanBlock) void scan_component_kernel(
     PeelArgs a, const int32_t *__restrict__ deg0, const int32_t *__restrict__ comp, int64_t n,
     int32_t vx, int32_t vy, const int32_t *__restrict__ corr_x,
-    const int32_t *__restrict__ corr_d, int ncorr) {
+    const int32_t *__restrict__ corr_d, int ncorr, uint32_t *__restrict__ bits) {
   __shared__ ScanCollector col;
+  __shared__ int64_t s_acc;
   __shared__ int32_t h_key[kCorrHash];
   __shared__ int32_t h_val[kCorrHash];
   if (threadIdx.x == 0) col.count = 0;
@@ -377,10 +387,12 @@ __global__ __launch_bounds__(kScanBlock) void scan_component_kernel(
   const int32_t c1 = comp[vx], c2 = comp[vy];
   const int sub = blockIdx.x % kSub;
   int32_t *q = a.queue + (int64_t)sub * a.qcap;
+  int64_t f0 = 0, f0deg = 0;
   for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < n;
        cb += (int64_t)gridDim.x * kScanChunk) {
     for (int t = 0; t < kScanChunk; t += kScanBlock * 4) {
       const int64_t x0 = cb + t + (int64_t)threadIdx.x * 4;
+      uint32_t alive = 0;
       int32_t cc[4] = {-1, -1, -1, -1};
       if (x0 + 3 < n) {
         int4 c = *reinterpret_cast<const int4 *>(comp + x0);
@@ -409,30 +421,47 @@ __global__ __launch_bounds__(kScanBlock) void scan_component_kernel(
             }
           }
           a.deg[x0 + j] = d;
-          if (d < ((x0 + j) < a.nU ? a.thrU : a.thrL)) items[cnt++] = (int32_t)(x0 + j);
+          if (d < ((x0 + j) < a.nU ? a.thrU : a.thrL)) {
+            items[cnt++] = (int32_t)(x0 + j);
+            f0deg += d;
+          } else {
+            alive |= 1u << j;
+          }
         }
       }
+      if (bits != nullptr) {
+        // eight consecutive threads hold the 32 vertices of one bitmap word
+        uint32_t wd = alive << (4 * (lane_id() & 7));
+        wd |= __shfl_xor(wd, 1, kWave);
+        wd |= __shfl_xor(wd, 2, kWave);
+        wd |= __shfl_xor(wd, 4, kWave);
+        if ((lane_id() & 7) == 0 && x0 < n) bits[x0 / 32] = wd;
+      }
+      f0 += cnt;
       col.append(items, cnt);
     }
     col.flush(q, &a.st->tail[sub][0]);
   }
+  add_part(a.part, kPartF0, f0, &s_acc);
+  add_part(a.part, kPartF0Deg, f0deg, &s_acc);
   if (last_block_done<false>(a.st)) start_rounds_wave(a.st);
 }
 
 hipError_t launch_scan_component_of(Graph &g, int32_t thrU, int32_t thrL, int32_t x, int32_t y,
                                     hipStream_t s) {
   PeelArgs a = make_args(g, thrU, thrL);
-  scan_component_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, g.deg0, g.comp, g.n, x, y,
-                                                            nullptr, nullptr, 0);
+  scan_component_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(
+      a, g.deg0, g.comp, g.n, x, y, nullptr, nullptr, 0,
+      g.pull_mode != 1 ? g.alive_bits : nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_scan_component_view(Graph &g, const PeelArgs &a, int32_t x, int32_t y,
                                       const int32_t *corr_x, const int32_t *corr_d, int ncorr,
-                                      hipStream_t s) {
+                                      uint32_t *bits, hipStream_t s) {
   if (ncorr < 0 || ncorr > kCorrMax) return hipErrorInvalidValue;
   scan_component_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, g.deg0, g.comp, g.n, x, y,
-                                                            corr_x, corr_d, ncorr);
+                                                            corr_x, corr_d, ncorr, bits);
   return hipGetLastError();
 }
 
@@ -527,21 +556,28 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
   entries += d;
   for (int base = 0; base < bw.total; base += kUnroll * kWave) {
     int32_t w[kUnroll];
+    int64_t p[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int k = base + u * kWave + lane_id();
       int j;
       const int64_t pos = bw.locate(k < bw.total ? k : bw.total - 1, j);
       w[u] = k < bw.total ? a.cols[pos] : -1;
-      // an entry deleted after this query's version is still its edge
-      if (a.del_ver != nullptr && k < bw.total && w[u] < 0 && ld_agent(&a.del_ver[pos]) > a.ver)
-        w[u] = ~w[u];
+      p[u] = k < bw.total ? pos : -1;
+    }
+    if (a.del_ver != nullptr) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) w[u] = view_col(a, p[u] >= 0, p[u], w[u]);
     }
     int32_t t[kUnroll], dw[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       t[u] = (KIND == kKCore) ? level + 1 : (w[u] < a.nU ? a.thrU : a.thrL);
+#ifdef ABC_NO_FILTER
+      dw[u] = w[u] >= 0 ? 0x7FFFFFFE : -1;
+#else
       dw[u] = w[u] >= 0 ? a.deg[w[u]] : -1;
+#endif
     }
     bool push[kUnroll];
 #pragma unroll
@@ -913,6 +949,10 @@ __device__ __forceinline__ int count_row_thread(const PeelArgs &a, const uint32_
   int32_t w[kLightRow];
 #pragma unroll
   for (int j = 0; j < kLightRow; ++j) w[j] = j < d ? a.cols[s + j] : -1;
+  if (a.del_ver != nullptr) {
+#pragma unroll
+    for (int j = 0; j < kLightRow; ++j) w[j] = view_col(a, j < d, s + j, w[j]);
+  }
   int c = 0;
 #pragma unroll
   for (int j = 0; j < kLightRow; ++j) c += w[j] >= 0 ? (int)test_bit(lk, lk_base, w[j]) : 0;
@@ -955,6 +995,13 @@ __device__ __forceinline__ void count_chunks(const PeelArgs &a, const uint32_t *
         const int k = l + 16 * j;
         w[r][j] = k < cdn[r] ? a.cols[cs[r] + k] : -1;
       }
+    if (a.del_ver != nullptr) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          w[r][j] = view_col(a, l + 16 * j < cdn[r], cs[r] + l + 16 * j, w[r][j]);
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       int c = 0;
@@ -971,15 +1018,30 @@ __device__ __forceinline__ void count_chunks(const PeelArgs &a, const uint32_t *
   __builtin_amdgcn_wave_barrier();
 }
 
+// Inserted neighbours of x with their bit set (versioned view as in the
+// peel: pairs from the limit on are skipped, pairs deleted after the
+// query's version still count).
 __device__ __forceinline__ int delta_alive(const PeelArgs &a, const uint32_t *gbits, int32_t x,
                                            int64_t &entries) {
   int extra = 0;
-  for (int e = a.ins_head[x]; e >= 0; e = a.ins_next[e]) {
-    const int32_t w = a.ins_other[e];
+  for (int e = a.ins_head[x]; e >= 0;) {
+    int32_t w, next;
+    if (a.del_ver == nullptr) {
+      w = a.ins_other[e];
+      next = a.ins_next[e];
+    } else if ((e >> 1) >= a.pair_limit) {
+      w = -1;
+      next = ld_agent(&a.ins_next[e]);
+    } else {
+      w = a.ins_other[e];
+      if (w < 0 && ld_agent(&a.pair_del_ver[e >> 1]) > a.ver) w = ~w;
+      next = a.ins_next[e];
+    }
     if (w >= 0) {
       ++entries;
       extra += (gbits[w >> 5] >> (w & 31)) & 1u;
     }
+    e = next;
   }
   return extra;
 }
@@ -987,7 +1049,8 @@ __device__ __forceinline__ int delta_alive(const PeelArgs &a, const uint32_t *gb
 __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     PeelArgs a, const uint32_t *__restrict__ gbits, const int32_t *__restrict__ deg0, int64_t n,
     int scan_blocks, int mode, int use_lds, int64_t total_entries, int64_t npieces,
-    int64_t npieces_upper) {
+    int64_t npieces_upper, const int32_t *__restrict__ corr_x,
+    const int32_t *__restrict__ corr_d, int ncorr) {
   extern __shared__ uint32_t s_bits[];
   __shared__ PullShared sh;
   if (wave_in_block() == 0) {
@@ -1078,7 +1141,11 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
         c = cnt[lane_id()];
         if (first) {
           if (a.ins_head != nullptr) c += delta_alive(a, gbits, row, entries);
-          c -= deg0[row];  // the scan wrote deg[row] = deg0[row]
+          // the scan wrote deg[row] = deg0[row] (plus the view's correction)
+          int32_t written = deg0[row];
+          for (int i = 0; i < ncorr; ++i)
+            if (corr_x[i] == row) written += corr_d[i];
+          c -= written;
         }
       }
       // segmented sum over lanes of equal rows (dead rows contribute 0)
@@ -1144,27 +1211,37 @@ bool pull_uses_lds(const Graph &g) {
   return (size_t)need + sizeof(PullShared) + 1024 <= g.lds_per_block;
 }
 
-hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s) {
+hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
+                                  const int32_t *corr_x, const int32_t *corr_d, int ncorr,
+                                  hipStream_t s) {
   if (g.pull_mode == 1) return hipSuccess;
-  PeelArgs a = make_args(g, thrU, thrL);
   const int64_t words_upper = g.nU > 0 ? ((int64_t)g.nU - 1) / 32 + 1 : 0;
   const int64_t words_lower = g.nL > 0 ? ((g.n - 1) >> 5) - (g.nU >> 5) + 1 : 0;
   const bool use_lds = pull_uses_lds(g);
   const size_t dyn = use_lds ? (size_t)(4 * std::max(words_upper, words_lower)) : 0;
   const int64_t total_entries = 2 * g.m;
   pull_round_kernel<<<g.cu_count, kPullBlock, dyn, s>>>(
-      a, g.alive_bits, g.deg0, g.n, scan_grid(g), g.pull_mode, use_lds ? 1 : 0, total_entries,
-      g.npieces, g.npieces_upper);
+      a, bits, g.deg0, g.n, scan_grid(g), g.pull_mode, use_lds ? 1 : 0, total_entries,
+      g.npieces, g.npieces_upper, corr_x, corr_d, ncorr);
   return hipGetLastError();
 }
 
-// Must follow launch_pull_round on the same stream (it completes that round).
-hipError_t launch_pull_fixup(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s) {
+hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s) {
+  return launch_pull_round_args(g, make_args(g, thrU, thrL), g.alive_bits, nullptr, nullptr, 0,
+                                s);
+}
+
+// Must follow the pull round on the same stream (it completes that round).
+hipError_t launch_pull_fixup_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
+                                  hipStream_t s) {
   if (g.pull_mode == 1) return hipSuccess;
-  PeelArgs a = make_args(g, thrU, thrL);
   pull_fixup_kernel<<<flat_grid(g, std::max<int64_t>(g.nheavy, 1), kPeelBlock), kPeelBlock, 0, s>>>(
-      a, g.alive_bits, g.heavy_rows, g.nheavy);
+      a, bits, g.heavy_rows, g.nheavy);
   return hipGetLastError();
+}
+
+hipError_t launch_pull_fixup(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s) {
+  return launch_pull_fixup_args(g, make_args(g, thrU, thrL), g.alive_bits, s);
 }
 
 // ----------------------------------------------------------------- pack --

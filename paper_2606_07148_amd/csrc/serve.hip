@@ -9,7 +9,7 @@
 // insertion order), so every query reads exactly its version:
 //   - degrees: the scan starts from the current degrees and undoes the later
 //     updates of its window (updates of later windows are applied only after
-//     this window's scans, ordered by events);
+//     this window's scans and pull rounds, ordered by events);
 //   - edges: the versioned view of the peel;
 //   - components: labels only merge while serving, so a query's scope is a
 //     union of components of its version (stale, unsplit labels are exact).
@@ -58,6 +58,7 @@ struct Slot {
   int32_t *queue = nullptr;
   PeelState *state = nullptr;
   int64_t *part = nullptr;
+  uint32_t *bits = nullptr;   // survivors of the scan (pull round)
   int32_t *d_corr = nullptr;  // 2 * kCorrMax: vertices, then deltas
   int32_t *h_corr = nullptr;  // pinned staging of d_corr
   int32_t *h_out = nullptr;   // pinned: aux0, aux1, pulled, abort_flag of the state
@@ -96,7 +97,7 @@ namespace {
 void free_slot(Slot &s) {
   if (s.stream) (void)hipStreamDestroy(s.stream);
   for (void *p : {(void *)s.deg, (void *)s.queue, (void *)s.state, (void *)s.part,
-                  (void *)s.d_corr})
+                  (void *)s.d_corr, (void *)s.bits})
     if (p) (void)hipFree(p);
   if (s.h_corr) (void)hipHostFree(s.h_corr);
   if (s.h_out) (void)hipHostFree(s.h_out);
@@ -130,6 +131,8 @@ hipError_t alloc_slot(Graph &g, Slot &s) {
   if (e == hipSuccess) e = hipMemset(s.state, 0, sizeof(PeelState));
   if (e == hipSuccess) e = hipMalloc(&s.part, sizeof(int64_t) * kMaxBlocks * kPartFields);
   if (e == hipSuccess) e = hipMalloc(&s.d_corr, sizeof(int32_t) * 2 * kCorrMax);
+  if (e == hipSuccess)
+    e = hipMalloc(&s.bits, sizeof(uint32_t) * std::max<int64_t>((g.n + 31) / 32, 1));
   if (e == hipSuccess) e = hipHostMalloc(&s.h_corr, sizeof(int32_t) * 2 * kCorrMax);
   if (e == hipSuccess) e = hipHostMalloc(&s.h_out, sizeof(int32_t) * 4);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&s.scanned, hipEventDisableTiming);
@@ -237,7 +240,9 @@ bool run_window(Graph &g, Server &S, const std::vector<Request> &win) {
   g.version += 1;
   SCHK(hipEventRecord(S.applied, S.main));
   S.windows += 1;
-  const int grid = std::max(1, async_peel_grid(g) / std::max<int>(1, (int)S.slots.size()));
+  // the working sets share the co-resident capacity of the peel
+  const int cap = g.async_grid > 0 ? g.async_grid : async_peel_grid(g);
+  const int grid = std::max(1, cap / std::max<int>(1, (int)S.slots.size()));
   size_t next_slot = 0;
   for (int i = 0; i < w; ++i) {
     const WindowRecord &r = S.h_rec[i];
@@ -277,7 +282,18 @@ bool run_window(Graph &g, Server &S, const std::vector<Request> &win) {
       SCHK(hipMemcpyAsync(s.d_corr, s.h_corr, sizeof(int32_t) * 2 * kCorrMax,
                           hipMemcpyHostToDevice, s.stream));
     SCHK(launch_init_workspace(g, s.queue, s.state, s.part, s.stream));
-    SCHK(launch_scan_component_view(g, a, x, y, s.d_corr, s.d_corr + kCorrMax, c, s.stream));
+    // the pull round takes every compute unit with a full-LDS workgroup and
+    // keeps served queries from overlapping: served peels push their first
+    // round unless the pull form is forced (ABCORE_OPT_PULL = 2)
+    const bool pull = g.pull_mode == 2;
+    SCHK(launch_scan_component_view(g, a, x, y, s.d_corr, s.d_corr + kCorrMax, c,
+                                    pull ? s.bits : nullptr, s.stream));
+    if (pull) {
+      SCHK(launch_pull_round_args(g, a, s.bits, s.d_corr, s.d_corr + kCorrMax, c, s.stream));
+      SCHK(launch_pull_fixup_args(g, a, s.bits, s.stream));
+    }
+    // the scan and the pull round read the current degrees: the next
+    // window's updates wait for them
     SCHK(hipEventRecord(s.scanned, s.stream));
     S.last_scans.push_back(s.scanned);
     SCHK(launch_peel_async_args(g, kGCC, a, grid, s.stream));

@@ -258,14 +258,16 @@ def test_edge_cases():
 # -------------------------------------------------------------------- GFQ --
 
 
-def test_gfq_stream_matches_recomputation():
+@pytest.mark.parametrize("pull", [0, 2, 1])
+def test_gfq_stream_matches_recomputation(pull):
     spec = dict(kind="chung_lu", n_upper=3000, n_lower=2000, m=12_000, gamma_upper=2.1,
                 gamma_lower=2.1, cap=400, seed=401)
     eu, ev = bigraph_gen.make_graph(spec)
     ups = bigraph_gen.update_stream(spec, eu, ev, 300, 1401, qlo=1, qhi=6)
     g = pkg.abcore_build_csr(spec["n_upper"], spec["n_lower"], to_dev(eu), to_dev(ev))
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_PULL, pull)
     want = oracle.gfq_stream(spec["n_upper"], spec["n_lower"], eu, ev, ups)
-    say("gfq: 300 updates")
+    say("gfq: 300 updates, pull mode", pull)
     for i in range(len(ups["u"])):
         ans, bits = pkg.abcore_query(g, ups["u"][i], ups["v"][i], ups["op"][i],
                                      ups["alpha"][i], ups["beta"][i])

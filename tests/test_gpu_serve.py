@@ -86,15 +86,19 @@ def _compare(served, want, tag):
             assert (r["answer"], r["bits"]) == (w[1], w[2]), f"{tag} request {i}: {r} vs {w}"
 
 
-@pytest.mark.parametrize("slots,window,inflight", [(8, 64, 256), (3, 5, 7), (1, 1, 1)])
-def test_served_stream_equals_alone_and_oracle(slots, window, inflight):
+@pytest.mark.parametrize("slots,window,inflight,pull",
+                         [(8, 64, 256, 0), (3, 5, 7, 0), (1, 1, 1, 0), (8, 64, 256, 2),
+                          (4, 16, 32, 1)])
+def test_served_stream_equals_alone_and_oracle(slots, window, inflight, pull):
     spec = dict(kind="chung_lu", n_upper=3000, n_lower=2000, m=12_000, gamma_upper=2.1,
                 gamma_lower=2.1, cap=400, seed=501)
     nU, nL = spec["n_upper"], spec["n_lower"]
     eu, ev = bigraph_gen.make_graph(spec)
     ups = _with_invalid(bigraph_gen.update_stream(spec, eu, ev, 400, 1501, qlo=1, qhi=6))
-    say(f"serve: {len(ups['u'])} requests, slots {slots}, window {window}, inflight {inflight}")
+    say(f"serve: {len(ups['u'])} requests, slots {slots}, window {window}, "
+        f"inflight {inflight}, pull {pull}")
     g = pkg.abcore_build_csr(nU, nL, to_dev(eu), to_dev(ev))
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_PULL, pull)
     pkg.abcore_serve_start(g, inflight, slots, window)
     served = serve_all(g, ups, inflight)
     counters = pkg.abcore_serve_stop(g)
@@ -174,8 +178,9 @@ def test_served_stream_power_law():
     nU, nL = spec["n_upper"], spec["n_lower"]
     eu, ev = bigraph_gen.make_graph(spec)
     ups = bigraph_gen.update_stream(spec, eu, ev, 240, spec["seed"] + 1000)
-    say("serve: power-law 1/100 scale, 240 requests")
+    say("serve: power-law 1/100 scale, 240 requests, pull always")
     g = pkg.abcore_build_csr(nU, nL, to_dev(eu), to_dev(ev))
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_PULL, 2)
     pkg.abcore_serve_start(g, 64, 8, 64)
     served = serve_all(g, ups, 64)
     pkg.abcore_serve_stop(g)
@@ -184,5 +189,32 @@ def test_served_stream_power_law():
     sample = {0, 1, 2, 57, 120, 239}
     want = oracle.gfq_stream(nU, nL, eu, ev, ups, check_only=sample)
     _compare([served[i] for i in sorted(sample)], [want[i] for i in sorted(sample)], "oracle")
+    g.destroy()
+    g2.destroy()
+
+
+@pytest.mark.parametrize("pull", [1, 2])
+def test_served_versions_of_vertex_zero_edges(pull):
+    """Queries in a window see edges of vertex 0 deleted later in the same
+    window (a deleted entry to vertex 0 is stored as ~0 = -1)."""
+    eu = np.array([0, 0, 1, 1, 3, 3, 4], np.int32)
+    ev = np.array([0, 1, 0, 1, 3, 4, 3], np.int32)
+    nU = nL = 6
+    cycle = [(2, 0, 1, 2, 2), (0, 0, -1, 2, 2), (0, 0, 1, 2, 2), (2, 0, -1, 1, 1),
+             (0, 1, -1, 2, 2), (0, 1, 1, 1, 2)]
+    reqs = cycle * 40
+    ups = {k: np.array([r[i] for r in reqs], np.int32)
+           for i, k in enumerate(("u", "v", "op", "alpha", "beta"))}
+    say("serve: vertex-0 versions, pull", pull)
+    g = pkg.abcore_build_csr(nU, nL, to_dev(eu), to_dev(ev))
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_PULL, pull)
+    pkg.abcore_serve_start(g, 64, 8, 64)
+    served = serve_all(g, ups, 64)
+    counters = pkg.abcore_serve_stop(g)
+    g2, alone = _sequential(nU, nL, eu, ev, ups)
+    _compare(served, alone, "alone")
+    want = oracle.gfq_stream(nU, nL, eu, ev, ups)
+    _compare(served, want, "oracle")
+    assert counters["windows"] < len(reqs)  # several requests shared windows
     g.destroy()
     g2.destroy()
