@@ -59,18 +59,58 @@ __global__ void uf_init_kernel(int32_t *parent, const int32_t *comp, int32_t lab
     if (in_scope(comp, label, x)) parent[x] = (int32_t)x;
 }
 
-// Every edge appears once in the upper rows; waves take 64 consecutive upper
-// vertices and walk their rows edge-balanced (as in the peel).
-__global__ __launch_bounds__(kBlock) void uf_union_kernel(
+// Sampling phase (the Afforest strategy of Sutton, Ben-Nun and Barak, 2018):
+// every vertex in scope first unites with the first kSampleLinks entries of
+// its row, which on skewed graphs already joins almost every vertex of the
+// largest component into one tree.
+constexpr int kSampleLinks = 2;
+
+__global__ void uf_sample_link_kernel(const int64_t *__restrict__ off,
+                                      const int32_t *__restrict__ cols, const int32_t *comp,
+                                      int32_t label, int32_t *parent, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
+    if (!in_scope(comp, label, x)) continue;
+    const int64_t s = off[x], e = off[x + 1];
+    for (int64_t j = s; j < e && j < s + kSampleLinks; ++j) {
+      const int32_t w = cols[j];
+      if (w >= 0) uf_union(parent, (int32_t)x, w);
+    }
+  }
+}
+
+__global__ void uf_compress_kernel(int32_t *parent, const int32_t *comp, int32_t label,
+                                   int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride)
+    if (in_scope(comp, label, x)) astore(&parent[x], uf_find(parent, (int32_t)x));
+}
+
+// Roots of kRootSamples evenly spaced vertices (-1 when out of scope).
+constexpr int kRootSamples = 1024;
+
+__global__ void uf_sample_roots_kernel(const int32_t *parent, const int32_t *comp, int32_t label,
+                                       int64_t n, int32_t *roots) {
+  const int i = threadIdx.x;
+  if (i >= kRootSamples) return;
+  const int64_t x = (n * i) / kRootSamples;
+  roots[i] = (x < n && in_scope(comp, label, x)) ? aload(&parent[x]) : -1;
+}
+
+// Completion: every vertex in scope outside the tree of root `big` unites
+// with all of its neighbours (both layers' rows and inserted edges).  Edges
+// with both ends in that tree need nothing: they are joined already.
+__global__ __launch_bounds__(kBlock) void uf_rest_link_kernel(
     const int64_t *__restrict__ off, const int32_t *__restrict__ cols, const int32_t *comp,
     int32_t label, int32_t *parent, const int32_t *ins_head, const int32_t *ins_next,
-    const int32_t *ins_other, int32_t nU) {
+    const int32_t *ins_other, int64_t n, int32_t big) {
   const int gw = blockIdx.x * kWavesPerBlock + wave_in_block();
   const int nw = gridDim.x * kWavesPerBlock;
-  for (int64_t b = (int64_t)gw * kWave; b < nU; b += (int64_t)nw * kWave) {
+  for (int64_t b = (int64_t)gw * kWave; b < n; b += (int64_t)nw * kWave) {
     const int64_t xi = b + lane_id();
     int32_t x = -1;
-    if (xi < nU && in_scope(comp, label, xi)) x = (int32_t)xi;
+    if (xi < n && in_scope(comp, label, xi) && (big < 0 || uf_find(parent, (int32_t)xi) != big))
+      x = (int32_t)xi;
     int64_t s = 0;
     int d = 0;
     if (x >= 0) {
@@ -353,11 +393,40 @@ int small_grid(const Graph &g, int64_t items) {
 
 // Component labels for the whole graph (label < 0) or re-labelling of the
 // vertices currently labelled `label` (deletion may split that component).
+// Synchronises the stream once (the largest tree's root is read on the
+// host); uses the partial-sum buffers as scratch (they are reset before every
+// computation).
 hipError_t launch_cc(Graph &g, int32_t label, hipStream_t s) {
+  static_assert(kRootSamples * sizeof(int32_t) <= kMaxBlocks * kPartFields * sizeof(int64_t),
+                "root samples must fit the partial-sum buffer");
   const int32_t *head = g.delta.count > 0 ? g.delta.head : nullptr;
+  int32_t *d_roots = reinterpret_cast<int32_t *>(g.part);
+  int32_t *h_roots = reinterpret_cast<int32_t *>(g.h_part);
   uf_init_kernel<<<small_grid(g, g.n), 256, 0, s>>>(g.parent, g.comp, label, g.n);
-  uf_union_kernel<<<wide_grid(g), kBlock, 0, s>>>(g.off, g.cols, g.comp, label, g.parent, head,
-                                                  g.delta.next, g.delta.other, g.nU);
+  uf_sample_link_kernel<<<small_grid(g, g.n), 256, 0, s>>>(g.off, g.cols, g.comp, label,
+                                                           g.parent, g.n);
+  uf_compress_kernel<<<small_grid(g, g.n), 256, 0, s>>>(g.parent, g.comp, label, g.n);
+  uf_sample_roots_kernel<<<1, kRootSamples, 0, s>>>(g.parent, g.comp, label, g.n, d_roots);
+  hipError_t e = hipMemcpyAsync(h_roots, d_roots, sizeof(int32_t) * kRootSamples,
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  std::vector<int32_t> r(h_roots, h_roots + kRootSamples);
+  std::sort(r.begin(), r.end());
+  int32_t big = -1;
+  int best = 0;
+  for (size_t i = 0; i < r.size();) {
+    size_t j = i;
+    while (j < r.size() && r[j] == r[i]) ++j;
+    if (r[i] >= 0 && (int)(j - i) > best) {
+      best = (int)(j - i);
+      big = r[i];
+    }
+    i = j;
+  }
+  uf_rest_link_kernel<<<wide_grid(g), kBlock, 0, s>>>(g.off, g.cols, g.comp, label, g.parent,
+                                                      head, g.delta.next, g.delta.other, g.n,
+                                                      big);
   uf_label_kernel<<<small_grid(g, g.n), 256, 0, s>>>(g.parent, g.comp, label, g.n);
   return hipGetLastError();
 }
