@@ -275,7 +275,7 @@ def main() -> int:
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--serve-requests", type=int, default=600)
-    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-slots", type=int, default=2)
     ap.add_argument("--serve-inflight", type=int, default=64)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device copy of MIB MiB (hardware-counter scale)")

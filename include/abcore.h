@@ -185,8 +185,10 @@ abcore_status abcore_query(abcore_graph g, abcore_edge_update upd, uint32_t alph
 /* Starts the engine (abcore_submit starts it with defaults if needed).
  * max_inflight: admitted-but-unfinished requests allowed (0 = 1024);
  * device_slots: concurrent device working sets, n + 16 * (2n + pieces)
- * int32 each (0 = 8, at most 256); window: most updates per window (0 = 64,
- * at most 64).  Computes the component labels if needed.  Synchronous.
+ * int32 each (0 = 2, at most 256: on graphs of hundreds of millions of
+ * edges a single query already saturates the device's random-access
+ * throughput, and two working sets measured best); window: most updates
+ * per window (0 = 64, at most 64).  Computes the component labels if needed.  Synchronous.
  * Errors: EINVAL, ENOMEM, EDEVICE. */
 abcore_status abcore_serve_start(abcore_graph g, int64_t max_inflight, int32_t device_slots,
                                  int32_t window);

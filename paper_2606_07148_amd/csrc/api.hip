@@ -946,7 +946,7 @@ abcore_status abcore_serve_start(abcore_graph h, int64_t max_inflight, int32_t d
   TRY(ensure_delta(*g, s));
   CHK(hipStreamSynchronize(s));
   return serve_start(*g, max_inflight > 0 ? max_inflight : 1024,
-                     device_slots > 0 ? device_slots : 8, window > 0 ? window : kWindowMax);
+                     device_slots > 0 ? device_slots : 2, window > 0 ? window : kWindowMax);
 }
 
 abcore_status abcore_submit(abcore_graph h, abcore_edge_update upd, uint32_t alpha,
