@@ -518,18 +518,20 @@ __device__ __forceinline__ void segmented_count(int32_t *cnt, int j, bool act, b
 
 // ----------------------------------------------------------- peel phase --
 
-// One decrement of Algorithm 1 (and Algorithm 2's filtered variant).
-// The plain load is a filter: degrees only decrease, so a stale value is
-// never below the true one, and a value below the threshold means the vertex
-// is already removed or queued -- no atomic is needed.  GCC+ certain members
-// (kDegIn) are skipped; certain non-members (kDegOut) fail the threshold test.
+// One decrement of Algorithm 1 (and Algorithm 2's filtered variant): the
+// vertex is queued iff the decrement takes its degree from the threshold to
+// below it (the unique crossing: degrees only decrease).  GCC+ first loads
+// the degree as a filter: a stale value is never below the true one, certain
+// members (kDegIn) are skipped and certain non-members (kDegOut) fail the
+// threshold test.
 template <int KIND>
 __device__ __forceinline__ bool peel_visit(const PeelArgs &a, int32_t w, int32_t level) {
   if (w < 0) return false;  // deleted edge
   const int32_t t = (KIND == kKCore) ? level + 1 : (w < a.nU ? a.thrU : a.thrL);
-  const int32_t dw = a.deg[w];
-  if (dw < t) return false;
-  if (KIND == kGCCPlus && dw == kDegIn) return false;
+  if (KIND == kGCCPlus) {
+    const int32_t dw = a.deg[w];
+    if (dw < t || dw == kDegIn) return false;
+  }
   return atomicSub(&a.deg[w], 1) == t;
 }
 
@@ -573,17 +575,19 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       t[u] = (KIND == kKCore) ? level + 1 : (w[u] < a.nU ? a.thrU : a.thrL);
-#ifdef ABC_NO_FILTER
-      dw[u] = w[u] >= 0 ? 0x7FFFFFFE : -1;
-#else
-      dw[u] = w[u] >= 0 ? a.deg[w[u]] : -1;
-#endif
+      // GCC+ loads the degree first: certain members (kDegIn) are never
+      // decremented and certain non-members fail the threshold test.  The
+      // other peels decrement unconditionally: the atomic returns the old
+      // degree, which alone decides the crossing, and a removed vertex can
+      // never cross again (its degree is already below the threshold) --
+      // one round trip instead of a load followed by an atomic
+      dw[u] = w[u] >= 0 ? (KIND == kGCCPlus ? a.deg[w[u]] : kMaxThreshold) : -1;
     }
     bool push[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      // the plain load is a filter: degrees only decrease, so a stale value
-      // is never below the true one
+      // GCC+: the plain load is a filter (degrees only decrease, so a stale
+      // value is never below the true one)
       bool live = w[u] >= 0 && dw[u] >= t[u];
       if (KIND == kGCCPlus) live = live && dw[u] != kDegIn;
       push[u] = live && atomicSub(&a.deg[w[u]], 1) == t[u];
