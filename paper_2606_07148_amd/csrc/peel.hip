@@ -544,8 +544,12 @@ __device__ __forceinline__ bool peel_visit(const PeelArgs &a, int32_t w, int32_t
 constexpr int kUnroll = ABC_UNROLL;
 
 // Removes up to 64 queue items (vertices or pieces of split rows; -1 marks
-// an empty lane).
-template <int KIND>
+// an empty lane).  LAZY (the asynchronous peel, which has no rounds): removed
+// vertices are queued as plain ids, and a split row is expanded into its
+// pieces when its item is taken -- the producer saves a dependent load per
+// removal, the hub's walk moves one hop later.  Otherwise (round peels,
+// whose round count is reported) split rows are queued as pieces at once.
+template <int KIND, bool LAZY = false>
 __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t level,
                                            LocalQueue &lq, int64_t &entries) {
   int32_t row;
@@ -553,6 +557,20 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
   int d;
   bool first;
   decode_item(a, x, row, s, d, first);
+  if (LAZY) {
+    const bool split = x >= 0 && d > kPiece;
+    if (__ballot(split)) {
+      int np = 0;
+      int32_t pf = 0;
+      if (split) {
+        pf = a.piece_first[x];
+        np = (d + kPiece - 1) / kPiece;
+        d = 0;          // walked by its pieces
+        first = false;  // the first piece walks the inserted edges
+      }
+      for (int k = 0; __ballot(k < np); ++k) lq.push(k < np, piece_item(pf + k));
+    }
+  }
   BatchWalk bw;
   bw.init(s, d);
   entries += d;
@@ -595,7 +613,10 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (KIND == kKCore && push[u]) st_agent(&a.core[w[u]], level);
-      push_removed(a, lq, push[u], w[u]);
+      if (LAZY)
+        lq.push(push[u], w[u]);
+      else
+        push_removed(a, lq, push[u], w[u]);
     }
   }
   if (a.ins_head != nullptr) {
@@ -626,7 +647,10 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
         push = peel_visit<KIND>(a, w, level);
         if (KIND == kKCore && push) st_agent(&a.core[w], level);
       }
-      push_removed(a, lq, push, w);
+      if (LAZY)
+        lq.push(push, w);
+      else
+        push_removed(a, lq, push, w);
     }
   }
 }
@@ -781,14 +805,14 @@ template <int KIND>
 __device__ __forceinline__ void async_batch(const PeelArgs &a, int32_t item, int nitems,
                                             LocalQueue &lq, int32_t *consumed,
                                             int64_t &entries) {
-  peel_batch<KIND>(a, item, 0, lq, entries);
+  peel_batch<KIND, true>(a, item, 0, lq, entries);
   while (lq.count > 0) {
     const int take = min(lq.count, kWave);
     __builtin_amdgcn_wave_barrier();
     const int32_t xi = lane_id() < take ? lq.buf[lq.count - take + lane_id()] : -1;
     __builtin_amdgcn_wave_barrier();
     lq.count -= take;
-    peel_batch<KIND>(a, xi, 0, lq, entries);
+    peel_batch<KIND, true>(a, xi, 0, lq, entries);
   }
   lq.flush();
   __builtin_amdgcn_s_waitcnt(0);
