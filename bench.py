@@ -402,6 +402,12 @@ def main() -> int:
     # fixup: split rows (more than 64 entries): row id, deg0 and deg read
     fixup_bytes = 12 * int(np.count_nonzero(deg > 64)) if pulled else 0
     kbytes = {0: push_bytes, 1: pull_bytes, 2: scan_bytes, 3: pack_bytes, 4: fixup_bytes}
+    # the asynchronous peel runs the pack and the pull round's completion
+    # itself (no separate launches): its bytes include theirs
+    if ktime[3][1] == 0:
+        kbytes[0] += pack_bytes
+    if ktime[4][1] == 0:
+        kbytes[0] += fixup_bytes
     for kind, (ms, launches) in ktime.items():
         if launches == 0:
             continue

@@ -66,6 +66,7 @@ struct PeelState {
   int32_t tail[kSub][kPad];  // append cursors
   int32_t head[kSub][kPad];  // asynchronous peel: next slot to claim
   int32_t consumed[kSub][kPad];  // asynchronous peel: slots processed
+  int32_t started[kGroups][kPad];  // asynchronous peel: workgroups past their start phase
   int32_t lo[kSub];
   int32_t hi[kSub];
   Arrival arr;
@@ -85,6 +86,9 @@ struct PeelState {
   int32_t abort_flag;   // a grid barrier exceeded its spin limit
   int32_t pad0;
   int64_t launches;     // launches that did work
+  // arrival counters of the workspace reset only (never zeroed: that kernel
+  // always completes, so they always return to zero)
+  Arrival rst;
 };
 
 // Per-workgroup partial results, one slot line per workgroup (no atomics).
@@ -243,6 +247,16 @@ struct PeelArgs {
   int32_t ver;
   int32_t pair_limit;
   int32_t claim;  // asynchronous peel: slots per claim, 1..64
+  // asynchronous peel, fused work (all nullable): split rows of a pull round
+  // to queue when below their threshold (start phase, before any workgroup
+  // may end: start_expect workgroups must have started), and the membership
+  // bitmask to write after termination
+  const int32_t *fix_rows;
+  const uint32_t *fix_bits;
+  int64_t nfix;
+  uint32_t *pack_bits;
+  int32_t start_expect;
+  int64_t n;
   int32_t nU;
   int32_t thrU, thrL;
 };
@@ -262,7 +276,14 @@ hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, bool want_bits,
                            hipStream_t s);
 hipError_t launch_scan_nested(Graph &g, int32_t pU, int32_t pL, int32_t thrU, int32_t thrL,
                               hipStream_t s);
-hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s);
+hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
+                             bool advance = false);
+// Asynchronous peel fused with the pull round's completion (fix_bits: the
+// scan's survivors, or nullptr when no pull round ran) and the bitmask pack
+// (pack_bits nullable).
+hipError_t launch_peel_async_fused(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
+                                   const uint32_t *fix_bits, uint32_t *pack_bits,
+                                   hipStream_t s);
 hipError_t launch_pull_fixup(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s);
 hipError_t launch_scan_component_of(Graph &g, int32_t thrU, int32_t thrL, int32_t x,
                                     int32_t y, hipStream_t s);
@@ -272,9 +293,12 @@ hipError_t launch_scan_component_view(Graph &g, const PeelArgs &a, int32_t x, in
 // Pull-form first round for any working set: bits are the scan's survivors;
 // corr_x/corr_d (ncorr entries, nullable) the degree corrections the scan
 // applied (served views).
+// advance: the pull round's last workgroup starts the next round itself
+// (the asynchronous peel then queues the split rows in its start phase, in
+// place of the separate completion kernel).
 hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
                                   const int32_t *corr_x, const int32_t *corr_d, int ncorr,
-                                  hipStream_t s);
+                                  bool advance, hipStream_t s);
 hipError_t launch_pull_fixup_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
                                   hipStream_t s);
 hipError_t launch_peel_async_args(Graph &g, PeelKind kind, const PeelArgs &a, int grid,

@@ -241,6 +241,35 @@ abcore_status run_peel(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, hipS
   return ABCORE_EDEVICE;
 }
 
+// After a scan: the first round in pull form (when pull is set and the
+// device decides so), the peel to completion and, when bits is given, the
+// bitmask.  In the asynchronous mode the pull round's completion (split
+// rows below their threshold) and the pack run inside the peel kernel.
+abcore_status pull_peel_pack(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, bool pull,
+                             uint32_t *bits, hipStream_t s, int64_t *launches) {
+  const bool fused = g.peel_mode == 3;
+  if (pull) {
+    CHK(timed(g, ABCORE_KERNEL_PULL, s, 1,
+              [&] { return launch_pull_round(g, thrU, thrL, s, fused); }));
+    if (!fused)
+      CHK(timed(g, ABCORE_KERNEL_FIXUP, s, 1,
+                [&] { return launch_pull_fixup(g, thrU, thrL, s); }));
+  }
+  if (fused) {
+    CHK(timed(g, ABCORE_KERNEL_PEEL, s, 1, [&] {
+      return launch_peel_async_fused(g, kind, thrU, thrL, pull ? g.alive_bits : nullptr, bits,
+                                     s);
+    }));
+    *launches += 1;
+    return ABCORE_OK;
+  }
+  TRY(run_peel(g, kind, thrU, thrL, s, launches));
+  if (bits)
+    CHK(timed(g, ABCORE_KERNEL_PACK, s, 1,
+              [&] { return launch_pack(g, thrU, thrL, bits, s); }));
+  return ABCORE_OK;
+}
+
 abcore_status compute_core(Graph &g, hipStream_t s) {
   if (g.core_valid) return ABCORE_OK;
   TRY(ensure(&g.core, g.n));
@@ -319,19 +348,15 @@ abcore_status run_batch(Graph &g, const BatchPlan &plan, const int32_t *tu, cons
     if (p < 0) {
       CHK(launch_init_state(g, s, true));
       CHK(launch_scan_gcc(g, tu[i], tl[i], pull, s));
-      if (pull) {
-        CHK(launch_pull_round(g, tu[i], tl[i], s));
-        CHK(launch_pull_fixup(g, tu[i], tl[i], s));
-      }
+      TRY(pull_peel_pack(g, kGCC, tu[i], tl[i], pull, out, s, &launches));
     } else {
       if (plan.copy[i] && g.n > 0)
         CHK(hipMemcpyAsync(g.deg, g.slots[plan.slot[p]], sizeof(int32_t) * g.n,
                            hipMemcpyDeviceToDevice, s));
       CHK(launch_init_state(g, s, true));
       CHK(launch_scan_nested(g, tu[p], tl[p], tu[i], tl[i], s));
+      TRY(pull_peel_pack(g, kGCC, tu[i], tl[i], false, out, s, &launches));
     }
-    TRY(run_peel(g, kGCC, tu[i], tl[i], s, &launches));
-    CHK(launch_pack(g, tu[i], tl[i], out, s));
   }
   return ABCORE_OK;
 }
@@ -718,15 +743,7 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
     CHK(launch_init_state(*g, s));
     CHK(timed(*g, ABCORE_KERNEL_SCAN, s, 1,
               [&] { return launch_scan_gcc(*g, thrU, thrL, pull, s); }));
-    if (pull) {
-      CHK(timed(*g, ABCORE_KERNEL_PULL, s, 1,
-                [&] { return launch_pull_round(*g, thrU, thrL, s); }));
-      CHK(timed(*g, ABCORE_KERNEL_FIXUP, s, 1,
-                [&] { return launch_pull_fixup(*g, thrU, thrL, s); }));
-    }
-    TRY(run_peel(*g, kGCC, thrU, thrL, s, &launches));
-    CHK(timed(*g, ABCORE_KERNEL_PACK, s, 1,
-              [&] { return launch_pack(*g, thrU, thrL, d_bitmask, s); }));
+    TRY(pull_peel_pack(*g, kGCC, thrU, thrL, pull, d_bitmask, s, &launches));
   } else {
     TRY(compute_core(*g, s));
     const int32_t dl = std::min(thrU, thrL), dq = std::max(thrU, thrL);
@@ -736,8 +753,7 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
     } else {
       CHK(launch_classify(*g, dl, dq, s));
       CHK(launch_restricted_init(*g, thrU, thrL, dl, s));
-      TRY(run_peel(*g, kGCCPlus, thrU, thrL, s, &launches));
-      CHK(launch_pack(*g, thrU, thrL, d_bitmask, s));
+      TRY(pull_peel_pack(*g, kGCCPlus, thrU, thrL, false, d_bitmask, s, &launches));
     }
   }
   if (stats) {
@@ -919,11 +935,8 @@ abcore_status abcore_query(abcore_graph h, abcore_edge_update upd, uint32_t alph
   int64_t launches = 0;
   CHK(launch_init_state(*g, s));
   CHK(launch_scan_component_of(*g, thrU, thrL, x, y, s));
-  if (g->pull_mode != 1) {  // the first round in pull form when the frontier is heavy
-    CHK(launch_pull_round(*g, thrU, thrL, s));
-    CHK(launch_pull_fixup(*g, thrU, thrL, s));
-  }
-  TRY(run_peel(*g, kGCC, thrU, thrL, s, &launches));
+  // the first round in pull form when the frontier is heavy
+  TRY(pull_peel_pack(*g, kGCC, thrU, thrL, g->pull_mode != 1, nullptr, s, &launches));
   CHK(launch_answer(*g, x, y, thrU, thrL, s));
   TRY(read_state(*g, s));
   const int32_t bits = g->h_state->aux0;

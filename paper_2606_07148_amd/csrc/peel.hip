@@ -33,39 +33,46 @@ constexpr int kScanChunk = 4096;  // vertices per workgroup chunk (4 per thread,
 
 // ---------------------------------------------------------------- state --
 
-__global__ void init_state_kernel(int32_t *st_words, int nwords, int64_t *part, int nparts,
-                                  int keep_word) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += gridDim.x * blockDim.x)
-    if (i != keep_word) st_words[i] = 0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nparts; i += gridDim.x * blockDim.x)
-    part[i] = 0;
-}
-
 // Queue slots not yet written hold kEmpty (the asynchronous peel waits on
 // them); the previous computation's used prefixes [0, tail) are cleared
 // before its state is reset.
 constexpr int32_t kEmpty = -1;
 
-__global__ void queue_reset_kernel(int32_t *queue, int64_t qcap, const PeelState *st) {
+// Both steps in one launch: every workgroup clears its share of the used
+// queue prefixes and of the partial sums; the last one to finish (after
+// every workgroup has read the append cursors) zeroes the state.
+__global__ void reset_workspace_kernel(int32_t *queue, int64_t qcap, PeelState *st,
+                                       int64_t *part, int nparts, int keep_word) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int j = 0; j < kSub; ++j) {
-    // clamped: the range can never leave the sub-queue whatever the state holds
     const int64_t t = min(max((int64_t)st->tail[j][0], (int64_t)0), qcap);
     int32_t *q = queue + (int64_t)j * qcap;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < t; i += stride)
-      q[i] = kEmpty;
+    for (int64_t i = tid; i < t; i += stride) q[i] = kEmpty;
   }
+  for (int64_t i = tid; i < nparts; i += stride) part[i] = 0;
+  __syncthreads();
+  if (wave_in_block() != 0) return;
+  int last = 0;
+  if (lane_id() == 0) {
+    __threadfence();
+    last = arrive_on(&st->rst) ? 1 : 0;
+  }
+  if (!__shfl(last, 0, kWave)) return;
+  __threadfence();
+  int32_t *words = reinterpret_cast<int32_t *>(st);
+  constexpr int kRstBegin = (int)(offsetof(PeelState, rst) / 4);
+  for (int i = lane_id(); i < kRstBegin; i += kWave)
+    if (i != keep_word) words[i] = 0;
 }
 
 hipError_t launch_init_workspace(Graph &g, int32_t *queue, PeelState *state, int64_t *part,
                                   hipStream_t s, bool keep_abort) {
   static_assert(sizeof(PeelState) % 4 == 0, "state must be whole words");
   static_assert(offsetof(PeelState, abort_flag) % 4 == 0, "abort flag must be a word");
-  queue_reset_kernel<<<g.cu_count, 256, 0, s>>>(queue, g.qcap, state);
   const int keep = keep_abort ? (int)(offsetof(PeelState, abort_flag) / 4) : -1;
-  init_state_kernel<<<8, 256, 0, s>>>(reinterpret_cast<int32_t *>(state),
-                                      (int)(sizeof(PeelState) / 4), part,
-                                      kMaxBlocks * kPartFields, keep);
+  reset_workspace_kernel<<<g.cu_count, 256, 0, s>>>(queue, g.qcap, state, part,
+                                                    kMaxBlocks * kPartFields, keep);
   return hipGetLastError();
 }
 
@@ -121,6 +128,12 @@ PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL) {
   a.ver = 0x7FFFFFFF;
   a.pair_limit = 0x7FFFFFFF;
   a.claim = g.claim;
+  a.fix_rows = nullptr;
+  a.fix_bits = nullptr;
+  a.nfix = 0;
+  a.pack_bits = nullptr;
+  a.start_expect = 0;
+  a.n = g.n;
   a.nU = g.nU;
   a.thrU = thrU;
   a.thrL = thrL;
@@ -765,9 +778,17 @@ hipError_t launch_peel_persistent(Graph &g, PeelKind kind, int32_t thrU, int32_t
 // never wait for a workgroup of their own sub-queue to be resident, and
 // several peels can share the device without any co-residency assumption.
 
-__device__ __forceinline__ bool quiescent(PeelState *st) {
+__device__ __forceinline__ bool quiescent(PeelState *st, int32_t start_expect) {
   const int j = lane_id();
   int32_t d = 0, t = 0;
+  if (start_expect > 0) {
+    // every workgroup has queued its start-phase items
+    const int32_t sv = j < kGroups ? ld_agent(&st->started[j][0]) : 0;
+    if (wave_sum(sv) < start_expect) return false;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  }
   if (j < kSub) d = ld_agent(&st->consumed[j][0]);
   const int dsum = wave_sum(d);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -842,7 +863,31 @@ template <int KIND>
 __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
   __shared__ int32_t s_lq[kPeelWaves][kLocalQueue];
   __shared__ int64_t s_acc;
+  __shared__ int s_cnt[kPeelWaves + 1];
   LocalQueue lq = make_lq(s_lq[wave_in_block()], kLocalQueue, a);
+  const int waves = blockDim.x / kWave;
+  const int gw = blockIdx.x * waves + wave_in_block();
+  const int nw = gridDim.x * waves;
+  if (a.start_expect > 0) {
+    // start phase: after a pull round, the split rows below their threshold
+    // (their pieces' counts are complete at the kernel boundary)
+    if (a.fix_bits != nullptr && ld_agent(&a.st->pulled) != 0) {
+      for (int64_t b = (int64_t)gw * kWave; b < a.nfix; b += (int64_t)nw * kWave) {
+        const int64_t i = b + lane_id();
+        bool push = false;
+        int32_t x = -1;
+        if (i < a.nfix) x = a.fix_rows[i];
+        if (x >= 0 && ((a.fix_bits[x >> 5] >> (x & 31)) & 1u))
+          push = a.deg[x] < (x < a.nU ? a.thrU : a.thrL);
+        lq.push(push, x);
+      }
+    }
+    block_flush(lq, s_cnt);
+    if (threadIdx.x == 0) {
+      __threadfence();  // the appended items before the start count
+      atomicAdd(&a.st->started[blockIdx.x % kGroups][0], 1);
+    }
+  }
   const int j = blockIdx.x % kSub;
   int32_t *head = &a.st->head[j][0];
   int32_t *consumed = &a.st->consumed[j][0];
@@ -899,7 +944,8 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
       // the producers' atomics), test for termination every fourth poll,
       // and give up after the spin limit (an abort, reported)
       ++idle;
-      if ((idle & ABC_QMASK) == 0 && (quiescent(a.st) || ld_agent(&a.st->abort_flag))) {
+      if ((idle & ABC_QMASK) == 0 &&
+          (quiescent(a.st, a.start_expect) || ld_agent(&a.st->abort_flag))) {
         finished = true;
         break;
       }
@@ -912,6 +958,18 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
     }
   }
   add_part(a.part, kPartEntries, entries, &s_acc);
+  if (a.pack_bits != nullptr && ld_agent(&a.st->abort_flag) == 0) {
+    // the result (Algorithm 1's V(G)): termination means every decrement
+    // is done; degrees are read at device scope (they changed by atomics)
+    const int64_t n = a.n;
+    for (int64_t b = (int64_t)gw * kWave; b < n; b += (int64_t)nw * kWave) {
+      const int64_t x = b + lane_id();
+      const bool in = x < n && ld_agent(&a.deg[x]) >= (x < a.nU ? a.thrU : a.thrL);
+      const uint64_t m = __ballot(in);
+      if (lane_id() < 2 && b + 32 * lane_id() < n)
+        a.pack_bits[(b >> 5) + lane_id()] = (uint32_t)(m >> (32 * lane_id()));
+    }
+  }
 }
 
 hipError_t launch_peel_async_args(Graph &g, PeelKind kind, const PeelArgs &a, int grid,
@@ -923,6 +981,21 @@ hipError_t launch_peel_async_args(Graph &g, PeelKind kind, const PeelArgs &a, in
   else
     peel_async_kernel<kGCCPlus><<<grid, kPeelBlock, 0, s>>>(a);
   return hipGetLastError();
+}
+
+hipError_t launch_peel_async_fused(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
+                                   const uint32_t *fix_bits, uint32_t *pack_bits,
+                                   hipStream_t s) {
+  PeelArgs a = make_args(g, thrU, thrL);
+  const int grid = async_peel_grid(g);
+  if (fix_bits != nullptr) {
+    a.fix_rows = g.heavy_rows;
+    a.fix_bits = fix_bits;
+    a.nfix = g.nheavy;
+    a.start_expect = grid;
+  }
+  a.pack_bits = pack_bits;
+  return launch_peel_async_args(g, kind, a, grid, s);
 }
 
 hipError_t launch_peel_async(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
@@ -1078,7 +1151,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     PeelArgs a, const uint32_t *__restrict__ gbits, const int32_t *__restrict__ deg0, int64_t n,
     int scan_blocks, int mode, int use_lds, int64_t total_entries, int64_t npieces,
     int64_t npieces_upper, const int32_t *__restrict__ corr_x,
-    const int32_t *__restrict__ corr_d, int ncorr) {
+    const int32_t *__restrict__ corr_d, int ncorr, int advance) {
   extern __shared__ uint32_t s_bits[];
   __shared__ PullShared sh;
   if (wave_in_block() == 0) {
@@ -1194,6 +1267,10 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
   }
   block_flush(lq, sh.s_cnt);
   add_part(a.part, kPartEntries, entries, &sh.acc);
+  if (advance && last_block_done<false>(a.st)) {
+    advance_round_wave(a.st);
+    if (lane_id() == 0) atomicAdd((unsigned long long *)&a.st->launches, 1ull);
+  }
 }
 
 // After a pull round: queues the split rows that ended below their threshold
@@ -1241,7 +1318,7 @@ bool pull_uses_lds(const Graph &g) {
 
 hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
                                   const int32_t *corr_x, const int32_t *corr_d, int ncorr,
-                                  hipStream_t s) {
+                                  bool advance, hipStream_t s) {
   if (g.pull_mode == 1) return hipSuccess;
   const int64_t words_upper = g.nU > 0 ? ((int64_t)g.nU - 1) / 32 + 1 : 0;
   const int64_t words_lower = g.nL > 0 ? ((g.n - 1) >> 5) - (g.nU >> 5) + 1 : 0;
@@ -1250,13 +1327,14 @@ hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *b
   const int64_t total_entries = 2 * g.m;
   pull_round_kernel<<<g.cu_count, kPullBlock, dyn, s>>>(
       a, bits, g.deg0, g.n, scan_grid(g), g.pull_mode, use_lds ? 1 : 0, total_entries,
-      g.npieces, g.npieces_upper, corr_x, corr_d, ncorr);
+      g.npieces, g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s) {
+hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
+                             bool advance) {
   return launch_pull_round_args(g, make_args(g, thrU, thrL), g.alive_bits, nullptr, nullptr, 0,
-                                s);
+                                advance, s);
 }
 
 // Must follow the pull round on the same stream (it completes that round).

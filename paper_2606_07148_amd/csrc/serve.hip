@@ -288,15 +288,21 @@ bool run_window(Graph &g, Server &S, const std::vector<Request> &win) {
     const bool pull = g.pull_mode == 2;
     SCHK(launch_scan_component_view(g, a, x, y, s.d_corr, s.d_corr + kCorrMax, c,
                                     pull ? s.bits : nullptr, s.stream));
+    PeelArgs ap = a;
     if (pull) {
-      SCHK(launch_pull_round_args(g, a, s.bits, s.d_corr, s.d_corr + kCorrMax, c, s.stream));
-      SCHK(launch_pull_fixup_args(g, a, s.bits, s.stream));
+      // the pull round's completion runs in the peel's start phase
+      SCHK(launch_pull_round_args(g, a, s.bits, s.d_corr, s.d_corr + kCorrMax, c, true,
+                                  s.stream));
+      ap.fix_rows = g.heavy_rows;
+      ap.fix_bits = s.bits;
+      ap.nfix = g.nheavy;
+      ap.start_expect = grid;
     }
     // the scan and the pull round read the current degrees: the next
     // window's updates wait for them
     SCHK(hipEventRecord(s.scanned, s.stream));
     S.last_scans.push_back(s.scanned);
-    SCHK(launch_peel_async_args(g, kGCC, a, grid, s.stream));
+    SCHK(launch_peel_async_args(g, kGCC, ap, grid, s.stream));
     SCHK(launch_answer_view(a, x, y, s.stream));
     SCHK(hipMemcpyAsync(s.h_out, &s.state->aux0, sizeof(int32_t) * 4, hipMemcpyDeviceToHost,
                         s.stream));

@@ -214,18 +214,20 @@ __device__ __forceinline__ void start_rounds_wave(PeelState *st) {
 }
 
 // Arrival on the group/top lines; true in lane 0 for the last arrival.
-__device__ __forceinline__ bool arrive(PeelState *st) {
+__device__ __forceinline__ bool arrive_on(Arrival *arr) {
   const int ng = min((int)gridDim.x, kGroups);
   const int grp = blockIdx.x % kGroups;
   const int gsize = ((int)gridDim.x - grp + kGroups - 1) / kGroups;
-  const uint32_t c = atomicAdd(&st->arr.group[grp][0], 1u);
+  const uint32_t c = atomicAdd(&arr->group[grp][0], 1u);
   if ((int)c != gsize - 1) return false;
-  st_agent(&st->arr.group[grp][0], 0u);
-  const uint32_t t = atomicAdd(&st->arr.top[0], 1u);
+  st_agent(&arr->group[grp][0], 0u);
+  const uint32_t t = atomicAdd(&arr->top[0], 1u);
   if ((int)t != ng - 1) return false;
-  st_agent(&st->arr.top[0], 0u);
+  st_agent(&arr->top[0], 0u);
   return true;
 }
+
+__device__ __forceinline__ bool arrive(PeelState *st) { return arrive_on(&st->arr); }
 
 // Last-workgroup detection.  Returns true in every lane of wave 0 of the
 // workgroup that arrives last.  With kRelease, each workgroup first makes
