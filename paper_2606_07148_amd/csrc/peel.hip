@@ -51,15 +51,14 @@ __global__ void reset_workspace_kernel(int32_t *queue, int64_t qcap, PeelState *
     for (int64_t i = tid; i < t; i += stride) q[i] = kEmpty;
   }
   for (int64_t i = tid; i < nparts; i += stride) part[i] = 0;
+  // no fence: the cursors were consumed (as loop bounds) before the arrival,
+  // and the clearing stores need no order against the state's zeroing (the
+  // next launch orders both)
   __syncthreads();
   if (wave_in_block() != 0) return;
   int last = 0;
-  if (lane_id() == 0) {
-    __threadfence();
-    last = arrive_on(&st->rst) ? 1 : 0;
-  }
+  if (lane_id() == 0) last = arrive_on(&st->rst) ? 1 : 0;
   if (!__shfl(last, 0, kWave)) return;
-  __threadfence();
   int32_t *words = reinterpret_cast<int32_t *>(st);
   constexpr int kRstBegin = (int)(offsetof(PeelState, rst) / 4);
   for (int i = lane_id(); i < kRstBegin; i += kWave)
