@@ -1038,8 +1038,11 @@ struct PullShared {
   int64_t acc;
 };
 
+// Bit of neighbour v (0 for v < 0: padding or a deleted entry), branch-free
+// so that a group of lookups issues together.
 __device__ __forceinline__ uint32_t test_bit(const uint32_t *w, int64_t base_word, int32_t v) {
-  return (w[(v >> 5) - base_word] >> (v & 31)) & 1u;
+  const int64_t idx = v >= 0 ? (int64_t)(v >> 5) - base_word : 0;
+  return (w[idx] >> (v & 31)) & (v >= 0 ? 1u : 0u);
 }
 
 // Neighbours with their bit set in the row [s, s+d), d <= kLightRow (deleted
@@ -1055,7 +1058,7 @@ __device__ __forceinline__ int count_row_thread(const PeelArgs &a, const uint32_
   }
   int c = 0;
 #pragma unroll
-  for (int j = 0; j < kLightRow; ++j) c += w[j] >= 0 ? (int)test_bit(lk, lk_base, w[j]) : 0;
+  for (int j = 0; j < kLightRow; ++j) c += (int)test_bit(lk, lk_base, w[j]);
   return c;
 }
 
@@ -1106,7 +1109,7 @@ __device__ __forceinline__ void count_chunks(const PeelArgs &a, const uint32_t *
     for (int r = 0; r < 4; ++r) {
       int c = 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) c += w[r][j] >= 0 ? (int)test_bit(lk, lk_base, w[r][j]) : 0;
+      for (int j = 0; j < 4; ++j) c += (int)test_bit(lk, lk_base, w[r][j]);
       c += __shfl_xor(c, 8, 16);
       c += __shfl_xor(c, 4, 16);
       c += __shfl_xor(c, 2, 16);
@@ -1146,6 +1149,9 @@ __device__ __forceinline__ int delta_alive(const PeelArgs &a, const uint32_t *gb
   return extra;
 }
 
+// kLds: the neighbour layer's bitmap is staged in LDS (a compile-time
+// choice, so that lookups are LDS reads and not generic-address loads).
+template <bool kLds>
 __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     PeelArgs a, const uint32_t *__restrict__ gbits, const int32_t *__restrict__ deg0, int64_t n,
     int scan_blocks, int mode, int use_lds, int64_t total_entries, int64_t npieces,
@@ -1181,7 +1187,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     if (lo >= hi) continue;
     const uint32_t *lk = gbits;
     int64_t lk_base = 0;
-    if (use_lds) {
+    if (kLds) {
       const int64_t w0 = nb_lo >> 5;
       const int64_t w1 = nb_hi > nb_lo ? ((nb_hi - 1) >> 5) : w0;
       __syncthreads();
@@ -1304,7 +1310,7 @@ __global__ __launch_bounds__(kPeelBlock) void pull_fixup_kernel(
 // per-workgroup LDS permits.
 hipError_t prepare_pull_kernel(Graph &g) {
   const int dyn = (int)std::max<int64_t>(0, (int64_t)g.lds_per_block - (int64_t)sizeof(PullShared));
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&pull_round_kernel),
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&pull_round_kernel<true>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
 }
 
@@ -1324,9 +1330,14 @@ hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *b
   const bool use_lds = pull_uses_lds(g);
   const size_t dyn = use_lds ? (size_t)(4 * std::max(words_upper, words_lower)) : 0;
   const int64_t total_entries = 2 * g.m;
-  pull_round_kernel<<<g.cu_count, kPullBlock, dyn, s>>>(
-      a, bits, g.deg0, g.n, scan_grid(g), g.pull_mode, use_lds ? 1 : 0, total_entries,
-      g.npieces, g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0);
+  if (use_lds)
+    pull_round_kernel<true><<<g.cu_count, kPullBlock, dyn, s>>>(
+        a, bits, g.deg0, g.n, scan_grid(g), g.pull_mode, 1, total_entries, g.npieces,
+        g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0);
+  else
+    pull_round_kernel<false><<<g.cu_count, kPullBlock, dyn, s>>>(
+        a, bits, g.deg0, g.n, scan_grid(g), g.pull_mode, 0, total_entries, g.npieces,
+        g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0);
   return hipGetLastError();
 }
 
