@@ -260,6 +260,61 @@ def bench_serve(args, pkg, torch, np, bigraph_gen) -> dict:
     }
 
 
+def bench_sweep(args, pkg, torch, np, bigraph_gen) -> dict:
+    """The billion-edge GCC+ sweep: Chung-Lu |U|=50M |L|=20M m=10^9, degree
+    exponents 2.0 / 2.3, cap 50k; core numbers once, then alpha = beta in
+    {1, 2, 4, ..., 256} with GCC+ (each a scan of the core numbers) and, for
+    comparison, with GCC.  Results compared bit for bit."""
+    spec = bigraph_gen.CONFIGS[3]
+    nU, nL = spec["n_upper"], spec["n_lower"]
+    t0 = time.perf_counter()
+    eu, ev = bigraph_gen.make_graph(spec)
+    print(f"# sweep graph generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    m = len(eu)
+    deu = torch.from_numpy(eu).cuda()
+    dev = torch.from_numpy(ev).cuda()
+    del eu, ev
+    g = pkg.abcore_build_csr(nU, nL, deu, dev)
+    del deu, dev
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, max_core = pkg.abcore_core_numbers(g)
+    torch.cuda.synchronize()
+    prep_ms = (time.perf_counter() - t0) * 1e3
+    out = torch.empty(g.nwords, dtype=torch.int32, device="cuda")
+    ref = torch.empty(g.nwords, dtype=torch.int32, device="cuda")
+    rows = []
+    parity = True
+    for k in [1, 2, 4, 8, 16, 32, 64, 128, 256]:
+        times = {}
+        for algo, name in ((pkg.ABCORE_GCC, "gcc"), (pkg.ABCORE_GCC_PLUS, "gcc_plus")):
+            dst = ref if algo == pkg.ABCORE_GCC else out
+            pkg.abcore_compute(g, k, k, algo, out=dst)
+            torch.cuda.synchronize()
+            reps = 5
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                pkg.abcore_compute(g, k, k, algo, out=dst)
+            torch.cuda.synchronize()
+            times[name] = (time.perf_counter() - t0) * 1e3 / reps
+        parity = parity and bool(torch.equal(out, ref))
+        rows.append({"alpha": k, "beta": k, "gcc_plus_ms": times["gcc_plus"],
+                     "gcc_ms": times["gcc"]})
+    g.destroy()
+    total_plus = sum(r["gcc_plus_ms"] for r in rows)
+    return {
+        "workload": "chung-lu |U|=50,000,000 |L|=20,000,000 m=1,000,000,000 "
+                    "gamma=2.0/2.3 cap=50,000; alpha=beta in {1,2,4,...,256}",
+        "m": m, "core_preprocessing_ms": prep_ms, "max_core": max_core,
+        "queries": rows, "gcc_plus_total_ms": total_plus,
+        "gcc_total_ms": sum(r["gcc_ms"] for r in rows),
+        "gcc_plus_input_edges_per_s": m * len(rows) / (total_plus / 1e3),
+        "parity_gcc_plus_vs_gcc": parity,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,6 +329,8 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-query section")
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the billion-edge GCC+ sweep section")
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-slots", type=int, default=2)
     ap.add_argument("--serve-inflight", type=int, default=64)
@@ -448,6 +505,9 @@ def main() -> int:
     serve = None
     if not args.no_serve:
         serve = bench_serve(args, pkg, torch, np, bigraph_gen)
+    sweep = None
+    if not args.no_sweep:
+        sweep = bench_sweep(args, pkg, torch, np, bigraph_gen)
 
     result = {
         "metric": "edges peeled/sec",
@@ -492,6 +552,7 @@ def main() -> int:
         "gcc_plus": gcc_plus,
         "batch": batch,
         "serve": serve,
+        "sweep": sweep,
         "build_s": build_s,
     }
     if not args.no_cpu_baseline:
@@ -505,7 +566,8 @@ def main() -> int:
     print(json.dumps(result), flush=True)
     g.destroy()
     ok = (parity and plus_parity and (batch is None or batch["parity_vs_sequential"])
-          and (serve is None or serve["answers_equal_sequential"]))
+          and (serve is None or serve["answers_equal_sequential"])
+          and (sweep is None or sweep["parity_gcc_plus_vs_gcc"]))
     return 0 if ok else 1
 
 
