@@ -318,6 +318,7 @@ hipError_t launch_restricted_init(Graph &g, int32_t thrU, int32_t thrL, int32_t 
 hipError_t launch_kcore_init(Graph &g, hipStream_t s);
 hipError_t launch_kcore_persistent(Graph &g, hipStream_t s);
 hipError_t launch_kcore_steps(Graph &g, int steps, hipStream_t s);
+hipError_t launch_kcore_levels(Graph &g, int levels, hipStream_t s);
 hipError_t launch_cc(Graph &g, int32_t only_label, hipStream_t s);
 hipError_t query_persistent_grids(Graph &g);
 abcore_status build_pieces(Graph &g, hipStream_t s);

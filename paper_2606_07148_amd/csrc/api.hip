@@ -276,7 +276,23 @@ abcore_status compute_core(Graph &g, hipStream_t s) {
   TRY(ensure(&g.list, g.n));
   TRY(ensure(&g.list2, g.n));
   CHK(launch_kcore_init(g, s));
-  if (g.peel_mode >= 2 && g.kcore_grid > 0) {
+  if (g.peel_mode == 3) {
+    // levels of a scan and an asynchronous peel, in growing batches between
+    // checks; every level either removes a vertex or jumps to one that does
+    const int64_t max_levels = 2 * g.n + 8;
+    int batch = 8;
+    int64_t done = 0;
+    for (; done < max_levels; done += batch) {
+      CHK(launch_kcore_levels(g, batch, s));
+      TRY(read_state(g, s));
+      if (g.h_state->done) break;
+      batch = std::min(batch * 2, 256);
+    }
+    if (done >= max_levels) {
+      set_error("core decomposition did not converge");
+      return ABCORE_EDEVICE;
+    }
+  } else if (g.peel_mode >= 2 && g.kcore_grid > 0) {
     CHK(launch_kcore_persistent(g, s));
     TRY(read_state(g, s));
     if (!g.h_state->done) {

@@ -824,15 +824,15 @@ constexpr uint32_t kAsyncSpinLimit = 1u << 21;
 template <int KIND>
 __device__ __forceinline__ void async_batch(const PeelArgs &a, int32_t item, int nitems,
                                             LocalQueue &lq, int32_t *consumed,
-                                            int64_t &entries) {
-  peel_batch<KIND, true>(a, item, 0, lq, entries);
+                                            int64_t &entries, int32_t level) {
+  peel_batch<KIND, true>(a, item, level, lq, entries);
   while (lq.count > 0) {
     const int take = min(lq.count, kWave);
     __builtin_amdgcn_wave_barrier();
     const int32_t xi = lane_id() < take ? lq.buf[lq.count - take + lane_id()] : -1;
     __builtin_amdgcn_wave_barrier();
     lq.count -= take;
-    peel_batch<KIND, true>(a, xi, 0, lq, entries);
+    peel_batch<KIND, true>(a, xi, level, lq, entries);
   }
   lq.flush();
   __builtin_amdgcn_s_waitcnt(0);
@@ -890,6 +890,10 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
   const int j = blockIdx.x % kSub;
   int32_t *head = &a.st->head[j][0];
   int32_t *consumed = &a.st->consumed[j][0];
+  // core decomposition: the level set by the preceding scan (nothing to do
+  // once every vertex has its core number)
+  if (KIND == kKCore && ld_agent(&a.st->done) != 0) return;
+  const int32_t level = KIND == kKCore ? ld_agent(&a.st->k) : 0;
   int64_t entries = 0;
   uint32_t idle = 0, victim = 0;
   bool finished = false;
@@ -908,7 +912,8 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
       const bool ready = pending && item != kEmpty;
       const uint64_t rmask = __ballot(ready);
       if (rmask) {
-        async_batch<KIND>(a, ready ? item : -1, (int)__popcll(rmask), lq, consumed, entries);
+        async_batch<KIND>(a, ready ? item : -1, (int)__popcll(rmask), lq, consumed, entries,
+                          level);
         pending = pending && !ready;
         idle = 0;
         continue;
@@ -935,7 +940,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
             sitem = -1;
           }
         }
-        async_batch<KIND>(a, sitem, taken, lq, consumed, entries);
+        async_batch<KIND>(a, sitem, taken, lq, consumed, entries, level);
         idle = 0;
         continue;
       }
@@ -957,6 +962,11 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
     }
   }
   add_part(a.part, kPartEntries, entries, &s_acc);
+  if (KIND == kKCore && threadIdx.x < kSub) {
+    // everything appended so far is processed: the next level's scan starts
+    // its range here (every workgroup writes the same final cursors)
+    st_agent(&a.st->hi[threadIdx.x], ld_agent(&a.st->tail[threadIdx.x][0]));
+  }
   if (a.pack_bits != nullptr && ld_agent(&a.st->abort_flag) == 0) {
     // the result (Algorithm 1's V(G)): termination means every decrement
     // is done; degrees are read at device scope (they changed by atomics)
@@ -1810,6 +1820,101 @@ hipError_t launch_kcore_persistent(Graph &g, hipStream_t s) {
   void *args[] = {&a, &l0, &l1, &max_phases};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&kcore_persistent_kernel),
                                     dim3(g.kcore_grid), dim3(kPeelBlock), args, 0, s);
+}
+
+// ---------------------------------------------- core numbers by levels --
+// Level k of the decomposition (Definition 2: core(x) = the largest k with x
+// in the k-core) as one scan and one asynchronous peel.  The scan takes the
+// live vertices of degree <= k (core k), queues them, and appends the others
+// to the next alive list (so the list only ever holds live vertices); the
+// peel then gives core k to every vertex whose degree falls to k, in any
+// order (the k-core is unique).  A level that queues nothing jumps to the
+// smallest live degree.  No grid barrier: two launches per level.
+__global__ __launch_bounds__(kScanBlock) void kcore_level_scan_kernel(PeelArgs a,
+                                                                      int32_t *list0,
+                                                                      int32_t *list1) {
+  __shared__ ScanCollector col;   // queued vertices
+  __shared__ ScanCollector keep;  // live vertices for the next level
+  __shared__ int32_t s_min;
+  PeelState *st = a.st;
+  if (st->done) return;  // written by an earlier launch
+  const int32_t kn = st->next_k;
+  const int32_t cur = st->alive_cur;
+  const int sel = st->alive_sel;
+  const int32_t *A = sel ? list1 : list0;
+  int32_t *N = sel ? list0 : list1;
+  if (threadIdx.x == 0) {
+    col.count = 0;
+    keep.count = 0;
+    s_min = 0x7FFFFFFF;
+  }
+  __syncthreads();
+  const int sub = blockIdx.x % kSub;
+  int32_t *q = a.queue + (int64_t)sub * a.qcap;
+  int32_t mn = 0x7FFFFFFF;
+  for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < cur;
+       cb += (int64_t)gridDim.x * kScanChunk) {
+    for (int t = 0; t < kScanChunk; t += kScanBlock * 4) {
+      const int64_t i0 = cb + t + (int64_t)threadIdx.x * 4;
+      int32_t items[4], kept[4];
+      int cnt = 0, kc = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (i0 + j < cur) {
+          const int32_t x = A[i0 + j];
+          if (a.core[x] < 0) {
+            const int32_t d = a.deg[x];
+            if (d <= kn) {
+              a.core[x] = kn;
+              items[cnt++] = x;
+            } else {
+              kept[kc++] = x;
+              mn = min(mn, d);
+            }
+          }
+        }
+      }
+      col.append(items, cnt);
+      keep.append(kept, kc);
+    }
+    col.flush(q, &a.st->tail[sub][0]);
+    keep.flush(N, &a.st->kept);
+  }
+  mn = wave_min(mn);
+  if (lane_id() == 0) atomicMin(&s_min, mn);
+  __syncthreads();
+  if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * kPartFields + kPartMin] = s_min;
+  if (last_block_done<false>(st)) {
+    const int lane = lane_id();
+    int32_t after = 0;
+    if (lane < kSub) after = ld_agent(&st->tail[lane][0]) - ld_agent(&st->hi[lane]);
+    after = wave_sum(after);
+    const int32_t gmin =
+        (int32_t)wave_min_strided(a.part + kPartMin, (int)gridDim.x, kPartFields, 0x7FFFFFFF);
+    advance_round_wave(st);  // the queued vertices start the level's peel
+    if (lane == 0) {
+      const int32_t kept_n = ld_agent(&st->kept);
+      st->k = kn;
+      if (after > 0) st->max_core = kn;
+      st->next_k = after > 0 ? kn + 1 : max(kn + 1, gmin);
+      st->alive_cur = kept_n;
+      st->alive_sel = sel ^ 1;
+      st->kept = 0;
+      if (kept_n == 0) st->done = 1;
+      atomicAdd((unsigned long long *)&st->launches, 1ull);
+    }
+  }
+}
+
+hipError_t launch_kcore_levels(Graph &g, int levels, hipStream_t s) {
+  PeelArgs a = make_args(g, 0, 0);
+  const int sgrid = std::min(g.cu_count * 4, kMaxBlocks);
+  const int agrid = async_peel_grid(g);
+  for (int l = 0; l < levels; ++l) {
+    kcore_level_scan_kernel<<<sgrid, kScanBlock, 0, s>>>(a, g.list, g.list2);
+    peel_async_kernel<kKCore><<<agrid, kPeelBlock, 0, s>>>(a);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_kcore_steps(Graph &g, int steps, hipStream_t s) {
