@@ -67,6 +67,7 @@ struct PeelState {
   int32_t head[kSub][kPad];  // asynchronous peel: next slot to claim
   int32_t consumed[kSub][kPad];  // asynchronous peel: slots processed
   int32_t started[kGroups][kPad];  // asynchronous peel: workgroups past their start phase
+  int32_t fin[kGroups][kPad];  // asynchronous peel: termination detected (one copy per group)
   int32_t lo[kSub];
   int32_t hi[kSub];
   Arrival arr;
@@ -256,6 +257,9 @@ struct PeelArgs {
   int64_t nfix;
   uint32_t *pack_bits;
   int32_t start_expect;
+  // vertices alive after the scan (bit set; nullable): GCC skips decrements
+  // of the scan frontier, which is out of the core whatever its degree
+  const uint32_t *alive0;
   int64_t n;
   int32_t nU;
   int32_t thrU, thrL;

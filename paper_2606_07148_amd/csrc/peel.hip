@@ -132,6 +132,7 @@ PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL) {
   a.nfix = 0;
   a.pack_bits = nullptr;
   a.start_expect = 0;
+  a.alive0 = nullptr;
   a.n = g.n;
   a.nU = g.nU;
   a.thrU = thrU;
@@ -620,6 +621,10 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
       // value is never below the true one)
       bool live = w[u] >= 0 && dw[u] >= t[u];
       if (KIND == kGCCPlus) live = live && dw[u] != kDegIn;
+      // the decrements are atomic-throughput bound: a vertex of the scan
+      // frontier (a small, cache-resident bitmap) needs none
+      if (KIND == kGCC && a.alive0 != nullptr && w[u] >= 0)
+        live = live && ((a.alive0[w[u] >> 5] >> (w[u] & 31)) & 1u);
       push[u] = live && atomicSub(&a.deg[w[u]], 1) == t[u];
     }
 #pragma unroll
@@ -765,17 +770,20 @@ hipError_t launch_peel_persistent(Graph &g, PeelKind kind, int32_t thrU, int32_t
 // The peel without rounds: since the core does not depend on the order of
 // removals (Definition 1 fixes a unique result), a removed vertex can be
 // processed as soon as it is queued.  Each workgroup is bound to one
-// sub-queue; its waves claim 64 slots at a time, process the items as they
+// sub-queue; its waves claim slots in groups, process the items as they
 // are written (a slot holds kEmpty until then) and append what they remove to
 // the same sub-queue, whose claimed-but-unwritten slots always belong to a
 // waiting wave of that sub-queue.  Termination: every queued item has been
 // processed, read as sum(done) == sum(tail) with all `done` read before any
 // `tail` (an item's appends precede its `done` increment), which means no item
-// was in flight and none can be appended any more.  A waiting wave also
-// steals: it claims exactly the appended-but-unclaimed slots of another
-// sub-queue (compare-and-swap on that head, never past its tail), so items
-// never wait for a workgroup of their own sub-queue to be resident, and
-// several peels can share the device without any co-residency assumption.
+// was in flight and none can be appended any more.  Wave 0 of a waiting
+// workgroup also steals: it claims exactly the appended-but-unclaimed slots
+// of another sub-queue (compare-and-swap on that head, never past its tail),
+// so items never wait for a workgroup of their own sub-queue to be
+// resident, and several peels can share the device without any co-residency
+// assumption.  Only wave 0 of a workgroup reads the shared termination words
+// (same-address reads serialise like atomics); it tells the other waves
+// through LDS.  Claims are 32 slots by default (a.claim).
 
 __device__ __forceinline__ bool quiescent(PeelState *st, int32_t start_expect) {
   const int j = lane_id();
@@ -863,6 +871,9 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
   __shared__ int32_t s_lq[kPeelWaves][kLocalQueue];
   __shared__ int64_t s_acc;
   __shared__ int s_cnt[kPeelWaves + 1];
+  __shared__ int s_stop;
+  if (threadIdx.x == 0) s_stop = 0;
+  __syncthreads();
   LocalQueue lq = make_lq(s_lq[wave_in_block()], kLocalQueue, a);
   const int waves = blockDim.x / kWave;
   const int gw = blockIdx.x * waves + wave_in_block();
@@ -882,10 +893,11 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
       }
     }
     block_flush(lq, s_cnt);
-    if (threadIdx.x == 0) {
-      __threadfence();  // the appended items before the start count
-      atomicAdd(&a.st->started[blockIdx.x % kGroups][0], 1);
-    }
+    // the appended items (agent-scope stores) are complete before the start
+    // count, so a termination test that sees the count sees them
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(&a.st->started[blockIdx.x % kGroups][0], 1);
   }
   const int j = blockIdx.x % kSub;
   int32_t *head = &a.st->head[j][0];
@@ -918,11 +930,12 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
         idle = 0;
         continue;
       }
-      // nothing in the own slots: steal from another sub-queue (one victim
-      // per poll, in rotation)
+      // nothing in the own slots: wave 0 steals from another sub-queue (one
+      // victim per poll, in rotation; one wave per workgroup keeps the
+      // polls of the shared cursors few)
       victim = victim % (kSub - 1) + 1;
       int sbase = 0;
-      const int taken = (idle % ABC_STEAL_EVERY) == 0
+      const int taken = (wave_in_block() == 0 && (idle % ABC_STEAL_EVERY) == 0)
                             ? steal_claim(a.st, (j + (int)victim) % kSub, claim, &sbase)
                             : 0;
       if (taken > 0) {
@@ -944,17 +957,39 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
         idle = 0;
         continue;
       }
-      // waiting: poll with growing back-off (the counters share lines with
-      // the producers' atomics), test for termination every fourth poll,
-      // and give up after the spin limit (an abort, reported)
+      // waiting: poll with growing back-off and give up after the spin
+      // limit (an abort, reported).  Only wave 0 of a workgroup polls the
+      // shared words (same-address reads serialise like atomics): its
+      // group's copy of `fin` every poll, and every fourth poll the
+      // termination test, whose first success sets every copy.  It passes
+      // the verdict to the other waves through LDS.
       ++idle;
-      if ((idle & ABC_QMASK) == 0 &&
-          (quiescent(a.st, a.start_expect) || ld_agent(&a.st->abort_flag))) {
+      int stop = 0;
+      if (wave_in_block() == 0) {
+        if (lane_id() == 0) stop = ld_agent(&a.st->fin[blockIdx.x % kGroups][0]);
+        stop = __shfl(stop, 0, kWave);
+        if (!stop && (idle & ABC_QMASK) == 0) {
+          if (quiescent(a.st, a.start_expect)) {
+            if (lane_id() < kGroups) st_agent(&a.st->fin[lane_id()][0], 1);
+            stop = 1;
+          } else {
+            if (lane_id() == 0) stop = ld_agent(&a.st->abort_flag);
+            stop = __shfl(stop, 0, kWave);
+          }
+        }
+        if (stop && lane_id() == 0) __hip_atomic_store(&s_stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+        stop = __hip_atomic_load(&s_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      if (stop) {
         finished = true;
         break;
       }
       if (idle > kAsyncSpinLimit) {
-        if (lane_id() == 0) st_agent(&a.st->abort_flag, 1);
+        if (lane_id() == 0) {
+          st_agent(&a.st->abort_flag, 1);
+          __hip_atomic_store(&s_stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
         finished = true;
         break;
       }
@@ -970,13 +1005,26 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
   if (a.pack_bits != nullptr && ld_agent(&a.st->abort_flag) == 0) {
     // the result (Algorithm 1's V(G)): termination means every decrement
     // is done; degrees are read at device scope (they changed by atomics)
+    // kPackSpan consecutive vertices per lane pass, all loads issued before
+    // the first test, so a wave has that many reads in flight
     const int64_t n = a.n;
-    for (int64_t b = (int64_t)gw * kWave; b < n; b += (int64_t)nw * kWave) {
-      const int64_t x = b + lane_id();
-      const bool in = x < n && ld_agent(&a.deg[x]) >= (x < a.nU ? a.thrU : a.thrL);
-      const uint64_t m = __ballot(in);
-      if (lane_id() < 2 && b + 32 * lane_id() < n)
-        a.pack_bits[(b >> 5) + lane_id()] = (uint32_t)(m >> (32 * lane_id()));
+    constexpr int kPackSpan = 8;
+    for (int64_t b = (int64_t)gw * kWave * kPackSpan; b < n;
+         b += (int64_t)nw * kWave * kPackSpan) {
+      int32_t dv[kPackSpan];
+#pragma unroll
+      for (int u = 0; u < kPackSpan; ++u) {
+        const int64_t x = b + u * kWave + lane_id();
+        dv[u] = x < n ? ld_agent(&a.deg[x]) : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kPackSpan; ++u) {
+        const int64_t b64 = b + u * kWave;
+        const int64_t x = b64 + lane_id();
+        const uint64_t m = __ballot(x < n && dv[u] >= (x < a.nU ? a.thrU : a.thrL));
+        if (lane_id() < 2 && b64 + 32 * lane_id() < n)
+          a.pack_bits[(b64 >> 5) + lane_id()] = (uint32_t)(m >> (32 * lane_id()));
+      }
     }
   }
 }
@@ -1002,6 +1050,7 @@ hipError_t launch_peel_async_fused(Graph &g, PeelKind kind, int32_t thrU, int32_
     a.fix_bits = fix_bits;
     a.nfix = g.nheavy;
     a.start_expect = grid;
+    a.alive0 = fix_bits;
   }
   a.pack_bits = pack_bits;
   return launch_peel_async_args(g, kind, a, grid, s);
@@ -1892,6 +1941,7 @@ __global__ __launch_bounds__(kScanBlock) void kcore_level_scan_kernel(PeelArgs a
     const int32_t gmin =
         (int32_t)wave_min_strided(a.part + kPartMin, (int)gridDim.x, kPartFields, 0x7FFFFFFF);
     advance_round_wave(st);  // the queued vertices start the level's peel
+    if (lane < kGroups) st->fin[lane][0] = 0;  // the level's peel detects its own end
     if (lane == 0) {
       const int32_t kept_n = ld_agent(&st->kept);
       st->k = kn;
