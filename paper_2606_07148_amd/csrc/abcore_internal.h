@@ -169,6 +169,11 @@ struct Graph {
   int32_t *heavy_rows = nullptr;   // nheavy: the split rows, ascending
   int64_t npieces = 0, npieces_upper = 0;
   int64_t nheavy = 0, nheavy_upper = 0;
+  // Pull round work split: workgroup k of a cu_count grid walks the upper
+  // rows [b[k], b[k+1]) and the lower rows [b[G+1+k], b[G+2+k]), ranges of
+  // equal weight (entries of unsplit rows plus a per-row cost).
+  int32_t *pull_bounds = nullptr;  // 2 * (pull_bounds_grid + 1)
+  int pull_bounds_grid = 0;
   int32_t *comp = nullptr;  // component labels
   bool comp_valid = false;
   int32_t *parent = nullptr; // union-find scratch

@@ -134,7 +134,8 @@ void free_graph(Graph *g) {
                   g->queue,      g->list,        g->list2,       g->state,
                   g->core,       g->comp,        g->parent,      g->delta.head,
                   g->delta.next, g->delta.other, g->alive_bits,  g->part,
-                  g->piece_row,  g->piece_start, g->piece_first, g->heavy_rows};
+                  g->piece_row,  g->piece_start, g->piece_first, g->heavy_rows,
+                  g->pull_bounds};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   if (g->h_state) (void)hipHostFree(g->h_state);

@@ -101,6 +101,40 @@ __global__ void fill_pieces_kernel(const int64_t *__restrict__ off, int64_t n,
   }
 }
 
+// Weight of a row in the pull round: its entries when it is walked as a row
+// (a split row is walked by its pieces) plus a fixed cost per row.
+constexpr int64_t kRowCost = 4;
+__global__ void row_weight_kernel(const int64_t *__restrict__ off, int64_t n,
+                                  int64_t *__restrict__ w) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= n; x += stride) {
+    const int64_t d = x < n ? off[x + 1] - off[x] : 0;
+    w[x] = x < n ? (d <= kPiece ? d : 0) + kRowCost : 0;
+  }
+}
+
+// Bound k of layer p (0 upper, 1 lower): the first row of the layer whose
+// exclusive weight prefix reaches k/G of the layer's weight.  The prefix is
+// strictly increasing (every row costs at least kRowCost), so bound 0 and
+// bound G are the layer's first row and its end.
+__global__ void pull_bounds_kernel(const int64_t *__restrict__ pre, int64_t nU, int64_t n, int G,
+                                   int32_t *__restrict__ bounds) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * (G + 1)) return;
+  const int p = t / (G + 1), k = t % (G + 1);
+  int64_t lo = p == 0 ? 0 : nU, hi = p == 0 ? nU : n;
+  const int64_t base = pre[lo];
+  const int64_t target = base + (pre[hi] - base) * k / G;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (pre[mid] >= target)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  bounds[t] = (int32_t)lo;
+}
+
 int bits_for(uint64_t maxkey) {
   int b = 0;
   while (b < 64 && (maxkey >> b) != 0) ++b;
@@ -248,6 +282,15 @@ abcore_status build_pieces(Graph &g, hipStream_t s) {
   PCHK(hipMalloc(&g.heavy_rows, sizeof(int32_t) * std::max<int64_t>(g.nheavy, 1)));
   fill_pieces_kernel<<<grid, 256, 0, s>>>(g.off, g.n, first, hfirst, g.piece_row, g.piece_start,
                                           g.piece_first, g.heavy_rows);
+  PCHK(hipGetLastError());
+  // pull round work split (np and hv are free again: weights and prefix)
+  g.pull_bounds_grid = g.cu_count;
+  PCHK(hipMalloc(&g.pull_bounds, sizeof(int32_t) * 2 * (g.pull_bounds_grid + 1)));
+  row_weight_kernel<<<grid, 256, 0, s>>>(g.off, g.n, np);
+  PCHK(hipGetLastError());
+  PCHK(hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, np, hv, (int)(g.n + 1), s));
+  pull_bounds_kernel<<<(2 * (g.pull_bounds_grid + 1) + 255) / 256, 256, 0, s>>>(
+      hv, g.nU, g.n, g.pull_bounds_grid, g.pull_bounds);
   PCHK(hipGetLastError());
   PCHK(hipStreamSynchronize(s));
 done:

@@ -1094,6 +1094,7 @@ struct PullShared {
   ChunkDesc desc[kPullWaves][kWave];
   int s_cnt[kPullWaves + 1];
   int decide;
+  int next_row, next_piece;  // the workgroup's next unclaimed row / piece
   int64_t acc;
 };
 
@@ -1215,9 +1216,36 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     PeelArgs a, const uint32_t *__restrict__ gbits, const int32_t *__restrict__ deg0, int64_t n,
     int scan_blocks, int mode, int use_lds, int64_t total_entries, int64_t npieces,
     int64_t npieces_upper, const int32_t *__restrict__ corr_x,
-    const int32_t *__restrict__ corr_d, int ncorr, int advance) {
-  extern __shared__ uint32_t s_bits[];
+    const int32_t *__restrict__ corr_d, int ncorr, int advance,
+    const int32_t *__restrict__ bounds) {
+  extern __shared__ __align__(16) uint32_t s_bits[];
   __shared__ PullShared sh;
+  // Each phase walks one layer's rows; its bitmap of the other layer is
+  // staged in LDS (kLds) from the 16-byte boundary at or below its first
+  // word, 16 bytes per load.  Phase 0
+  // (upper rows) is staged while wave 0 makes the push/pull decision.
+  auto stage_base = [&](int phase) -> int64_t { return ((phase == 0 ? a.nU : 0) >> 5) & ~3LL; };
+  auto stage = [&](int phase) {
+    const int64_t nb_lo = phase == 0 ? a.nU : 0, nb_hi = phase == 0 ? n : a.nU;
+    const int64_t w1 = nb_hi > nb_lo ? ((nb_hi - 1) >> 5) : (nb_lo >> 5);
+    const int64_t a0 = stage_base(phase);
+    const int64_t n4 = (w1 + 1 - a0) / 4;  // whole 16-byte groups up to w1
+    const uint4 *src = reinterpret_cast<const uint4 *>(gbits + a0);
+    uint4 *dst = reinterpret_cast<uint4 *>(s_bits);
+    // every workgroup reads the same words: each starts at its own offset so
+    // that the requests of the grid spread over the cache channels (one
+    // 16-byte load in flight per thread: more costs registers the walk needs)
+    const int64_t rot = n4 > 0 ? (int64_t)blockIdx.x * n4 / gridDim.x : 0;
+    for (int64_t i = threadIdx.x; i < n4; i += blockDim.x) {
+      const int64_t j = i + rot < n4 ? i + rot : i + rot - n4;
+      dst[j] = src[j];
+    }
+    for (int64_t i = a0 + 4 * n4 + threadIdx.x; i <= w1; i += blockDim.x) s_bits[i - a0] = gbits[i];
+  };
+  if (threadIdx.x == 0) {
+    sh.next_row = 0;
+    sh.next_piece = 0;
+  }
   if (wave_in_block() == 0) {
     // the scan's frontier degree sum, from its per-workgroup slots
     const int64_t f0deg = wave_sum_strided(a.part + kPartF0Deg, scan_blocks, kPartFields);
@@ -1228,6 +1256,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
                                     (use_lds ? f0deg * 16 >= rest : f0deg * 2 >= rest));
     if (lane_id() == 0) sh.decide = pull ? 1 : 0;
   }
+  if (kLds) stage(0);
   __syncthreads();
   if (!sh.decide) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(&a.st->pulled, 1);
@@ -1235,30 +1264,42 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
   int32_t *cnt = sh.cnt[wave_in_block()];
   ChunkDesc *desc = sh.desc[wave_in_block()];
   int64_t entries = 0;
-  const int waves = blockDim.x / kWave;
-  const int gw = blockIdx.x * waves + wave_in_block();
-  const int nw = gridDim.x * waves;
   for (int phase = 0; phase < 2; ++phase) {
     // phase 0: upper rows (neighbours are lower ids), phase 1: lower rows
     const int64_t lo = phase == 0 ? 0 : a.nU, hi = phase == 0 ? a.nU : n;
     const int64_t plo = phase == 0 ? 0 : npieces_upper, phi = phase == 0 ? npieces_upper : npieces;
-    const int64_t nb_lo = phase == 0 ? a.nU : 0, nb_hi = phase == 0 ? n : a.nU;
+    if (phase == 1) {
+      // every wave is done with phase 0 before its bitmap and counters go
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        sh.next_row = 0;
+        sh.next_piece = 0;
+      }
+      if (kLds) stage(1);
+      __syncthreads();
+    }
     if (lo >= hi) continue;
     const uint32_t *lk = gbits;
     int64_t lk_base = 0;
     if (kLds) {
-      const int64_t w0 = nb_lo >> 5;
-      const int64_t w1 = nb_hi > nb_lo ? ((nb_hi - 1) >> 5) : w0;
-      __syncthreads();
-      for (int64_t i = threadIdx.x; i <= w1 - w0; i += blockDim.x) s_bits[i] = gbits[w0 + i];
-      __syncthreads();
       lk = s_bits;
-      lk_base = w0;
+      lk_base = stage_base(phase);
     }
-    // rows of at most kPiece entries, 64 consecutive vertices per wave
-    for (int64_t b = lo + (int64_t)gw * kWave; b < hi; b += (int64_t)nw * kWave) {
+    // This workgroup's rows (a range of equal weight, else an equal share)
+    // and pieces; its waves claim 64 of them at a time through LDS.
+    const int G = (int)gridDim.x, k = (int)blockIdx.x;
+    const int64_t r0 = bounds != nullptr ? bounds[phase * (G + 1) + k] : lo + (hi - lo) * k / G;
+    const int64_t r1 = bounds != nullptr ? bounds[phase * (G + 1) + k + 1]
+                                         : lo + (hi - lo) * (k + 1) / G;
+    const int64_t p0 = plo + (phi - plo) * k / G, p1 = plo + (phi - plo) * (k + 1) / G;
+    // rows of at most kPiece entries, 64 consecutive vertices per claim
+    for (;;) {
+      int claim = 0;
+      if (lane_id() == 0) claim = atomicAdd(&sh.next_row, kWave);
+      const int64_t b = r0 + __shfl(claim, 0, kWave);
+      if (b >= r1) break;
       const int64_t xi = b + lane_id();
-      const int32_t x = xi < hi ? (int32_t)xi : -1;
+      const int32_t x = xi < r1 ? (int32_t)xi : -1;
       int64_t s = 0;
       int d = 0;
       bool alive = false;
@@ -1285,13 +1326,17 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     }
     // pieces of longer rows: per-piece counts summed per row inside the
     // wave (a row's pieces are consecutive), one atomic per row and wave
-    for (int64_t b = plo + (int64_t)gw * kWave; b < phi; b += (int64_t)nw * kWave) {
+    for (;;) {
+      int claim = 0;
+      if (lane_id() == 0) claim = atomicAdd(&sh.next_piece, kWave);
+      const int64_t b = p0 + __shfl(claim, 0, kWave);
+      if (b >= p1) break;
       const int64_t pi = b + lane_id();
       int32_t row = -1;
       int64_t s = 0;
       int d = 0;
       bool first = false, alive = false;
-      if (pi < phi) {
+      if (pi < p1) {
         row = a.piece_row[pi];
         s = a.piece_start[pi];
         const int64_t rs = a.off[row], re = a.off[row + 1];
@@ -1368,7 +1413,9 @@ __global__ __launch_bounds__(kPeelBlock) void pull_fixup_kernel(
 // Allows the pull kernel to stage a layer bitmap as large as the device's
 // per-workgroup LDS permits.
 hipError_t prepare_pull_kernel(Graph &g) {
-  const int dyn = (int)std::max<int64_t>(0, (int64_t)g.lds_per_block - (int64_t)sizeof(PullShared));
+  // (256 bytes left for the alignment of the dynamic part)
+  const int dyn = (int)std::max<int64_t>(
+      0, (int64_t)g.lds_per_block - (int64_t)sizeof(PullShared) - 256);
   return hipFuncSetAttribute(reinterpret_cast<const void *>(&pull_round_kernel<true>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
 }
@@ -1376,7 +1423,7 @@ hipError_t prepare_pull_kernel(Graph &g) {
 bool pull_uses_lds(const Graph &g) {
   const int64_t words_upper = g.nU > 0 ? ((int64_t)g.nU - 1) / 32 + 1 : 0;
   const int64_t words_lower = g.nL > 0 ? ((g.n - 1) >> 5) - (g.nU >> 5) + 1 : 0;
-  const int64_t need = 4 * std::max(words_upper, words_lower);
+  const int64_t need = 4 * (std::max(words_upper, words_lower) + 4);
   return (size_t)need + sizeof(PullShared) + 1024 <= g.lds_per_block;
 }
 
@@ -1387,16 +1434,18 @@ hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *b
   const int64_t words_upper = g.nU > 0 ? ((int64_t)g.nU - 1) / 32 + 1 : 0;
   const int64_t words_lower = g.nL > 0 ? ((g.n - 1) >> 5) - (g.nU >> 5) + 1 : 0;
   const bool use_lds = pull_uses_lds(g);
-  const size_t dyn = use_lds ? (size_t)(4 * std::max(words_upper, words_lower)) : 0;
+  const size_t dyn = use_lds ? (size_t)(4 * (std::max(words_upper, words_lower) + 4)) : 0;
   const int64_t total_entries = 2 * g.m;
+  const int grid = g.cu_count;
+  const int32_t *bounds = g.pull_bounds_grid == grid ? g.pull_bounds : nullptr;
   if (use_lds)
-    pull_round_kernel<true><<<g.cu_count, kPullBlock, dyn, s>>>(
+    pull_round_kernel<true><<<grid, kPullBlock, dyn, s>>>(
         a, bits, g.deg0, g.n, scan_grid(g), g.pull_mode, 1, total_entries, g.npieces,
-        g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0);
+        g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds);
   else
-    pull_round_kernel<false><<<g.cu_count, kPullBlock, dyn, s>>>(
+    pull_round_kernel<false><<<grid, kPullBlock, dyn, s>>>(
         a, bits, g.deg0, g.n, scan_grid(g), g.pull_mode, 0, total_entries, g.npieces,
-        g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0);
+        g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds);
   return hipGetLastError();
 }
 

@@ -299,9 +299,21 @@ __device__ __forceinline__ void grid_sync(PeelState *st, F on_last) {
 
 // Sum over lanes of v[i * stride] for i in [0, count): plain loads spread
 // over the wave (values written before the caller's last acquire).
+// Eight loads per lane are issued before any is added, so the sum takes
+// one memory round trip per 512 values.
 __device__ __forceinline__ int64_t wave_sum_strided(const int64_t *v, int count, int stride) {
+  constexpr int kU = 8;
   int64_t acc = 0;
-  for (int i = lane_id(); i < count; i += kWave) acc += v[(int64_t)i * stride];
+  for (int i0 = 0; i0 < count; i0 += kU * kWave) {
+    int64_t t[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u * kWave + lane_id();
+      t[u] = i < count ? v[(int64_t)i * stride] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) acc += t[u];
+  }
   return wave_sum64(acc);
 }
 
