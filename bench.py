@@ -449,12 +449,25 @@ def main() -> int:
     else:
         push_bytes = 16 * removed + 4 * sum_deg_removed + 8 * m_peeled
         pull_bytes = 0
-    scan_bytes = 8 * n + 4 * int(f0.sum()) + (n // 8 if pulled else 0)
+    # the asynchronous mode scans and resets the workspace in one kernel
+    # that does not queue the frontier: it returns the previous query's
+    # queued items to empty, and a pushed first round queues the frontier
+    # from the bitmap in the pull kernel instead
+    fused_scan = args.peel_mode in (0, 3)
+    n_f0 = int(f0.sum())
+    if fused_scan:
+        queued = removed - n_f0 if pulled else removed
+        scan_bytes = 8 * n + n // 8 + 4 * queued
+        if not pulled:
+            pull_bytes = n // 8 + 4 * n_f0
+    else:
+        scan_bytes = 8 * n + 4 * n_f0 + (n // 8 if pulled else 0)
     pack_bytes = 4 * n + n // 8
     kinfo = {}
     peel_name = {1: "peel_round_kernel<0>", 2: "peel_persistent_kernel<0>"}.get(
         args.peel_mode, "peel_async_kernel<0>")  # <0> = the GCC instantiation
-    names = {0: peel_name, 1: "pull_round_kernel", 2: "scan_gcc_kernel", 3: "pack_kernel",
+    names = {0: peel_name, 1: "pull_round_kernel<true>",
+             2: "scan_reset_gcc_kernel" if fused_scan else "scan_gcc_kernel", 3: "pack_kernel",
              4: "pull_fixup_kernel"}
     # fixup: split rows (more than 64 entries): row id, deg0 and deg read
     fixup_bytes = 12 * int(np.count_nonzero(deg > 64)) if pulled else 0

@@ -285,8 +285,11 @@ hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, bool want_bits,
                            hipStream_t s);
 hipError_t launch_scan_nested(Graph &g, int32_t pU, int32_t pL, int32_t thrU, int32_t thrL,
                               hipStream_t s);
+// queue_f0: the scan did not queue its frontier (launch_scan_reset_gcc);
+// a pushed first round then queues it from the bitmap.
+hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s);
 hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
-                             bool advance = false);
+                             bool advance = false, bool queue_f0 = false);
 // Asynchronous peel fused with the pull round's completion (fix_bits: the
 // scan's survivors, or nullptr when no pull round ran) and the bitmask pack
 // (pack_bits nullable).
@@ -307,7 +310,7 @@ hipError_t launch_scan_component_view(Graph &g, const PeelArgs &a, int32_t x, in
 // place of the separate completion kernel).
 hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
                                   const int32_t *corr_x, const int32_t *corr_d, int ncorr,
-                                  bool advance, hipStream_t s);
+                                  bool advance, hipStream_t s, bool queue_f0 = false);
 hipError_t launch_pull_fixup_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
                                   hipStream_t s);
 hipError_t launch_peel_async_args(Graph &g, PeelKind kind, const PeelArgs &a, int grid,

@@ -247,11 +247,12 @@ abcore_status run_peel(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, hipS
 // bitmask.  In the asynchronous mode the pull round's completion (split
 // rows below their threshold) and the pack run inside the peel kernel.
 abcore_status pull_peel_pack(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, bool pull,
-                             uint32_t *bits, hipStream_t s, int64_t *launches) {
+                             uint32_t *bits, hipStream_t s, int64_t *launches,
+                             bool queue_f0 = false) {
   const bool fused = g.peel_mode == 3;
   if (pull) {
     CHK(timed(g, ABCORE_KERNEL_PULL, s, 1,
-              [&] { return launch_pull_round(g, thrU, thrL, s, fused); }));
+              [&] { return launch_pull_round(g, thrU, thrL, s, fused, queue_f0); }));
     if (!fused)
       CHK(timed(g, ABCORE_KERNEL_FIXUP, s, 1,
                 [&] { return launch_pull_fixup(g, thrU, thrL, s); }));
@@ -757,10 +758,18 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
   int64_t launches = 0;
   if (algo == ABCORE_GCC) {
     const bool pull = g->pull_mode != 1;
-    CHK(launch_init_state(*g, s));
-    CHK(timed(*g, ABCORE_KERNEL_SCAN, s, 1,
-              [&] { return launch_scan_gcc(*g, thrU, thrL, pull, s); }));
-    TRY(pull_peel_pack(*g, kGCC, thrU, thrL, pull, d_bitmask, s, &launches));
+    if (pull && g->peel_mode == 3) {
+      // scan and workspace reset in one launch; the frontier is queued only
+      // if the first round is pushed (by the pull kernel, from the bitmap)
+      CHK(timed(*g, ABCORE_KERNEL_SCAN, s, 1,
+                [&] { return launch_scan_reset_gcc(*g, thrU, thrL, s); }));
+      TRY(pull_peel_pack(*g, kGCC, thrU, thrL, true, d_bitmask, s, &launches, true));
+    } else {
+      CHK(launch_init_state(*g, s));
+      CHK(timed(*g, ABCORE_KERNEL_SCAN, s, 1,
+                [&] { return launch_scan_gcc(*g, thrU, thrL, pull, s); }));
+      TRY(pull_peel_pack(*g, kGCC, thrU, thrL, pull, d_bitmask, s, &launches));
+    }
   } else {
     TRY(compute_core(*g, s));
     const int32_t dl = std::min(thrU, thrL), dq = std::max(thrU, thrL);
@@ -796,7 +805,9 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
     stats->rounds = (g->peel_mode == 3 && !(algo == ABCORE_GCC_PLUS && thrU == thrL)) ? -1
                                                                                      : p.rounds;
     stats->entries_read = entries;
-    stats->initial = p.first;
+    // the scan frontier (its per-workgroup counts; it need not be queued)
+    stats->initial = plus ? p.first : sum_part(*g, kPartF0, s, &st);
+    if (st != ABCORE_OK) return st;
     stats->uncertain = plus ? p.aux0 : 0;
     stats->launches = launches;
     stats->pulled = p.pulled;

@@ -310,6 +310,88 @@ hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, bool want_bits,
   return hipGetLastError();
 }
 
+// The scan fused with the workspace reset, for the asynchronous peel after
+// a pull round: the frontier is not queued here (the pull round counts it
+// out of every surviving row, or queues it from the bitmap when it pushes
+// instead).  Every workgroup first returns its share of the previous
+// computation's queue prefixes to kEmpty and zeroes its partial slots; the
+// last one to finish zeroes the state (all cursors were read by then).
+__global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
+    PeelArgs a, const int32_t *__restrict__ deg0, uint32_t *__restrict__ bits, int64_t n,
+    int keep_word) {
+  __shared__ int64_t s_acc;
+  PeelState *st = a.st;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int j = 0; j < kSub; ++j) {
+    const int64_t t = min(max((int64_t)st->tail[j][0], (int64_t)0), a.qcap);
+    int32_t *q = a.queue + (int64_t)j * a.qcap;
+    for (int64_t i = tid; i < t; i += stride) q[i] = kEmpty;
+  }
+  const int64_t nparts = (int64_t)kMaxBlocks * kPartFields;
+  for (int64_t i = (int64_t)gridDim.x * kPartFields + tid; i < nparts; i += stride) a.part[i] = 0;
+  if (threadIdx.x < kPartFields) a.part[(int64_t)blockIdx.x * kPartFields + threadIdx.x] = 0;
+  __syncthreads();
+  int64_t f0 = 0, f0deg = 0;
+  for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < n;
+       cb += (int64_t)gridDim.x * kScanChunk) {
+    for (int t = 0; t < kScanChunk; t += kScanBlock * 4) {
+      const int64_t x0 = cb + t + (int64_t)threadIdx.x * 4;
+      int32_t d[4] = {0, 0, 0, 0};
+      bool p[4] = {false, false, false, false};
+      if (x0 + 3 < n) {
+        const int4 v = *reinterpret_cast<const int4 *>(deg0 + x0);
+        *reinterpret_cast<int4 *>(a.deg + x0) = v;
+        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) p[j] = d[j] < ((x0 + j) < a.nU ? a.thrU : a.thrL);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t x = x0 + j;
+          if (x < n) {
+            d[j] = deg0[x];
+            a.deg[x] = d[j];
+            p[j] = d[j] < (x < a.nU ? a.thrU : a.thrL);
+          }
+        }
+      }
+      uint32_t alive = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (x0 + j < n) alive |= (uint32_t)(!p[j]) << j;
+        if (p[j]) {
+          f0 += 1;
+          f0deg += d[j];
+        }
+      }
+      // eight consecutive threads hold the 32 vertices of one bitmap word
+      uint32_t w = alive << (4 * (lane_id() & 7));
+      w |= __shfl_xor(w, 1, kWave);
+      w |= __shfl_xor(w, 2, kWave);
+      w |= __shfl_xor(w, 4, kWave);
+      if ((lane_id() & 7) == 0 && x0 < n) bits[x0 / 32] = w;
+    }
+  }
+  add_part(a.part, kPartF0, f0, &s_acc);
+  add_part(a.part, kPartF0Deg, f0deg, &s_acc);
+  __syncthreads();
+  if (wave_in_block() != 0) return;
+  int last = 0;
+  if (lane_id() == 0) last = arrive_on(&st->rst) ? 1 : 0;
+  if (!__shfl(last, 0, kWave)) return;
+  int32_t *words = reinterpret_cast<int32_t *>(st);
+  constexpr int kRstBegin = (int)(offsetof(PeelState, rst) / 4);
+  for (int i = lane_id(); i < kRstBegin; i += kWave)
+    if (i != keep_word) words[i] = 0;
+}
+
+hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s) {
+  PeelArgs a = make_args(g, thrU, thrL);
+  scan_reset_gcc_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, g.deg0, g.alive_bits, g.n, -1);
+  return hipGetLastError();
+}
+
 // Scan of a nested query.  The working degrees hold the final state of a
 // query (pU, pL) that the new query (thrU, thrL) dominates (pU <= thrU and
 // pL <= thrL).  Its core contains the new core (the nesting of cores that
@@ -1217,7 +1299,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     int scan_blocks, int mode, int use_lds, int64_t total_entries, int64_t npieces,
     int64_t npieces_upper, const int32_t *__restrict__ corr_x,
     const int32_t *__restrict__ corr_d, int ncorr, int advance,
-    const int32_t *__restrict__ bounds) {
+    const int32_t *__restrict__ bounds, int queue_f0) {
   extern __shared__ __align__(16) uint32_t s_bits[];
   __shared__ PullShared sh;
   // Each phase walks one layer's rows; its bitmap of the other layer is
@@ -1258,7 +1340,38 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
   }
   if (kLds) stage(0);
   __syncthreads();
-  if (!sh.decide) return;
+  if (!sh.decide) {
+    if (queue_f0) {
+      // the first round is pushed and the scan did not queue its frontier:
+      // queue every vertex of the scan's frontier (bit clear), 32 per lane;
+      // each wave appends its 64 words to a sub-queue of its own choice, so
+      // that the sub-queues receive even shares
+      const int64_t nwords = (n + 31) >> 5;
+      const int waves = blockDim.x / kWave;
+      for (int64_t w0 = ((int64_t)blockIdx.x * waves + wave_in_block()) * kWave; w0 < nwords;
+           w0 += (int64_t)gridDim.x * waves * kWave) {
+        const int64_t w = w0 + lane_id();
+        uint32_t dead = 0;
+        if (w < nwords) {
+          dead = ~gbits[w];
+          const int64_t valid = n - (w << 5);
+          if (valid < 32) dead &= (1u << valid) - 1u;
+        }
+        const int cnt = __popc(dead);
+        const int incl = wave_incl_scan(cnt);
+        const int sub = (int)((w0 / kWave) % kSub);
+        int base = 0;
+        if (lane_id() == kWave - 1 && incl > 0) base = atomicAdd(&a.st->tail[sub][0], incl);
+        int pos = __shfl(base, kWave - 1, kWave) + incl - cnt;
+        int32_t *q = a.queue + (int64_t)sub * a.qcap;
+        while (dead != 0) {
+          q[pos++] = (int32_t)((w << 5) + (__ffs(dead) - 1));
+          dead &= dead - 1;
+        }
+      }
+    }
+    return;
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(&a.st->pulled, 1);
   LocalQueue lq = make_lq(sh.lq[wave_in_block()], kPullLocalQueue, a);
   int32_t *cnt = sh.cnt[wave_in_block()];
@@ -1429,7 +1542,7 @@ bool pull_uses_lds(const Graph &g) {
 
 hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
                                   const int32_t *corr_x, const int32_t *corr_d, int ncorr,
-                                  bool advance, hipStream_t s) {
+                                  bool advance, hipStream_t s, bool queue_f0) {
   if (g.pull_mode == 1) return hipSuccess;
   const int64_t words_upper = g.nU > 0 ? ((int64_t)g.nU - 1) / 32 + 1 : 0;
   const int64_t words_lower = g.nL > 0 ? ((g.n - 1) >> 5) - (g.nU >> 5) + 1 : 0;
@@ -1441,18 +1554,18 @@ hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *b
   if (use_lds)
     pull_round_kernel<true><<<grid, kPullBlock, dyn, s>>>(
         a, bits, g.deg0, g.n, scan_grid(g), g.pull_mode, 1, total_entries, g.npieces,
-        g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds);
+        g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0);
   else
     pull_round_kernel<false><<<grid, kPullBlock, dyn, s>>>(
         a, bits, g.deg0, g.n, scan_grid(g), g.pull_mode, 0, total_entries, g.npieces,
-        g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds);
+        g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
-                             bool advance) {
+                             bool advance, bool queue_f0) {
   return launch_pull_round_args(g, make_args(g, thrU, thrL), g.alive_bits, nullptr, nullptr, 0,
-                                advance, s);
+                                advance, s, queue_f0);
 }
 
 // Must follow the pull round on the same stream (it completes that round).
