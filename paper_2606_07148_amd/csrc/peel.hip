@@ -38,6 +38,21 @@ constexpr int kScanChunk = 4096;  // vertices per workgroup chunk (4 per thread,
 // before its state is reset.
 constexpr int32_t kEmpty = -1;
 
+// Returns the used prefixes [0, tail) of the sub-queues to kEmpty, this
+// thread's share of them.  The cursors are read in one round trip (one lane
+// each), then every prefix is cleared in turn.
+__device__ __forceinline__ void clear_used_queue(int32_t *queue, int64_t qcap,
+                                                 const PeelState *st, int64_t tid,
+                                                 int64_t stride) {
+  const int l = lane_id();
+  const int32_t mine = l < kSub ? st->tail[l][0] : 0;
+  for (int j = 0; j < kSub; ++j) {
+    const int64_t t = min(max((int64_t)__shfl(mine, j, kWave), (int64_t)0), qcap);
+    int32_t *q = queue + (int64_t)j * qcap;
+    for (int64_t i = tid; i < t; i += stride) q[i] = kEmpty;
+  }
+}
+
 // Both steps in one launch: every workgroup clears its share of the used
 // queue prefixes and of the partial sums; the last one to finish (after
 // every workgroup has read the append cursors) zeroes the state.
@@ -45,11 +60,7 @@ __global__ void reset_workspace_kernel(int32_t *queue, int64_t qcap, PeelState *
                                        int64_t *part, int nparts, int keep_word) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int j = 0; j < kSub; ++j) {
-    const int64_t t = min(max((int64_t)st->tail[j][0], (int64_t)0), qcap);
-    int32_t *q = queue + (int64_t)j * qcap;
-    for (int64_t i = tid; i < t; i += stride) q[i] = kEmpty;
-  }
+  clear_used_queue(queue, qcap, st, tid, stride);
   for (int64_t i = tid; i < nparts; i += stride) part[i] = 0;
   // no fence: the cursors were consumed (as loop bounds) before the arrival,
   // and the clearing stores need no order against the state's zeroing (the
@@ -323,11 +334,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
   PeelState *st = a.st;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int j = 0; j < kSub; ++j) {
-    const int64_t t = min(max((int64_t)st->tail[j][0], (int64_t)0), a.qcap);
-    int32_t *q = a.queue + (int64_t)j * a.qcap;
-    for (int64_t i = tid; i < t; i += stride) q[i] = kEmpty;
-  }
+  clear_used_queue(a.queue, a.qcap, st, tid, stride);
   const int64_t nparts = (int64_t)kMaxBlocks * kPartFields;
   for (int64_t i = (int64_t)gridDim.x * kPartFields + tid; i < nparts; i += stride) a.part[i] = 0;
   if (threadIdx.x < kPartFields) a.part[(int64_t)blockIdx.x * kPartFields + threadIdx.x] = 0;
@@ -1304,7 +1311,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
   __shared__ PullShared sh;
   // Each phase walks one layer's rows; its bitmap of the other layer is
   // staged in LDS (kLds) from the 16-byte boundary at or below its first
-  // word, 16 bytes per load.  Phase 0
+  // word.  Phase 0
   // (upper rows) is staged while wave 0 makes the push/pull decision.
   auto stage_base = [&](int phase) -> int64_t { return ((phase == 0 ? a.nU : 0) >> 5) & ~3LL; };
   auto stage = [&](int phase) {
@@ -1312,17 +1319,22 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     const int64_t w1 = nb_hi > nb_lo ? ((nb_hi - 1) >> 5) : (nb_lo >> 5);
     const int64_t a0 = stage_base(phase);
     const int64_t n4 = (w1 + 1 - a0) / 4;  // whole 16-byte groups up to w1
-    const uint4 *src = reinterpret_cast<const uint4 *>(gbits + a0);
-    uint4 *dst = reinterpret_cast<uint4 *>(s_bits);
-    // every workgroup reads the same words: each starts at its own offset so
-    // that the requests of the grid spread over the cache channels (one
-    // 16-byte load in flight per thread: more costs registers the walk needs)
-    const int64_t rot = n4 > 0 ? (int64_t)blockIdx.x * n4 / gridDim.x : 0;
-    for (int64_t i = threadIdx.x; i < n4; i += blockDim.x) {
-      const int64_t j = i + rot < n4 ? i + rot : i + rot - n4;
-      dst[j] = src[j];
+    // direct global-to-LDS loads (lane l fills bytes [16 l, 16 l + 16) of
+    // its wave's 1 KiB chunk), all in flight at once and holding no
+    // registers; every workgroup reads the same words, so each starts at its
+    // own chunk to spread the grid's requests over the cache channels
+    const int64_t nchunks = (n4 + kWave - 1) / kWave;
+    const int64_t rot = nchunks > 0 ? (int64_t)blockIdx.x * nchunks / gridDim.x : 0;
+    for (int64_t c = wave_in_block(); c < nchunks; c += blockDim.x / kWave) {
+      const int64_t cc = c + rot < nchunks ? c + rot : c + rot - nchunks;
+      const int64_t i = cc * kWave + lane_id();
+      if (i < n4)
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void *)(gbits + a0 + 4 * i),
+            (__attribute__((address_space(3))) void *)(s_bits + 4 * cc * kWave), 16, 0, 0);
     }
     for (int64_t i = a0 + 4 * n4 + threadIdx.x; i <= w1; i += blockDim.x) s_bits[i - a0] = gbits[i];
+    __builtin_amdgcn_s_waitcnt(0);  // the loads have landed in LDS (the caller then syncs)
   };
   if (threadIdx.x == 0) {
     sh.next_row = 0;
