@@ -46,6 +46,9 @@ constexpr int32_t kDegIn = 0x7FFFFFFF;
 constexpr int32_t kDegOut = -1;
 // Largest usable threshold: kDegIn must stay above every threshold.
 constexpr int32_t kMaxThreshold = 0x7FFFFFFE;
+// Degree of a removed split row once a consumer has claimed it (far below
+// any degree a vertex reaches by decrements, since degrees stay below 2^30).
+constexpr int32_t kClaimedDeg = -(1 << 30);
 
 // Hierarchical arrival counters: workgroups arrive on their group's line,
 // the last of each group on the top line.

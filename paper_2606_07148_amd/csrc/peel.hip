@@ -665,8 +665,18 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
       int np = 0;
       int32_t pf = 0;
       if (split) {
-        pf = a.piece_first[x];
-        np = (d + kPiece - 1) / kPiece;
+        // After a pull round a split row can be queued twice: by the
+        // decrement that takes it below its threshold and by the start
+        // phase's test of its pull-round count, which may read the degree
+        // after that decrement.  The first consumer marks the degree (the
+        // row is out of the core, its count no longer matters) and walks
+        // the row; a later copy finds the mark and walks nothing.
+        const bool mine = a.fix_bits == nullptr ||
+                          atomicExch(&a.deg[x], kClaimedDeg) > kClaimedDeg / 2;
+        if (mine) {
+          pf = a.piece_first[x];
+          np = (d + kPiece - 1) / kPiece;
+        }
         d = 0;          // walked by its pieces
         first = false;  // the first piece walks the inserted edges
       }
@@ -1417,23 +1427,36 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     const int64_t r1 = bounds != nullptr ? bounds[phase * (G + 1) + k + 1]
                                          : lo + (hi - lo) * (k + 1) / G;
     const int64_t p0 = plo + (phi - plo) * k / G, p1 = plo + (phi - plo) * (k + 1) / G;
-    // rows of at most kPiece entries, 64 consecutive vertices per claim
-    for (;;) {
+    // rows of at most kPiece entries, 64 consecutive vertices per claim; the
+    // offsets and survivor bits of the next claim are loaded before this one
+    // is counted (one memory round trip per claim instead of two)
+    auto claim_rows = [&]() -> int64_t {
       int claim = 0;
       if (lane_id() == 0) claim = atomicAdd(&sh.next_row, kWave);
-      const int64_t b = r0 + __shfl(claim, 0, kWave);
-      if (b >= r1) break;
+      return r0 + __shfl(claim, 0, kWave);
+    };
+    int64_t s_next = 0, e_next = 0;
+    uint32_t w_next = 0;
+    auto fetch_rows = [&](int64_t bb) {
+      const int64_t xi = bb + lane_id();
+      if (xi < r1) {
+        w_next = gbits[xi >> 5];
+        s_next = a.off[xi];
+        e_next = a.off[xi + 1];
+      }
+    };
+    int64_t b = claim_rows();
+    fetch_rows(b);
+    while (b < r1) {
       const int64_t xi = b + lane_id();
       const int32_t x = xi < r1 ? (int32_t)xi : -1;
-      int64_t s = 0;
-      int d = 0;
-      bool alive = false;
-      if (x >= 0) {
-        alive = (gbits[xi >> 5] >> (xi & 31)) & 1u;
-        s = a.off[x];
-        d = (int)(a.off[x + 1] - s);
-        alive = alive && d <= kPiece;  // split rows are counted by their pieces
-      }
+      const int64_t s = s_next;
+      const int d = (int)(e_next - s_next);
+      // split rows are counted by their pieces
+      const bool alive = x >= 0 && ((w_next >> (xi & 31)) & 1u) && d <= kPiece;
+      const int64_t bn = claim_rows();
+      fetch_rows(bn);
+      b = bn;
       int c = 0;
       if (alive && d <= kLightRow) c = count_row_thread(a, lk, lk_base, s, d);
       const bool grouped = alive && d > kLightRow;
