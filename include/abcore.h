@@ -225,7 +225,10 @@ abcore_status abcore_serve_stop(abcore_graph g, int64_t *counters);
  *                          waves take queued vertices as soon as they are
  *                          appended (stats.rounds is then -1).  Modes 2 and 3
  *                          fall back to 1 when the device reports no
- *                          co-residency of the grid.
+ *                          co-residency of the grid.  For core numbers,
+ *                          mode 3 peels level by level (a scan and an
+ *                          asynchronous peel per level) and modes 1 and 2
+ *                          run rounds.
  *   ABCORE_OPT_GRID      : workgroups per peel launch.
  *   ABCORE_OPT_ROUNDS_PER_SYNC : round kernels enqueued between checks.
  *   ABCORE_OPT_TIMING    : 1 = record a HIP event pair on the caller's stream
