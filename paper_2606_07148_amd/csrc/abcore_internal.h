@@ -102,6 +102,7 @@ enum PartField : int {
   kPartF0Deg = 2,     // their degree sum
   kPartKept = 3,      // core decomposition: kept vertices of the last scan
   kPartMin = 4,       // core decomposition: smallest kept degree
+  kPartF1 = 5,        // vertices a pull round found below their threshold
   kPartFields = 8
 };
 
@@ -154,6 +155,7 @@ struct Graph {
   int32_t *queue = nullptr; // kSub sub-queues of qcap entries
   int64_t qcap = 0;
   uint32_t *alive_bits = nullptr;  // n bits: alive after the scan (pull round)
+  uint32_t *row_bits = nullptr;    // n bits: rows a GCC+ pull round counts (uncertain)
   int32_t *list = nullptr;  // n: alive list 0 (core decomposition)
   int32_t *list2 = nullptr; // n: alive list 1
   int64_t *part = nullptr;  // kMaxBlocks * kPartFields
@@ -291,8 +293,15 @@ hipError_t launch_scan_nested(Graph &g, int32_t pU, int32_t pL, int32_t thrU, in
 // queue_f0: the scan did not queue its frontier (launch_scan_reset_gcc);
 // a pushed first round then queues it from the bitmap.
 hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s);
+// GCC+: the classification, fused with the workspace reset, that prepares
+// a pull round (rowbits = g.row_bits, force = true) as its initialisation.
+hipError_t launch_classify_reset(Graph &g, int32_t thrU, int32_t thrL, int32_t dl, int32_t dq,
+                                  hipStream_t s);
+// rowbits: the rows to count (nullptr: the rows whose bit is set in the
+// lookup bitmap); force: pull whatever the pull mode and the frontier.
 hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
-                             bool advance = false, bool queue_f0 = false);
+                             bool advance = false, bool queue_f0 = false,
+                             const uint32_t *rowbits = nullptr, bool force = false);
 // Asynchronous peel fused with the pull round's completion (fix_bits: the
 // scan's survivors, or nullptr when no pull round ran) and the bitmask pack
 // (pack_bits nullable).
@@ -313,7 +322,8 @@ hipError_t launch_scan_component_view(Graph &g, const PeelArgs &a, int32_t x, in
 // place of the separate completion kernel).
 hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
                                   const int32_t *corr_x, const int32_t *corr_d, int ncorr,
-                                  bool advance, hipStream_t s, bool queue_f0 = false);
+                                  bool advance, hipStream_t s, bool queue_f0 = false,
+                                  const uint32_t *rowbits = nullptr, bool force = false);
 hipError_t launch_pull_fixup_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
                                   hipStream_t s);
 hipError_t launch_peel_async_args(Graph &g, PeelKind kind, const PeelArgs &a, int grid,

@@ -135,7 +135,7 @@ void free_graph(Graph *g) {
                   g->core,       g->comp,        g->parent,      g->delta.head,
                   g->delta.next, g->delta.other, g->alive_bits,  g->part,
                   g->piece_row,  g->piece_start, g->piece_first, g->heavy_rows,
-                  g->pull_bounds};
+                  g->pull_bounds, g->row_bits};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   if (g->h_state) (void)hipHostFree(g->h_state);
@@ -248,18 +248,21 @@ abcore_status run_peel(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, hipS
 // rows below their threshold) and the pack run inside the peel kernel.
 abcore_status pull_peel_pack(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, bool pull,
                              uint32_t *bits, hipStream_t s, int64_t *launches,
-                             bool queue_f0 = false) {
+                             bool queue_f0 = false, const uint32_t *rowbits = nullptr,
+                             bool force = false) {
   const bool fused = g.peel_mode == 3;
   if (pull) {
-    CHK(timed(g, ABCORE_KERNEL_PULL, s, 1,
-              [&] { return launch_pull_round(g, thrU, thrL, s, fused, queue_f0); }));
+    CHK(timed(g, ABCORE_KERNEL_PULL, s, 1, [&] {
+      return launch_pull_round(g, thrU, thrL, s, fused, queue_f0, rowbits, force);
+    }));
     if (!fused)
       CHK(timed(g, ABCORE_KERNEL_FIXUP, s, 1,
                 [&] { return launch_pull_fixup(g, thrU, thrL, s); }));
   }
   if (fused) {
     CHK(timed(g, ABCORE_KERNEL_PEEL, s, 1, [&] {
-      return launch_peel_async_fused(g, kind, thrU, thrL, pull ? g.alive_bits : nullptr, bits,
+      return launch_peel_async_fused(g, kind, thrU, thrL,
+                                     pull ? (rowbits ? rowbits : g.alive_bits) : nullptr, bits,
                                      s);
     }));
     *launches += 1;
@@ -560,6 +563,7 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
       break;
     }
     if ((st = ensure(&g->alive_bits, (g->n + 31) / 32 + 1)) != ABCORE_OK) break;
+    if ((st = ensure(&g->row_bits, (g->n + 31) / 32 + 1)) != ABCORE_OK) break;
     if ((st = ensure(&g->part, (int64_t)kMaxBlocks * kPartFields)) != ABCORE_OK) break;
     hipError_t e = hipMalloc(&g->state, sizeof(PeelState));
     // the state is read (queue tails) by the first initialisation: zero it
@@ -756,6 +760,7 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
   hipStream_t s = as_stream(stream);
   const int32_t thrU = clamp_thr(alpha), thrL = clamp_thr(beta);
   int64_t launches = 0;
+  bool plus_pull = false;  // GCC+ initialised by a pull round
   if (algo == ABCORE_GCC) {
     const bool pull = g->pull_mode != 1;
     if (pull && g->peel_mode == 3) {
@@ -773,9 +778,17 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
   } else {
     TRY(compute_core(*g, s));
     const int32_t dl = std::min(thrU, thrL), dq = std::max(thrU, thrL);
-    CHK(launch_init_state(*g, s));
+    plus_pull = dl != dq && g->peel_mode == 3 && g->pull_mode != 1;
+    if (!plus_pull) CHK(launch_init_state(*g, s));
     if (dl == dq) {
       CHK(launch_pack_from_core(*g, dl, d_bitmask, s));
+    } else if (plus_pull) {
+      // the uncertain rows' degrees inside G[{core >= delta_l}] by a pull
+      // round over LDS-staged bitmaps, then the asynchronous peel
+      CHK(timed(*g, ABCORE_KERNEL_SCAN, s, 1,
+                [&] { return launch_classify_reset(*g, thrU, thrL, dl, dq, s); }));
+      TRY(pull_peel_pack(*g, kGCCPlus, thrU, thrL, true, d_bitmask, s, &launches, false,
+                         g->row_bits, true));
     } else {
       CHK(launch_classify(*g, dl, dq, s));
       CHK(launch_restricted_init(*g, thrU, thrL, dl, s));
@@ -805,10 +818,18 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
     stats->rounds = (g->peel_mode == 3 && !(algo == ABCORE_GCC_PLUS && thrU == thrL)) ? -1
                                                                                      : p.rounds;
     stats->entries_read = entries;
-    // the scan frontier (its per-workgroup counts; it need not be queued)
-    stats->initial = plus ? p.first : sum_part(*g, kPartF0, s, &st);
+    // GCC: the scan frontier (its per-workgroup counts; it need not be
+    // queued).  GCC+: the uncertain vertices below their threshold after the
+    // initialisation, and the uncertain count.
+    if (!plus)
+      stats->initial = sum_part(*g, kPartF0, s, &st);
+    else if (plus_pull)
+      stats->initial = sum_part(*g, kPartF1, s, &st);
+    else
+      stats->initial = p.first;
     if (st != ABCORE_OK) return st;
-    stats->uncertain = plus ? p.aux0 : 0;
+    stats->uncertain = !plus ? 0 : (plus_pull ? sum_part(*g, kPartF0, s, &st) : p.aux0);
+    if (st != ABCORE_OK) return st;
     stats->launches = launches;
     stats->pulled = p.pulled;
   }

@@ -977,6 +977,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
   const int waves = blockDim.x / kWave;
   const int gw = blockIdx.x * waves + wave_in_block();
   const int nw = gridDim.x * waves;
+  int64_t fixed = 0;  // split rows the start phase queued
   if (a.start_expect > 0) {
     // start phase: after a pull round, the split rows below their threshold
     // (their pieces' counts are complete at the kernel boundary)
@@ -988,6 +989,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
         if (i < a.nfix) x = a.fix_rows[i];
         if (x >= 0 && ((a.fix_bits[x >> 5] >> (x & 31)) & 1u))
           push = a.deg[x] < (x < a.nU ? a.thrU : a.thrL);
+        fixed += push ? 1 : 0;
         lq.push(push, x);
       }
     }
@@ -1096,6 +1098,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
     }
   }
   add_part(a.part, kPartEntries, entries, &s_acc);
+  add_part(a.part, kPartF1, fixed, &s_acc);
   if (KIND == kKCore && threadIdx.x < kSub) {
     // everything appended so far is processed: the next level's scan starts
     // its range here (every workgroup writes the same final cursors)
@@ -1316,7 +1319,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     int scan_blocks, int mode, int use_lds, int64_t total_entries, int64_t npieces,
     int64_t npieces_upper, const int32_t *__restrict__ corr_x,
     const int32_t *__restrict__ corr_d, int ncorr, int advance,
-    const int32_t *__restrict__ bounds, int queue_f0) {
+    const int32_t *__restrict__ bounds, int queue_f0, const uint32_t *__restrict__ rowbits) {
   extern __shared__ __align__(16) uint32_t s_bits[];
   __shared__ PullShared sh;
   // Each phase walks one layer's rows; its bitmap of the other layer is
@@ -1398,7 +1401,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
   LocalQueue lq = make_lq(sh.lq[wave_in_block()], kPullLocalQueue, a);
   int32_t *cnt = sh.cnt[wave_in_block()];
   ChunkDesc *desc = sh.desc[wave_in_block()];
-  int64_t entries = 0;
+  int64_t entries = 0, f1 = 0;
   for (int phase = 0; phase < 2; ++phase) {
     // phase 0: upper rows (neighbours are lower ids), phase 1: lower rows
     const int64_t lo = phase == 0 ? 0 : a.nU, hi = phase == 0 ? a.nU : n;
@@ -1440,7 +1443,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     auto fetch_rows = [&](int64_t bb) {
       const int64_t xi = bb + lane_id();
       if (xi < r1) {
-        w_next = gbits[xi >> 5];
+        w_next = rowbits[xi >> 5];
         s_next = a.off[xi];
         e_next = a.off[xi + 1];
       }
@@ -1468,6 +1471,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
         if (a.ins_head != nullptr) c += delta_alive(a, gbits, x, entries);
         a.deg[x] = c;
         push = c < (x < a.nU ? a.thrU : a.thrL);
+        f1 += push ? 1 : 0;
       }
       lq.push(push, x);
       __builtin_amdgcn_wave_barrier();
@@ -1488,7 +1492,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
         row = a.piece_row[pi];
         s = a.piece_start[pi];
         const int64_t rs = a.off[row], re = a.off[row + 1];
-        alive = (gbits[row >> 5] >> (row & 31)) & 1u;
+        alive = (rowbits[row >> 5] >> (row & 31)) & 1u;
         d = (int)(min(s + kPiece, re) - s);
         first = s == rs;
       }
@@ -1524,6 +1528,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
   }
   block_flush(lq, sh.s_cnt);
   add_part(a.part, kPartEntries, entries, &sh.acc);
+  add_part(a.part, kPartF1, f1, &sh.acc);
   if (advance && last_block_done<false>(a.st)) {
     advance_round_wave(a.st);
     if (lane_id() == 0) atomicAdd((unsigned long long *)&a.st->launches, 1ull);
@@ -1577,8 +1582,11 @@ bool pull_uses_lds(const Graph &g) {
 
 hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
                                   const int32_t *corr_x, const int32_t *corr_d, int ncorr,
-                                  bool advance, hipStream_t s, bool queue_f0) {
-  if (g.pull_mode == 1) return hipSuccess;
+                                  bool advance, hipStream_t s, bool queue_f0,
+                                  const uint32_t *rowbits, bool force) {
+  if (g.pull_mode == 1 && !force) return hipSuccess;
+  const int mode = force ? 2 : g.pull_mode;
+  if (rowbits == nullptr) rowbits = bits;
   const int64_t words_upper = g.nU > 0 ? ((int64_t)g.nU - 1) / 32 + 1 : 0;
   const int64_t words_lower = g.nL > 0 ? ((g.n - 1) >> 5) - (g.nU >> 5) + 1 : 0;
   const bool use_lds = pull_uses_lds(g);
@@ -1588,19 +1596,21 @@ hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *b
   const int32_t *bounds = g.pull_bounds_grid == grid ? g.pull_bounds : nullptr;
   if (use_lds)
     pull_round_kernel<true><<<grid, kPullBlock, dyn, s>>>(
-        a, bits, g.deg0, g.n, scan_grid(g), g.pull_mode, 1, total_entries, g.npieces,
-        g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0);
+        a, bits, g.deg0, g.n, scan_grid(g), mode, 1, total_entries, g.npieces,
+        g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0,
+        rowbits);
   else
     pull_round_kernel<false><<<grid, kPullBlock, dyn, s>>>(
-        a, bits, g.deg0, g.n, scan_grid(g), g.pull_mode, 0, total_entries, g.npieces,
-        g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0);
+        a, bits, g.deg0, g.n, scan_grid(g), mode, 0, total_entries, g.npieces,
+        g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0,
+        rowbits);
   return hipGetLastError();
 }
 
 hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
-                             bool advance, bool queue_f0) {
+                             bool advance, bool queue_f0, const uint32_t *rowbits, bool force) {
   return launch_pull_round_args(g, make_args(g, thrU, thrL), g.alive_bits, nullptr, nullptr, 0,
-                                advance, s, queue_f0);
+                                advance, s, queue_f0, rowbits, force);
 }
 
 // Must follow the pull round on the same stream (it completes that round).
@@ -1724,6 +1734,102 @@ __global__ __launch_bounds__(kScanBlock) void classify_kernel(PeelArgs a, int64_
 hipError_t launch_classify(Graph &g, int32_t dl, int32_t dq, hipStream_t s) {
   PeelArgs a = make_args(g, 0, 0);
   classify_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, g.n, dl, dq);
+  return hipGetLastError();
+}
+
+// The same classification for the asynchronous peel, fused with the
+// workspace reset (as the GCC scan): nothing is queued.  An uncertain vertex
+// whose whole degree is already below its threshold is out as well
+// (Algorithm 1's scan).  It writes the degrees the pull round starts from
+// (out, in, or deg0 for an uncertain vertex, whose row the pull round
+// recounts), the bitmap of the vertices not known to be out ({core >=
+// delta_l} less the scan frontier: Algorithm 2's uncertain vertices count
+// only neighbours with core >= delta_l, and a neighbour below its threshold
+// is removed at once), the bitmap of the remaining uncertain vertices (the
+// rows the pull round counts) and the number of uncertain vertices (Lemma
+// 1's classes) per workgroup.
+__global__ __launch_bounds__(kScanBlock) void classify_reset_kernel(
+    PeelArgs a, const int32_t *__restrict__ deg0, uint32_t *__restrict__ hbits,
+    uint32_t *__restrict__ ubits, int64_t n, int32_t dl, int32_t dq) {
+  __shared__ int64_t s_acc;
+  PeelState *st = a.st;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  clear_used_queue(a.queue, a.qcap, st, tid, stride);
+  const int64_t nparts = (int64_t)kMaxBlocks * kPartFields;
+  for (int64_t i = (int64_t)gridDim.x * kPartFields + tid; i < nparts; i += stride) a.part[i] = 0;
+  if (threadIdx.x < kPartFields) a.part[(int64_t)blockIdx.x * kPartFields + threadIdx.x] = 0;
+  __syncthreads();
+  int64_t nunc = 0;
+  for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < n;
+       cb += (int64_t)gridDim.x * kScanChunk) {
+    for (int t = 0; t < kScanChunk; t += kScanBlock * 4) {
+      const int64_t x0 = cb + t + (int64_t)threadIdx.x * 4;
+      int32_t c[4] = {0, 0, 0, 0}, d0[4] = {0, 0, 0, 0};
+      const bool full = x0 + 3 < n;
+      if (full) {
+        const int4 v = *reinterpret_cast<const int4 *>(a.core + x0);
+        const int4 e = *reinterpret_cast<const int4 *>(deg0 + x0);
+        c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+        d0[0] = e.x; d0[1] = e.y; d0[2] = e.z; d0[3] = e.w;
+      } else {
+        for (int j = 0; j < 4; ++j)
+          if (x0 + j < n) {
+            c[j] = a.core[x0 + j];
+            d0[j] = deg0[x0 + j];
+          }
+      }
+      int32_t dv[4];
+      uint32_t h = 0, u = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool valid = x0 + j < n;
+        const int32_t th = (x0 + j) < a.nU ? a.thrU : a.thrL;
+        const bool unc = valid && c[j] >= dl && c[j] < dq;
+        const bool counted = unc && d0[j] >= th;
+        // (a certain member has deg0 >= core >= delta_q >= its threshold)
+        dv[j] = c[j] >= dq ? kDegIn : (counted ? d0[j] : kDegOut);
+        h |= (uint32_t)(valid && c[j] >= dl && d0[j] >= th) << j;
+        u |= (uint32_t)counted << j;
+        nunc += unc ? 1 : 0;
+      }
+      if (full) {
+        *reinterpret_cast<int4 *>(a.deg + x0) = make_int4(dv[0], dv[1], dv[2], dv[3]);
+      } else {
+        for (int j = 0; j < 4; ++j)
+          if (x0 + j < n) a.deg[x0 + j] = dv[j];
+      }
+      // eight consecutive threads hold the 32 vertices of one bitmap word
+      h <<= 4 * (lane_id() & 7);
+      u <<= 4 * (lane_id() & 7);
+      h |= __shfl_xor(h, 1, kWave);
+      u |= __shfl_xor(u, 1, kWave);
+      h |= __shfl_xor(h, 2, kWave);
+      u |= __shfl_xor(u, 2, kWave);
+      h |= __shfl_xor(h, 4, kWave);
+      u |= __shfl_xor(u, 4, kWave);
+      if ((lane_id() & 7) == 0 && x0 < n) {
+        hbits[x0 / 32] = h;
+        ubits[x0 / 32] = u;
+      }
+    }
+  }
+  add_part(a.part, kPartF0, nunc, &s_acc);
+  __syncthreads();
+  if (wave_in_block() != 0) return;
+  int last = 0;
+  if (lane_id() == 0) last = arrive_on(&st->rst) ? 1 : 0;
+  if (!__shfl(last, 0, kWave)) return;
+  int32_t *words = reinterpret_cast<int32_t *>(st);
+  constexpr int kRstBegin = (int)(offsetof(PeelState, rst) / 4);
+  for (int i = lane_id(); i < kRstBegin; i += kWave) words[i] = 0;
+}
+
+hipError_t launch_classify_reset(Graph &g, int32_t thrU, int32_t thrL, int32_t dl, int32_t dq,
+                                  hipStream_t s) {
+  PeelArgs a = make_args(g, thrU, thrL);
+  classify_reset_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, g.deg0, g.alive_bits, g.row_bits,
+                                                            g.n, dl, dq);
   return hipGetLastError();
 }
 
