@@ -510,6 +510,26 @@ def main() -> int:
         gcc_plus = {"ms_per_query": plus_ms, "parity": plus_parity,
                     "edges_peeled_per_s": m_peeled / (plus_ms / 1e3),
                     "core_preprocessing_ms": prep_ms, "max_core": max_core}
+        # Algorithm 2 with alpha != beta (uncertain vertices are peeled),
+        # against GCC on the same pairs; both results must agree bit for bit
+        asym = []
+        for (pa, pb) in ((5, 20), (40, 8)):
+            row = {"alpha": pa, "beta": pb}
+            res = {}
+            for name, algo in (("gcc", pkg.ABCORE_GCC), ("gcc_plus", pkg.ABCORE_GCC_PLUS)):
+                for _ in range(args.warmup):
+                    pkg.abcore_compute(g, pa, pb, algo, out=out)
+                torch.cuda.synchronize()
+                res[name] = out.clone()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    pkg.abcore_compute(g, pa, pb, algo, out=out)
+                torch.cuda.synchronize()
+                row[name + "_ms"] = (time.perf_counter() - t0) * 1e3 / args.steps
+            row["equal"] = bool(torch.equal(res["gcc"], res["gcc_plus"]))
+            plus_parity = plus_parity and row["equal"]
+            asym.append(row)
+        gcc_plus["asymmetric"] = asym
 
     batch = None
     if not args.no_batch:
