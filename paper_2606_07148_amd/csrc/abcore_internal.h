@@ -103,6 +103,7 @@ enum PartField : int {
   kPartKept = 3,      // core decomposition: kept vertices of the last scan
   kPartMin = 4,       // core decomposition: smallest kept degree
   kPartF1 = 5,        // vertices a pull round found below their threshold
+  kPartRest = 6,      // nested scan: entries of the rows that survive it
   kPartFields = 8
 };
 
@@ -171,6 +172,9 @@ struct Graph {
   int32_t *piece_row = nullptr;    // npieces
   int64_t *piece_start = nullptr;  // npieces: absolute position in cols
   int32_t *piece_first = nullptr;  // n: first piece of a split row, else -1
+  // At the slot of a split row's first piece: the degree a nested scan left
+  // in place for a pull round to replace (npieces).
+  int32_t *split_written = nullptr;
   int32_t *heavy_rows = nullptr;   // nheavy: the split rows, ascending
   int64_t npieces = 0, npieces_upper = 0;
   int64_t nheavy = 0, nheavy_upper = 0;
@@ -288,8 +292,13 @@ hipError_t launch_init_workspace(Graph &g, int32_t *queue, PeelState *state, int
                                  hipStream_t s, bool keep_abort = false);
 hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, bool want_bits,
                            hipStream_t s);
+// bits (nullable): also writes the survivor bitmap, the partial sums and the
+// surviving split rows' degrees (g.split_written) a pull round needs
+// (rest_part in the pull then compares the frontier's degrees with the
+// survivors' row entries, and written_snap replaces deg0 as what the
+// split rows' pieces subtract).
 hipError_t launch_scan_nested(Graph &g, int32_t pU, int32_t pL, int32_t thrU, int32_t thrL,
-                              hipStream_t s);
+                              hipStream_t s, uint32_t *bits = nullptr);
 // queue_f0: the scan did not queue its frontier (launch_scan_reset_gcc);
 // a pushed first round then queues it from the bitmap.
 hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s);
@@ -299,9 +308,11 @@ hipError_t launch_classify_reset(Graph &g, int32_t thrU, int32_t thrL, int32_t d
                                   hipStream_t s);
 // rowbits: the rows to count (nullptr: the rows whose bit is set in the
 // lookup bitmap); force: pull whatever the pull mode and the frontier.
+// rest_part: the pull cost is the scan's kPartRest sums (nested scans).
 hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
                              bool advance = false, bool queue_f0 = false,
-                             const uint32_t *rowbits = nullptr, bool force = false);
+                             const uint32_t *rowbits = nullptr, bool force = false,
+                             bool rest_part = false);
 // Asynchronous peel fused with the pull round's completion (fix_bits: the
 // scan's survivors, or nullptr when no pull round ran) and the bitmask pack
 // (pack_bits nullable).
@@ -323,7 +334,8 @@ hipError_t launch_scan_component_view(Graph &g, const PeelArgs &a, int32_t x, in
 hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
                                   const int32_t *corr_x, const int32_t *corr_d, int ncorr,
                                   bool advance, hipStream_t s, bool queue_f0 = false,
-                                  const uint32_t *rowbits = nullptr, bool force = false);
+                                  const uint32_t *rowbits = nullptr, bool force = false,
+                                  bool rest_part = false);
 hipError_t launch_pull_fixup_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
                                   hipStream_t s);
 hipError_t launch_peel_async_args(Graph &g, PeelKind kind, const PeelArgs &a, int grid,

@@ -135,7 +135,7 @@ void free_graph(Graph *g) {
                   g->core,       g->comp,        g->parent,      g->delta.head,
                   g->delta.next, g->delta.other, g->alive_bits,  g->part,
                   g->piece_row,  g->piece_start, g->piece_first, g->heavy_rows,
-                  g->pull_bounds, g->row_bits};
+                  g->pull_bounds, g->row_bits,    g->split_written};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   if (g->h_state) (void)hipHostFree(g->h_state);
@@ -249,11 +249,11 @@ abcore_status run_peel(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, hipS
 abcore_status pull_peel_pack(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, bool pull,
                              uint32_t *bits, hipStream_t s, int64_t *launches,
                              bool queue_f0 = false, const uint32_t *rowbits = nullptr,
-                             bool force = false) {
+                             bool force = false, bool rest_part = false) {
   const bool fused = g.peel_mode == 3;
   if (pull) {
     CHK(timed(g, ABCORE_KERNEL_PULL, s, 1, [&] {
-      return launch_pull_round(g, thrU, thrL, s, fused, queue_f0, rowbits, force);
+      return launch_pull_round(g, thrU, thrL, s, fused, queue_f0, rowbits, force, rest_part);
     }));
     if (!fused)
       CHK(timed(g, ABCORE_KERNEL_FIXUP, s, 1,
@@ -375,8 +375,11 @@ abcore_status run_batch(Graph &g, const BatchPlan &plan, const int32_t *tu, cons
         CHK(hipMemcpyAsync(g.deg, g.slots[plan.slot[p]], sizeof(int32_t) * g.n,
                            hipMemcpyDeviceToDevice, s));
       CHK(launch_init_state(g, s, true));
-      CHK(launch_scan_nested(g, tu[p], tl[p], tu[i], tl[i], s));
-      TRY(pull_peel_pack(g, kGCC, tu[i], tl[i], false, out, s, &launches));
+      // a pull round over the parent's survivors when the frontier is heavy
+      // (decided on the device from the scan's sums)
+      CHK(launch_scan_nested(g, tu[p], tl[p], tu[i], tl[i], s, pull ? g.alive_bits : nullptr));
+      TRY(pull_peel_pack(g, kGCC, tu[i], tl[i], pull, out, s, &launches, false, nullptr, false,
+                         true));
     }
   }
   return ABCORE_OK;

@@ -280,6 +280,7 @@ abcore_status build_pieces(Graph &g, hipStream_t s) {
   PCHK(hipMalloc(&g.piece_start, sizeof(int64_t) * std::max<int64_t>(g.npieces, 1)));
   PCHK(hipMalloc(&g.piece_first, sizeof(int32_t) * std::max<int64_t>(g.n, 1)));
   PCHK(hipMalloc(&g.heavy_rows, sizeof(int32_t) * std::max<int64_t>(g.nheavy, 1)));
+  PCHK(hipMalloc(&g.split_written, sizeof(int32_t) * std::max<int64_t>(g.npieces, 1)));
   fill_pieces_kernel<<<grid, 256, 0, s>>>(g.off, g.n, first, hfirst, g.piece_row, g.piece_start,
                                           g.piece_first, g.heavy_rows);
   PCHK(hipGetLastError());

@@ -406,16 +406,24 @@ hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream
 // inside it: every removed neighbour decremented it once (the filter never
 // skips a vertex at or above its threshold).  Vertices the earlier query
 // removed hold degrees below their old threshold and stay out; survivors
-// below the new threshold form the frontier.
+// below the new threshold form the frontier.  With bits, the scan also
+// prepares a pull round: the bitmap of the survivors, the frontier's degree
+// sum (what pushing it costs), the survivors' row entries (what pulling
+// costs) and, for a surviving split row, the degree it leaves in place (its
+// pieces recount the row from scratch and subtract that degree once; a
+// pushed round keeps it).
 __global__ __launch_bounds__(kScanBlock) void scan_nested_kernel(PeelArgs a, int32_t pU,
-                                                                 int32_t pL, int64_t n) {
+                                                                 int32_t pL, int64_t n,
+                                                                 const int32_t *__restrict__ deg0,
+                                                                 uint32_t *__restrict__ bits,
+                                                                 int32_t *__restrict__ written) {
   __shared__ ScanCollector col;
   __shared__ int64_t s_acc;
   if (threadIdx.x == 0) col.count = 0;
   __syncthreads();
   const int sub = blockIdx.x % kSub;
   int32_t *q = a.queue + (int64_t)sub * a.qcap;
-  int64_t f0 = 0;
+  int64_t f0 = 0, f0deg = 0, rest = 0;
   for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < n;
        cb += (int64_t)gridDim.x * kScanChunk) {
     for (int t = 0; t < kScanChunk; t += kScanBlock * 4) {
@@ -430,11 +438,32 @@ __global__ __launch_bounds__(kScanBlock) void scan_nested_kernel(PeelArgs a, int
       }
       int32_t items[4];
       int cnt = 0;
+      uint32_t alive = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const bool up = (x0 + j) < a.nU;
-        if (x0 + j < n && d[j] >= (up ? pU : pL) && d[j] < (up ? a.thrU : a.thrL))
+        const bool stays = x0 + j < n && d[j] >= (up ? a.thrU : a.thrL);
+        if (x0 + j < n && d[j] >= (up ? pU : pL) && !stays) {
           items[cnt++] = (int32_t)(x0 + j);
+          f0deg += d[j];
+        }
+        alive |= (uint32_t)stays << j;
+      }
+      if (bits != nullptr) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if ((alive >> j) & 1u) {
+            const int32_t d0 = deg0[x0 + j];
+            rest += d0;
+            if (d0 > kPiece) written[a.piece_first[x0 + j]] = d[j];
+          }
+        }
+        // eight consecutive threads hold the 32 vertices of one bitmap word
+        uint32_t w = alive << (4 * (lane_id() & 7));
+        w |= __shfl_xor(w, 1, kWave);
+        w |= __shfl_xor(w, 2, kWave);
+        w |= __shfl_xor(w, 4, kWave);
+        if ((lane_id() & 7) == 0 && x0 < n) bits[x0 / 32] = w;
       }
       f0 += cnt;
       col.append(items, cnt);
@@ -442,13 +471,18 @@ __global__ __launch_bounds__(kScanBlock) void scan_nested_kernel(PeelArgs a, int
     col.flush(q, &a.st->tail[sub][0]);
   }
   add_part(a.part, kPartF0, f0, &s_acc);
+  if (bits != nullptr) {
+    add_part(a.part, kPartF0Deg, f0deg, &s_acc);
+    add_part(a.part, kPartRest, rest, &s_acc);
+  }
   if (last_block_done<false>(a.st)) start_rounds_wave(a.st);
 }
 
 hipError_t launch_scan_nested(Graph &g, int32_t pU, int32_t pL, int32_t thrU, int32_t thrL,
-                              hipStream_t s) {
+                              hipStream_t s, uint32_t *bits) {
   PeelArgs a = make_args(g, thrU, thrL);
-  scan_nested_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, pU, pL, g.n);
+  scan_nested_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, pU, pL, g.n, g.deg0, bits,
+                                                         g.split_written);
   return hipGetLastError();
 }
 
@@ -1319,7 +1353,8 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     int scan_blocks, int mode, int use_lds, int64_t total_entries, int64_t npieces,
     int64_t npieces_upper, const int32_t *__restrict__ corr_x,
     const int32_t *__restrict__ corr_d, int ncorr, int advance,
-    const int32_t *__restrict__ bounds, int queue_f0, const uint32_t *__restrict__ rowbits) {
+    const int32_t *__restrict__ bounds, int queue_f0, const uint32_t *__restrict__ rowbits,
+    int rest_part, const int32_t *__restrict__ written_snap) {
   extern __shared__ __align__(16) uint32_t s_bits[];
   __shared__ PullShared sh;
   // Each phase walks one layer's rows; its bitmap of the other layer is
@@ -1356,7 +1391,8 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
   if (wave_in_block() == 0) {
     // the scan's frontier degree sum, from its per-workgroup slots
     const int64_t f0deg = wave_sum_strided(a.part + kPartF0Deg, scan_blocks, kPartFields);
-    const int64_t rest = total_entries - f0deg;
+    const int64_t rest = rest_part ? wave_sum_strided(a.part + kPartRest, scan_blocks, kPartFields)
+                                   : total_entries - f0deg;
     // pull pays one streaming read per surviving entry instead of one atomic
     // per frontier entry: worth it when the frontier carries a sizeable share
     const bool pull = mode == 2 || (mode == 0 && f0deg > 0 &&
@@ -1503,8 +1539,9 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
         c = cnt[lane_id()];
         if (first) {
           if (a.ins_head != nullptr) c += delta_alive(a, gbits, row, entries);
-          // the scan wrote deg[row] = deg0[row] (plus the view's correction)
-          int32_t written = deg0[row];
+          // the scan wrote deg[row] = deg0[row] (plus the view's correction),
+          // or a nested scan left the degree recorded at the first piece
+          int32_t written = written_snap != nullptr ? written_snap[pi] : deg0[row];
           for (int i = 0; i < ncorr; ++i)
             if (corr_x[i] == row) written += corr_d[i];
           c -= written;
@@ -1583,7 +1620,7 @@ bool pull_uses_lds(const Graph &g) {
 hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
                                   const int32_t *corr_x, const int32_t *corr_d, int ncorr,
                                   bool advance, hipStream_t s, bool queue_f0,
-                                  const uint32_t *rowbits, bool force) {
+                                  const uint32_t *rowbits, bool force, bool rest_part) {
   if (g.pull_mode == 1 && !force) return hipSuccess;
   const int mode = force ? 2 : g.pull_mode;
   if (rowbits == nullptr) rowbits = bits;
@@ -1598,19 +1635,20 @@ hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *b
     pull_round_kernel<true><<<grid, kPullBlock, dyn, s>>>(
         a, bits, g.deg0, g.n, scan_grid(g), mode, 1, total_entries, g.npieces,
         g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0,
-        rowbits);
+        rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr);
   else
     pull_round_kernel<false><<<grid, kPullBlock, dyn, s>>>(
         a, bits, g.deg0, g.n, scan_grid(g), mode, 0, total_entries, g.npieces,
         g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0,
-        rowbits);
+        rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
-                             bool advance, bool queue_f0, const uint32_t *rowbits, bool force) {
+                             bool advance, bool queue_f0, const uint32_t *rowbits, bool force,
+                             bool rest_part) {
   return launch_pull_round_args(g, make_args(g, thrU, thrL), g.alive_bits, nullptr, nullptr, 0,
-                                advance, s, queue_f0, rowbits, force);
+                                advance, s, queue_f0, rowbits, force, rest_part);
 }
 
 // Must follow the pull round on the same stream (it completes that round).
