@@ -204,6 +204,8 @@ def bench_serve(args, pkg, torch, np, bigraph_gen) -> dict:
             seq.append((e.name, None, None))
         t_seq.append(time.perf_counter() - t1)
     seq_qps = total / sum(t_seq)
+    if args.serve_pull:
+        pkg.abcore_set_option(g_srv, pkg.ABCORE_OPT_PULL, args.serve_pull)
     pkg.abcore_serve_start(g_srv, args.serve_inflight, args.serve_slots, 0)
     phases = []
     served = []
@@ -334,6 +336,8 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-slots", type=int, default=2)
     ap.add_argument("--serve-inflight", type=int, default=64)
+    ap.add_argument("--serve-pull", type=int, default=0,
+                    help="ABCORE_OPT_PULL of the served handle (0 = default)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device copy of MIB MiB (hardware-counter scale)")
     args = ap.parse_args()
