@@ -464,17 +464,29 @@ def main() -> int:
         scan_bytes = 8 * n + n // 8 + 4 * queued
         if not pulled:
             pull_bytes = n // 8 + 4 * n_f0
+        else:
+            # on an unchanged graph the pull round counts on the degree-rank
+            # copy: a row of at most 64 entries is read whole, a split row is
+            # searched (16 probes of 4 B in about four steps) and completed
+            # at once; the survivor bits are read, no bitmap is staged
+            light = a1 & (deg <= 64)
+            heavy = a1 & (deg > 64)
+            pull_bytes = (20 * int(light.sum()) + 4 * int(deg[light].sum())
+                          + (24 + 4 * 16 * 4) * int(heavy.sum()) + n // 8)
     else:
         scan_bytes = 8 * n + 4 * n_f0 + (n // 8 if pulled else 0)
     pack_bytes = 4 * n + n // 8
     kinfo = {}
     peel_name = {1: "peel_round_kernel<0>", 2: "peel_persistent_kernel<0>"}.get(
         args.peel_mode, "peel_async_kernel<0>")  # <0> = the GCC instantiation
-    names = {0: peel_name, 1: "pull_round_kernel<true>",
+    # the degree-rank pull round stages no bitmap: the kLds = false build
+    names = {0: peel_name, 1: "pull_round_kernel<false>" if (fused_scan and pulled)
+             else "pull_round_kernel<true>",
              2: "scan_reset_gcc_kernel" if fused_scan else "scan_gcc_kernel", 3: "pack_kernel",
              4: "pull_fixup_kernel"}
     # fixup: split rows (more than 64 entries): row id, deg0 and deg read
-    fixup_bytes = 12 * int(np.count_nonzero(deg > 64)) if pulled else 0
+    # (none after a degree-rank pull round, which completes them itself)
+    fixup_bytes = 12 * int(np.count_nonzero(deg > 64)) if pulled and not fused_scan else 0
     kbytes = {0: push_bytes, 1: pull_bytes, 2: scan_bytes, 3: pack_bytes, 4: fixup_bytes}
     # the asynchronous peel runs the pack and the pull round's completion
     # itself (no separate launches): its bytes include theirs

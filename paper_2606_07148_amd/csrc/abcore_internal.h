@@ -104,7 +104,9 @@ enum PartField : int {
   kPartMin = 4,       // core decomposition: smallest kept degree
   kPartF1 = 5,        // vertices a pull round found below their threshold
   kPartRest = 6,      // nested scan: entries of the rows that survive it
-  kPartFields = 8
+  kPartAliveU = 7,    // GCC scan: upper vertices that survive it
+  kPartAliveL = 8,    // GCC scan: lower vertices that survive it
+  kPartFields = 10
 };
 
 // Dynamic edge storage for updates after the build (Sec. V).  Deleted CSR
@@ -178,6 +180,15 @@ struct Graph {
   int32_t *heavy_rows = nullptr;   // nheavy: the split rows, ascending
   int64_t npieces = 0, npieces_upper = 0;
   int64_t nheavy = 0, nheavy_upper = 0;
+  // Degree ranks (the build's degrees): rank[x] is x's position within its
+  // layer in the order of decreasing degree (ties by id), and rcols holds
+  // every row's neighbours as ranks, ascending.  A scan leaves alive exactly
+  // the K vertices of a layer with degree >= its threshold, i.e. ranks
+  // [0, K), so a row's surviving neighbours are the prefix of its rank row
+  // below K: a first pull round on an unchanged graph counts them by binary
+  // search.  (Null when the build could not afford them.)
+  int32_t *rank = nullptr;   // n
+  int32_t *rcols = nullptr;  // 2*m_csr
   // Pull round work split: workgroup k of a cu_count grid walks the upper
   // rows [b[k], b[k+1]) and the lower rows [b[G+1+k], b[G+2+k]), ranges of
   // equal weight (entries of unsplit rows plus a per-row cost).
@@ -309,16 +320,20 @@ hipError_t launch_classify_reset(Graph &g, int32_t thrU, int32_t thrL, int32_t d
 // rowbits: the rows to count (nullptr: the rows whose bit is set in the
 // lookup bitmap); force: pull whatever the pull mode and the frontier.
 // rest_part: the pull cost is the scan's kPartRest sums (nested scans).
+// rank: count by the degree-rank copy (Graph::rcols; the GCC scan's
+// survivors on an unchanged graph only), completing split rows at once.
 hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
                              bool advance = false, bool queue_f0 = false,
                              const uint32_t *rowbits = nullptr, bool force = false,
-                             bool rest_part = false);
+                             bool rest_part = false, bool rank = false);
 // Asynchronous peel fused with the pull round's completion (fix_bits: the
 // scan's survivors, or nullptr when no pull round ran) and the bitmask pack
 // (pack_bits nullable).
+// split_done: the pull round completed its split rows itself (rank form):
+// no start phase, fix_bits serves as the decrement filter only.
 hipError_t launch_peel_async_fused(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
                                    const uint32_t *fix_bits, uint32_t *pack_bits,
-                                   hipStream_t s);
+                                   hipStream_t s, bool split_done = false);
 hipError_t launch_pull_fixup(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s);
 hipError_t launch_scan_component_of(Graph &g, int32_t thrU, int32_t thrL, int32_t x,
                                     int32_t y, hipStream_t s);
@@ -335,7 +350,7 @@ hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *b
                                   const int32_t *corr_x, const int32_t *corr_d, int ncorr,
                                   bool advance, hipStream_t s, bool queue_f0 = false,
                                   const uint32_t *rowbits = nullptr, bool force = false,
-                                  bool rest_part = false);
+                                  bool rest_part = false, bool rank = false);
 hipError_t launch_pull_fixup_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
                                   hipStream_t s);
 hipError_t launch_peel_async_args(Graph &g, PeelKind kind, const PeelArgs &a, int grid,
@@ -359,6 +374,9 @@ hipError_t launch_kcore_levels(Graph &g, int levels, hipStream_t s);
 hipError_t launch_cc(Graph &g, int32_t only_label, hipStream_t s);
 hipError_t query_persistent_grids(Graph &g);
 abcore_status build_pieces(Graph &g, hipStream_t s);
+// Degree ranks and the rank-sorted adjacency copy (Graph::rank, rcols); on
+// an allocation failure it leaves them null and succeeds.
+abcore_status build_ranks(Graph &g, hipStream_t s);
 hipError_t launch_answer_view(const PeelArgs &a, int32_t x, int32_t y, hipStream_t s);
 hipError_t launch_update_window(Graph &g, const int32_t *d_upd, int w, WindowRecord *d_rec,
                                 hipStream_t s);

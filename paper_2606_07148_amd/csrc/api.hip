@@ -135,7 +135,8 @@ void free_graph(Graph *g) {
                   g->core,       g->comp,        g->parent,      g->delta.head,
                   g->delta.next, g->delta.other, g->alive_bits,  g->part,
                   g->piece_row,  g->piece_start, g->piece_first, g->heavy_rows,
-                  g->pull_bounds, g->row_bits,    g->split_written};
+                  g->pull_bounds, g->row_bits,    g->split_written, g->rank,
+                  g->rcols};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   if (g->h_state) (void)hipHostFree(g->h_state);
@@ -249,11 +250,13 @@ abcore_status run_peel(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, hipS
 abcore_status pull_peel_pack(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, bool pull,
                              uint32_t *bits, hipStream_t s, int64_t *launches,
                              bool queue_f0 = false, const uint32_t *rowbits = nullptr,
-                             bool force = false, bool rest_part = false) {
+                             bool force = false, bool rest_part = false, bool rank = false) {
   const bool fused = g.peel_mode == 3;
+  rank = rank && fused && g.rcols != nullptr;
   if (pull) {
     CHK(timed(g, ABCORE_KERNEL_PULL, s, 1, [&] {
-      return launch_pull_round(g, thrU, thrL, s, fused, queue_f0, rowbits, force, rest_part);
+      return launch_pull_round(g, thrU, thrL, s, fused, queue_f0, rowbits, force, rest_part,
+                               rank);
     }));
     if (!fused)
       CHK(timed(g, ABCORE_KERNEL_FIXUP, s, 1,
@@ -263,7 +266,7 @@ abcore_status pull_peel_pack(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL
     CHK(timed(g, ABCORE_KERNEL_PEEL, s, 1, [&] {
       return launch_peel_async_fused(g, kind, thrU, thrL,
                                      pull ? (rowbits ? rowbits : g.alive_bits) : nullptr, bits,
-                                     s);
+                                     s, rank && pull);
     }));
     *launches += 1;
     return ABCORE_OK;
@@ -555,6 +558,8 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
     if (st != ABCORE_OK) break;
     st = build_pieces(*g, s);
     if (st != ABCORE_OK) break;
+    st = build_ranks(*g, s);
+    if (st != ABCORE_OK) break;
     // per computation a vertex enters the queues at most twice (GCC+: as
     // uncertain, then as removed) and a split row once more as its pieces
     g->qcap = 2 * g->n + g->npieces + kLocalQueue;
@@ -771,7 +776,9 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
       // if the first round is pushed (by the pull kernel, from the bitmap)
       CHK(timed(*g, ABCORE_KERNEL_SCAN, s, 1,
                 [&] { return launch_scan_reset_gcc(*g, thrU, thrL, s); }));
-      TRY(pull_peel_pack(*g, kGCC, thrU, thrL, true, d_bitmask, s, &launches, true));
+      // an unchanged graph counts the first round on its degree-rank copy
+      TRY(pull_peel_pack(*g, kGCC, thrU, thrL, true, d_bitmask, s, &launches, true, nullptr,
+                         false, false, g->version == 0));
     } else {
       CHK(launch_init_state(*g, s));
       CHK(timed(*g, ABCORE_KERNEL_SCAN, s, 1,

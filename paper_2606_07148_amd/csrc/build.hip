@@ -304,4 +304,110 @@ done:
 #undef PCHK
 }
 
+namespace {
+
+// (layer-local key) decreasing degree, then id: 64-bit keys whose order is
+// the rank order of one layer.
+__global__ void rank_keys_kernel(const int64_t *__restrict__ off, int64_t lo, int64_t hi,
+                                 uint64_t *__restrict__ keys) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < hi; x += stride) {
+    const uint64_t d = (uint64_t)(off[x + 1] - off[x]);
+    keys[x - lo] = ((0x7FFFFFFFull - d) << 32) | (uint64_t)(x - lo);
+  }
+}
+
+__global__ void rank_scatter_kernel(const uint64_t *__restrict__ sorted, int64_t cnt, int64_t lo,
+                                    int32_t *__restrict__ rank) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride)
+    rank[lo + (int64_t)(uint32_t)sorted[i]] = (int32_t)i;
+}
+
+// Entry keys (row, neighbour's rank): sorted, the rows keep their places
+// and each row's ranks come out ascending.
+__global__ void entry_keys_kernel(const int64_t *__restrict__ off, const int32_t *__restrict__ cols,
+                                  const int32_t *__restrict__ rank, int64_t n, int rbits,
+                                  uint64_t *__restrict__ keys) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride)
+    for (int64_t e = off[x]; e < off[x + 1]; ++e)
+      keys[e] = ((uint64_t)x << rbits) | (uint64_t)rank[cols[e]];
+}
+
+__global__ void entry_unkey_kernel(const uint64_t *__restrict__ keys, int64_t cnt, int rbits,
+                                   int32_t *__restrict__ rcols) {
+  const uint64_t mask = (1ull << rbits) - 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride)
+    rcols[i] = (int32_t)(keys[i] & mask);
+}
+
+}  // namespace
+
+abcore_status build_ranks(Graph &g, hipStream_t s) {
+  const int64_t ent = 2 * g.m_csr;
+  if (g.n == 0) return ABCORE_OK;
+  // 2^31 items is the sort's limit; larger graphs keep the bitmap pull
+  if (ent >= 0x7FFFFFFFLL) return ABCORE_OK;
+  uint64_t *k0 = nullptr, *k1 = nullptr;
+  void *temp = nullptr;
+  size_t temp_bytes = 0, need = 0;
+  bool ok = true;
+  const int grid = std::max(1, std::min(g.cu_count * 8, (int)((g.n + 255) / 256)));
+  const int64_t nmax = std::max<int64_t>(std::max<int64_t>(g.nU, g.nL), 1);
+  const int rbits = bits_for((uint64_t)nmax - 1);
+  const int xbits = bits_for((uint64_t)std::max<int64_t>(g.n, 1) - 1);
+  const int64_t items = std::max<int64_t>(ent, nmax);
+  auto fail = [&](hipError_t e) {
+    if (e != hipSuccess) ok = false;
+    return e != hipSuccess;
+  };
+  do {
+    if (fail(hipMalloc(&g.rank, sizeof(int32_t) * g.n))) break;
+    if (fail(hipMalloc(&g.rcols, sizeof(int32_t) * std::max<int64_t>(ent, 1)))) break;
+    if (fail(hipMalloc(&k0, sizeof(uint64_t) * items))) break;
+    if (fail(hipMalloc(&k1, sizeof(uint64_t) * items))) break;
+    // temporary storage for the largest sort
+    if (fail(hipcub::DeviceRadixSort::SortKeys(nullptr, need, k0, k1, (int)items, 0, 64, s)))
+      break;
+    temp_bytes = std::max<size_t>(need, 16);
+    if (fail(hipMalloc(&temp, temp_bytes))) break;
+    // ranks, one layer at a time
+    for (int layer = 0; layer < 2 && ok; ++layer) {
+      const int64_t lo = layer == 0 ? 0 : g.nU, hi = layer == 0 ? g.nU : g.n;
+      if (hi <= lo) continue;
+      rank_keys_kernel<<<grid, 256, 0, s>>>(g.off, lo, hi, k0);
+      if (fail(hipGetLastError())) break;
+      size_t tb = temp_bytes;
+      if (fail(hipcub::DeviceRadixSort::SortKeys(temp, tb, k0, k1, (int)(hi - lo), 0, 64, s)))
+        break;
+      rank_scatter_kernel<<<grid, 256, 0, s>>>(k1, hi - lo, lo, g.rank);
+      if (fail(hipGetLastError())) break;
+    }
+    if (!ok) break;
+    if (ent > 0) {
+      entry_keys_kernel<<<grid, 256, 0, s>>>(g.off, g.cols, g.rank, g.n, rbits, k0);
+      if (fail(hipGetLastError())) break;
+      size_t tb = temp_bytes;
+      if (fail(hipcub::DeviceRadixSort::SortKeys(temp, tb, k0, k1, (int)ent, 0, rbits + xbits, s)))
+        break;
+      entry_unkey_kernel<<<grid, 256, 0, s>>>(k1, ent, rbits, g.rcols);
+      if (fail(hipGetLastError())) break;
+    }
+    if (fail(hipStreamSynchronize(s))) break;
+  } while (0);
+  if (k0) (void)hipFree(k0);
+  if (k1) (void)hipFree(k1);
+  if (temp) (void)hipFree(temp);
+  if (!ok) {
+    (void)hipGetLastError();
+    if (g.rank) (void)hipFree(g.rank);
+    if (g.rcols) (void)hipFree(g.rcols);
+    g.rank = nullptr;
+    g.rcols = nullptr;
+  }
+  return ABCORE_OK;
+}
+
 }  // namespace abc

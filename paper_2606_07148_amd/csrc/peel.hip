@@ -339,7 +339,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
   for (int64_t i = (int64_t)gridDim.x * kPartFields + tid; i < nparts; i += stride) a.part[i] = 0;
   if (threadIdx.x < kPartFields) a.part[(int64_t)blockIdx.x * kPartFields + threadIdx.x] = 0;
   __syncthreads();
-  int64_t f0 = 0, f0deg = 0;
+  int64_t f0 = 0, f0deg = 0, alive_u = 0, alive_l = 0;
   for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < n;
        cb += (int64_t)gridDim.x * kScanChunk) {
     for (int t = 0; t < kScanChunk; t += kScanBlock * 4) {
@@ -366,7 +366,15 @@ __global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
       uint32_t alive = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        if (x0 + j < n) alive |= (uint32_t)(!p[j]) << j;
+        if (x0 + j < n) {
+          alive |= (uint32_t)(!p[j]) << j;
+          if (!p[j]) {
+            if (x0 + j < a.nU)
+              ++alive_u;
+            else
+              ++alive_l;
+          }
+        }
         if (p[j]) {
           f0 += 1;
           f0deg += d[j];
@@ -382,6 +390,8 @@ __global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
   }
   add_part(a.part, kPartF0, f0, &s_acc);
   add_part(a.part, kPartF0Deg, f0deg, &s_acc);
+  add_part(a.part, kPartAliveU, alive_u, &s_acc);
+  add_part(a.part, kPartAliveL, alive_l, &s_acc);
   __syncthreads();
   if (wave_in_block() != 0) return;
   int last = 0;
@@ -1178,10 +1188,12 @@ hipError_t launch_peel_async_args(Graph &g, PeelKind kind, const PeelArgs &a, in
 
 hipError_t launch_peel_async_fused(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL,
                                    const uint32_t *fix_bits, uint32_t *pack_bits,
-                                   hipStream_t s) {
+                                   hipStream_t s, bool split_done) {
   PeelArgs a = make_args(g, thrU, thrL);
   const int grid = async_peel_grid(g);
-  if (fix_bits != nullptr) {
+  if (split_done) {
+    a.alive0 = fix_bits;  // the filter only: the pull round queued its split rows
+  } else if (fix_bits != nullptr) {
     a.fix_rows = g.heavy_rows;
     a.fix_bits = fix_bits;
     a.nfix = g.nheavy;
@@ -1231,6 +1243,7 @@ struct PullShared {
   int s_cnt[kPullWaves + 1];
   int decide;
   int next_row, next_piece;  // the workgroup's next unclaimed row / piece
+  int32_t k_alive[2];        // rank mode: survivors of the upper / lower layer
   int64_t acc;
 };
 
@@ -1241,28 +1254,31 @@ __device__ __forceinline__ uint32_t test_bit(const uint32_t *w, int64_t base_wor
   return (w[idx] >> (v & 31)) & (v >= 0 ? 1u : 0u);
 }
 
-// Neighbours with their bit set in the row [s, s+d), d <= kLightRow (deleted
-// entries are negative and never count).
-__device__ __forceinline__ int count_row_thread(const PeelArgs &a, const uint32_t *lk,
-                                                int64_t lk_base, int64_t s, int d) {
+// Row entries that pass `test` in [s, s+d) of `src` (the adjacency with the
+// bitmap test, deleted entries negative and never counting, or the rank
+// copy with a rank bound), d <= kLightRow.
+template <class Test>
+__device__ __forceinline__ int count_row_thread(const PeelArgs &a, const int32_t *src, int64_t s,
+                                                int d, Test test) {
   int32_t w[kLightRow];
 #pragma unroll
-  for (int j = 0; j < kLightRow; ++j) w[j] = j < d ? a.cols[s + j] : -1;
+  for (int j = 0; j < kLightRow; ++j) w[j] = j < d ? src[s + j] : -1;
   if (a.del_ver != nullptr) {
 #pragma unroll
     for (int j = 0; j < kLightRow; ++j) w[j] = view_col(a, j < d, s + j, w[j]);
   }
   int c = 0;
 #pragma unroll
-  for (int j = 0; j < kLightRow; ++j) c += (int)test_bit(lk, lk_base, w[j]);
+  for (int j = 0; j < kLightRow; ++j) c += (int)test(w[j]);
   return c;
 }
 
-// Counts, for every lane with pred, the neighbours with their bit set in its
-// chunk [s, s+d) (d <= 64); the count lands in cnt[lane].  Whole wave.
-__device__ __forceinline__ void count_chunks(const PeelArgs &a, const uint32_t *lk,
-                                             int64_t lk_base, bool pred, int64_t s, int d,
-                                             ChunkDesc *desc, int32_t *cnt) {
+// Counts, for every lane with pred, the entries of its chunk [s, s+d) of
+// `src` (d <= 64) that pass `test`; the count lands in cnt[lane].  Whole wave.
+template <class Test>
+__device__ __forceinline__ void count_chunks(const PeelArgs &a, const int32_t *src, bool pred,
+                                             int64_t s, int d, ChunkDesc *desc, int32_t *cnt,
+                                             Test test) {
   const uint64_t m = __ballot(pred);
   const int total = __popcll(m);
   if (total == 0) return;
@@ -1292,7 +1308,7 @@ __device__ __forceinline__ void count_chunks(const PeelArgs &a, const uint32_t *
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int k = l + 16 * j;
-        w[r][j] = k < cdn[r] ? a.cols[cs[r] + k] : -1;
+        w[r][j] = k < cdn[r] ? src[cs[r] + k] : -1;
       }
     if (a.del_ver != nullptr) {
 #pragma unroll
@@ -1305,7 +1321,7 @@ __device__ __forceinline__ void count_chunks(const PeelArgs &a, const uint32_t *
     for (int r = 0; r < 4; ++r) {
       int c = 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) c += (int)test_bit(lk, lk_base, w[r][j]);
+      for (int j = 0; j < 4; ++j) c += (int)test(w[r][j]);
       c += __shfl_xor(c, 8, 16);
       c += __shfl_xor(c, 4, 16);
       c += __shfl_xor(c, 2, 16);
@@ -1354,7 +1370,8 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     int64_t npieces_upper, const int32_t *__restrict__ corr_x,
     const int32_t *__restrict__ corr_d, int ncorr, int advance,
     const int32_t *__restrict__ bounds, int queue_f0, const uint32_t *__restrict__ rowbits,
-    int rest_part, const int32_t *__restrict__ written_snap) {
+    int rest_part, const int32_t *__restrict__ written_snap, const int32_t *__restrict__ rcols,
+    const int32_t *__restrict__ heavy_rows, int64_t nheavy, int64_t nheavy_upper) {
   extern __shared__ __align__(16) uint32_t s_bits[];
   __shared__ PullShared sh;
   // Each phase walks one layer's rows; its bitmap of the other layer is
@@ -1395,8 +1412,23 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
                                    : total_entries - f0deg;
     // pull pays one streaming read per surviving entry instead of one atomic
     // per frontier entry: worth it when the frontier carries a sizeable share
-    const bool pull = mode == 2 || (mode == 0 && f0deg > 0 &&
-                                    (use_lds ? f0deg * 16 >= rest : f0deg * 2 >= rest));
+    // with the rank copy a pull round reads about a line per surviving row
+    // (a few per split row): worth it once the frontier's atomics are about
+    // half as many as the survivors
+    int64_t ku = 0, kl = 0;
+    if (rcols != nullptr) {
+      ku = wave_sum_strided(a.part + kPartAliveU, scan_blocks, kPartFields);
+      kl = wave_sum_strided(a.part + kPartAliveL, scan_blocks, kPartFields);
+      if (lane_id() == 0) {
+        sh.k_alive[0] = (int32_t)ku;
+        sh.k_alive[1] = (int32_t)kl;
+      }
+    }
+    const bool pull =
+        mode == 2 ||
+        (mode == 0 && f0deg > 0 &&
+         (rcols != nullptr ? f0deg * 2 >= ku + kl
+                           : (use_lds ? f0deg * 16 >= rest : f0deg * 2 >= rest)));
     if (lane_id() == 0) sh.decide = pull ? 1 : 0;
   }
   if (kLds) stage(0);
@@ -1497,9 +1529,18 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
       fetch_rows(bn);
       b = bn;
       int c = 0;
-      if (alive && d <= kLightRow) c = count_row_thread(a, lk, lk_base, s, d);
       const bool grouped = alive && d > kLightRow;
-      count_chunks(a, lk, lk_base, grouped, s, d, desc, cnt);
+      if (rcols != nullptr) {
+        // surviving neighbours: the row's ranks below the other layer's K
+        const int32_t kb = sh.k_alive[phase ^ 1];
+        auto below = [kb](int32_t v) { return (uint32_t)(v >= 0 && v < kb); };
+        if (alive && d <= kLightRow) c = count_row_thread(a, rcols, s, d, below);
+        count_chunks(a, rcols, grouped, s, d, desc, cnt, below);
+      } else {
+        auto bit = [&](int32_t v) { return test_bit(lk, lk_base, v); };
+        if (alive && d <= kLightRow) c = count_row_thread(a, a.cols, s, d, bit);
+        count_chunks(a, a.cols, grouped, s, d, desc, cnt, bit);
+      }
       if (grouped) c = cnt[lane_id()];
       bool push = false;
       if (alive) {
@@ -1511,6 +1552,60 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
       }
       lq.push(push, x);
       __builtin_amdgcn_wave_barrier();
+    }
+    if (rcols != nullptr) {
+      // Split rows: a 16-lane group per row finds the end of the row's
+      // prefix of ranks below K, 16 probes per step (a 50,000-entry row
+      // takes three steps and a final one), and the row is complete at once
+      // (no pieces, no completion in the peel's start phase).
+      const int32_t kb = sh.k_alive[phase ^ 1];
+      const int64_t h0 = phase == 0 ? 0 : nheavy_upper, h1 = phase == 0 ? nheavy_upper : nheavy;
+      const int64_t q0 = h0 + (h1 - h0) * k / G, q1 = h0 + (h1 - h0) * (k + 1) / G;
+      const int grp = lane_id() >> 4, l = lane_id() & 15;
+      for (;;) {
+        int claim = 0;
+        if (lane_id() == 0) claim = atomicAdd(&sh.next_piece, 4);
+        const int64_t hb = q0 + __shfl(claim, 0, kWave);
+        if (hb >= q1) break;
+        const int64_t hi_ = hb + grp;
+        int32_t x = -1;
+        int64_t s = 0;
+        bool alive = false;
+        int lo = 0, hi = 0;
+        if (hi_ < q1) {
+          x = heavy_rows[hi_];
+          alive = (rowbits[x >> 5] >> (x & 31)) & 1u;
+          s = a.off[x];
+          hi = alive ? (int)(a.off[x + 1] - s) : 0;
+        }
+        while (__ballot(hi - lo > 16)) {
+          const bool act = hi - lo > 16;
+          const int span = hi - lo;
+          const int p = lo + (int)(((int64_t)span * l) / 16);
+          const bool t = act && rcols[s + p] < kb;
+          const int c = __popcll((__ballot(t) >> (16 * grp)) & 0xFFFFull);
+          if (act) {
+            // the end lies in (p_{c-1}, p_c]
+            const int pprev = lo + (int)(((int64_t)span * (c - 1)) / 16);
+            const int pcur = lo + (int)(((int64_t)span * c) / 16);
+            const int nlo = c == 0 ? lo : pprev + 1;
+            hi = c == 16 ? hi : pcur;
+            lo = nlo;
+          }
+        }
+        const bool t = lo + l < hi && rcols[s + lo + l] < kb;
+        const int cnt_row = lo + __popcll((__ballot(t) >> (16 * grp)) & 0xFFFFull);
+        bool push = false;
+        if (alive && l == 0) {
+          a.deg[x] = cnt_row;
+          push = cnt_row < (x < a.nU ? a.thrU : a.thrL);
+          f1 += push ? 1 : 0;
+          entries += 64;
+        }
+        lq.push(push, x);
+        __builtin_amdgcn_wave_barrier();
+      }
+      continue;
     }
     // pieces of longer rows: per-piece counts summed per row inside the
     // wave (a row's pieces are consecutive), one atomic per row and wave
@@ -1532,7 +1627,8 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
         d = (int)(min(s + kPiece, re) - s);
         first = s == rs;
       }
-      count_chunks(a, lk, lk_base, alive, s, d, desc, cnt);
+      count_chunks(a, a.cols, alive, s, d, desc, cnt,
+                   [&](int32_t v) { return test_bit(lk, lk_base, v); });
       int c = 0;
       if (alive) {
         entries += d;
@@ -1620,35 +1716,41 @@ bool pull_uses_lds(const Graph &g) {
 hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *bits,
                                   const int32_t *corr_x, const int32_t *corr_d, int ncorr,
                                   bool advance, hipStream_t s, bool queue_f0,
-                                  const uint32_t *rowbits, bool force, bool rest_part) {
+                                  const uint32_t *rowbits, bool force, bool rest_part,
+                                  bool rank) {
   if (g.pull_mode == 1 && !force) return hipSuccess;
   const int mode = force ? 2 : g.pull_mode;
   if (rowbits == nullptr) rowbits = bits;
+  rank = rank && g.rcols != nullptr;
   const int64_t words_upper = g.nU > 0 ? ((int64_t)g.nU - 1) / 32 + 1 : 0;
   const int64_t words_lower = g.nL > 0 ? ((g.n - 1) >> 5) - (g.nU >> 5) + 1 : 0;
-  const bool use_lds = pull_uses_lds(g);
+  // the rank form looks nothing up: no bitmap in LDS
+  const bool use_lds = !rank && pull_uses_lds(g);
   const size_t dyn = use_lds ? (size_t)(4 * (std::max(words_upper, words_lower) + 4)) : 0;
   const int64_t total_entries = 2 * g.m;
   const int grid = g.cu_count;
   const int32_t *bounds = g.pull_bounds_grid == grid ? g.pull_bounds : nullptr;
+  const int32_t *rcols = rank ? g.rcols : nullptr;
   if (use_lds)
     pull_round_kernel<true><<<grid, kPullBlock, dyn, s>>>(
         a, bits, g.deg0, g.n, scan_grid(g), mode, 1, total_entries, g.npieces,
         g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0,
-        rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr);
+        rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr, rcols, g.heavy_rows,
+        g.nheavy, g.nheavy_upper);
   else
     pull_round_kernel<false><<<grid, kPullBlock, dyn, s>>>(
         a, bits, g.deg0, g.n, scan_grid(g), mode, 0, total_entries, g.npieces,
         g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0,
-        rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr);
+        rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr, rcols, g.heavy_rows,
+        g.nheavy, g.nheavy_upper);
   return hipGetLastError();
 }
 
 hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
                              bool advance, bool queue_f0, const uint32_t *rowbits, bool force,
-                             bool rest_part) {
+                             bool rest_part, bool rank) {
   return launch_pull_round_args(g, make_args(g, thrU, thrL), g.alive_bits, nullptr, nullptr, 0,
-                                advance, s, queue_f0, rowbits, force, rest_part);
+                                advance, s, queue_f0, rowbits, force, rest_part, rank);
 }
 
 // Must follow the pull round on the same stream (it completes that round).
