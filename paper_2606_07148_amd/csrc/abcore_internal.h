@@ -181,14 +181,19 @@ struct Graph {
   int64_t npieces = 0, npieces_upper = 0;
   int64_t nheavy = 0, nheavy_upper = 0;
   // Degree ranks (the build's degrees): rank[x] is x's position within its
-  // layer in the order of decreasing degree (ties by id), and rcols holds
-  // every row's neighbours as ranks, ascending.  A scan leaves alive exactly
-  // the K vertices of a layer with degree >= its threshold, i.e. ranks
-  // [0, K), so a row's surviving neighbours are the prefix of its rank row
-  // below K: a first pull round on an unchanged graph counts them by binary
-  // search.  (Null when the build could not afford them.)
-  int32_t *rank = nullptr;   // n
-  int32_t *rcols = nullptr;  // 2*m_csr
+  // layer in the order of decreasing degree (ties by id); rank_vtx maps the
+  // global rank R (a layer's ranks follow its first unified id) back to the
+  // vertex.  rcols holds the rows in rank order (row R at roff[R]), each as
+  // its neighbours' ranks, ascending.  A scan leaves alive exactly the K
+  // vertices of a layer with degree >= its threshold, i.e. ranks [0, K): the
+  // surviving rows are a prefix of the rank order (the split rows first),
+  // and a row's surviving neighbours are the prefix of its rank row below
+  // the other layer's K.  A first pull round on an unchanged graph counts
+  // them so.  (Null when the build could not afford them.)
+  int32_t *rank = nullptr;      // n
+  int32_t *rank_vtx = nullptr;  // n
+  int64_t *roff = nullptr;      // n + 1
+  int32_t *rcols = nullptr;     // 2*m_csr
   // Pull round work split: workgroup k of a cu_count grid walks the upper
   // rows [b[k], b[k+1]) and the lower rows [b[G+1+k], b[G+2+k]), ranges of
   // equal weight (entries of unsplit rows plus a per-row cost).

@@ -136,7 +136,7 @@ void free_graph(Graph *g) {
                   g->delta.next, g->delta.other, g->alive_bits,  g->part,
                   g->piece_row,  g->piece_start, g->piece_first, g->heavy_rows,
                   g->pull_bounds, g->row_bits,    g->split_written, g->rank,
-                  g->rcols};
+                  g->rcols,       g->rank_vtx,    g->roff};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   if (g->h_state) (void)hipHostFree(g->h_state);

@@ -318,21 +318,28 @@ __global__ void rank_keys_kernel(const int64_t *__restrict__ off, int64_t lo, in
 }
 
 __global__ void rank_scatter_kernel(const uint64_t *__restrict__ sorted, int64_t cnt, int64_t lo,
-                                    int32_t *__restrict__ rank) {
+                                    const int64_t *__restrict__ off, int32_t *__restrict__ rank,
+                                    int32_t *__restrict__ rank_vtx, int64_t *__restrict__ rdeg) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride)
-    rank[lo + (int64_t)(uint32_t)sorted[i]] = (int32_t)i;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
+    const int64_t x = lo + (int64_t)(uint32_t)sorted[i];
+    rank[x] = (int32_t)i;
+    rank_vtx[lo + i] = (int32_t)x;
+    rdeg[lo + i] = off[x + 1] - off[x];
+  }
 }
 
-// Entry keys (row, neighbour's rank): sorted, the rows keep their places
-// and each row's ranks come out ascending.
+// Entry keys (global rank of the row, neighbour's rank): sorted, the rows
+// come out in rank order and each row's ranks ascending.
 __global__ void entry_keys_kernel(const int64_t *__restrict__ off, const int32_t *__restrict__ cols,
-                                  const int32_t *__restrict__ rank, int64_t n, int rbits,
+                                  const int32_t *__restrict__ rank, int64_t n, int64_t nU, int rbits,
                                   uint64_t *__restrict__ keys) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride)
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
+    const uint64_t r = (uint64_t)rank[x] + (x < nU ? 0 : (uint64_t)nU);
     for (int64_t e = off[x]; e < off[x + 1]; ++e)
-      keys[e] = ((uint64_t)x << rbits) | (uint64_t)rank[cols[e]];
+      keys[e] = (r << rbits) | (uint64_t)rank[cols[e]];
+  }
 }
 
 __global__ void entry_unkey_kernel(const uint64_t *__restrict__ keys, int64_t cnt, int rbits,
@@ -365,13 +372,21 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
   };
   do {
     if (fail(hipMalloc(&g.rank, sizeof(int32_t) * g.n))) break;
+    if (fail(hipMalloc(&g.rank_vtx, sizeof(int32_t) * g.n))) break;
+    if (fail(hipMalloc(&g.roff, sizeof(int64_t) * (g.n + 1)))) break;
     if (fail(hipMalloc(&g.rcols, sizeof(int32_t) * std::max<int64_t>(ent, 1)))) break;
-    if (fail(hipMalloc(&k0, sizeof(uint64_t) * items))) break;
+    // k0 also holds the degrees by rank (n + 1 values after n + 1 slots)
+    if (fail(hipMalloc(&k0, sizeof(uint64_t) * std::max<int64_t>(items, 2 * (g.n + 1))))) break;
     if (fail(hipMalloc(&k1, sizeof(uint64_t) * items))) break;
-    // temporary storage for the largest sort
+    // temporary storage for the largest sort, and the offsets' scan
     if (fail(hipcub::DeviceRadixSort::SortKeys(nullptr, need, k0, k1, (int)items, 0, 64, s)))
       break;
     temp_bytes = std::max<size_t>(need, 16);
+    need = 0;
+    if (fail(hipcub::DeviceScan::ExclusiveSum(nullptr, need, reinterpret_cast<int64_t *>(k0),
+                                              g.roff, (int)(g.n + 1), s)))
+      break;
+    temp_bytes = std::max(temp_bytes, need);
     if (fail(hipMalloc(&temp, temp_bytes))) break;
     // ranks, one layer at a time
     for (int layer = 0; layer < 2 && ok; ++layer) {
@@ -382,12 +397,21 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
       size_t tb = temp_bytes;
       if (fail(hipcub::DeviceRadixSort::SortKeys(temp, tb, k0, k1, (int)(hi - lo), 0, 64, s)))
         break;
-      rank_scatter_kernel<<<grid, 256, 0, s>>>(k1, hi - lo, lo, g.rank);
+      // (k0 holds no keys any more past the sort: its tail collects the
+      // degrees by rank, the offsets' scan input)
+      rank_scatter_kernel<<<grid, 256, 0, s>>>(k1, hi - lo, lo, g.off, g.rank, g.rank_vtx,
+                                               reinterpret_cast<int64_t *>(k0) + g.n + 1);
       if (fail(hipGetLastError())) break;
     }
     if (!ok) break;
+    {
+      int64_t *rdeg = reinterpret_cast<int64_t *>(k0) + g.n + 1;
+      if (fail(hipMemsetAsync(rdeg + g.n, 0, sizeof(int64_t), s))) break;
+      size_t tb = temp_bytes;
+      if (fail(hipcub::DeviceScan::ExclusiveSum(temp, tb, rdeg, g.roff, (int)(g.n + 1), s))) break;
+    }
     if (ent > 0) {
-      entry_keys_kernel<<<grid, 256, 0, s>>>(g.off, g.cols, g.rank, g.n, rbits, k0);
+      entry_keys_kernel<<<grid, 256, 0, s>>>(g.off, g.cols, g.rank, g.n, g.nU, rbits, k0);
       if (fail(hipGetLastError())) break;
       size_t tb = temp_bytes;
       if (fail(hipcub::DeviceRadixSort::SortKeys(temp, tb, k0, k1, (int)ent, 0, rbits + xbits, s)))
@@ -403,8 +427,12 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
   if (!ok) {
     (void)hipGetLastError();
     if (g.rank) (void)hipFree(g.rank);
+    if (g.rank_vtx) (void)hipFree(g.rank_vtx);
+    if (g.roff) (void)hipFree(g.roff);
     if (g.rcols) (void)hipFree(g.rcols);
     g.rank = nullptr;
+    g.rank_vtx = nullptr;
+    g.roff = nullptr;
     g.rcols = nullptr;
   }
   return ABCORE_OK;

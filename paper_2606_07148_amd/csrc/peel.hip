@@ -1371,7 +1371,8 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     const int32_t *__restrict__ corr_d, int ncorr, int advance,
     const int32_t *__restrict__ bounds, int queue_f0, const uint32_t *__restrict__ rowbits,
     int rest_part, const int32_t *__restrict__ written_snap, const int32_t *__restrict__ rcols,
-    const int32_t *__restrict__ heavy_rows, int64_t nheavy, int64_t nheavy_upper) {
+    const int32_t *__restrict__ rank_vtx, const int64_t *__restrict__ roff, int64_t nheavy,
+    int64_t nheavy_upper) {
   extern __shared__ __align__(16) uint32_t s_bits[];
   __shared__ PullShared sh;
   // Each phase walks one layer's rows; its bitmap of the other layer is
@@ -1498,6 +1499,97 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     const int64_t r1 = bounds != nullptr ? bounds[phase * (G + 1) + k + 1]
                                          : lo + (hi - lo) * (k + 1) / G;
     const int64_t p0 = plo + (phi - plo) * k / G, p1 = plo + (phi - plo) * (k + 1) / G;
+    if (rcols != nullptr) {
+      // Rank form: the surviving rows of this layer are its ranks below
+      // kself, split rows (more than kPiece entries) first; a row's
+      // surviving neighbours are its rank row's prefix below kb.  Chunks of
+      // 64 ranks are dealt to the workgroups in turn (workgroup k takes
+      // chunks k, k + G, ...), its waves claiming them through LDS.
+      const int64_t base = phase == 0 ? 0 : a.nU;
+      const int64_t kself = sh.k_alive[phase];
+      const int32_t kb = sh.k_alive[phase ^ 1];
+      const int64_t nh = phase == 0 ? nheavy_upper : nheavy - nheavy_upper;
+      const int64_t hend = base + min(nh, kself), lend = base + kself;
+      auto below = [kb](int32_t v) { return (uint32_t)(v >= 0 && v < kb); };
+      for (;;) {
+        int claim = 0;
+        if (lane_id() == 0) claim = atomicAdd(&sh.next_row, 1);
+        const int64_t b = hend + ((int64_t)k + (int64_t)__shfl(claim, 0, kWave) * G) * kWave;
+        if (b >= lend) break;
+        const int64_t r = b + lane_id();
+        const bool alive = r < lend;
+        int32_t x = -1;
+        int64_t s = 0;
+        int d = 0;
+        if (alive) {
+          x = rank_vtx[r];
+          s = roff[r];
+          d = (int)(roff[r + 1] - s);
+        }
+        int c = 0;
+        const bool grouped = alive && d > kLightRow;
+        if (alive && d <= kLightRow) c = count_row_thread(a, rcols, s, d, below);
+        count_chunks(a, rcols, grouped, s, d, desc, cnt, below);
+        if (grouped) c = cnt[lane_id()];
+        bool push = false;
+        if (alive) {
+          entries += d;
+          a.deg[x] = c;
+          push = c < (x < a.nU ? a.thrU : a.thrL);
+          f1 += push ? 1 : 0;
+        }
+        lq.push(push, x);
+        __builtin_amdgcn_wave_barrier();
+      }
+      // split rows: a 16-lane group per row finds the end of the row's
+      // prefix below kb, 16 probes per step (a 50,000-entry row takes three
+      // steps and a final one), so the row is complete at once (no pieces,
+      // no completion in the peel's start phase)
+      const int grp = lane_id() >> 4, l = lane_id() & 15;
+      for (;;) {
+        int claim = 0;
+        if (lane_id() == 0) claim = atomicAdd(&sh.next_piece, 1);
+        const int64_t hb = base + ((int64_t)k + (int64_t)__shfl(claim, 0, kWave) * G) * 4;
+        if (hb >= hend) break;
+        const int64_t r = hb + grp;
+        int32_t x = -1;
+        int64_t s = 0;
+        const bool alive = r < hend;
+        int lo = 0, hi = 0;
+        if (alive) {
+          x = rank_vtx[r];
+          s = roff[r];
+          hi = (int)(roff[r + 1] - s);
+        }
+        while (__ballot(hi - lo > 16)) {
+          const bool act = hi - lo > 16;
+          const int span = hi - lo;
+          const int p = lo + (int)(((int64_t)span * l) / 16);
+          const bool t = act && rcols[s + p] < kb;
+          const int cc = __popcll((__ballot(t) >> (16 * grp)) & 0xFFFFull);
+          if (act) {
+            // the end lies in (p_{cc-1}, p_cc]
+            const int pprev = lo + (int)(((int64_t)span * (cc - 1)) / 16);
+            const int pcur = lo + (int)(((int64_t)span * cc) / 16);
+            const int nlo = cc == 0 ? lo : pprev + 1;
+            hi = cc == 16 ? hi : pcur;
+            lo = nlo;
+          }
+        }
+        const bool t = lo + l < hi && rcols[s + lo + l] < kb;
+        const int cnt_row = lo + __popcll((__ballot(t) >> (16 * grp)) & 0xFFFFull);
+        bool push = false;
+        if (alive && l == 0) {
+          a.deg[x] = cnt_row;
+          push = cnt_row < (x < a.nU ? a.thrU : a.thrL);
+          f1 += push ? 1 : 0;
+          entries += 64;
+        }
+        lq.push(push, x);
+        __builtin_amdgcn_wave_barrier();
+      }
+      continue;
+    }
     // rows of at most kPiece entries, 64 consecutive vertices per claim; the
     // offsets and survivor bits of the next claim are loaded before this one
     // is counted (one memory round trip per claim instead of two)
@@ -1530,17 +1622,9 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
       b = bn;
       int c = 0;
       const bool grouped = alive && d > kLightRow;
-      if (rcols != nullptr) {
-        // surviving neighbours: the row's ranks below the other layer's K
-        const int32_t kb = sh.k_alive[phase ^ 1];
-        auto below = [kb](int32_t v) { return (uint32_t)(v >= 0 && v < kb); };
-        if (alive && d <= kLightRow) c = count_row_thread(a, rcols, s, d, below);
-        count_chunks(a, rcols, grouped, s, d, desc, cnt, below);
-      } else {
-        auto bit = [&](int32_t v) { return test_bit(lk, lk_base, v); };
-        if (alive && d <= kLightRow) c = count_row_thread(a, a.cols, s, d, bit);
-        count_chunks(a, a.cols, grouped, s, d, desc, cnt, bit);
-      }
+      auto bit = [&](int32_t v) { return test_bit(lk, lk_base, v); };
+      if (alive && d <= kLightRow) c = count_row_thread(a, a.cols, s, d, bit);
+      count_chunks(a, a.cols, grouped, s, d, desc, cnt, bit);
       if (grouped) c = cnt[lane_id()];
       bool push = false;
       if (alive) {
@@ -1552,60 +1636,6 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
       }
       lq.push(push, x);
       __builtin_amdgcn_wave_barrier();
-    }
-    if (rcols != nullptr) {
-      // Split rows: a 16-lane group per row finds the end of the row's
-      // prefix of ranks below K, 16 probes per step (a 50,000-entry row
-      // takes three steps and a final one), and the row is complete at once
-      // (no pieces, no completion in the peel's start phase).
-      const int32_t kb = sh.k_alive[phase ^ 1];
-      const int64_t h0 = phase == 0 ? 0 : nheavy_upper, h1 = phase == 0 ? nheavy_upper : nheavy;
-      const int64_t q0 = h0 + (h1 - h0) * k / G, q1 = h0 + (h1 - h0) * (k + 1) / G;
-      const int grp = lane_id() >> 4, l = lane_id() & 15;
-      for (;;) {
-        int claim = 0;
-        if (lane_id() == 0) claim = atomicAdd(&sh.next_piece, 4);
-        const int64_t hb = q0 + __shfl(claim, 0, kWave);
-        if (hb >= q1) break;
-        const int64_t hi_ = hb + grp;
-        int32_t x = -1;
-        int64_t s = 0;
-        bool alive = false;
-        int lo = 0, hi = 0;
-        if (hi_ < q1) {
-          x = heavy_rows[hi_];
-          alive = (rowbits[x >> 5] >> (x & 31)) & 1u;
-          s = a.off[x];
-          hi = alive ? (int)(a.off[x + 1] - s) : 0;
-        }
-        while (__ballot(hi - lo > 16)) {
-          const bool act = hi - lo > 16;
-          const int span = hi - lo;
-          const int p = lo + (int)(((int64_t)span * l) / 16);
-          const bool t = act && rcols[s + p] < kb;
-          const int c = __popcll((__ballot(t) >> (16 * grp)) & 0xFFFFull);
-          if (act) {
-            // the end lies in (p_{c-1}, p_c]
-            const int pprev = lo + (int)(((int64_t)span * (c - 1)) / 16);
-            const int pcur = lo + (int)(((int64_t)span * c) / 16);
-            const int nlo = c == 0 ? lo : pprev + 1;
-            hi = c == 16 ? hi : pcur;
-            lo = nlo;
-          }
-        }
-        const bool t = lo + l < hi && rcols[s + lo + l] < kb;
-        const int cnt_row = lo + __popcll((__ballot(t) >> (16 * grp)) & 0xFFFFull);
-        bool push = false;
-        if (alive && l == 0) {
-          a.deg[x] = cnt_row;
-          push = cnt_row < (x < a.nU ? a.thrU : a.thrL);
-          f1 += push ? 1 : 0;
-          entries += 64;
-        }
-        lq.push(push, x);
-        __builtin_amdgcn_wave_barrier();
-      }
-      continue;
     }
     // pieces of longer rows: per-piece counts summed per row inside the
     // wave (a row's pieces are consecutive), one atomic per row and wave
@@ -1735,14 +1765,14 @@ hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *b
     pull_round_kernel<true><<<grid, kPullBlock, dyn, s>>>(
         a, bits, g.deg0, g.n, scan_grid(g), mode, 1, total_entries, g.npieces,
         g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0,
-        rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr, rcols, g.heavy_rows,
-        g.nheavy, g.nheavy_upper);
+        rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr, rcols, g.rank_vtx,
+        g.roff, g.nheavy, g.nheavy_upper);
   else
     pull_round_kernel<false><<<grid, kPullBlock, dyn, s>>>(
         a, bits, g.deg0, g.n, scan_grid(g), mode, 0, total_entries, g.npieces,
         g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0,
-        rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr, rcols, g.heavy_rows,
-        g.nheavy, g.nheavy_upper);
+        rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr, rcols, g.rank_vtx,
+        g.roff, g.nheavy, g.nheavy_upper);
   return hipGetLastError();
 }
 
