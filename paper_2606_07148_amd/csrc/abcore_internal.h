@@ -317,7 +317,8 @@ hipError_t launch_scan_nested(Graph &g, int32_t pU, int32_t pL, int32_t thrU, in
                               hipStream_t s, uint32_t *bits = nullptr);
 // queue_f0: the scan did not queue its frontier (launch_scan_reset_gcc);
 // a pushed first round then queues it from the bitmap.
-hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s);
+hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
+                                  bool keep_abort = false);
 // GCC+: the classification, fused with the workspace reset, that prepares
 // a pull round (rowbits = g.row_bits, force = true) as its initialisation.
 hipError_t launch_classify_reset(Graph &g, int32_t thrU, int32_t thrL, int32_t dl, int32_t dq,

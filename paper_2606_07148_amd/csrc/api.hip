@@ -369,7 +369,13 @@ abcore_status run_batch(Graph &g, const BatchPlan &plan, const int32_t *tu, cons
       continue;
     }
     g.deg = g.slots[plan.slot[i]];
-    if (p < 0) {
+    if (p < 0 && pull && g.peel_mode == 3) {
+      // a root runs as a single query does: the fused scan and reset, then a
+      // first round counted on the degree-rank copy when the graph has one
+      CHK(launch_scan_reset_gcc(g, tu[i], tl[i], s, true));
+      TRY(pull_peel_pack(g, kGCC, tu[i], tl[i], true, out, s, &launches, true, nullptr, false,
+                         false, g.version == 0));
+    } else if (p < 0) {
       CHK(launch_init_state(g, s, true));
       CHK(launch_scan_gcc(g, tu[i], tl[i], pull, s));
       TRY(pull_peel_pack(g, kGCC, tu[i], tl[i], pull, out, s, &launches));

@@ -403,9 +403,11 @@ __global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
     if (i != keep_word) words[i] = 0;
 }
 
-hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s) {
+hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
+                                  bool keep_abort) {
   PeelArgs a = make_args(g, thrU, thrL);
-  scan_reset_gcc_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, g.deg0, g.alive_bits, g.n, -1);
+  const int keep = keep_abort ? (int)(offsetof(PeelState, abort_flag) / 4) : -1;
+  scan_reset_gcc_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, g.deg0, g.alive_bits, g.n, keep);
   return hipGetLastError();
 }
 

@@ -84,6 +84,24 @@ def test_chung_lu_batch_modes_and_replay():
     g.destroy()
 
 
+def test_batch_many_roots():
+    """Mutually incomparable thresholds make every query a root of the plan
+    (each runs the single-query path on the degree-rank copy); queries that
+    dominate them nest under those roots."""
+    spec = bigraph_gen.scaled(4, 0.01)
+    eu, ev = bigraph_gen.make_graph(spec)
+    nU, nL = spec["n_upper"], spec["n_lower"]
+    g = pkg.abcore_build_csr(nU, nL, to_dev(eu), to_dev(ev))
+    ref = oracle.Graph(nU, nL, eu, ev)
+    alphas = [1, 2, 4, 8, 16, 32, 64, 128, 5, 9, 17, 40, 130]
+    betas = [128, 64, 32, 16, 8, 4, 2, 1, 33, 17, 9, 5, 2]
+    parent, _, _ = pkg.abcore_batch_plan(alphas, betas)
+    assert sum(1 for p in parent if p < 0) == 8
+    say("batch: eight roots and five nested queries")
+    _check_batch(g, ref, alphas, betas, "roots")
+    g.destroy()
+
+
 def test_batch_after_updates():
     spec = dict(kind="chung_lu", n_upper=3000, n_lower=2000, m=15_000, gamma_upper=2.1,
                 gamma_lower=2.1, cap=400, seed=402)
