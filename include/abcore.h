@@ -58,6 +58,9 @@ typedef struct {
   int64_t uncertain;      /* GCC+: vertices with delta_l <= core < delta_q */
   int64_t launches;       /* kernels launched for the peel phase */
   int64_t pulled;         /* 1 if the first round ran in pull form */
+  int64_t rank_order;     /* 1 if the query ran on the degree-rank relabelling
+                             of an unchanged graph (survivors of the scan are
+                             the vertices of degree >= threshold, Sec. IV-A) */
 } abcore_stats;
 
 /* One edge update for the on-the-fly query (Problem 2, Sec. III). */
@@ -237,14 +240,21 @@ abcore_status abcore_serve_stop(abcore_graph g, int64_t *counters);
  *   ABCORE_OPT_PULL      : first GCC round in pull form: 0 = decided on the
  *                          device from the scan frontier, 1 = never, 2 = always.
  *   ABCORE_OPT_CLAIM     : queue slots a wave of the asynchronous peel takes
- *                          at a time, 1..64 (0 = 32). */
+ *                          at a time, 1..64 (0 = 32).
+ *   ABCORE_OPT_RANK_ORDER: 1 (default) = a GCC query whose first round is
+ *                          pulled runs on the degree-rank relabelling of the
+ *                          graph while it is unchanged since the build (the
+ *                          scan's survivors are then known in advance, Sec.
+ *                          IV-A); 2 = always in vertex order.
+ */
 enum {
   ABCORE_OPT_PEEL_MODE = 1,
   ABCORE_OPT_GRID = 2,
   ABCORE_OPT_ROUNDS_PER_SYNC = 3,
   ABCORE_OPT_TIMING = 4,
   ABCORE_OPT_PULL = 5,
-  ABCORE_OPT_CLAIM = 6
+  ABCORE_OPT_CLAIM = 6,
+  ABCORE_OPT_RANK_ORDER = 7
 };
 abcore_status abcore_set_option(abcore_graph g, int32_t option, int64_t value);
 

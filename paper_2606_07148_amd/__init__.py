@@ -25,6 +25,7 @@ ABCORE_OPT_ROUNDS_PER_SYNC = 3
 ABCORE_OPT_TIMING = 4
 ABCORE_OPT_PULL = 5
 ABCORE_OPT_CLAIM = 6
+ABCORE_OPT_RANK_ORDER = 7
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOENT", 5: "EEXIST",
           6: "EBUSY", 7: "EAGAIN"}
@@ -41,7 +42,7 @@ class abcore_stats(ctypes.Structure):
     _fields_ = [("removed", ctypes.c_int64), ("rounds", ctypes.c_int64),
                 ("entries_read", ctypes.c_int64), ("initial", ctypes.c_int64),
                 ("uncertain", ctypes.c_int64), ("launches", ctypes.c_int64),
-                ("pulled", ctypes.c_int64)]
+                ("pulled", ctypes.c_int64), ("rank_order", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

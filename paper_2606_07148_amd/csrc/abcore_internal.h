@@ -184,7 +184,9 @@ struct Graph {
   // layer in the order of decreasing degree (ties by id); rank_vtx maps the
   // global rank R (a layer's ranks follow its first unified id) back to the
   // vertex.  rcols holds the rows in rank order (row R at roff[R]), each as
-  // its neighbours' ranks, ascending.  A scan leaves alive exactly the K
+  // its neighbours' global ranks, ascending: the rank rows are the graph
+  // relabelled by rank, a layer's vertices keeping their id range.  A scan
+  // leaves alive exactly the K
   // vertices of a layer with degree >= its threshold, i.e. ranks [0, K): the
   // surviving rows are a prefix of the rank order (the split rows first),
   // and a row's surviving neighbours are the prefix of its rank row below
@@ -194,6 +196,20 @@ struct Graph {
   int32_t *rank_vtx = nullptr;  // n
   int64_t *roff = nullptr;      // n + 1
   int32_t *rcols = nullptr;     // 2*m_csr
+  // The rank rows' pieces (as piece_row/start/first for the vertex rows), and
+  // per layer, indexed by a threshold t <= its largest degree + 1, the
+  // vertices of degree >= t (K) and their entries (host copies): a query on
+  // an unchanged graph runs in rank order, its survivors known in advance.
+  int32_t *rp_row = nullptr;    // npieces
+  int64_t *rp_start = nullptr;  // npieces
+  int32_t *rp_first = nullptr;  // n
+  std::vector<int64_t> rk_cnt[2], rk_ent[2];
+  // Working degrees of a query in rank order, at hashed slots: the hubs lead
+  // each layer's ranks and would otherwise share cache lines and channels
+  // under the peel's atomics (rdeg_mask + 1 entries, a power of two >= n).
+  int32_t *rdeg = nullptr;
+  uint32_t rdeg_mask = 0;
+  bool rank_order = true;  // ABCORE_OPT_RANK_ORDER
   // Pull round work split: workgroup k of a cu_count grid walks the upper
   // rows [b[k], b[k+1]) and the lower rows [b[G+1+k], b[G+2+k]), ranges of
   // equal weight (entries of unsplit rows plus a per-row cost).
@@ -290,6 +306,16 @@ struct PeelArgs {
   // vertices alive after the scan (bit set; nullable): GCC skips decrements
   // of the scan frontier, which is out of the core whatever its degree
   const uint32_t *alive0;
+  // Rank order (klim_u >= 0): ids are global ranks, the scan's survivors are
+  // the ranks below klim_u (upper) and nU + klim_l (lower), which replaces
+  // alive0.  pack_vtx (global rank -> vertex, non-null in rank order): the
+  // result bitmask already holds the scan's survivors and the peel clears
+  // each vertex it removes (no pack after termination).
+  int32_t klim_u, klim_l;
+  const int32_t *pack_vtx;
+  // Rank order: a rank's degree sits at slot (rank * kRankMul) & rs_mask of
+  // a power-of-two array (0: the degree array is indexed by id).
+  uint32_t rs_mask;
   int64_t n;
   int32_t nU;
   int32_t thrU, thrL;
@@ -317,8 +343,15 @@ hipError_t launch_scan_nested(Graph &g, int32_t pU, int32_t pL, int32_t thrU, in
                               hipStream_t s, uint32_t *bits = nullptr);
 // queue_f0: the scan did not queue its frontier (launch_scan_reset_gcc);
 // a pushed first round then queues it from the bitmap.
+// rank_bits (a query in rank order): the survivor bitmap goes there (the
+// result bitmask) and nothing else is computed but the reset.
 hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
-                                  bool keep_abort = false);
+                                  bool keep_abort = false, uint32_t *rank_bits = nullptr);
+// A GCC query in rank order (g.rcols and g.rp_* present, unchanged graph):
+// part 0 is the pulled first round, part 1 the asynchronous peel with the
+// pack into pack_bits; ku and kl are the layers' survivor counts.
+hipError_t launch_rank_query(Graph &g, int32_t thrU, int32_t thrL, int64_t ku, int64_t kl,
+                             uint32_t *pack_bits, hipStream_t s, int part);
 // GCC+: the classification, fused with the workspace reset, that prepares
 // a pull round (rowbits = g.row_bits, force = true) as its initialisation.
 hipError_t launch_classify_reset(Graph &g, int32_t thrU, int32_t thrL, int32_t dl, int32_t dq,

@@ -136,7 +136,8 @@ void free_graph(Graph *g) {
                   g->delta.next, g->delta.other, g->alive_bits,  g->part,
                   g->piece_row,  g->piece_start, g->piece_first, g->heavy_rows,
                   g->pull_bounds, g->row_bits,    g->split_written, g->rank,
-                  g->rcols,       g->rank_vtx,    g->roff};
+                  g->rcols,       g->rank_vtx,    g->roff,        g->rp_row,
+                  g->rp_start,    g->rp_first,    g->rdeg};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   if (g->h_state) (void)hipHostFree(g->h_state);
@@ -247,6 +248,25 @@ abcore_status run_peel(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, hipS
 // device decides so), the peel to completion and, when bits is given, the
 // bitmask.  In the asynchronous mode the pull round's completion (split
 // rows below their threshold) and the pack run inside the peel kernel.
+// Survivor counts of a query in rank order: ku upper and kl lower vertices
+// of degree >= their threshold, and the entries of the other vertices (what
+// pushing them would cost).  False when the graph has changed since the
+// build or has no rank relabelling.
+bool rank_counts(const Graph &g, int32_t thrU, int32_t thrL, int64_t &ku, int64_t &kl,
+                 int64_t &f0deg) {
+  if (g.version != 0 || g.delta.count > 0 || g.rcols == nullptr || g.rp_first == nullptr ||
+      g.rdeg == nullptr ||
+      g.rk_cnt[0].empty() || g.rk_cnt[1].empty())
+    return false;
+  auto at = [](const std::vector<int64_t> &v, int32_t t) {
+    return t >= 0 && (size_t)t < v.size() ? v[t] : 0;
+  };
+  ku = at(g.rk_cnt[0], thrU);
+  kl = at(g.rk_cnt[1], thrL);
+  f0deg = 2 * g.m_csr - at(g.rk_ent[0], thrU) - at(g.rk_ent[1], thrL);
+  return true;
+}
+
 abcore_status pull_peel_pack(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, bool pull,
                              uint32_t *bits, hipStream_t s, int64_t *launches,
                              bool queue_f0 = false, const uint32_t *rowbits = nullptr,
@@ -678,6 +698,13 @@ abcore_status abcore_set_option(abcore_graph h, int32_t option, int64_t value) {
       }
       g->pull_mode = (int)value;
       return ABCORE_OK;
+    case ABCORE_OPT_RANK_ORDER:
+      if (value > 2) {
+        set_error("abcore_set_option: rank order mode %lld unknown", (long long)value);
+        return ABCORE_EINVAL;
+      }
+      g->rank_order = value != 2;
+      return ABCORE_OK;
     case ABCORE_OPT_CLAIM:
       if (value > kWave) {
         set_error("abcore_set_option: claim %lld above %d", (long long)value, kWave);
@@ -775,9 +802,31 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
   const int32_t thrU = clamp_thr(alpha), thrL = clamp_thr(beta);
   int64_t launches = 0;
   bool plus_pull = false;  // GCC+ initialised by a pull round
+  bool rank_order = false;
+  int64_t ku = 0, kl = 0, f0deg = 0;
   if (algo == ABCORE_GCC) {
     const bool pull = g->pull_mode != 1;
-    if (pull && g->peel_mode == 3) {
+    // On an unchanged graph the scan's survivors are known in advance (the
+    // ranks below K of each layer) and so are the frontier's entries: a
+    // pulled first round then runs in rank order, without a scan.
+    rank_order = pull && g->peel_mode == 3 && g->rank_order &&
+                 rank_counts(*g, thrU, thrL, ku, kl, f0deg) &&
+                 (g->pull_mode == 2 || (f0deg > 0 && f0deg * 2 >= ku + kl));
+    if (rank_order) {
+      // the scan only writes the survivor bitmap into the result (the peel
+      // clears the vertices it removes) and resets the workspace
+      CHK(timed(*g, ABCORE_KERNEL_SCAN, s, 1, [&] {
+        return d_bitmask ? launch_scan_reset_gcc(*g, thrU, thrL, s, false, d_bitmask)
+                         : launch_init_state(*g, s);
+      }));
+      CHK(timed(*g, ABCORE_KERNEL_PULL, s, 1, [&] {
+        return launch_rank_query(*g, thrU, thrL, ku, kl, d_bitmask, s, 0);
+      }));
+      CHK(timed(*g, ABCORE_KERNEL_PEEL, s, 1, [&] {
+        return launch_rank_query(*g, thrU, thrL, ku, kl, d_bitmask, s, 1);
+      }));
+      launches += 1;
+    } else if (pull && g->peel_mode == 3) {
       // scan and workspace reset in one launch; the frontier is queued only
       // if the first round is pushed (by the pull kernel, from the bitmap)
       CHK(timed(*g, ABCORE_KERNEL_SCAN, s, 1,
@@ -837,7 +886,9 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
     // GCC: the scan frontier (its per-workgroup counts; it need not be
     // queued).  GCC+: the uncertain vertices below their threshold after the
     // initialisation, and the uncertain count.
-    if (!plus)
+    if (rank_order)
+      stats->initial = g->n - ku - kl;
+    else if (!plus)
       stats->initial = sum_part(*g, kPartF0, s, &st);
     else if (plus_pull)
       stats->initial = sum_part(*g, kPartF1, s, &st);
@@ -848,6 +899,7 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
     if (st != ABCORE_OK) return st;
     stats->launches = launches;
     stats->pulled = p.pulled;
+    stats->rank_order = rank_order ? 1 : 0;
   }
   return ABCORE_OK;
 }

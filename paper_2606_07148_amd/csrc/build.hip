@@ -342,12 +342,32 @@ __global__ void entry_keys_kernel(const int64_t *__restrict__ off, const int32_t
   }
 }
 
+// The neighbour's global rank: a lower neighbour (of an upper row) is its
+// layer rank past nU, so that the rank rows form a CSR graph of their own.
 __global__ void entry_unkey_kernel(const uint64_t *__restrict__ keys, int64_t cnt, int rbits,
-                                   int32_t *__restrict__ rcols) {
+                                   int64_t nU, int32_t *__restrict__ rcols) {
   const uint64_t mask = (1ull << rbits) - 1;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride)
-    rcols[i] = (int32_t)(keys[i] & mask);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
+    const bool upper_row = (int64_t)(keys[i] >> rbits) < nU;
+    rcols[i] = (int32_t)((int64_t)(keys[i] & mask) + (upper_row ? nU : 0));
+  }
+}
+
+// Degree counts by threshold, from the rank order (degrees decrease along a
+// layer's ranks): at the last rank of each run of equal degrees d, the
+// layer's vertices of degree >= d and their entries.
+__global__ void rank_table_kernel(const int64_t *__restrict__ roff, int64_t lo, int64_t hi,
+                                  int64_t *__restrict__ ge_cnt, int64_t *__restrict__ ge_ent) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < hi; r += stride) {
+    const int64_t d = roff[r + 1] - roff[r];
+    const int64_t dn = r + 1 < hi ? roff[r + 2] - roff[r + 1] : -1;
+    if (d != dn) {
+      ge_cnt[d] = r + 1 - lo;
+      ge_ent[d] = roff[r + 1] - roff[lo];
+    }
+  }
 }
 
 }  // namespace
@@ -375,6 +395,8 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
     if (fail(hipMalloc(&g.rank_vtx, sizeof(int32_t) * g.n))) break;
     if (fail(hipMalloc(&g.roff, sizeof(int64_t) * (g.n + 1)))) break;
     if (fail(hipMalloc(&g.rcols, sizeof(int32_t) * std::max<int64_t>(ent, 1)))) break;
+    g.rdeg_mask = (uint32_t)((1ull << xbits) - 1);
+    if (fail(hipMalloc(&g.rdeg, sizeof(int32_t) * ((size_t)g.rdeg_mask + 1)))) break;
     // k0 also holds the degrees by rank (n + 1 values after n + 1 slots)
     if (fail(hipMalloc(&k0, sizeof(uint64_t) * std::max<int64_t>(items, 2 * (g.n + 1))))) break;
     if (fail(hipMalloc(&k1, sizeof(uint64_t) * items))) break;
@@ -416,9 +438,82 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
       size_t tb = temp_bytes;
       if (fail(hipcub::DeviceRadixSort::SortKeys(temp, tb, k0, k1, (int)ent, 0, rbits + xbits, s)))
         break;
-      entry_unkey_kernel<<<grid, 256, 0, s>>>(k1, ent, rbits, g.rcols);
+      entry_unkey_kernel<<<grid, 256, 0, s>>>(k1, ent, rbits, g.nU, g.rcols);
       if (fail(hipGetLastError())) break;
     }
+    // the rank rows' pieces (the same lengths as the vertex rows', in rank
+    // order; k0 and k1 serve as the counts and their scans)
+    {
+      int64_t *np = reinterpret_cast<int64_t *>(k0), *hv = np + (g.n + 1);
+      int64_t *hfirst = nullptr;
+      if (fail(hipMalloc(&hfirst, sizeof(int64_t) * 2 * (g.n + 1)))) break;
+      int32_t *hrows = nullptr;
+      bool pok = false;
+      do {
+        int64_t *fcopy = hfirst + (g.n + 1);
+        count_pieces_kernel<<<grid, 256, 0, s>>>(g.roff, g.n, np, hv);
+        if (fail(hipGetLastError())) break;
+        size_t tb = temp_bytes;
+        if (fail(hipcub::DeviceScan::ExclusiveSum(temp, tb, np, fcopy, (int)(g.n + 1), s))) break;
+        tb = temp_bytes;
+        if (fail(hipcub::DeviceScan::ExclusiveSum(temp, tb, hv, hfirst, (int)(g.n + 1), s))) break;
+        if (fail(hipMalloc(&g.rp_row, sizeof(int32_t) * std::max<int64_t>(g.npieces, 1)))) break;
+        if (fail(hipMalloc(&g.rp_start, sizeof(int64_t) * std::max<int64_t>(g.npieces, 1))))
+          break;
+        if (fail(hipMalloc(&g.rp_first, sizeof(int32_t) * g.n))) break;
+        if (fail(hipMalloc(&hrows, sizeof(int32_t) * std::max<int64_t>(g.nheavy, 1)))) break;
+        fill_pieces_kernel<<<grid, 256, 0, s>>>(g.roff, g.n, fcopy, hfirst, g.rp_row, g.rp_start,
+                                                g.rp_first, hrows);
+        if (fail(hipGetLastError())) break;
+        pok = true;
+      } while (0);
+      if (fail(hipStreamSynchronize(s))) pok = false;
+      if (hrows) (void)hipFree(hrows);
+      (void)hipFree(hfirst);
+      if (!pok) {
+        ok = false;
+        break;
+      }
+    }
+    // per layer and threshold t: the vertices of degree >= t (ranks [0, K))
+    // and their entries, kept on the host
+    for (int layer = 0; layer < 2 && ok; ++layer) {
+      const int64_t lo = layer == 0 ? 0 : g.nU, hi = layer == 0 ? g.nU : g.n;
+      g.rk_cnt[layer].assign(1, 0);
+      g.rk_ent[layer].assign(1, 0);
+      if (hi <= lo) continue;
+      int64_t r01[2] = {0, 0};
+      if (fail(hipMemcpyAsync(r01, g.roff + lo, sizeof(int64_t) * 2, hipMemcpyDeviceToHost, s)))
+        break;
+      if (fail(hipStreamSynchronize(s))) break;
+      const int64_t maxdeg = r01[1] - r01[0];
+      // (k0 and k1 are free again and hold at least n + 1 values each)
+      int64_t *gc = reinterpret_cast<int64_t *>(k0), *ge = reinterpret_cast<int64_t *>(k1);
+      if (maxdeg + 1 > g.n + 1) {
+        ok = false;
+        break;
+      }
+      if (fail(hipMemsetAsync(gc, 0xFF, sizeof(int64_t) * (maxdeg + 1), s))) break;
+      rank_table_kernel<<<grid, 256, 0, s>>>(g.roff, lo, hi, gc, ge);
+      if (fail(hipGetLastError())) break;
+      std::vector<int64_t> hc(maxdeg + 1), he(maxdeg + 1);
+      if (fail(hipMemcpyAsync(hc.data(), gc, sizeof(int64_t) * (maxdeg + 1),
+                              hipMemcpyDeviceToHost, s)))
+        break;
+      if (fail(hipMemcpyAsync(he.data(), ge, sizeof(int64_t) * (maxdeg + 1),
+                              hipMemcpyDeviceToHost, s)))
+        break;
+      if (fail(hipStreamSynchronize(s))) break;
+      // a degree no vertex has takes the counts of the next larger one
+      std::vector<int64_t> &kc = g.rk_cnt[layer], &ke = g.rk_ent[layer];
+      kc.assign(maxdeg + 2, 0);
+      ke.assign(maxdeg + 2, 0);
+      for (int64_t t = maxdeg; t >= 0; --t) {
+        kc[t] = hc[t] >= 0 ? hc[t] : kc[t + 1];
+        ke[t] = hc[t] >= 0 ? he[t] : ke[t + 1];
+      }
+    }
+    if (!ok) break;
     if (fail(hipStreamSynchronize(s))) break;
   } while (0);
   if (k0) (void)hipFree(k0);
@@ -430,10 +525,23 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
     if (g.rank_vtx) (void)hipFree(g.rank_vtx);
     if (g.roff) (void)hipFree(g.roff);
     if (g.rcols) (void)hipFree(g.rcols);
+    if (g.rdeg) (void)hipFree(g.rdeg);
+    g.rdeg = nullptr;
+    g.rdeg_mask = 0;
+    if (g.rp_row) (void)hipFree(g.rp_row);
+    if (g.rp_start) (void)hipFree(g.rp_start);
+    if (g.rp_first) (void)hipFree(g.rp_first);
     g.rank = nullptr;
     g.rank_vtx = nullptr;
     g.roff = nullptr;
     g.rcols = nullptr;
+    g.rp_row = nullptr;
+    g.rp_start = nullptr;
+    g.rp_first = nullptr;
+    for (int layer = 0; layer < 2; ++layer) {
+      g.rk_cnt[layer].clear();
+      g.rk_ent[layer].clear();
+    }
   }
   return ABCORE_OK;
 }

@@ -144,6 +144,10 @@ PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL) {
   a.pack_bits = nullptr;
   a.start_expect = 0;
   a.alive0 = nullptr;
+  a.klim_u = -1;
+  a.klim_l = -1;
+  a.pack_vtx = nullptr;
+  a.rs_mask = 0;
   a.n = g.n;
   a.nU = g.nU;
   a.thrU = thrU;
@@ -166,6 +170,14 @@ __device__ __forceinline__ int32_t piece_item(int32_t p) { return -(p + 2); }
 
 // Row, entry range and "first piece" flag of an item (x < 0 with x != -1 is
 // a piece; -1 is an empty lane).
+// The degree slot of vertex (or, in rank order, rank) x.  In rank order
+// consecutive ranks map to slots far apart (an odd multiplier is a bijection
+// modulo a power of two).
+constexpr uint32_t kRankMul = 0x9E3779B1u;
+__device__ __forceinline__ int32_t deg_slot(const PeelArgs &a, int32_t x) {
+  return a.rs_mask != 0 ? (int32_t)(((uint32_t)x * kRankMul) & a.rs_mask) : x;
+}
+
 __device__ __forceinline__ void decode_item(const PeelArgs &a, int32_t x, int32_t &row,
                                             int64_t &s, int &d, bool &first) {
   row = -1;
@@ -327,9 +339,12 @@ hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, bool want_bits,
 // instead).  Every workgroup first returns its share of the previous
 // computation's queue prefixes to kEmpty and zeroes its partial slots; the
 // last one to finish zeroes the state (all cursors were read by then).
+// rank_bits: a query in rank order, which needs only the survivor bitmap
+// (written into the result bitmask, from which the peel clears the vertices
+// it removes): no degrees are copied and no counts kept.
 __global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
     PeelArgs a, const int32_t *__restrict__ deg0, uint32_t *__restrict__ bits, int64_t n,
-    int keep_word) {
+    int keep_word, int rank_bits) {
   __shared__ int64_t s_acc;
   PeelState *st = a.st;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -348,7 +363,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
       bool p[4] = {false, false, false, false};
       if (x0 + 3 < n) {
         const int4 v = *reinterpret_cast<const int4 *>(deg0 + x0);
-        *reinterpret_cast<int4 *>(a.deg + x0) = v;
+        if (!rank_bits) *reinterpret_cast<int4 *>(a.deg + x0) = v;
         d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
 #pragma unroll
         for (int j = 0; j < 4; ++j) p[j] = d[j] < ((x0 + j) < a.nU ? a.thrU : a.thrL);
@@ -358,7 +373,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
           const int64_t x = x0 + j;
           if (x < n) {
             d[j] = deg0[x];
-            a.deg[x] = d[j];
+            if (!rank_bits) a.deg[x] = d[j];
             p[j] = d[j] < (x < a.nU ? a.thrU : a.thrL);
           }
         }
@@ -388,10 +403,12 @@ __global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
       if ((lane_id() & 7) == 0 && x0 < n) bits[x0 / 32] = w;
     }
   }
-  add_part(a.part, kPartF0, f0, &s_acc);
-  add_part(a.part, kPartF0Deg, f0deg, &s_acc);
-  add_part(a.part, kPartAliveU, alive_u, &s_acc);
-  add_part(a.part, kPartAliveL, alive_l, &s_acc);
+  if (!rank_bits) {
+    add_part(a.part, kPartF0, f0, &s_acc);
+    add_part(a.part, kPartF0Deg, f0deg, &s_acc);
+    add_part(a.part, kPartAliveU, alive_u, &s_acc);
+    add_part(a.part, kPartAliveL, alive_l, &s_acc);
+  }
   __syncthreads();
   if (wave_in_block() != 0) return;
   int last = 0;
@@ -404,10 +421,11 @@ __global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
 }
 
 hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
-                                  bool keep_abort) {
+                                  bool keep_abort, uint32_t *rank_bits) {
   PeelArgs a = make_args(g, thrU, thrL);
   const int keep = keep_abort ? (int)(offsetof(PeelState, abort_flag) / 4) : -1;
-  scan_reset_gcc_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, g.deg0, g.alive_bits, g.n, keep);
+  scan_reset_gcc_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(
+      a, g.deg0, rank_bits ? rank_bits : g.alive_bits, g.n, keep, rank_bits ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -705,6 +723,14 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
   int d;
   bool first;
   decode_item(a, x, row, s, d, first);
+  if (LAZY && a.pack_vtx != nullptr && a.pack_bits != nullptr && x >= 0) {
+    // rank order: the result bitmask holds the scan's survivors; a removed
+    // vertex is taken here exactly once (its rank), so its bit is cleared
+    // here, off the removal chain (no return value is waited for), and no
+    // pack follows termination
+    const int32_t v = a.pack_vtx[x];
+    atomicAnd(&a.pack_bits[v >> 5], ~(1u << (v & 31)));
+  }
   if (LAZY) {
     const bool split = x >= 0 && d > kPiece;
     if (__ballot(split)) {
@@ -770,7 +796,10 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
       // frontier (a small, cache-resident bitmap) needs none
       if (KIND == kGCC && a.alive0 != nullptr && w[u] >= 0)
         live = live && ((a.alive0[w[u] >> 5] >> (w[u] & 31)) & 1u);
-      push[u] = live && atomicSub(&a.deg[w[u]], 1) == t[u];
+      // in rank order the scan's survivors are a prefix of each layer
+      if (KIND == kGCC && a.klim_u >= 0)
+        live = live && (w[u] < a.nU ? w[u] < a.klim_u : w[u] - a.nU < a.klim_l);
+      push[u] = live && atomicSub(&a.deg[deg_slot(a, w[u])], 1) == t[u];
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
@@ -1150,7 +1179,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
     // its range here (every workgroup writes the same final cursors)
     st_agent(&a.st->hi[threadIdx.x], ld_agent(&a.st->tail[threadIdx.x][0]));
   }
-  if (a.pack_bits != nullptr && ld_agent(&a.st->abort_flag) == 0) {
+  if (a.pack_bits != nullptr && a.pack_vtx == nullptr && ld_agent(&a.st->abort_flag) == 0) {
     // the result (Algorithm 1's V(G)): termination means every decrement
     // is done; degrees are read at device scope (they changed by atomics)
     // kPackSpan consecutive vertices per lane pass, all loads issued before
@@ -1374,7 +1403,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     const int32_t *__restrict__ bounds, int queue_f0, const uint32_t *__restrict__ rowbits,
     int rest_part, const int32_t *__restrict__ written_snap, const int32_t *__restrict__ rcols,
     const int32_t *__restrict__ rank_vtx, const int64_t *__restrict__ roff, int64_t nheavy,
-    int64_t nheavy_upper) {
+    int64_t nheavy_upper, int rspace, int64_t rk_u, int64_t rk_l) {
   extern __shared__ __align__(16) uint32_t s_bits[];
   __shared__ PullShared sh;
   // Each phase walks one layer's rows; its bitmap of the other layer is
@@ -1420,8 +1449,9 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     // half as many as the survivors
     int64_t ku = 0, kl = 0;
     if (rcols != nullptr) {
-      ku = wave_sum_strided(a.part + kPartAliveU, scan_blocks, kPartFields);
-      kl = wave_sum_strided(a.part + kPartAliveL, scan_blocks, kPartFields);
+      // (known in advance for a query in rank order)
+      ku = rk_u >= 0 ? rk_u : wave_sum_strided(a.part + kPartAliveU, scan_blocks, kPartFields);
+      kl = rk_l >= 0 ? rk_l : wave_sum_strided(a.part + kPartAliveL, scan_blocks, kPartFields);
       if (lane_id() == 0) {
         sh.k_alive[0] = (int32_t)ku;
         sh.k_alive[1] = (int32_t)kl;
@@ -1507,9 +1537,12 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
       // surviving neighbours are its rank row's prefix below kb.  Chunks of
       // 64 ranks are dealt to the workgroups in turn (workgroup k takes
       // chunks k, k + G, ...), its waves claiming them through LDS.
+      // (rank order, rspace: the rank rows are the rows, a row's degree is
+      // written at its rank and a removed row is queued as its rank)
       const int64_t base = phase == 0 ? 0 : a.nU;
       const int64_t kself = sh.k_alive[phase];
-      const int32_t kb = sh.k_alive[phase ^ 1];
+      // neighbours are global ranks: an upper row's lie past nU
+      const int32_t kb = sh.k_alive[phase ^ 1] + (phase == 0 ? a.nU : 0);
       const int64_t nh = phase == 0 ? nheavy_upper : nheavy - nheavy_upper;
       const int64_t hend = base + min(nh, kself), lend = base + kself;
       auto below = [kb](int32_t v) { return (uint32_t)(v >= 0 && v < kb); };
@@ -1524,7 +1557,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
         int64_t s = 0;
         int d = 0;
         if (alive) {
-          x = rank_vtx[r];
+          x = rspace ? (int32_t)r : rank_vtx[r];
           s = roff[r];
           d = (int)(roff[r + 1] - s);
         }
@@ -1536,7 +1569,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
         bool push = false;
         if (alive) {
           entries += d;
-          a.deg[x] = c;
+          a.deg[deg_slot(a, x)] = c;
           push = c < (x < a.nU ? a.thrU : a.thrL);
           f1 += push ? 1 : 0;
         }
@@ -1559,7 +1592,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
         const bool alive = r < hend;
         int lo = 0, hi = 0;
         if (alive) {
-          x = rank_vtx[r];
+          x = rspace ? (int32_t)r : rank_vtx[r];
           s = roff[r];
           hi = (int)(roff[r + 1] - s);
         }
@@ -1582,7 +1615,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
         const int cnt_row = lo + __popcll((__ballot(t) >> (16 * grp)) & 0xFFFFull);
         bool push = false;
         if (alive && l == 0) {
-          a.deg[x] = cnt_row;
+          a.deg[deg_slot(a, x)] = cnt_row;
           push = cnt_row < (x < a.nU ? a.thrU : a.thrL);
           f1 += push ? 1 : 0;
           entries += 64;
@@ -1768,13 +1801,13 @@ hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *b
         a, bits, g.deg0, g.n, scan_grid(g), mode, 1, total_entries, g.npieces,
         g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0,
         rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr, rcols, g.rank_vtx,
-        g.roff, g.nheavy, g.nheavy_upper);
+        g.roff, g.nheavy, g.nheavy_upper, 0, -1, -1);
   else
     pull_round_kernel<false><<<grid, kPullBlock, dyn, s>>>(
         a, bits, g.deg0, g.n, scan_grid(g), mode, 0, total_entries, g.npieces,
         g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0,
         rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr, rcols, g.rank_vtx,
-        g.roff, g.nheavy, g.nheavy_upper);
+        g.roff, g.nheavy, g.nheavy_upper, 0, -1, -1);
   return hipGetLastError();
 }
 
@@ -1783,6 +1816,40 @@ hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s
                              bool rest_part, bool rank) {
   return launch_pull_round_args(g, make_args(g, thrU, thrL), g.alive_bits, nullptr, nullptr, 0,
                                 advance, s, queue_f0, rowbits, force, rest_part, rank);
+}
+
+// A query in rank order (unchanged graph): the first round pulled on the
+// rank rows, whose survivors are ranks [0, ku) and [nU, nU + kl), then the
+// asynchronous peel and the pack on the rank rows.  The workspace must have
+// been reset.
+hipError_t launch_rank_query(Graph &g, int32_t thrU, int32_t thrL, int64_t ku, int64_t kl,
+                             uint32_t *pack_bits, hipStream_t s, int part) {
+  if (part == 0) {
+    PeelArgs a = make_args(g, thrU, thrL);
+    a.ins_head = nullptr;
+    a.deg = g.rdeg;
+    a.rs_mask = g.rdeg_mask;
+    const int grid = g.cu_count;
+    pull_round_kernel<false><<<grid, kPullBlock, 0, s>>>(
+        a, g.alive_bits, g.deg0, g.n, scan_grid(g), 2, 0, 2 * g.m, g.npieces, g.npieces_upper,
+        nullptr, nullptr, 0, 0, nullptr, 0, g.alive_bits, 0, nullptr, g.rcols, g.rank_vtx, g.roff,
+        g.nheavy, g.nheavy_upper, 1, ku, kl);
+    return hipGetLastError();
+  }
+  PeelArgs a = make_args(g, thrU, thrL);
+  a.off = g.roff;
+  a.cols = g.rcols;
+  a.piece_row = g.rp_row;
+  a.piece_start = g.rp_start;
+  a.piece_first = g.rp_first;
+  a.ins_head = nullptr;
+  a.klim_u = (int32_t)ku;
+  a.klim_l = (int32_t)kl;
+  a.pack_vtx = g.rank_vtx;
+  a.pack_bits = pack_bits;
+  a.deg = g.rdeg;
+  a.rs_mask = g.rdeg_mask;
+  return launch_peel_async_args(g, kGCC, a, async_peel_grid(g), s);
 }
 
 // Must follow the pull round on the same stream (it completes that round).

@@ -129,6 +129,42 @@ def test_chung_lu_small_grid(seed, peel, pull):
     g.destroy()
 
 
+def test_rank_order_queries():
+    """GCC queries on an unchanged graph run on its degree-rank relabelling
+    (survivors of the scan = the vertices of degree >= threshold, a prefix of
+    each layer's rank order); after an update they run in vertex order.  Both
+    equal the oracle; the first frontier counts the scan's frontier."""
+    nU, nL, m = 30_000, 20_000, 400_000
+    eu, ev = bigraph_gen.chung_lu(nU, nL, m, 2.1, 2.1, 5000, 111)
+    g, ref = _make(nU, nL, eu, ev)
+    deg = ref.degrees()
+    pairs = [(1, 1), (2, 3), (5, 5), (4, 9), (9, 4), (12, 30), (64, 64), (1000, 1),
+             (int(deg[:nU].max()), 2), (int(deg[:nU].max()) + 1, 1),
+             (3, int(deg[nU:].max()) + 1), (2**31 - 1, 2**31 - 1)]
+    for pull in (2, 0):
+        pkg.abcore_set_option(g, pkg.ABCORE_OPT_PULL, pull)
+        for a, b in pairs:
+            say("rank order: pull", pull, a, b)
+            st, _ = _check_core(g, ref, a, b, pkg.ABCORE_GCC, f"rank pull{pull}")
+            thr = np.where(np.arange(nU + nL) < nU, a, b)
+            if pull == 2:
+                assert st["rank_order"] == 1 and st["pulled"] == 1, (a, b)
+            if st["rank_order"]:
+                assert st["initial"] == int(np.count_nonzero(deg < thr)), (a, b)
+    # an inserted edge: vertex order from then on
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_PULL, 2)
+    u, v = 0, 0
+    have = set(zip(eu.tolist(), ev.tolist()))
+    while (u, v) in have:
+        v += 1
+    pkg.abcore_query(g, u, v, 1, 1, 1)
+    ref = oracle.Graph(nU, nL, np.append(eu, np.int32(u)), np.append(ev, np.int32(v)))
+    for a, b in [(2, 3), (5, 5), (12, 30)]:
+        st, _ = _check_core(g, ref, a, b, pkg.ABCORE_GCC, "after insert")
+        assert st["rank_order"] == 0
+    g.destroy()
+
+
 def test_repeat_runs_identical():
     eu, ev = bigraph_gen.chung_lu(50_000, 30_000, 600_000, 2.1, 2.1, 8000, 7)
     g = pkg.abcore_build_csr(50_000, 30_000, to_dev(eu), to_dev(ev))
