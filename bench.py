@@ -461,20 +461,22 @@ def main() -> int:
     rank_order = bool(gst.get("rank_order", 0))
     n_f0 = int(f0.sum())
     if rank_order:
-        # the query runs on the degree-rank relabelling: the scan reads deg0
-        # and writes only the survivor bitmap (into the result) and returns
-        # the previous query's queued items to empty; the pull round reads a
-        # light row's offsets (8 B) and entries and writes its degree (4 B),
-        # searches a split row; the peel maps each survivor it removes to
-        # its vertex (4 B) and clears its bit in the result (an 8 B
-        # read-modify-write), so no pack pass follows
+        # the query runs on the degree-rank relabelling, without a scan
+        # launch: the pull round reads a light row's offsets (8 B) and
+        # entries and writes its degree (4 B), searches a split row, and
+        # writes the survivor bitmap into the result (deg0 read, n/8
+        # written); the peel maps each survivor it removes to its vertex
+        # (4 B) and clears its bit in the result (an 8 B read-modify-write),
+        # so no pack pass follows, and after termination returns its queued
+        # items to empty (4 B each) and zeroes the next query's 4096 x 10
+        # partial sums
         a1 = ~f0
         light = a1 & (deg <= 64)
         heavy = a1 & (deg > 64)
         r2n = removed - n_f0
-        scan_bytes = 4 * n + n // 8 + 4 * r2n
+        scan_bytes = 0
         pull_bytes = (12 * int(light.sum()) + 4 * int(deg[light].sum())
-                      + (24 + 4 * 16 * 4) * int(heavy.sum()))
+                      + (24 + 4 * 16 * 4) * int(heavy.sum()) + 4 * n + n // 8)
     elif fused_scan:
         queued = removed - n_f0 if pulled else removed
         scan_bytes = 8 * n + n // 8 + 4 * queued
@@ -491,7 +493,8 @@ def main() -> int:
                           + (24 + 4 * 16 * 4) * int(heavy.sum()) + n // 8)
     else:
         scan_bytes = 8 * n + 4 * n_f0 + (n // 8 if pulled else 0)
-    pack_bytes = 12 * (removed - n_f0) if rank_order else 4 * n + n // 8
+    pack_bytes = (12 * (removed - n_f0) + 4 * (removed - n_f0) + 8 * 4096 * 10 if rank_order
+                  else 4 * n + n // 8)
     kinfo = {}
     peel_name = {1: "peel_round_kernel<0>", 2: "peel_persistent_kernel<0>"}.get(
         args.peel_mode, "peel_async_kernel<0>")  # <0> = the GCC instantiation

@@ -143,6 +143,7 @@ struct BatchCache {
   int version = -1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  int parity = 0;  // Graph::rs_parity when captured (the state it refers to)
 };
 
 struct Graph {
@@ -210,6 +211,14 @@ struct Graph {
   int32_t *rdeg = nullptr;
   uint32_t rdeg_mask = 0;
   bool rank_order = true;  // ABCORE_OPT_RANK_ORDER
+  // Second workspace state and partial sums: queries in rank order alternate
+  // between the two, each leaving the other one zeroed and the queue empty
+  // (rs_ready).  Any other launch through make_args clears rs_ready.
+  PeelState *state_alt = nullptr;
+  int64_t *part_alt = nullptr;
+  int32_t *rs_fail = nullptr;  // device word, see PeelArgs
+  bool rs_ready = false;
+  int rs_parity = 0;  // flips with every exchange of state and state_alt
   // Pull round work split: workgroup k of a cu_count grid walks the upper
   // rows [b[k], b[k+1]) and the lower rows [b[G+1+k], b[G+2+k]), ranges of
   // equal weight (entries of unsplit rows plus a per-row cost).
@@ -316,6 +325,15 @@ struct PeelArgs {
   // Rank order: a rank's degree sits at slot (rank * kRankMul) & rs_mask of
   // a power-of-two array (0: the degree array is indexed by id).
   uint32_t rs_mask;
+  // Rank order (nullable): after termination the peel returns the queue's
+  // used slots to empty and zeroes this state and these partial sums, the
+  // next query's workspace (its own stay readable for the statistics).
+  PeelState *rs_next_st;
+  int64_t *rs_next_part;
+  // Rank order: set when a peel ended without termination (a spin-limit
+  // abort) and so left the queue as it was; later queries in rank order
+  // then abort at once until a preparation clears it.
+  int32_t *rs_fail;
   int64_t n;
   int32_t nU;
   int32_t thrU, thrL;
@@ -352,6 +370,9 @@ hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream
 // pack into pack_bits; ku and kl are the layers' survivor counts.
 hipError_t launch_rank_query(Graph &g, int32_t thrU, int32_t thrL, int64_t ku, int64_t kl,
                              uint32_t *pack_bits, hipStream_t s, int part);
+// Returns the queue's used slots (cursors in g.state) to empty and zeroes
+// g.state_alt and g.part_alt: the workspace a query in rank order expects.
+hipError_t launch_rank_prep(Graph &g, hipStream_t s);
 // GCC+: the classification, fused with the workspace reset, that prepares
 // a pull round (rowbits = g.row_bits, force = true) as its initialisation.
 hipError_t launch_classify_reset(Graph &g, int32_t thrU, int32_t thrL, int32_t dl, int32_t dq,

@@ -137,7 +137,8 @@ void free_graph(Graph *g) {
                   g->piece_row,  g->piece_start, g->piece_first, g->heavy_rows,
                   g->pull_bounds, g->row_bits,    g->split_written, g->rank,
                   g->rcols,       g->rank_vtx,    g->roff,        g->rp_row,
-                  g->rp_start,    g->rp_first,    g->rdeg};
+                  g->rp_start,    g->rp_first,    g->rdeg,        g->state_alt,
+                  g->part_alt,    g->rs_fail};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   if (g->h_state) (void)hipHostFree(g->h_state);
@@ -188,6 +189,7 @@ abcore_status read_state(Graph &g, hipStream_t s) {
   CHK(hipMemcpyAsync(g.h_state, g.state, sizeof(PeelState), hipMemcpyDeviceToHost, s));
   CHK(hipStreamSynchronize(s));
   if (g.h_state->abort_flag) {
+    g.rs_ready = false;  // the next query in rank order prepares the workspace
     set_error("a grid barrier exceeded its spin limit; the result is invalid");
     return ABCORE_EDEVICE;
   }
@@ -599,9 +601,14 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
     if ((st = ensure(&g->alive_bits, (g->n + 31) / 32 + 1)) != ABCORE_OK) break;
     if ((st = ensure(&g->row_bits, (g->n + 31) / 32 + 1)) != ABCORE_OK) break;
     if ((st = ensure(&g->part, (int64_t)kMaxBlocks * kPartFields)) != ABCORE_OK) break;
+    if ((st = ensure(&g->part_alt, (int64_t)kMaxBlocks * kPartFields)) != ABCORE_OK) break;
     hipError_t e = hipMalloc(&g->state, sizeof(PeelState));
     // the state is read (queue tails) by the first initialisation: zero it
     if (e == hipSuccess) e = hipMemsetAsync(g->state, 0, sizeof(PeelState), s);
+    if (e == hipSuccess) e = hipMalloc(&g->state_alt, sizeof(PeelState));
+    if (e == hipSuccess) e = hipMemsetAsync(g->state_alt, 0, sizeof(PeelState), s);
+    if (e == hipSuccess) e = hipMalloc(&g->rs_fail, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemsetAsync(g->rs_fail, 0, sizeof(int32_t), s);
     if (e == hipSuccess) e = hipHostMalloc(&g->h_state, sizeof(PeelState));
     if (e == hipSuccess)
       e = hipHostMalloc(&g->h_part, sizeof(int64_t) * kMaxBlocks * kPartFields);
@@ -813,18 +820,22 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
                  rank_counts(*g, thrU, thrL, ku, kl, f0deg) &&
                  (g->pull_mode == 2 || (f0deg > 0 && f0deg * 2 >= ku + kl));
     if (rank_order) {
-      // the scan only writes the survivor bitmap into the result (the peel
-      // clears the vertices it removes) and resets the workspace
-      CHK(timed(*g, ABCORE_KERNEL_SCAN, s, 1, [&] {
-        return d_bitmask ? launch_scan_reset_gcc(*g, thrU, thrL, s, false, d_bitmask)
-                         : launch_init_state(*g, s);
-      }));
+      // No scan launch: the pull round writes the survivor bitmap into the
+      // result (the peel clears the vertices it removes).  The workspace
+      // alternates between two states; the previous query in rank order left
+      // this one zeroed and the queue empty, else one launch prepares them.
+      if (!g->rs_ready)
+        CHK(timed(*g, ABCORE_KERNEL_SCAN, s, 1, [&] { return launch_rank_prep(*g, s); }));
+      std::swap(g->state, g->state_alt);
+      std::swap(g->part, g->part_alt);
+      g->rs_parity ^= 1;
       CHK(timed(*g, ABCORE_KERNEL_PULL, s, 1, [&] {
         return launch_rank_query(*g, thrU, thrL, ku, kl, d_bitmask, s, 0);
       }));
       CHK(timed(*g, ABCORE_KERNEL_PEEL, s, 1, [&] {
         return launch_rank_query(*g, thrU, thrL, ku, kl, d_bitmask, s, 1);
       }));
+      g->rs_ready = true;
       launches += 1;
     } else if (pull && g->peel_mode == 3) {
       // scan and workspace reset in one launch; the frontier is queued only
@@ -991,9 +1002,19 @@ abcore_status abcore_compute_batch(abcore_graph h, const uint32_t *h_alpha,
     }
     c.graph = graph;
     c.exec = exec;
+    c.parity = g->rs_parity;
     c.bits = d_bitmasks;
     c.version = g->version;
     c.key = std::move(key);
+  }
+  // the replay uses the queue without passing through make_args, and the
+  // state captured: make that one current again if queries in rank order
+  // have exchanged the two since
+  g->rs_ready = false;
+  if (g->rs_parity != c.parity) {
+    std::swap(g->state, g->state_alt);
+    std::swap(g->part, g->part_alt);
+    g->rs_parity ^= 1;
   }
   CHK(hipGraphLaunch(c.exec, s));
   return read_state(*g, s);

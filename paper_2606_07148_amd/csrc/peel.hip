@@ -148,6 +148,11 @@ PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL) {
   a.klim_l = -1;
   a.pack_vtx = nullptr;
   a.rs_mask = 0;
+  a.rs_next_st = nullptr;
+  a.rs_next_part = nullptr;
+  a.rs_fail = nullptr;
+  // any launch but a query in rank order may leave the queue in use
+  g.rs_ready = false;
   a.n = g.n;
   a.nU = g.nU;
   a.thrU = thrU;
@@ -1046,6 +1051,11 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
   __shared__ int64_t s_acc;
   __shared__ int s_cnt[kPeelWaves + 1];
   __shared__ int s_stop;
+  // rank order after an aborted query: the queue may hold stale items
+  if (a.rs_fail != nullptr && ld_agent(a.rs_fail) != 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(&a.st->abort_flag, 1);
+    return;
+  }
   if (threadIdx.x == 0) s_stop = 0;
   __syncthreads();
   LocalQueue lq = make_lq(s_lq[wave_in_block()], kLocalQueue, a);
@@ -1178,6 +1188,27 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
     // everything appended so far is processed: the next level's scan starts
     // its range here (every workgroup writes the same final cursors)
     st_agent(&a.st->hi[threadIdx.x], ld_agent(&a.st->tail[threadIdx.x][0]));
+  }
+  if (a.rs_next_st != nullptr && ld_agent(&a.st->abort_flag) != 0) {
+    // ended by an abort: other workgroups may still use the queue
+    if (threadIdx.x == 0) st_agent(a.rs_fail, 1);
+  } else if (a.rs_next_st != nullptr) {
+    // rank order: the next query's workspace.  Termination means every
+    // queued slot below its cursor is processed and no wave reads it again
+    // (claims past a cursor stay empty), so the used slots return to empty;
+    // the other state and partial sums are not this launch's
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int32_t mine = lane_id() < kSub ? ld_agent(&a.st->tail[lane_id()][0]) : 0;
+    for (int q = 0; q < kSub; ++q) {
+      const int64_t t = min(max((int64_t)__shfl(mine, q, kWave), (int64_t)0), a.qcap);
+      int32_t *qq = a.queue + (int64_t)q * a.qcap;
+      for (int64_t i = tid; i < t; i += stride) qq[i] = kEmpty;
+    }
+    for (int64_t i = tid; i < (int64_t)kMaxBlocks * kPartFields; i += stride)
+      a.rs_next_part[i] = 0;
+    int32_t *words = reinterpret_cast<int32_t *>(a.rs_next_st);
+    for (int64_t i = tid; i < (int64_t)(sizeof(PeelState) / 4); i += stride) words[i] = 0;
   }
   if (a.pack_bits != nullptr && a.pack_vtx == nullptr && ld_agent(&a.st->abort_flag) == 0) {
     // the result (Algorithm 1's V(G)): termination means every decrement
@@ -1403,9 +1434,14 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     const int32_t *__restrict__ bounds, int queue_f0, const uint32_t *__restrict__ rowbits,
     int rest_part, const int32_t *__restrict__ written_snap, const int32_t *__restrict__ rcols,
     const int32_t *__restrict__ rank_vtx, const int64_t *__restrict__ roff, int64_t nheavy,
-    int64_t nheavy_upper, int rspace, int64_t rk_u, int64_t rk_l) {
+    int64_t nheavy_upper, int rspace, int64_t rk_u, int64_t rk_l, uint32_t *__restrict__ rs_bits) {
   extern __shared__ __align__(16) uint32_t s_bits[];
   __shared__ PullShared sh;
+  if (rspace && a.rs_fail != nullptr && ld_agent(a.rs_fail) != 0) {
+    // rank order after an aborted query: the queue may hold stale items
+    if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(&a.st->abort_flag, 1);
+    return;
+  }
   // Each phase walks one layer's rows; its bitmap of the other layer is
   // staged in LDS (kLds) from the 16-byte boundary at or below its first
   // word.  Phase 0
@@ -1727,6 +1763,35 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
   block_flush(lq, sh.s_cnt);
   add_part(a.part, kPartEntries, entries, &sh.acc);
   add_part(a.part, kPartF1, f1, &sh.acc);
+  if (rs_bits != nullptr) {
+    // rank order: the scan's survivors (degree >= threshold) into the result
+    // bitmask, from which the peel clears the vertices it removes.  Each lane
+    // tests 4 consecutive vertices; 8 lanes assemble one 32-bit word.
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * 4;
+    for (int64_t b = ((int64_t)blockIdx.x * blockDim.x + wave_in_block() * kWave) * 4; b < n;
+         b += step) {
+      const int64_t x0 = b + 4 * lane_id();
+      int32_t d[4] = {0, 0, 0, 0};
+      if (x0 + 3 < n) {
+        const int4 v = *reinterpret_cast<const int4 *>(deg0 + x0);
+        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+      } else {
+        for (int k2 = 0; k2 < 4; ++k2)
+          if (x0 + k2 < n) d[k2] = deg0[x0 + k2];
+      }
+      uint32_t alive = 0;
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) {
+        const int64_t x = x0 + k2;
+        alive |= (uint32_t)(x < n && d[k2] >= (x < a.nU ? a.thrU : a.thrL)) << k2;
+      }
+      uint32_t w = alive << (4 * (lane_id() & 7));
+      w |= __shfl_xor(w, 1, kWave);
+      w |= __shfl_xor(w, 2, kWave);
+      w |= __shfl_xor(w, 4, kWave);
+      if ((lane_id() & 7) == 0 && x0 < n) rs_bits[x0 >> 5] = w;
+    }
+  }
   if (advance && last_block_done<false>(a.st)) {
     advance_round_wave(a.st);
     if (lane_id() == 0) atomicAdd((unsigned long long *)&a.st->launches, 1ull);
@@ -1801,13 +1866,13 @@ hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *b
         a, bits, g.deg0, g.n, scan_grid(g), mode, 1, total_entries, g.npieces,
         g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0,
         rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr, rcols, g.rank_vtx,
-        g.roff, g.nheavy, g.nheavy_upper, 0, -1, -1);
+        g.roff, g.nheavy, g.nheavy_upper, 0, -1, -1, nullptr);
   else
     pull_round_kernel<false><<<grid, kPullBlock, dyn, s>>>(
         a, bits, g.deg0, g.n, scan_grid(g), mode, 0, total_entries, g.npieces,
         g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0,
         rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr, rcols, g.rank_vtx,
-        g.roff, g.nheavy, g.nheavy_upper, 0, -1, -1);
+        g.roff, g.nheavy, g.nheavy_upper, 0, -1, -1, nullptr);
   return hipGetLastError();
 }
 
@@ -1829,11 +1894,12 @@ hipError_t launch_rank_query(Graph &g, int32_t thrU, int32_t thrL, int64_t ku, i
     a.ins_head = nullptr;
     a.deg = g.rdeg;
     a.rs_mask = g.rdeg_mask;
+    a.rs_fail = g.rs_fail;
     const int grid = g.cu_count;
     pull_round_kernel<false><<<grid, kPullBlock, 0, s>>>(
         a, g.alive_bits, g.deg0, g.n, scan_grid(g), 2, 0, 2 * g.m, g.npieces, g.npieces_upper,
         nullptr, nullptr, 0, 0, nullptr, 0, g.alive_bits, 0, nullptr, g.rcols, g.rank_vtx, g.roff,
-        g.nheavy, g.nheavy_upper, 1, ku, kl);
+        g.nheavy, g.nheavy_upper, 1, ku, kl, pack_bits);
     return hipGetLastError();
   }
   PeelArgs a = make_args(g, thrU, thrL);
@@ -1849,7 +1915,28 @@ hipError_t launch_rank_query(Graph &g, int32_t thrU, int32_t thrL, int64_t ku, i
   a.pack_bits = pack_bits;
   a.deg = g.rdeg;
   a.rs_mask = g.rdeg_mask;
+  a.rs_next_st = g.state_alt;
+  a.rs_next_part = g.part_alt;
+  a.rs_fail = g.rs_fail;
   return launch_peel_async_args(g, kGCC, a, async_peel_grid(g), s);
+}
+
+__global__ void rank_prep_kernel(int32_t *queue, int64_t qcap, const PeelState *st,
+                                 PeelState *next_st, int64_t *next_part, int nparts,
+                                 int32_t *rs_fail) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid == 0) *rs_fail = 0;
+  clear_used_queue(queue, qcap, st, tid, stride);
+  for (int64_t i = tid; i < nparts; i += stride) next_part[i] = 0;
+  int32_t *words = reinterpret_cast<int32_t *>(next_st);
+  for (int64_t i = tid; i < (int64_t)(sizeof(PeelState) / 4); i += stride) words[i] = 0;
+}
+
+hipError_t launch_rank_prep(Graph &g, hipStream_t s) {
+  rank_prep_kernel<<<g.cu_count, 256, 0, s>>>(g.queue, g.qcap, g.state, g.state_alt, g.part_alt,
+                                              kMaxBlocks * kPartFields, g.rs_fail);
+  return hipGetLastError();
 }
 
 // Must follow the pull round on the same stream (it completes that round).

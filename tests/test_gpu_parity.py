@@ -165,6 +165,48 @@ def test_rank_order_queries():
     g.destroy()
 
 
+def test_rank_order_interleaved_with_other_work():
+    """Queries in rank order alternate between two workspace states, each
+    leaving the other ready; batches (captured and replayed), GCC+, core
+    numbers and vertex-order queries in between must not disturb them."""
+    nU, nL, m = 20_000, 15_000, 250_000
+    eu, ev = bigraph_gen.chung_lu(nU, nL, m, 2.1, 2.1, 3000, 112)
+    g, ref = _make(nU, nL, eu, ev)
+    want = {}
+
+    def check(a, b, tag):
+        if (a, b) not in want:
+            want[(a, b)] = oracle.pack(oracle.peel(ref, a, b)[0])
+        w = want[(a, b)]
+        got = bits_np(pkg.abcore_compute(g, a, b, pkg.ABCORE_GCC))[: len(w)]
+        assert np.array_equal(got, w), (tag, a, b)
+
+    seq = [(10, 10), (5, 20), (40, 8), (2, 3), (10, 10)]
+    for i, ab in enumerate(seq):
+        check(*ab, f"run {i}")
+    alphas, betas = [3, 5, 9, 12], [4, 4, 10, 2]
+    for rep in range(3):
+        got = bits_np(pkg.abcore_compute_batch(g, alphas, betas))
+        for i, ab in enumerate(zip(alphas, betas)):
+            if ab not in want:
+                want[ab] = oracle.pack(oracle.peel(ref, *ab)[0])
+            assert np.array_equal(got[i, : len(want[ab])], want[ab]), ("batch", rep, ab)
+        for k in range(rep + 1):  # an odd, then an even number of exchanges
+            check(*seq[k], f"after batch {rep}")
+    pkg.abcore_compute(g, 4, 9, pkg.ABCORE_GCC_PLUS)
+    check(7, 7, "after GCC+")
+    pkg.abcore_core_numbers(g)
+    check(7, 7, "after core numbers")
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_RANK_ORDER, 2)
+    check(6, 11, "vertex order")
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_RANK_ORDER, 1)
+    check(6, 11, "rank order again")
+    _, st = pkg.abcore_compute(g, 6, 11, pkg.ABCORE_GCC, stats=True)
+    assert st["rank_order"] == 1
+    check(6, 11, "after stats")
+    g.destroy()
+
+
 def test_repeat_runs_identical():
     eu, ev = bigraph_gen.chung_lu(50_000, 30_000, 600_000, 2.1, 2.1, 8000, 7)
     g = pkg.abcore_build_csr(50_000, 30_000, to_dev(eu), to_dev(ev))
