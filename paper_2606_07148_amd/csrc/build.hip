@@ -330,14 +330,19 @@ __global__ void rank_scatter_kernel(const uint64_t *__restrict__ sorted, int64_t
 }
 
 // Entry keys (global rank of the row, neighbour's rank): sorted, the rows
-// come out in rank order and each row's ranks ascending.
+// come out in rank order and each row's ranks ascending.  A wave per row
+// (rows in turn), its lanes over the row's entries, so that hubs do not
+// serialise on one thread.
 __global__ void entry_keys_kernel(const int64_t *__restrict__ off, const int32_t *__restrict__ cols,
                                   const int32_t *__restrict__ rank, int64_t n, int64_t nU, int rbits,
                                   uint64_t *__restrict__ keys) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = (int)(threadIdx.x % kWave);
+  for (int64_t x = w0; x < n; x += waves) {
     const uint64_t r = (uint64_t)rank[x] + (x < nU ? 0 : (uint64_t)nU);
-    for (int64_t e = off[x]; e < off[x + 1]; ++e)
+    const int64_t e1 = off[x + 1];
+    for (int64_t e = off[x] + lane; e < e1; e += kWave)
       keys[e] = (r << rbits) | (uint64_t)rank[cols[e]];
   }
 }
