@@ -361,13 +361,13 @@ hipError_t launch_scan_nested(Graph &g, int32_t pU, int32_t pL, int32_t thrU, in
                               hipStream_t s, uint32_t *bits = nullptr);
 // queue_f0: the scan did not queue its frontier (launch_scan_reset_gcc);
 // a pushed first round then queues it from the bitmap.
-// rank_bits (a query in rank order): the survivor bitmap goes there (the
-// result bitmask) and nothing else is computed but the reset.
 hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
-                                  bool keep_abort = false, uint32_t *rank_bits = nullptr);
+                                  bool keep_abort = false);
 // A GCC query in rank order (g.rcols and g.rp_* present, unchanged graph):
-// part 0 is the pulled first round, part 1 the asynchronous peel with the
-// pack into pack_bits; ku and kl are the layers' survivor counts.
+// part 0 is the pulled first round (and the survivor bitmap into pack_bits),
+// part 1 the asynchronous peel (clearing the removed vertices' bits, then
+// readying g.state_alt, g.part_alt and the queue); ku and kl are the layers'
+// survivor counts.
 hipError_t launch_rank_query(Graph &g, int32_t thrU, int32_t thrL, int64_t ku, int64_t kl,
                              uint32_t *pack_bits, hipStream_t s, int part);
 // Returns the queue's used slots (cursors in g.state) to empty and zeroes

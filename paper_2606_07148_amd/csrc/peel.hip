@@ -344,12 +344,9 @@ hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, bool want_bits,
 // instead).  Every workgroup first returns its share of the previous
 // computation's queue prefixes to kEmpty and zeroes its partial slots; the
 // last one to finish zeroes the state (all cursors were read by then).
-// rank_bits: a query in rank order, which needs only the survivor bitmap
-// (written into the result bitmask, from which the peel clears the vertices
-// it removes): no degrees are copied and no counts kept.
 __global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
     PeelArgs a, const int32_t *__restrict__ deg0, uint32_t *__restrict__ bits, int64_t n,
-    int keep_word, int rank_bits) {
+    int keep_word) {
   __shared__ int64_t s_acc;
   PeelState *st = a.st;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -368,7 +365,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
       bool p[4] = {false, false, false, false};
       if (x0 + 3 < n) {
         const int4 v = *reinterpret_cast<const int4 *>(deg0 + x0);
-        if (!rank_bits) *reinterpret_cast<int4 *>(a.deg + x0) = v;
+        *reinterpret_cast<int4 *>(a.deg + x0) = v;
         d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
 #pragma unroll
         for (int j = 0; j < 4; ++j) p[j] = d[j] < ((x0 + j) < a.nU ? a.thrU : a.thrL);
@@ -378,7 +375,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
           const int64_t x = x0 + j;
           if (x < n) {
             d[j] = deg0[x];
-            if (!rank_bits) a.deg[x] = d[j];
+            a.deg[x] = d[j];
             p[j] = d[j] < (x < a.nU ? a.thrU : a.thrL);
           }
         }
@@ -408,12 +405,10 @@ __global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
       if ((lane_id() & 7) == 0 && x0 < n) bits[x0 / 32] = w;
     }
   }
-  if (!rank_bits) {
-    add_part(a.part, kPartF0, f0, &s_acc);
-    add_part(a.part, kPartF0Deg, f0deg, &s_acc);
-    add_part(a.part, kPartAliveU, alive_u, &s_acc);
-    add_part(a.part, kPartAliveL, alive_l, &s_acc);
-  }
+  add_part(a.part, kPartF0, f0, &s_acc);
+  add_part(a.part, kPartF0Deg, f0deg, &s_acc);
+  add_part(a.part, kPartAliveU, alive_u, &s_acc);
+  add_part(a.part, kPartAliveL, alive_l, &s_acc);
   __syncthreads();
   if (wave_in_block() != 0) return;
   int last = 0;
@@ -426,11 +421,11 @@ __global__ __launch_bounds__(kScanBlock) void scan_reset_gcc_kernel(
 }
 
 hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
-                                  bool keep_abort, uint32_t *rank_bits) {
+                                  bool keep_abort) {
   PeelArgs a = make_args(g, thrU, thrL);
   const int keep = keep_abort ? (int)(offsetof(PeelState, abort_flag) / 4) : -1;
   scan_reset_gcc_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(
-      a, g.deg0, rank_bits ? rank_bits : g.alive_bits, g.n, keep, rank_bits ? 1 : 0);
+      a, g.deg0, g.alive_bits, g.n, keep);
   return hipGetLastError();
 }
 
@@ -1883,10 +1878,12 @@ hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s
                                 advance, s, queue_f0, rowbits, force, rest_part, rank);
 }
 
-// A query in rank order (unchanged graph): the first round pulled on the
-// rank rows, whose survivors are ranks [0, ku) and [nU, nU + kl), then the
-// asynchronous peel and the pack on the rank rows.  The workspace must have
-// been reset.
+// A query in rank order (unchanged graph): part 0, the first round pulled on
+// the rank rows, whose survivors are ranks [0, ku) and [nU, nU + kl), which
+// also writes their bitmap into the result; part 1, the asynchronous peel on
+// the rank rows, which clears the result bit of each vertex it removes and,
+// after termination, leaves the other workspace state ready for the next
+// query.  g.state must be a zeroed state and the queue empty.
 hipError_t launch_rank_query(Graph &g, int32_t thrU, int32_t thrL, int64_t ku, int64_t kl,
                              uint32_t *pack_bits, hipStream_t s, int part) {
   if (part == 0) {
