@@ -414,4 +414,17 @@ def test_config2_full_size():
         _check_core(g, ref, a, b, pkg.ABCORE_GCC_PLUS, "c2")
     core, mx = pkg.abcore_core_numbers(g)
     assert np.array_equal(core.cpu().numpy(), oracle.core_numbers(ref))
+    # rank order against vertex order over a spread of thresholds (the same
+    # graph, both on the device; the four pairs above also against the oracle)
+    alphas, betas = bigraph_gen.loguniform_pairs(24, 1, 300, 2002)
+    say("config 2: rank order against vertex order, 24 pairs")
+    for a, b in zip(alphas.tolist(), betas.tolist()):
+        pkg.abcore_set_option(g, pkg.ABCORE_OPT_RANK_ORDER, 2)
+        want, sv = pkg.abcore_compute(g, a, b, pkg.ABCORE_GCC, stats=True)
+        want = bits_np(want)
+        pkg.abcore_set_option(g, pkg.ABCORE_OPT_RANK_ORDER, 1)
+        got, sr = pkg.abcore_compute(g, a, b, pkg.ABCORE_GCC, stats=True)
+        assert sv["rank_order"] == 0
+        assert np.array_equal(bits_np(got), want), (a, b)
+        assert sr["removed"] == sv["removed"], (a, b)
     g.destroy()
