@@ -325,9 +325,10 @@ struct PeelArgs {
   // Rank order: a rank's degree sits at slot (rank * kRankMul) & rs_mask of
   // a power-of-two array (0: the degree array is indexed by id).
   uint32_t rs_mask;
-  // Rank order (nullable): after termination the peel returns the queue's
-  // used slots to empty and zeroes this state and these partial sums, the
-  // next query's workspace (its own stay readable for the statistics).
+  // Rank order (nullable): the peel returns each queue slot to empty as it
+  // takes the slot's item, and after termination zeroes this state and these
+  // partial sums, the next query's workspace (its own stay readable for the
+  // statistics).
   PeelState *rs_next_st;
   int64_t *rs_next_part;
   // Rank order: set when a peel ended without termination (a spin-limit

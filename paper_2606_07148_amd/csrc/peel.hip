@@ -1103,6 +1103,9 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
       int32_t item = kEmpty;
       if (pending && slot < a.qcap) item = ld_agent(&lq.q[slot]);
       const bool ready = pending && item != kEmpty;
+      // rank order: a slot is claimed once and read once, so it returns to
+      // empty as soon as its item is taken (the next query finds it so)
+      if (a.rs_next_st != nullptr && ready) lq.q[slot] = kEmpty;
       const uint64_t rmask = __ballot(ready);
       if (rmask) {
         async_batch<KIND>(a, ready ? item : -1, (int)__popcll(rmask), lq, consumed, entries,
@@ -1132,6 +1135,8 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
           if (sitem == kEmpty) {
             st_agent(&a.st->abort_flag, 1);
             sitem = -1;
+          } else if (a.rs_next_st != nullptr) {
+            const_cast<int32_t *>(vq)[sbase + lane_id()] = kEmpty;
           }
         }
         async_batch<KIND>(a, sitem, taken, lq, consumed, entries, level);
@@ -1189,17 +1194,10 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
     if (threadIdx.x == 0) st_agent(a.rs_fail, 1);
   } else if (a.rs_next_st != nullptr) {
     // rank order: the next query's workspace.  Termination means every
-    // queued slot below its cursor is processed and no wave reads it again
-    // (claims past a cursor stay empty), so the used slots return to empty;
-    // the other state and partial sums are not this launch's
+    // queued slot was taken, and each was returned to empty when it was; the
+    // other state and partial sums (not this launch's) are zeroed
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int32_t mine = lane_id() < kSub ? ld_agent(&a.st->tail[lane_id()][0]) : 0;
-    for (int q = 0; q < kSub; ++q) {
-      const int64_t t = min(max((int64_t)__shfl(mine, q, kWave), (int64_t)0), a.qcap);
-      int32_t *qq = a.queue + (int64_t)q * a.qcap;
-      for (int64_t i = tid; i < t; i += stride) qq[i] = kEmpty;
-    }
     for (int64_t i = tid; i < (int64_t)kMaxBlocks * kPartFields; i += stride)
       a.rs_next_part[i] = 0;
     int32_t *words = reinterpret_cast<int32_t *>(a.rs_next_st);
