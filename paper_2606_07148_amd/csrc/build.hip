@@ -32,28 +32,60 @@ __global__ void make_keys_kernel(const int32_t *__restrict__ eu, const int32_t *
     keys[i] = (uint64_t)(uint32_t)eu[i] * (uint64_t)nL + (uint64_t)(uint32_t)ev[i];
 }
 
-// Upper side: unique key i = (u, v) -> cols[i] = nU + v; degree counts; and
-// the transposed key (v*nU + u) for the lower rows.
+// Counts one per valid lane into deg[row] where the lanes of a wave hold
+// sorted rows (the valid lanes a prefix of the wave): one atomic per run of
+// equal rows, so that a hub's entries do not queue on one address.
+__device__ __forceinline__ void add_row_runs(int32_t *deg, int32_t row, bool ok) {
+  const int lane = (int)(threadIdx.x % kWave);
+  const int32_t prev = __shfl_up(row, 1, kWave);
+  const bool start = ok && (lane == 0 || prev != row);
+  const uint64_t starts = __ballot(start);
+  const int nvalid = __popcll(__ballot(ok));
+  if (start) {
+    const uint64_t above = lane == kWave - 1 ? 0ull : (starts >> (lane + 1)) << (lane + 1);
+    const int end = above ? __builtin_ctzll(above) : nvalid;
+    atomicAdd(&deg[row], end - lane);
+  }
+}
+
+// Upper side: unique key i = (u, v) -> cols[i] = nU + v; upper degrees; and
+// the transposed key (v*nU + u) for the lower rows.  (Wave-uniform loop.)
 __global__ void upper_rows_kernel(const uint64_t *__restrict__ ukeys, int64_t md, int32_t nU,
                                   int32_t nL, int32_t *__restrict__ cols,
                                   int32_t *__restrict__ deg, uint64_t *__restrict__ tkeys) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < md; i += stride) {
-    const uint64_t k = ukeys[i];
-    const int32_t u = (int32_t)(k / (uint64_t)nL);
-    const int32_t v = (int32_t)(k % (uint64_t)nL);
-    cols[i] = nU + v;
-    atomicAdd(&deg[u], 1);
-    atomicAdd(&deg[(int64_t)nU + v], 1);
-    tkeys[i] = (uint64_t)(uint32_t)v * (uint64_t)nU + (uint64_t)(uint32_t)u;
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x / kWave) * kWave; b < md;
+       b += stride) {
+    const int64_t i = b + (int64_t)(threadIdx.x % kWave);
+    const bool ok = i < md;
+    int32_t u = 0;
+    if (ok) {
+      const uint64_t k = ukeys[i];
+      u = (int32_t)(k / (uint64_t)nL);
+      const int32_t v = (int32_t)(k % (uint64_t)nL);
+      cols[i] = nU + v;
+      tkeys[i] = (uint64_t)(uint32_t)v * (uint64_t)nU + (uint64_t)(uint32_t)u;
+    }
+    add_row_runs(deg, u, ok);
   }
 }
 
+// Lower side: keys sorted by (v, u) -> cols[md + i] = u; lower degrees.
 __global__ void lower_rows_kernel(const uint64_t *__restrict__ lkeys, int64_t md, int32_t nU,
-                                  int32_t *__restrict__ cols) {
+                                  int32_t *__restrict__ cols, int32_t *__restrict__ deg) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < md; i += stride)
-    cols[md + i] = (int32_t)(lkeys[i] % (uint64_t)nU);
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x / kWave) * kWave; b < md;
+       b += stride) {
+    const int64_t i = b + (int64_t)(threadIdx.x % kWave);
+    const bool ok = i < md;
+    int32_t v = 0;
+    if (ok) {
+      const uint64_t k = lkeys[i];
+      cols[md + i] = (int32_t)(k % (uint64_t)nU);
+      v = (int32_t)(k / (uint64_t)nU);
+    }
+    add_row_runs(deg + nU, v, ok);
+  }
 }
 
 __global__ void widen_kernel(const int32_t *__restrict__ deg, int64_t n,
@@ -210,7 +242,7 @@ abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, i
     upper_rows_kernel<<<gridm, 256, 0, s>>>(k0, md, g.nU, g.nL, g.cols, g.deg0, k1);
     BCHK(hipGetLastError());
     BCHK(hipcub::DeviceRadixSort::SortKeys(temp, temp_bytes, k1, k0, (int)md, 0, lbits, s));
-    lower_rows_kernel<<<gridm, 256, 0, s>>>(k0, md, g.nU, g.cols);
+    lower_rows_kernel<<<gridm, 256, 0, s>>>(k0, md, g.nU, g.cols, g.deg0);
     BCHK(hipGetLastError());
   }
   BCHK(hipMalloc(&deg64, sizeof(int64_t) * (g.n + 1)));
