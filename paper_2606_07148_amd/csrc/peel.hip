@@ -752,7 +752,19 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
         d = 0;          // walked by its pieces
         first = false;  // the first piece walks the inserted edges
       }
-      for (int k = 0; __ballot(k < np); ++k) lq.push(k < np, piece_item(pf + k));
+      if (KIND == kKCore) {
+        // core numbers: a level near the top removes a few hubs and little
+        // else, and a hub's pieces kept local would be walked by one wave
+        // (levels of 1,000 take 0.5 ms so); all but its first piece go to the
+        // shared sub-queue at once, for the idle waves to take
+        if (__ballot(np > 1)) {
+          for (int k = 1; __ballot(k < np); ++k) lq.push(k < np, piece_item(pf + k));
+          lq.flush();
+        }
+        lq.push(np > 0, piece_item(pf));
+      } else {
+        for (int k = 0; __ballot(k < np); ++k) lq.push(k < np, piece_item(pf + k));
+      }
     }
   }
   BatchWalk bw;
