@@ -246,6 +246,20 @@ abcore_status abcore_serve_stop(abcore_graph g, int64_t *counters);
  *                          graph while it is unchanged since the build (the
  *                          scan's survivors are then known in advance, Sec.
  *                          IV-A); 2 = always in vertex order.
+ *   ABCORE_OPT_SPIN_LIMIT: failure injection for tests: polls a waiting wave
+ *                          of the asynchronous peel makes before it declares
+ *                          a hang and aborts (0 = the default, 2^21, i.e.
+ *                          seconds; small values make peels abort at once).
+ *
+ * Aborts.  Every device-side wait is bounded.  A computation whose wait
+ * exceeds its bound leaves an invalid result; a call that requested stats
+ * (or that synchronises internally) returns ABCORE_EDEVICE at once.  An
+ * asynchronous call cannot know yet: its peel sets a pinned host word when it
+ * ends, and the first later computing call on the handle that finds the word
+ * set (abcore_compute, _compute_batch, _core_numbers, _query, _autotune,
+ * _serve_start) returns ABCORE_EDEVICE without computing, after resetting the
+ * handle's workspace, so that the calls after it are exact again.  Results of
+ * calls enqueued between the aborted one and that report may be invalid too.
  */
 enum {
   ABCORE_OPT_PEEL_MODE = 1,
@@ -254,7 +268,8 @@ enum {
   ABCORE_OPT_TIMING = 4,
   ABCORE_OPT_PULL = 5,
   ABCORE_OPT_CLAIM = 6,
-  ABCORE_OPT_RANK_ORDER = 7
+  ABCORE_OPT_RANK_ORDER = 7,
+  ABCORE_OPT_SPIN_LIMIT = 8
 };
 abcore_status abcore_set_option(abcore_graph g, int32_t option, int64_t value);
 

@@ -13,6 +13,10 @@ compositions the paper defines in terms of those routines:
 * ``gfq_stream``   -- Problem 2 (Sec. III) / GFQ (Sec. V): after each edge
   update, membership of the updated edge's endpoints in the core of the
   updated graph, by full recomputation on that graph.
+* ``peel_order``   -- ``compute`` plus the sequential removal order (the
+  certificate of maximality).
+* ``gfq_stream_sampled`` -- ``gfq_stream`` at sampled indices of a stream on
+  a graph too large for a Python edge set.
 * ``pack``         -- the membership bitmask layout (bit x of word x // 32,
   least significant bit first; unified ids, lower vertex v is nU + v).
 
@@ -56,6 +60,9 @@ def _load():
     lib.or_peel.restype = ctypes.c_int
     lib.or_peel.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_int64,
                             ctypes.c_int64, vp, vp]
+    lib.or_peel_order.restype = ctypes.c_int
+    lib.or_peel_order.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_int64,
+                                  ctypes.c_int64, vp, vp, vp]
     lib.or_core_numbers.restype = ctypes.c_int
     lib.or_core_numbers.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     lib.or_components.restype = ctypes.c_int
@@ -112,6 +119,23 @@ def peel(g: Graph, alpha: int, beta: int):
 
 def compute(g: Graph, alpha: int, beta: int) -> np.ndarray:
     return peel(g, alpha, beta)[0]
+
+
+def peel_order(g: Graph, alpha: int, beta: int):
+    """Like ``peel``, plus the removed vertices in the order the sequential
+    peel marked them (int64[|R|]).  Each of them had fewer than its threshold
+    of neighbours outside the earlier-removed ones when it was marked, which
+    is what makes the result maximal (Definition 1)."""
+    member = np.zeros(max(1, g.n), np.uint8)
+    st = np.zeros(4, np.int64)
+    order = np.zeros(max(1, g.n), np.int64)
+    rc = _load().or_peel_order(g.n_upper, g.n_lower, _ptr(g.off), _ptr(g.cols), int(alpha),
+                               int(beta), _ptr(member), _ptr(st), _ptr(order))
+    if rc != 0:
+        raise MemoryError("oracle peel failed")
+    stats = dict(removed=int(st[0]), removed_degree_sum=int(st[1]), m_peeled=int(st[2]),
+                 rounds=int(st[3]))
+    return member[: g.n].astype(bool), stats, order[: stats["removed"]].copy()
 
 
 def batch(g: Graph, alphas, betas) -> np.ndarray:
@@ -187,6 +211,70 @@ def gfq_stream(n_upper: int, n_lower: int, eu, ev, updates, check_only=None):
         member = compute(g, int(updates["alpha"][i]), int(updates["beta"][i]))
         bu, bv = bool(member[u]), bool(member[n_upper + v])
         out.append(("OK", bu and bv, int(bu) | (int(bv) << 1)))
+    return out
+
+
+def gfq_stream_sampled(n_upper: int, n_lower: int, eu, ev, updates, indices, on_graph=None):
+    """``gfq_stream`` for graphs too large for a Python edge set: the same
+    cumulative semantics (Problem 2 of Sec. III, recomputation per Sec. V),
+    with the base edges kept as one sorted key array and the updates as two
+    small sets (inserted keys, deleted base keys).  Only the updates listed in
+    ``indices`` are answered (a full peel of the graph after that update);
+    the stream is applied up to the largest of them.  Returns
+    {index: (status, answer, endpoint_bits)} for those indices; a rejected
+    update reports (status, None, None).  ``on_graph(i, graph)``, if given, is
+    called with each oracle graph built for an answered index."""
+    nL = int(n_lower)
+    want = sorted(set(int(i) for i in indices))
+    if not want:
+        return {}
+    base = np.unique(np.asarray(eu, np.int64) * nL + np.asarray(ev, np.int64))
+    inserted, deleted = set(), set()
+
+    def in_base(key):
+        j = int(np.searchsorted(base, key))
+        return j < len(base) and int(base[j]) == key
+
+    out = {}
+    wanted = set(want)
+    for i in range(want[-1] + 1):
+        u, v, op = int(updates["u"][i]), int(updates["v"][i]), int(updates["op"][i])
+        key = u * nL + v
+        b = in_base(key)
+        present = key in inserted or (b and key not in deleted)
+        if op > 0:
+            if present:
+                if i in wanted:
+                    out[i] = ("EEXIST", None, None)
+                continue
+            if b:
+                deleted.discard(key)
+            else:
+                inserted.add(key)
+        else:
+            if not present:
+                if i in wanted:
+                    out[i] = ("ENOENT", None, None)
+                continue
+            if key in inserted:
+                inserted.discard(key)
+            else:
+                deleted.add(key)
+        if i not in wanted:
+            continue
+        keep = np.ones(len(base), bool)
+        if deleted:
+            keep[np.searchsorted(base, np.fromiter(deleted, np.int64, len(deleted)))] = False
+        keys = np.concatenate([base[keep], np.fromiter(inserted, np.int64, len(inserted))])
+        del keep
+        g = Graph(n_upper, n_lower, (keys // nL).astype(np.int32), (keys % nL).astype(np.int32))
+        del keys
+        member = compute(g, int(updates["alpha"][i]), int(updates["beta"][i]))
+        bu, bv = bool(member[u]), bool(member[n_upper + v])
+        out[i] = ("OK", bu and bv, int(bu) | (int(bv) << 1))
+        if on_graph is not None:
+            on_graph(i, g)
+        del g
     return out
 
 

@@ -105,9 +105,12 @@ int64_t or_build_csr(int32_t nU, int32_t nL, int64_t m, const int32_t *eu,
  * member[x] = 1 for core vertices.  stats (nullable, 4 entries):
  *   [0] |R| removed vertices, [1] sum of |N(x)| over removed x,
  *   [2] m_peeled = m - |E(core)|, [3] number of FIFO generations (rounds).
+ * order (nullable, room for n entries): the removed vertices in the order
+ *   they were marked, i.e. the FIFO contents; order[0..|R|) is written.
  * Returns 0, or -1 on allocation failure. */
-int or_peel(int32_t nU, int32_t nL, const int64_t *off, const int32_t *cols,
-            int64_t alpha, int64_t beta, uint8_t *member, int64_t *stats) {
+int or_peel_order(int32_t nU, int32_t nL, const int64_t *off, const int32_t *cols,
+                  int64_t alpha, int64_t beta, uint8_t *member, int64_t *stats,
+                  int64_t *order) {
   int64_t n = (int64_t)nU + nL;
   int64_t *deg = malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
   int64_t *queue = malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
@@ -158,8 +161,14 @@ int or_peel(int32_t nU, int32_t nL, const int64_t *off, const int32_t *cols,
     stats[2] = m_total - m_core;
     stats[3] = rounds;
   }
+  if (order) memcpy(order, queue, sizeof(int64_t) * (size_t)tail);
   free(deg); free(queue); free(removed);
   return 0;
+}
+
+int or_peel(int32_t nU, int32_t nL, const int64_t *off, const int32_t *cols,
+            int64_t alpha, int64_t beta, uint8_t *member, int64_t *stats) {
+  return or_peel_order(nU, nL, off, cols, alpha, beta, member, stats, NULL);
 }
 
 /* ---------------------------------------------------------- core number --

@@ -26,6 +26,7 @@ ABCORE_OPT_TIMING = 4
 ABCORE_OPT_PULL = 5
 ABCORE_OPT_CLAIM = 6
 ABCORE_OPT_RANK_ORDER = 7
+ABCORE_OPT_SPIN_LIMIT = 8
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOENT", 5: "EEXIST",
           6: "EBUSY", 7: "EAGAIN"}

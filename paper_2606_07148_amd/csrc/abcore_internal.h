@@ -44,6 +44,10 @@ constexpr int kDefaultClaim = 32;
 // certain members are never decremented, certain non-members never counted.
 constexpr int32_t kDegIn = 0x7FFFFFFF;
 constexpr int32_t kDegOut = -1;
+// Polls of one waiting wave of the asynchronous peel before it declares a
+// hang (each poll takes at least a few microseconds, so this is seconds: far
+// beyond any legitimate wait of a peel).  ABCORE_OPT_SPIN_LIMIT lowers it.
+constexpr uint32_t kAsyncSpinLimit = 1u << 21;
 // Largest usable threshold: kDegIn must stay above every threshold.
 constexpr int32_t kMaxThreshold = 0x7FFFFFFE;
 // Degree of a removed split row once a consumer has claimed it (far below
@@ -218,6 +222,11 @@ struct Graph {
   int64_t *part_alt = nullptr;
   int32_t *rs_fail = nullptr;  // device word, see PeelArgs
   bool rs_ready = false;
+  // Pinned host word set by a peel that ended by a spin-limit abort (see
+  // PeelArgs::abort_host); the next computing call reports it and resets
+  // the workspace.
+  int32_t *h_abort = nullptr;
+  uint32_t spin_limit = 0;  // ABCORE_OPT_SPIN_LIMIT (0 = kAsyncSpinLimit)
   int rs_parity = 0;  // flips with every exchange of state and state_alt
   // Pull round work split: workgroup k of a cu_count grid walks the upper
   // rows [b[k], b[k+1]) and the lower rows [b[G+1+k], b[G+2+k]), ranges of
@@ -335,6 +344,12 @@ struct PeelArgs {
   // abort) and so left the queue as it was; later queries in rank order
   // then abort at once until a preparation clears it.
   int32_t *rs_fail;
+  // Polls of a waiting wave before it declares a hang (kAsyncSpinLimit
+  // unless lowered by ABCORE_OPT_SPIN_LIMIT).
+  uint32_t spin_limit;
+  // Host-visible word (pinned, coherent; nullable) the peel sets when it
+  // ends by an abort, so the host learns of it without a synchronisation.
+  int32_t *abort_host;
   int64_t n;
   int32_t nU;
   int32_t thrU, thrL;

@@ -141,6 +141,7 @@ void free_graph(Graph *g) {
                   g->part_alt,    g->rs_fail};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
+  if (g->h_abort) (void)hipHostFree(g->h_abort);
   if (g->h_state) (void)hipHostFree(g->h_state);
   if (g->h_part) (void)hipHostFree(g->h_part);
   delete g;
@@ -190,10 +191,26 @@ abcore_status read_state(Graph &g, hipStream_t s) {
   CHK(hipStreamSynchronize(s));
   if (g.h_state->abort_flag) {
     g.rs_ready = false;  // the next query in rank order prepares the workspace
-    set_error("a grid barrier exceeded its spin limit; the result is invalid");
+    if (g.h_abort) __atomic_store_n(g.h_abort, 0, __ATOMIC_RELEASE);  // reported here
+    set_error("a device-side wait exceeded its spin limit; the result is invalid");
     return ABCORE_EDEVICE;
   }
   return ABCORE_OK;
+}
+
+// Reports a spin-limit abort of an earlier asynchronous computation on the
+// handle (its peel set the pinned word when it ended) and readies the
+// workspace again: the next query in rank order runs its preparation, which
+// returns the queue's used slots to empty and clears the failure word, and
+// any other computation resets the workspace as it starts.
+abcore_status check_abort(Graph &g) {
+  if (g.h_abort == nullptr || __atomic_load_n(g.h_abort, __ATOMIC_ACQUIRE) == 0)
+    return ABCORE_OK;
+  __atomic_store_n(g.h_abort, 0, __ATOMIC_RELEASE);
+  g.rs_ready = false;
+  set_error("an earlier computation on this handle ended by a spin-limit abort; its result "
+            "was invalid (the workspace is reset; later calls are exact)");
+  return ABCORE_EDEVICE;
 }
 
 int64_t sum_part(Graph &g, int field, hipStream_t s, abcore_status *st) {
@@ -611,6 +628,9 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
     if (e == hipSuccess) e = hipMemsetAsync(g->rs_fail, 0, sizeof(int32_t), s);
     if (e == hipSuccess) e = hipHostMalloc(&g->h_state, sizeof(PeelState));
     if (e == hipSuccess)
+      e = hipHostMalloc(&g->h_abort, sizeof(int32_t), hipHostMallocCoherent);
+    if (e == hipSuccess) *g->h_abort = 0;
+    if (e == hipSuccess)
       e = hipHostMalloc(&g->h_part, sizeof(int64_t) * kMaxBlocks * kPartFields);
     if (e != hipSuccess) {
       set_error("abcore_build_csr: state allocation failed: %s", hipGetErrorString(e));
@@ -712,6 +732,9 @@ abcore_status abcore_set_option(abcore_graph h, int32_t option, int64_t value) {
       }
       g->rank_order = value != 2;
       return ABCORE_OK;
+    case ABCORE_OPT_SPIN_LIMIT:
+      g->spin_limit = (uint32_t)std::min<int64_t>(value, (int64_t)kAsyncSpinLimit);
+      return ABCORE_OK;
     case ABCORE_OPT_CLAIM:
       if (value > kWave) {
         set_error("abcore_set_option: claim %lld above %d", (long long)value, kWave);
@@ -763,6 +786,7 @@ abcore_status abcore_core_numbers(abcore_graph h, int32_t *d_core, int32_t *max_
     return ABCORE_EINVAL;
   }
   CHK(hipSetDevice(g->device));
+  TRY(check_abort(*g));
   hipStream_t s = as_stream(stream);
   TRY(compute_core(*g, s));
   if (d_core && g->n > 0)
@@ -805,6 +829,7 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
     return ABCORE_EINVAL;
   }
   CHK(hipSetDevice(g->device));
+  TRY(check_abort(*g));
   hipStream_t s = as_stream(stream);
   const int32_t thrU = clamp_thr(alpha), thrL = clamp_thr(beta);
   int64_t launches = 0;
@@ -961,6 +986,7 @@ abcore_status abcore_compute_batch(abcore_graph h, const uint32_t *h_alpha,
   TRY(batch_thresholds(h_alpha, h_beta, q, tu, tl));
   if (q == 0 || g->n == 0) return ABCORE_OK;
   CHK(hipSetDevice(g->device));
+  TRY(check_abort(*g));
   hipStream_t s = as_stream(stream);
   BatchPlan plan = make_batch_plan(tu.data(), tl.data(), q);
   TRY(ensure_slots(*g, plan.nslots));
@@ -1039,6 +1065,7 @@ abcore_status abcore_query(abcore_graph h, abcore_edge_update upd, uint32_t alph
     return ABCORE_EINVAL;
   }
   CHK(hipSetDevice(g->device));
+  TRY(check_abort(*g));
   hipStream_t s = as_stream(stream);
   TRY(compute_components(*g, s));
   TRY(ensure_delta(*g, s));
@@ -1092,6 +1119,7 @@ abcore_status abcore_serve_start(abcore_graph h, int64_t max_inflight, int32_t d
   }
   if (serving(*g)) return ABCORE_OK;
   CHK(hipSetDevice(g->device));
+  TRY(check_abort(*g));
   hipStream_t s = nullptr;
   TRY(compute_components(*g, s));
   TRY(ensure_delta(*g, s));
@@ -1147,6 +1175,7 @@ abcore_status abcore_autotune(abcore_graph h, uint32_t alpha, uint32_t beta, int
     return ABCORE_EINVAL;
   }
   CHK(hipSetDevice(g->device));
+  TRY(check_abort(*g));
   hipStream_t s = as_stream(stream);
   const int64_t words = std::max<int64_t>(1, (g->n + 31) / 32);
   uint32_t *bits = nullptr;

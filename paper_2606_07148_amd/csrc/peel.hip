@@ -151,6 +151,8 @@ PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL) {
   a.rs_next_st = nullptr;
   a.rs_next_part = nullptr;
   a.rs_fail = nullptr;
+  a.spin_limit = g.spin_limit > 0 ? g.spin_limit : kAsyncSpinLimit;
+  a.abort_host = g.h_abort;
   // any launch but a query in rank order may leave the queue in use
   g.rs_ready = false;
   a.n = g.n;
@@ -926,6 +928,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_persistent_kernel(PeelArgs a,
       if (lane_id() == 0) atomicAdd((unsigned long long *)&a.st->launches, 1ull);
     });
   }
+  if (threadIdx.x == 0 && ld_agent(&a.st->abort_flag) != 0) report_abort(a);
   add_part(a.part, kPartEntries, entries, &s_acc);
 }
 
@@ -992,10 +995,6 @@ __device__ __forceinline__ bool quiescent(PeelState *st, int32_t start_expect) {
   return dsum == tsum;
 }
 
-// Polls of one waiting wave before it declares a hang (each poll takes at
-// least a few microseconds, so this is seconds: far beyond any legitimate
-// wait of a peel).
-constexpr uint32_t kAsyncSpinLimit = 1u << 21;
 #ifndef ABC_QMASK
 #define ABC_QMASK 3
 #endif
@@ -1060,7 +1059,10 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
   __shared__ int s_stop;
   // rank order after an aborted query: the queue may hold stale items
   if (a.rs_fail != nullptr && ld_agent(a.rs_fail) != 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(&a.st->abort_flag, 1);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st_agent(&a.st->abort_flag, 1);
+      report_abort(a);
+    }
     return;
   }
   if (threadIdx.x == 0) s_stop = 0;
@@ -1143,7 +1145,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
           uint32_t spin = 0;
           do {
             sitem = ld_agent(&vq[sbase + lane_id()]);
-          } while (sitem == kEmpty && ++spin < kAsyncSpinLimit);
+          } while (sitem == kEmpty && ++spin < a.spin_limit);
           if (sitem == kEmpty) {
             st_agent(&a.st->abort_flag, 1);
             sitem = -1;
@@ -1183,7 +1185,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
         finished = true;
         break;
       }
-      if (idle > kAsyncSpinLimit) {
+      if (idle > a.spin_limit) {
         if (lane_id() == 0) {
           st_agent(&a.st->abort_flag, 1);
           __hip_atomic_store(&s_stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1201,7 +1203,9 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
     // its range here (every workgroup writes the same final cursors)
     st_agent(&a.st->hi[threadIdx.x], ld_agent(&a.st->tail[threadIdx.x][0]));
   }
-  if (a.rs_next_st != nullptr && ld_agent(&a.st->abort_flag) != 0) {
+  const bool aborted = ld_agent(&a.st->abort_flag) != 0;
+  if (aborted && threadIdx.x == 0) report_abort(a);
+  if (a.rs_next_st != nullptr && aborted) {
     // ended by an abort: other workgroups may still use the queue
     if (threadIdx.x == 0) st_agent(a.rs_fail, 1);
   } else if (a.rs_next_st != nullptr) {
@@ -1215,7 +1219,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
     int32_t *words = reinterpret_cast<int32_t *>(a.rs_next_st);
     for (int64_t i = tid; i < (int64_t)(sizeof(PeelState) / 4); i += stride) words[i] = 0;
   }
-  if (a.pack_bits != nullptr && a.pack_vtx == nullptr && ld_agent(&a.st->abort_flag) == 0) {
+  if (a.pack_bits != nullptr && a.pack_vtx == nullptr && !aborted) {
     // the result (Algorithm 1's V(G)): termination means every decrement
     // is done; degrees are read at device scope (they changed by atomics)
     // kPackSpan consecutive vertices per lane pass, all loads issued before

@@ -276,6 +276,7 @@ bool run_window(Graph &g, Server &S, const std::vector<Request> &win) {
     a.ver = r.version;
     a.pair_limit = r.pairs_after;
     a.ins_head = r.pairs_after > 0 ? g.delta.head : nullptr;
+    a.abort_host = nullptr;  // a served abort is reported with its request
     const int32_t x = win[i].u, y = g.nU + win[i].v;
     SCHK(hipStreamWaitEvent(s.stream, S.applied, 0));
     if (c > 0)

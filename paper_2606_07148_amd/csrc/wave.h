@@ -27,6 +27,13 @@ __device__ __forceinline__ void st_agent(uint32_t *p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Tells the host that a computation ended by a spin-limit abort: one store
+// at system scope into the handle's pinned, coherent word (if any).
+__device__ __forceinline__ void report_abort(const PeelArgs &a) {
+  if (a.abort_host != nullptr)
+    __hip_atomic_store(a.abort_host, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Inclusive prefix sum across the 64 lanes (all lanes must be active).
 __device__ __forceinline__ int wave_incl_scan(int v) {
   const int lane = lane_id();
