@@ -4,13 +4,17 @@
 Workload: seeded Chung-Lu bipartite graph with |U| = 1,000,000,
 |L| = 500,000, 20,000,000 distinct edges, degree-distribution exponent 2.1 on
 both layers, expected degrees capped at 50,000; query (alpha,beta) = (10,10).
-One step = one GCC query (Algorithm 1: scan, peel rounds, bitmask pack) on
-the resident graph.  GCC+ (Algorithm 2) on the same query and its core-number
-preprocessing are timed separately and reported as extra fields, like the
-paper's Table II separates preprocessing from query time.
+One step = one index-free GCC query (Algorithm 1: scan, peel, bitmask) on
+the resident CSR.  The same query on the build's degree-rank copy, cold-cache
+runs of both, GCC+ (Algorithm 2) with its core-number preprocessing, the
+billion-edge sweep, the batch and the serving loop are reported as extra
+fields; preprocessing is timed apart from queries, as in Table II.
 
 Metric: edges peeled per second = (m - |E(core)|) / step time, with the
 numerator taken from the CPU oracle so it does not depend on the GPU code.
+Roofline: the query's algorithmic bytes, computed from the oracle's counts
+(8 B per vertex, n/8, 16 B + 4 B per entry of each removed vertex, 8 B per
+peeled edge), over the step's device time (HIP events), against 8 TB/s.
 """
 from __future__ import annotations
 
@@ -51,20 +55,23 @@ def _kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def _counter_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed hardware-counter
-    summary, or None when the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "gcc_chung_lu_1M_500k_20M_a10_b10.md")
+PROFILE = os.path.join(ROOT, "profiles", "gcc_chung_lu_1M_500k_20M_a10_b10.md")
+
+
+def _counter_traffic_step(mode: str):
+    """HBM bytes of one step of `mode` ("index_free" or "rank_order") from
+    the committed hardware-counter summary (FETCH_SIZE and WRITE_SIZE of
+    every kernel of the step, scaled by a plain copy's readings), or None
+    when the kernel sources changed since the counters were taken."""
     try:
-        text = open(path).read()
+        text = open(PROFILE).read()
         block = text.split("```json", 1)[1].split("```", 1)[0]
         rec = json.loads(block)
     except (OSError, IndexError, ValueError):
         return None
     if rec.get("source_sha256") != _kernel_source_hash():
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k["traffic_bytes"]
+    return rec.get("steps", {}).get(mode)
 
 
 def bench_batch(args, pkg, torch, np, bigraph_gen) -> dict:
@@ -80,6 +87,7 @@ def bench_batch(args, pkg, torch, np, bigraph_gen) -> dict:
           flush=True)
     deu = torch.from_numpy(eu).cuda()
     dev = torch.from_numpy(ev).cuda()
+    pkg.abcore_device_memory(reset_peak=True)
     g = pkg.abcore_build_csr(nU, nL, deu, dev)
     del deu, dev, eu, ev
     a, b = bigraph_gen.loguniform_pairs(256, 1, 256, spec["seed"] + 1000)
@@ -110,6 +118,34 @@ def bench_batch(args, pkg, torch, np, bigraph_gen) -> dict:
     batch_s = (time.perf_counter() - t0) / reps
     parity = bool(torch.equal(out, seq))
     parent, _, states = pkg.abcore_batch_plan(alphas, betas)
+    _, peak = pkg.abcore_device_memory()
+    n = nU + nL
+    gold = _golden("c4")
+    extra = {}
+    if gold is not None and len(gold["queries"]) == q:
+        gq = gold["queries"]
+        extra["parity_vs_oracle_digests"] = all(
+            _sha_words(out[i][: (n + 31) // 32]) == gq[i]["bitmask_sha256"] for i in range(q))
+        seq_bytes = sum(_gcc_bytes(n, x) for x in gq)
+        # a nested query scans n vertices and peels only the difference
+        # between its parent's core and its own; a repeated query copies a
+        # bitmask
+        nested = 0
+        for i in range(q):
+            p = parent[i]
+            if p >= 0 and (alphas[p], betas[p]) == (alphas[i], betas[i]):
+                nested += 2 * (n // 8)
+            elif p >= 0:
+                nested += 8 * n + n // 8 + sum(
+                    c * (gq[i][k] - gq[p][k]) for c, k in
+                    ((16, "removed"), (4, "removed_degree_sum"), (8, "m_peeled")))
+            else:
+                nested += _gcc_bytes(n, gq[i])
+        extra.update(sequential_algorithmic_bytes=seq_bytes,
+                     sequential_frac=seq_bytes / seq_s / 1e9 / HBM_PEAK_GBS,
+                     batch_algorithmic_bytes=nested,
+                     batch_frac=nested / batch_s / 1e9 / HBM_PEAK_GBS,
+                     batch_frac_of_sequential_bytes=seq_bytes / batch_s / 1e9 / HBM_PEAK_GBS)
     g.destroy()
     return {
         "workload": "chung-lu |U|=10,000,000 |L|=5,000,000 m=200,000,000 gamma=2.1/2.1 "
@@ -125,6 +161,8 @@ def bench_batch(args, pkg, torch, np, bigraph_gen) -> dict:
         "roots": sum(1 for p in parent if p < 0),
         "state_buffers": states,
         "replays": reps,
+        "device_memory_library_peak_bytes": peak,
+        **extra,
     }
 
 
@@ -181,6 +219,7 @@ def bench_serve(args, pkg, torch, np, bigraph_gen) -> dict:
     print(f"# serving graph and stream generated in {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
     handles = []
+    pkg.abcore_device_memory(reset_peak=True)
     for _ in range(2):
         deu = torch.from_numpy(eu).cuda()
         dev = torch.from_numpy(ev).cuda()
@@ -234,6 +273,7 @@ def bench_serve(args, pkg, torch, np, bigraph_gen) -> dict:
                        "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99)})
         served += res
         lo = hi
+    _, peak = pkg.abcore_device_memory()
     counters = pkg.abcore_serve_stop(g_srv)
     n_cmp = len(served)
     mismatch = 0
@@ -257,18 +297,47 @@ def bench_serve(args, pkg, torch, np, bigraph_gen) -> dict:
         "device_slots": args.serve_slots,
         "max_inflight": args.serve_inflight,
         "windows": counters["windows"],
+        "device_memory_library_peak_bytes_two_handles": peak,
         "answers_equal_sequential": mismatch == 0,
         "mismatches": mismatch,
     }
 
 
+def _golden(name: str):
+    """Oracle digests of a large workload (tests/golden/<name>_oracle.json,
+    written offline from the oracle alone), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_oracle.json")
+    try:
+        return json.load(open(path))
+    except (OSError, ValueError):
+        return None
+
+
+def _gcc_bytes(n: int, q: dict) -> int:
+    """Algorithmic bytes of one GCC query from the oracle's counts: deg0
+    read and deg written (8 B per vertex), the bitmask (n/8), offsets and
+    row of every removed vertex (16 B + 4 B per entry), one 4-byte
+    read-modify-write atomic per peeled edge (8 B)."""
+    return 8 * n + n // 8 + 16 * q["removed"] + 4 * q["removed_degree_sum"] + 8 * q["m_peeled"]
+
+
+def _sha_words(t) -> str:
+    import hashlib
+    return hashlib.sha256(t.cpu().numpy().astype("<u4").tobytes()).hexdigest()
+
+
 def bench_sweep(args, pkg, torch, np, bigraph_gen) -> dict:
     """The billion-edge GCC+ sweep: Chung-Lu |U|=50M |L|=20M m=10^9, degree
     exponents 2.0 / 2.3, cap 50k; core numbers once, then alpha = beta in
-    {1, 2, 4, ..., 256} with GCC+ (each a scan of the core numbers) and, for
-    comparison, with GCC.  Results compared bit for bit."""
+    {1, 2, 4, ..., 256} with GCC+ (each a pack of the core numbers) and, for
+    comparison, with index-free GCC (each a full peel).  Every bitmask is
+    compared with the oracle's digest; GCC's rate and roofline use the
+    oracle's counts of each query."""
     spec = bigraph_gen.CONFIGS[3]
     nU, nL = spec["n_upper"], spec["n_lower"]
+    n = nU + nL
+    gold = _golden("c3")
+    gq = {} if gold is None else {(q["alpha"], q["beta"]): q for q in gold["queries"]}
     t0 = time.perf_counter()
     eu, ev = bigraph_gen.make_graph(spec)
     print(f"# sweep graph generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
@@ -277,9 +346,12 @@ def bench_sweep(args, pkg, torch, np, bigraph_gen) -> dict:
     deu = torch.from_numpy(eu).cuda()
     dev = torch.from_numpy(ev).cuda()
     del eu, ev
+    pkg.abcore_device_memory(reset_peak=True)
     g = pkg.abcore_build_csr(nU, nL, deu, dev)
     del deu, dev
     torch.cuda.empty_cache()
+    report = pkg.abcore_graph_report(g)
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_RANK_ORDER, 2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, max_core = pkg.abcore_core_numbers(g)
@@ -289,6 +361,8 @@ def bench_sweep(args, pkg, torch, np, bigraph_gen) -> dict:
     ref = torch.empty(g.nwords, dtype=torch.int32, device="cuda")
     rows = []
     parity = True
+    oracle_parity = gold is not None
+    pack_bytes = 4 * n + n // 8
     for k in [1, 2, 4, 8, 16, 32, 64, 128, 256]:
         times = {}
         for algo, name in ((pkg.ABCORE_GCC, "gcc"), (pkg.ABCORE_GCC_PLUS, "gcc_plus")):
@@ -302,18 +376,35 @@ def bench_sweep(args, pkg, torch, np, bigraph_gen) -> dict:
             torch.cuda.synchronize()
             times[name] = (time.perf_counter() - t0) * 1e3 / reps
         parity = parity and bool(torch.equal(out, ref))
-        rows.append({"alpha": k, "beta": k, "gcc_plus_ms": times["gcc_plus"],
-                     "gcc_ms": times["gcc"]})
+        row = {"alpha": k, "beta": k, "gcc_plus_ms": times["gcc_plus"],
+               "gcc_plus_pack_frac": pack_bytes / (times["gcc_plus"] / 1e3) / 1e9 / HBM_PEAK_GBS,
+               "gcc_ms": times["gcc"]}
+        q = gq.get((k, k))
+        if q is not None:
+            B = _gcc_bytes(n, q)
+            row.update(gcc_edges_peeled_per_s=q["m_peeled"] / (times["gcc"] / 1e3),
+                       gcc_algorithmic_bytes=B,
+                       gcc_frac=B / (times["gcc"] / 1e3) / 1e9 / HBM_PEAK_GBS)
+            oracle_parity = oracle_parity and _sha_words(ref[: (n + 31) // 32]) == \
+                q["bitmask_sha256"]
+        rows.append(row)
+    _, peak = pkg.abcore_device_memory()
     g.destroy()
     total_plus = sum(r["gcc_plus_ms"] for r in rows)
     return {
         "workload": "chung-lu |U|=50,000,000 |L|=20,000,000 m=1,000,000,000 "
                     "gamma=2.0/2.3 cap=50,000; alpha=beta in {1,2,4,...,256}",
-        "m": m, "core_preprocessing_ms": prep_ms, "max_core": max_core,
+        "m": m, "core_preprocessing_ms": prep_ms,
+        "core_preprocessing_edges_per_s": m / (prep_ms / 1e3),
+        "core_preprocessing_frac": (20 * n + 16 * m) / (prep_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "max_core": max_core,
         "queries": rows, "gcc_plus_total_ms": total_plus,
         "gcc_total_ms": sum(r["gcc_ms"] for r in rows),
-        "gcc_plus_input_edges_per_s": m * len(rows) / (total_plus / 1e3),
+        "gcc_plus_pack_bytes": pack_bytes,
         "parity_gcc_plus_vs_gcc": parity,
+        "parity_vs_oracle_digests": oracle_parity,
+        "build": report,
+        "device_memory_library_peak_bytes": peak,
     }
 
 
@@ -338,6 +429,8 @@ def main() -> int:
     ap.add_argument("--serve-inflight", type=int, default=64)
     ap.add_argument("--serve-pull", type=int, default=0,
                     help="ABCORE_OPT_PULL of the served handle (0 = default)")
+    ap.add_argument("--step-mode", choices=["both", "index_free", "rank_order"], default="both",
+                    help="GCC step variants to run (one alone for per-kernel hardware counters)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device copy of MIB MiB (hardware-counter scale)")
     args = ap.parse_args()
@@ -380,6 +473,7 @@ def main() -> int:
     deu = torch.from_numpy(eu).cuda()
     dev = torch.from_numpy(ev).cuda()
     torch.cuda.synchronize()
+    pkg.abcore_device_memory(reset_peak=True)
     t0 = time.perf_counter()
     g = pkg.abcore_build_csr(nU, nL, deu, dev)
     torch.cuda.synchronize()
@@ -407,122 +501,95 @@ def main() -> int:
     sum_deg_removed = stats_o["removed_degree_sum"]
     want = oracle.pack(member)
 
-    # --- GPU: GCC timed region -------------------------------------------
+    # --- GPU: GCC steps ---------------------------------------------------
+    # Algorithmic bytes of one GCC query, from the oracle's counts alone
+    # (independent of the implementation): deg0 read and deg written (8 B
+    # per vertex), the bitmask (n/8), offsets and row of every removed
+    # vertex (16 B + 4 B per entry), one 4-byte read-modify-write atomic per
+    # peeled edge (8 B).
+    B = 8 * n + n // 8 + 16 * removed + 4 * sum_deg_removed + 8 * m_peeled
     out = torch.empty(max(1, g.nwords), dtype=torch.int32, device="cuda")
-    for _ in range(args.warmup):
-        pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out)
-    torch.cuda.synchronize()
-    got = out.cpu().numpy().view(np.uint32)[: len(want)]
-    parity = bool(np.array_equal(got, want))
-    _, gst = pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out, stats=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed * 1e3 / args.steps
-    # per-kernel durations: the same steps again with an event pair around
-    # every launch, on the stream the kernels run on
-    pkg.abcore_set_option(g, pkg.ABCORE_OPT_TIMING, 1)
-    for kind in range(5):
-        pkg.abcore_kernel_timing(g, kind, reset=True)
-    for _ in range(args.steps):
-        pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out)
-    torch.cuda.synchronize()
-    ktime = {kind: pkg.abcore_kernel_timing(g, kind, reset=True) for kind in range(5)}
-    pkg.abcore_set_option(g, pkg.ABCORE_OPT_TIMING, 0)
-    value = m_peeled / (ms_per_step / 1e3)
+    stream = torch.cuda.current_stream()
+    flush = torch.empty(1 << 28, dtype=torch.int32, device="cuda")  # 1 GiB
 
-    # algorithmic bytes per query of each kernel, from the oracle's sets:
-    # F0 = scan frontier, A1 = its complement, R = removed vertices
-    thr = np.where(np.arange(n) < nU, alpha, beta)
-    f0 = deg < thr
-    removed_mask = ~member
-    lower = nU + ev.astype(np.int64)
-    upper = eu.astype(np.int64)
-    pulled = bool(gst["pulled"])
-    if pulled:
-        a1 = ~f0
-        r2 = removed_mask & a1
-        touch_r2 = r2[upper] | r2[lower]
-        touch_f0 = f0[upper] | f0[lower]
-        m2 = int(np.count_nonzero(touch_r2 & ~touch_f0))
-        push_bytes = 16 * int(r2.sum()) + 4 * int(deg[r2].sum()) + 8 * m2
-        pull_bytes = 20 * int(a1.sum()) + 4 * int(deg[a1].sum()) + n // 8
-    else:
-        push_bytes = 16 * removed + 4 * sum_deg_removed + 8 * m_peeled
-        pull_bytes = 0
-    # the asynchronous mode scans and resets the workspace in one kernel
-    # that does not queue the frontier: it returns the previous query's
-    # queued items to empty, and a pushed first round queues the frontier
-    # from the bitmap in the pull kernel instead
-    fused_scan = args.peel_mode in (0, 3)
-    rank_order = bool(gst.get("rank_order", 0))
-    n_f0 = int(f0.sum())
-    if rank_order:
-        # the query runs on the degree-rank relabelling, without a scan
-        # launch: the pull round reads a light row's offsets (8 B) and
-        # entries and writes its degree (4 B), searches a split row, and
-        # writes the survivor bitmap into the result (deg0 read, n/8
-        # written); the peel maps each survivor it removes to its vertex
-        # (4 B) and clears its bit in the result (an 8 B read-modify-write),
-        # so no pack pass follows, and after termination returns its queued
-        # items to empty (4 B each) and zeroes the next query's 4096 x 10
-        # partial sums
-        a1 = ~f0
-        light = a1 & (deg <= 64)
-        heavy = a1 & (deg > 64)
-        r2n = removed - n_f0
-        scan_bytes = 0
-        pull_bytes = (12 * int(light.sum()) + 4 * int(deg[light].sum())
-                      + (24 + 4 * 16 * 4) * int(heavy.sum()) + 4 * n + n // 8)
-    elif fused_scan:
-        queued = removed - n_f0 if pulled else removed
-        scan_bytes = 8 * n + n // 8 + 4 * queued
-        if not pulled:
-            pull_bytes = n // 8 + 4 * n_f0
-        else:
-            # on an unchanged graph the pull round counts on the degree-rank
-            # copy: a row of at most 64 entries is read whole, a split row is
-            # searched (16 probes of 4 B in about four steps) and completed
-            # at once; the survivor bits are read, no bitmap is staged
-            light = a1 & (deg <= 64)
-            heavy = a1 & (deg > 64)
-            pull_bytes = (20 * int(light.sum()) + 4 * int(deg[light].sum())
-                          + (24 + 4 * 16 * 4) * int(heavy.sum()) + n // 8)
-    else:
-        scan_bytes = 8 * n + 4 * n_f0 + (n // 8 if pulled else 0)
-    pack_bytes = (12 * (removed - n_f0) + 4 * (removed - n_f0) + 8 * 4096 * 10 if rank_order
-                  else 4 * n + n // 8)
-    kinfo = {}
-    peel_name = {1: "peel_round_kernel<0>", 2: "peel_persistent_kernel<0>"}.get(
-        args.peel_mode, "peel_async_kernel<0>")  # <0> = the GCC instantiation
-    # the degree-rank pull round stages no bitmap: the kLds = false build
-    names = {0: peel_name, 1: "pull_round_kernel<false>" if (fused_scan and pulled)
-             else "pull_round_kernel<true>",
-             2: "scan_reset_gcc_kernel" if fused_scan else "scan_gcc_kernel", 3: "pack_kernel",
-             4: "pull_fixup_kernel"}
-    # fixup: split rows (more than 64 entries): row id, deg0 and deg read
-    # (none after a degree-rank pull round, which completes them itself)
-    fixup_bytes = 12 * int(np.count_nonzero(deg > 64)) if pulled and not fused_scan else 0
-    kbytes = {0: push_bytes, 1: pull_bytes, 2: scan_bytes, 3: pack_bytes, 4: fixup_bytes}
-    # the asynchronous peel runs the pack and the pull round's completion
-    # itself (no separate launches): its bytes include theirs
-    if ktime[3][1] == 0:
-        kbytes[0] += pack_bytes
-    if ktime[4][1] == 0:
-        kbytes[0] += fixup_bytes
-    for kind, (ms, launches) in ktime.items():
-        if launches == 0:
+    def run_steps(rank_mode: int, cold: bool = False, steps: int = args.steps) -> dict:
+        """Warm-up, parity, then `steps` wall-clock-timed steps and `steps`
+        steps each bracketed by a HIP event pair on the kernels' stream; a
+        cold step first writes 1 GiB (evicting L2 and the 256 MB Infinity
+        Cache) outside its events."""
+        pkg.abcore_set_option(g, pkg.ABCORE_OPT_RANK_ORDER, rank_mode)
+        for _ in range(args.warmup):
+            pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out)
+        torch.cuda.synchronize()
+        ok = bool(np.array_equal(out.cpu().numpy().view(np.uint32)[: len(want)], want))
+        _, st = pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out, stats=True)
+        torch.cuda.synchronize()
+        wall = None
+        if not cold:
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) * 1e3 / steps
+        evs = []
+        for k in range(steps):
+            if cold:
+                flush.fill_(k)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out)
+            e1.record(stream)
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        ok = ok and bool(np.array_equal(out.cpu().numpy().view(np.uint32)[: len(want)], want))
+        durs = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+        ev_ms = float(durs.mean())
+        return {"ms_per_step": wall, "event_ms_mean": ev_ms,
+                "event_ms_p50": float(np.percentile(durs, 50)),
+                "event_ms_p90": float(np.percentile(durs, 90)),
+                "algorithmic_GBs": B / (ev_ms / 1e3) / 1e9,
+                "frac": B / (ev_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                "parity": ok, "stats": st}
+
+    def kernel_split(rank_mode: int) -> dict:
+        """Per-kernel device time of the step (an event pair around every
+        launch, recorded by the library on the launch stream)."""
+        pkg.abcore_set_option(g, pkg.ABCORE_OPT_RANK_ORDER, rank_mode)
+        pkg.abcore_set_option(g, pkg.ABCORE_OPT_TIMING, 1)
+        for kind in range(5):
+            pkg.abcore_kernel_timing(g, kind, reset=True)
+        for _ in range(args.steps):
+            pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC, out=out)
+        torch.cuda.synchronize()
+        kt = {kind: pkg.abcore_kernel_timing(g, kind, reset=True) for kind in range(5)}
+        pkg.abcore_set_option(g, pkg.ABCORE_OPT_TIMING, 0)
+        names = {0: "peel", 1: "pull", 2: "scan", 3: "pack", 4: "fixup"}
+        return {names[k]: {"avg_launch_us": ms * 1e3 / cnt, "launches_per_step": cnt / args.steps}
+                for k, (ms, cnt) in kt.items() if cnt > 0}
+
+    modes = {"index_free": 2, "rank_order": 1}
+    runs = {}
+    for name, mode in modes.items():
+        if args.step_mode not in ("both", name):
             continue
-        per_launch_s = ms / 1e3 / launches
-        bpl = kbytes[kind] * args.steps / launches
-        kinfo[names[kind]] = {"avg_launch_us": per_launch_s * 1e6, "launches_per_step":
-                              launches / args.steps, "bytes_per_launch": bpl,
-                              "achieved_GBs": bpl / per_launch_s / 1e9 if per_launch_s > 0 else 0}
-    dom = max(kinfo, key=lambda k: kinfo[k]["avg_launch_us"] * kinfo[k]["launches_per_step"])
-    step_bytes = scan_bytes + pull_bytes + push_bytes + pack_bytes + fixup_bytes
+        runs[name] = run_steps(mode)
+        runs[name]["kernels"] = kernel_split(mode)
+        if args.step_mode == "both":
+            runs[name + "_cold"] = run_steps(mode, cold=True)
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_RANK_ORDER, 2)
+    parity = all(r["parity"] for r in runs.values())
+    # the headline is the index-free step (Algorithm 1 on the CSR alone)
+    free = runs.get("index_free") or runs["rank_order"]
+    ranked = runs.get("rank_order")
+    free_cold = runs.get("index_free_cold")
+    ranked_cold = runs.get("rank_order_cold")
+    gst = free["stats"]
+    ms_per_step = free["ms_per_step"]
+    value = m_peeled / (ms_per_step / 1e3)
+    report = pkg.abcore_graph_report(g)
+    traffic = _counter_traffic_step("index_free" if "index_free" in runs else "rank_order")
+    ranked_traffic = _counter_traffic_step("rank_order")
 
     # --- GCC+ (Algorithm 2): preprocessing + query ------------------------
     gcc_plus = None
@@ -542,9 +609,16 @@ def main() -> int:
             pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC_PLUS, out=out)
         torch.cuda.synchronize()
         plus_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        # alpha = beta: Lemma 1 leaves no uncertain vertex, so the query is a
+        # pack of the cached core numbers (4 B read per vertex, n/8 written)
+        pack_bytes = 4 * n + n // 8
         gcc_plus = {"ms_per_query": plus_ms, "parity": plus_parity,
-                    "edges_peeled_per_s": m_peeled / (plus_ms / 1e3),
-                    "core_preprocessing_ms": prep_ms, "max_core": max_core}
+                    "query_is_pack_of_core_numbers": True,
+                    "pack_GBs": pack_bytes / (plus_ms / 1e3) / 1e9,
+                    "pack_frac": pack_bytes / (plus_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                    "core_preprocessing_ms": prep_ms, "max_core": max_core,
+                    "edges_peeled_per_s_incl_preprocessing":
+                        m_peeled / ((prep_ms + plus_ms) / 1e3)}
         # Algorithm 2 with alpha != beta (uncertain vertices are peeled),
         # against GCC on the same pairs; both results must agree bit for bit
         asym = []
@@ -564,7 +638,11 @@ def main() -> int:
             row["equal"] = bool(torch.equal(res["gcc"], res["gcc_plus"]))
             plus_parity = plus_parity and row["equal"]
             asym.append(row)
-        gcc_plus["asymmetric"] = asym
+        gcc_plus["asymmetric_index_free"] = asym
+    _, peak_c2 = pkg.abcore_device_memory()
+    c2_torch_peak = torch.cuda.max_memory_allocated()
+    del flush
+    torch.cuda.empty_cache()
 
     batch = None
     if not args.no_batch:
@@ -592,30 +670,43 @@ def main() -> int:
         "data": "synthetic: seeded Chung-Lu bipartite graph (bigraph_gen config 2)",
         "config": {
             "workload": "chung-lu |U|=1,000,000 |L|=500,000 m=20,000,000 gamma=2.1/2.1 "
-                        "cap=50,000; (alpha,beta)=(10,10); GCC",
+                        "cap=50,000; (alpha,beta)=(10,10); GCC, index-free (vertex order, "
+                        "CSR only)",
             "n_upper": nU, "n_lower": nL, "m": int(ref.m), "alpha": alpha, "beta": beta,
             "algo": "GCC", "seed": spec["seed"],
             "edge_sha256": bigraph_gen.edge_hash(eu, ev),
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": dom,
-            "achieved": kinfo[dom]["achieved_GBs"],
+            "scope": "one GCC query (scan, pull round, asynchronous peel)",
+            "achieved": free["algorithmic_GBs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": kinfo[dom]["achieved_GBs"] / HBM_PEAK_GBS,
-            "traffic": _counter_traffic(dom),
-            "bytes_per_launch": kinfo[dom]["bytes_per_launch"],
-            "avg_launch_us": kinfo[dom]["avg_launch_us"],
+            "frac": free["frac"],
+            "traffic": None if traffic is None else traffic["bytes"],
+            "algorithmic_bytes": B,
+            "step_event_us": free["event_ms_mean"] * 1e3,
+            "traffic_ratio": None if traffic is None else traffic["bytes"] / B,
         },
-        "kernels": kinfo,
+        "index_free": {k: v for k, v in free.items() if k != "stats"},
+        "rank_order": None if ranked is None else dict(
+            {k: v for k, v in ranked.items() if k != "stats"},
+            preprocessing_ms=report["ranks_ms"], extra_device_bytes=report["ranks_bytes"],
+            traffic=None if ranked_traffic is None else ranked_traffic["bytes"],
+            edges_peeled_per_s=m_peeled / (ranked["ms_per_step"] / 1e3)),
+        "cold_cache": None if free_cold is None else {
+            "index_free": {k: v for k, v in free_cold.items() if k not in ("stats", "ms_per_step")},
+            "rank_order": {k: v for k, v in ranked_cold.items()
+                           if k not in ("stats", "ms_per_step")},
+            "flush": "1 GiB written before each step, outside its events"},
+        "build": report,
+        "device_memory": {"library_peak_bytes": peak_c2, "torch_peak_bytes": c2_torch_peak},
         "gpu_stats": gst,
         "parity": parity,
         "m_peeled": m_peeled,
         "removed": removed,
+        "removed_degree_sum": sum_deg_removed,
         "rounds": stats_o["rounds"],
-        "step_algorithmic_bytes": step_bytes,
-        "step_gbs": step_bytes / (ms_per_step / 1e3) / 1e9,
         "input_edges_per_s": ref.m / (ms_per_step / 1e3),
         "gcc_plus": gcc_plus,
         "batch": batch,
@@ -634,8 +725,10 @@ def main() -> int:
     print(json.dumps(result), flush=True)
     g.destroy()
     ok = (parity and plus_parity and (batch is None or batch["parity_vs_sequential"])
+          and (batch is None or batch.get("parity_vs_oracle_digests", True))
           and (serve is None or serve["answers_equal_sequential"])
-          and (sweep is None or sweep["parity_gcc_plus_vs_gcc"]))
+          and (sweep is None or (sweep["parity_gcc_plus_vs_gcc"]
+                                 and sweep["parity_vs_oracle_digests"])))
     return 0 if ok else 1
 
 

@@ -86,6 +86,32 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
                                const int32_t *d_ev, int64_t m, void *stream,
                                abcore_graph *out, int64_t *out_m_distinct);
 
+/* What a handle's build cost and what it holds (the paper reports GPU
+ * memory per dataset, Sec. VI Fig. 4; Table II separates preprocessing from
+ * query time).  Times are wall-clock milliseconds of abcore_build_csr's
+ * phases, each ended by a synchronisation: the CSR (dedupe, both
+ * adjacencies), the row pieces, and the degree-rank copy -- an optional
+ * index the build adds for queries on an unchanged graph (0 when the build
+ * skipped it); Algorithm 1 itself needs none of it.  Bytes: the graph (CSR
+ * offsets and columns, degrees, row pieces), the degree-rank copy, and the
+ * frontier sub-queues of the handle's working set. */
+typedef struct {
+  double build_ms;      /* whole abcore_build_csr */
+  double csr_ms;        /* dedupe and the unified CSR */
+  double pieces_ms;     /* row pieces of rows longer than 64 entries */
+  double ranks_ms;      /* degree-rank copy and its tables */
+  int64_t graph_bytes;  /* off, cols, deg0, row pieces */
+  int64_t ranks_bytes;  /* degree-rank copy: ranks, relabelled CSR, pieces, degree slots */
+  int64_t queue_bytes;  /* frontier sub-queues of the handle's working set */
+} abcore_report;
+
+abcore_status abcore_graph_report(abcore_graph g, abcore_report *out);
+
+/* Device memory the library holds, summed over all handles and devices:
+ * current bytes and the peak since the last reset (reset_peak != 0 sets the
+ * peak to the current value after reading).  Host bookkeeping only. */
+abcore_status abcore_device_memory(int64_t *current, int64_t *peak, int32_t reset_peak);
+
 /* Releases every resource of the handle.  NULL is accepted. */
 abcore_status abcore_destroy(abcore_graph g);
 
@@ -245,7 +271,9 @@ abcore_status abcore_serve_stop(abcore_graph g, int64_t *counters);
  *                          pulled runs on the degree-rank relabelling of the
  *                          graph while it is unchanged since the build (the
  *                          scan's survivors are then known in advance, Sec.
- *                          IV-A); 2 = always in vertex order.
+ *                          IV-A), and other first pull rounds count on it;
+ *                          2 = index-free: every query runs in vertex order
+ *                          on the CSR alone, as Algorithm 1 does.
  *   ABCORE_OPT_SPIN_LIMIT: failure injection for tests: polls a waiting wave
  *                          of the asynchronous peel makes before it declares
  *                          a hang and aborts (0 = the default, 2^21, i.e.

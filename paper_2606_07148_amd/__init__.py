@@ -49,6 +49,16 @@ class abcore_stats(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class abcore_report(ctypes.Structure):
+    _fields_ = [("build_ms", ctypes.c_double), ("csr_ms", ctypes.c_double),
+                ("pieces_ms", ctypes.c_double), ("ranks_ms", ctypes.c_double),
+                ("graph_bytes", ctypes.c_int64), ("ranks_bytes", ctypes.c_int64),
+                ("queue_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class abcore_edge_update(ctypes.Structure):
     _fields_ = [("u", ctypes.c_int32), ("v", ctypes.c_int32), ("op", ctypes.c_int32)]
 
@@ -85,6 +95,8 @@ def load():
         "abcore_submit": (i32, [vp, abcore_edge_update, u32, u32, P(ctypes.c_uint64)]),
         "abcore_poll": (i32, [vp, ctypes.c_uint64, P(i32), P(u32), P(ctypes.c_uint64)]),
         "abcore_serve_stop": (i32, [vp, P(i64)]),
+        "abcore_graph_report": (i32, [vp, P(abcore_report)]),
+        "abcore_device_memory": (i32, [P(i64), P(i64), i32]),
         "abcore_autotune": (i32, [vp, u32, u32, i32, P(i32), P(i32), P(ctypes.c_double), vp]),
     }
     for name, (res, args) in sig.items():
@@ -170,6 +182,20 @@ def abcore_build_csr(n_upper: int, n_lower: int, eu, ev, stream=None) -> Graph:
                                    int(eu.numel()), _stream(stream), ctypes.byref(h),
                                    ctypes.byref(md)))
     return Graph(h, int(n_upper), int(n_lower), int(md.value))
+
+
+def abcore_graph_report(g: Graph) -> dict:
+    """Build phase times (ms) and byte counts of a handle."""
+    r = abcore_report()
+    _check(load().abcore_graph_report(g.handle, ctypes.byref(r)))
+    return r.as_dict()
+
+
+def abcore_device_memory(reset_peak: bool = False):
+    """(current, peak) device bytes held by the library."""
+    cur, peak = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().abcore_device_memory(ctypes.byref(cur), ctypes.byref(peak), int(reset_peak)))
+    return int(cur.value), int(peak.value)
 
 
 def abcore_destroy(g: Graph) -> None:

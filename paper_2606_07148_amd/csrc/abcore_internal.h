@@ -238,6 +238,8 @@ struct Graph {
   int32_t *parent = nullptr; // union-find scratch
   Delta delta;
   int version = 0;
+  // wall times of the build's phases: CSR, row pieces, degree-rank copy, all
+  double build_ms[4] = {0, 0, 0, 0};
   // device facts and options
   int cu_count = 256;
   size_t lds_per_block = 65536;
@@ -357,6 +359,15 @@ struct PeelArgs {
 
 void set_error(const char *fmt, ...);
 PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL);
+
+// Every device allocation of the library goes through these two, which keep
+// the library-wide current and peak byte counts (abcore_device_memory).
+hipError_t dev_malloc_bytes(void **p, size_t bytes);
+template <class T>
+hipError_t dev_malloc(T **p, size_t bytes) {
+  return dev_malloc_bytes(reinterpret_cast<void **>(p), bytes);
+}
+hipError_t dev_free(void *p);
 
 // Launchers (defined in the .hip files).
 // keep_abort: leave the abort flag as it is (several computations in one

@@ -4,13 +4,45 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 
 #include "abcore_internal.h"
 
 namespace abc {
 
 static thread_local char g_error[512] = "";
+
+// ------------------------------------------------- allocation accounting --
+static std::mutex g_mem_mu;
+static std::unordered_map<void *, size_t> g_mem_sizes;
+static int64_t g_mem_current = 0, g_mem_peak = 0;
+
+hipError_t dev_malloc_bytes(void **p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipSuccess && *p != nullptr) {
+    std::lock_guard<std::mutex> lock(g_mem_mu);
+    g_mem_sizes[*p] = bytes;
+    g_mem_current += (int64_t)bytes;
+    g_mem_peak = std::max(g_mem_peak, g_mem_current);
+  }
+  return e;
+}
+
+hipError_t dev_free(void *p) {
+  if (p == nullptr) return hipSuccess;
+  {
+    std::lock_guard<std::mutex> lock(g_mem_mu);
+    auto it = g_mem_sizes.find(p);
+    if (it != g_mem_sizes.end()) {
+      g_mem_current -= (int64_t)it->second;
+      g_mem_sizes.erase(it);
+    }
+  }
+  return hipFree(p);
+}
 
 void set_error(const char *fmt, ...) {
   va_list ap;
@@ -46,11 +78,11 @@ abcore_status grow_delta(Graph &g, int64_t min_cap, hipStream_t s) {
   Delta &d = g.delta;
   hipError_t e = hipSuccess;
   if (d.head == nullptr) {
-    e = hipMalloc(&d.head, sizeof(int32_t) * std::max<int64_t>(g.n, 1));
+    e = dev_malloc(&d.head, sizeof(int32_t) * std::max<int64_t>(g.n, 1));
     if (e == hipSuccess)
       e = hipMemsetAsync(d.head, 0xFF, sizeof(int32_t) * std::max<int64_t>(g.n, 1), s);
     if (e != hipSuccess) {
-      if (d.head) (void)hipFree(d.head);
+      if (d.head) (void)dev_free(d.head);
       d.head = nullptr;
       set_error("delta allocation failed: %s", hipGetErrorString(e));
       return ABCORE_ENOMEM;
@@ -60,9 +92,9 @@ abcore_status grow_delta(Graph &g, int64_t min_cap, hipStream_t s) {
   int64_t ncap = std::max<int64_t>(1024, d.cap);
   while (ncap < min_cap) ncap *= 2;
   int32_t *nn = nullptr, *no = nullptr, *nv = nullptr;
-  e = hipMalloc(&nn, sizeof(int32_t) * 2 * ncap);
-  if (e == hipSuccess) e = hipMalloc(&no, sizeof(int32_t) * 2 * ncap);
-  if (e == hipSuccess) e = hipMalloc(&nv, sizeof(int32_t) * ncap);
+  e = dev_malloc(&nn, sizeof(int32_t) * 2 * ncap);
+  if (e == hipSuccess) e = dev_malloc(&no, sizeof(int32_t) * 2 * ncap);
+  if (e == hipSuccess) e = dev_malloc(&nv, sizeof(int32_t) * ncap);
   if (e == hipSuccess) e = hipMemsetAsync(nv, 0, sizeof(int32_t) * ncap, s);
   if (e == hipSuccess && d.count > 0) {
     e = hipMemcpyAsync(nn, d.next, sizeof(int32_t) * 2 * d.count, hipMemcpyDeviceToDevice, s);
@@ -75,13 +107,13 @@ abcore_status grow_delta(Graph &g, int64_t min_cap, hipStream_t s) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     for (void *p : {(void *)nn, (void *)no, (void *)nv})
-      if (p) (void)hipFree(p);
+      if (p) (void)dev_free(p);
     set_error("delta growth failed: %s", hipGetErrorString(e));
     return ABCORE_ENOMEM;
   }
-  if (d.next) (void)hipFree(d.next);
-  if (d.other) (void)hipFree(d.other);
-  if (g.pair_del_ver) (void)hipFree(g.pair_del_ver);
+  if (d.next) (void)dev_free(d.next);
+  if (d.other) (void)dev_free(d.other);
+  if (g.pair_del_ver) (void)dev_free(g.pair_del_ver);
   d.next = nn;
   d.other = no;
   g.pair_del_ver = nv;
@@ -117,8 +149,8 @@ void free_graph(Graph *g) {
   if (!g) return;
   (void)hipSetDevice(g->device);
   destroy_server(*g);
-  if (g->del_ver) (void)hipFree(g->del_ver);
-  if (g->pair_del_ver) (void)hipFree(g->pair_del_ver);
+  if (g->del_ver) (void)dev_free(g->del_ver);
+  if (g->pair_del_ver) (void)dev_free(g->pair_del_ver);
   for (auto &ev : g->events)
     for (auto &pr : ev) {
       (void)hipEventDestroy(pr.first);
@@ -129,7 +161,7 @@ void free_graph(Graph *g) {
   if (g->batch.graph) (void)hipGraphDestroy(g->batch.graph);
   if (g->capture_stream) (void)hipStreamDestroy(g->capture_stream);
   for (int32_t *p : g->slots)
-    if (p) (void)hipFree(p);
+    if (p) (void)dev_free(p);
   void *bufs[] = {g->off,        g->cols,        g->deg0,        g->deg,
                   g->queue,      g->list,        g->list2,       g->state,
                   g->core,       g->comp,        g->parent,      g->delta.head,
@@ -140,7 +172,7 @@ void free_graph(Graph *g) {
                   g->rp_start,    g->rp_first,    g->rdeg,        g->state_alt,
                   g->part_alt,    g->rs_fail};
   for (void *p : bufs)
-    if (p) (void)hipFree(p);
+    if (p) (void)dev_free(p);
   if (g->h_abort) (void)hipHostFree(g->h_abort);
   if (g->h_state) (void)hipHostFree(g->h_state);
   if (g->h_part) (void)hipHostFree(g->h_part);
@@ -150,7 +182,7 @@ void free_graph(Graph *g) {
 template <class T>
 abcore_status ensure(T **p, int64_t count) {
   if (*p) return ABCORE_OK;
-  hipError_t e = hipMalloc(p, sizeof(T) * std::max<int64_t>(count, 1));
+  hipError_t e = dev_malloc(p, sizeof(T) * std::max<int64_t>(count, 1));
   if (e != hipSuccess) {
     *p = nullptr;
     set_error("device allocation of %lld elements failed: %s", (long long)count,
@@ -413,7 +445,7 @@ abcore_status run_batch(Graph &g, const BatchPlan &plan, const int32_t *tu, cons
       // first round counted on the degree-rank copy when the graph has one
       CHK(launch_scan_reset_gcc(g, tu[i], tl[i], s, true));
       TRY(pull_peel_pack(g, kGCC, tu[i], tl[i], true, out, s, &launches, true, nullptr, false,
-                         false, g.version == 0));
+                         false, g.rank_order && g.version == 0));
     } else if (p < 0) {
       CHK(launch_init_state(g, s, true));
       CHK(launch_scan_gcc(g, tu[i], tl[i], pull, s));
@@ -436,7 +468,7 @@ abcore_status run_batch(Graph &g, const BatchPlan &plan, const int32_t *tu, cons
 abcore_status ensure_slots(Graph &g, int n_slots) {
   while ((int)g.slots.size() < n_slots) {
     int32_t *p = nullptr;
-    hipError_t e = hipMalloc(&p, sizeof(int32_t) * std::max<int64_t>(g.n, 1));
+    hipError_t e = dev_malloc(&p, sizeof(int32_t) * std::max<int64_t>(g.n, 1));
     if (e != hipSuccess) {
       set_error("batch: allocation of degree state %d failed: %s", (int)g.slots.size(),
                 hipGetErrorString(e));
@@ -585,6 +617,7 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
   }
   hipStream_t s = as_stream(stream);
   abcore_status st = ABCORE_OK;
+  const auto t_build = std::chrono::steady_clock::now();
   do {
     if (hipGetDevice(&g->device) != hipSuccess) {
       set_error("abcore_build_csr: no HIP device");
@@ -599,12 +632,26 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
     g->nU = n_upper;
     g->nL = n_lower;
     g->n = (int64_t)n_upper + n_lower;
+    // each phase ends synchronised, so its wall time is its own
+    auto now = [] { return std::chrono::steady_clock::now(); };
+    auto ms_since = [&](std::chrono::steady_clock::time_point t) {
+      return std::chrono::duration<double, std::milli>(now() - t).count();
+    };
+    auto t0 = now();
     st = build_csr_device(*g, d_eu, d_ev, m, s);
+    if (st == ABCORE_OK && hipStreamSynchronize(s) != hipSuccess) st = ABCORE_EDEVICE;
     if (st != ABCORE_OK) break;
+    g->build_ms[0] = ms_since(t0);
+    t0 = now();
     st = build_pieces(*g, s);
+    if (st == ABCORE_OK && hipStreamSynchronize(s) != hipSuccess) st = ABCORE_EDEVICE;
     if (st != ABCORE_OK) break;
+    g->build_ms[1] = ms_since(t0);
+    t0 = now();
     st = build_ranks(*g, s);
+    if (st == ABCORE_OK && hipStreamSynchronize(s) != hipSuccess) st = ABCORE_EDEVICE;
     if (st != ABCORE_OK) break;
+    g->build_ms[2] = ms_since(t0);
     // per computation a vertex enters the queues at most twice (GCC+: as
     // uncertain, then as removed) and a split row once more as its pieces
     g->qcap = 2 * g->n + g->npieces + kLocalQueue;
@@ -619,12 +666,12 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
     if ((st = ensure(&g->row_bits, (g->n + 31) / 32 + 1)) != ABCORE_OK) break;
     if ((st = ensure(&g->part, (int64_t)kMaxBlocks * kPartFields)) != ABCORE_OK) break;
     if ((st = ensure(&g->part_alt, (int64_t)kMaxBlocks * kPartFields)) != ABCORE_OK) break;
-    hipError_t e = hipMalloc(&g->state, sizeof(PeelState));
+    hipError_t e = dev_malloc(&g->state, sizeof(PeelState));
     // the state is read (queue tails) by the first initialisation: zero it
     if (e == hipSuccess) e = hipMemsetAsync(g->state, 0, sizeof(PeelState), s);
-    if (e == hipSuccess) e = hipMalloc(&g->state_alt, sizeof(PeelState));
+    if (e == hipSuccess) e = dev_malloc(&g->state_alt, sizeof(PeelState));
     if (e == hipSuccess) e = hipMemsetAsync(g->state_alt, 0, sizeof(PeelState), s);
-    if (e == hipSuccess) e = hipMalloc(&g->rs_fail, sizeof(int32_t));
+    if (e == hipSuccess) e = dev_malloc(&g->rs_fail, sizeof(int32_t));
     if (e == hipSuccess) e = hipMemsetAsync(g->rs_fail, 0, sizeof(int32_t), s);
     if (e == hipSuccess) e = hipHostMalloc(&g->h_state, sizeof(PeelState));
     if (e == hipSuccess)
@@ -656,8 +703,40 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
     free_graph(g);
     return st;
   }
+  g->build_ms[3] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                             t_build).count();
   if (out_m_distinct) *out_m_distinct = g->m;
   *out = reinterpret_cast<abcore_graph>(g);
+  return ABCORE_OK;
+}
+
+abcore_status abcore_graph_report(abcore_graph h, abcore_report *out) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (!g || !out) {
+    set_error("abcore_graph_report: null handle or output");
+    return ABCORE_EINVAL;
+  }
+  out->build_ms = g->build_ms[3];
+  out->csr_ms = g->build_ms[0];
+  out->pieces_ms = g->build_ms[1];
+  out->ranks_ms = g->rcols != nullptr ? g->build_ms[2] : 0.0;
+  const int64_t n = g->n, np = g->npieces;
+  out->graph_bytes = 8 * (n + 1) + 4 * 2 * g->m_csr + 4 * n + (4 + 8 + 4) * np + 4 * n +
+                     4 * g->nheavy;
+  out->ranks_bytes = g->rcols == nullptr
+                         ? 0
+                         : 4 * n + 4 * n + 8 * (n + 1) + 4 * 2 * g->m_csr +
+                               (g->rp_row != nullptr ? (4 + 8) * np + 4 * n : 0) +
+                               (g->rdeg != nullptr ? 4 * ((int64_t)g->rdeg_mask + 1) : 0);
+  out->queue_bytes = 4 * (int64_t)kSub * g->qcap;
+  return ABCORE_OK;
+}
+
+abcore_status abcore_device_memory(int64_t *current, int64_t *peak, int32_t reset_peak) {
+  std::lock_guard<std::mutex> lock(g_mem_mu);
+  if (current) *current = g_mem_current;
+  if (peak) *peak = g_mem_peak;
+  if (reset_peak) g_mem_peak = g_mem_current;
   return ABCORE_OK;
 }
 
@@ -869,7 +948,7 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
                 [&] { return launch_scan_reset_gcc(*g, thrU, thrL, s); }));
       // an unchanged graph counts the first round on its degree-rank copy
       TRY(pull_peel_pack(*g, kGCC, thrU, thrL, true, d_bitmask, s, &launches, true, nullptr,
-                         false, false, g->version == 0));
+                         false, false, g->rank_order && g->version == 0));
     } else {
       CHK(launch_init_state(*g, s));
       CHK(timed(*g, ABCORE_KERNEL_SCAN, s, 1,
@@ -1003,6 +1082,8 @@ abcore_status abcore_compute_batch(abcore_graph h, const uint32_t *h_alpha,
   key.push_back(q);
   key.push_back(g->pull_mode);
   key.push_back(g->grid);
+  key.push_back(g->claim);
+  key.push_back(g->rank_order ? 1 : 0);
   key.push_back(g->delta.count > 0 ? 1 : 0);
   BatchCache &c = g->batch;
   if (!(c.exec && c.bits == d_bitmasks && c.version == g->version && c.key == key)) {
@@ -1179,7 +1260,7 @@ abcore_status abcore_autotune(abcore_graph h, uint32_t alpha, uint32_t beta, int
   hipStream_t s = as_stream(stream);
   const int64_t words = std::max<int64_t>(1, (g->n + 31) / 32);
   uint32_t *bits = nullptr;
-  CHK(hipMalloc(&bits, sizeof(uint32_t) * words));
+  CHK(dev_malloc(&bits, sizeof(uint32_t) * words));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
@@ -1232,7 +1313,7 @@ abcore_status abcore_autotune(abcore_graph h, uint32_t alpha, uint32_t beta, int
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  (void)hipFree(bits);
+  (void)dev_free(bits);
   return st;
 }
 

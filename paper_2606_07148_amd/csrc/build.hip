@@ -202,11 +202,11 @@ abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, i
   const int ubits = bits_for((uint64_t)std::max(g.nU, 1) * (uint64_t)std::max(g.nL, 1) - 1);
   const int lbits = ubits;
 
-  BCHK(hipMalloc(&g.off, sizeof(int64_t) * (g.n + 1)));
-  BCHK(hipMalloc(&g.deg0, sizeof(int32_t) * std::max<int64_t>(g.n, 1)));
+  BCHK(dev_malloc(&g.off, sizeof(int64_t) * (g.n + 1)));
+  BCHK(dev_malloc(&g.deg0, sizeof(int32_t) * std::max<int64_t>(g.n, 1)));
   BCHK(hipMemsetAsync(g.deg0, 0, sizeof(int32_t) * std::max<int64_t>(g.n, 1), s));
   if (m > 0) {
-    BCHK(hipMalloc(&d_bad, sizeof(int32_t)));
+    BCHK(dev_malloc(&d_bad, sizeof(int32_t)));
     BCHK(hipMemsetAsync(d_bad, 0, sizeof(int32_t), s));
     validate_kernel<<<grid, 256, 0, s>>>(eu, ev, m, g.nU, g.nL, d_bad);
     BCHK(hipGetLastError());
@@ -217,9 +217,9 @@ abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, i
       status = ABCORE_EINVAL;
       goto done;
     }
-    BCHK(hipMalloc(&k0, sizeof(uint64_t) * m));
-    BCHK(hipMalloc(&k1, sizeof(uint64_t) * m));
-    BCHK(hipMalloc(&d_nsel, sizeof(int)));
+    BCHK(dev_malloc(&k0, sizeof(uint64_t) * m));
+    BCHK(dev_malloc(&k1, sizeof(uint64_t) * m));
+    BCHK(dev_malloc(&d_nsel, sizeof(int)));
     make_keys_kernel<<<grid, 256, 0, s>>>(eu, ev, m, g.nL, k0);
     BCHK(hipGetLastError());
     // temp storage large enough for the sort and the unique selection
@@ -227,7 +227,7 @@ abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, i
     temp_bytes = std::max(temp_bytes, need);
     BCHK(hipcub::DeviceSelect::Unique(nullptr, need, k1, k0, d_nsel, (int)m, s));
     temp_bytes = std::max(temp_bytes, need);
-    BCHK(hipMalloc(&temp, std::max<size_t>(temp_bytes, 16)));
+    BCHK(dev_malloc(&temp, std::max<size_t>(temp_bytes, 16)));
     BCHK(hipcub::DeviceRadixSort::SortKeys(temp, temp_bytes, k0, k1, (int)m, 0, ubits, s));
     BCHK(hipcub::DeviceSelect::Unique(temp, temp_bytes, k1, k0, d_nsel, (int)m, s));
     BCHK(hipMemcpyAsync(&h_nsel, d_nsel, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -236,7 +236,7 @@ abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, i
   }
   g.m_csr = md;
   g.m = md;
-  BCHK(hipMalloc(&g.cols, sizeof(int32_t) * std::max<int64_t>(2 * md, 1)));
+  BCHK(dev_malloc(&g.cols, sizeof(int32_t) * std::max<int64_t>(2 * md, 1)));
   if (md > 0) {
     const int gridm = std::max(1, std::min(g.cu_count * 8, (int)((md + 255) / 256)));
     upper_rows_kernel<<<gridm, 256, 0, s>>>(k0, md, g.nU, g.nL, g.cols, g.deg0, k1);
@@ -245,7 +245,7 @@ abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, i
     lower_rows_kernel<<<gridm, 256, 0, s>>>(k0, md, g.nU, g.cols, g.deg0);
     BCHK(hipGetLastError());
   }
-  BCHK(hipMalloc(&deg64, sizeof(int64_t) * (g.n + 1)));
+  BCHK(dev_malloc(&deg64, sizeof(int64_t) * (g.n + 1)));
   {
     const int gridn = std::max(1, std::min(g.cu_count * 8, (int)((g.n + 256) / 256)));
     widen_kernel<<<gridn, 256, 0, s>>>(g.deg0, g.n, deg64);
@@ -253,21 +253,21 @@ abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, i
     need = 0;
     BCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, deg64, g.off, (int)(g.n + 1), s));
     if (need > temp_bytes) {
-      BCHK(hipFree(temp));
+      BCHK(dev_free(temp));
       temp = nullptr;
       temp_bytes = need;
-      BCHK(hipMalloc(&temp, temp_bytes));
+      BCHK(dev_malloc(&temp, temp_bytes));
     }
     BCHK(hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, deg64, g.off, (int)(g.n + 1), s));
   }
   BCHK(hipStreamSynchronize(s));
 done:
-  if (d_bad) (void)hipFree(d_bad);
-  if (k0) (void)hipFree(k0);
-  if (k1) (void)hipFree(k1);
-  if (d_nsel) (void)hipFree(d_nsel);
-  if (temp) (void)hipFree(temp);
-  if (deg64) (void)hipFree(deg64);
+  if (d_bad) (void)dev_free(d_bad);
+  if (k0) (void)dev_free(k0);
+  if (k1) (void)dev_free(k1);
+  if (d_nsel) (void)dev_free(d_nsel);
+  if (temp) (void)dev_free(temp);
+  if (deg64) (void)dev_free(deg64);
   return status;
 #undef BCHK
 }
@@ -289,14 +289,14 @@ abcore_status build_pieces(Graph &g, hipStream_t s) {
   size_t temp_bytes = 0;
   int64_t h_tot[4] = {0, 0, 0, 0};
   const int grid = std::max(1, std::min(g.cu_count * 8, (int)((g.n + 256) / 256)));
-  PCHK(hipMalloc(&np, sizeof(int64_t) * (g.n + 1)));
-  PCHK(hipMalloc(&hv, sizeof(int64_t) * (g.n + 1)));
-  PCHK(hipMalloc(&first, sizeof(int64_t) * (g.n + 1)));
-  PCHK(hipMalloc(&hfirst, sizeof(int64_t) * (g.n + 1)));
+  PCHK(dev_malloc(&np, sizeof(int64_t) * (g.n + 1)));
+  PCHK(dev_malloc(&hv, sizeof(int64_t) * (g.n + 1)));
+  PCHK(dev_malloc(&first, sizeof(int64_t) * (g.n + 1)));
+  PCHK(dev_malloc(&hfirst, sizeof(int64_t) * (g.n + 1)));
   count_pieces_kernel<<<grid, 256, 0, s>>>(g.off, g.n, np, hv);
   PCHK(hipGetLastError());
   PCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, temp_bytes, np, first, (int)(g.n + 1), s));
-  PCHK(hipMalloc(&temp, std::max<size_t>(temp_bytes, 16)));
+  PCHK(dev_malloc(&temp, std::max<size_t>(temp_bytes, 16)));
   PCHK(hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, np, first, (int)(g.n + 1), s));
   PCHK(hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, hv, hfirst, (int)(g.n + 1), s));
   PCHK(hipMemcpyAsync(&h_tot[0], first + g.n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -308,17 +308,17 @@ abcore_status build_pieces(Graph &g, hipStream_t s) {
   g.npieces_upper = h_tot[1];
   g.nheavy = h_tot[2];
   g.nheavy_upper = h_tot[3];
-  PCHK(hipMalloc(&g.piece_row, sizeof(int32_t) * std::max<int64_t>(g.npieces, 1)));
-  PCHK(hipMalloc(&g.piece_start, sizeof(int64_t) * std::max<int64_t>(g.npieces, 1)));
-  PCHK(hipMalloc(&g.piece_first, sizeof(int32_t) * std::max<int64_t>(g.n, 1)));
-  PCHK(hipMalloc(&g.heavy_rows, sizeof(int32_t) * std::max<int64_t>(g.nheavy, 1)));
-  PCHK(hipMalloc(&g.split_written, sizeof(int32_t) * std::max<int64_t>(g.npieces, 1)));
+  PCHK(dev_malloc(&g.piece_row, sizeof(int32_t) * std::max<int64_t>(g.npieces, 1)));
+  PCHK(dev_malloc(&g.piece_start, sizeof(int64_t) * std::max<int64_t>(g.npieces, 1)));
+  PCHK(dev_malloc(&g.piece_first, sizeof(int32_t) * std::max<int64_t>(g.n, 1)));
+  PCHK(dev_malloc(&g.heavy_rows, sizeof(int32_t) * std::max<int64_t>(g.nheavy, 1)));
+  PCHK(dev_malloc(&g.split_written, sizeof(int32_t) * std::max<int64_t>(g.npieces, 1)));
   fill_pieces_kernel<<<grid, 256, 0, s>>>(g.off, g.n, first, hfirst, g.piece_row, g.piece_start,
                                           g.piece_first, g.heavy_rows);
   PCHK(hipGetLastError());
   // pull round work split (np and hv are free again: weights and prefix)
   g.pull_bounds_grid = g.cu_count;
-  PCHK(hipMalloc(&g.pull_bounds, sizeof(int32_t) * 2 * (g.pull_bounds_grid + 1)));
+  PCHK(dev_malloc(&g.pull_bounds, sizeof(int32_t) * 2 * (g.pull_bounds_grid + 1)));
   row_weight_kernel<<<grid, 256, 0, s>>>(g.off, g.n, np);
   PCHK(hipGetLastError());
   PCHK(hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, np, hv, (int)(g.n + 1), s));
@@ -327,11 +327,11 @@ abcore_status build_pieces(Graph &g, hipStream_t s) {
   PCHK(hipGetLastError());
   PCHK(hipStreamSynchronize(s));
 done:
-  if (np) (void)hipFree(np);
-  if (hv) (void)hipFree(hv);
-  if (first) (void)hipFree(first);
-  if (hfirst) (void)hipFree(hfirst);
-  if (temp) (void)hipFree(temp);
+  if (np) (void)dev_free(np);
+  if (hv) (void)dev_free(hv);
+  if (first) (void)dev_free(first);
+  if (hfirst) (void)dev_free(hfirst);
+  if (temp) (void)dev_free(temp);
   return status;
 #undef PCHK
 }
@@ -428,15 +428,15 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
     return e != hipSuccess;
   };
   do {
-    if (fail(hipMalloc(&g.rank, sizeof(int32_t) * g.n))) break;
-    if (fail(hipMalloc(&g.rank_vtx, sizeof(int32_t) * g.n))) break;
-    if (fail(hipMalloc(&g.roff, sizeof(int64_t) * (g.n + 1)))) break;
-    if (fail(hipMalloc(&g.rcols, sizeof(int32_t) * std::max<int64_t>(ent, 1)))) break;
+    if (fail(dev_malloc(&g.rank, sizeof(int32_t) * g.n))) break;
+    if (fail(dev_malloc(&g.rank_vtx, sizeof(int32_t) * g.n))) break;
+    if (fail(dev_malloc(&g.roff, sizeof(int64_t) * (g.n + 1)))) break;
+    if (fail(dev_malloc(&g.rcols, sizeof(int32_t) * std::max<int64_t>(ent, 1)))) break;
     g.rdeg_mask = (uint32_t)((1ull << xbits) - 1);
-    if (fail(hipMalloc(&g.rdeg, sizeof(int32_t) * ((size_t)g.rdeg_mask + 1)))) break;
+    if (fail(dev_malloc(&g.rdeg, sizeof(int32_t) * ((size_t)g.rdeg_mask + 1)))) break;
     // k0 also holds the degrees by rank (n + 1 values after n + 1 slots)
-    if (fail(hipMalloc(&k0, sizeof(uint64_t) * std::max<int64_t>(items, 2 * (g.n + 1))))) break;
-    if (fail(hipMalloc(&k1, sizeof(uint64_t) * items))) break;
+    if (fail(dev_malloc(&k0, sizeof(uint64_t) * std::max<int64_t>(items, 2 * (g.n + 1))))) break;
+    if (fail(dev_malloc(&k1, sizeof(uint64_t) * items))) break;
     // temporary storage for the largest sort, and the offsets' scan
     if (fail(hipcub::DeviceRadixSort::SortKeys(nullptr, need, k0, k1, (int)items, 0, 64, s)))
       break;
@@ -446,7 +446,7 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
                                               g.roff, (int)(g.n + 1), s)))
       break;
     temp_bytes = std::max(temp_bytes, need);
-    if (fail(hipMalloc(&temp, temp_bytes))) break;
+    if (fail(dev_malloc(&temp, temp_bytes))) break;
     // ranks, one layer at a time
     for (int layer = 0; layer < 2 && ok; ++layer) {
       const int64_t lo = layer == 0 ? 0 : g.nU, hi = layer == 0 ? g.nU : g.n;
@@ -483,7 +483,7 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
     {
       int64_t *np = reinterpret_cast<int64_t *>(k0), *hv = np + (g.n + 1);
       int64_t *hfirst = nullptr;
-      if (fail(hipMalloc(&hfirst, sizeof(int64_t) * 2 * (g.n + 1)))) break;
+      if (fail(dev_malloc(&hfirst, sizeof(int64_t) * 2 * (g.n + 1)))) break;
       int32_t *hrows = nullptr;
       bool pok = false;
       do {
@@ -494,19 +494,19 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
         if (fail(hipcub::DeviceScan::ExclusiveSum(temp, tb, np, fcopy, (int)(g.n + 1), s))) break;
         tb = temp_bytes;
         if (fail(hipcub::DeviceScan::ExclusiveSum(temp, tb, hv, hfirst, (int)(g.n + 1), s))) break;
-        if (fail(hipMalloc(&g.rp_row, sizeof(int32_t) * std::max<int64_t>(g.npieces, 1)))) break;
-        if (fail(hipMalloc(&g.rp_start, sizeof(int64_t) * std::max<int64_t>(g.npieces, 1))))
+        if (fail(dev_malloc(&g.rp_row, sizeof(int32_t) * std::max<int64_t>(g.npieces, 1)))) break;
+        if (fail(dev_malloc(&g.rp_start, sizeof(int64_t) * std::max<int64_t>(g.npieces, 1))))
           break;
-        if (fail(hipMalloc(&g.rp_first, sizeof(int32_t) * g.n))) break;
-        if (fail(hipMalloc(&hrows, sizeof(int32_t) * std::max<int64_t>(g.nheavy, 1)))) break;
+        if (fail(dev_malloc(&g.rp_first, sizeof(int32_t) * g.n))) break;
+        if (fail(dev_malloc(&hrows, sizeof(int32_t) * std::max<int64_t>(g.nheavy, 1)))) break;
         fill_pieces_kernel<<<grid, 256, 0, s>>>(g.roff, g.n, fcopy, hfirst, g.rp_row, g.rp_start,
                                                 g.rp_first, hrows);
         if (fail(hipGetLastError())) break;
         pok = true;
       } while (0);
       if (fail(hipStreamSynchronize(s))) pok = false;
-      if (hrows) (void)hipFree(hrows);
-      (void)hipFree(hfirst);
+      if (hrows) (void)dev_free(hrows);
+      (void)dev_free(hfirst);
       if (!pok) {
         ok = false;
         break;
@@ -553,21 +553,21 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
     if (!ok) break;
     if (fail(hipStreamSynchronize(s))) break;
   } while (0);
-  if (k0) (void)hipFree(k0);
-  if (k1) (void)hipFree(k1);
-  if (temp) (void)hipFree(temp);
+  if (k0) (void)dev_free(k0);
+  if (k1) (void)dev_free(k1);
+  if (temp) (void)dev_free(temp);
   if (!ok) {
     (void)hipGetLastError();
-    if (g.rank) (void)hipFree(g.rank);
-    if (g.rank_vtx) (void)hipFree(g.rank_vtx);
-    if (g.roff) (void)hipFree(g.roff);
-    if (g.rcols) (void)hipFree(g.rcols);
-    if (g.rdeg) (void)hipFree(g.rdeg);
+    if (g.rank) (void)dev_free(g.rank);
+    if (g.rank_vtx) (void)dev_free(g.rank_vtx);
+    if (g.roff) (void)dev_free(g.roff);
+    if (g.rcols) (void)dev_free(g.rcols);
+    if (g.rdeg) (void)dev_free(g.rdeg);
     g.rdeg = nullptr;
     g.rdeg_mask = 0;
-    if (g.rp_row) (void)hipFree(g.rp_row);
-    if (g.rp_start) (void)hipFree(g.rp_start);
-    if (g.rp_first) (void)hipFree(g.rp_first);
+    if (g.rp_row) (void)dev_free(g.rp_row);
+    if (g.rp_start) (void)dev_free(g.rp_start);
+    if (g.rp_first) (void)dev_free(g.rp_first);
     g.rank = nullptr;
     g.rank_vtx = nullptr;
     g.roff = nullptr;

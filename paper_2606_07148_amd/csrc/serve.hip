@@ -98,7 +98,7 @@ void free_slot(Slot &s) {
   if (s.stream) (void)hipStreamDestroy(s.stream);
   for (void *p : {(void *)s.deg, (void *)s.queue, (void *)s.state, (void *)s.part,
                   (void *)s.d_corr, (void *)s.bits})
-    if (p) (void)hipFree(p);
+    if (p) (void)dev_free(p);
   if (s.h_corr) (void)hipHostFree(s.h_corr);
   if (s.h_out) (void)hipHostFree(s.h_out);
   if (s.scanned) (void)hipEventDestroy(s.scanned);
@@ -111,9 +111,9 @@ void free_server_device(Server &S) {
   S.slots.clear();
   if (S.main) (void)hipStreamDestroy(S.main);
   if (S.applied) (void)hipEventDestroy(S.applied);
-  if (S.d_upd) (void)hipFree(S.d_upd);
+  if (S.d_upd) (void)dev_free(S.d_upd);
   if (S.h_upd) (void)hipHostFree(S.h_upd);
-  if (S.d_rec) (void)hipFree(S.d_rec);
+  if (S.d_rec) (void)dev_free(S.d_rec);
   if (S.h_rec) (void)hipHostFree(S.h_rec);
   S.main = nullptr;
   S.applied = nullptr;
@@ -124,15 +124,15 @@ void free_server_device(Server &S) {
 
 hipError_t alloc_slot(Graph &g, Slot &s) {
   hipError_t e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipMalloc(&s.deg, sizeof(int32_t) * std::max<int64_t>(g.n, 1));
-  if (e == hipSuccess) e = hipMalloc(&s.queue, sizeof(int32_t) * kSub * g.qcap);
+  if (e == hipSuccess) e = dev_malloc(&s.deg, sizeof(int32_t) * std::max<int64_t>(g.n, 1));
+  if (e == hipSuccess) e = dev_malloc(&s.queue, sizeof(int32_t) * kSub * g.qcap);
   if (e == hipSuccess) e = hipMemset(s.queue, 0xFF, sizeof(int32_t) * kSub * g.qcap);
-  if (e == hipSuccess) e = hipMalloc(&s.state, sizeof(PeelState));
+  if (e == hipSuccess) e = dev_malloc(&s.state, sizeof(PeelState));
   if (e == hipSuccess) e = hipMemset(s.state, 0, sizeof(PeelState));
-  if (e == hipSuccess) e = hipMalloc(&s.part, sizeof(int64_t) * kMaxBlocks * kPartFields);
-  if (e == hipSuccess) e = hipMalloc(&s.d_corr, sizeof(int32_t) * 2 * kCorrMax);
+  if (e == hipSuccess) e = dev_malloc(&s.part, sizeof(int64_t) * kMaxBlocks * kPartFields);
+  if (e == hipSuccess) e = dev_malloc(&s.d_corr, sizeof(int32_t) * 2 * kCorrMax);
   if (e == hipSuccess)
-    e = hipMalloc(&s.bits, sizeof(uint32_t) * std::max<int64_t>((g.n + 31) / 32, 1));
+    e = dev_malloc(&s.bits, sizeof(uint32_t) * std::max<int64_t>((g.n + 31) / 32, 1));
   if (e == hipSuccess) e = hipHostMalloc(&s.h_corr, sizeof(int32_t) * 2 * kCorrMax);
   if (e == hipSuccess) e = hipHostMalloc(&s.h_out, sizeof(int32_t) * 4);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&s.scanned, hipEventDisableTiming);
@@ -435,14 +435,14 @@ abcore_status serve_start(Graph &g, int64_t max_inflight, int32_t slots, int32_t
   S.slots.assign(slots, Slot());
   hipError_t e = hipStreamCreateWithFlags(&S.main, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&S.applied, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipMalloc(&S.d_upd, sizeof(int32_t) * 3 * kWindowMax);
+  if (e == hipSuccess) e = dev_malloc(&S.d_upd, sizeof(int32_t) * 3 * kWindowMax);
   if (e == hipSuccess) e = hipHostMalloc(&S.h_upd, sizeof(int32_t) * 3 * kWindowMax);
-  if (e == hipSuccess) e = hipMalloc(&S.d_rec, sizeof(WindowRecord) * kWindowMax);
+  if (e == hipSuccess) e = dev_malloc(&S.d_rec, sizeof(WindowRecord) * kWindowMax);
   if (e == hipSuccess) e = hipHostMalloc(&S.h_rec, sizeof(WindowRecord) * kWindowMax);
   for (Slot &s : S.slots)
     if (e == hipSuccess) e = alloc_slot(g, s);
   if (e == hipSuccess && g.del_ver == nullptr) {
-    e = hipMalloc(&g.del_ver, sizeof(int32_t) * std::max<int64_t>(2 * g.m_csr, 1));
+    e = dev_malloc(&g.del_ver, sizeof(int32_t) * std::max<int64_t>(2 * g.m_csr, 1));
     if (e == hipSuccess) e = hipMemset(g.del_ver, 0, sizeof(int32_t) * std::max<int64_t>(2 * g.m_csr, 1));
   }
   if (e == hipSuccess) e = hipDeviceSynchronize();

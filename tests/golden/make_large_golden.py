@@ -4,6 +4,7 @@ and ``oracle`` (the sequential CPU oracle); nothing here touches the device
 library.  Run on a CPU host with about 48 GB of memory:
 
     python tests/golden/make_large_golden.py c3   # -> c3_oracle.json
+    python tests/golden/make_large_golden.py c4   # -> c4_oracle.json
     python tests/golden/make_large_golden.py c5   # -> c5_oracle.json
 
 c3: Chung-Lu |U| = 5e7, |L| = 2e7, m = 1e9, degree exponents 2.0 / 2.3,
@@ -11,6 +12,9 @@ c3: Chung-Lu |U| = 5e7, |L| = 2e7, m = 1e9, degree exponents 2.0 / 2.3,
     unified ids of Sec. IV-A), the core numbers (Definition 2) and, for the
     GCC+ sweep alpha = beta in {1, 2, ..., 256} and three asymmetric pairs,
     the (alpha,beta)-core's bitmask (Definition 1) with the peel's counts.
+c4: Chung-Lu |U| = 1e7, |L| = 5e6, m = 2e8, exponent 2.1, cap 50,000 (seed 4)
+    and its 256 queries, log-uniform in [1,256]^2 (seed 1004): each query's
+    bitmask digest and peel counts.
 c5: Chung-Lu |U| = 2e7, |L| = 1e7, m = 5e8, exponent 2.1, cap 50,000
     (seed 5) and its update stream (seed 1005).  Answers of sampled updates
     of a prefix (Problem 2 of Sec. III, by recomputation on the updated
@@ -36,43 +40,16 @@ sys.path.insert(0, ROOT)
 
 import bigraph_gen  # noqa: E402
 import oracle  # noqa: E402
+from tests.digests import sha_array, sha_edges  # noqa: E402
 
 C3_SWEEP = [1, 2, 4, 8, 16, 32, 64, 128, 256]
 C3_ASYM = [(3, 17), (40, 6), (100, 2)]
 C5_PREFIX = 2000
 C5_SAMPLES = [0, 1, 2, 3, 7, 50, 199, 400, 777, 1000, 1333, 1666, 1999]
-CHUNK = 1 << 26
 
 
 def log(*a):
     print(f"[{time.strftime('%H:%M:%S')}]", *a, flush=True)
-
-
-def sha_array(a: np.ndarray, dtype: str) -> str:
-    h = hashlib.sha256()
-    a = np.asarray(a)
-    for s in range(0, len(a), CHUNK):
-        h.update(np.ascontiguousarray(a[s:s + CHUNK], dtype).tobytes())
-    return h.hexdigest()
-
-
-def sha_edges(eu: np.ndarray, ev: np.ndarray) -> str:
-    """SHA-256 of the (u, v)-sorted interleaved int32 pairs (the generator
-    returns them sorted; checked here chunk by chunk)."""
-    h = hashlib.sha256()
-    prev = None
-    for s in range(0, len(eu), CHUNK):
-        u = eu[s:s + CHUNK].astype(np.int64)
-        v = ev[s:s + CHUNK].astype(np.int64)
-        k = u * (1 << 32) + v
-        if len(k) > 1 and not bool(np.all(k[1:] > k[:-1])):
-            raise ValueError("edge list not strictly sorted")
-        if prev is not None and len(k) and not k[0] > prev:
-            raise ValueError("edge list not strictly sorted across chunks")
-        if len(k):
-            prev = int(k[-1])
-        h.update(np.stack([eu[s:s + CHUNK], ev[s:s + CHUNK]], axis=1).astype("<i4").tobytes())
-    return h.hexdigest()
 
 
 def query_record(g, a, b):
@@ -125,6 +102,32 @@ def c3():
     log("wrote", path)
 
 
+def c4():
+    spec = bigraph_gen.CONFIGS[4]
+    nU, nL = spec["n_upper"], spec["n_lower"]
+    t0 = time.time()
+    eu, ev = bigraph_gen.make_graph(spec)
+    log(f"c4: generated {len(eu)} edges in {time.time() - t0:.0f}s")
+    a, b = bigraph_gen.loguniform_pairs(256, 1, 256, spec["seed"] + 1000)
+    out = dict(config=4, spec={k: spec[k] for k in spec}, n_upper=nU, n_lower=nL,
+               query_seed=spec["seed"] + 1000)
+    out["edge_sha256"] = sha_edges(eu, ev)
+    g = oracle.Graph(nU, nL, eu, ev)
+    del eu, ev
+    out["m"] = g.m
+    out["off_sha256"] = sha_array(g.off, "<i8")
+    out["cols_sha256"] = sha_array(g.cols, "<i4")
+    out["queries"] = []
+    for i, (x, y) in enumerate(zip(a.tolist(), b.tolist())):
+        out["queries"].append(query_record(g, int(x), int(y)))
+        if i % 32 == 31:
+            log(f"c4: {i + 1} queries")
+    path = os.path.join(HERE, "c4_oracle.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    log("wrote", path)
+
+
 def c5():
     spec = bigraph_gen.CONFIGS[5]
     nU, nL = spec["n_upper"], spec["n_lower"]
@@ -160,6 +163,6 @@ def c5():
 
 
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["c3", "c5"]
+    which = sys.argv[1:] or ["c3", "c4", "c5"]
     for w in which:
-        {"c3": c3, "c5": c5}[w]()
+        {"c3": c3, "c4": c4, "c5": c5}[w]()

@@ -6,7 +6,7 @@ import pytest
 
 import bigraph_gen
 import oracle
-from tests.gpu_util import ensure_built, say, to_dev
+from tests.gpu_util import ensure_built, say, serve_all, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -34,34 +34,6 @@ def _with_invalid(ups, every=23):
             for k in out:
                 out[k].append(int(ups[k][i]))  # the same update again: rejected
     return {k: np.array(v, np.int32) for k, v in out.items()}
-
-
-def serve_all(g, ups, max_inflight):
-    """Submits the stream in order, polling while admission is full; returns
-    the results in ticket order."""
-    n = len(ups["u"])
-    tickets, results = [], {}
-    waiting = []
-    i = 0
-    while i < n or waiting:
-        if i < n:
-            t = pkg.abcore_try_submit(g, ups["u"][i], ups["v"][i], ups["op"][i],
-                                      ups["alpha"][i], ups["beta"][i])
-            if t is not None:
-                tickets.append(t)
-                waiting.append(t)
-                i += 1
-                continue
-        still = []
-        for t in waiting:
-            r = pkg.abcore_poll(g, t)
-            if r is None:
-                still.append(t)
-            else:
-                results[t] = r
-        waiting = still
-    assert tickets == list(range(tickets[0], tickets[0] + n))
-    return [results[t] for t in tickets]
 
 
 def _sequential(nU, nL, eu, ev, ups):

@@ -392,3 +392,75 @@ def test_component_decomposition():
             mem = oracle.compute(sub, a, b)
             union |= mem & (comp == c)
         assert (union == whole).all()
+
+
+def _certify(g, mem, order, a, b):
+    """Definition 1 certificate, computed here from the CSR alone: the
+    survivors form an (a,b)-subgraph (feasibility), and the removed vertices,
+    taken in the peel's order, each had fewer than its threshold of
+    neighbours not removed before it -- so by induction along the order no
+    removed vertex belongs to any (a,b)-subgraph, and the survivors are the
+    maximal one."""
+    n, nU = g.n, g.n_upper
+    thr = np.where(np.arange(n) < nU, a, b)
+    deg = g.degrees()
+    rows = np.repeat(np.arange(n, dtype=np.int64), deg)
+    cols = g.cols.astype(np.int64)
+    assert len(order) == int((~mem).sum())
+    assert len(np.unique(order)) == len(order)
+    assert not mem[order].any()
+    pos = np.full(n, np.iinfo(np.int64).max, np.int64)
+    pos[order] = np.arange(len(order))
+    later = pos[cols] > pos[rows]
+    left = np.bincount(rows[later], minlength=n)
+    removed = ~mem
+    assert (left[removed] < thr[removed]).all(), "a removed vertex kept its threshold"
+    inside = np.bincount(rows[mem[cols] & mem[rows]], minlength=n)
+    assert (inside[mem] >= thr[mem]).all(), "a survivor lacks its threshold"
+
+
+@pytest.mark.parametrize("which", ["uniform", "chung_lu_2", "chung_lu_3"])
+def test_removal_order_certificate(which):
+    """Maximality pinned in O(m): the oracle's removal order certifies its
+    result on medium graphs of each workload shape, over a grid of queries
+    including asymmetric ones and an empty core."""
+    if which == "uniform":
+        spec = bigraph_gen.CONFIGS[1]
+    elif which == "chung_lu_2":
+        spec = bigraph_gen.scaled(2, 0.01)
+    else:
+        spec = bigraph_gen.scaled(3, 1 / 2000)
+    eu, ev = bigraph_gen.make_graph(spec)
+    g = oracle.Graph(spec["n_upper"], spec["n_lower"], eu, ev)
+    for a, b in [(1, 1), (3, 2), (2, 7), (10, 10), (40, 6), (100, 2), (10 ** 6, 1)]:
+        mem, st, order = oracle.peel_order(g, a, b)
+        assert np.array_equal(mem, oracle.compute(g, a, b))
+        _certify(g, mem, order, a, b)
+
+
+def test_certificate_rejects_planted_mistakes():
+    """The certificate catches a wrong result: a dropped removal (a vertex
+    kept that lacks support), an extra removal (a vertex removed that kept
+    its threshold), and a swapped order."""
+    spec = bigraph_gen.scaled(2, 0.01)
+    eu, ev = bigraph_gen.make_graph(spec)
+    g = oracle.Graph(spec["n_upper"], spec["n_lower"], eu, ev)
+    a, b = 10, 10
+    mem, st, order = oracle.peel_order(g, a, b)
+    assert st["rounds"] >= 3  # the last removals had their threshold at the start
+    _certify(g, mem, order, a, b)
+    # the last removal undone: that vertex is kept without its support
+    bad = mem.copy()
+    bad[order[-1]] = True
+    with pytest.raises(AssertionError):
+        _certify(g, bad, order[:-1], a, b)
+    # a survivor with neighbours inside removed first: it kept its threshold
+    x = int(np.flatnonzero(mem)[0])
+    bad = mem.copy()
+    bad[x] = False
+    with pytest.raises(AssertionError):
+        _certify(g, bad, np.concatenate([[x], order]), a, b)
+    # the first and last removals exchanged: a late vertex removed too early
+    rev = order[::-1].copy()
+    with pytest.raises(AssertionError):
+        _certify(g, mem, rev, a, b)
