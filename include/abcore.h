@@ -139,6 +139,27 @@ abcore_status abcore_export_csr(abcore_graph g, int64_t *d_off, int32_t *d_cols,
 abcore_status abcore_compute(abcore_graph g, uint32_t alpha, uint32_t beta, int32_t algo,
                              uint32_t *d_bitmask, abcore_stats *stats, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the GCC
+ * computation of abcore_compute(g, alpha, beta, ABCORE_GCC, d_bitmask, NULL,
+ * stream), bit for bit, with no allocation and no free of any kind.  Its
+ * per-query working set (working degrees, frontier sub-queues, peel state,
+ * partial sums, survivor bitmap) lives in a static device array of 64 MiB
+ * that the library holds on every device it runs on until the process ends;
+ * the handle's graph arrays are read only.  It fits graphs whose working set,
+ * 64 * (2n + pieces + 256) + 4.125 n bytes plus about 330 KB (pieces: one per
+ * 64 adjacency entries of each row longer than 64), is at most 64 MiB --
+ * about 440,000 vertices at the degree skew of a power-law graph; larger
+ * graphs return ABCORE_EINVAL and change nothing.  Every call on a device
+ * shares that device's array and starts by filling it afresh (queue slots
+ * empty, state zero), with kernels only (no memset node), on `stream`:
+ * calls that overlap on one device, on any handles or streams, race, and
+ * the caller must serialise them.  Asynchronous on `stream`.  Errors: EINVAL
+ * (null handle or bitmask, alpha or beta 0, graph too large), EBUSY
+ * (serving), EDEVICE. */
+abcore_status abcore_compute_static(abcore_graph g, uint32_t alpha, uint32_t beta,
+                                    uint32_t *d_bitmask, void *stream);
+
 /* Batch of q queries (thresholds h_alpha[i], h_beta[i], HOST arrays of q
  * values >= 1) computed in one call.  Result i is written to d_bitmasks +
  * i * ceil(n/32) (DEVICE, q * ceil(n/32) words, every word written) and equals

@@ -84,6 +84,7 @@ def load():
         "abcore_graph_info": (i32, [vp, P(i32), P(i32), P(i64)]),
         "abcore_export_csr": (i32, [vp, vp, vp, P(i64), vp]),
         "abcore_compute": (i32, [vp, u32, u32, i32, vp, P(abcore_stats), vp]),
+        "abcore_compute_static": (i32, [vp, u32, u32, vp, vp]),
         "abcore_core_numbers": (i32, [vp, vp, P(i32), vp]),
         "abcore_components": (i32, [vp, vp, vp]),
         "abcore_query": (i32, [vp, abcore_edge_update, u32, u32, P(i32), P(u32), vp]),
@@ -247,6 +248,15 @@ def abcore_compute(g: Graph, alpha: int, beta: int, algo: int = ABCORE_GCC, out=
                                  ctypes.byref(st) if st is not None else None,
                                  _stream(stream)))
     return (out, st.as_dict()) if stats else out
+
+
+def abcore_compute_static(g: Graph, alpha: int, beta: int, out, stream=None):
+    """The GCC bitmask of abcore_compute, computed with no allocation (the
+    working set lives in the library's static device array); ``out`` is a
+    caller-allocated int32 CUDA tensor of ceil(n/32) words."""
+    _check(load().abcore_compute_static(g.handle, int(alpha), int(beta), _ptr(out),
+                                        _stream(stream)))
+    return out
 
 
 def _u32_array(values):

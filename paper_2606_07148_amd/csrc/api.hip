@@ -584,6 +584,75 @@ BatchPlan make_batch_plan(const int32_t *tu, const int32_t *tl, int32_t q) {
   return plan;
 }
 
+// --------------------------------------------- allocation-free variant --
+// abcore_compute_static runs GCC's vertex-order path with its per-query
+// working set -- working degrees, frontier sub-queues, peel state, partial
+// sums, survivor bitmap -- in this file-scope device array instead of the
+// handle's buffers, so the call allocates nothing.  Each device that loads
+// the library holds its own copy for the life of the process.  In host code
+// the name `scratch` only stands in for the symbol: its device address comes
+// from hipGetSymbolAddress, once per device (scratch_base).
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static uint8_t *g_scratch_ptr[kMaxDevices] = {};
+
+// This device's copy of `scratch` (the device must be current).
+abcore_status scratch_base(int device, uint8_t **out) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("static scratch: device %d out of range", device);
+    return ABCORE_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device] == nullptr) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      set_error("static scratch: hipGetSymbolAddress failed: %s", hipGetErrorString(e));
+      return ABCORE_EDEVICE;
+    }
+    g_scratch_ptr[device] = static_cast<uint8_t *>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return ABCORE_OK;
+}
+
+// Byte offsets of the working set in the scratch array (256-byte aligned).
+struct StaticLayout {
+  size_t queue, deg, bits, state, part, total;
+};
+
+StaticLayout static_layout(const Graph &g) {
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  StaticLayout L;
+  size_t at = 0;
+  L.queue = at;
+  at += up(sizeof(int32_t) * (size_t)kSub * (size_t)g.qcap);
+  L.deg = at;
+  at += up(sizeof(int32_t) * (size_t)std::max<int64_t>(g.n, 1));
+  L.bits = at;
+  at += up(sizeof(uint32_t) * (size_t)((g.n + 31) / 32 + 1));
+  L.state = at;
+  at += up(sizeof(PeelState));
+  L.part = at;
+  at += up(sizeof(int64_t) * (size_t)kMaxBlocks * kPartFields);
+  L.total = at;
+  return L;
+}
+
+// The working set as a fresh one: every queue slot empty, the survivor
+// bitmap, the state (cursors, flags, arrival counters) and the partial sums
+// zero.  A plain fill kernel, so that a caller may capture the call.
+__global__ void static_fill_kernel(uint32_t *queue, int64_t nqueue, uint32_t *zero,
+                                   int64_t nzero) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = tid; i < nqueue; i += stride) queue[i] = 0xFFFFFFFFu;  // kEmpty
+  for (int64_t i = tid; i < nzero; i += stride) zero[i] = 0u;
+}
+
 }  // namespace abc
 
 using namespace abc;
@@ -632,6 +701,12 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
     g->nU = n_upper;
     g->nL = n_lower;
     g->n = (int64_t)n_upper + n_lower;
+    {
+      // set-up of the allocation-free variant on this device (a failure is
+      // reported again by abcore_compute_static, which retries)
+      uint8_t *unused = nullptr;
+      if (scratch_base(g->device, &unused) != ABCORE_OK) set_error("");
+    }
     // each phase ends synchronised, so its wall time is its own
     auto now = [] { return std::chrono::steady_clock::now(); };
     auto ms_since = [&](std::chrono::steady_clock::time_point t) {
@@ -1015,6 +1090,75 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
     stats->launches = launches;
     stats->pulled = p.pulled;
     stats->rank_order = rank_order ? 1 : 0;
+  }
+  return ABCORE_OK;
+}
+
+abcore_status abcore_compute_static(abcore_graph h, uint32_t alpha, uint32_t beta,
+                                    uint32_t *d_bitmask, void *stream) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (g && serving(*g)) return busy_error(__func__);
+  if (!g || (!d_bitmask && g->n > 0)) {
+    set_error("abcore_compute_static: null handle or bitmask");
+    return ABCORE_EINVAL;
+  }
+  if (alpha < 1 || beta < 1) {
+    set_error("abcore_compute_static: alpha and beta must be >= 1");
+    return ABCORE_EINVAL;
+  }
+  CHK(hipSetDevice(g->device));
+  TRY(check_abort(*g));
+  if (g->n == 0) return ABCORE_OK;
+  const StaticLayout L = static_layout(*g);
+  if (L.total > kStaticScratchBytes) {
+    set_error("abcore_compute_static: the working set needs %zu bytes, the static scratch "
+              "holds %zu",
+              L.total, kStaticScratchBytes);
+    return ABCORE_EINVAL;
+  }
+  uint8_t *base = nullptr;
+  TRY(scratch_base(g->device, &base));
+  hipStream_t s = as_stream(stream);
+  // the handle's working-set pointers point into the scratch for this call
+  struct Swap {
+    Graph &g;
+    int32_t *deg, *queue;
+    uint32_t *bits;
+    PeelState *state;
+    int64_t *part;
+    int peel_mode;
+    bool timing;
+    ~Swap() {
+      g.deg = deg;
+      g.queue = queue;
+      g.alive_bits = bits;
+      g.state = state;
+      g.part = part;
+      g.peel_mode = peel_mode;
+      g.timing = timing;
+    }
+  } restore{*g, g->deg, g->queue, g->alive_bits, g->state, g->part, g->peel_mode, g->timing};
+  g->queue = reinterpret_cast<int32_t *>(base + L.queue);
+  g->deg = reinterpret_cast<int32_t *>(base + L.deg);
+  g->alive_bits = reinterpret_cast<uint32_t *>(base + L.bits);
+  g->state = reinterpret_cast<PeelState *>(base + L.state);
+  g->part = reinterpret_cast<int64_t *>(base + L.part);
+  g->peel_mode = 3;     // the asynchronous worklist (no host reads)
+  g->timing = false;    // event pairs would be created on demand
+  const int64_t nqueue = (int64_t)kSub * g->qcap;
+  const int64_t nzero = (int64_t)((L.total - L.bits) / sizeof(uint32_t));
+  static_fill_kernel<<<std::min(g->cu_count * 8, kMaxBlocks), 256, 0, s>>>(
+      reinterpret_cast<uint32_t *>(base + L.queue), nqueue,
+      reinterpret_cast<uint32_t *>(base + L.bits), nzero);
+  CHK(hipGetLastError());
+  const int32_t thrU = clamp_thr(alpha), thrL = clamp_thr(beta);
+  int64_t launches = 0;
+  if (g->pull_mode != 1) {
+    CHK(launch_scan_reset_gcc(*g, thrU, thrL, s));
+    TRY(pull_peel_pack(*g, kGCC, thrU, thrL, true, d_bitmask, s, &launches, true));
+  } else {
+    CHK(launch_scan_gcc(*g, thrU, thrL, false, s));
+    TRY(pull_peel_pack(*g, kGCC, thrU, thrL, false, d_bitmask, s, &launches));
   }
   return ABCORE_OK;
 }
