@@ -215,6 +215,53 @@ abcore_status abcore_query(abcore_graph g, abcore_edge_update upd, uint32_t alph
                            uint32_t beta, int32_t *h_answer, uint32_t *h_endpoint_bits,
                            void *stream);
 
+/* Query parameters of Sec. VI-B.  *out_delta (nullable): delta of Table I,
+ * the largest value with a non-empty (delta,delta)-core (the largest core
+ * number, Definition 2; core numbers are computed and cached if needed).
+ * h_offset[i] (HOST, q entries): alpha_offset(h_alpha[i]), the largest beta
+ * with a non-empty (h_alpha[i], beta)-core, 0 when even the (h_alpha[i],
+ * 1)-core is empty.  The cores are nested in beta, so a binary search of
+ * GCC+ queries finds it exactly (non-empty at beta = delta when alpha <=
+ * delta, empty above the largest lower degree).  h_alpha: HOST, q values >= 1.
+ * Errors: EINVAL, EBUSY, ENOMEM, EDEVICE.  Synchronous. */
+abcore_status abcore_alpha_offsets(abcore_graph g, const uint32_t *h_alpha, int32_t q,
+                                   uint32_t *h_offset, int32_t *out_delta, void *stream);
+
+/* The default query of Sec. VI-B: alpha = 0.4 delta and beta = 0.6
+ * alpha_offset(alpha), each rounded down and at least 1.  Synchronous. */
+abcore_status abcore_default_query(abcore_graph g, uint32_t *alpha, uint32_t *beta,
+                                   void *stream);
+
+/* Remark of Sec. V: GFQ returning the vertex set instead of one bit.  Does
+ * what abcore_query does (the update, the component maintenance, the peel
+ * scoped to the component(s) of u and v, the answer in *h_answer and
+ * *h_endpoint_bits) and writes to d_bitmask (DEVICE, ceil(n/32) words, every
+ * word written) the vertices that peel leaves: the (alpha,beta)-core members
+ * in the component(s) of u and v in the updated graph; with connected != 0
+ * only the members connected to u or v through members (the connected part
+ * of the core that holds them; empty when neither is a member).
+ * out_count (nullable, HOST): the set's size.  Errors as abcore_query, and
+ * EINVAL for a null bitmask.  Synchronous. */
+abcore_status abcore_query_set(abcore_graph g, abcore_edge_update upd, uint32_t alpha,
+                               uint32_t beta, int32_t connected, int32_t *h_answer,
+                               uint32_t *h_endpoint_bits, uint32_t *d_bitmask,
+                               int64_t *out_count, void *stream);
+
+/* Remark of Sec. V: localized community search in the static setting.
+ * Algorithm 1 runs on the connected component of vertex q (a unified id)
+ * only, as GFQ scopes its peel; d_bitmask (DEVICE, ceil(n/32) words, every
+ * word written) receives the (alpha,beta)-core members of that component,
+ * or with connected != 0 only the members connected to q through members:
+ * the connected part of the (alpha,beta)-core containing q, empty when q is
+ * not in the core.  For a query edge (u, v), take q = u: if the edge is in
+ * the core, v is in the same connected part (the core is an induced
+ * subgraph).  The graph is not changed.  out_count (nullable, HOST): the
+ * set's size.  Errors: EINVAL (null pointer, q out of range, alpha or beta
+ * 0), EBUSY (serving), ENOMEM, EDEVICE.  Synchronous. */
+abcore_status abcore_community(abcore_graph g, int32_t q, uint32_t alpha, uint32_t beta,
+                               int32_t connected, uint32_t *d_bitmask, int64_t *out_count,
+                               void *stream);
+
 /* ---- Serving: a stream of on-the-fly queries (Problem 2, Sec. V) -------
  * Requests are the calls abcore_query would get, in submission order; each
  * result equals what abcore_query returns when the requests are applied one

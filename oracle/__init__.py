@@ -13,6 +13,14 @@ compositions the paper defines in terms of those routines:
 * ``gfq_stream``   -- Problem 2 (Sec. III) / GFQ (Sec. V): after each edge
   update, membership of the updated edge's endpoints in the core of the
   updated graph, by full recomputation on that graph.
+* ``community``    -- localized community search (Remark of Sec. V): the
+  core around a query vertex.
+* ``gfq_set_stream`` -- GFQ returning the core's vertex set around the updated
+  edge (Remark of Sec. V), by recomputation.
+* ``alpha_offset``, ``delta``, ``default_query`` -- the query parameters of
+  Sec. VI-B (largest beta with a non-empty (alpha,beta)-core, largest
+  non-empty symmetric core, and the default alpha = 0.4 delta, beta = 0.6
+  alpha_offset).
 * ``peel_order``   -- ``compute`` plus the sequential removal order (the
   certificate of maximality).
 * ``gfq_stream_sampled`` -- ``gfq_stream`` at sampled indices of a stream on
@@ -211,6 +219,100 @@ def gfq_stream(n_upper: int, n_lower: int, eu, ev, updates, check_only=None):
         member = compute(g, int(updates["alpha"][i]), int(updates["beta"][i]))
         bu, bv = bool(member[u]), bool(member[n_upper + v])
         out.append(("OK", bu and bv, int(bu) | (int(bv) << 1)))
+    return out
+
+
+def _connected_from(g: Graph, member: np.ndarray, seeds) -> np.ndarray:
+    """Vertices reachable from the member seeds through member vertices
+    only (breadth-first search over the induced subgraph of the members)."""
+    out = np.zeros(g.n, bool)
+    queue = [int(s) for s in seeds if member[int(s)] and not out[int(s)]]
+    for s in queue:
+        out[s] = True
+    head = 0
+    while head < len(queue):
+        x = queue[head]
+        head += 1
+        for w in g.cols[g.off[x]:g.off[x + 1]]:
+            w = int(w)
+            if member[w] and not out[w]:
+                out[w] = True
+                queue.append(w)
+    return out
+
+
+def community(g: Graph, q: int, alpha: int, beta: int, connected: bool) -> np.ndarray:
+    """Localized community search (Remark of Sec. V): the (alpha,beta)-core
+    members in the connected component of G holding vertex q -- what peeling
+    only that component leaves, since peeling never crosses components -- or,
+    with ``connected``, the members connected to q through members (the
+    connected part of the core containing q; empty when q is not a member)."""
+    member = compute(g, alpha, beta)
+    if connected:
+        return _connected_from(g, member, [q])
+    comp = components(g)
+    return member & (comp == comp[int(q)])
+
+
+def alpha_offset(g: Graph, alpha: int) -> int:
+    """The largest beta >= 1 with a non-empty (alpha,beta)-core (alpha_offset
+    of the default query rule in Sec. VI-B), 0 when even the (alpha,1)-core is
+    empty: a plain sweep beta = 1, 2, ... of full peels."""
+    beta = 0
+    while compute(g, alpha, beta + 1).any():
+        beta += 1
+    return beta
+
+
+def delta(g: Graph) -> int:
+    """The largest delta with a non-empty (delta,delta)-core (the delta of
+    Table I): a plain sweep of symmetric peels."""
+    d = 0
+    while compute(g, d + 1, d + 1).any():
+        d += 1
+    return d
+
+
+def default_query(g: Graph):
+    """The default (alpha,beta) of Sec. VI-B: alpha = 0.4 delta and beta =
+    0.6 alpha_offset(alpha), each rounded down and at least 1."""
+    a = max(1, (4 * delta(g)) // 10)
+    return a, max(1, (6 * alpha_offset(g, a)) // 10)
+
+
+def gfq_set_stream(n_upper: int, n_lower: int, eu, ev, updates, connected: bool):
+    """GFQ returning the vertex set (Remark of Sec. V), by recomputation:
+    after each cumulative update (u, v, op), the core members in the
+    component(s) of u and nU + v in the updated graph, or with ``connected``
+    the members connected to u or nU + v through members.  Rejected updates
+    (present insertion, absent deletion) give (status, None).  Returns
+    [(status, member bool array or None)]."""
+    nL = int(n_lower)
+    present = set((int(a) * nL + int(b)) for a, b in zip(np.asarray(eu), np.asarray(ev)))
+    out = []
+    for i in range(len(updates["u"])):
+        u, v, op = int(updates["u"][i]), int(updates["v"][i]), int(updates["op"][i])
+        key = u * nL + v
+        if op > 0:
+            if key in present:
+                out.append(("EEXIST", None))
+                continue
+            present.add(key)
+        else:
+            if key not in present:
+                out.append(("ENOENT", None))
+                continue
+            present.discard(key)
+        keys = np.fromiter(present, np.int64, len(present))
+        g = Graph(n_upper, n_lower, (keys // nL).astype(np.int32), (keys % nL).astype(np.int32))
+        member = compute(g, int(updates["alpha"][i]), int(updates["beta"][i]))
+        x, y = u, n_upper + v
+        if connected:
+            res = _connected_from(g, member, [x, y])
+        else:
+            comp = components(g)
+            res = member & ((comp == comp[x]) | (comp == comp[y]))
+        out.append(("OK", res))
     return out
 
 

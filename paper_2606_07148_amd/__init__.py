@@ -88,6 +88,11 @@ def load():
         "abcore_core_numbers": (i32, [vp, vp, P(i32), vp]),
         "abcore_components": (i32, [vp, vp, vp]),
         "abcore_query": (i32, [vp, abcore_edge_update, u32, u32, P(i32), P(u32), vp]),
+        "abcore_query_set": (i32, [vp, abcore_edge_update, u32, u32, i32, P(i32), P(u32), vp,
+                                   P(i64), vp]),
+        "abcore_community": (i32, [vp, i32, u32, u32, i32, vp, P(i64), vp]),
+        "abcore_alpha_offsets": (i32, [vp, P(u32), i32, P(u32), P(i32), vp]),
+        "abcore_default_query": (i32, [vp, P(u32), P(u32), vp]),
         "abcore_set_option": (i32, [vp, i32, i64]),
         "abcore_kernel_timing": (i32, [vp, i32, P(ctypes.c_double), P(i64), i32]),
         "abcore_compute_batch": (i32, [vp, P(u32), P(u32), i32, vp, vp]),
@@ -379,3 +384,53 @@ def abcore_query(g: Graph, u: int, v: int, op: int, alpha: int, beta: int, strea
                                ctypes.byref(bits), _stream(stream)))
     g.m += int(op)
     return bool(ans.value), int(bits.value)
+
+
+def abcore_query_set(g: Graph, u: int, v: int, op: int, alpha: int, beta: int,
+                     connected: bool = False, out=None, stream=None):
+    """Apply one edge update; return (answer, endpoint_bits, bitmask tensor,
+    set size): the core members the scoped peel leaves in the component(s)
+    of u and v, or with connected=True those connected to u or v."""
+    import torch
+    if out is None:
+        out = torch.empty(max(1, g.nwords), dtype=torch.int32, device="cuda")
+    ans = ctypes.c_int32()
+    bits = ctypes.c_uint32()
+    cnt = ctypes.c_int64()
+    upd = abcore_edge_update(int(u), int(v), int(op))
+    _check(load().abcore_query_set(g.handle, upd, int(alpha), int(beta), int(bool(connected)),
+                                   ctypes.byref(ans), ctypes.byref(bits), _ptr(out),
+                                   ctypes.byref(cnt), _stream(stream)))
+    g.m += int(op)
+    return bool(ans.value), int(bits.value), out, int(cnt.value)
+
+
+def abcore_community(g: Graph, q: int, alpha: int, beta: int, connected: bool = False,
+                     out=None, stream=None):
+    """(bitmask tensor, size) of the (alpha,beta)-core members around vertex
+    q (unified id): its component's members, or with connected=True the
+    connected part of the core containing q."""
+    import torch
+    if out is None:
+        out = torch.empty(max(1, g.nwords), dtype=torch.int32, device="cuda")
+    cnt = ctypes.c_int64()
+    _check(load().abcore_community(g.handle, int(q), int(alpha), int(beta), int(bool(connected)),
+                                   _ptr(out), ctypes.byref(cnt), _stream(stream)))
+    return out, int(cnt.value)
+
+
+def abcore_alpha_offsets(g: Graph, alphas, stream=None):
+    """(alpha_offset of each alpha, delta) -- the query parameters of Sec. VI-B."""
+    a, q = _u32_array(alphas)
+    off = (ctypes.c_uint32 * max(1, q))()
+    d = ctypes.c_int32()
+    _check(load().abcore_alpha_offsets(g.handle, a, q, off, ctypes.byref(d), _stream(stream)))
+    return [int(x) for x in list(off)[:q]], int(d.value)
+
+
+def abcore_default_query(g: Graph, stream=None):
+    """The default (alpha, beta) of Sec. VI-B."""
+    a, b = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(load().abcore_default_query(g.handle, ctypes.byref(a), ctypes.byref(b),
+                                       _stream(stream)))
+    return int(a.value), int(b.value)

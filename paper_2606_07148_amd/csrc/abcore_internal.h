@@ -233,6 +233,8 @@ struct Graph {
   // equal weight (entries of unsplit rows plus a per-row cost).
   int32_t *pull_bounds = nullptr;  // 2 * (pull_bounds_grid + 1)
   int pull_bounds_grid = 0;
+  int64_t *aux = nullptr;   // small counters of the vertex-set searches (4)
+  uint32_t *probe_bits = nullptr;  // ceil(n/32) words: results of offset probes
   int32_t *comp = nullptr;  // component labels
   bool comp_valid = false;
   int32_t *parent = nullptr; // union-find scratch
@@ -465,6 +467,16 @@ abcore_status build_pieces(Graph &g, hipStream_t s);
 // an allocation failure it leaves them null and succeeds.
 abcore_status build_ranks(Graph &g, hipStream_t s);
 hipError_t launch_answer_view(const PeelArgs &a, int32_t x, int32_t y, hipStream_t s);
+// After a peel scoped to the components of vx and vy: the survivors of that
+// scope, or with `connected` those reachable from vx or vy through
+// survivors, into d_bits (every word); *count (nullable) their number.
+// Synchronous.  Needs g.list and g.list2 for `connected`.
+abcore_status scoped_set(Graph &g, int32_t vx, int32_t vy, int32_t thrU, int32_t thrL,
+                         bool connected, uint32_t *d_bits, int64_t *count, hipStream_t s);
+// Largest deg0 over ids [lo, hi); set bits of a ceil(n/32)-word bitmask.
+// Synchronous.
+abcore_status max_degree(Graph &g, int64_t lo, int64_t hi, int32_t *out, hipStream_t s);
+abcore_status count_bits(Graph &g, const uint32_t *bits, int64_t *out, hipStream_t s);
 hipError_t launch_update_window(Graph &g, const int32_t *d_upd, int w, WindowRecord *d_rec,
                                 hipStream_t s);
 hipError_t launch_relabel(Graph &g, int32_t from, int32_t to, hipStream_t s);

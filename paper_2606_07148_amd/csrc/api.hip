@@ -170,7 +170,7 @@ void free_graph(Graph *g) {
                   g->pull_bounds, g->row_bits,    g->split_written, g->rank,
                   g->rcols,       g->rank_vtx,    g->roff,        g->rp_row,
                   g->rp_start,    g->rp_first,    g->rdeg,        g->state_alt,
-                  g->part_alt,    g->rs_fail};
+                  g->part_alt,    g->rs_fail,     g->aux,         g->probe_bits};
   for (void *p : bufs)
     if (p) (void)dev_free(p);
   if (g->h_abort) (void)hipHostFree(g->h_abort);
@@ -1271,22 +1271,24 @@ abcore_status abcore_compute_batch(abcore_graph h, const uint32_t *h_alpha,
   return read_state(*g, s);
 }
 
-abcore_status abcore_query(abcore_graph h, abcore_edge_update upd, uint32_t alpha,
-                           uint32_t beta, int32_t *h_answer, uint32_t *h_endpoint_bits,
-                           void *stream) {
-  Graph *g = reinterpret_cast<Graph *>(h);
-  if (g && serving(*g)) return busy_error(__func__);
+// abcore_query and abcore_query_set: the update, the component maintenance,
+// the scoped peel, the answer and (d_set non-null) the vertex set.
+static abcore_status query_impl(Graph *g, abcore_edge_update upd, uint32_t alpha, uint32_t beta,
+                                int32_t *h_answer, uint32_t *h_endpoint_bits, uint32_t *d_set,
+                                bool connected, int64_t *set_count, void *stream,
+                                const char *fn) {
+  if (g && serving(*g)) return busy_error(fn);
   if (!g || !h_answer) {
-    set_error("abcore_query: null handle or answer pointer");
+    set_error("%s: null handle or answer pointer", fn);
     return ABCORE_EINVAL;
   }
   if (upd.u < 0 || upd.u >= g->nU || upd.v < 0 || upd.v >= g->nL ||
       (upd.op != 1 && upd.op != -1)) {
-    set_error("abcore_query: update (%d, %d, op %d) out of range", upd.u, upd.v, upd.op);
+    set_error("%s: update (%d, %d, op %d) out of range", fn, upd.u, upd.v, upd.op);
     return ABCORE_EINVAL;
   }
   if (alpha < 1 || beta < 1) {
-    set_error("abcore_query: alpha and beta must be >= 1");
+    set_error("%s: alpha and beta must be >= 1", fn);
     return ABCORE_EINVAL;
   }
   CHK(hipSetDevice(g->device));
@@ -1294,17 +1296,21 @@ abcore_status abcore_query(abcore_graph h, abcore_edge_update upd, uint32_t alph
   hipStream_t s = as_stream(stream);
   TRY(compute_components(*g, s));
   TRY(ensure_delta(*g, s));
+  if (d_set != nullptr && connected) {
+    TRY(ensure(&g->list, g->n));
+    TRY(ensure(&g->list2, g->n));
+  }
   // 1. apply the update (validated on the device before any write)
   CHK(launch_init_state(*g, s));
   CHK(launch_update(*g, upd.u, upd.v, upd.op, g->delta.count, s));
   TRY(read_state(*g, s));
   const int32_t ustat = g->h_state->status;
   if (ustat == -(int32_t)ABCORE_EEXIST) {
-    set_error("abcore_query: edge (%d, %d) already present", upd.u, upd.v);
+    set_error("%s: edge (%d, %d) already present", fn, upd.u, upd.v);
     return ABCORE_EEXIST;
   }
   if (ustat == -(int32_t)ABCORE_ENOENT) {
-    set_error("abcore_query: edge (%d, %d) not present", upd.u, upd.v);
+    set_error("%s: edge (%d, %d) not present", fn, upd.u, upd.v);
     return ABCORE_ENOENT;
   }
   if (ustat == 1) g->delta.count += 1;
@@ -1332,7 +1338,139 @@ abcore_status abcore_query(abcore_graph h, abcore_edge_update upd, uint32_t alph
   const int32_t bits = g->h_state->aux0;
   *h_answer = (bits & 3) == 3 ? 1 : 0;
   if (h_endpoint_bits) *h_endpoint_bits = (uint32_t)bits;
+  // 4. the vertex set (Remark of Sec. V): what the scoped peel left
+  if (d_set != nullptr) TRY(scoped_set(*g, x, y, thrU, thrL, connected, d_set, set_count, s));
   return ABCORE_OK;
+}
+
+abcore_status abcore_query(abcore_graph h, abcore_edge_update upd, uint32_t alpha,
+                           uint32_t beta, int32_t *h_answer, uint32_t *h_endpoint_bits,
+                           void *stream) {
+  return query_impl(reinterpret_cast<Graph *>(h), upd, alpha, beta, h_answer, h_endpoint_bits,
+                    nullptr, false, nullptr, stream, __func__);
+}
+
+abcore_status abcore_query_set(abcore_graph h, abcore_edge_update upd, uint32_t alpha,
+                               uint32_t beta, int32_t connected, int32_t *h_answer,
+                               uint32_t *h_endpoint_bits, uint32_t *d_bitmask,
+                               int64_t *out_count, void *stream) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (g && !d_bitmask && g->n > 0) {
+    set_error("abcore_query_set: null bitmask");
+    return ABCORE_EINVAL;
+  }
+  return query_impl(g, upd, alpha, beta, h_answer, h_endpoint_bits, d_bitmask, connected != 0,
+                    out_count, stream, __func__);
+}
+
+// alpha_offset(alpha): the largest beta with a non-empty (alpha,beta)-core.
+// Cores are nested (the (alpha,beta+1)-core lies inside the (alpha,beta)-
+// core), so emptiness is monotone in beta and a binary search of GCC+
+// queries finds it: non-empty at beta = delta when alpha <= delta (the
+// (delta,delta)-core is inside), empty above the largest lower degree.
+static abcore_status alpha_offset(Graph *g, uint32_t alpha, int32_t maxdeg_l, uint32_t *out,
+                                  hipStream_t s) {
+  auto nonempty = [&](uint32_t beta, bool *yes) -> abcore_status {
+    TRY(abcore_compute(reinterpret_cast<abcore_graph>(g), alpha, beta, ABCORE_GCC_PLUS,
+                       g->probe_bits, nullptr, s));
+    int64_t c = 0;
+    TRY(count_bits(*g, g->probe_bits, &c, s));
+    *yes = c > 0;
+    return ABCORE_OK;
+  };
+  bool yes = false;
+  TRY(nonempty(1, &yes));
+  if (!yes) {
+    *out = 0;
+    return ABCORE_OK;
+  }
+  uint64_t lo = 1, hi = (uint64_t)maxdeg_l + 1;  // non-empty at lo, empty at hi
+  if (alpha <= (uint32_t)g->max_core && (uint64_t)g->max_core > lo)
+    lo = std::min<uint64_t>((uint64_t)g->max_core, hi - 1);
+  while (hi - lo > 1) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    TRY(nonempty((uint32_t)mid, &yes));
+    (yes ? lo : hi) = mid;
+  }
+  *out = (uint32_t)lo;
+  return ABCORE_OK;
+}
+
+abcore_status abcore_alpha_offsets(abcore_graph h, const uint32_t *h_alpha, int32_t q,
+                                   uint32_t *h_offset, int32_t *out_delta, void *stream) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (g && serving(*g)) return busy_error(__func__);
+  if (!g || q < 0 || (q > 0 && (!h_alpha || !h_offset))) {
+    set_error("abcore_alpha_offsets: null handle or arrays, or q < 0");
+    return ABCORE_EINVAL;
+  }
+  for (int32_t i = 0; i < q; ++i)
+    if (h_alpha[i] < 1) {
+      set_error("abcore_alpha_offsets: alpha %d is 0", i);
+      return ABCORE_EINVAL;
+    }
+  CHK(hipSetDevice(g->device));
+  TRY(check_abort(*g));
+  hipStream_t s = as_stream(stream);
+  TRY(compute_core(*g, s));
+  if (out_delta) *out_delta = g->max_core;
+  if (q == 0) return ABCORE_OK;
+  TRY(ensure(&g->probe_bits, (g->n + 31) / 32 + 1));
+  int32_t maxdeg_l = 0;
+  TRY(max_degree(*g, g->nU, g->n, &maxdeg_l, s));
+  for (int32_t i = 0; i < q; ++i) TRY(alpha_offset(g, h_alpha[i], maxdeg_l, &h_offset[i], s));
+  return ABCORE_OK;
+}
+
+abcore_status abcore_default_query(abcore_graph h, uint32_t *alpha, uint32_t *beta,
+                                   void *stream) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (!g || !alpha || !beta) {
+    set_error("abcore_default_query: null pointer");
+    return ABCORE_EINVAL;
+  }
+  int32_t delta = 0;
+  TRY(abcore_alpha_offsets(h, nullptr, 0, nullptr, &delta, stream));
+  const uint32_t a = std::max<uint32_t>(1, (uint32_t)((4 * (int64_t)delta) / 10));
+  uint32_t off = 0;
+  TRY(abcore_alpha_offsets(h, &a, 1, &off, nullptr, stream));
+  *alpha = a;
+  *beta = std::max<uint32_t>(1, (uint32_t)((6 * (uint64_t)off) / 10));
+  return ABCORE_OK;
+}
+
+abcore_status abcore_community(abcore_graph h, int32_t q, uint32_t alpha, uint32_t beta,
+                               int32_t connected, uint32_t *d_bitmask, int64_t *out_count,
+                               void *stream) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (g && serving(*g)) return busy_error(__func__);
+  if (!g || !d_bitmask) {
+    set_error("abcore_community: null handle or bitmask");
+    return ABCORE_EINVAL;
+  }
+  if (q < 0 || (int64_t)q >= g->n) {
+    set_error("abcore_community: vertex %d out of range", q);
+    return ABCORE_EINVAL;
+  }
+  if (alpha < 1 || beta < 1) {
+    set_error("abcore_community: alpha and beta must be >= 1");
+    return ABCORE_EINVAL;
+  }
+  CHK(hipSetDevice(g->device));
+  TRY(check_abort(*g));
+  hipStream_t s = as_stream(stream);
+  TRY(compute_components(*g, s));
+  if (connected) {
+    TRY(ensure(&g->list, g->n));
+    TRY(ensure(&g->list2, g->n));
+  }
+  // Algorithm 1 on q's connected component only, as GFQ scopes its peel
+  const int32_t thrU = clamp_thr(alpha), thrL = clamp_thr(beta);
+  int64_t launches = 0;
+  CHK(launch_init_state(*g, s));
+  CHK(launch_scan_component_of(*g, thrU, thrL, q, q, s));
+  TRY(pull_peel_pack(*g, kGCC, thrU, thrL, g->pull_mode != 1, nullptr, s, &launches));
+  return scoped_set(*g, q, q, thrU, thrL, connected != 0, d_bitmask, out_count, s);
 }
 
 abcore_status abcore_serve_start(abcore_graph h, int64_t max_inflight, int32_t device_slots,

@@ -55,3 +55,34 @@ def core_numbers_by_enumeration(n_upper, n_lower, edges):
             if mem[i]:
                 core[i] = delta
         delta += 1
+
+
+def connected_core_by_enumeration(n_upper, n_lower, edges, alpha, beta, q):
+    """Union of every vertex set S that contains q, induces a connected
+    subgraph and gives each upper vertex >= alpha and each lower vertex >=
+    beta neighbours inside S.  The union of such sets is itself one (it is
+    connected through q and keeps every degree), so it is the maximal
+    connected (alpha,beta)-subgraph containing q (empty if there is none)."""
+    import itertools
+    n = n_upper + n_lower
+    adj = [set() for _ in range(n)]
+    for u, v in edges:
+        adj[u].add(n_upper + v)
+        adj[n_upper + v].add(u)
+    best = set()
+    others = [x for x in range(n) if x != q]
+    for r in range(len(others) + 1):
+        for comb in itertools.combinations(others, r):
+            S = set(comb) | {q}
+            if any(len(adj[x] & S) < (alpha if x < n_upper else beta) for x in S):
+                continue
+            seen, stack = {q}, [q]
+            while stack:
+                x = stack.pop()
+                for w in adj[x] & S:
+                    if w not in seen:
+                        seen.add(w)
+                        stack.append(w)
+            if seen == S:
+                best |= S
+    return best

@@ -464,3 +464,124 @@ def test_certificate_rejects_planted_mistakes():
     rev = order[::-1].copy()
     with pytest.raises(AssertionError):
         _certify(g, mem, rev, a, b)
+
+
+def test_community_equals_enumeration_tiny():
+    """Localized community search (Remark of Sec. V), both readings, against
+    enumeration on tiny graphs: the connected reading is the maximal
+    connected (alpha,beta)-subgraph containing q (brute force over vertex
+    sets); the component reading is Definition 1's core (brute force)
+    inside q's connected component (networkx)."""
+    from tests.bruteforce import connected_core_by_enumeration
+    rng = np.random.default_rng(77)
+    checked = 0
+    for _ in range(120):
+        nU, nL, edges = _random_tiny(rng, max_n=11)
+        g = _graph(nU, nL, edges)
+        a, b = int(rng.integers(1, 4)), int(rng.integers(1, 4))
+        core = np.array(core_by_enumeration(nU, nL, edges, a, b))
+        comps = list(nx.connected_components(_nx_graph(g)))
+        for q in range(g.n):
+            want_conn = connected_core_by_enumeration(nU, nL, edges, a, b, q)
+            got_conn = oracle.community(g, q, a, b, connected=True)
+            assert set(np.flatnonzero(got_conn).tolist()) == want_conn
+            cq = next(c for c in comps if q in c)
+            want_comp = {x for x in cq if core[x]}
+            got_comp = oracle.community(g, q, a, b, connected=False)
+            assert set(np.flatnonzero(got_comp).tolist()) == want_comp
+            checked += len(want_conn) > 0
+    assert checked > 50
+
+
+def test_community_on_worked_example():
+    """The worked example's (1,3)-core is {u0..u7, v0, v1, v2, v4}.  The
+    fixture has two components (the K_{4,3} block and the rest), so the
+    component reading splits the core between them, and the (2,3)-core
+    K_{4,3} is one connected community."""
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                     "worked_example.json")))
+    nU = fx["n_upper"]
+    g = _graph(nU, fx["n_lower"], [tuple(e) for e in fx["edges"]])
+    cores = {(f["alpha"], f["beta"]): {_name_to_id(s, nU) for s in f["members"]}
+             for f in fx["facts"] if f["kind"] == "core"}
+    want13 = cores[(1, 3)]
+    block = {_name_to_id(s, nU) for s in ("u0", "u1", "u2", "u3", "v0", "v1", "v2")}
+    a = set(np.flatnonzero(oracle.community(g, 0, 1, 3, connected=False)).tolist())
+    b = set(np.flatnonzero(oracle.community(g, _name_to_id("u4", nU), 1, 3,
+                                            connected=False)).tolist())
+    assert a == want13 & block and b == want13 - block and a | b == want13
+    want23 = cores[(2, 3)]
+    for q in want23:
+        got = oracle.community(g, q, 2, 3, connected=True)
+        assert set(np.flatnonzero(got).tolist()) == want23
+    # a vertex outside the core has an empty connected community
+    assert not oracle.community(g, _name_to_id("u7", nU), 2, 3, connected=True).any()
+
+
+def test_gfq_set_equals_community_after_update():
+    """The GFQ set variant after each update equals the community search on
+    the updated graph around its endpoints (both readings), and its endpoint
+    membership equals gfq_stream's answer bits."""
+    spec = bigraph_gen.CONFIGS[1]
+    eu, ev = bigraph_gen.make_graph(spec)
+    ups = bigraph_gen.update_stream(spec, eu, ev, 12, 4242)
+    nU, nL = spec["n_upper"], spec["n_lower"]
+    for connected in (False, True):
+        res = oracle.gfq_set_stream(nU, nL, eu, ev, ups, connected)
+        ans = oracle.gfq_stream(nU, nL, eu, ev, ups)
+        present = set(zip(eu.tolist(), ev.tolist()))
+        for i, ((st, mem), (st2, a, bits)) in enumerate(zip(res, ans)):
+            assert st == st2
+            u, v, op = int(ups["u"][i]), int(ups["v"][i]), int(ups["op"][i])
+            if op > 0:
+                present.add((u, v))
+            else:
+                present.discard((u, v))
+            if st != "OK":
+                continue
+            assert bool(mem[u]) == bool(bits & 1) and bool(mem[nU + v]) == bool(bits >> 1 & 1)
+            if i % 4 == 0:
+                pe = np.array(sorted(present), np.int32)
+                g = oracle.Graph(nU, nL, pe[:, 0], pe[:, 1])
+                al, be = int(ups["alpha"][i]), int(ups["beta"][i])
+                want = (oracle.community(g, u, al, be, connected) |
+                        oracle.community(g, nU + v, al, be, connected))
+                assert np.array_equal(mem, want)
+
+
+def test_offsets_and_delta_equal_enumeration_tiny():
+    """alpha_offset (Sec. VI-B) and delta (Table I) against Definition 1 by
+    enumeration: the largest beta whose brute-force core is non-empty, and
+    the largest symmetric one; delta also equals the maximum core number
+    (Definition 2)."""
+    rng = np.random.default_rng(91)
+    for _ in range(60):
+        nU, nL, edges = _random_tiny(rng, max_n=10)
+        g = _graph(nU, nL, edges)
+        for a in (1, 2, 3):
+            want = 0
+            for b in range(1, nU + 2):
+                if any(core_by_enumeration(nU, nL, edges, a, b)):
+                    want = b
+            assert oracle.alpha_offset(g, a) == want
+        want_d = max([d for d in range(1, nU + nL + 1)
+                      if any(core_by_enumeration(nU, nL, edges, d, d))] or [0])
+        assert oracle.delta(g) == want_d
+        assert want_d == (int(oracle.core_numbers(g).max()) if g.n else 0)
+
+
+def test_default_query_on_worked_example():
+    """On the worked example delta = 3 (the K_{4,3} block's core number), so
+    alpha = floor(1.2) = 1; the (1,beta)-core is non-empty up to beta = 4
+    (u0..u3 keep v0..v2 at degree 4, and the star around v4 has degree 4),
+    so alpha_offset(1) = 4 and beta = floor(2.4) = 2.  In K_{4,3} each upper
+    vertex has degree 3 and each lower vertex 4, so alpha_offset(3) = 4; no
+    upper vertex has degree 4, so alpha_offset(4) = 0."""
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                     "worked_example.json")))
+    g = _graph(fx["n_upper"], fx["n_lower"], [tuple(e) for e in fx["edges"]])
+    assert oracle.delta(g) == 3
+    assert oracle.alpha_offset(g, 1) == 4
+    assert oracle.alpha_offset(g, 3) == 4
+    assert oracle.alpha_offset(g, 4) == 0
+    assert oracle.default_query(g) == (1, 2)
