@@ -342,6 +342,11 @@ abcore_status abcore_serve_stop(abcore_graph g, int64_t *counters);
  *                          IV-A), and other first pull rounds count on it;
  *                          2 = index-free: every query runs in vertex order
  *                          on the CSR alone, as Algorithm 1 does.
+ *   ABCORE_OPT_AUTOTUNE  : 0 or 1 (default) = take mappings from the tuning
+ *                          cache and tune batches on first use (below);
+ *                          2 = off.  Setting ABCORE_OPT_GRID or
+ *                          ABCORE_OPT_CLAIM to a non-zero value fixes the
+ *                          mapping (no cache lookups).
  *   ABCORE_OPT_SPIN_LIMIT: failure injection for tests: polls a waiting wave
  *                          of the asynchronous peel makes before it declares
  *                          a hang and aborts (0 = the default, 2^21, i.e.
@@ -365,7 +370,8 @@ enum {
   ABCORE_OPT_PULL = 5,
   ABCORE_OPT_CLAIM = 6,
   ABCORE_OPT_RANK_ORDER = 7,
-  ABCORE_OPT_SPIN_LIMIT = 8
+  ABCORE_OPT_SPIN_LIMIT = 8,
+  ABCORE_OPT_AUTOTUNE = 9
 };
 abcore_status abcore_set_option(abcore_graph g, int32_t option, int64_t value);
 
@@ -381,6 +387,22 @@ abcore_status abcore_set_option(abcore_graph g, int32_t option, int64_t value);
 abcore_status abcore_autotune(abcore_graph g, uint32_t alpha, uint32_t beta, int32_t algo,
                               int32_t *out_grid, int32_t *out_claim, double *out_ms,
                               void *stream);
+
+/* Tuning cache.  abcore_autotune stores its choice under the device's
+ * architecture name, compute-unit count, graph shape (floor log2 of the
+ * vertex count and of the 2m adjacency entries) and kind 0 (single
+ * queries); later handles of that shape take it on their first
+ * abcore_compute unless the caller set the grid or claim.  A batch
+ * (abcore_compute_batch, kind 1) looks its mapping up there and, the first
+ * time a shape is seen, tunes it on the batch's median query (by alpha +
+ * beta) and stores it; it applies to that call only.  ABCORE_OPT_AUTOTUNE:
+ * 0 or 1 = on (default), 2 = off.  abcore_tuned reads the entry for the
+ * handle's shape (*found = 0 if none).  abcore_tune_cache: mode 0 loads
+ * (merges) the text file at path, 1 saves the cache there, 2 clears it
+ * (path unused); one entry per line: arch cu nlog elog kind grid claim ms. */
+abcore_status abcore_tuned(abcore_graph g, int32_t kind, int32_t *out_grid, int32_t *out_claim,
+                           double *out_ms, int32_t *found);
+abcore_status abcore_tune_cache(const char *path, int32_t mode);
 
 /* Kernel kinds timed while ABCORE_OPT_TIMING is on: the push peel
  * (Algorithm 1, peel phase), the pull-form first round, the scan phase, the

@@ -27,6 +27,7 @@ ABCORE_OPT_PULL = 5
 ABCORE_OPT_CLAIM = 6
 ABCORE_OPT_RANK_ORDER = 7
 ABCORE_OPT_SPIN_LIMIT = 8
+ABCORE_OPT_AUTOTUNE = 9
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOENT", 5: "EEXIST",
           6: "EBUSY", 7: "EAGAIN"}
@@ -103,6 +104,8 @@ def load():
         "abcore_serve_stop": (i32, [vp, P(i64)]),
         "abcore_graph_report": (i32, [vp, P(abcore_report)]),
         "abcore_device_memory": (i32, [P(i64), P(i64), i32]),
+        "abcore_tuned": (i32, [vp, i32, P(i32), P(i32), P(ctypes.c_double), P(i32)]),
+        "abcore_tune_cache": (i32, [ctypes.c_char_p, i32]),
         "abcore_autotune": (i32, [vp, u32, u32, i32, P(i32), P(i32), P(ctypes.c_double), vp]),
     }
     for name, (res, args) in sig.items():
@@ -434,3 +437,17 @@ def abcore_default_query(g: Graph, stream=None):
     _check(load().abcore_default_query(g.handle, ctypes.byref(a), ctypes.byref(b),
                                        _stream(stream)))
     return int(a.value), int(b.value)
+
+
+def abcore_tuned(g: Graph, kind: int = 1):
+    """(grid, claim, ms) cached for the handle's architecture and shape
+    (kind 0 single queries, 1 batches), or None."""
+    gr, cl, ms, found = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
+    _check(load().abcore_tuned(g.handle, int(kind), ctypes.byref(gr), ctypes.byref(cl),
+                               ctypes.byref(ms), ctypes.byref(found)))
+    return (int(gr.value), int(cl.value), float(ms.value)) if found.value else None
+
+
+def abcore_tune_cache(path, mode: int):
+    """Tuning cache file: mode 0 load, 1 save, 2 clear."""
+    _check(load().abcore_tune_cache(None if path is None else str(path).encode(), int(mode)))

@@ -152,6 +152,9 @@ struct BatchCache {
 
 struct Graph {
   int device = 0;
+  char arch[64] = "";  // gcnArchName of the device (key of the tuning cache)
+  int autotune = 1;    // ABCORE_OPT_AUTOTUNE: batches take a tuned mapping
+  bool tuned = false;  // grid and claim chosen (by a tuner or by the caller)
   int32_t nU = 0, nL = 0;
   int64_t n = 0;
   int64_t m = 0;      // current distinct edges

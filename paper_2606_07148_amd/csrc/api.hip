@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <tuple>
 #include <mutex>
 #include <new>
 #include <unordered_map>
@@ -42,6 +44,52 @@ hipError_t dev_free(void *p) {
     }
   }
   return hipFree(p);
+}
+
+// ----------------------------------------------------------- tuning cache --
+// Mappings chosen by abcore_autotune, per device architecture, compute-unit
+// count, graph shape (log2 of the vertex count and of the adjacency entries)
+// and workload kind (0 = single query, 1 = batch), shared by every handle
+// of the process and savable to a text file.
+struct TuneKey {
+  std::string arch;
+  int cu, nlog, elog, kind;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(arch, cu, nlog, elog, kind) < std::tie(o.arch, o.cu, o.nlog, o.elog, o.kind);
+  }
+};
+struct TuneVal {
+  int grid, claim;
+  double ms;
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, TuneVal> g_tune;
+
+static int floor_log2(int64_t v) {
+  int l = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++l;
+  }
+  return l;
+}
+
+static TuneKey tune_key(const Graph &g, int kind) {
+  return TuneKey{g.arch, g.cu_count, floor_log2(std::max<int64_t>(g.n, 1)),
+                 floor_log2(std::max<int64_t>(2 * g.m, 1)), kind};
+}
+
+static void tune_store(const Graph &g, int kind, int grid, int claim, double ms) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune[tune_key(g, kind)] = TuneVal{grid, claim, ms};
+}
+
+static bool tune_find(const Graph &g, int kind, TuneVal *out) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune.find(tune_key(g, kind));
+  if (it == g_tune.end()) return false;
+  *out = it->second;
+  return true;
 }
 
 void set_error(const char *fmt, ...) {
@@ -696,6 +744,9 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) {
       if (prop.multiProcessorCount > 0) g->cu_count = prop.multiProcessorCount;
+      snprintf(g->arch, sizeof(g->arch), "%s", prop.gcnArchName);
+      for (char *c = g->arch; *c; ++c)
+        if (*c == ' ' || *c == '\t') *c = '_';
       if (prop.sharedMemPerBlock > 0) g->lds_per_block = prop.sharedMemPerBlock;
     }
     g->nU = n_upper;
@@ -865,6 +916,14 @@ abcore_status abcore_set_option(abcore_graph h, int32_t option, int64_t value) {
       return ABCORE_OK;
     case ABCORE_OPT_GRID:
       g->grid = (int)std::min<int64_t>(value, kMaxBlocks);
+      g->tuned = value != 0;  // the caller's choice stands
+      return ABCORE_OK;
+    case ABCORE_OPT_AUTOTUNE:
+      if (value > 2) {
+        set_error("abcore_set_option: autotune mode %lld unknown", (long long)value);
+        return ABCORE_EINVAL;
+      }
+      g->autotune = value != 2;
       return ABCORE_OK;
     case ABCORE_OPT_ROUNDS_PER_SYNC:
       g->rounds_per_sync = value == 0 ? 16 : (int)std::min<int64_t>(value, 4096);
@@ -895,6 +954,7 @@ abcore_status abcore_set_option(abcore_graph h, int32_t option, int64_t value) {
         return ABCORE_EINVAL;
       }
       g->claim = value == 0 ? kDefaultClaim : (int)value;
+      g->tuned = value != 0;
       return ABCORE_OK;
     default:
       set_error("abcore_set_option: unknown option %d", option);
@@ -985,6 +1045,14 @@ abcore_status abcore_compute(abcore_graph h, uint32_t alpha, uint32_t beta, int3
   CHK(hipSetDevice(g->device));
   TRY(check_abort(*g));
   hipStream_t s = as_stream(stream);
+  if (g->autotune && !g->tuned) {
+    // a mapping tuned for single queries on this architecture and shape
+    TuneVal v{};
+    if (tune_find(*g, 0, &v)) {
+      g->grid = v.grid;
+      g->claim = v.claim;
+    }
+  }
   const int32_t thrU = clamp_thr(alpha), thrL = clamp_thr(beta);
   int64_t launches = 0;
   bool plus_pull = false;  // GCC+ initialised by a pull round
@@ -1163,6 +1231,9 @@ abcore_status abcore_compute_static(abcore_graph h, uint32_t alpha, uint32_t bet
   return ABCORE_OK;
 }
 
+static abcore_status tune_mapping(Graph *g, uint32_t alpha, uint32_t beta, int32_t algo,
+                                  void *stream, int *out_grid, int *out_claim, double *out_ms);
+
 static abcore_status batch_thresholds(const uint32_t *h_alpha, const uint32_t *h_beta,
                                       int32_t q, std::vector<int32_t> &tu,
                                       std::vector<int32_t> &tl) {
@@ -1211,6 +1282,37 @@ abcore_status abcore_compute_batch(abcore_graph h, const uint32_t *h_alpha,
   CHK(hipSetDevice(g->device));
   TRY(check_abort(*g));
   hipStream_t s = as_stream(stream);
+  // the batch's mapping holds for this call only
+  struct RestoreMapping {
+    Graph &g;
+    int grid, claim;
+    bool active;
+    ~RestoreMapping() {
+      if (active) {
+        g.grid = grid;
+        g.claim = claim;
+      }
+    }
+  } restore_mapping{*g, g->grid, g->claim, false};
+  if (g->autotune && !g->tuned && g->peel_mode == 3) {
+    // the asynchronous peel's mapping for this architecture and graph
+    // shape: from the tuning cache, else tuned now on the batch's median
+    // query (by alpha + beta) and cached
+    TuneVal v{};
+    if (!tune_find(*g, 1, &v)) {
+      std::vector<int32_t> idx(q);
+      for (int32_t i = 0; i < q; ++i) idx[i] = i;
+      std::sort(idx.begin(), idx.end(),
+                [&](int32_t x, int32_t y) { return tu[x] + tl[x] < tu[y] + tl[y]; });
+      const int32_t r = idx[q / 2];
+      TRY(tune_mapping(g, (uint32_t)tu[r], (uint32_t)tl[r], ABCORE_GCC, stream, &v.grid,
+                       &v.claim, &v.ms));
+      tune_store(*g, 1, v.grid, v.claim, v.ms);
+    }
+    restore_mapping.active = true;
+    g->grid = v.grid;
+    g->claim = v.claim;
+  }
   BatchPlan plan = make_batch_plan(tu.data(), tl.data(), q);
   TRY(ensure_slots(*g, plan.nslots));
   // the sequence has no host reads in the asynchronous peel mode: it is
@@ -1528,17 +1630,13 @@ abcore_status abcore_serve_stop(abcore_graph h, int64_t *counters) {
   return st;
 }
 
-abcore_status abcore_autotune(abcore_graph h, uint32_t alpha, uint32_t beta, int32_t algo,
-                              int32_t *out_grid, int32_t *out_claim, double *out_ms,
-                              void *stream) {
-  Graph *g = reinterpret_cast<Graph *>(h);
-  if (g && serving(*g)) return busy_error(__func__);
-  if (!g || alpha < 1 || beta < 1 || (algo != ABCORE_GCC && algo != ABCORE_GCC_PLUS)) {
-    set_error("abcore_autotune: null handle, threshold 0 or unknown algorithm");
-    return ABCORE_EINVAL;
-  }
-  CHK(hipSetDevice(g->device));
-  TRY(check_abort(*g));
+// Times the query (alpha, beta) with algorithm algo (3 runs after a warm
+// run, median) for every pair of asynchronous-peel grid size and claim size
+// and returns the fastest pair; the handle's grid and claim are left as
+// they were.
+static abcore_status tune_mapping(Graph *g, uint32_t alpha, uint32_t beta, int32_t algo,
+                                  void *stream, int *out_grid, int *out_claim, double *out_ms) {
+  abcore_graph h = reinterpret_cast<abcore_graph>(g);
   hipStream_t s = as_stream(stream);
   const int64_t words = std::max<int64_t>(1, (g->n + 31) / 32);
   uint32_t *bits = nullptr;
@@ -1547,8 +1645,9 @@ abcore_status abcore_autotune(abcore_graph h, uint32_t alpha, uint32_t beta, int
   hipError_t he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
   const int saved_grid = g->grid, saved_claim = g->claim;
-  const bool saved_timing = g->timing;
+  const bool saved_timing = g->timing, saved_tuned = g->tuned;
   g->timing = false;
+  g->tuned = true;  // the sweep's settings hold for its queries
   abcore_status st = he == hipSuccess ? ABCORE_OK : ABCORE_EDEVICE;
   const int cu = g->cu_count;
   const int grids[] = {cu / 2, (3 * cu) / 4, cu, (3 * cu) / 2, 2 * cu, 3 * cu};
@@ -1582,21 +1681,107 @@ abcore_status abcore_autotune(abcore_graph h, uint32_t alpha, uint32_t beta, int
     }
   }
   g->timing = saved_timing;
+  g->tuned = saved_tuned;
+  g->grid = saved_grid;
+  g->claim = saved_claim;
   if (st == ABCORE_OK && read_state(*g, s) != ABCORE_OK) st = ABCORE_EDEVICE;
   if (st == ABCORE_OK) {
-    g->grid = best_grid;
-    g->claim = best_claim;
-    if (out_grid) *out_grid = best_grid;
-    if (out_claim) *out_claim = best_claim;
-    if (out_ms) *out_ms = best;
-  } else {
-    g->grid = saved_grid;
-    g->claim = saved_claim;
+    *out_grid = best_grid;
+    *out_claim = best_claim;
+    *out_ms = best;
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)dev_free(bits);
   return st;
+}
+
+abcore_status abcore_autotune(abcore_graph h, uint32_t alpha, uint32_t beta, int32_t algo,
+                              int32_t *out_grid, int32_t *out_claim, double *out_ms,
+                              void *stream) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (g && serving(*g)) return busy_error(__func__);
+  if (!g || alpha < 1 || beta < 1 || (algo != ABCORE_GCC && algo != ABCORE_GCC_PLUS)) {
+    set_error("abcore_autotune: null handle, threshold 0 or unknown algorithm");
+    return ABCORE_EINVAL;
+  }
+  CHK(hipSetDevice(g->device));
+  TRY(check_abort(*g));
+  int grid = 0, claim = 0;
+  double ms = 0;
+  TRY(tune_mapping(g, alpha, beta, algo, stream, &grid, &claim, &ms));
+  g->grid = grid;
+  g->claim = claim;
+  g->tuned = true;
+  tune_store(*g, 0, grid, claim, ms);
+  if (out_grid) *out_grid = grid;
+  if (out_claim) *out_claim = claim;
+  if (out_ms) *out_ms = ms;
+  return ABCORE_OK;
+}
+
+abcore_status abcore_tuned(abcore_graph h, int32_t kind, int32_t *out_grid, int32_t *out_claim,
+                           double *out_ms, int32_t *found) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (!g || !found || (kind != 0 && kind != 1)) {
+    set_error("abcore_tuned: null handle or output, or unknown kind");
+    return ABCORE_EINVAL;
+  }
+  TuneVal v{};
+  *found = tune_find(*g, kind, &v) ? 1 : 0;
+  if (*found) {
+    if (out_grid) *out_grid = v.grid;
+    if (out_claim) *out_claim = v.claim;
+    if (out_ms) *out_ms = v.ms;
+  }
+  return ABCORE_OK;
+}
+
+abcore_status abcore_tune_cache(const char *path, int32_t mode) {
+  if (mode == 2) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
+    return ABCORE_OK;
+  }
+  if (!path || (mode != 0 && mode != 1)) {
+    set_error("abcore_tune_cache: null path or unknown mode %d", mode);
+    return ABCORE_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  if (mode == 1) {
+    FILE *f = fopen(path, "w");
+    if (!f) {
+      set_error("abcore_tune_cache: cannot write %s", path);
+      return ABCORE_EINVAL;
+    }
+    for (const auto &kv : g_tune)
+      fprintf(f, "%s %d %d %d %d %d %d %.6f\n", kv.first.arch.c_str(), kv.first.cu,
+              kv.first.nlog, kv.first.elog, kv.first.kind, kv.second.grid, kv.second.claim,
+              kv.second.ms);
+    fclose(f);
+    return ABCORE_OK;
+  }
+  FILE *f = fopen(path, "r");
+  if (!f) {
+    set_error("abcore_tune_cache: cannot read %s", path);
+    return ABCORE_EINVAL;
+  }
+  char arch[64];
+  TuneKey k;
+  TuneVal v;
+  int read = 0;
+  while ((read = fscanf(f, "%63s %d %d %d %d %d %d %lf", arch, &k.cu, &k.nlog, &k.elog,
+                        &k.kind, &v.grid, &v.claim, &v.ms)) == 8) {
+    if (v.grid < 1 || v.grid > kMaxBlocks || v.claim < 1 || v.claim > kWave) continue;
+    k.arch = arch;
+    g_tune[k] = v;
+  }
+  fclose(f);
+  if (read != EOF) {
+    set_error("abcore_tune_cache: malformed line in %s", path);
+    return ABCORE_EINVAL;
+  }
+  return ABCORE_OK;
 }
 
 }  // extern "C"

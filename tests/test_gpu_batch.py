@@ -1,11 +1,15 @@
 """GPU parity of batched queries (abcore_compute_batch): every bitmask of a
 batch equals the oracle's independent peel of that query and the library's
 single-query call, bit for bit."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 import bigraph_gen
 import oracle
+from tests.digests import sha_array, sha_edges
 from tests.gpu_util import bits_np, ensure_built, say, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -146,7 +150,7 @@ def test_batch_edge_cases():
 def test_batch_workload_full_size():
     """The batch workload at full size: Chung-Lu |U| = 10M, |L| = 5M, 200M
     edges, 256 log-uniform pairs in [1,256]^2.  Every query equals the
-    single-query call; the oracle checks sampled queries."""
+    single-query call and the oracle's digest of its bitmask."""
     spec = bigraph_gen.CONFIGS[4]
     eu, ev = bigraph_gen.make_graph(spec)
     nU, nL = spec["n_upper"], spec["n_lower"]
@@ -158,10 +162,49 @@ def test_batch_workload_full_size():
     for i, (a, b) in enumerate(zip(alphas, betas)):
         one = bits_np(pkg.abcore_compute(g, a, b, pkg.ABCORE_GCC))[:words]
         assert np.array_equal(got[i, :words], one), f"query {i} ({a},{b})"
-    say("batch: full-size workload, singles equal; oracle samples")
-    ref = oracle.Graph(nU, nL, eu, ev)
-    del eu, ev
-    for i in (0, 97, 255):
-        want = oracle.pack(oracle.compute(ref, alphas[i], betas[i]))
-        assert np.array_equal(got[i, :words], want), f"oracle query {i}"
+    say("batch: full-size workload, singles equal; oracle digests")
+    # every query against the oracle's digest (tests/golden/c4_oracle.json,
+    # written offline by make_large_golden.py from the oracle alone)
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "c4_oracle.json")))
+    assert sha_edges(eu, ev) == gold["edge_sha256"]
+    assert [(q["alpha"], q["beta"]) for q in gold["queries"]] == list(zip(alphas, betas))
+    for i, q in enumerate(gold["queries"]):
+        assert sha_array(got[i, :words], "<u4") == q["bitmask_sha256"], f"oracle query {i}"
     g.destroy()
+
+
+def test_tuning_cache_and_batch_autotune(tmp_path):
+    """A batch on a shape the tuning cache has not seen tunes the mapping on
+    its median query and stores it; a second handle of that shape finds it
+    without tuning; the cache survives a save, clear and load; a single-query
+    tuning is taken by the next handle's first query; every result stays
+    equal to the oracle's."""
+    pkg.abcore_tune_cache(None, 2)
+    nU, nL, m = 40_000, 25_000, 500_000
+    eu, ev = bigraph_gen.chung_lu(nU, nL, m, 2.1, 2.1, 6000, 93)
+    ref = oracle.Graph(nU, nL, eu, ev)
+    g1 = pkg.abcore_build_csr(nU, nL, to_dev(eu), to_dev(ev))
+    assert pkg.abcore_tuned(g1, 1) is None
+    alphas, betas = _pairs(24, 1, 32, 1093)
+    _check_batch(g1, ref, alphas, betas, "tuned batch")
+    t = pkg.abcore_tuned(g1, 1)
+    assert t is not None and t[0] >= 1 and t[1] in (16, 32, 64) and t[2] > 0
+    g2 = pkg.abcore_build_csr(nU, nL, to_dev(eu), to_dev(ev))
+    assert pkg.abcore_tuned(g2, 1) == t
+    path = tmp_path / "tune.txt"
+    pkg.abcore_tune_cache(path, 1)
+    pkg.abcore_tune_cache(None, 2)
+    assert pkg.abcore_tuned(g2, 1) is None
+    pkg.abcore_tune_cache(path, 0)
+    got = pkg.abcore_tuned(g2, 1)
+    assert got[:2] == t[:2] and abs(got[2] - t[2]) < 1e-3
+    _check_batch(g2, ref, alphas, betas, "cached batch", singles=False)
+    grid, claim, ms = pkg.abcore_autotune(g1, 6, 9, pkg.ABCORE_GCC)
+    assert pkg.abcore_tuned(g2, 0)[:2] == (grid, claim)
+    for ab in [(6, 9), (2, 2), (12, 4)]:
+        want = oracle.pack(oracle.compute(ref, *ab))
+        got = bits_np(pkg.abcore_compute(g2, *ab, pkg.ABCORE_GCC))[: len(want)]
+        assert np.array_equal(got, want), ab
+    g1.destroy()
+    g2.destroy()
