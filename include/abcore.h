@@ -309,6 +309,13 @@ abcore_status abcore_submit(abcore_graph g, abcore_edge_update upd, uint32_t alp
 abcore_status abcore_poll(abcore_graph g, uint64_t ticket, int32_t *answer,
                           uint32_t *endpoint_bits, uint64_t *t_done_ns);
 
+/* Counters of the serving engine (HOST int64[count], count <= 6): windows
+ * run, requests answered, requests rejected, requests decided without a
+ * peel by stale core-number pruning, core-number snapshots taken, and their
+ * total wall time in microseconds.  Valid while serving and after
+ * abcore_serve_stop. */
+abcore_status abcore_serve_counters(abcore_graph g, int64_t *out, int32_t count);
+
 /* Waits for every admitted request to finish, stops the worker and frees the
  * working sets (unpolled results stay available).  counters (nullable, HOST
  * int64[3]): windows run, requests answered, requests rejected. */
@@ -347,6 +354,20 @@ abcore_status abcore_serve_stop(abcore_graph g, int64_t *counters);
  *                          2 = off.  Setting ABCORE_OPT_GRID or
  *                          ABCORE_OPT_CLAIM to a non-zero value fixes the
  *                          mapping (no cache lookups).
+ *   ABCORE_OPT_SERVE_PRUNE: stale core-number pruning of served requests
+ *                          (set before abcore_serve_start).  0 (default) =
+ *                          off; 1 = on, with the snapshot of the core numbers
+ *                          taken at serve start; k >= 2 = on, with a new
+ *                          snapshot after every k applied updates.  An edge
+ *                          update changes only the core numbers equal to
+ *                          min(core(u), core(v)), each by one (the k-core
+ *                          maintenance property; beyond the paper), so the
+ *                          engine keeps an interval per snapshot value that
+ *                          holds the current core numbers of its vertices.
+ *                          A request whose two endpoints Lemma 1 decides on
+ *                          those intervals (lower end >= max(alpha,beta): in;
+ *                          upper end < min(alpha,beta): out) is answered
+ *                          without a peel.  Results stay exact.
  *   ABCORE_OPT_SPIN_LIMIT: failure injection for tests: polls a waiting wave
  *                          of the asynchronous peel makes before it declares
  *                          a hang and aborts (0 = the default, 2^21, i.e.
@@ -371,7 +392,8 @@ enum {
   ABCORE_OPT_CLAIM = 6,
   ABCORE_OPT_RANK_ORDER = 7,
   ABCORE_OPT_SPIN_LIMIT = 8,
-  ABCORE_OPT_AUTOTUNE = 9
+  ABCORE_OPT_AUTOTUNE = 9,
+  ABCORE_OPT_SERVE_PRUNE = 10
 };
 abcore_status abcore_set_option(abcore_graph g, int32_t option, int64_t value);
 

@@ -28,6 +28,7 @@ ABCORE_OPT_CLAIM = 6
 ABCORE_OPT_RANK_ORDER = 7
 ABCORE_OPT_SPIN_LIMIT = 8
 ABCORE_OPT_AUTOTUNE = 9
+ABCORE_OPT_SERVE_PRUNE = 10
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOENT", 5: "EEXIST",
           6: "EBUSY", 7: "EAGAIN"}
@@ -102,6 +103,7 @@ def load():
         "abcore_submit": (i32, [vp, abcore_edge_update, u32, u32, P(ctypes.c_uint64)]),
         "abcore_poll": (i32, [vp, ctypes.c_uint64, P(i32), P(u32), P(ctypes.c_uint64)]),
         "abcore_serve_stop": (i32, [vp, P(i64)]),
+        "abcore_serve_counters": (i32, [vp, P(i64), i32]),
         "abcore_graph_report": (i32, [vp, P(abcore_report)]),
         "abcore_device_memory": (i32, [P(i64), P(i64), i32]),
         "abcore_tuned": (i32, [vp, i32, P(i32), P(i32), P(ctypes.c_double), P(i32)]),
@@ -349,6 +351,15 @@ def abcore_poll(g: Graph, ticket: int):
         _check(st)
     return {"status": STATUS[st], "answer": bool(ans.value), "bits": int(bits.value),
             "t_done_ns": int(t.value)}
+
+
+def abcore_serve_counters(g: Graph) -> dict:
+    """The serving engine's counters."""
+    c = (ctypes.c_int64 * 6)()
+    _check(load().abcore_serve_counters(g.handle, c, 6))
+    return {"windows": int(c[0]), "answered": int(c[1]), "rejected": int(c[2]),
+            "decided_without_peel": int(c[3]), "core_snapshots": int(c[4]),
+            "snapshot_ms": c[5] / 1e3}
 
 
 def abcore_serve_stop(g: Graph) -> dict:

@@ -154,6 +154,10 @@ struct Graph {
   int device = 0;
   char arch[64] = "";  // gcnArchName of the device (key of the tuning cache)
   int autotune = 1;    // ABCORE_OPT_AUTOTUNE: batches take a tuned mapping
+  // ABCORE_OPT_SERVE_PRUNE: 0 off; 1 stale core-number pruning of served
+  // requests from the snapshot taken at serve start; k >= 2 the same with a
+  // new snapshot after every k applied updates
+  int64_t serve_prune = 0;
   bool tuned = false;  // grid and claim chosen (by a tuner or by the caller)
   int32_t nU = 0, nL = 0;
   int64_t n = 0;
@@ -479,6 +483,9 @@ abcore_status scoped_set(Graph &g, int32_t vx, int32_t vy, int32_t thrU, int32_t
 // Largest deg0 over ids [lo, hi); set bits of a ceil(n/32)-word bitmask.
 // Synchronous.
 abcore_status max_degree(Graph &g, int64_t lo, int64_t hi, int32_t *out, hipStream_t s);
+// Core numbers (Definition 2) of the current graph into g.core (cached per
+// graph version).  Synchronous.
+abcore_status compute_core_numbers(Graph &g, hipStream_t s);
 abcore_status count_bits(Graph &g, const uint32_t *bits, int64_t *out, hipStream_t s);
 hipError_t launch_update_window(Graph &g, const int32_t *d_upd, int w, WindowRecord *d_rec,
                                 hipStream_t s);

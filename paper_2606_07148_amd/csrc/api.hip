@@ -116,7 +116,7 @@ abcore_status serve_submit(Graph &g, const abcore_edge_update &upd, int32_t thrU
                            uint64_t *ticket);
 abcore_status serve_poll(Graph &g, uint64_t ticket, int32_t *answer, uint32_t *bits,
                          uint64_t *t_done);
-void serve_counters(const Graph &g, int64_t *out);
+void serve_counters(const Graph &g, int64_t *out, int count);
 
 // Storage for edges inserted after the build: the per-vertex list heads and
 // room for at least min_cap pairs (doubling), with a deletion version per
@@ -447,6 +447,12 @@ abcore_status compute_core(Graph &g, hipStream_t s) {
   g.core_valid = true;
   return ABCORE_OK;
 }
+
+}  // namespace
+
+abcore_status compute_core_numbers(Graph &g, hipStream_t s) { return compute_core(g, s); }
+
+namespace {
 
 abcore_status compute_components(Graph &g, hipStream_t s) {
   if (g.comp_valid) return ABCORE_OK;
@@ -917,6 +923,9 @@ abcore_status abcore_set_option(abcore_graph h, int32_t option, int64_t value) {
     case ABCORE_OPT_GRID:
       g->grid = (int)std::min<int64_t>(value, kMaxBlocks);
       g->tuned = value != 0;  // the caller's choice stands
+      return ABCORE_OK;
+    case ABCORE_OPT_SERVE_PRUNE:
+      g->serve_prune = value;
       return ABCORE_OK;
     case ABCORE_OPT_AUTOTUNE:
       if (value > 2) {
@@ -1619,6 +1628,16 @@ abcore_status abcore_poll(abcore_graph h, uint64_t ticket, int32_t *answer,
   return serve_poll(*g, ticket, answer, endpoint_bits, t_done_ns);
 }
 
+abcore_status abcore_serve_counters(abcore_graph h, int64_t *out, int32_t count) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (!g || !out || count < 0) {
+    set_error("abcore_serve_counters: null handle or output");
+    return ABCORE_EINVAL;
+  }
+  serve_counters(*g, out, count);
+  return ABCORE_OK;
+}
+
 abcore_status abcore_serve_stop(abcore_graph h, int64_t *counters) {
   Graph *g = reinterpret_cast<Graph *>(h);
   if (!g) {
@@ -1626,7 +1645,7 @@ abcore_status abcore_serve_stop(abcore_graph h, int64_t *counters) {
     return ABCORE_EINVAL;
   }
   abcore_status st = serve_stop(*g);
-  if (counters) serve_counters(*g, counters);
+  if (counters) serve_counters(*g, counters, 3);
   return st;
 }
 

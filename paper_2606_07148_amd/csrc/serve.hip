@@ -88,8 +88,23 @@ struct Server {
   int32_t *d_upd = nullptr, *h_upd = nullptr;  // 3 * kWindowMax
   WindowRecord *d_rec = nullptr, *h_rec = nullptr;
   std::vector<hipEvent_t> last_scans;  // scans of the previous window
+  // Stale core-number pruning (Graph::serve_prune > 0): a snapshot of the
+  // core numbers (Definition 2) and, per snapshot value c, how far the core
+  // numbers of the vertices that had c may have moved since: they lie in
+  // [c - dlo[c], c + dhi[c]].  An edge update changes only the core numbers
+  // equal to K = min(core(u), core(v)), each by one (up on insertion, down
+  // on deletion) -- the k-core maintenance property -- so an update widens
+  // exactly the values whose interval meets K's possible range.  Lemma 1
+  // with these intervals decides a request without a peel when both
+  // endpoints are certainly in (lower end >= max(alpha,beta)) or certainly
+  // out (upper end < min(alpha,beta)).
+  std::vector<int32_t> core_h;
+  std::vector<int64_t> dlo, dhi;
+  int64_t since_refresh = 0;
   // counters
   int64_t windows = 0, served = 0, rejected = 0;
+  int64_t decided = 0, refreshes = 0;
+  double refresh_ms = 0;
 };
 
 namespace {
@@ -186,6 +201,59 @@ bool reap(Server &S, bool wait) {
     }                                                                    \
   } while (0)
 
+// A fresh snapshot of the core numbers of the current graph (every running
+// query drained first, so nothing else uses the device meanwhile).
+bool refresh_cores(Graph &g, Server &S) {
+  reap(S, true);
+  const auto t0 = std::chrono::steady_clock::now();
+  g.core_valid = false;
+  if (compute_core_numbers(g, S.main) != ABCORE_OK) {
+    S.fail = "serving: core numbers for pruning failed";
+    return false;
+  }
+  S.core_h.resize((size_t)g.n);
+  if (g.n > 0)
+    SCHK(hipMemcpyAsync(S.core_h.data(), g.core, sizeof(int32_t) * g.n, hipMemcpyDeviceToHost,
+                        S.main));
+  SCHK(hipStreamSynchronize(S.main));
+  S.dlo.assign((size_t)g.max_core + 2, 0);
+  S.dhi.assign((size_t)g.max_core + 2, 0);
+  S.since_refresh = 0;
+  S.refreshes += 1;
+  S.refresh_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                      .count();
+  return true;
+}
+
+// The interval that holds the current core number of vertex x.
+inline void core_interval(const Server &S, int32_t x, int64_t *lo, int64_t *hi) {
+  const int32_t c = S.core_h[(size_t)x];
+  *lo = (int64_t)c - S.dlo[(size_t)c];
+  *hi = (int64_t)c + S.dhi[(size_t)c];
+}
+
+// Widens the intervals an applied update (u, v, op) may have moved.
+void widen_for_update(Server &S, int32_t x, int32_t y, int32_t op) {
+  int64_t lx, hx, ly, hy;
+  core_interval(S, x, &lx, &hx);
+  core_interval(S, y, &ly, &hy);
+  const int64_t klo = std::min(lx, ly), khi = std::min(hx, hy);
+  const size_t nc = S.dlo.size();
+  for (size_t c = 0; c < nc; ++c) {
+    const int64_t lo = (int64_t)c - S.dlo[c], hi = (int64_t)c + S.dhi[c];
+    if (hi >= klo && lo <= khi) (op > 0 ? S.dhi[c] : S.dlo[c]) += 1;
+  }
+}
+
+// Lemma 1 on the intervals: 1 certainly in, 0 certainly out, -1 undecided.
+inline int classify(const Server &S, int32_t x, int32_t dl, int32_t dq) {
+  int64_t lo, hi;
+  core_interval(S, x, &lo, &hi);
+  if (lo >= dq) return 1;
+  if (hi < dl) return 0;
+  return -1;
+}
+
 // Applies one window of updates and launches its queries.
 bool run_window(Graph &g, Server &S, const std::vector<Request> &win) {
   const int w = (int)win.size();
@@ -253,6 +321,25 @@ bool run_window(Graph &g, Server &S, const std::vector<Request> &win) {
       finish(S, win[i].ticket, res);
       continue;
     }
+    if (!S.core_h.empty()) {
+      // the snapshot's intervals, widened by this update and those before
+      const int32_t x = win[i].u, y = g.nU + win[i].v;
+      widen_for_update(S, x, y, win[i].op);
+      S.since_refresh += 1;
+      const int32_t dl = std::min(win[i].thrU, win[i].thrL);
+      const int32_t dq = std::max(win[i].thrU, win[i].thrL);
+      const int cu = classify(S, x, dl, dq), cv = classify(S, y, dl, dq);
+      if (cu >= 0 && cv >= 0) {
+        Result res{};
+        res.status = ABCORE_OK;
+        res.bits = (uint32_t)cu | ((uint32_t)cv << 1);
+        res.answer = res.bits == 3u ? 1 : 0;
+        res.t_done = now_ns();
+        S.decided += 1;
+        finish(S, win[i].ticket, res);
+        continue;
+      }
+    }
     while (S.slots[next_slot].busy) ++next_slot;  // the window fits the free slots
     Slot &s = S.slots[next_slot];
     // the later updates of the window, undone for this query's view
@@ -311,6 +398,8 @@ bool run_window(Graph &g, Server &S, const std::vector<Request> &win) {
     s.req = win[i];
     s.busy = true;
   }
+  if (!S.core_h.empty() && g.serve_prune >= 2 && S.since_refresh >= g.serve_prune)
+    return refresh_cores(g, S);
   return true;
 }
 
@@ -457,6 +546,14 @@ abcore_status serve_start(Graph &g, int64_t max_inflight, int32_t slots, int32_t
     free_server_device(S);
     return st;
   }
+  S.core_h.clear();
+  S.decided = S.refreshes = 0;
+  S.refresh_ms = 0;
+  if (g.serve_prune > 0 && !refresh_cores(g, S)) {
+    free_server_device(S);
+    set_error("%s", S.fail.c_str());
+    return ABCORE_EDEVICE;
+  }
   S.running = true;
   try {
     S.worker = std::thread(worker_main, &g);
@@ -520,11 +617,12 @@ abcore_status serve_poll(Graph &g, uint64_t ticket, int32_t *answer, uint32_t *b
   return (abcore_status)r.status;
 }
 
-void serve_counters(const Graph &g, int64_t *out) {
+void serve_counters(const Graph &g, int64_t *out, int count) {
   const Server *S = g.server;
-  out[0] = S ? S->windows : 0;
-  out[1] = S ? S->served : 0;
-  out[2] = S ? S->rejected : 0;
+  const int64_t v[6] = {S ? S->windows : 0,  S ? S->served : 0,    S ? S->rejected : 0,
+                        S ? S->decided : 0,  S ? S->refreshes : 0,
+                        S ? (int64_t)(S->refresh_ms * 1000.0) : 0};
+  for (int i = 0; i < count && i < 6; ++i) out[i] = v[i];
 }
 
 }  // namespace abc

@@ -190,3 +190,44 @@ def test_served_versions_of_vertex_zero_edges(pull):
     assert counters["windows"] < len(reqs)  # several requests shared windows
     g.destroy()
     g2.destroy()
+
+
+@pytest.mark.parametrize("prune,slots,window", [(1, 4, 16), (7, 3, 5), (64, 8, 64), (2, 1, 1)])
+def test_served_stream_with_stale_core_pruning(prune, slots, window):
+    """Stale core-number pruning (ABCORE_OPT_SERVE_PRUNE): requests decided
+    from the snapshot's intervals skip the peel, every answer and endpoint
+    bit still equals the oracle's recomputation and the one-at-a-time
+    result, snapshots are retaken every `prune` updates (prune >= 2), and
+    the final graph equals the one-at-a-time graph."""
+    spec = dict(kind="chung_lu", n_upper=3000, n_lower=2000, m=12_000, gamma_upper=2.1,
+                gamma_lower=2.1, cap=400, seed=502)
+    nU, nL = spec["n_upper"], spec["n_lower"]
+    eu, ev = bigraph_gen.make_graph(spec)
+    ups = _with_invalid(bigraph_gen.update_stream(spec, eu, ev, 300, 1502, qlo=1, qhi=12))
+    g = pkg.abcore_build_csr(nU, nL, to_dev(eu), to_dev(ev))
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_SERVE_PRUNE, prune)
+    pkg.abcore_serve_start(g, 64, slots, window)
+    served = serve_all(g, ups, 64)
+    c = pkg.abcore_serve_counters(g)
+    pkg.abcore_serve_stop(g)
+    say(f"serve prune {prune}: decided {c['decided_without_peel']} of {c['answered']}, "
+        f"snapshots {c['core_snapshots']} ({c['snapshot_ms']:.1f} ms)")
+    assert c["decided_without_peel"] > 0
+    valid = c["answered"]
+    if prune >= 2:
+        # a snapshot is retaken at the end of the window in which the count
+        # of updates since the last one reaches `prune`
+        again = c["core_snapshots"] - 1
+        assert valid // (prune + window - 1) - 1 <= again <= valid // prune
+    else:
+        assert c["core_snapshots"] == 1
+    want = oracle.gfq_stream(nU, nL, eu, ev, ups)
+    _compare(served, want, "oracle")
+    g2, alone = _sequential(nU, nL, eu, ev, ups)
+    _compare(served, alone, "alone")
+    o1, c1 = pkg.abcore_export_csr(g)
+    o2, c2 = pkg.abcore_export_csr(g2)
+    assert np.array_equal(o1.cpu().numpy(), o2.cpu().numpy())
+    assert np.array_equal(c1.cpu().numpy(), c2.cpu().numpy())
+    g.destroy()
+    g2.destroy()

@@ -585,3 +585,36 @@ def test_default_query_on_worked_example():
     assert oracle.alpha_offset(g, 3) == 4
     assert oracle.alpha_offset(g, 4) == 0
     assert oracle.default_query(g) == (1, 2)
+
+
+def test_core_maintenance_property_on_streams():
+    """The fact behind stale core-number pruning in serving (beyond the
+    paper; the k-core maintenance property of Li, Yu and Mao, and Sariyuce et
+    al.): inserting or deleting edge (u, v) changes only core numbers equal
+    to K = min(core(u), core(v)) before the update, each by exactly one, up
+    for an insertion and down for a deletion.  Checked with the oracle's
+    core numbers (Definition 2) before and after every update of streams on
+    power-law and uniform graphs."""
+    for spec in (bigraph_gen.scaled(2, 0.002), bigraph_gen.CONFIGS[1]):
+        nU, nL = spec["n_upper"], spec["n_lower"]
+        eu, ev = bigraph_gen.make_graph(spec)
+        ups = bigraph_gen.update_stream(spec, eu, ev, 60, 777)
+        present = set(zip(eu.tolist(), ev.tolist()))
+        g = oracle.Graph(nU, nL, eu, ev)
+        before = oracle.core_numbers(g)
+        changed_any = 0
+        for i in range(len(ups["u"])):
+            u, v, op = int(ups["u"][i]), int(ups["v"][i]), int(ups["op"][i])
+            if (op > 0) == ((u, v) in present):
+                continue  # rejected update
+            k = min(int(before[u]), int(before[nU + v]))
+            (present.add if op > 0 else present.discard)((u, v))
+            pe = np.array(sorted(present), np.int32)
+            after = oracle.core_numbers(oracle.Graph(nU, nL, pe[:, 0], pe[:, 1]))
+            diff = after.astype(np.int64) - before
+            moved = np.flatnonzero(diff)
+            assert (before[moved] == k).all(), (i, k)
+            assert (diff[moved] == (1 if op > 0 else -1)).all(), i
+            changed_any += len(moved)
+            before = after
+        assert changed_any > 0
