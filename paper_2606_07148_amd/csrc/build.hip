@@ -4,7 +4,7 @@
 // directly, a second sort on (v*nU + u) gives the lower rows.  Both sorts use
 // rocPRIM's device radix sort through hipCUB; the build is preprocessing and
 // is not part of the timed peel.
-#include <hipcub/hipcub.hpp>
+#include "prim.h"
 
 #include <algorithm>
 
@@ -223,13 +223,13 @@ abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, i
     make_keys_kernel<<<grid, 256, 0, s>>>(eu, ev, m, g.nL, k0);
     BCHK(hipGetLastError());
     // temp storage large enough for the sort and the unique selection
-    BCHK(hipcub::DeviceRadixSort::SortKeys(nullptr, need, k0, k1, (int)m, 0, ubits, s));
+    BCHK(prim::sort_keys(nullptr, need, k0, k1, (size_t)m, 0, ubits, s));
     temp_bytes = std::max(temp_bytes, need);
-    BCHK(hipcub::DeviceSelect::Unique(nullptr, need, k1, k0, d_nsel, (int)m, s));
+    BCHK(prim::unique(nullptr, need, k1, k0, d_nsel, (size_t)m, s));
     temp_bytes = std::max(temp_bytes, need);
     BCHK(dev_malloc(&temp, std::max<size_t>(temp_bytes, 16)));
-    BCHK(hipcub::DeviceRadixSort::SortKeys(temp, temp_bytes, k0, k1, (int)m, 0, ubits, s));
-    BCHK(hipcub::DeviceSelect::Unique(temp, temp_bytes, k1, k0, d_nsel, (int)m, s));
+    BCHK(prim::sort_keys(temp, temp_bytes, k0, k1, (size_t)m, 0, ubits, s));
+    BCHK(prim::unique(temp, temp_bytes, k1, k0, d_nsel, (size_t)m, s));
     BCHK(hipMemcpyAsync(&h_nsel, d_nsel, sizeof(int), hipMemcpyDeviceToHost, s));
     BCHK(hipStreamSynchronize(s));
     md = h_nsel;
@@ -241,7 +241,7 @@ abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, i
     const int gridm = std::max(1, std::min(g.cu_count * 8, (int)((md + 255) / 256)));
     upper_rows_kernel<<<gridm, 256, 0, s>>>(k0, md, g.nU, g.nL, g.cols, g.deg0, k1);
     BCHK(hipGetLastError());
-    BCHK(hipcub::DeviceRadixSort::SortKeys(temp, temp_bytes, k1, k0, (int)md, 0, lbits, s));
+    BCHK(prim::sort_keys(temp, temp_bytes, k1, k0, (size_t)md, 0, lbits, s));
     lower_rows_kernel<<<gridm, 256, 0, s>>>(k0, md, g.nU, g.cols, g.deg0);
     BCHK(hipGetLastError());
   }
@@ -251,14 +251,14 @@ abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, i
     widen_kernel<<<gridn, 256, 0, s>>>(g.deg0, g.n, deg64);
     BCHK(hipGetLastError());
     need = 0;
-    BCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, deg64, g.off, (int)(g.n + 1), s));
+    BCHK(prim::exclusive_sum(nullptr, need, deg64, g.off, (size_t)(g.n + 1), s));
     if (need > temp_bytes) {
       BCHK(dev_free(temp));
       temp = nullptr;
       temp_bytes = need;
       BCHK(dev_malloc(&temp, temp_bytes));
     }
-    BCHK(hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, deg64, g.off, (int)(g.n + 1), s));
+    BCHK(prim::exclusive_sum(temp, temp_bytes, deg64, g.off, (size_t)(g.n + 1), s));
   }
   BCHK(hipStreamSynchronize(s));
 done:
@@ -295,10 +295,10 @@ abcore_status build_pieces(Graph &g, hipStream_t s) {
   PCHK(dev_malloc(&hfirst, sizeof(int64_t) * (g.n + 1)));
   count_pieces_kernel<<<grid, 256, 0, s>>>(g.off, g.n, np, hv);
   PCHK(hipGetLastError());
-  PCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, temp_bytes, np, first, (int)(g.n + 1), s));
+  PCHK(prim::exclusive_sum(nullptr, temp_bytes, np, first, (size_t)(g.n + 1), s));
   PCHK(dev_malloc(&temp, std::max<size_t>(temp_bytes, 16)));
-  PCHK(hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, np, first, (int)(g.n + 1), s));
-  PCHK(hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, hv, hfirst, (int)(g.n + 1), s));
+  PCHK(prim::exclusive_sum(temp, temp_bytes, np, first, (size_t)(g.n + 1), s));
+  PCHK(prim::exclusive_sum(temp, temp_bytes, hv, hfirst, (size_t)(g.n + 1), s));
   PCHK(hipMemcpyAsync(&h_tot[0], first + g.n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   PCHK(hipMemcpyAsync(&h_tot[1], first + g.nU, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   PCHK(hipMemcpyAsync(&h_tot[2], hfirst + g.n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -321,7 +321,7 @@ abcore_status build_pieces(Graph &g, hipStream_t s) {
   PCHK(dev_malloc(&g.pull_bounds, sizeof(int32_t) * 2 * (g.pull_bounds_grid + 1)));
   row_weight_kernel<<<grid, 256, 0, s>>>(g.off, g.n, np);
   PCHK(hipGetLastError());
-  PCHK(hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, np, hv, (int)(g.n + 1), s));
+  PCHK(prim::exclusive_sum(temp, temp_bytes, np, hv, (size_t)(g.n + 1), s));
   pull_bounds_kernel<<<(2 * (g.pull_bounds_grid + 1) + 255) / 256, 256, 0, s>>>(
       hv, g.nU, g.n, g.pull_bounds_grid, g.pull_bounds);
   PCHK(hipGetLastError());
@@ -438,12 +438,12 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
     if (fail(dev_malloc(&k0, sizeof(uint64_t) * std::max<int64_t>(items, 2 * (g.n + 1))))) break;
     if (fail(dev_malloc(&k1, sizeof(uint64_t) * items))) break;
     // temporary storage for the largest sort, and the offsets' scan
-    if (fail(hipcub::DeviceRadixSort::SortKeys(nullptr, need, k0, k1, (int)items, 0, 64, s)))
+    if (fail(prim::sort_keys(nullptr, need, k0, k1, (size_t)items, 0, 64, s)))
       break;
     temp_bytes = std::max<size_t>(need, 16);
     need = 0;
-    if (fail(hipcub::DeviceScan::ExclusiveSum(nullptr, need, reinterpret_cast<int64_t *>(k0),
-                                              g.roff, (int)(g.n + 1), s)))
+    if (fail(prim::exclusive_sum(nullptr, need, reinterpret_cast<int64_t *>(k0),
+                                              g.roff, (size_t)(g.n + 1), s)))
       break;
     temp_bytes = std::max(temp_bytes, need);
     if (fail(dev_malloc(&temp, temp_bytes))) break;
@@ -454,7 +454,7 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
       rank_keys_kernel<<<grid, 256, 0, s>>>(g.off, lo, hi, k0);
       if (fail(hipGetLastError())) break;
       size_t tb = temp_bytes;
-      if (fail(hipcub::DeviceRadixSort::SortKeys(temp, tb, k0, k1, (int)(hi - lo), 0, 64, s)))
+      if (fail(prim::sort_keys(temp, tb, k0, k1, (size_t)(hi - lo), 0, 64, s)))
         break;
       // (k0 holds no keys any more past the sort: its tail collects the
       // degrees by rank, the offsets' scan input)
@@ -467,13 +467,13 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
       int64_t *rdeg = reinterpret_cast<int64_t *>(k0) + g.n + 1;
       if (fail(hipMemsetAsync(rdeg + g.n, 0, sizeof(int64_t), s))) break;
       size_t tb = temp_bytes;
-      if (fail(hipcub::DeviceScan::ExclusiveSum(temp, tb, rdeg, g.roff, (int)(g.n + 1), s))) break;
+      if (fail(prim::exclusive_sum(temp, tb, rdeg, g.roff, (size_t)(g.n + 1), s))) break;
     }
     if (ent > 0) {
       entry_keys_kernel<<<grid, 256, 0, s>>>(g.off, g.cols, g.rank, g.n, g.nU, rbits, k0);
       if (fail(hipGetLastError())) break;
       size_t tb = temp_bytes;
-      if (fail(hipcub::DeviceRadixSort::SortKeys(temp, tb, k0, k1, (int)ent, 0, rbits + xbits, s)))
+      if (fail(prim::sort_keys(temp, tb, k0, k1, (size_t)ent, 0, rbits + xbits, s)))
         break;
       entry_unkey_kernel<<<grid, 256, 0, s>>>(k1, ent, rbits, g.nU, g.rcols);
       if (fail(hipGetLastError())) break;
@@ -491,9 +491,9 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
         count_pieces_kernel<<<grid, 256, 0, s>>>(g.roff, g.n, np, hv);
         if (fail(hipGetLastError())) break;
         size_t tb = temp_bytes;
-        if (fail(hipcub::DeviceScan::ExclusiveSum(temp, tb, np, fcopy, (int)(g.n + 1), s))) break;
+        if (fail(prim::exclusive_sum(temp, tb, np, fcopy, (size_t)(g.n + 1), s))) break;
         tb = temp_bytes;
-        if (fail(hipcub::DeviceScan::ExclusiveSum(temp, tb, hv, hfirst, (int)(g.n + 1), s))) break;
+        if (fail(prim::exclusive_sum(temp, tb, hv, hfirst, (size_t)(g.n + 1), s))) break;
         if (fail(dev_malloc(&g.rp_row, sizeof(int32_t) * std::max<int64_t>(g.npieces, 1)))) break;
         if (fail(dev_malloc(&g.rp_start, sizeof(int64_t) * std::max<int64_t>(g.npieces, 1))))
           break;

@@ -1,6 +1,6 @@
 // On-the-fly query support (Sec. V, GFQ): connected components by parallel
 // union-find, edge updates on the resident graph, and the scoped answer.
-#include <hipcub/hipcub.hpp>
+#include "prim.h"
 
 #include <algorithm>
 
@@ -472,10 +472,10 @@ hipError_t launch_export(Graph &g, int64_t *out_off, int32_t *out_cols, hipStrea
   hipError_t e = dev_malloc(&tmp64, sizeof(int64_t) * (g.n + 1));
   if (e != hipSuccess) return e;
   widen_deg_kernel<<<small_grid(g, g.n + 1), 256, 0, s>>>(g.deg0, g.n, tmp64);
-  e = hipcub::DeviceScan::ExclusiveSum(nullptr, temp_bytes, tmp64, out_off, (int)(g.n + 1), s);
+  e = prim::exclusive_sum(nullptr, temp_bytes, tmp64, out_off, (size_t)(g.n + 1), s);
   if (e == hipSuccess) e = dev_malloc(&temp, std::max<size_t>(temp_bytes, 16));
   if (e == hipSuccess)
-    e = hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, tmp64, out_off, (int)(g.n + 1), s);
+    e = prim::exclusive_sum(temp, temp_bytes, tmp64, out_off, (size_t)(g.n + 1), s);
   if (e == hipSuccess && out_cols != nullptr) {
     const int32_t *head = g.delta.count > 0 ? g.delta.head : nullptr;
     export_rows_kernel<<<small_grid(g, g.n), 256, 0, s>>>(g.off, g.cols, head, g.delta.next,
