@@ -103,6 +103,11 @@ typedef struct {
   int64_t graph_bytes;  /* off, cols, deg0, row pieces */
   int64_t ranks_bytes;  /* degree-rank copy: ranks, relabelled CSR, pieces, degree slots */
   int64_t queue_bytes;  /* frontier sub-queues of the handle's working set */
+  /* last core decomposition's h-index phase (zeros if it did not run):
+   * switch level k0, vertices and adjacency entries of the k0-core, sweeps */
+  int64_t core_top[4];
+  double core_levels_ms;  /* levels peeled before the switch (wall clock) */
+  double core_top_ms;     /* the h-index phase (wall clock) */
 } abcore_report;
 
 abcore_status abcore_graph_report(abcore_graph g, abcore_report *out);
@@ -368,6 +373,15 @@ abcore_status abcore_serve_stop(abcore_graph g, int64_t *counters);
  *                          those intervals (lower end >= max(alpha,beta): in;
  *                          upper end < min(alpha,beta): out) is answered
  *                          without a peel.  Results stay exact.
+ *   ABCORE_OPT_KCORE_SWITCH: core numbers (default peel mode): levels are
+ *                          peeled one by one until at most `value` vertices
+ *                          are live (0 = 131072; checked between batches of
+ *                          levels); the rest -- the k0-core, whose core
+ *                          numbers in G are its own -- is finished by the
+ *                          h-index fixpoint (iterate est(x) <- h-index of the
+ *                          neighbours' est, from the degrees, until nothing
+ *                          changes).  1 = levels only.  Results are
+ *                          identical either way.
  *   ABCORE_OPT_SPIN_LIMIT: failure injection for tests: polls a waiting wave
  *                          of the asynchronous peel makes before it declares
  *                          a hang and aborts (0 = the default, 2^21, i.e.
@@ -393,7 +407,8 @@ enum {
   ABCORE_OPT_RANK_ORDER = 7,
   ABCORE_OPT_SPIN_LIMIT = 8,
   ABCORE_OPT_AUTOTUNE = 9,
-  ABCORE_OPT_SERVE_PRUNE = 10
+  ABCORE_OPT_SERVE_PRUNE = 10,
+  ABCORE_OPT_KCORE_SWITCH = 11
 };
 abcore_status abcore_set_option(abcore_graph g, int32_t option, int64_t value);
 

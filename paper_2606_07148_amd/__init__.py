@@ -29,6 +29,7 @@ ABCORE_OPT_RANK_ORDER = 7
 ABCORE_OPT_SPIN_LIMIT = 8
 ABCORE_OPT_AUTOTUNE = 9
 ABCORE_OPT_SERVE_PRUNE = 10
+ABCORE_OPT_KCORE_SWITCH = 11
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOENT", 5: "EEXIST",
           6: "EBUSY", 7: "EAGAIN"}
@@ -55,10 +56,13 @@ class abcore_report(ctypes.Structure):
     _fields_ = [("build_ms", ctypes.c_double), ("csr_ms", ctypes.c_double),
                 ("pieces_ms", ctypes.c_double), ("ranks_ms", ctypes.c_double),
                 ("graph_bytes", ctypes.c_int64), ("ranks_bytes", ctypes.c_int64),
-                ("queue_bytes", ctypes.c_int64)]
+                ("queue_bytes", ctypes.c_int64), ("core_top", ctypes.c_int64 * 4),
+                ("core_levels_ms", ctypes.c_double), ("core_top_ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "core_top"}
+        d["core_top"] = dict(zip(("k0", "vertices", "entries", "sweeps"), list(self.core_top)))
+        return d
 
 
 class abcore_edge_update(ctypes.Structure):

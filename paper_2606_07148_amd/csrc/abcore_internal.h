@@ -48,6 +48,10 @@ constexpr int32_t kDegOut = -1;
 // hang (each poll takes at least a few microseconds, so this is seconds: far
 // beyond any legitimate wait of a peel).  ABCORE_OPT_SPIN_LIMIT lowers it.
 constexpr uint32_t kAsyncSpinLimit = 1u << 21;
+// Live vertices at or below which the core decomposition leaves the level
+// peel for the h-index fixpoint (measured best at about 5e4 to 1.6e5 live
+// vertices on the 2e7- and 1e9-edge power-law graphs).
+constexpr int64_t kKcoreSwitch = 1 << 17;
 // Largest usable threshold: kDegIn must stay above every threshold.
 constexpr int32_t kMaxThreshold = 0x7FFFFFFE;
 // Degree of a removed split row once a consumer has claimed it (far below
@@ -158,6 +162,14 @@ struct Graph {
   // requests from the snapshot taken at serve start; k >= 2 the same with a
   // new snapshot after every k applied updates
   int64_t serve_prune = 0;
+  // ABCORE_OPT_KCORE_SWITCH: core numbers finish by the h-index fixpoint
+  // once at most kcore_switch vertices are live (checked between batches of
+  // levels)
+  int64_t kcore_switch = kKcoreSwitch;
+  bool kcore_top_used = false;  // the last core decomposition used it
+  // its switch level, vertices, adjacency entries, sweeps and phase times
+  int64_t top_stats[4] = {0, 0, 0, 0};
+  double top_ms[2] = {0, 0};  // levels before the switch, the h-index phase
   bool tuned = false;  // grid and claim chosen (by a tuner or by the caller)
   int32_t nU = 0, nL = 0;
   int64_t n = 0;
@@ -486,6 +498,11 @@ abcore_status max_degree(Graph &g, int64_t lo, int64_t hi, int32_t *out, hipStre
 // Core numbers (Definition 2) of the current graph into g.core (cached per
 // graph version).  Synchronous.
 abcore_status compute_core_numbers(Graph &g, hipStream_t s);
+// The core numbers of the live vertices of an alive list (cnt entries,
+// those with core < 0) once every vertex of core < k0 has its value, by the
+// h-index fixpoint; *finished false if it needed more than max_sweeps.
+abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
+                        int max_sweeps, bool *finished, int32_t *top_max, hipStream_t s);
 abcore_status count_bits(Graph &g, const uint32_t *bits, int64_t *out, hipStream_t s);
 hipError_t launch_update_window(Graph &g, const int32_t *d_upd, int w, WindowRecord *d_rec,
                                 hipStream_t s);

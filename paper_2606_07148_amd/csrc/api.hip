@@ -403,16 +403,40 @@ abcore_status compute_core(Graph &g, hipStream_t s) {
   TRY(ensure(&g.list, g.n));
   TRY(ensure(&g.list2, g.n));
   CHK(launch_kcore_init(g, s));
+  g.kcore_top_used = false;
+  for (int64_t &v : g.top_stats) v = 0;
+  const auto t_levels = std::chrono::steady_clock::now();
   if (g.peel_mode == 3) {
     // levels of a scan and an asynchronous peel, in growing batches between
     // checks; every level either removes a vertex or jumps to one that does
     const int64_t max_levels = 2 * g.n + 8;
     int batch = 8;
     int64_t done = 0;
+    bool top_tried = false;
     for (; done < max_levels; done += batch) {
       CHK(launch_kcore_levels(g, batch, s));
       TRY(read_state(g, s));
       if (g.h_state->done) break;
+      // the deep levels by the h-index fixpoint once the live part (the
+      // next_k-core) is small: at most kcore_switch vertices
+      const int64_t alive = g.h_state->alive_cur;
+      if (!top_tried && g.h_state->next_k >= 1 && alive <= g.kcore_switch) {
+        top_tried = true;
+        bool fin = false;
+        int32_t tmax = 0;
+        const int32_t *L = g.h_state->alive_sel ? g.list2 : g.list;
+        const auto t_top = std::chrono::steady_clock::now();
+        g.top_ms[0] = std::chrono::duration<double, std::milli>(t_top - t_levels).count();
+        TRY(kcore_top(g, L, alive, g.h_state->next_k, 4096, &fin, &tmax, s));
+        g.top_ms[1] = std::chrono::duration<double, std::milli>(
+                          std::chrono::steady_clock::now() - t_top).count();
+        if (fin) {
+          g.max_core = std::max(g.h_state->max_core, tmax);
+          g.core_valid = true;
+          g.kcore_top_used = true;
+          return ABCORE_OK;
+        }
+      }
       batch = std::min(batch * 2, 256);
     }
     if (done >= max_levels) {
@@ -861,6 +885,9 @@ abcore_status abcore_graph_report(abcore_graph h, abcore_report *out) {
                                (g->rp_row != nullptr ? (4 + 8) * np + 4 * n : 0) +
                                (g->rdeg != nullptr ? 4 * ((int64_t)g->rdeg_mask + 1) : 0);
   out->queue_bytes = 4 * (int64_t)kSub * g->qcap;
+  for (int i = 0; i < 4; ++i) out->core_top[i] = g->kcore_top_used ? g->top_stats[i] : 0;
+  out->core_levels_ms = g->kcore_top_used ? g->top_ms[0] : 0.0;
+  out->core_top_ms = g->kcore_top_used ? g->top_ms[1] : 0.0;
   return ABCORE_OK;
 }
 
@@ -923,6 +950,10 @@ abcore_status abcore_set_option(abcore_graph h, int32_t option, int64_t value) {
     case ABCORE_OPT_GRID:
       g->grid = (int)std::min<int64_t>(value, kMaxBlocks);
       g->tuned = value != 0;  // the caller's choice stands
+      return ABCORE_OK;
+    case ABCORE_OPT_KCORE_SWITCH:
+      g->kcore_switch = value == 0 ? kKcoreSwitch : value;
+      g->core_valid = false;
       return ABCORE_OK;
     case ABCORE_OPT_SERVE_PRUNE:
       g->serve_prune = value;

@@ -428,3 +428,39 @@ def test_config2_full_size():
         assert np.array_equal(bits_np(got), want), (a, b)
         assert sr["removed"] == sv["removed"], (a, b)
     g.destroy()
+
+
+@pytest.mark.parametrize("switch", [0, 1, 2, 8, 1 << 20])
+def test_core_numbers_level_and_hindex_phases(switch):
+    """Core numbers (Definition 2) equal the oracle's Batagelj-Zaversnik
+    values whichever share of the levels the h-index fixpoint finishes: the
+    default switch, levels only (1, 2, 8 live vertices: never reached before
+    the end), and from the first check (2^20 live vertices), on two
+    power-law graphs and the uniform one, and after updates (tombstones and
+    inserted edges in the rows)."""
+    specs = [bigraph_gen.scaled(2, 0.05), bigraph_gen.scaled(3, 1 / 400), bigraph_gen.CONFIGS[1]]
+    for spec in specs:
+        nU, nL = spec["n_upper"], spec["n_lower"]
+        eu, ev = bigraph_gen.make_graph(spec)
+        g, ref = _make(nU, nL, eu, ev)
+        pkg.abcore_set_option(g, pkg.ABCORE_OPT_KCORE_SWITCH, switch)
+        core, mx = pkg.abcore_core_numbers(g)
+        want = oracle.core_numbers(ref)
+        assert np.array_equal(core.cpu().numpy(), want), (spec, switch)
+        assert mx == int(want.max())
+        # after updates: the rows hold tombstones and inserted edges
+        ups = bigraph_gen.update_stream(spec, eu, ev, 30, 2024)
+        present = set(zip(eu.tolist(), ev.tolist()))
+        for i in range(len(ups["u"])):
+            u, v, op = int(ups["u"][i]), int(ups["v"][i]), int(ups["op"][i])
+            if (op > 0) == ((u, v) in present):
+                continue
+            pkg.abcore_query(g, u, v, op, 2, 2)
+            (present.add if op > 0 else present.discard)((u, v))
+        pe = np.array(sorted(present), np.int32)
+        ref2 = oracle.Graph(nU, nL, pe[:, 0], pe[:, 1])
+        core, mx = pkg.abcore_core_numbers(g)
+        want = oracle.core_numbers(ref2)
+        assert np.array_equal(core.cpu().numpy(), want), (spec, switch, "after updates")
+        say(f"core numbers switch {switch}: n={nU + nL}, max {mx}")
+        g.destroy()
