@@ -220,14 +220,14 @@ def bench_serve(args, pkg, torch, np, bigraph_gen) -> dict:
           file=sys.stderr, flush=True)
     handles = []
     pkg.abcore_device_memory(reset_peak=True)
-    for _ in range(2):
+    for _ in range(3 if args.serve_prune else 2):
         deu = torch.from_numpy(eu).cuda()
         dev = torch.from_numpy(ev).cuda()
         handles.append(pkg.abcore_build_csr(nU, nL, deu, dev))
         del deu, dev
     del eu, ev
     torch.cuda.empty_cache()
-    g_seq, g_srv = handles
+    g_seq, g_srv = handles[:2]
     pkg.abcore_components(g_seq)
     total = len(ups["u"])
     # sequential: one abcore_query at a time
@@ -275,6 +275,31 @@ def bench_serve(args, pkg, torch, np, bigraph_gen) -> dict:
         lo = hi
     _, peak = pkg.abcore_device_memory()
     counters = pkg.abcore_serve_stop(g_srv)
+    pruned = None
+    if args.serve_prune:
+        # the same requests, closed loop, with stale core-number pruning: a
+        # snapshot of the core numbers at start and after every
+        # serve_prune applied updates (its time included)
+        g_pr = handles[2]
+        pkg.abcore_set_option(g_pr, pkg.ABCORE_OPT_SERVE_PRUNE, args.serve_prune)
+        if args.serve_pull:
+            pkg.abcore_set_option(g_pr, pkg.ABCORE_OPT_PULL, args.serve_pull)
+        t0 = time.perf_counter()
+        pkg.abcore_serve_start(g_pr, args.serve_inflight, args.serve_slots, 0)
+        start_s = time.perf_counter() - t0
+        res, t_sub, wall = _drive(pkg, g_pr, ups, 0, total)
+        pc = pkg.abcore_serve_counters(g_pr)
+        pkg.abcore_serve_stop(g_pr)
+        lat = [(r["t_done_ns"] - s0) / 1e6 for r, s0 in zip(res, t_sub)]
+        pmis = sum(1 for r, w in zip(res, seq) if r["status"] != w[0] or
+                   (w[0] == "OK" and (r["answer"], r["bits"]) != (w[1], w[2])))
+        pruned = {"requests": total, "refresh_every": args.serve_prune,
+                  "queries_per_s": total / wall, "speedup_vs_sequential": (total / wall) / seq_qps,
+                  "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
+                  "decided_without_peel": pc["decided_without_peel"],
+                  "core_snapshots": pc["core_snapshots"], "snapshot_ms": pc["snapshot_ms"],
+                  "first_snapshot_in_serve_start_s": start_s,
+                  "answers_equal_sequential": pmis == 0, "mismatches": pmis}
     n_cmp = len(served)
     mismatch = 0
     for r, w in zip(served, seq[:n_cmp]):
@@ -298,7 +323,9 @@ def bench_serve(args, pkg, torch, np, bigraph_gen) -> dict:
         "max_inflight": args.serve_inflight,
         "windows": counters["windows"],
         "device_memory_library_peak_bytes_two_handles": peak,
-        "answers_equal_sequential": mismatch == 0,
+        "stale_core_pruning": pruned,
+        "answers_equal_sequential": mismatch == 0 and (pruned is None or
+                                                        pruned["answers_equal_sequential"]),
         "mismatches": mismatch,
     }
 
@@ -427,6 +454,8 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-slots", type=int, default=2)
     ap.add_argument("--serve-inflight", type=int, default=64)
+    ap.add_argument("--serve-prune", type=int, default=256,
+                    help="ABCORE_OPT_SERVE_PRUNE of a third, pruned served run (0 = none)")
     ap.add_argument("--serve-pull", type=int, default=0,
                     help="ABCORE_OPT_PULL of the served handle (0 = default)")
     ap.add_argument("--step-mode", choices=["both", "index_free", "rank_order"], default="both",

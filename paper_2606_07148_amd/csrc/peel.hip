@@ -1489,9 +1489,12 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
                                    : total_entries - f0deg;
     // pull pays one streaming read per surviving entry instead of one atomic
     // per frontier entry: worth it when the frontier carries a sizeable share
-    // with the rank copy a pull round reads about a line per surviving row
-    // (a few per split row): worth it once the frontier's atomics are about
-    // half as many as the survivors
+    // (a random 4-byte atomic moves about 100 bytes of lines to and from
+    // HBM; a pulled entry about 18 with its bitmap lookup in L2 or the
+    // Infinity Cache, hence the factor 6 when the bitmap is not in LDS, and
+    // 16 when it is); with the rank copy a pull round reads about a line per
+    // surviving row (a few per split row): worth it once the frontier's
+    // atomics are about half as many as the survivors
     int64_t ku = 0, kl = 0;
     if (rcols != nullptr) {
       // (known in advance for a query in rank order)
@@ -1506,7 +1509,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
         mode == 2 ||
         (mode == 0 && f0deg > 0 &&
          (rcols != nullptr ? f0deg * 2 >= ku + kl
-                           : (use_lds ? f0deg * 16 >= rest : f0deg * 2 >= rest)));
+                           : (use_lds ? f0deg * 16 >= rest : f0deg * 6 >= rest)));
     if (lane_id() == 0) sh.decide = pull ? 1 : 0;
   }
   if (kLds) stage(0);
