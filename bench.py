@@ -378,6 +378,7 @@ def bench_sweep(args, pkg, torch, np, bigraph_gen) -> dict:
     del deu, dev
     torch.cuda.empty_cache()
     report = pkg.abcore_graph_report(g)
+    resident, _ = pkg.abcore_device_memory()
     pkg.abcore_set_option(g, pkg.ABCORE_OPT_RANK_ORDER, 2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -432,6 +433,7 @@ def bench_sweep(args, pkg, torch, np, bigraph_gen) -> dict:
         "parity_vs_oracle_digests": oracle_parity,
         "build": report,
         "device_memory_library_peak_bytes": peak,
+        "device_memory_library_resident_after_build_bytes": resident,
     }
 
 
@@ -507,6 +509,7 @@ def main() -> int:
     g = pkg.abcore_build_csr(nU, nL, deu, dev)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
+    resident_c2, _ = pkg.abcore_device_memory()
     del deu, dev
     if args.peel_mode:
         pkg.abcore_set_option(g, pkg.ABCORE_OPT_PEEL_MODE, args.peel_mode)
@@ -729,7 +732,9 @@ def main() -> int:
                            if k not in ("stats", "ms_per_step")},
             "flush": "1 GiB written before each step, outside its events"},
         "build": report,
-        "device_memory": {"library_peak_bytes": peak_c2, "torch_peak_bytes": c2_torch_peak},
+        "device_memory": {"library_peak_bytes": peak_c2,
+                          "library_resident_after_build_bytes": resident_c2,
+                          "torch_peak_bytes": c2_torch_peak},
         "gpu_stats": gst,
         "parity": parity,
         "m_peeled": m_peeled,

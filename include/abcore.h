@@ -152,10 +152,10 @@ abcore_status abcore_compute(abcore_graph g, uint32_t alpha, uint32_t beta, int3
  * partial sums, survivor bitmap) lives in a static device array of 64 MiB
  * that the library holds on every device it runs on until the process ends;
  * the handle's graph arrays are read only.  It fits graphs whose working set,
- * 64 * (2n + pieces + 256) + 4.125 n bytes plus about 330 KB (pieces: one per
- * 64 adjacency entries of each row longer than 64), is at most 64 MiB --
- * about 440,000 vertices at the degree skew of a power-law graph; larger
- * graphs return ABCORE_EINVAL and change nothing.  Every call on a device
+ * 4 * (2n + pieces) + 4.125 n bytes plus about 600 KB (pieces: one per 64
+ * adjacency entries of each row longer than 64), is at most 64 MiB -- about
+ * 5,000,000 vertices at the degree skew of a power-law graph; larger graphs
+ * return ABCORE_EINVAL and change nothing.  Every call on a device
  * shares that device's array and starts by filling it afresh (queue slots
  * empty, state zero), with kernels only (no memset node), on `stream`:
  * calls that overlap on one device, on any handles or streams, race, and
@@ -386,6 +386,15 @@ abcore_status abcore_serve_stop(abcore_graph g, int64_t *counters);
  *                          of the asynchronous peel makes before it declares
  *                          a hang and aborts (0 = the default, 2^21, i.e.
  *                          seconds; small values make peels abort at once).
+ *   ABCORE_OPT_APPEND_SUBQUEUE: test of the frontier queue's shared capacity
+ *                          (the 16 sub-queues together hold the bound of
+ *                          2n + pieces + 256 appends per computation, each a
+ *                          16th plus 4,096 slots; an append that does not fit
+ *                          one goes to the next): 0 (default) = each
+ *                          workgroup appends to its own sub-queue first;
+ *                          j in 1..16 = every append tries sub-queue j-1
+ *                          first, so that it fills and the rest overflow.
+ *                          Results are identical either way.
  *
  * Aborts.  Every device-side wait is bounded.  A computation whose wait
  * exceeds its bound leaves an invalid result; a call that requested stats
@@ -408,7 +417,8 @@ enum {
   ABCORE_OPT_SPIN_LIMIT = 8,
   ABCORE_OPT_AUTOTUNE = 9,
   ABCORE_OPT_SERVE_PRUNE = 10,
-  ABCORE_OPT_KCORE_SWITCH = 11
+  ABCORE_OPT_KCORE_SWITCH = 11,
+  ABCORE_OPT_APPEND_SUBQUEUE = 12
 };
 abcore_status abcore_set_option(abcore_graph g, int32_t option, int64_t value);
 

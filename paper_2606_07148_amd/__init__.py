@@ -30,6 +30,7 @@ ABCORE_OPT_SPIN_LIMIT = 8
 ABCORE_OPT_AUTOTUNE = 9
 ABCORE_OPT_SERVE_PRUNE = 10
 ABCORE_OPT_KCORE_SWITCH = 11
+ABCORE_OPT_APPEND_SUBQUEUE = 12
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOENT", 5: "EEXIST",
           6: "EBUSY", 7: "EAGAIN"}

@@ -27,11 +27,24 @@ constexpr int kPullLocalQueue = 128;
 // Row piece length (entries) for load balancing over skewed degrees.
 constexpr int kPiece = 64;
 
-// Spread append counters: workgroup b appends to sub-queue b % kSub, each
-// with its own counter on its own 64-byte line.  Same-address device-scope
-// atomics serialise (about 11 ns each on MI355X), so no counter may take
-// more than a few dozen increments per launch.
+// Spread append counters: workgroup b appends to sub-queue b % kSub (the
+// next one with room when it is full), each with its own counter on its own
+// 64-byte line.  Same-address device-scope atomics serialise (about 11 ns
+// each on MI355X), so no counter may take more than a few dozen increments
+// per launch.
 constexpr int kSub = 16;
+// Largest single append (a scan workgroup's chunk).
+constexpr int kMaxAppend = 4096;
+// A slot filled by an append that did not fit its sub-queue: consumers take
+// it and count it as processed, and nothing else.
+constexpr int32_t kSkipItem = INT32_MIN;
+// Slots per sub-queue.  A computation appends at most 2n + pieces +
+// kLocalQueue items (a vertex at most twice: GCC+'s uncertain list and
+// frontier, or a split row's two queueings after a pull round; a piece
+// once); the sub-queues share that bound, each with kMaxAppend of slack.
+inline int64_t queue_capacity(int64_t n, int64_t npieces) {
+  return (2 * n + npieces + kLocalQueue + kSub - 1) / kSub + kMaxAppend;
+}
 constexpr int kPad = 16;      // int32 words per 64-byte line
 constexpr int kGroups = 16;   // grid-barrier / last-workgroup groups
 constexpr int kMaxBlocks = 4096;
@@ -246,6 +259,7 @@ struct Graph {
   // the workspace.
   int32_t *h_abort = nullptr;
   uint32_t spin_limit = 0;  // ABCORE_OPT_SPIN_LIMIT (0 = kAsyncSpinLimit)
+  int32_t append_sub = -1;  // ABCORE_OPT_APPEND_SUBQUEUE - 1
   int rs_parity = 0;  // flips with every exchange of state and state_alt
   // Pull round work split: workgroup k of a cu_count grid walks the upper
   // rows [b[k], b[k+1]) and the lower rows [b[G+1+k], b[G+2+k]), ranges of
@@ -373,6 +387,9 @@ struct PeelArgs {
   // Host-visible word (pinned, coherent; nullable) the peel sets when it
   // ends by an abort, so the host learns of it without a synchronisation.
   int32_t *abort_host;
+  // Sub-queue every append tries first (-1: the producer's own; a fixed one
+  // makes appends overflow into the others, ABCORE_OPT_APPEND_SUBQUEUE).
+  int32_t append_sub;
   int64_t n;
   int32_t nU;
   int32_t thrU, thrL;

@@ -808,9 +808,7 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
     if (st == ABCORE_OK && hipStreamSynchronize(s) != hipSuccess) st = ABCORE_EDEVICE;
     if (st != ABCORE_OK) break;
     g->build_ms[2] = ms_since(t0);
-    // per computation a vertex enters the queues at most twice (GCC+: as
-    // uncertain, then as removed) and a split row once more as its pieces
-    g->qcap = 2 * g->n + g->npieces + kLocalQueue;
+    g->qcap = queue_capacity(g->n, g->npieces);
     if ((st = ensure(&g->deg, g->n)) != ABCORE_OK) break;
     if ((st = ensure(&g->queue, (int64_t)kSub * g->qcap)) != ABCORE_OK) break;
     if (hipMemsetAsync(g->queue, 0xFF, sizeof(int32_t) * kSub * g->qcap, s) != hipSuccess) {
@@ -984,6 +982,13 @@ abcore_status abcore_set_option(abcore_graph h, int32_t option, int64_t value) {
         return ABCORE_EINVAL;
       }
       g->rank_order = value != 2;
+      return ABCORE_OK;
+    case ABCORE_OPT_APPEND_SUBQUEUE:
+      if (value > kSub) {
+        set_error("abcore_set_option: sub-queue %lld above %d", (long long)value, kSub);
+        return ABCORE_EINVAL;
+      }
+      g->append_sub = (int32_t)value - 1;
       return ABCORE_OK;
     case ABCORE_OPT_SPIN_LIMIT:
       g->spin_limit = (uint32_t)std::min<int64_t>(value, (int64_t)kAsyncSpinLimit);

@@ -153,6 +153,7 @@ PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL) {
   a.rs_fail = nullptr;
   a.spin_limit = g.spin_limit > 0 ? g.spin_limit : kAsyncSpinLimit;
   a.abort_host = g.h_abort;
+  a.append_sub = g.append_sub;
   // any launch but a query in rank order may leave the queue in use
   g.rs_ready = false;
   a.n = g.n;
@@ -235,6 +236,7 @@ struct ScanCollector {
   int32_t buf[kScanChunk];
   int count;
   int base;
+  int rsub;
 
   // up to 4 items per thread; the whole workgroup calls in uniform flow
   __device__ __forceinline__ void append(const int32_t *items, int cnt) {
@@ -246,6 +248,7 @@ struct ScanCollector {
     for (int j = 0; j < cnt; ++j) buf[pos + j] = items[j];
   }
 
+  // to a plain list with its own cursor
   __device__ __forceinline__ void flush(int32_t *q, int32_t *tail) {
     __syncthreads();
     const int c = count;
@@ -256,7 +259,28 @@ struct ScanCollector {
     if (threadIdx.x == 0) count = 0;
     __syncthreads();
   }
+
+  // to the frontier queues, sub-queue `sub` first (reserve_slots)
+  __device__ __forceinline__ void flush_queue(const PeelArgs &a, int sub) {
+    __syncthreads();
+    const int c = count;
+    if (threadIdx.x == 0) {
+      int2 r = make_int2(0, 0);
+      if (c > 0) r = reserve_slots(a.st, a.queue, a.qcap, append_pref(a, sub), c, a.abort_host);
+      base = r.y;
+      rsub = r.x;
+    }
+    __syncthreads();
+    if (rsub >= 0) {
+      int32_t *q = a.queue + (int64_t)rsub * a.qcap + base;
+      for (int i = threadIdx.x; i < c; i += blockDim.x) q[i] = buf[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) count = 0;
+    __syncthreads();
+  }
 };
+static_assert(kScanChunk <= kMaxAppend, "a scan chunk is one append");
 
 // ----------------------------------------------------------- scan phase --
 // Algorithm 1, scan phase: deg <- deg0 for every vertex and every vertex
@@ -275,7 +299,6 @@ __global__ __launch_bounds__(kScanBlock) void scan_gcc_kernel(PeelArgs a,
   if (threadIdx.x == 0) col.count = 0;
   __syncthreads();
   const int sub = blockIdx.x % kSub;
-  int32_t *q = a.queue + (int64_t)sub * a.qcap;
   int64_t f0 = 0, f0deg = 0;
   for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < n;
        cb += (int64_t)gridDim.x * kScanChunk) {
@@ -325,11 +348,11 @@ __global__ __launch_bounds__(kScanBlock) void scan_gcc_kernel(PeelArgs a,
       f0 += cnt;
       col.append(items, cnt);
     }
-    col.flush(q, &a.st->tail[sub][0]);
+    col.flush_queue(a, sub);
   }
   add_part(a.part, kPartF0, f0, &s_acc);
   add_part(a.part, kPartF0Deg, f0deg, &s_acc);
-  if (last_block_done<false>(a.st)) start_rounds_wave(a.st);
+  if (last_block_done<false>(a.st)) start_rounds_wave(a.st, a.qcap);
 }
 
 hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, bool want_bits,
@@ -454,7 +477,6 @@ __global__ __launch_bounds__(kScanBlock) void scan_nested_kernel(PeelArgs a, int
   if (threadIdx.x == 0) col.count = 0;
   __syncthreads();
   const int sub = blockIdx.x % kSub;
-  int32_t *q = a.queue + (int64_t)sub * a.qcap;
   int64_t f0 = 0, f0deg = 0, rest = 0;
   for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < n;
        cb += (int64_t)gridDim.x * kScanChunk) {
@@ -500,14 +522,14 @@ __global__ __launch_bounds__(kScanBlock) void scan_nested_kernel(PeelArgs a, int
       f0 += cnt;
       col.append(items, cnt);
     }
-    col.flush(q, &a.st->tail[sub][0]);
+    col.flush_queue(a, sub);
   }
   add_part(a.part, kPartF0, f0, &s_acc);
   if (bits != nullptr) {
     add_part(a.part, kPartF0Deg, f0deg, &s_acc);
     add_part(a.part, kPartRest, rest, &s_acc);
   }
-  if (last_block_done<false>(a.st)) start_rounds_wave(a.st);
+  if (last_block_done<false>(a.st)) start_rounds_wave(a.st, a.qcap);
 }
 
 hipError_t launch_scan_nested(Graph &g, int32_t pU, int32_t pL, int32_t thrU, int32_t thrL,
@@ -554,7 +576,6 @@ __global__ __launch_bounds__(kScanBlock) void scan_component_kernel(
   __syncthreads();
   const int32_t c1 = comp[vx], c2 = comp[vy];
   const int sub = blockIdx.x % kSub;
-  int32_t *q = a.queue + (int64_t)sub * a.qcap;
   int64_t f0 = 0, f0deg = 0;
   for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < n;
        cb += (int64_t)gridDim.x * kScanChunk) {
@@ -608,11 +629,11 @@ __global__ __launch_bounds__(kScanBlock) void scan_component_kernel(
       f0 += cnt;
       col.append(items, cnt);
     }
-    col.flush(q, &a.st->tail[sub][0]);
+    col.flush_queue(a, sub);
   }
   add_part(a.part, kPartF0, f0, &s_acc);
   add_part(a.part, kPartF0Deg, f0deg, &s_acc);
-  if (last_block_done<false>(a.st)) start_rounds_wave(a.st);
+  if (last_block_done<false>(a.st)) start_rounds_wave(a.st, a.qcap);
 }
 
 hipError_t launch_scan_component_of(Graph &g, int32_t thrU, int32_t thrL, int32_t x, int32_t y,
@@ -882,7 +903,7 @@ template <int KIND>
 __global__ __launch_bounds__(kPeelBlock) void peel_round_kernel(PeelArgs a) {
   __shared__ int32_t s_lq[kPeelWaves][kLocalQueue];
   __shared__ RangeView s_view;
-  __shared__ int s_cnt[kPeelWaves + 1];
+  __shared__ int s_cnt[kPeelWaves + 2];
   __shared__ int64_t s_acc;
   load_view(s_view, a.st);
   if (s_view.pre[kSub] == 0) return;
@@ -892,7 +913,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_round_kernel(PeelArgs a) {
   block_flush(lq, s_cnt);
   add_part(a.part, kPartEntries, entries, &s_acc);
   if (last_block_done<false>(a.st)) {
-    advance_round_wave(a.st);
+    advance_round_wave(a.st, a.qcap);
     if (lane_id() == 0) atomicAdd((unsigned long long *)&a.st->launches, 1ull);
   }
 }
@@ -908,7 +929,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_persistent_kernel(PeelArgs a,
                                                                      int64_t max_rounds) {
   __shared__ int32_t s_lq[kPeelWaves][kLocalQueue];
   __shared__ RangeView s_view;
-  __shared__ int s_cnt[kPeelWaves + 1];
+  __shared__ int s_cnt[kPeelWaves + 2];
   __shared__ int s_abort;
   __shared__ int64_t s_acc;
   LocalQueue lq = make_lq(s_lq[wave_in_block()], kLocalQueue, a);
@@ -924,7 +945,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_persistent_kernel(PeelArgs a,
     peel_round_body<KIND>(a, s_view, 0, lq, entries);
     block_flush(lq, s_cnt);
     grid_sync<false>(a.st, [&] {
-      advance_round_wave(a.st);
+      advance_round_wave(a.st, a.qcap);
       if (lane_id() == 0) atomicAdd((unsigned long long *)&a.st->launches, 1ull);
     });
   }
@@ -974,7 +995,7 @@ hipError_t launch_peel_persistent(Graph &g, PeelKind kind, int32_t thrU, int32_t
 // (same-address reads serialise like atomics); it tells the other waves
 // through LDS.  Claims are 32 slots by default (a.claim).
 
-__device__ __forceinline__ bool quiescent(PeelState *st, int32_t start_expect) {
+__device__ __forceinline__ bool quiescent(PeelState *st, int32_t start_expect, int64_t qcap) {
   const int j = lane_id();
   int32_t d = 0, t = 0;
   if (start_expect > 0) {
@@ -990,7 +1011,7 @@ __device__ __forceinline__ bool quiescent(PeelState *st, int32_t start_expect) {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  if (j < kSub) t = ld_agent(&st->tail[j][0]);
+  if (j < kSub) t = phys_tail(st, j, qcap);
   const int tsum = wave_sum(t);
   return dsum == tsum;
 }
@@ -1034,11 +1055,12 @@ __device__ __forceinline__ void async_batch(const PeelArgs &a, int32_t item, int
 
 // Claims up to 64 appended, unclaimed slots of sub-queue v (none past its
 // tail); returns the count claimed, base in *base.  Wave-uniform.
-__device__ __forceinline__ int steal_claim(PeelState *st, int v, int max_take, int *base) {
+__device__ __forceinline__ int steal_claim(PeelState *st, int v, int max_take, int64_t qcap,
+                                           int *base) {
   int b = 0, c = 0;
   if (lane_id() == 0) {
     const int h = ld_agent(&st->head[v][0]);
-    const int t = ld_agent(&st->tail[v][0]);
+    const int t = phys_tail(st, v, qcap);
     if (h < t) {
       const int want = min(t - h, max_take);
       if (atomicCAS(&st->head[v][0], h, h + want) == h) {
@@ -1055,7 +1077,7 @@ template <int KIND>
 __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
   __shared__ int32_t s_lq[kPeelWaves][kLocalQueue];
   __shared__ int64_t s_acc;
-  __shared__ int s_cnt[kPeelWaves + 1];
+  __shared__ int s_cnt[kPeelWaves + 2];
   __shared__ int s_stop;
   // rank order after an aborted query: the queue may hold stale items
   if (a.rs_fail != nullptr && ld_agent(a.rs_fail) != 0) {
@@ -1122,8 +1144,8 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
       if (a.rs_next_st != nullptr && ready) lq.q[slot] = kEmpty;
       const uint64_t rmask = __ballot(ready);
       if (rmask) {
-        async_batch<KIND>(a, ready ? item : -1, (int)__popcll(rmask), lq, consumed, entries,
-                          level);
+        async_batch<KIND>(a, ready && item != kSkipItem ? item : -1, (int)__popcll(rmask), lq,
+                          consumed, entries, level);
         pending = pending && !ready;
         idle = 0;
         continue;
@@ -1134,7 +1156,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
       victim = victim % (kSub - 1) + 1;
       int sbase = 0;
       const int taken = (wave_in_block() == 0 && (idle % ABC_STEAL_EVERY) == 0)
-                            ? steal_claim(a.st, (j + (int)victim) % kSub, claim, &sbase)
+                            ? steal_claim(a.st, (j + (int)victim) % kSub, claim, a.qcap, &sbase)
                             : 0;
       if (taken > 0) {
         const int32_t *vq = a.queue + (int64_t)((j + (int)victim) % kSub) * a.qcap;
@@ -1152,6 +1174,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
           } else if (a.rs_next_st != nullptr) {
             const_cast<int32_t *>(vq)[sbase + lane_id()] = kEmpty;
           }
+          if (sitem == kSkipItem) sitem = -1;
         }
         async_batch<KIND>(a, sitem, taken, lq, consumed, entries, level);
         idle = 0;
@@ -1169,7 +1192,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
         if (lane_id() == 0) stop = ld_agent(&a.st->fin[blockIdx.x % kGroups][0]);
         stop = __shfl(stop, 0, kWave);
         if (!stop && (idle & ABC_QMASK) == 0) {
-          if (quiescent(a.st, a.start_expect)) {
+          if (quiescent(a.st, a.start_expect, a.qcap)) {
             if (lane_id() < kGroups) st_agent(&a.st->fin[lane_id()][0], 1);
             stop = 1;
           } else {
@@ -1201,7 +1224,7 @@ __global__ __launch_bounds__(kPeelBlock) void peel_async_kernel(PeelArgs a) {
   if (KIND == kKCore && threadIdx.x < kSub) {
     // everything appended so far is processed: the next level's scan starts
     // its range here (every workgroup writes the same final cursors)
-    st_agent(&a.st->hi[threadIdx.x], ld_agent(&a.st->tail[threadIdx.x][0]));
+    st_agent(&a.st->hi[threadIdx.x], phys_tail(a.st, threadIdx.x, a.qcap));
   }
   const bool aborted = ld_agent(&a.st->abort_flag) != 0;
   if (aborted && threadIdx.x == 0) report_abort(a);
@@ -1311,7 +1334,7 @@ struct PullShared {
   int32_t lq[kPullWaves][kPullLocalQueue];
   int32_t cnt[kPullWaves][kWave];
   ChunkDesc desc[kPullWaves][kWave];
-  int s_cnt[kPullWaves + 1];
+  int s_cnt[kPullWaves + 2];
   int decide;
   int next_row, next_piece;  // the workgroup's next unclaimed row / piece
   int32_t k_alive[2];        // rank mode: survivors of the upper / lower layer
@@ -1534,11 +1557,13 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
         const int cnt = __popc(dead);
         const int incl = wave_incl_scan(cnt);
         const int sub = (int)((w0 / kWave) % kSub);
-        int base = 0;
-        if (lane_id() == kWave - 1 && incl > 0) base = atomicAdd(&a.st->tail[sub][0], incl);
-        int pos = __shfl(base, kWave - 1, kWave) + incl - cnt;
-        int32_t *q = a.queue + (int64_t)sub * a.qcap;
-        while (dead != 0) {
+        int2 r = make_int2(0, 0);
+        if (lane_id() == kWave - 1 && incl > 0)
+          r = reserve_slots(a.st, a.queue, a.qcap, append_pref(a, sub), incl, a.abort_host);
+        const int rs = __shfl(r.x, kWave - 1, kWave);
+        int pos = __shfl(r.y, kWave - 1, kWave) + incl - cnt;
+        int32_t *q = a.queue + (int64_t)rs * a.qcap;
+        while (rs >= 0 && dead != 0) {
           q[pos++] = (int32_t)((w << 5) + (__ffs(dead) - 1));
           dead &= dead - 1;
         }
@@ -1805,7 +1830,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     }
   }
   if (advance && last_block_done<false>(a.st)) {
-    advance_round_wave(a.st);
+    advance_round_wave(a.st, a.qcap);
     if (lane_id() == 0) atomicAdd((unsigned long long *)&a.st->launches, 1ull);
   }
 }
@@ -1816,7 +1841,7 @@ __global__ __launch_bounds__(kPeelBlock) void pull_fixup_kernel(
     PeelArgs a, const uint32_t *__restrict__ gbits, const int32_t *__restrict__ heavy_rows,
     int64_t nheavy) {
   __shared__ int32_t s_lq[kPeelWaves][kLocalQueue];
-  __shared__ int s_cnt[kPeelWaves + 1];
+  __shared__ int s_cnt[kPeelWaves + 2];
   if (ld_agent(&a.st->pulled) == 0) return;
   LocalQueue lq = make_lq(s_lq[wave_in_block()], kLocalQueue, a);
   const int waves = blockDim.x / kWave;
@@ -1833,7 +1858,7 @@ __global__ __launch_bounds__(kPeelBlock) void pull_fixup_kernel(
   }
   block_flush(lq, s_cnt);
   if (last_block_done<false>(a.st)) {
-    advance_round_wave(a.st);
+    advance_round_wave(a.st, a.qcap);
     if (lane_id() == 0) atomicAdd((unsigned long long *)&a.st->launches, 1ull);
   }
 }
@@ -2033,7 +2058,6 @@ __global__ __launch_bounds__(kScanBlock) void classify_kernel(PeelArgs a, int64_
   if (threadIdx.x == 0) col.count = 0;
   __syncthreads();
   const int sub = blockIdx.x % kSub;
-  int32_t *q = a.queue + (int64_t)sub * a.qcap;
   for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < n;
        cb += (int64_t)gridDim.x * kScanChunk) {
     for (int t = 0; t < kScanChunk; t += kScanBlock * 4) {
@@ -2063,10 +2087,10 @@ __global__ __launch_bounds__(kScanBlock) void classify_kernel(PeelArgs a, int64_
       }
       col.append(items, cnt);
     }
-    col.flush(q, &a.st->tail[sub][0]);
+    col.flush_queue(a, sub);
   }
   if (last_block_done<false>(a.st)) {
-    start_rounds_wave(a.st);
+    start_rounds_wave(a.st, a.qcap);
     if (lane_id() == 0) st_agent(&a.st->aux0, ld_agent(&a.st->first));  // uncertain count
   }
 }
@@ -2180,7 +2204,7 @@ __global__ __launch_bounds__(kPeelBlock) void restricted_init_kernel(PeelArgs a,
   __shared__ int32_t s_lq[kPeelWaves][kLocalQueue];
   __shared__ int32_t s_cnt_own[kPeelWaves][kWave];
   __shared__ RangeView s_view;
-  __shared__ int s_cnt[kPeelWaves + 1];
+  __shared__ int s_cnt[kPeelWaves + 2];
   __shared__ int64_t s_acc;
   load_view(s_view, a.st);
   LocalQueue lq = make_lq(s_lq[wave_in_block()], kLocalQueue, a);
@@ -2243,7 +2267,7 @@ __global__ __launch_bounds__(kPeelBlock) void restricted_init_kernel(PeelArgs a,
   block_flush(lq, s_cnt);
   add_part(a.part, kPartEntries, entries, &s_acc);
   if (last_block_done<false>(a.st)) {
-    advance_round_wave(a.st);
+    advance_round_wave(a.st, a.qcap);
     // the uncertain list is not a round: the frontier starts the count
     const int j = lane_id();
     int32_t f = 0;
@@ -2306,7 +2330,7 @@ hipError_t launch_kcore_init(Graph &g, hipStream_t s) {
 struct KCoreShared {
   int32_t lq[kPeelWaves][kLocalQueue];
   RangeView view;
-  int s_cnt[kPeelWaves + 1];
+  int s_cnt[kPeelWaves + 2];
   int s_wsum[kPeelWaves + 1];
   int phase;   // 0 done, 1 round, 2 scan, 3 compaction
   int level, next_k, cur, sel;
@@ -2436,16 +2460,16 @@ __device__ void kcore_complete(const PeelArgs &a, int phase, int nblocks) {
   PeelState *st = a.st;
   const int lane = lane_id();
   if (phase == 1) {
-    advance_round_wave(st);
+    advance_round_wave(st, a.qcap);
   } else if (phase == 2) {
     const int32_t kn = st->next_k;
     const int64_t kept = wave_sum_strided(a.part + kPartKept, nblocks, kPartFields);
     const int32_t mn =
         (int32_t)wave_min_strided(a.part + kPartMin, nblocks, kPartFields, 0x7FFFFFFF);
     int32_t after = 0;
-    if (lane < kSub) after = ld_agent(&st->tail[lane][0]) - ld_agent(&st->hi[lane]);
+    if (lane < kSub) after = phys_tail(st, lane, a.qcap) - ld_agent(&st->hi[lane]);
     after = wave_sum(after);
-    advance_round_wave(st);  // the scan's pushes become the level's first round
+    advance_round_wave(st, a.qcap);  // the scan's pushes become the level's first round
     if (lane == 0) {
       const bool pushed = after > 0;
       st->k = kn;
@@ -2542,7 +2566,6 @@ __global__ __launch_bounds__(kScanBlock) void kcore_level_scan_kernel(PeelArgs a
   }
   __syncthreads();
   const int sub = blockIdx.x % kSub;
-  int32_t *q = a.queue + (int64_t)sub * a.qcap;
   int32_t mn = 0x7FFFFFFF;
   for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < cur;
        cb += (int64_t)gridDim.x * kScanChunk) {
@@ -2569,7 +2592,7 @@ __global__ __launch_bounds__(kScanBlock) void kcore_level_scan_kernel(PeelArgs a
       col.append(items, cnt);
       keep.append(kept, kc);
     }
-    col.flush(q, &a.st->tail[sub][0]);
+    col.flush_queue(a, sub);
     keep.flush(N, &a.st->kept);
   }
   mn = wave_min(mn);
@@ -2579,11 +2602,11 @@ __global__ __launch_bounds__(kScanBlock) void kcore_level_scan_kernel(PeelArgs a
   if (last_block_done<false>(st)) {
     const int lane = lane_id();
     int32_t after = 0;
-    if (lane < kSub) after = ld_agent(&st->tail[lane][0]) - ld_agent(&st->hi[lane]);
+    if (lane < kSub) after = phys_tail(st, lane, a.qcap) - ld_agent(&st->hi[lane]);
     after = wave_sum(after);
     const int32_t gmin =
         (int32_t)wave_min_strided(a.part + kPartMin, (int)gridDim.x, kPartFields, 0x7FFFFFFF);
-    advance_round_wave(st);  // the queued vertices start the level's peel
+    advance_round_wave(st, a.qcap);  // the queued vertices start the level's peel
     if (lane < kGroups) st->fin[lane][0] = 0;  // the level's peel detects its own end
     if (lane == 0) {
       const int32_t kept_n = ld_agent(&st->kept);

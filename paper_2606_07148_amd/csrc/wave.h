@@ -57,22 +57,79 @@ __device__ __forceinline__ int wave_min(int v) {
   return v;
 }
 
-// Per-wave frontier buffer in LDS, flushed to the workgroup's sub-queue.
+// Reserves `cnt` consecutive slots for one append; called by one thread.
+// The sub-queues share one bound instead of each holding the worst case:
+// a computation appends at most 2n + pieces + kLocalQueue items, and each
+// sub-queue holds a 16th of that plus kMaxAppend (the largest single append).
+// Sub-queue `pref` is tried first.  An append that does not fit fills the
+// rest of that sub-queue with kSkipItem (consumers take such a slot and
+// count it as processed) and tries the next sub-queue; the slots past qcap
+// that its failed reservation counted are never written or claimed (every
+// range end, every steal and the termination test use min(tail, qcap)).
+// A sub-queue that rejects an append is full from then on with fewer than
+// kMaxAppend skips, so if all kSub rejected, more than kSub * (qcap -
+// kMaxAppend) >= the bound real items would have been appended: the loop
+// always ends with a reservation.  Should the bound ever be broken anyway,
+// the computation aborts (nothing is written past qcap).  Returns the
+// sub-queue in .x (-1 on that abort) and the first slot in .y.
+__device__ __forceinline__ int2 reserve_slots(PeelState *st, int32_t *queue, int64_t qcap,
+                                              int pref, int cnt, int *abort_host) {
+  int s = pref;
+  for (int tries = 0; tries < kSub; ++tries) {
+    // a full sub-queue stays full: after the first attempt, skip such ones
+    // without counting more slots past their capacity
+    if (tries > 0 && ld_agent(&st->tail[s][0]) >= qcap) {
+      s = (s + 1) % kSub;
+      continue;
+    }
+    const int base = atomicAdd(&st->tail[s][0], cnt);
+    if ((int64_t)base + cnt <= qcap) return make_int2(s, base);
+    int32_t *q = queue + (int64_t)s * qcap;
+    for (int64_t i = base; i < qcap; ++i) st_agent(&q[i], kSkipItem);
+    s = (s + 1) % kSub;
+  }
+  st_agent(&st->abort_flag, 1);
+  if (abort_host != nullptr)
+    __hip_atomic_store(abort_host, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  return make_int2(-1, 0);
+}
+
+// The sub-queue an append tries first.
+__device__ __forceinline__ int append_pref(const PeelArgs &a, int own) {
+  return a.append_sub >= 0 ? a.append_sub : own;
+}
+
+// End of sub-queue j's written range: its tail, less the slots a rejected
+// append counted past the capacity.
+__device__ __forceinline__ int32_t phys_tail(PeelState *st, int j, int64_t qcap) {
+  return (int32_t)min((int64_t)ld_agent(&st->tail[j][0]), qcap);
+}
+
+// Per-wave frontier buffer in LDS, flushed to the workgroup's sub-queue (or
+// the next with room, see reserve_slots).
 // Every call must be made by the whole wave in uniform control flow.
 struct LocalQueue {
   int32_t *buf;
   int cap;
-  int count;     // wave-uniform
-  int32_t *q;    // this workgroup's sub-queue
-  int32_t *tail; // its append cursor
+  int count;      // wave-uniform
+  int32_t *q;     // this workgroup's sub-queue (its consumers read it)
+  int32_t *queue; // every sub-queue
+  int64_t qcap;
+  PeelState *st;
+  int *abort_host;
+  int sub;
 
   __device__ __forceinline__ void flush() {
     if (count == 0) return;
     __builtin_amdgcn_wave_barrier();
-    int base = 0;
-    if (lane_id() == 0) base = atomicAdd(tail, count);
-    base = __shfl(base, 0, kWave);
-    for (int i = lane_id(); i < count; i += kWave) st_agent(&q[base + i], buf[i]);
+    int2 r = make_int2(0, 0);
+    if (lane_id() == 0) r = reserve_slots(st, queue, qcap, sub, count, abort_host);
+    const int s = __shfl(r.x, 0, kWave);
+    const int base = __shfl(r.y, 0, kWave);
+    if (s >= 0) {
+      int32_t *dst = queue + (int64_t)s * qcap + base;
+      for (int i = lane_id(); i < count; i += kWave) st_agent(&dst[i], buf[i]);
+    }
     __builtin_amdgcn_wave_barrier();
     count = 0;
   }
@@ -94,12 +151,16 @@ __device__ __forceinline__ LocalQueue make_lq(int32_t *buf, int cap, const PeelA
   lq.cap = cap;
   lq.count = 0;
   lq.q = a.queue + (int64_t)sub * a.qcap;
-  lq.tail = &a.st->tail[sub][0];
+  lq.queue = a.queue;
+  lq.qcap = a.qcap;
+  lq.st = a.st;
+  lq.abort_host = a.abort_host;
+  lq.sub = append_pref(a, sub);
   return lq;
 }
 
 // Flushes every wave's local queue of the workgroup with a single append.
-// s_cnt: LDS, at least (waves + 1) ints.  Whole workgroup, uniform flow.
+// s_cnt: LDS, at least (waves + 2) ints.  Whole workgroup, uniform flow.
 __device__ __forceinline__ void block_flush(LocalQueue &lq, int *s_cnt) {
   const int waves = blockDim.x / kWave;
   if (lane_id() == 0) s_cnt[wave_in_block()] = lq.count;
@@ -111,35 +172,19 @@ __device__ __forceinline__ void block_flush(LocalQueue &lq, int *s_cnt) {
       s_cnt[w] = tot;
       tot += t;
     }
-    s_cnt[waves] = tot > 0 ? atomicAdd(lq.tail, tot) : 0;
+    int2 r = make_int2(0, 0);
+    if (tot > 0) r = reserve_slots(lq.st, lq.queue, lq.qcap, lq.sub, tot, lq.abort_host);
+    s_cnt[waves] = r.y;
+    s_cnt[waves + 1] = r.x;
   }
   __syncthreads();
-  const int base = s_cnt[waves] + s_cnt[wave_in_block()];
-  for (int i = lane_id(); i < lq.count; i += kWave) st_agent(&lq.q[base + i], lq.buf[i]);
+  const int s = s_cnt[waves + 1];
+  if (s >= 0) {
+    int32_t *dst = lq.queue + (int64_t)s * lq.qcap + s_cnt[waves] + s_cnt[wave_in_block()];
+    for (int i = lane_id(); i < lq.count; i += kWave) st_agent(&dst[i], lq.buf[i]);
+  }
   lq.count = 0;
   __syncthreads();
-}
-
-// Workgroup-aggregated append of `cnt` items per thread to this workgroup's
-// sub-queue; returns the thread's first position.  Whole workgroup.
-__device__ __forceinline__ int block_reserve(int cnt, int32_t *tail, int *s_wsum) {
-  const int waves = blockDim.x / kWave;
-  int incl = wave_incl_scan(cnt);
-  if (lane_id() == kWave - 1) s_wsum[wave_in_block()] = incl;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int tot = 0;
-    for (int w = 0; w < waves; ++w) {
-      int t = s_wsum[w];
-      s_wsum[w] = tot;
-      tot += t;
-    }
-    s_wsum[waves] = tot > 0 ? atomicAdd(tail, tot) : 0;
-  }
-  __syncthreads();
-  int pos = s_wsum[waves] + s_wsum[wave_in_block()] + incl - cnt;
-  __syncthreads();
-  return pos;
 }
 
 // A round's items: the sub-queue ranges [lo[j], hi[j]) seen as one
@@ -168,7 +213,8 @@ __device__ __forceinline__ int32_t view_item(const RangeView &v, const int32_t *
 #pragma unroll
   for (int s = kSub / 2; s > 0; s >>= 1)
     if (v.pre[j + s] <= i) j += s;
-  return ld_agent(&queue[(int64_t)j * qcap + v.lo[j] + (i - v.pre[j])]);
+  const int32_t x = ld_agent(&queue[(int64_t)j * qcap + v.lo[j] + (i - v.pre[j])]);
+  return x == kSkipItem ? -1 : x;
 }
 
 __device__ __forceinline__ int wave_sum(int v) {
@@ -184,13 +230,13 @@ __device__ __forceinline__ void bump(int32_t *p) { st_agent(p, ld_agent(p) + 1);
 // Advances the round: the items appended since the last snapshot become the
 // next round.  Called by the 64 lanes of one wave (lane j < kSub handles
 // sub-queue j) once every append of the round is complete.
-__device__ __forceinline__ void advance_round_wave(PeelState *st) {
+__device__ __forceinline__ void advance_round_wave(PeelState *st, int64_t qcap) {
   const int j = lane_id();
   int32_t h = 0, l = 0, t = 0;
   if (j < kSub) {
     h = ld_agent(&st->hi[j]);
     l = ld_agent(&st->lo[j]);
-    t = ld_agent(&st->tail[j][0]);
+    t = phys_tail(st, j, qcap);
   }
   const int prev = wave_sum(h - l);
   if (j < kSub) {
@@ -203,11 +249,11 @@ __device__ __forceinline__ void advance_round_wave(PeelState *st) {
 }
 
 // Sets lo to 0 and hi to the tails: the first round after a scan.  One wave.
-__device__ __forceinline__ void start_rounds_wave(PeelState *st) {
+__device__ __forceinline__ void start_rounds_wave(PeelState *st, int64_t qcap) {
   const int j = lane_id();
   int32_t t = 0;
   if (j < kSub) {
-    t = ld_agent(&st->tail[j][0]);
+    t = phys_tail(st, j, qcap);
     st_agent(&st->lo[j], 0);
     st_agent(&st->hi[j], t);
     st_agent(&st->head[j][0], 0);

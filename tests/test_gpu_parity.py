@@ -247,6 +247,42 @@ def test_autotune_keeps_results_exact():
     g.destroy()
 
 
+@pytest.mark.parametrize("peel,pull", [(3, 0), (3, 1), (3, 2), (2, 2), (1, 1)])
+def test_shared_queue_capacity_overflow(peel, pull):
+    """The 16 frontier sub-queues share one capacity bound (a 16th of
+    2n + pieces + 256 each, plus 4,096 slots).  With every append sent to
+    sub-queue 0 first, it fills and later appends overflow into the others
+    (the rest of a full sub-queue is filled with skip slots): results stay
+    exact for GCC, GCC+, core numbers and GFQ updates in every peel mode."""
+    nU, nL, m = 30_000, 20_000, 400_000
+    eu, ev = bigraph_gen.chung_lu(nU, nL, m, 2.1, 2.1, 5000, 108)
+    g, ref = _make(nU, nL, eu, ev)
+    _set_mode(g, peel, pull)
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_APPEND_SUBQUEUE, 1)
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_KCORE_SWITCH, 1)  # every level queued
+    for a, b in [(1, 1), (2, 3), (5, 5), (9, 4), (12, 30), (64, 64)]:
+        say("shared capacity: mode", peel, pull, "query", a, b)
+        for algo in (pkg.ABCORE_GCC, pkg.ABCORE_GCC_PLUS):
+            _check_core(g, ref, a, b, algo, "overflow")
+    say("shared capacity: core numbers")
+    core, mx = pkg.abcore_core_numbers(g)
+    want = oracle.core_numbers(ref)
+    assert np.array_equal(core.cpu().numpy(), want)
+    assert mx == int(want.max())
+    spec = dict(kind="chung_lu", n_upper=nU, n_lower=nL, m=m, gamma_upper=2.1,
+                gamma_lower=2.1, cap=5000, seed=108)
+    ups = bigraph_gen.update_stream(spec, eu, ev, 40, 1108, qlo=1, qhi=16)
+    want = oracle.gfq_stream(nU, nL, eu, ev, ups)
+    say("shared capacity: 40 GFQ updates")
+    for i in range(len(ups["u"])):
+        ans, bits = pkg.abcore_query(g, ups["u"][i], ups["v"][i], ups["op"][i],
+                                     ups["alpha"][i], ups["beta"][i])
+        st, wans, wbits = want[i]
+        assert st == "OK"
+        assert (ans, bits) == (wans, wbits), f"update {i}"
+    g.destroy()
+
+
 # ----------------------------------------------------------- core numbers --
 
 

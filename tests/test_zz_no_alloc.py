@@ -20,7 +20,7 @@ def test_static_matches_compute_and_oracle():
     ensure_built()
     import paper_2606_07148_amd as pkg
     graphs = []
-    for f in (0.2, 0.05):
+    for f in (1.0, 0.05):
         spec = bigraph_gen.scaled(2, f)
         nU, nL = spec["n_upper"], spec["n_lower"]
         eu, ev = bigraph_gen.make_graph(spec)
@@ -41,8 +41,9 @@ def test_static_matches_compute_and_oracle():
                 assert np.array_equal(got, want), f"static differs from the oracle ({a},{b})"
     for g, _ in graphs:
         g.destroy()
-    # too large for the static array: rejected, nothing written
-    spec = bigraph_gen.scaled(2, 0.3)
+    # too large for the static array (6,000,000 vertices): rejected, nothing
+    # written
+    spec = bigraph_gen.scaled(2, 4.0)
     eu, ev = bigraph_gen.make_graph(spec)
     g = pkg.abcore_build_csr(spec["n_upper"], spec["n_lower"], to_dev(eu), to_dev(ev))
     out = torch.full((g.nwords,), 7, dtype=torch.int32, device="cuda")
