@@ -42,7 +42,8 @@ typedef enum {
   ABCORE_ENOENT = 4,  /* deletion of an edge that is not present */
   ABCORE_EEXIST = 5,  /* insertion of an edge that is already present */
   ABCORE_EBUSY = 6,   /* no admission slot free, or the handle is serving */
-  ABCORE_EAGAIN = 7   /* abcore_poll: the request has not finished yet */
+  ABCORE_EAGAIN = 7,  /* abcore_poll: the request has not finished yet */
+  ABCORE_ETIMEDOUT = 8 /* abcore_poll: past its deadline, query dropped */
 } abcore_status;
 
 /* Algorithms of Sec. IV. */
@@ -117,8 +118,28 @@ abcore_status abcore_graph_report(abcore_graph g, abcore_report *out);
  * peak to the current value after reading).  Host bookkeeping only. */
 abcore_status abcore_device_memory(int64_t *current, int64_t *peak, int32_t reset_peak);
 
+/* Process-wide cap on the device bytes the library holds (every handle and
+ * device together; 0 = none, the default).  An allocation that would exceed
+ * it fails as out of memory: the entry point that needed it returns
+ * ABCORE_ENOMEM and changes nothing (a build creates no handle; a computation
+ * leaves the handle as it was), except abcore_serve_start, which admits with
+ * fewer device working sets when at least one fits (see there).  Lowering
+ * the budget frees nothing.  Errors: EINVAL (negative). */
+abcore_status abcore_set_memory_budget(int64_t bytes);
+
 /* Releases every resource of the handle.  NULL is accepted. */
 abcore_status abcore_destroy(abcore_graph g);
+
+/* Debug builds only (libabcore_debug.so, compiled with ABC_DEBUG_ENQUEUE):
+ * every vertex id appended to the frontier queues is counted per vertex, so
+ * that a test can check the crossing rule of Algorithm 1's peel -- a vertex
+ * is queued when its degree crosses its threshold, once -- and the scan's
+ * frontier.  The counts accumulate over computations on the handle.
+ * d_counts (DEVICE int32[n], nullable) receives them; reset != 0 zeroes them
+ * afterwards.  Synchronous on `stream`.  Errors: EINVAL (null handle, or a
+ * release build, which keeps no counts), EBUSY (serving), EDEVICE. */
+abcore_status abcore_debug_enqueue_counts(abcore_graph g, int32_t *d_counts, int32_t reset,
+                                          void *stream);
 
 /* Sizes: n_upper, n_lower and the current number of distinct edges. */
 abcore_status abcore_graph_info(abcore_graph g, int32_t *n_upper, int32_t *n_lower,
@@ -291,6 +312,10 @@ abcore_status abcore_community(abcore_graph g, int32_t q, uint32_t alpha, uint32
  * edges a single query already saturates the device's random-access
  * throughput, and two working sets measured best); window: most updates
  * per window (0 = 64, at most 64).  Computes the component labels if needed.  Synchronous.
+ * Under a memory budget (abcore_set_memory_budget) it creates as many working
+ * sets as fit, at least one (ENOMEM if none does; abcore_serve_counters
+ * reports how many): windows then take fewer requests and the rest wait,
+ * admitted, until abcore_submit's EBUSY at max_inflight.
  * Errors: EINVAL, ENOMEM, EDEVICE. */
 abcore_status abcore_serve_start(abcore_graph g, int64_t max_inflight, int32_t device_slots,
                                  int32_t window);
@@ -310,15 +335,18 @@ abcore_status abcore_submit(abcore_graph g, abcore_edge_update upd, uint32_t alp
  * it finish) are written (each pointer nullable) and the result is released.
  * EEXIST / ENOENT: the update was rejected (graph unchanged by it).
  * EAGAIN: not finished yet, or already taken.  EINVAL: a ticket never
- * issued.  EDEVICE: the engine failed.  Thread-safe with abcore_submit. */
+ * issued.  ETIMEDOUT: the deadline (ABCORE_OPT_SERVE_DEADLINE_US) passed
+ * before the request's query started: its update was applied as usual, the
+ * query was dropped and nothing else is written.  EDEVICE: the engine
+ * failed.  Thread-safe with abcore_submit. */
 abcore_status abcore_poll(abcore_graph g, uint64_t ticket, int32_t *answer,
                           uint32_t *endpoint_bits, uint64_t *t_done_ns);
 
-/* Counters of the serving engine (HOST int64[count], count <= 6): windows
+/* Counters of the serving engine (HOST int64[count], count <= 8): windows
  * run, requests answered, requests rejected, requests decided without a
- * peel by stale core-number pruning, core-number snapshots taken, and their
- * total wall time in microseconds.  Valid while serving and after
- * abcore_serve_stop. */
+ * peel by stale core-number pruning, core-number snapshots taken, their
+ * total wall time in microseconds, requests past their deadline, and device
+ * working sets in use.  Valid while serving and after abcore_serve_stop. */
 abcore_status abcore_serve_counters(abcore_graph g, int64_t *out, int32_t count);
 
 /* Waits for every admitted request to finish, stops the worker and frees the
@@ -386,6 +414,12 @@ abcore_status abcore_serve_stop(abcore_graph g, int64_t *counters);
  *                          of the asynchronous peel makes before it declares
  *                          a hang and aborts (0 = the default, 2^21, i.e.
  *                          seconds; small values make peels abort at once).
+ *   ABCORE_OPT_SERVE_DEADLINE_US: per-request deadline of the serving
+ *                          engine, from admission (set before
+ *                          abcore_serve_start; 0 = none, the default): a
+ *                          request whose query would start later is answered
+ *                          ABCORE_ETIMEDOUT by abcore_poll; its update is
+ *                          applied all the same, so the stream stays ordered.
  *   ABCORE_OPT_APPEND_SUBQUEUE: test of the frontier queue's shared capacity
  *                          (the 16 sub-queues together hold the bound of
  *                          2n + pieces + 256 appends per computation, each a
@@ -418,7 +452,8 @@ enum {
   ABCORE_OPT_AUTOTUNE = 9,
   ABCORE_OPT_SERVE_PRUNE = 10,
   ABCORE_OPT_KCORE_SWITCH = 11,
-  ABCORE_OPT_APPEND_SUBQUEUE = 12
+  ABCORE_OPT_APPEND_SUBQUEUE = 12,
+  ABCORE_OPT_SERVE_DEADLINE_US = 13
 };
 abcore_status abcore_set_option(abcore_graph g, int32_t option, int64_t value);
 

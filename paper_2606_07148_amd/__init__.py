@@ -9,12 +9,14 @@ package raises ``ImportError`` when the library has not been built.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import re
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libabcore.so")
+DEBUG_LIB_PATH = os.path.join(_HERE, "libabcore_debug.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "abcore.h")
 
 ABCORE_GCC = 0
@@ -31,9 +33,10 @@ ABCORE_OPT_AUTOTUNE = 9
 ABCORE_OPT_SERVE_PRUNE = 10
 ABCORE_OPT_KCORE_SWITCH = 11
 ABCORE_OPT_APPEND_SUBQUEUE = 12
+ABCORE_OPT_SERVE_DEADLINE_US = 13
 
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOENT", 5: "EEXIST",
-          6: "EBUSY", 7: "EAGAIN"}
+          6: "EBUSY", 7: "EAGAIN", 8: "ETIMEDOUT"}
 
 
 class AbcoreError(RuntimeError):
@@ -71,23 +74,46 @@ class abcore_edge_update(ctypes.Structure):
 
 
 _lib = None
+_libs = {}
 
 
 def load():
     """The loaded library; ImportError if it has not been built."""
     global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"libabcore.so not built ({LIB_PATH}); run "
+    if _lib is None:
+        _lib = _open(LIB_PATH)
+    return _lib
+
+
+@contextlib.contextmanager
+def debug_library():
+    """Within the block every call goes to libabcore_debug.so, the same
+    sources built with per-vertex enqueue counters (ABC_DEBUG_ENQUEUE).
+    Handles made inside the block belong to that library; destroy them
+    before leaving it (a Graph keeps the library that made it)."""
+    global _lib
+    prev = load()
+    _lib = _open(DEBUG_LIB_PATH)
+    try:
+        yield _lib
+    finally:
+        _lib = prev
+
+
+def _open(path):
+    if path in _libs:
+        return _libs[path]
+    if not os.path.exists(path):
+        raise ImportError(f"{os.path.basename(path)} not built ({path}); run "
                           "`python -m paper_2606_07148_amd.build`")
-    lib = ctypes.CDLL(LIB_PATH)
+    lib = ctypes.CDLL(path)
     vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
     P = ctypes.POINTER
     sig = {
         "abcore_last_error": (ctypes.c_char_p, []),
         "abcore_build_csr": (i32, [i32, i32, vp, vp, i64, vp, P(vp), P(i64)]),
         "abcore_destroy": (i32, [vp]),
+        "abcore_debug_enqueue_counts": (i32, [vp, vp, i32, vp]),
         "abcore_graph_info": (i32, [vp, P(i32), P(i32), P(i64)]),
         "abcore_export_csr": (i32, [vp, vp, vp, P(i64), vp]),
         "abcore_compute": (i32, [vp, u32, u32, i32, vp, P(abcore_stats), vp]),
@@ -111,6 +137,7 @@ def load():
         "abcore_serve_counters": (i32, [vp, P(i64), i32]),
         "abcore_graph_report": (i32, [vp, P(abcore_report)]),
         "abcore_device_memory": (i32, [P(i64), P(i64), i32]),
+        "abcore_set_memory_budget": (i32, [i64]),
         "abcore_tuned": (i32, [vp, i32, P(i32), P(i32), P(ctypes.c_double), P(i32)]),
         "abcore_tune_cache": (i32, [ctypes.c_char_p, i32]),
         "abcore_autotune": (i32, [vp, u32, u32, i32, P(i32), P(i32), P(ctypes.c_double), vp]),
@@ -119,7 +146,7 @@ def load():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    _lib = lib
+    _libs[path] = lib
     return lib
 
 
@@ -151,6 +178,7 @@ class Graph:
 
     def __init__(self, handle, n_upper, n_lower, m):
         self._h = handle
+        self._lib = load()
         self.n_upper = n_upper
         self.n_lower = n_lower
         self.n = n_upper + n_lower
@@ -168,7 +196,7 @@ class Graph:
 
     def destroy(self):
         if self._h is not None:
-            load().abcore_destroy(self._h)
+            self._lib.abcore_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -212,6 +240,21 @@ def abcore_device_memory(reset_peak: bool = False):
     cur, peak = ctypes.c_int64(), ctypes.c_int64()
     _check(load().abcore_device_memory(ctypes.byref(cur), ctypes.byref(peak), int(reset_peak)))
     return int(cur.value), int(peak.value)
+
+
+def abcore_debug_enqueue_counts(g: Graph, reset: bool = False, stream=None):
+    """Per-vertex counts of appends to the frontier queues since the last
+    reset (debug library only; EINVAL from the release library)."""
+    import torch
+    out = torch.zeros(max(g.n, 1), dtype=torch.int32, device="cuda")
+    _check(load().abcore_debug_enqueue_counts(g.handle, _ptr(out), int(bool(reset)),
+                                              _stream(stream)))
+    return out[: g.n]
+
+
+def abcore_set_memory_budget(nbytes: int) -> None:
+    """Process-wide cap on the library's device bytes (0 = none)."""
+    _check(load().abcore_set_memory_budget(int(nbytes)))
 
 
 def abcore_destroy(g: Graph) -> None:
@@ -344,7 +387,8 @@ def abcore_try_submit(g: Graph, u: int, v: int, op: int, alpha: int, beta: int):
 
 def abcore_poll(g: Graph, ticket: int):
     """None while the request runs; else a dict with status ("OK", "EEXIST",
-    "ENOENT", ...), answer, bits and t_done_ns (time.monotonic_ns clock)."""
+    "ENOENT", "ETIMEDOUT", ...), answer, bits and t_done_ns (time.monotonic_ns
+    clock)."""
     ans = ctypes.c_int32()
     bits = ctypes.c_uint32()
     t = ctypes.c_uint64()
@@ -352,7 +396,7 @@ def abcore_poll(g: Graph, ticket: int):
                             ctypes.byref(t))
     if st == 7:
         return None
-    if st not in (0, 4, 5):
+    if st not in (0, 4, 5, 8):
         _check(st)
     return {"status": STATUS[st], "answer": bool(ans.value), "bits": int(bits.value),
             "t_done_ns": int(t.value)}
@@ -360,11 +404,11 @@ def abcore_poll(g: Graph, ticket: int):
 
 def abcore_serve_counters(g: Graph) -> dict:
     """The serving engine's counters."""
-    c = (ctypes.c_int64 * 6)()
-    _check(load().abcore_serve_counters(g.handle, c, 6))
+    c = (ctypes.c_int64 * 8)()
+    _check(load().abcore_serve_counters(g.handle, c, 8))
     return {"windows": int(c[0]), "answered": int(c[1]), "rejected": int(c[2]),
             "decided_without_peel": int(c[3]), "core_snapshots": int(c[4]),
-            "snapshot_ms": c[5] / 1e3}
+            "snapshot_ms": c[5] / 1e3, "timed_out": int(c[6]), "device_slots": int(c[7])}
 
 
 def abcore_serve_stop(g: Graph) -> dict:

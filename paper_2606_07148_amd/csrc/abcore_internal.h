@@ -260,6 +260,8 @@ struct Graph {
   int32_t *h_abort = nullptr;
   uint32_t spin_limit = 0;  // ABCORE_OPT_SPIN_LIMIT (0 = kAsyncSpinLimit)
   int32_t append_sub = -1;  // ABCORE_OPT_APPEND_SUBQUEUE - 1
+  int32_t *dbg_enqueue = nullptr;  // debug builds: int32[n] enqueue counts
+  int64_t serve_deadline_us = 0;   // ABCORE_OPT_SERVE_DEADLINE_US (0: none)
   int rs_parity = 0;  // flips with every exchange of state and state_alt
   // Pull round work split: workgroup k of a cu_count grid walks the upper
   // rows [b[k], b[k+1]) and the lower rows [b[G+1+k], b[G+2+k]), ranges of
@@ -390,6 +392,8 @@ struct PeelArgs {
   // Sub-queue every append tries first (-1: the producer's own; a fixed one
   // makes appends overflow into the others, ABCORE_OPT_APPEND_SUBQUEUE).
   int32_t append_sub;
+  // Debug builds: per-vertex counts of appends to the frontier queues.
+  int32_t *dbg_enqueue;
   int64_t n;
   int32_t nU;
   int32_t thrU, thrL;

@@ -21,14 +21,27 @@ static thread_local char g_error[512] = "";
 static std::mutex g_mem_mu;
 static std::unordered_map<void *, size_t> g_mem_sizes;
 static int64_t g_mem_current = 0, g_mem_peak = 0;
+static int64_t g_mem_budget = 0;  // abcore_set_memory_budget (0: none)
 
+// Every device allocation of the library.  Under a budget the bytes are
+// reserved before hipMalloc, so that concurrent callers cannot overrun it;
+// a request beyond it fails as out of memory.
 hipError_t dev_malloc_bytes(void **p, size_t bytes) {
-  hipError_t e = hipMalloc(p, bytes);
-  if (e == hipSuccess && *p != nullptr) {
+  {
     std::lock_guard<std::mutex> lock(g_mem_mu);
-    g_mem_sizes[*p] = bytes;
+    if (g_mem_budget > 0 && g_mem_current + (int64_t)bytes > g_mem_budget) {
+      *p = nullptr;
+      return hipErrorOutOfMemory;
+    }
     g_mem_current += (int64_t)bytes;
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  std::lock_guard<std::mutex> lock(g_mem_mu);
+  if (e == hipSuccess && *p != nullptr) {
+    g_mem_sizes[*p] = bytes;
     g_mem_peak = std::max(g_mem_peak, g_mem_current);
+  } else {
+    g_mem_current -= (int64_t)bytes;
   }
   return e;
 }
@@ -218,7 +231,8 @@ void free_graph(Graph *g) {
                   g->pull_bounds, g->row_bits,    g->split_written, g->rank,
                   g->rcols,       g->rank_vtx,    g->roff,        g->rp_row,
                   g->rp_start,    g->rp_first,    g->rdeg,        g->state_alt,
-                  g->part_alt,    g->rs_fail,     g->aux,         g->probe_bits};
+                  g->part_alt,    g->rs_fail,     g->aux,         g->probe_bits,
+                  g->dbg_enqueue};
   for (void *p : bufs)
     if (p) (void)dev_free(p);
   if (g->h_abort) (void)hipHostFree(g->h_abort);
@@ -839,6 +853,15 @@ abcore_status abcore_build_csr(int32_t n_upper, int32_t n_lower, const int32_t *
       break;
     }
     memset(g->h_state, 0, sizeof(PeelState));
+#ifdef ABC_DEBUG_ENQUEUE
+    if ((st = ensure(&g->dbg_enqueue, g->n)) != ABCORE_OK) break;
+    if (hipMemsetAsync(g->dbg_enqueue, 0, sizeof(int32_t) * std::max<int64_t>(g->n, 1), s) !=
+        hipSuccess) {
+      set_error("abcore_build_csr: debug counter initialisation failed");
+      st = ABCORE_EDEVICE;
+      break;
+    }
+#endif
     if (query_persistent_grids(*g) != hipSuccess) {
       // no co-residency information: the cooperative kernels are not used
       g->persistent_grid = 0;
@@ -889,6 +912,16 @@ abcore_status abcore_graph_report(abcore_graph h, abcore_report *out) {
   return ABCORE_OK;
 }
 
+abcore_status abcore_set_memory_budget(int64_t bytes) {
+  if (bytes < 0) {
+    set_error("abcore_set_memory_budget: negative budget");
+    return ABCORE_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_mem_mu);
+  g_mem_budget = bytes;
+  return ABCORE_OK;
+}
+
 abcore_status abcore_device_memory(int64_t *current, int64_t *peak, int32_t reset_peak) {
   std::lock_guard<std::mutex> lock(g_mem_mu);
   if (current) *current = g_mem_current;
@@ -899,6 +932,28 @@ abcore_status abcore_device_memory(int64_t *current, int64_t *peak, int32_t rese
 
 abcore_status abcore_destroy(abcore_graph h) {
   free_graph(reinterpret_cast<Graph *>(h));
+  return ABCORE_OK;
+}
+
+abcore_status abcore_debug_enqueue_counts(abcore_graph h, int32_t *d_counts, int32_t reset,
+                                          void *stream) {
+  Graph *g = reinterpret_cast<Graph *>(h);
+  if (!g) {
+    set_error("abcore_debug_enqueue_counts: null handle");
+    return ABCORE_EINVAL;
+  }
+  if (serving(*g)) return busy_error(__func__);
+  if (g->dbg_enqueue == nullptr) {
+    set_error("abcore_debug_enqueue_counts: not a debug build (ABC_DEBUG_ENQUEUE)");
+    return ABCORE_EINVAL;
+  }
+  (void)hipSetDevice(g->device);
+  hipStream_t s = as_stream(stream);
+  const size_t bytes = sizeof(int32_t) * (size_t)std::max<int64_t>(g->n, 1);
+  if (d_counts != nullptr)
+    CHK(hipMemcpyAsync(d_counts, g->dbg_enqueue, bytes, hipMemcpyDeviceToDevice, s));
+  if (reset) CHK(hipMemsetAsync(g->dbg_enqueue, 0, bytes, s));
+  CHK(hipStreamSynchronize(s));
   return ABCORE_OK;
 }
 
@@ -982,6 +1037,9 @@ abcore_status abcore_set_option(abcore_graph h, int32_t option, int64_t value) {
         return ABCORE_EINVAL;
       }
       g->rank_order = value != 2;
+      return ABCORE_OK;
+    case ABCORE_OPT_SERVE_DEADLINE_US:
+      g->serve_deadline_us = value;
       return ABCORE_OK;
     case ABCORE_OPT_APPEND_SUBQUEUE:
       if (value > kSub) {

@@ -154,6 +154,7 @@ PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL) {
   a.spin_limit = g.spin_limit > 0 ? g.spin_limit : kAsyncSpinLimit;
   a.abort_host = g.h_abort;
   a.append_sub = g.append_sub;
+  a.dbg_enqueue = g.dbg_enqueue;
   // any launch but a query in rank order may leave the queue in use
   g.rs_ready = false;
   a.n = g.n;
@@ -273,7 +274,10 @@ struct ScanCollector {
     __syncthreads();
     if (rsub >= 0) {
       int32_t *q = a.queue + (int64_t)rsub * a.qcap + base;
-      for (int i = threadIdx.x; i < c; i += blockDim.x) q[i] = buf[i];
+      for (int i = threadIdx.x; i < c; i += blockDim.x) {
+        q[i] = buf[i];
+        ABC_COUNT_ENQUEUE(a.dbg_enqueue, buf[i]);
+      }
     }
     __syncthreads();
     if (threadIdx.x == 0) count = 0;
@@ -1564,7 +1568,9 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
         int pos = __shfl(r.y, kWave - 1, kWave) + incl - cnt;
         int32_t *q = a.queue + (int64_t)rs * a.qcap;
         while (rs >= 0 && dead != 0) {
-          q[pos++] = (int32_t)((w << 5) + (__ffs(dead) - 1));
+          const int32_t x = (int32_t)((w << 5) + (__ffs(dead) - 1));
+          q[pos++] = x;
+          ABC_COUNT_ENQUEUE(a.dbg_enqueue, x);
           dead &= dead - 1;
         }
       }

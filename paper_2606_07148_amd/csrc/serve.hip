@@ -42,6 +42,7 @@ struct Request {
   uint64_t ticket;
   int32_t u, v, op;
   int32_t thrU, thrL;
+  uint64_t t_submit;  // steady-clock nanoseconds at admission
 };
 
 struct Result {
@@ -103,8 +104,9 @@ struct Server {
   int64_t since_refresh = 0;
   // counters
   int64_t windows = 0, served = 0, rejected = 0;
-  int64_t decided = 0, refreshes = 0;
+  int64_t decided = 0, refreshes = 0, timed_out = 0;
   double refresh_ms = 0;
+  int64_t device_slots = 0;  // working sets in use (fewer under a memory budget)
 };
 
 namespace {
@@ -161,6 +163,8 @@ void finish(Server &S, uint64_t ticket, Result r) {
   S.inflight -= 1;
   if (r.status == ABCORE_OK)
     S.served += 1;
+  else if (r.status == ABCORE_ETIMEDOUT)
+    S.timed_out += 1;
   else
     S.rejected += 1;
 }
@@ -323,9 +327,21 @@ bool run_window(Graph &g, Server &S, const std::vector<Request> &win) {
     }
     if (!S.core_h.empty()) {
       // the snapshot's intervals, widened by this update and those before
-      const int32_t x = win[i].u, y = g.nU + win[i].v;
-      widen_for_update(S, x, y, win[i].op);
+      widen_for_update(S, win[i].u, g.nU + win[i].v, win[i].op);
       S.since_refresh += 1;
+    }
+    if (g.serve_deadline_us > 0 &&
+        now_ns() > win[i].t_submit + (uint64_t)g.serve_deadline_us * 1000ull) {
+      // past its deadline before its query started: the update stays
+      // applied, the query is dropped
+      Result res{};
+      res.status = ABCORE_ETIMEDOUT;
+      res.t_done = now_ns();
+      finish(S, win[i].ticket, res);
+      continue;
+    }
+    if (!S.core_h.empty()) {
+      const int32_t x = win[i].u, y = g.nU + win[i].v;
       const int32_t dl = std::min(win[i].thrU, win[i].thrL);
       const int32_t dq = std::max(win[i].thrU, win[i].thrL);
       const int cu = classify(S, x, dl, dq), cv = classify(S, y, dl, dq);
@@ -521,15 +537,13 @@ abcore_status serve_start(Graph &g, int64_t max_inflight, int32_t slots, int32_t
   S.fail.clear();
   S.max_inflight = max_inflight;
   S.window_max = std::max(1, std::min(window, kWindowMax));
-  S.slots.assign(slots, Slot());
+  S.slots.clear();
   hipError_t e = hipStreamCreateWithFlags(&S.main, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&S.applied, hipEventDisableTiming);
   if (e == hipSuccess) e = dev_malloc(&S.d_upd, sizeof(int32_t) * 3 * kWindowMax);
   if (e == hipSuccess) e = hipHostMalloc(&S.h_upd, sizeof(int32_t) * 3 * kWindowMax);
   if (e == hipSuccess) e = dev_malloc(&S.d_rec, sizeof(WindowRecord) * kWindowMax);
   if (e == hipSuccess) e = hipHostMalloc(&S.h_rec, sizeof(WindowRecord) * kWindowMax);
-  for (Slot &s : S.slots)
-    if (e == hipSuccess) e = alloc_slot(g, s);
   if (e == hipSuccess && g.del_ver == nullptr) {
     e = dev_malloc(&g.del_ver, sizeof(int32_t) * std::max<int64_t>(2 * g.m_csr, 1));
     if (e == hipSuccess) e = hipMemset(g.del_ver, 0, sizeof(int32_t) * std::max<int64_t>(2 * g.m_csr, 1));
@@ -546,8 +560,29 @@ abcore_status serve_start(Graph &g, int64_t max_inflight, int32_t slots, int32_t
     free_server_device(S);
     return st;
   }
+  // Admission under a memory budget (abcore_set_memory_budget): as many
+  // device working sets as fit, at least one; fewer working sets mean fewer
+  // requests per window, and the rest wait in the admission queue (EBUSY
+  // once max_inflight are admitted).
+  for (int i = 0; i < slots; ++i) {
+    S.slots.emplace_back();
+    e = alloc_slot(g, S.slots.back());
+    if (e != hipSuccess) {
+      free_slot(S.slots.back());
+      S.slots.pop_back();
+      if (e == hipErrorOutOfMemory && !S.slots.empty()) e = hipSuccess;
+      break;
+    }
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_server_device(S);
+    set_error("serving: working-set allocation failed: %s", hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? ABCORE_ENOMEM : ABCORE_EDEVICE;
+  }
+  S.device_slots = (int64_t)S.slots.size();
   S.core_h.clear();
-  S.decided = S.refreshes = 0;
+  S.decided = S.refreshes = S.timed_out = 0;
   S.refresh_ms = 0;
   if (g.serve_prune > 0 && !refresh_cores(g, S)) {
     free_server_device(S);
@@ -585,6 +620,7 @@ abcore_status serve_submit(Graph &g, const abcore_edge_update &upd, int32_t thrU
   r.op = upd.op;
   r.thrU = thrU;
   r.thrL = thrL;
+  r.t_submit = now_ns();
   S.pending.push_back(r);
   S.inflight += 1;
   *ticket = r.ticket;
@@ -613,16 +649,20 @@ abcore_status serve_poll(Graph &g, uint64_t ticket, int32_t *answer, uint32_t *b
   if (answer) *answer = r.answer;
   if (bits) *bits = r.bits;
   if (t_done) *t_done = r.t_done;
-  if (r.status != ABCORE_OK) set_error("served update rejected or failed (status %d)", r.status);
+  if (r.status == ABCORE_ETIMEDOUT)
+    set_error("served request past its deadline: its update was applied, its query dropped");
+  else if (r.status != ABCORE_OK)
+    set_error("served update rejected or failed (status %d)", r.status);
   return (abcore_status)r.status;
 }
 
 void serve_counters(const Graph &g, int64_t *out, int count) {
   const Server *S = g.server;
-  const int64_t v[6] = {S ? S->windows : 0,  S ? S->served : 0,    S ? S->rejected : 0,
-                        S ? S->decided : 0,  S ? S->refreshes : 0,
-                        S ? (int64_t)(S->refresh_ms * 1000.0) : 0};
-  for (int i = 0; i < count && i < 6; ++i) out[i] = v[i];
+  const int64_t v[8] = {S ? S->windows : 0,   S ? S->served : 0,    S ? S->rejected : 0,
+                        S ? S->decided : 0,   S ? S->refreshes : 0,
+                        S ? (int64_t)(S->refresh_ms * 1000.0) : 0,
+                        S ? S->timed_out : 0, S ? S->device_slots : 0};
+  for (int i = 0; i < count && i < 8; ++i) out[i] = v[i];
 }
 
 }  // namespace abc

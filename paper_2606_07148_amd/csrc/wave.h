@@ -94,6 +94,21 @@ __device__ __forceinline__ int2 reserve_slots(PeelState *st, int32_t *queue, int
   return make_int2(-1, 0);
 }
 
+// Debug builds (ABC_DEBUG_ENQUEUE) count every vertex that enters the
+// frontier (a wave's local queue or a sub-queue), per vertex, so that tests
+// can check that each removal is queued exactly once (the crossing rule);
+// release builds emit nothing.
+#ifdef ABC_DEBUG_ENQUEUE
+#define ABC_COUNT_ENQUEUE(counts, x)                                   \
+  do {                                                                 \
+    if ((counts) != nullptr && (x) >= 0) atomicAdd(&(counts)[(x)], 1); \
+  } while (0)
+#else
+#define ABC_COUNT_ENQUEUE(counts, x) \
+  do {                               \
+  } while (0)
+#endif
+
 // The sub-queue an append tries first.
 __device__ __forceinline__ int append_pref(const PeelArgs &a, int own) {
   return a.append_sub >= 0 ? a.append_sub : own;
@@ -117,6 +132,7 @@ struct LocalQueue {
   int64_t qcap;
   PeelState *st;
   int *abort_host;
+  int32_t *dbg;   // debug builds: per-vertex enqueue counts
   int sub;
 
   __device__ __forceinline__ void flush() {
@@ -139,7 +155,12 @@ struct LocalQueue {
     int c = __popcll(mask);
     if (c == 0) return;
     if (count + c > cap) flush();
-    if (pred) buf[count + __popcll(mask & lanemask_lt())] = val;
+    if (pred) {
+      buf[count + __popcll(mask & lanemask_lt())] = val;
+      // counted on entry: a wave may process its own removals without
+      // ever sharing them
+      ABC_COUNT_ENQUEUE(dbg, val);
+    }
     count += c;
   }
 };
@@ -155,6 +176,7 @@ __device__ __forceinline__ LocalQueue make_lq(int32_t *buf, int cap, const PeelA
   lq.qcap = a.qcap;
   lq.st = a.st;
   lq.abort_host = a.abort_host;
+  lq.dbg = a.dbg_enqueue;
   lq.sub = append_pref(a, sub);
   return lq;
 }

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def ensure_built():
     import paper_2606_07148_amd as pkg
-    if not os.path.exists(pkg.LIB_PATH):
+    if not (os.path.exists(pkg.LIB_PATH) and os.path.exists(pkg.DEBUG_LIB_PATH)):
         sys.path.insert(0, ROOT)
         import __graft_entry__
         __graft_entry__.build()

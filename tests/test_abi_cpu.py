@@ -43,3 +43,19 @@ def test_null_handle_and_bad_arguments_rejected(lib):
     assert lib.abcore_submit(None, upd, 1, 1, ctypes.byref(t)) == EINVAL
     assert lib.abcore_poll(None, 0, None, None, None) == EINVAL
     assert lib.abcore_serve_stop(None, None) == EINVAL
+
+
+def test_budget_and_debug_entry_points_validate_arguments(lib):
+    EINVAL = 1
+    assert lib.abcore_set_memory_budget(-1) == EINVAL
+    assert lib.abcore_set_memory_budget(1 << 30) == 0
+    assert lib.abcore_set_memory_budget(0) == 0  # back to no budget
+    assert lib.abcore_debug_enqueue_counts(None, None, 0, None) == EINVAL
+    assert lib.abcore_set_option(None, pkg.ABCORE_OPT_SERVE_DEADLINE_US, 10) == EINVAL
+
+
+def test_debug_library_exports_the_same_symbols():
+    with pkg.debug_library() as dlib:
+        for name in pkg.declared_symbols():
+            assert hasattr(dlib, name), name
+    assert pkg.load() is not dlib
