@@ -57,9 +57,12 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
+    # ABC_BIGRAPH_GEN_LIB: another build of the same source (the sanitizer test loads
+    # one compiled with AddressSanitizer and UndefinedBehaviorSanitizer)
+    path = os.environ.get("ABC_BIGRAPH_GEN_LIB", _LIB_PATH)
+    if path == _LIB_PATH and not os.path.exists(_LIB_PATH):
         build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    lib = ctypes.CDLL(path)
     i32p = ctypes.POINTER(ctypes.c_int32)
     f64p = ctypes.POINTER(ctypes.c_double)
     lib.bg_uniform.restype = ctypes.c_int64

@@ -30,9 +30,12 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
+    # ABC_CPU_PEEL_LIB: another build of the same source (the sanitizer test loads
+    # one compiled with AddressSanitizer and UndefinedBehaviorSanitizer)
+    path = os.environ.get("ABC_CPU_PEEL_LIB", _LIB_PATH)
+    if path == _LIB_PATH and not os.path.exists(_LIB_PATH):
         build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     lib.cp_peel.restype = ctypes.c_int
     lib.cp_peel.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_int64,

@@ -15,7 +15,9 @@ import os
 import re
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libabcore.so")
+# ABCORE_LIBRARY: another build of the same sources (the sanitizer test
+# loads one whose host code is compiled with AddressSanitizer)
+LIB_PATH = os.environ.get("ABCORE_LIBRARY", os.path.join(_HERE, "libabcore.so"))
 DEBUG_LIB_PATH = os.path.join(_HERE, "libabcore_debug.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "abcore.h")
 
