@@ -43,14 +43,20 @@ def _cpu_model() -> str:
     return platform.processor()
 
 
+# The sources of the GCC step's kernels, their launches and the data layout
+# they read (the core-number, component, vertex-set and serving sources are
+# not part of the step).
+STEP_SOURCES = ("abcore_internal.h", "api.hip", "build.hip", "peel.hip", "prim.h", "wave.h")
+
+
 def _kernel_source_hash() -> str:
-    """SHA-256 over the kernel sources, sorted by name (name, then content)."""
-    import glob
+    """SHA-256 over the GCC step's sources, sorted by name (name, then
+    content)."""
     import hashlib
     h = hashlib.sha256()
-    for path in sorted(glob.glob(os.path.join(ROOT, "paper_2606_07148_amd", "csrc", "*"))):
-        h.update(os.path.basename(path).encode())
-        with open(path, "rb") as f:
+    for name in sorted(STEP_SOURCES):
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_2606_07148_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 

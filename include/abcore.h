@@ -403,7 +403,7 @@ abcore_status abcore_serve_stop(abcore_graph g, int64_t *counters);
  *                          without a peel.  Results stay exact.
  *   ABCORE_OPT_KCORE_SWITCH: core numbers (default peel mode): levels are
  *                          peeled one by one until at most `value` vertices
- *                          are live (0 = 131072; checked between batches of
+ *                          are live (0 = 262144; checked between batches of
  *                          levels); the rest -- the k0-core, whose core
  *                          numbers in G are its own -- is finished by the
  *                          h-index fixpoint (iterate est(x) <- h-index of the

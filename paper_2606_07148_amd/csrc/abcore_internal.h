@@ -62,9 +62,10 @@ constexpr int32_t kDegOut = -1;
 // beyond any legitimate wait of a peel).  ABCORE_OPT_SPIN_LIMIT lowers it.
 constexpr uint32_t kAsyncSpinLimit = 1u << 21;
 // Live vertices at or below which the core decomposition leaves the level
-// peel for the h-index fixpoint (measured best at about 5e4 to 1.6e5 live
-// vertices on the 2e7- and 1e9-edge power-law graphs).
-constexpr int64_t kKcoreSwitch = 1 << 17;
+// peel for the h-index fixpoint (measured best at 2^18 on the 2e7-, 5e8- and
+// 1e9-edge power-law graphs: 10, 129 and 222 ms, against 20, 159 and 239 ms
+// at 2^17).
+constexpr int64_t kKcoreSwitch = 1 << 18;
 // Largest usable threshold: kDegIn must stay above every threshold.
 constexpr int32_t kMaxThreshold = 0x7FFFFFFE;
 // Degree of a removed split row once a consumer has claimed it (far below

@@ -15,10 +15,11 @@
 // small where the number of cascade rounds is large.
 //
 // Here H's adjacency is compacted (local ids, live-live entries only), the
-// sweeps run Jacobi-style (one kernel per sweep reads one buffer and writes
-// the other, so every read is of the previous sweep), a sweep that changes
-// nothing ends the iteration, and the values are written back as core
-// numbers.
+// sweeps update the values in place (Gauss-Seidel: a vertex may already see
+// values its neighbours lowered in the same sweep; every value read is still
+// an upper bound of its core number, so every value computed is too), a
+// sweep that changes nothing ends the iteration, and the values are written
+// back as core numbers.
 #include "abcore_internal.h"
 #include "prim.h"
 #include "wave.h"
@@ -137,20 +138,32 @@ __global__ __launch_bounds__(kBlock) void top_fill_kernel(
 // Loads are issued kUnroll at a time per lane, so a long row keeps many
 // in flight.
 constexpr int kRegSpan = 8;
+
+// A neighbour's value, which other waves may be lowering: a relaxed load
+// that may be served by this compute unit's cache (a stale value is an
+// older, larger one, still an upper bound; a sweep that changes nothing
+// reads only values written before it began, after the caches were
+// invalidated at the kernel boundary).
+__device__ __forceinline__ int32_t ld_near(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
 constexpr int kBins = 2048;
 constexpr int kUnroll = 8;
 
-// One Jacobi sweep: out[j] = largest h <= in[j] with at least h neighbours
-// whose in-value is >= h (>= k0 always: the iterates bound the core numbers,
-// all >= k0, from above).  Only vertices marked in dirty_now are computed
-// (a vertex none of whose neighbours changed would get its value again);
-// each vertex this sweep lowers marks its neighbours in dirty_next.  A
-// sweep after one that changed nothing returns at once (its buffers already
-// hold the fixpoint).  changed[t] counts the vertices this sweep lowered.
+// One sweep in place: est[j] <- largest h <= est[j] with at least h
+// neighbours whose value is >= h (>= k0 always: the iterates bound the core
+// numbers, all >= k0, from above).  Values are written at device scope, so
+// a vertex may see what other waves lowered so far.  Only vertices
+// marked in dirty_now are computed (a vertex none of whose neighbours
+// changed would get its value again); each vertex this sweep lowers marks its
+// neighbours in dirty_next (also those already computed in this sweep with
+// its older value).  A sweep that lowers nothing read only values written
+// before it began, so est is then the fixpoint; the sweeps after it return
+// at once.  changed[t] counts the vertices sweep t lowered.
 __global__ __launch_bounds__(kBlock) void hindex_sweep_kernel(
     const int64_t *__restrict__ hoff, const int32_t *__restrict__ hcols, int64_t h,
-    int32_t k0, const int32_t *__restrict__ in, int32_t *__restrict__ out, int32_t *changed,
-    int t, uint8_t *__restrict__ dirty_now, uint8_t *__restrict__ dirty_next) {
+    int32_t k0, int32_t *est, int32_t *changed, int t, uint8_t *__restrict__ dirty_now,
+    uint8_t *__restrict__ dirty_next) {
   __shared__ int32_t s_bins[kWavesPerBlock][kBins];
   if (t > 0 && ld_agent(&changed[t - 1]) == 0) return;
   int32_t *bins = s_bins[wave_in_block()];
@@ -158,12 +171,9 @@ __global__ __launch_bounds__(kBlock) void hindex_sweep_kernel(
   const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
   int lowered = 0;
   for (int64_t j = gw; j < h; j += nw) {
-    const int32_t cur = in[j];
     // no neighbour changed in the previous sweep: its value stands
-    if (!dirty_now[j]) {
-      if (lane_id() == 0) out[j] = cur;
-      continue;
-    }
+    if (!dirty_now[j]) continue;
+    const int32_t cur = ld_agent(&est[j]);
     __builtin_amdgcn_wave_barrier();
     if (lane_id() == 0) dirty_now[j] = 0;  // cleared for the marks of the next sweep but one
     const int64_t b = hoff[j], e = hoff[j + 1], d = e - b;
@@ -173,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void hindex_sweep_kernel(
 #pragma unroll
       for (int u = 0; u < kRegSpan; ++u) {
         const int64_t k = b + u * kWave + lane_id();
-        v[u] = k < e ? in[hcols[k]] : -1;
+        v[u] = k < e ? ld_near(&est[hcols[k]]) : -1;
       }
       auto count_ge = [&](int32_t th) -> int64_t {
         int64_t c = 0;
@@ -209,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void hindex_sweep_kernel(
           w[u] = k < e ? hcols[k] : -1;
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) v[u] = w[u] >= 0 ? in[w[u]] : -1;
+        for (int u = 0; u < kUnroll; ++u) v[u] = w[u] >= 0 ? ld_near(&est[w[u]]) : -1;
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           top += (int64_t)__popcll(__ballot(v[u] >= cap));
@@ -230,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void hindex_sweep_kernel(
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u)
-              c += (int64_t)__popcll(__ballot(w[u] >= 0 && in[w[u]] >= th));
+              c += (int64_t)__popcll(__ballot(w[u] >= 0 && ld_near(&est[w[u]]) >= th));
           }
           return c;
         };
@@ -271,8 +281,8 @@ __global__ __launch_bounds__(kBlock) void hindex_sweep_kernel(
       }
       __builtin_amdgcn_wave_barrier();
     }
-    if (lane_id() == 0) out[j] = res;
     if (res != cur) {
+      if (lane_id() == 0) st_agent(&est[j], res);
       // its neighbours are recomputed in the next sweep
       ++lowered;
       for (int64_t k = b + lane_id(); k < e; k += kWave) dirty_next[hcols[k]] = 1;
@@ -346,7 +356,7 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
     h = h32;
     if (!ok(dev_malloc(&hlen, sizeof(int64_t) * (h + 1))) ||
         !ok(dev_malloc(&hoff, sizeof(int64_t) * (h + 1))) ||
-        !ok(dev_malloc(&est, sizeof(int32_t) * 2 * std::max<int64_t>(h, 1)))) {
+        !ok(dev_malloc(&est, sizeof(int32_t) * std::max<int64_t>(h, 1)))) {
       st = ABCORE_ENOMEM;
       break;
     }
@@ -383,18 +393,15 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
     if (h > 0 && (!ok(hipMemsetAsync(dirty, 1, sizeof(uint8_t) * h, s)) ||
                   !ok(hipMemsetAsync(dirty + h, 0, sizeof(uint8_t) * h, s))))
       break;
-    // Jacobi sweeps, checked every sweeps_per_check: sweep t reads buffer
-    // t % 2 and writes the other
+    // sweeps in place, checked every sweeps_per_check
     int t = 0, fixed_at = -1;
     std::vector<int32_t> hc(sweeps_per_check);
     bool failed = false;
     while (t < max_sweeps && fixed_at < 0 && h > 0) {
       const int t0 = t;
       for (int r = 0; r < sweeps_per_check && t < max_sweeps; ++r, ++t) {
-        const int32_t *in = est + (t % 2) * h;
-        int32_t *out = est + ((t + 1) % 2) * h;
         hindex_sweep_kernel<<<grid_of(g, h * kWave, kBlock), kBlock, 0, s>>>(
-            hoff, hcols, h, k0, in, out, ctr, t, dirty + (t % 2) * h, dirty + ((t + 1) % 2) * h);
+            hoff, hcols, h, k0, est, ctr, t, dirty + (t % 2) * h, dirty + ((t + 1) % 2) * h);
       }
       if (!ok(hipGetLastError()) ||
           !ok(hipMemcpyAsync(hc.data(), ctr + t0, sizeof(int32_t) * (t - t0),
@@ -414,12 +421,11 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
       st = ABCORE_OK;  // not converged: the caller continues level by level
       break;
     }
-    // the fixpoint is in the buffer the converged sweep wrote (equal to its input)
     g.top_stats[0] = k0;
     g.top_stats[1] = h;
     g.top_stats[2] = eh;
     g.top_stats[3] = fixed_at + 1;
-    const int32_t *fin = est + ((fixed_at + 1) % 2) * h;
+    const int32_t *fin = est;
     int32_t *dmax = ctr + nctr;
     int32_t hmax = 0;
     if (!ok(hipMemsetAsync(dmax, 0, sizeof(int32_t), s))) break;
