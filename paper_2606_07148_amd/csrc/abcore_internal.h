@@ -403,14 +403,24 @@ struct PeelArgs {
 void set_error(const char *fmt, ...);
 PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL);
 
-// Every device allocation of the library goes through these two, which keep
-// the library-wide current and peak byte counts (abcore_device_memory).
+// Every device allocation of the library goes through these, which keep
+// the library-wide current and peak byte counts (abcore_device_memory) and
+// apply the budget (abcore_set_memory_budget).  Memory a handle keeps comes
+// from hipMalloc; temporaries of one call (sort keys, scan storage, the
+// compacted deep core) are stream-ordered on the caller's stream
+// (hipMallocAsync / hipFreeAsync), so freeing them waits for nothing.
 hipError_t dev_malloc_bytes(void **p, size_t bytes);
 template <class T>
 hipError_t dev_malloc(T **p, size_t bytes) {
   return dev_malloc_bytes(reinterpret_cast<void **>(p), bytes);
 }
 hipError_t dev_free(void *p);
+hipError_t dev_malloc_async_bytes(void **p, size_t bytes, hipStream_t s);
+template <class T>
+hipError_t dev_malloc_async(T **p, size_t bytes, hipStream_t s) {
+  return dev_malloc_async_bytes(reinterpret_cast<void **>(p), bytes, s);
+}
+hipError_t dev_free_async(void *p, hipStream_t s);
 
 // Launchers (defined in the .hip files).
 // keep_abort: leave the abort flag as it is (several computations in one

@@ -46,17 +46,46 @@ hipError_t dev_malloc_bytes(void **p, size_t bytes) {
   return e;
 }
 
-hipError_t dev_free(void *p) {
-  if (p == nullptr) return hipSuccess;
+hipError_t dev_malloc_async_bytes(void **p, size_t bytes, hipStream_t s) {
   {
     std::lock_guard<std::mutex> lock(g_mem_mu);
-    auto it = g_mem_sizes.find(p);
-    if (it != g_mem_sizes.end()) {
-      g_mem_current -= (int64_t)it->second;
-      g_mem_sizes.erase(it);
+    if (g_mem_budget > 0 && g_mem_current + (int64_t)bytes > g_mem_budget) {
+      *p = nullptr;
+      return hipErrorOutOfMemory;
     }
+    g_mem_current += (int64_t)bytes;
   }
+  hipError_t e = hipMallocAsync(p, bytes, s);
+  std::lock_guard<std::mutex> lock(g_mem_mu);
+  if (e == hipSuccess && *p != nullptr) {
+    g_mem_sizes[*p] = bytes;
+    g_mem_peak = std::max(g_mem_peak, g_mem_current);
+  } else {
+    *p = nullptr;
+    g_mem_current -= (int64_t)bytes;
+  }
+  return e;
+}
+
+static void forget(void *p) {
+  std::lock_guard<std::mutex> lock(g_mem_mu);
+  auto it = g_mem_sizes.find(p);
+  if (it != g_mem_sizes.end()) {
+    g_mem_current -= (int64_t)it->second;
+    g_mem_sizes.erase(it);
+  }
+}
+
+hipError_t dev_free(void *p) {
+  if (p == nullptr) return hipSuccess;
+  forget(p);
   return hipFree(p);
+}
+
+hipError_t dev_free_async(void *p, hipStream_t s) {
+  if (p == nullptr) return hipSuccess;
+  forget(p);
+  return hipFreeAsync(p, s);
 }
 
 // ----------------------------------------------------------- tuning cache --

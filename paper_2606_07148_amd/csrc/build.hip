@@ -206,7 +206,7 @@ abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, i
   BCHK(dev_malloc(&g.deg0, sizeof(int32_t) * std::max<int64_t>(g.n, 1)));
   BCHK(hipMemsetAsync(g.deg0, 0, sizeof(int32_t) * std::max<int64_t>(g.n, 1), s));
   if (m > 0) {
-    BCHK(dev_malloc(&d_bad, sizeof(int32_t)));
+    BCHK(dev_malloc_async(&d_bad, sizeof(int32_t), s));
     BCHK(hipMemsetAsync(d_bad, 0, sizeof(int32_t), s));
     validate_kernel<<<grid, 256, 0, s>>>(eu, ev, m, g.nU, g.nL, d_bad);
     BCHK(hipGetLastError());
@@ -217,9 +217,9 @@ abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, i
       status = ABCORE_EINVAL;
       goto done;
     }
-    BCHK(dev_malloc(&k0, sizeof(uint64_t) * m));
-    BCHK(dev_malloc(&k1, sizeof(uint64_t) * m));
-    BCHK(dev_malloc(&d_nsel, sizeof(int)));
+    BCHK(dev_malloc_async(&k0, sizeof(uint64_t) * m, s));
+    BCHK(dev_malloc_async(&k1, sizeof(uint64_t) * m, s));
+    BCHK(dev_malloc_async(&d_nsel, sizeof(int), s));
     make_keys_kernel<<<grid, 256, 0, s>>>(eu, ev, m, g.nL, k0);
     BCHK(hipGetLastError());
     // temp storage large enough for the sort and the unique selection
@@ -227,7 +227,7 @@ abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, i
     temp_bytes = std::max(temp_bytes, need);
     BCHK(prim::unique(nullptr, need, k1, k0, d_nsel, (size_t)m, s));
     temp_bytes = std::max(temp_bytes, need);
-    BCHK(dev_malloc(&temp, std::max<size_t>(temp_bytes, 16)));
+    BCHK(dev_malloc_async(&temp, std::max<size_t>(temp_bytes, 16), s));
     BCHK(prim::sort_keys(temp, temp_bytes, k0, k1, (size_t)m, 0, ubits, s));
     BCHK(prim::unique(temp, temp_bytes, k1, k0, d_nsel, (size_t)m, s));
     BCHK(hipMemcpyAsync(&h_nsel, d_nsel, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -245,7 +245,7 @@ abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, i
     lower_rows_kernel<<<gridm, 256, 0, s>>>(k0, md, g.nU, g.cols, g.deg0);
     BCHK(hipGetLastError());
   }
-  BCHK(dev_malloc(&deg64, sizeof(int64_t) * (g.n + 1)));
+  BCHK(dev_malloc_async(&deg64, sizeof(int64_t) * (g.n + 1), s));
   {
     const int gridn = std::max(1, std::min(g.cu_count * 8, (int)((g.n + 256) / 256)));
     widen_kernel<<<gridn, 256, 0, s>>>(g.deg0, g.n, deg64);
@@ -253,21 +253,17 @@ abcore_status build_csr_device(Graph &g, const int32_t *eu, const int32_t *ev, i
     need = 0;
     BCHK(prim::exclusive_sum(nullptr, need, deg64, g.off, (size_t)(g.n + 1), s));
     if (need > temp_bytes) {
-      BCHK(dev_free(temp));
+      BCHK(dev_free_async(temp, s));
       temp = nullptr;
       temp_bytes = need;
-      BCHK(dev_malloc(&temp, temp_bytes));
+      BCHK(dev_malloc_async(&temp, temp_bytes, s));
     }
     BCHK(prim::exclusive_sum(temp, temp_bytes, deg64, g.off, (size_t)(g.n + 1), s));
   }
   BCHK(hipStreamSynchronize(s));
 done:
-  if (d_bad) (void)dev_free(d_bad);
-  if (k0) (void)dev_free(k0);
-  if (k1) (void)dev_free(k1);
-  if (d_nsel) (void)dev_free(d_nsel);
-  if (temp) (void)dev_free(temp);
-  if (deg64) (void)dev_free(deg64);
+  for (void *p : {(void *)d_bad, (void *)k0, (void *)k1, (void *)d_nsel, temp, (void *)deg64})
+    if (p) (void)dev_free_async(p, s);
   return status;
 #undef BCHK
 }
@@ -289,14 +285,14 @@ abcore_status build_pieces(Graph &g, hipStream_t s) {
   size_t temp_bytes = 0;
   int64_t h_tot[4] = {0, 0, 0, 0};
   const int grid = std::max(1, std::min(g.cu_count * 8, (int)((g.n + 256) / 256)));
-  PCHK(dev_malloc(&np, sizeof(int64_t) * (g.n + 1)));
-  PCHK(dev_malloc(&hv, sizeof(int64_t) * (g.n + 1)));
-  PCHK(dev_malloc(&first, sizeof(int64_t) * (g.n + 1)));
-  PCHK(dev_malloc(&hfirst, sizeof(int64_t) * (g.n + 1)));
+  PCHK(dev_malloc_async(&np, sizeof(int64_t) * (g.n + 1), s));
+  PCHK(dev_malloc_async(&hv, sizeof(int64_t) * (g.n + 1), s));
+  PCHK(dev_malloc_async(&first, sizeof(int64_t) * (g.n + 1), s));
+  PCHK(dev_malloc_async(&hfirst, sizeof(int64_t) * (g.n + 1), s));
   count_pieces_kernel<<<grid, 256, 0, s>>>(g.off, g.n, np, hv);
   PCHK(hipGetLastError());
   PCHK(prim::exclusive_sum(nullptr, temp_bytes, np, first, (size_t)(g.n + 1), s));
-  PCHK(dev_malloc(&temp, std::max<size_t>(temp_bytes, 16)));
+  PCHK(dev_malloc_async(&temp, std::max<size_t>(temp_bytes, 16), s));
   PCHK(prim::exclusive_sum(temp, temp_bytes, np, first, (size_t)(g.n + 1), s));
   PCHK(prim::exclusive_sum(temp, temp_bytes, hv, hfirst, (size_t)(g.n + 1), s));
   PCHK(hipMemcpyAsync(&h_tot[0], first + g.n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -327,11 +323,8 @@ abcore_status build_pieces(Graph &g, hipStream_t s) {
   PCHK(hipGetLastError());
   PCHK(hipStreamSynchronize(s));
 done:
-  if (np) (void)dev_free(np);
-  if (hv) (void)dev_free(hv);
-  if (first) (void)dev_free(first);
-  if (hfirst) (void)dev_free(hfirst);
-  if (temp) (void)dev_free(temp);
+  for (void *p : {(void *)np, (void *)hv, (void *)first, (void *)hfirst, temp})
+    if (p) (void)dev_free_async(p, s);
   return status;
 #undef PCHK
 }
@@ -435,8 +428,8 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
     g.rdeg_mask = (uint32_t)((1ull << xbits) - 1);
     if (fail(dev_malloc(&g.rdeg, sizeof(int32_t) * ((size_t)g.rdeg_mask + 1)))) break;
     // k0 also holds the degrees by rank (n + 1 values after n + 1 slots)
-    if (fail(dev_malloc(&k0, sizeof(uint64_t) * std::max<int64_t>(items, 2 * (g.n + 1))))) break;
-    if (fail(dev_malloc(&k1, sizeof(uint64_t) * items))) break;
+    if (fail(dev_malloc_async(&k0, sizeof(uint64_t) * std::max<int64_t>(items, 2 * (g.n + 1)), s))) break;
+    if (fail(dev_malloc_async(&k1, sizeof(uint64_t) * items, s))) break;
     // temporary storage for the largest sort, and the offsets' scan
     if (fail(prim::sort_keys(nullptr, need, k0, k1, (size_t)items, 0, 64, s)))
       break;
@@ -446,7 +439,7 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
                                               g.roff, (size_t)(g.n + 1), s)))
       break;
     temp_bytes = std::max(temp_bytes, need);
-    if (fail(dev_malloc(&temp, temp_bytes))) break;
+    if (fail(dev_malloc_async(&temp, temp_bytes, s))) break;
     // ranks, one layer at a time
     for (int layer = 0; layer < 2 && ok; ++layer) {
       const int64_t lo = layer == 0 ? 0 : g.nU, hi = layer == 0 ? g.nU : g.n;
@@ -483,7 +476,7 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
     {
       int64_t *np = reinterpret_cast<int64_t *>(k0), *hv = np + (g.n + 1);
       int64_t *hfirst = nullptr;
-      if (fail(dev_malloc(&hfirst, sizeof(int64_t) * 2 * (g.n + 1)))) break;
+      if (fail(dev_malloc_async(&hfirst, sizeof(int64_t) * 2 * (g.n + 1), s))) break;
       int32_t *hrows = nullptr;
       bool pok = false;
       do {
@@ -498,15 +491,15 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
         if (fail(dev_malloc(&g.rp_start, sizeof(int64_t) * std::max<int64_t>(g.npieces, 1))))
           break;
         if (fail(dev_malloc(&g.rp_first, sizeof(int32_t) * g.n))) break;
-        if (fail(dev_malloc(&hrows, sizeof(int32_t) * std::max<int64_t>(g.nheavy, 1)))) break;
+        if (fail(dev_malloc_async(&hrows, sizeof(int32_t) * std::max<int64_t>(g.nheavy, 1), s))) break;
         fill_pieces_kernel<<<grid, 256, 0, s>>>(g.roff, g.n, fcopy, hfirst, g.rp_row, g.rp_start,
                                                 g.rp_first, hrows);
         if (fail(hipGetLastError())) break;
         pok = true;
       } while (0);
       if (fail(hipStreamSynchronize(s))) pok = false;
-      if (hrows) (void)dev_free(hrows);
-      (void)dev_free(hfirst);
+      if (hrows) (void)dev_free_async(hrows, s);
+      (void)dev_free_async(hfirst, s);
       if (!pok) {
         ok = false;
         break;
@@ -553,9 +546,8 @@ abcore_status build_ranks(Graph &g, hipStream_t s) {
     if (!ok) break;
     if (fail(hipStreamSynchronize(s))) break;
   } while (0);
-  if (k0) (void)dev_free(k0);
-  if (k1) (void)dev_free(k1);
-  if (temp) (void)dev_free(temp);
+  for (void *p : {(void *)k0, (void *)k1, temp})
+    if (p) (void)dev_free_async(p, s);
   if (!ok) {
     (void)hipGetLastError();
     if (g.rank) (void)dev_free(g.rank);

@@ -469,11 +469,11 @@ hipError_t launch_export(Graph &g, int64_t *out_off, int32_t *out_cols, hipStrea
   int64_t *tmp64 = nullptr;
   void *temp = nullptr;
   size_t temp_bytes = 0;
-  hipError_t e = dev_malloc(&tmp64, sizeof(int64_t) * (g.n + 1));
+  hipError_t e = dev_malloc_async(&tmp64, sizeof(int64_t) * (g.n + 1), s);
   if (e != hipSuccess) return e;
   widen_deg_kernel<<<small_grid(g, g.n + 1), 256, 0, s>>>(g.deg0, g.n, tmp64);
   e = prim::exclusive_sum(nullptr, temp_bytes, tmp64, out_off, (size_t)(g.n + 1), s);
-  if (e == hipSuccess) e = dev_malloc(&temp, std::max<size_t>(temp_bytes, 16));
+  if (e == hipSuccess) e = dev_malloc_async(&temp, std::max<size_t>(temp_bytes, 16), s);
   if (e == hipSuccess)
     e = prim::exclusive_sum(temp, temp_bytes, tmp64, out_off, (size_t)(g.n + 1), s);
   if (e == hipSuccess && out_cols != nullptr) {
@@ -484,8 +484,8 @@ hipError_t launch_export(Graph &g, int64_t *out_off, int32_t *out_cols, hipStrea
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (temp) (void)dev_free(temp);
-  (void)dev_free(tmp64);
+  if (temp) (void)dev_free_async(temp, s);
+  (void)dev_free_async(tmp64, s);
   return e;
 }
 

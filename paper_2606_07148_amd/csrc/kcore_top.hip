@@ -338,9 +338,9 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
   const int nctr = max_sweeps + 1;
   auto ok = [](hipError_t e) { return e == hipSuccess; };
   do {
-    if (!ok(dev_malloc(&lid, sizeof(int32_t) * std::max<int64_t>(g.n, 1))) ||
-        !ok(dev_malloc(&hv, sizeof(int32_t) * std::max<int64_t>(cnt, 1))) ||
-        !ok(dev_malloc(&ctr, sizeof(int32_t) * (nctr + 1)))) {
+    if (!ok(dev_malloc_async(&lid, sizeof(int32_t) * std::max<int64_t>(g.n, 1), s)) ||
+        !ok(dev_malloc_async(&hv, sizeof(int32_t) * std::max<int64_t>(cnt, 1), s)) ||
+        !ok(dev_malloc_async(&ctr, sizeof(int32_t) * (nctr + 1), s))) {
       st = ABCORE_ENOMEM;
       break;
     }
@@ -354,9 +354,9 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
         !ok(hipStreamSynchronize(s)))
       break;
     h = h32;
-    if (!ok(dev_malloc(&hlen, sizeof(int64_t) * (h + 1))) ||
-        !ok(dev_malloc(&hoff, sizeof(int64_t) * (h + 1))) ||
-        !ok(dev_malloc(&est, sizeof(int32_t) * std::max<int64_t>(h, 1)))) {
+    if (!ok(dev_malloc_async(&hlen, sizeof(int64_t) * (h + 1), s)) ||
+        !ok(dev_malloc_async(&hoff, sizeof(int64_t) * (h + 1), s)) ||
+        !ok(dev_malloc_async(&est, sizeof(int32_t) * std::max<int64_t>(h, 1), s))) {
       st = ABCORE_ENOMEM;
       break;
     }
@@ -367,7 +367,7 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
       if (!ok(hipGetLastError())) break;
     }
     if (!ok(prim::exclusive_sum(nullptr, temp_bytes, hlen, hoff, (size_t)(h + 1), s))) break;
-    if (!ok(dev_malloc(&temp, std::max<size_t>(temp_bytes, 16)))) {
+    if (!ok(dev_malloc_async(&temp, std::max<size_t>(temp_bytes, 16), s))) {
       st = ABCORE_ENOMEM;
       break;
     }
@@ -375,7 +375,7 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
     if (!ok(hipMemcpyAsync(&eh, hoff + h, sizeof(int64_t), hipMemcpyDeviceToHost, s)) ||
         !ok(hipStreamSynchronize(s)))
       break;
-    if (!ok(dev_malloc(&hcols, sizeof(int32_t) * std::max<int64_t>(eh, 1)))) {
+    if (!ok(dev_malloc_async(&hcols, sizeof(int32_t) * std::max<int64_t>(eh, 1), s))) {
       st = ABCORE_ENOMEM;
       break;
     }
@@ -386,7 +386,7 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
     }
     // which vertices a sweep recomputes: all in the first, then those with a
     // neighbour lowered by the sweep before (two byte arrays, alternating)
-    if (!ok(dev_malloc(&dirty, sizeof(uint8_t) * 2 * std::max<int64_t>(h, 1)))) {
+    if (!ok(dev_malloc_async(&dirty, sizeof(uint8_t) * 2 * std::max<int64_t>(h, 1), s))) {
       st = ABCORE_ENOMEM;
       break;
     }
@@ -442,7 +442,7 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
   } while (0);
   for (void *p : {(void *)lid, (void *)hv, (void *)hcols, (void *)est, (void *)ctr, (void *)hlen,
                   (void *)hoff, (void *)dirty, temp})
-    if (p) (void)dev_free(p);
+    if (p) (void)dev_free_async(p, s);
   if (st != ABCORE_OK) set_error("core numbers: the h-index phase failed");
   return st;
 }
