@@ -153,6 +153,9 @@ struct BatchPlan {
   std::vector<uint8_t> dup;     // 1: same thresholds as parent, bitmask copied
   std::vector<uint8_t> copy;    // 1: starts from a copy of the parent's state
   std::vector<int32_t> slot;    // state buffer (-1 for duplicates)
+  // 1: runs from scratch as a root does (in its buffer) although it has a
+  // parent, because that measured faster (see abcore_compute_batch)
+  std::vector<uint8_t> scratch;
   int nslots = 0;
 };
 BatchPlan make_batch_plan(const int32_t *tu, const int32_t *tl, int32_t q);
@@ -364,6 +367,8 @@ struct PeelArgs {
   // vertices alive after the scan (bit set; nullable): GCC skips decrements
   // of the scan frontier, which is out of the core whatever its degree
   const uint32_t *alive0;
+  // the frontier a pushed first round queues, when not the scan's clear bits
+  const uint32_t *f0_bits;
   // Rank order (klim_u >= 0): ids are global ranks, the scan's survivors are
   // the ranks below klim_u (upper) and nU + klim_l (lower), which replaces
   // alive0.  pack_vtx (global rank -> vertex, non-null in rank order): the
@@ -437,8 +442,14 @@ hipError_t launch_scan_gcc(Graph &g, int32_t thrU, int32_t thrL, bool want_bits,
 // (rest_part in the pull then compares the frontier's degrees with the
 // survivors' row entries, and written_snap replaces deg0 as what the
 // split rows' pieces subtract).
+// src (nullable): the parent's state, copied into g.deg as it is read (a
+// child that does not continue in its parent's buffer).  fbits (nullable,
+// with bits): the frontier goes to this bitmap instead of the queue, and the
+// pull kernel queues it if it pushes the first round (launch_pull_round's
+// f0bits).
 hipError_t launch_scan_nested(Graph &g, int32_t pU, int32_t pL, int32_t thrU, int32_t thrL,
-                              hipStream_t s, uint32_t *bits = nullptr);
+                              hipStream_t s, uint32_t *bits = nullptr,
+                              const int32_t *src = nullptr, uint32_t *fbits = nullptr);
 // queue_f0: the scan did not queue its frontier (launch_scan_reset_gcc);
 // a pushed first round then queues it from the bitmap.
 hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
@@ -462,10 +473,13 @@ hipError_t launch_classify_reset(Graph &g, int32_t thrU, int32_t thrL, int32_t d
 // rest_part: the pull cost is the scan's kPartRest sums (nested scans).
 // rank: count by the degree-rank copy (Graph::rcols; the GCC scan's
 // survivors on an unchanged graph only), completing split rows at once.
+// f0bits (nullable, with queue_f0): the frontier to queue when pushing is
+// this bitmap's set bits instead of the lookup bitmap's clear bits.
 hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
                              bool advance = false, bool queue_f0 = false,
                              const uint32_t *rowbits = nullptr, bool force = false,
-                             bool rest_part = false, bool rank = false);
+                             bool rest_part = false, bool rank = false,
+                             const uint32_t *f0bits = nullptr);
 // Asynchronous peel fused with the pull round's completion (fix_bits: the
 // scan's survivors, or nullptr when no pull round ran) and the bitmask pack
 // (pack_bits nullable).

@@ -412,13 +412,14 @@ bool rank_counts(const Graph &g, int32_t thrU, int32_t thrL, int64_t &ku, int64_
 abcore_status pull_peel_pack(Graph &g, PeelKind kind, int32_t thrU, int32_t thrL, bool pull,
                              uint32_t *bits, hipStream_t s, int64_t *launches,
                              bool queue_f0 = false, const uint32_t *rowbits = nullptr,
-                             bool force = false, bool rest_part = false, bool rank = false) {
+                             bool force = false, bool rest_part = false, bool rank = false,
+                             const uint32_t *f0bits = nullptr) {
   const bool fused = g.peel_mode == 3;
   rank = rank && fused && g.rcols != nullptr;
   if (pull) {
     CHK(timed(g, ABCORE_KERNEL_PULL, s, 1, [&] {
       return launch_pull_round(g, thrU, thrL, s, fused, queue_f0, rowbits, force, rest_part,
-                               rank);
+                               rank, f0bits);
     }));
     if (!fused)
       CHK(timed(g, ABCORE_KERNEL_FIXUP, s, 1,
@@ -540,8 +541,11 @@ abcore_status ensure_delta(Graph &g, hipStream_t s) {
 // stream-ordered with no host read, so the sequence can be captured).
 // Working degrees of query i live in slot plan.slot[i]; g.deg is restored on
 // every exit.
+// Runs the plan on stream s.  times (nullable, q entries): the device time
+// of each query's launches in milliseconds (an event pair around each;
+// synchronises at the end), for the calibration of the first call.
 abcore_status run_batch(Graph &g, const BatchPlan &plan, const int32_t *tu, const int32_t *tl,
-                        uint32_t *bits, hipStream_t s) {
+                        uint32_t *bits, hipStream_t s, std::vector<float> *times = nullptr) {
   struct Restore {
     Graph &g;
     int32_t *deg;
@@ -551,15 +555,39 @@ abcore_status run_batch(Graph &g, const BatchPlan &plan, const int32_t *tu, cons
   const bool pull = g.pull_mode != 1;
   int64_t launches = 0;
   CHK(launch_init_state(g, s));  // clears the abort flag once for the batch
+  std::vector<hipEvent_t> ev;
+  struct FreeEvents {
+    std::vector<hipEvent_t> &ev;
+    ~FreeEvents() {
+      for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+  } free_events{ev};
+  if (times) {
+    times->assign(plan.parent.size(), 0.0f);
+    ev.resize(2 * plan.parent.size(), nullptr);
+    for (hipEvent_t &e : ev) CHK(hipEventCreate(&e));
+  }
   for (int32_t i : plan.order) {
     uint32_t *out = bits + (int64_t)i * words;
-    const int32_t p = plan.parent[i];
+    const int32_t p0 = plan.parent[i];
     if (plan.dup[i]) {
       if (words > 0)
-        CHK(hipMemcpyAsync(out, bits + (int64_t)p * words, sizeof(uint32_t) * words,
+        CHK(hipMemcpyAsync(out, bits + (int64_t)p0 * words, sizeof(uint32_t) * words,
                            hipMemcpyDeviceToDevice, s));
       continue;
     }
+    // a query measured faster from scratch starts as a root does
+    const int32_t p = !plan.scratch.empty() && plan.scratch[i] ? -1 : p0;
+    if (times) CHK(hipEventRecord(ev[2 * i], s));
+    struct Stop {
+      std::vector<hipEvent_t> &ev;
+      int32_t i;
+      hipStream_t s;
+      bool on;
+      ~Stop() {
+        if (on) (void)hipEventRecord(ev[2 * i + 1], s);
+      }
+    } stop{ev, i, s, times != nullptr};
     g.deg = g.slots[plan.slot[i]];
     if (p < 0 && pull && g.peel_mode == 3) {
       // a root runs as a single query does: the fused scan and reset, then a
@@ -572,18 +600,63 @@ abcore_status run_batch(Graph &g, const BatchPlan &plan, const int32_t *tu, cons
       CHK(launch_scan_gcc(g, tu[i], tl[i], pull, s));
       TRY(pull_peel_pack(g, kGCC, tu[i], tl[i], pull, out, s, &launches));
     } else {
-      if (plan.copy[i] && g.n > 0)
-        CHK(hipMemcpyAsync(g.deg, g.slots[plan.slot[p]], sizeof(int32_t) * g.n,
-                           hipMemcpyDeviceToDevice, s));
+      // a child that does not continue in its parent's buffer copies the
+      // parent's state as its scan reads it; a pull round over the parent's
+      // survivors when the frontier is heavy (decided on the device from
+      // the scan's sums), else the pull kernel queues the frontier from the
+      // scan's frontier bitmap (fused mode; otherwise the scan queues it)
+      const int32_t *src = plan.copy[i] ? g.slots[plan.slot[p]] : nullptr;
+      uint32_t *fbits = pull && g.peel_mode == 3 && g.pull_mode != 1 ? g.row_bits : nullptr;
       CHK(launch_init_state(g, s, true));
-      // a pull round over the parent's survivors when the frontier is heavy
-      // (decided on the device from the scan's sums)
-      CHK(launch_scan_nested(g, tu[p], tl[p], tu[i], tl[i], s, pull ? g.alive_bits : nullptr));
-      TRY(pull_peel_pack(g, kGCC, tu[i], tl[i], pull, out, s, &launches, false, nullptr, false,
-                         true));
+      CHK(launch_scan_nested(g, tu[p], tl[p], tu[i], tl[i], s, pull ? g.alive_bits : nullptr,
+                             src, fbits));
+      TRY(pull_peel_pack(g, kGCC, tu[i], tl[i], pull, out, s, &launches, fbits != nullptr,
+                         nullptr, false, true, false, fbits));
+    }
+  }
+  if (times) {
+    CHK(hipStreamSynchronize(s));
+    for (int32_t i : plan.order) {
+      if (plan.dup[i]) continue;
+      float ms = 0.0f;
+      CHK(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+      (*times)[i] = ms;
     }
   }
   return ABCORE_OK;
+}
+
+// The first call of a batch (before its capture) measures, per query with a
+// parent, the nested start against a start from scratch as a root does (on
+// an unchanged graph: the scan, then the first round counted on the
+// degree-rank copy).  Nesting peels only the difference between the two
+// cores, through atomic decrements; from scratch, the survivors of the
+// degree scan count their surviving neighbours by a search of their sorted
+// rank rows.  When the parent's core is much larger than the child's, the
+// second wins (measured 2 ms against 0.06 ms).  Both leave a valid state
+// for the query's own children (every survivor's degree in its core), so the
+// choice is per query.  Two eager passes of the batch, then the plan.
+abcore_status calibrate_batch(Graph &g, BatchPlan &plan, const int32_t *tu, const int32_t *tl,
+                              uint32_t *bits, hipStream_t s) {
+  const int32_t q = (int32_t)plan.parent.size();
+  plan.scratch.assign(q, 0);
+  std::vector<float> nested, fresh;
+  TRY(run_batch(g, plan, tu, tl, bits, s, &nested));
+  TRY(read_state(g, s));
+  plan.scratch.assign(q, 1);
+  TRY(run_batch(g, plan, tu, tl, bits, s, &fresh));
+  TRY(read_state(g, s));
+  for (int32_t i = 0; i < q; ++i)
+    plan.scratch[i] = plan.parent[i] >= 0 && !plan.dup[i] && fresh[i] < nested[i] ? 1 : 0;
+  return ABCORE_OK;
+}
+
+// The measured choice applies where a query from scratch starts as a root
+// does in the asynchronous mode: first round in pull form, degree-rank copy
+// available and the graph unchanged since its build.
+bool pull_mode_allows_calibration(const Graph &g) {
+  return g.peel_mode == 3 && g.pull_mode != 1 && g.rank_order && g.version == 0 &&
+         g.rcols != nullptr;
 }
 
 abcore_status ensure_slots(Graph &g, int n_slots) {
@@ -1469,6 +1542,13 @@ abcore_status abcore_compute_batch(abcore_graph h, const uint32_t *h_alpha,
     if (!g->capture_stream) CHK(hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking));
     const bool timing = g->timing;
     g->timing = false;
+    if (pull_mode_allows_calibration(*g)) {
+      abcore_status cst = calibrate_batch(*g, plan, tu.data(), tl.data(), d_bitmasks, s);
+      if (cst != ABCORE_OK) {
+        g->timing = timing;
+        return cst;
+      }
+    }
     CHK(hipStreamBeginCapture(g->capture_stream, hipStreamCaptureModeThreadLocal));
     abcore_status st = run_batch(*g, plan, tu.data(), tl.data(), d_bitmasks, g->capture_stream);
     hipGraph_t graph = nullptr;

@@ -144,6 +144,7 @@ PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL) {
   a.pack_bits = nullptr;
   a.start_expect = 0;
   a.alive0 = nullptr;
+  a.f0_bits = nullptr;
   a.klim_u = -1;
   a.klim_l = -1;
   a.pack_vtx = nullptr;
@@ -474,13 +475,16 @@ hipError_t launch_scan_reset_gcc(Graph &g, int32_t thrU, int32_t thrL, hipStream
 __global__ __launch_bounds__(kScanBlock) void scan_nested_kernel(PeelArgs a, int32_t pU,
                                                                  int32_t pL, int64_t n,
                                                                  const int32_t *__restrict__ deg0,
+                                                                 const int32_t *__restrict__ src,
                                                                  uint32_t *__restrict__ bits,
+                                                                 uint32_t *__restrict__ fbits,
                                                                  int32_t *__restrict__ written) {
   __shared__ ScanCollector col;
   __shared__ int64_t s_acc;
   if (threadIdx.x == 0) col.count = 0;
   __syncthreads();
   const int sub = blockIdx.x % kSub;
+  const int32_t *from = src != nullptr ? src : a.deg;
   int64_t f0 = 0, f0deg = 0, rest = 0;
   for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < n;
        cb += (int64_t)gridDim.x * kScanChunk) {
@@ -488,15 +492,19 @@ __global__ __launch_bounds__(kScanBlock) void scan_nested_kernel(PeelArgs a, int
       const int64_t x0 = cb + t + (int64_t)threadIdx.x * 4;
       int32_t d[4] = {-1, -1, -1, -1};
       if (x0 + 3 < n) {
-        const int4 v = *reinterpret_cast<const int4 *>(a.deg + x0);
+        const int4 v = *reinterpret_cast<const int4 *>(from + x0);
+        if (src != nullptr) *reinterpret_cast<int4 *>(a.deg + x0) = v;
         d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
       } else {
         for (int j = 0; j < 4; ++j)
-          if (x0 + j < n) d[j] = a.deg[x0 + j];
+          if (x0 + j < n) {
+            d[j] = from[x0 + j];
+            if (src != nullptr) a.deg[x0 + j] = d[j];
+          }
       }
       int32_t items[4];
       int cnt = 0;
-      uint32_t alive = 0;
+      uint32_t alive = 0, front = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const bool up = (x0 + j) < a.nU;
@@ -504,6 +512,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_nested_kernel(PeelArgs a, int
         if (x0 + j < n && d[j] >= (up ? pU : pL) && !stays) {
           items[cnt++] = (int32_t)(x0 + j);
           f0deg += d[j];
+          front |= 1u << j;
         }
         alive |= (uint32_t)stays << j;
       }
@@ -522,11 +531,20 @@ __global__ __launch_bounds__(kScanBlock) void scan_nested_kernel(PeelArgs a, int
         w |= __shfl_xor(w, 2, kWave);
         w |= __shfl_xor(w, 4, kWave);
         if ((lane_id() & 7) == 0 && x0 < n) bits[x0 / 32] = w;
+        if (fbits != nullptr) {
+          uint32_t f = front << (4 * (lane_id() & 7));
+          f |= __shfl_xor(f, 1, kWave);
+          f |= __shfl_xor(f, 2, kWave);
+          f |= __shfl_xor(f, 4, kWave);
+          if ((lane_id() & 7) == 0 && x0 < n) fbits[x0 / 32] = f;
+        }
       }
       f0 += cnt;
-      col.append(items, cnt);
+      // (with a frontier bitmap the pull kernel queues the frontier, and
+      // only if it pushes)
+      if (fbits == nullptr) col.append(items, cnt);
     }
-    col.flush_queue(a, sub);
+    if (fbits == nullptr) col.flush_queue(a, sub);
   }
   add_part(a.part, kPartF0, f0, &s_acc);
   if (bits != nullptr) {
@@ -537,10 +555,11 @@ __global__ __launch_bounds__(kScanBlock) void scan_nested_kernel(PeelArgs a, int
 }
 
 hipError_t launch_scan_nested(Graph &g, int32_t pU, int32_t pL, int32_t thrU, int32_t thrL,
-                              hipStream_t s, uint32_t *bits) {
+                              hipStream_t s, uint32_t *bits, const int32_t *src,
+                              uint32_t *fbits) {
   PeelArgs a = make_args(g, thrU, thrL);
-  scan_nested_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(a, pU, pL, g.n, g.deg0, bits,
-                                                         g.split_written);
+  scan_nested_kernel<<<scan_grid(g), kScanBlock, 0, s>>>(
+      a, pU, pL, g.n, g.deg0, src, bits, bits != nullptr ? fbits : nullptr, g.split_written);
   return hipGetLastError();
 }
 
@@ -1554,7 +1573,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
         const int64_t w = w0 + lane_id();
         uint32_t dead = 0;
         if (w < nwords) {
-          dead = ~gbits[w];
+          dead = a.f0_bits != nullptr ? a.f0_bits[w] : ~gbits[w];
           const int64_t valid = n - (w << 5);
           if (valid < 32) dead &= (1u << valid) - 1u;
         }
@@ -1921,9 +1940,11 @@ hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *b
 
 hipError_t launch_pull_round(Graph &g, int32_t thrU, int32_t thrL, hipStream_t s,
                              bool advance, bool queue_f0, const uint32_t *rowbits, bool force,
-                             bool rest_part, bool rank) {
-  return launch_pull_round_args(g, make_args(g, thrU, thrL), g.alive_bits, nullptr, nullptr, 0,
-                                advance, s, queue_f0, rowbits, force, rest_part, rank);
+                             bool rest_part, bool rank, const uint32_t *f0bits) {
+  PeelArgs a = make_args(g, thrU, thrL);
+  a.f0_bits = f0bits;
+  return launch_pull_round_args(g, a, g.alive_bits, nullptr, nullptr, 0, advance, s, queue_f0,
+                                rowbits, force, rest_part, rank);
 }
 
 // A query in rank order (unchanged graph): part 0, the first round pulled on
