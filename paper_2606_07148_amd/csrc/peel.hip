@@ -491,14 +491,21 @@ __global__ __launch_bounds__(kScanBlock) void scan_nested_kernel(PeelArgs a, int
     for (int t = 0; t < kScanChunk; t += kScanBlock * 4) {
       const int64_t x0 = cb + t + (int64_t)threadIdx.x * 4;
       int32_t d[4] = {-1, -1, -1, -1};
+      // whole degrees too when a pull round may follow: loaded with the
+      // state, not behind it (one memory round trip per pass)
+      int32_t w0[4] = {0, 0, 0, 0};
       if (x0 + 3 < n) {
         const int4 v = *reinterpret_cast<const int4 *>(from + x0);
+        int4 v0 = make_int4(0, 0, 0, 0);
+        if (bits != nullptr) v0 = *reinterpret_cast<const int4 *>(deg0 + x0);
         if (src != nullptr) *reinterpret_cast<int4 *>(a.deg + x0) = v;
         d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        w0[0] = v0.x; w0[1] = v0.y; w0[2] = v0.z; w0[3] = v0.w;
       } else {
         for (int j = 0; j < 4; ++j)
           if (x0 + j < n) {
             d[j] = from[x0 + j];
+            if (bits != nullptr) w0[j] = deg0[x0 + j];
             if (src != nullptr) a.deg[x0 + j] = d[j];
           }
       }
@@ -520,9 +527,8 @@ __global__ __launch_bounds__(kScanBlock) void scan_nested_kernel(PeelArgs a, int
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if ((alive >> j) & 1u) {
-            const int32_t d0 = deg0[x0 + j];
-            rest += d0;
-            if (d0 > kPiece) written[a.piece_first[x0 + j]] = d[j];
+            rest += w0[j];
+            if (w0[j] > kPiece) written[a.piece_first[x0 + j]] = d[j];
           }
         }
         // eight consecutive threads hold the 32 vertices of one bitmap word
