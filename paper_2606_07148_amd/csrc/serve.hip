@@ -386,10 +386,10 @@ bool run_window(Graph &g, Server &S, const std::vector<Request> &win) {
       SCHK(hipMemcpyAsync(s.d_corr, s.h_corr, sizeof(int32_t) * 2 * kCorrMax,
                           hipMemcpyHostToDevice, s.stream));
     SCHK(launch_init_workspace(g, s.queue, s.state, s.part, s.stream));
-    // the pull round takes every compute unit with a full-LDS workgroup and
-    // keeps served queries from overlapping: served peels push their first
-    // round unless the pull form is forced (ABCORE_OPT_PULL = 2)
-    const bool pull = g.pull_mode == 2;
+    // the first round as a single query takes it: pulled when the device
+    // finds it cheaper from the scan's sums (ABCORE_OPT_PULL 0), always (2)
+    // or never (1)
+    const bool pull = g.pull_mode != 1;
     SCHK(launch_scan_component_view(g, a, x, y, s.d_corr, s.d_corr + kCorrMax, c,
                                     pull ? s.bits : nullptr, s.stream));
     PeelArgs ap = a;
