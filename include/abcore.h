@@ -105,7 +105,8 @@ typedef struct {
   int64_t ranks_bytes;  /* degree-rank copy: ranks, relabelled CSR, pieces, degree slots */
   int64_t queue_bytes;  /* frontier sub-queues of the handle's working set */
   /* last core decomposition's h-index phase (zeros if it did not run):
-   * switch level k0, vertices and adjacency entries of the k0-core, sweeps */
+   * switch level k0, vertices of the k0-core, the adjacency slots it used
+   * (its vertices' degrees in the graph), half sweeps (one layer each) */
   int64_t core_top[4];
   double core_levels_ms;  /* levels peeled before the switch (wall clock) */
   double core_top_ms;     /* the h-index phase (wall clock) */
@@ -403,7 +404,7 @@ abcore_status abcore_serve_stop(abcore_graph g, int64_t *counters);
  *                          without a peel.  Results stay exact.
  *   ABCORE_OPT_KCORE_SWITCH: core numbers (default peel mode): levels are
  *                          peeled one by one until at most `value` vertices
- *                          are live (0 = 262144; checked between batches of
+ *                          are live (0 = 1048576; checked between batches of
  *                          levels); the rest -- the k0-core, whose core
  *                          numbers in G are its own -- is finished by the
  *                          h-index fixpoint (iterate est(x) <- h-index of the

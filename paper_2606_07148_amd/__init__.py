@@ -67,7 +67,7 @@ class abcore_report(ctypes.Structure):
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "core_top"}
-        d["core_top"] = dict(zip(("k0", "vertices", "entries", "sweeps"), list(self.core_top)))
+        d["core_top"] = dict(zip(("k0", "vertices", "entries", "half_sweeps"), list(self.core_top)))
         return d
 
 

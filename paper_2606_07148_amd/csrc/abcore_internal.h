@@ -62,10 +62,10 @@ constexpr int32_t kDegOut = -1;
 // beyond any legitimate wait of a peel).  ABCORE_OPT_SPIN_LIMIT lowers it.
 constexpr uint32_t kAsyncSpinLimit = 1u << 21;
 // Live vertices at or below which the core decomposition leaves the level
-// peel for the h-index fixpoint (measured best at 2^18 on the 2e7-, 5e8- and
-// 1e9-edge power-law graphs: 10, 129 and 222 ms, against 20, 159 and 239 ms
-// at 2^17).
-constexpr int64_t kKcoreSwitch = 1 << 18;
+// peel for the h-index fixpoint (measured best at 2^20 on the 2e7-, 5e8- and
+// 1e9-edge power-law graphs: 10, 78 and 131 ms, against 12, 96 and 152 ms
+// at 2^18).
+constexpr int64_t kKcoreSwitch = 1 << 20;
 // Largest usable threshold: kDegIn must stay above every threshold.
 constexpr int32_t kMaxThreshold = 0x7FFFFFFE;
 // Degree of a removed split row once a consumer has claimed it (far below
@@ -546,9 +546,10 @@ abcore_status max_degree(Graph &g, int64_t lo, int64_t hi, int32_t *out, hipStre
 abcore_status compute_core_numbers(Graph &g, hipStream_t s);
 // The core numbers of the live vertices of an alive list (cnt entries,
 // those with core < 0) once every vertex of core < k0 has its value, by the
-// h-index fixpoint; *finished false if it needed more than max_sweeps.
+// h-index fixpoint; *finished false if it needed more than max_halves
+// half sweeps.
 abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
-                        int max_sweeps, bool *finished, int32_t *top_max, hipStream_t s);
+                        int max_halves, bool *finished, int32_t *top_max, hipStream_t s);
 abcore_status count_bits(Graph &g, const uint32_t *bits, int64_t *out, hipStream_t s);
 hipError_t launch_update_window(Graph &g, const int32_t *d_upd, int w, WindowRecord *d_rec,
                                 hipStream_t s);

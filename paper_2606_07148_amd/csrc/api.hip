@@ -471,7 +471,7 @@ abcore_status compute_core(Graph &g, hipStream_t s) {
         const int32_t *L = g.h_state->alive_sel ? g.list2 : g.list;
         const auto t_top = std::chrono::steady_clock::now();
         g.top_ms[0] = std::chrono::duration<double, std::milli>(t_top - t_levels).count();
-        TRY(kcore_top(g, L, alive, g.h_state->next_k, 4096, &fin, &tmax, s));
+        TRY(kcore_top(g, L, alive, g.h_state->next_k, 8192, &fin, &tmax, s));
         g.top_ms[1] = std::chrono::duration<double, std::milli>(
                           std::chrono::steady_clock::now() - t_top).count();
         if (fin) {

@@ -7,19 +7,33 @@
 // below k0 has its value, the live vertices H are exactly the k0-core, and
 // the core numbers of H in G are its core numbers as a graph of its own (the
 // k-core of G for k >= k0 lies inside H).  They are also the fixpoint of
-//   est(x) <- min(est(x), h-index of { est(w) : w neighbour of x in H }),
+//   est(x) <- h-index of { est(w) : w neighbour of x in H },
 // started from the degrees in H (Lu, Zhou, Zhang and Stanley, 2016; the
 // h-index of a multiset is the largest h with at least h members >= h): the
-// iterates stay upper bounds of the core numbers and reach them.  Each sweep
-// is a fully parallel pass over H's adjacency, and the number of sweeps is
-// small where the number of cascade rounds is large.
+// iterates stay upper bounds of the core numbers and reach them.
 //
-// Here H's adjacency is compacted (local ids, live-live entries only), the
-// sweeps update the values in place (Gauss-Seidel: a vertex may already see
-// values its neighbours lowered in the same sweep; every value read is still
-// an upper bound of its core number, so every value computed is too), a
-// sweep that changes nothing ends the iteration, and the values are written
-// back as core numbers.
+// Schedule.  H is bipartite, so the layers take turns ("half sweeps"): a
+// half recomputes vertices of one layer against the other layer's values,
+// which stay fixed during it -- Gauss-Seidel order with no race.  A vertex
+// is recomputed only when its value must drop: c(x) counts the neighbours
+// whose value is >= est(x), and x is due exactly when c(x) < est(x).  A
+// vertex a half lowers from `old` to `new` decrements c(y) of each
+// neighbour y with old >= est(y) > new; the decrement that takes c(y) from
+// est(y) to est(y) - 1 queues y for the next half (at most once per half:
+// c(y) >= est(y) holds for every vertex when the half begins).  Past the
+// first few halves only a few thousand vertices drop per half, while a dense
+// core's every row has one of them as neighbour, so this does a fraction of
+// the work of sweeps that recompute every row with a changed neighbour.
+//
+// Layout.  H's vertices get local ids by layer, then by decreasing degree,
+// so the most referenced values of a layer come first: each workgroup keeps
+// the first 63,488 values of the layer a half reads in LDS (16 bits each,
+// offsets from k0), and only entries past them read the values array.  Rows
+// are written at offsets given by the vertices' degrees in G (an upper
+// bound of their degrees in H), so the adjacency is built in one walk.
+#include <algorithm>
+#include <vector>
+
 #include "abcore_internal.h"
 #include "prim.h"
 #include "wave.h"
@@ -28,171 +42,420 @@ namespace abc {
 
 namespace {
 
-// Live vertices of the alive list (core < 0) into hv, their local ids into
-// lid; *count receives their number.  One append counter increment per wave.
+constexpr int kHalfBlock = 1024;
+constexpr int kHalfWaves = kHalfBlock / kWave;
+constexpr int kCache = 63488;  // LDS values per workgroup (124 KB)
+constexpr int kFine = 256;     // unit bins just below the upper end of the search range
+constexpr int kCoarse = 256;   // equal-width bins over the rest of the range
+constexpr int kRegSpan = 8;    // rows of at most 8 x 64 entries keep their values in registers
+#ifndef ABC_TOP_UNROLL
+#define ABC_TOP_UNROLL 8
+#endif
+#ifndef ABC_TOP_LONG_ROW
+#define ABC_TOP_LONG_ROW 2048
+#endif
+#ifndef ABC_TOP_UNROLL_BLOCK
+#define ABC_TOP_UNROLL_BLOCK 4
+#endif
+constexpr int kUnroll = ABC_TOP_UNROLL;             // row entries in flight per lane
+constexpr int kLongRow = ABC_TOP_LONG_ROW;          // longer rows: walked by a whole workgroup
+constexpr int kUnrollBlock = ABC_TOP_UNROLL_BLOCK;  // the same for those walks
+
+// Live vertices of the alive list (core < 0) into hv and their bits into
+// live; count[0] receives their number, count[1] the number in the upper
+// layer.  One append counter increment per wave.
 __global__ __launch_bounds__(kBlock) void top_select_kernel(const int32_t *__restrict__ alive,
                                                             int64_t cnt,
                                                             const int32_t *__restrict__ core,
-                                                            int32_t *__restrict__ hv,
-                                                            int32_t *__restrict__ lid,
+                                                            int32_t nU, int32_t *__restrict__ hv,
+                                                            uint32_t *__restrict__ live,
                                                             int32_t *count) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < cnt; base += stride) {
     const int64_t i = base + threadIdx.x;
     int32_t x = -1;
-    bool live = false;
+    bool on = false;
     if (i < cnt) {
       x = alive[i];
-      live = core[x] < 0;
+      on = core[x] < 0;
     }
-    const uint64_t mask = __ballot(live);
+    const uint64_t mask = __ballot(on);
+    const uint64_t upper = __ballot(on && x < nU);
     int at = 0;
-    if (lane_id() == 0 && mask) at = atomicAdd(count, (int)__popcll(mask));
+    if (lane_id() == 0 && mask) {
+      at = atomicAdd(&count[0], (int)__popcll(mask));
+      if (upper) atomicAdd(&count[1], (int)__popcll(upper));
+    }
     at = __shfl(at, 0, kWave);
-    if (live) {
-      const int32_t j = at + (int)__popcll(mask & lanemask_lt());
-      hv[j] = x;
-      lid[x] = j;
+    if (on) {
+      hv[at + (int)__popcll(mask & lanemask_lt())] = x;
+      atomicOr(&live[x >> 5], 1u << (x & 31));
     }
   }
 }
 
-// Walks the live neighbours of x (CSR entries, tombstones ~col skipped, then
-// inserted edges) 64 at a time; f(w, rank) gets each live neighbour and its
-// rank among them, in row order.  Wave-uniform; returns the count.
-template <class F>
-__device__ __forceinline__ int64_t walk_live(const int64_t *__restrict__ off,
-                                             const int32_t *__restrict__ cols,
-                                             const int32_t *__restrict__ ins_head,
-                                             const int32_t *__restrict__ ins_next,
-                                             const int32_t *__restrict__ ins_other,
-                                             const int32_t *__restrict__ core, int32_t x, F f) {
-  const int64_t b = off[x], e = off[x + 1];
-  int64_t done = 0;
-  for (int64_t j0 = b; j0 < e; j0 += kWave) {
-    const int64_t j = j0 + lane_id();
-    int32_t w = -1;
-    bool live = false;
-    if (j < e) {
-      w = cols[j];
-      live = w >= 0 && core[w] < 0;
-    }
-    const uint64_t mask = __ballot(live);
-    if (live) f(w, done + (int64_t)__popcll(mask & lanemask_lt()));
-    done += (int64_t)__popcll(mask);
-  }
-  if (ins_head != nullptr) {
-    // inserted edges: lane 0 walks the list, the rest of the wave waits
-    int64_t extra = 0;
-    if (lane_id() == 0) {
-      for (int h = ins_head[x]; h >= 0; h = ins_next[h]) {
-        const int32_t w = ins_other[h];
-        if (w >= 0 && core[w] < 0) f(w, done + extra++);
-      }
-    }
-    done += __shfl(extra, 0, kWave);
-  }
-  return done;
-}
-
-// Degrees in H: hlen[j] = live neighbours of hv[j]; est[j] starts there.
-__global__ __launch_bounds__(kBlock) void top_count_kernel(
-    const int64_t *__restrict__ off, const int32_t *__restrict__ cols,
-    const int32_t *__restrict__ ins_head, const int32_t *__restrict__ ins_next,
-    const int32_t *__restrict__ ins_other, const int32_t *__restrict__ core,
-    const int32_t *__restrict__ hv, int64_t h, int64_t *__restrict__ hlen,
-    int32_t *__restrict__ est) {
-  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
-  const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
-  for (int64_t j = gw; j < h; j += nw) {
-    const int64_t d = walk_live(off, cols, ins_head, ins_next, ins_other, core, hv[j],
-                                [](int32_t, int64_t) {});
-    if (lane_id() == 0) {
-      hlen[j] = d;
-      est[j] = (int32_t)d;
-    }
+// Sort keys: layer, then decreasing degree in G, then id.
+__global__ void top_keys_kernel(const int32_t *__restrict__ hv, int64_t h,
+                                const int32_t *__restrict__ deg0, int32_t nU,
+                                uint64_t *__restrict__ keys) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < h; j += stride) {
+    const int32_t x = hv[j];
+    keys[j] = ((uint64_t)(x >= nU) << 63) | ((uint64_t)(0x7FFFFFFF - deg0[x]) << 32) |
+              (uint64_t)(uint32_t)x;
   }
 }
 
-// H's adjacency in local ids: row j at hoff[j], its live neighbours in order.
+// hv[j], lid[hv[j]] = j and the row capacity deg0 (the exclusive sum of
+// which places the rows) from the sorted keys.
+__global__ void top_place_kernel(const uint64_t *__restrict__ keys, int64_t h,
+                                 const int32_t *__restrict__ deg0, int32_t *__restrict__ hv,
+                                 int32_t *__restrict__ lid, int64_t *__restrict__ cap) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < h; j += stride) {
+    const int32_t x = (int32_t)(uint32_t)keys[j];
+    hv[j] = x;
+    lid[x] = (int32_t)j;
+    cap[j] = deg0[x];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) cap[h] = 0;
+}
+
+// Row j of H: the live neighbours of hv[j] (CSR entries, tombstones ~col
+// skipped, then inserted edges) as local ids, in row order, from hoff[j];
+// hlen[j] and est[j] receive their number.  *overflow is set if a row has
+// more live neighbours than its capacity (its degree in G): never, unless
+// the degrees are inconsistent with the rows.  One wave per row.
 __global__ __launch_bounds__(kBlock) void top_fill_kernel(
     const int64_t *__restrict__ off, const int32_t *__restrict__ cols,
     const int32_t *__restrict__ ins_head, const int32_t *__restrict__ ins_next,
-    const int32_t *__restrict__ ins_other, const int32_t *__restrict__ core,
+    const int32_t *__restrict__ ins_other, const uint32_t *__restrict__ live,
     const int32_t *__restrict__ hv, const int32_t *__restrict__ lid, int64_t h,
-    const int64_t *__restrict__ hoff, int32_t *__restrict__ hcols) {
+    const int64_t *__restrict__ hoff, int32_t *__restrict__ hcols, int32_t *__restrict__ hlen,
+    int32_t *__restrict__ est, int32_t *overflow) {
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
   const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
+  auto is_live = [&](int32_t w) { return w >= 0 && ((live[w >> 5] >> (w & 31)) & 1u); };
   for (int64_t j = gw; j < h; j += nw) {
+    const int32_t x = hv[j];
+    const int64_t cap = hoff[j + 1] - hoff[j];
     int32_t *row = hcols + hoff[j];
-    walk_live(off, cols, ins_head, ins_next, ins_other, core, hv[j],
-              [&](int32_t w, int64_t r) { row[r] = lid[w]; });
+    const int64_t b = off[x], e = off[x + 1];
+    int64_t done = 0;
+    for (int64_t j0 = b; j0 < e; j0 += (int64_t)kUnroll * kWave) {
+      int32_t w[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t k = j0 + u * kWave + lane_id();
+        w[u] = k < e ? cols[k] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const bool on = is_live(w[u]);
+        const uint64_t mask = __ballot(on);
+        const int64_t r = done + (int64_t)__popcll(mask & lanemask_lt());
+        if (on && r < cap) row[r] = lid[w[u]];
+        done += (int64_t)__popcll(mask);
+      }
+    }
+    if (ins_head != nullptr) {
+      // inserted edges: lane 0 walks the list
+      int64_t extra = 0;
+      if (lane_id() == 0) {
+        for (int q = ins_head[x]; q >= 0; q = ins_next[q]) {
+          const int32_t w = ins_other[q];
+          if (is_live(w)) {
+            if (done + extra < cap) row[done + extra] = lid[w];
+            ++extra;
+          }
+        }
+      }
+      done += __shfl(extra, 0, kWave);
+    }
+    if (lane_id() == 0) {
+      if (done > cap) atomicExch(overflow, 1);
+      const int32_t d = (int32_t)std::min<int64_t>(done, cap);
+      hlen[j] = d;
+      est[j] = d;
+    }
   }
 }
 
-// Rows of at most kRegSpan * 64 entries keep their neighbours' values in
-// registers through a binary search; longer rows count their neighbours'
-// values once into a per-wave LDS histogram of [k0, min(cur, k0 + kBins))
-// (values above go to a wave-level count); only an h-index above that
-// window needs a binary search that rereads the row per probe.
-// Loads are issued kUnroll at a time per lane, so a long row keeps many
-// in flight.
-constexpr int kRegSpan = 8;
+struct HalfArgs {
+  const int64_t *hoff;
+  const int32_t *hlen;
+  const int32_t *hcols;
+  int32_t *est;  // current values, by local id
+  int32_t *cnt;  // c(x): neighbours whose value is >= est(x)
+  int32_t k0;
+  int32_t tgt_base, tgt_cnt;  // the layer the rows read (fixed during the half)
+  // the vertices to recompute, in their layer's buffer of cap_in slots:
+  // rows of at most kLongRow entries from the front (len_in[0] of them),
+  // longer rows from the back (len_in[1])
+  const int32_t *q_in;
+  const int32_t *len_in;
+  int32_t cap_in;
+  int propagate;  // lowered vertices decrement their neighbours' counts
+};
 
-// A neighbour's value, which other waves may be lowering: a relaxed load
-// that may be served by this compute unit's cache (a stale value is an
-// older, larger one, still an upper bound; a sweep that changes nothing
-// reads only values written before it began, after the caches were
-// invalidated at the kernel boundary).
-__device__ __forceinline__ int32_t ld_near(const int32_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+// x lowered from cur to h: its neighbour y with cur >= est(y) = v > h no
+// longer counts toward c(y).  No value is returned (nothing waits): which
+// vertices became due is read from the counts before the next half.
+__device__ __forceinline__ void uncount(const HalfArgs &a, int32_t w, int32_t v, int32_t cur,
+                                        int32_t h) {
+  if (v <= cur && v > h)
+    (void)__hip_atomic_fetch_add(&a.cnt[w], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-constexpr int kBins = 2048;
-constexpr int kUnroll = 8;
 
-// One sweep in place: est[j] <- largest h <= est[j] with at least h
-// neighbours whose value is >= h (>= k0 always: the iterates bound the core
-// numbers, all >= k0, from above).  Values are written at device scope, so
-// a vertex may see what other waves lowered so far.  Only vertices
-// marked in dirty_now are computed (a vertex none of whose neighbours
-// changed would get its value again); each vertex this sweep lowers marks its
-// neighbours in dirty_next (also those already computed in this sweep with
-// its older value).  A sweep that lowers nothing read only values written
-// before it began, so est is then the fixpoint; the sweeps after it return
-// at once.  changed[t] counts the vertices sweep t lowered.
-__global__ __launch_bounds__(kBlock) void hindex_sweep_kernel(
-    const int64_t *__restrict__ hoff, const int32_t *__restrict__ hcols, int64_t h,
-    int32_t k0, int32_t *est, int32_t *changed, int t, uint8_t *__restrict__ dirty_now,
-    uint8_t *__restrict__ dirty_next) {
-  __shared__ int32_t s_bins[kWavesPerBlock][kBins];
-  if (t > 0 && ld_agent(&changed[t - 1]) == 0) return;
-  int32_t *bins = s_bins[wave_in_block()];
-  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
-  const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
-  int lowered = 0;
-  for (int64_t j = gw; j < h; j += nw) {
-    // no neighbour changed in the previous sweep: its value stands
-    if (!dirty_now[j]) continue;
-    const int32_t cur = ld_agent(&est[j]);
+// One pass of the binned h-index search over [lo, hi]: values above hi are
+// counted, the kFine integers just below hi get one bin each, the rest of
+// the range [lo, fine_lo) kCoarse equal-width bins.
+struct Pass {
+  int32_t lo, hi, fine_lo, width;
+  int nb;
+};
+
+__device__ __forceinline__ Pass pass_of(int32_t lo, int32_t hi) {
+  Pass p;
+  p.lo = lo;
+  p.hi = hi;
+  p.fine_lo = max(lo, hi - kFine + 1);
+  const int64_t nco = (int64_t)p.fine_lo - lo;
+  p.width = nco > 0 ? (int32_t)((nco + kCoarse - 1) / kCoarse) : 1;
+  p.nb = nco > 0 ? (int)((nco + p.width - 1) / p.width) : 0;
+  return p;
+}
+
+__device__ __forceinline__ void bin_value(const Pass &p, int32_t v, uint32_t *bins) {
+  if (v <= p.hi && v >= p.fine_lo)
+    atomicAdd(&bins[v - p.fine_lo], 1u);
+  else if (v < p.fine_lo && v >= p.lo)
+    atomicAdd(&bins[kFine + (v - p.lo) / p.width], 1u);
+}
+
+// After a pass (one wave): true and *res = the largest h in [lo, hi] with
+// count_ge(h) >= h if it lies among the unit bins, else false and the
+// highest coarse bin whose lower edge e has count_ge(e) >= e: the answer's
+// range [*res, *nhi] for the next pass (count_ge(lo) >= lo must hold, which
+// makes some bin qualify).  *c receives count_ge(*res).
+__device__ bool scan_bins(const Pass &p, const uint32_t *bins, int64_t above, int32_t *res,
+                          int32_t *nhi, int64_t *c) {
+  const uint32_t *fine = bins, *coarse = bins + kFine;
+  // unit bins from hi down: lane L at t = top - L; counts by an inclusive
+  // wave scan; the first t (from the top) with count >= t wins
+  int64_t acc = above;
+  for (int32_t top = p.hi; top >= p.fine_lo; top -= kWave) {
+    const int32_t t = top - lane_id();
+    int64_t incl = t >= p.fine_lo ? (int64_t)fine[t - p.fine_lo] : 0;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int64_t y = __shfl_up(incl, o, kWave);
+      if (lane_id() >= o) incl += y;
+    }
+    const uint64_t ok = __ballot(t >= p.fine_lo && acc + incl >= (int64_t)t);
+    if (ok) {
+      const int l = __ffsll((unsigned long long)ok) - 1;
+      *res = top - l;
+      *nhi = *res;
+      *c = acc + __shfl(incl, l, kWave);
+      return true;
+    }
+    acc += __shfl(incl, kWave - 1, kWave);
+  }
+  // coarse bins from the top: bin i covers [lo + i * width, lo + (i + 1) * width)
+  for (int topb = p.nb - 1; topb >= 0; topb -= kWave) {
+    const int bi = topb - lane_id();
+    int64_t incl = bi >= 0 ? (int64_t)coarse[bi] : 0;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int64_t y = __shfl_up(incl, o, kWave);
+      if (lane_id() >= o) incl += y;
+    }
+    const int64_t edge = (int64_t)p.lo + (int64_t)bi * p.width;
+    const uint64_t ok = __ballot(bi >= 0 && acc + incl >= edge);
+    if (ok) {
+      const int l = __ffsll((unsigned long long)ok) - 1;
+      *res = p.lo + (topb - l) * p.width;
+      *nhi = min(*res + p.width - 1, p.fine_lo - 1);
+      *c = acc + __shfl(incl, l, kWave);
+      return *res == *nhi;
+    }
+    acc += __shfl(incl, kWave - 1, kWave);
+  }
+  *res = p.lo;  // not reached while count_ge(lo) >= lo
+  *nhi = p.lo;
+  *c = acc;
+  return true;
+}
+
+// The search for a row walked by one wave, in passes that reread the row.
+// Two passes cover ranges up to kFine + kFine * kCoarse; more take more.
+template <class V>
+__device__ int32_t hindex_wave(const int32_t *__restrict__ hcols, int64_t b, int64_t e,
+                               int32_t lo, int32_t hi, uint32_t *bins, V val, int64_t *c) {
+  for (;;) {
+    const Pass p = pass_of(lo, hi);
+    for (int i = lane_id(); i < kFine + kCoarse; i += kWave) bins[i] = 0;
     __builtin_amdgcn_wave_barrier();
-    if (lane_id() == 0) dirty_now[j] = 0;  // cleared for the marks of the next sweep but one
-    const int64_t b = hoff[j], e = hoff[j + 1], d = e - b;
-    int32_t res = cur;
+    int64_t above = 0;
+    for (int64_t k0i = b; k0i < e; k0i += (int64_t)kUnroll * kWave) {
+      int32_t v[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t k = k0i + u * kWave + lane_id();
+        v[u] = k < e ? val(hcols[k]) : INT32_MIN;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        above += (int64_t)__popcll(__ballot(v[u] > p.hi));
+        bin_value(p, v[u], bins);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    int32_t res, nhi;
+    const bool exact = scan_bins(p, bins, above, &res, &nhi, c);
+    __builtin_amdgcn_wave_barrier();
+    if (exact) return res;
+    lo = res;
+    hi = nhi;
+  }
+}
+
+struct BlockShared {
+  uint32_t above;
+  int32_t res, nhi;
+  int exact;
+  int64_t c;
+};
+
+// The same search for a long row walked by the whole workgroup (bins shared
+// by its waves, scanned by wave 0).  Every thread calls it.
+template <class V>
+__device__ int32_t hindex_block(const int32_t *__restrict__ hcols, int64_t b, int64_t e,
+                                int32_t lo, int32_t hi, uint32_t *bins, BlockShared &sh, V val,
+                                int64_t *c) {
+  for (;;) {
+    const Pass p = pass_of(lo, hi);
+    for (int i = threadIdx.x; i < kFine + kCoarse; i += blockDim.x) bins[i] = 0;
+    if (threadIdx.x == 0) sh.above = 0;
+    __syncthreads();
+    uint32_t above = 0;
+    for (int64_t k0i = b; k0i < e; k0i += (int64_t)kUnrollBlock * kHalfBlock) {
+      int32_t v[kUnrollBlock];
+#pragma unroll
+      for (int u = 0; u < kUnrollBlock; ++u) {
+        const int64_t k = k0i + u * kHalfBlock + threadIdx.x;
+        v[u] = k < e ? val(hcols[k]) : INT32_MIN;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnrollBlock; ++u) {
+        above += (uint32_t)__popcll(__ballot(v[u] > p.hi));
+        bin_value(p, v[u], bins);
+      }
+    }
+    if (lane_id() == 0 && above) atomicAdd(&sh.above, above);
+    __syncthreads();
+    if (wave_in_block() == 0) {
+      int32_t res, nhi;
+      int64_t cc;
+      const bool exact = scan_bins(p, bins, (int64_t)sh.above, &res, &nhi, &cc);
+      if (lane_id() == 0) {
+        sh.res = res;
+        sh.nhi = nhi;
+        sh.exact = exact;
+        sh.c = cc;
+      }
+    }
+    __syncthreads();
+    const bool exact = sh.exact != 0;
+    const int32_t res = sh.res, nhi = sh.nhi;
+    const int64_t cc = sh.c;
+    __syncthreads();  // the next pass rewrites the shared words
+    if (exact) {
+      *c = cc;
+      return res;
+    }
+    lo = res;
+    hi = nhi;
+  }
+}
+
+// One half sweep (see the file comment).  One workgroup per compute unit
+// (the LDS holds the value cache and the bins): first the long rows, one
+// per workgroup at a time, then the others, one per wave.
+__global__ __launch_bounds__(kHalfBlock) void hindex_half_kernel(HalfArgs a) {
+  __shared__ uint16_t cache[kCache];
+  __shared__ uint32_t s_bins[kHalfWaves][kFine + kCoarse];
+  __shared__ BlockShared sh;
+  const int64_t n_short = a.len_in[0], n_long = a.len_in[1];
+  if (blockIdx.x >= n_long && (int64_t)blockIdx.x * kHalfWaves >= n_short) return;  // idle
+  const int kc = min(kCache, a.tgt_cnt);
+  for (int i = threadIdx.x; i < kc; i += blockDim.x)
+    cache[i] = (uint16_t)min(a.est[a.tgt_base + i] - a.k0, 65535);
+  __syncthreads();
+  const int32_t k0 = a.k0;
+  // cached values are offsets from k0 saturated at 65535: exact for every
+  // comparison with thresholds <= cur while cur - k0 < 65535
+  auto make_val = [&](int32_t cur) {
+    const int kcr = cur - k0 < 65535 ? kc : 0;
+    return [&, kcr](int32_t w) -> int32_t {
+      const uint32_t r = (uint32_t)(w - a.tgt_base);
+      return r < (uint32_t)kcr ? (int32_t)cache[r] + k0 : a.est[w];
+    };
+  };
+  for (int64_t i = blockIdx.x; i < n_long; i += gridDim.x) {
+    const int32_t x = a.q_in[a.cap_in - 1 - i];
+    const int32_t cur = a.est[x];
+    const int64_t b = a.hoff[x], e = b + a.hlen[x];
+    const auto val = make_val(cur);
+    int64_t c = 0;
+    const int32_t h = hindex_block(a.hcols, b, e, k0, cur, s_bins[0], sh, val, &c);
+    if (a.propagate && h < cur) {
+      for (int64_t k0i = b; k0i < e; k0i += (int64_t)kUnrollBlock * kHalfBlock) {
+        int32_t w[kUnrollBlock], v[kUnrollBlock];
+#pragma unroll
+        for (int u = 0; u < kUnrollBlock; ++u) {
+          const int64_t k = k0i + u * kHalfBlock + threadIdx.x;
+          w[u] = k < e ? a.hcols[k] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnrollBlock; ++u) v[u] = w[u] >= 0 ? val(w[u]) : INT32_MIN;
+#pragma unroll
+        for (int u = 0; u < kUnrollBlock; ++u) uncount(a, w[u], v[u], cur, h);
+      }
+    }
+    if (threadIdx.x == 0) {
+      a.cnt[x] = (int32_t)min<int64_t>(c, 0x7FFFFFFF);
+      if (h < cur) a.est[x] = h;
+    }
+  }
+  uint32_t *bins = s_bins[wave_in_block()];
+  const int64_t nw = (int64_t)gridDim.x * kHalfWaves;
+  for (int64_t i = (int64_t)blockIdx.x * kHalfWaves + wave_in_block(); i < n_short; i += nw) {
+    const int32_t x = a.q_in[i];
+    const int32_t cur = a.est[x];
+    const int64_t b = a.hoff[x], d = a.hlen[x], e = b + d;
+    const auto val = make_val(cur);
+    int32_t h = cur;
+    int64_t c = 0;
     if (d <= (int64_t)kRegSpan * kWave) {
-      int32_t v[kRegSpan];
+      int32_t w[kRegSpan], v[kRegSpan];
 #pragma unroll
       for (int u = 0; u < kRegSpan; ++u) {
         const int64_t k = b + u * kWave + lane_id();
-        v[u] = k < e ? ld_near(&est[hcols[k]]) : -1;
+        w[u] = k < e ? a.hcols[k] : -1;
       }
-      auto count_ge = [&](int32_t th) -> int64_t {
-        int64_t c = 0;
 #pragma unroll
-        for (int u = 0; u < kRegSpan; ++u) c += (int64_t)__popcll(__ballot(v[u] >= th));
-        return c;
+      for (int u = 0; u < kRegSpan; ++u) v[u] = w[u] >= 0 ? val(w[u]) : INT32_MIN;
+      auto count_ge = [&](int32_t th) -> int64_t {
+        int64_t n = 0;
+#pragma unroll
+        for (int u = 0; u < kRegSpan; ++u) n += (int64_t)__popcll(__ballot(v[u] >= th));
+        return n;
       };
-      if (count_ge(cur) < cur) {
-        // the predicate count_ge(x) >= x holds at k0 and fails at cur
+      c = count_ge(cur);
+      if (c < cur) {
+        // count_ge(x) >= x holds at k0 (H is the k0-core) and fails at cur
         int32_t lo = k0, hi = cur - 1;
         while (lo < hi) {
           const int32_t mid = lo + (hi - lo + 1) / 2;
@@ -201,94 +464,71 @@ __global__ __launch_bounds__(kBlock) void hindex_sweep_kernel(
           else
             hi = mid - 1;
         }
-        res = lo;
+        h = lo;
+        c = count_ge(h);
+      }
+      if (a.propagate && h < cur) {
+#pragma unroll
+        for (int u = 0; u < kRegSpan; ++u) uncount(a, w[u], v[u], cur, h);
       }
     } else {
-      // bins[v - k0] counts the neighbours of value v in [k0, cap), where
-      // cap = min(cur, k0 + kBins); `top` those of value >= cap
-      const int32_t cap = cur - k0 < kBins ? cur : k0 + kBins;
-      const int nb = cap - k0;
-      for (int i = lane_id(); i < nb; i += kWave) bins[i] = 0;
-      __builtin_amdgcn_wave_barrier();
-      int64_t top = 0;
-      for (int64_t k0i = b; k0i < e; k0i += (int64_t)kUnroll * kWave) {
-        int32_t w[kUnroll], v[kUnroll];
+      // the first pass also settles a row that does not drop (its answer
+      // is cur, among the unit bins)
+      h = hindex_wave(a.hcols, b, e, k0, cur, bins, val, &c);
+      if (a.propagate && h < cur) {
+        for (int64_t k0i = b; k0i < e; k0i += (int64_t)kUnroll * kWave) {
+          int32_t w[kUnroll], v[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int64_t k = k0i + u * kWave + lane_id();
-          w[u] = k < e ? hcols[k] : -1;
-        }
+          for (int u = 0; u < kUnroll; ++u) {
+            const int64_t k = k0i + u * kWave + lane_id();
+            w[u] = k < e ? a.hcols[k] : -1;
+          }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) v[u] = w[u] >= 0 ? ld_near(&est[w[u]]) : -1;
+          for (int u = 0; u < kUnroll; ++u) v[u] = w[u] >= 0 ? val(w[u]) : INT32_MIN;
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          top += (int64_t)__popcll(__ballot(v[u] >= cap));
-          if (v[u] >= k0 && v[u] < cap) atomicAdd(&bins[v[u] - k0], 1);
+          for (int u = 0; u < kUnroll; ++u) uncount(a, w[u], v[u], cur, h);
         }
       }
-      __builtin_amdgcn_wave_barrier();
-      if (top >= cap && cap < cur) {
-        // the h-index is at least cap: search [cap, cur) rereading the row
-        auto count_ge = [&](int32_t th) -> int64_t {
-          int64_t c = 0;
-          for (int64_t k0i = b; k0i < e; k0i += (int64_t)kUnroll * kWave) {
-            int32_t w[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-              const int64_t k = k0i + u * kWave + lane_id();
-              w[u] = k < e ? hcols[k] : -1;
-            }
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
-              c += (int64_t)__popcll(__ballot(w[u] >= 0 && ld_near(&est[w[u]]) >= th));
-          }
-          return c;
-        };
-        if (count_ge(cur) < cur) {
-          int32_t lo = cap, hi = cur - 1;
-          while (lo < hi) {
-            const int32_t mid = lo + (hi - lo + 1) / 2;
-            if (count_ge(mid) >= mid)
-              lo = mid;
-            else
-              hi = mid - 1;
-          }
-          res = lo;
-        }
-      } else if (top < cap) {
-        // count(>= x) for x = cap - 1, cap - 2, ... down to k0: the first x
-        // (from the top) with count >= x is the h-index; 64 bins a step,
-        // lane L at x = hi - L, the counts by an inclusive wave scan
-        int64_t acc = top;
-        int32_t found = k0;
-        for (int32_t hi = cap - 1; hi >= k0; hi -= kWave) {
-          const int32_t x = hi - lane_id();
-          const int64_t c = x >= k0 ? (int64_t)bins[x - k0] : 0;
-          int64_t incl = c;
-#pragma unroll
-          for (int o = 1; o < kWave; o <<= 1) {
-            const int64_t tt = __shfl_up(incl, o, kWave);
-            if (lane_id() >= o) incl += tt;
-          }
-          const uint64_t ok = __ballot(x >= k0 && acc + incl >= (int64_t)x);
-          if (ok) {
-            found = hi - (int32_t)(__ffsll((unsigned long long)ok) - 1);
-            break;
-          }
-          acc += __shfl(incl, kWave - 1, kWave);
-        }
-        res = found;
-      }
-      __builtin_amdgcn_wave_barrier();
     }
-    if (res != cur) {
-      if (lane_id() == 0) st_agent(&est[j], res);
-      // its neighbours are recomputed in the next sweep
-      ++lowered;
-      for (int64_t k = b + lane_id(); k < e; k += kWave) dirty_next[hcols[k]] = 1;
+    if (lane_id() == 0) {
+      a.cnt[x] = (int32_t)min<int64_t>(c, 0x7FFFFFFF);
+      if (h < cur) a.est[x] = h;
     }
   }
-  if (lane_id() == 0 && lowered > 0) atomicAdd(&changed[t], lowered);
+}
+
+// The list of half t: the vertices of the layer [base, base + count) that
+// are due (c(x) < est(x); c starts at 0, so the first half of each layer
+// takes all), short rows from the front of the layer's buffer, long rows
+// from its back; len[0] and len[1] receive their numbers.
+__global__ __launch_bounds__(kBlock) void top_due_kernel(const int32_t *__restrict__ est,
+                                                         const int32_t *__restrict__ cnt,
+                                                         const int32_t *__restrict__ hlen,
+                                                         int32_t base, int32_t count,
+                                                         int32_t *__restrict__ list,
+                                                         int32_t *len) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t o = (int64_t)blockIdx.x * blockDim.x; o < count; o += stride) {
+    const int64_t i = o + threadIdx.x;
+    const int32_t j = base + (int32_t)i;
+    const bool due = i < count && cnt[j] < est[j];
+    const bool lg = due && hlen[j] > kLongRow;
+    const uint64_t ms = __ballot(due && !lg), ml = __ballot(lg);
+    int bs = 0, bl = 0;
+    if (lane_id() == 0) {
+      if (ms) bs = atomicAdd(&len[0], (int)__popcll(ms));
+      if (ml) bl = atomicAdd(&len[1], (int)__popcll(ml));
+    }
+    bs = __shfl(bs, 0, kWave);
+    bl = __shfl(bl, 0, kWave);
+    if (due) {
+      // the two ends never meet: at most count vertices are due
+      if (lg)
+        list[count - 1 - (bl + (int)__popcll(ml & lanemask_lt()))] = j;
+      else
+        list[bs + (int)__popcll(ms & lanemask_lt())] = j;
+    }
+  }
 }
 
 // core[hv[j]] = est[j]; *vmax receives the largest value.
@@ -320,58 +560,81 @@ int grid_of(const Graph &g, int64_t items, int per_block) {
 // After the levels below k0 (every vertex of core < k0 has its value; the
 // live ones of the alive list, `cnt` entries, are the k0-core): the core
 // numbers of the live vertices by the h-index fixpoint.  *finished = false
-// (and nothing changed) if it did not converge within max_sweeps, so the
-// caller can go on level by level.  Synchronous.
+// (and nothing changed) if it did not converge within max_halves half
+// sweeps, so the caller can go on level by level.  Synchronous.
 abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
-                        int max_sweeps, bool *finished, int32_t *top_max, hipStream_t s) {
+                        int max_halves, bool *finished, int32_t *top_max, hipStream_t s) {
   *finished = false;
   int32_t *lid = nullptr, *hv = nullptr, *hcols = nullptr, *est = nullptr, *ctr = nullptr;
-  uint8_t *dirty = nullptr;
-  int64_t *hlen = nullptr, *hoff = nullptr;
+  int32_t *hlen = nullptr, *cntv = nullptr, *queue = nullptr, *qlen = nullptr;
+  uint32_t *live = nullptr;
+  uint64_t *keys = nullptr, *keys2 = nullptr;
+  int64_t *cap = nullptr, *hoff = nullptr;
   void *temp = nullptr;
   size_t temp_bytes = 0;
-  int32_t h32 = 0;
+  int32_t hc[3] = {0, 0, 0};
   int64_t h = 0, eh = 0;
   abcore_status st = ABCORE_EDEVICE;
+  const char *why = "core numbers: the h-index phase failed";
   const int32_t *ih = g.delta.count > 0 ? g.delta.head : nullptr;
-  const int sweeps_per_check = 16;
-  const int nctr = max_sweeps + 1;
+  const int halves_per_check = 16;
+  const int64_t words = (g.n + 31) / 32;
   auto ok = [](hipError_t e) { return e == hipSuccess; };
   do {
+    // ctr: [0] live count, [1] upper-layer count, [2] overflow, [3] maximum
     if (!ok(dev_malloc_async(&lid, sizeof(int32_t) * std::max<int64_t>(g.n, 1), s)) ||
         !ok(dev_malloc_async(&hv, sizeof(int32_t) * std::max<int64_t>(cnt, 1), s)) ||
-        !ok(dev_malloc_async(&ctr, sizeof(int32_t) * (nctr + 1), s))) {
+        !ok(dev_malloc_async(&live, sizeof(uint32_t) * std::max<int64_t>(words, 1), s)) ||
+        !ok(dev_malloc_async(&ctr, sizeof(int32_t) * 4, s)) ||
+        !ok(dev_malloc_async(&qlen, sizeof(int32_t) * 2 * (max_halves + 2), s))) {
       st = ABCORE_ENOMEM;
       break;
     }
-    if (!ok(hipMemsetAsync(ctr, 0, sizeof(int32_t) * (nctr + 1), s))) break;
+    if (!ok(hipMemsetAsync(ctr, 0, sizeof(int32_t) * 4, s)) ||
+        !ok(hipMemsetAsync(qlen, 0, sizeof(int32_t) * 2 * (max_halves + 2), s)) ||
+        !ok(hipMemsetAsync(live, 0, sizeof(uint32_t) * std::max<int64_t>(words, 1), s)))
+      break;
     if (cnt > 0) {
-      top_select_kernel<<<grid_of(g, cnt, kBlock), kBlock, 0, s>>>(alive, cnt, g.core, hv, lid,
-                                                                   ctr + nctr);
+      top_select_kernel<<<grid_of(g, cnt, kBlock), kBlock, 0, s>>>(alive, cnt, g.core, g.nU,
+                                                                   hv, live, ctr);
       if (!ok(hipGetLastError())) break;
     }
-    if (!ok(hipMemcpyAsync(&h32, ctr + nctr, sizeof(int32_t), hipMemcpyDeviceToHost, s)) ||
+    if (!ok(hipMemcpyAsync(hc, ctr, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s)) ||
         !ok(hipStreamSynchronize(s)))
       break;
-    h = h32;
-    if (!ok(dev_malloc_async(&hlen, sizeof(int64_t) * (h + 1), s)) ||
+    h = hc[0];
+    const int32_t hU = hc[1];
+    if (!ok(dev_malloc_async(&keys, sizeof(uint64_t) * std::max<int64_t>(h, 1), s)) ||
+        !ok(dev_malloc_async(&keys2, sizeof(uint64_t) * std::max<int64_t>(h, 1), s)) ||
+        !ok(dev_malloc_async(&cap, sizeof(int64_t) * (h + 1), s)) ||
         !ok(dev_malloc_async(&hoff, sizeof(int64_t) * (h + 1), s)) ||
-        !ok(dev_malloc_async(&est, sizeof(int32_t) * std::max<int64_t>(h, 1), s))) {
+        !ok(dev_malloc_async(&hlen, sizeof(int32_t) * std::max<int64_t>(h, 1), s)) ||
+        !ok(dev_malloc_async(&est, sizeof(int32_t) * std::max<int64_t>(h, 1), s)) ||
+        !ok(dev_malloc_async(&cntv, sizeof(int32_t) * std::max<int64_t>(h, 1), s)) ||
+        !ok(dev_malloc_async(&queue, sizeof(int32_t) * std::max<int64_t>(h, 1), s))) {
       st = ABCORE_ENOMEM;
       break;
     }
-    if (!ok(hipMemsetAsync(hlen + h, 0, sizeof(int64_t), s))) break;
+    // local ids: layer, then decreasing degree
     if (h > 0) {
-      top_count_kernel<<<grid_of(g, h * kWave, kBlock), kBlock, 0, s>>>(
-          g.off, g.cols, ih, g.delta.next, g.delta.other, g.core, hv, h, hlen, est);
+      top_keys_kernel<<<grid_of(g, h, kBlock), kBlock, 0, s>>>(hv, h, g.deg0, g.nU, keys);
       if (!ok(hipGetLastError())) break;
     }
-    if (!ok(prim::exclusive_sum(nullptr, temp_bytes, hlen, hoff, (size_t)(h + 1), s))) break;
-    if (!ok(dev_malloc_async(&temp, std::max<size_t>(temp_bytes, 16), s))) {
+    size_t sort_bytes = 0, scan_bytes = 0;
+    if (!ok(prim::sort_keys(nullptr, sort_bytes, keys, keys2, (size_t)h, 0, 64, s)) ||
+        !ok(prim::exclusive_sum(nullptr, scan_bytes, cap, hoff, (size_t)(h + 1), s)))
+      break;
+    temp_bytes = std::max<size_t>({sort_bytes, scan_bytes, 16});
+    if (!ok(dev_malloc_async(&temp, temp_bytes, s))) {
       st = ABCORE_ENOMEM;
       break;
     }
-    if (!ok(prim::exclusive_sum(temp, temp_bytes, hlen, hoff, (size_t)(h + 1), s))) break;
+    size_t tb = temp_bytes;
+    if (h > 0 && !ok(prim::sort_keys(temp, tb, keys, keys2, (size_t)h, 0, 64, s))) break;
+    top_place_kernel<<<grid_of(g, h + 1, kBlock), kBlock, 0, s>>>(keys2, h, g.deg0, hv, lid, cap);
+    if (!ok(hipGetLastError())) break;
+    tb = temp_bytes;
+    if (!ok(prim::exclusive_sum(temp, tb, cap, hoff, (size_t)(h + 1), s))) break;
     if (!ok(hipMemcpyAsync(&eh, hoff + h, sizeof(int64_t), hipMemcpyDeviceToHost, s)) ||
         !ok(hipStreamSynchronize(s)))
       break;
@@ -381,42 +644,62 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
     }
     if (h > 0) {
       top_fill_kernel<<<grid_of(g, h * kWave, kBlock), kBlock, 0, s>>>(
-          g.off, g.cols, ih, g.delta.next, g.delta.other, g.core, hv, lid, h, hoff, hcols);
+          g.off, g.cols, ih, g.delta.next, g.delta.other, live, hv, lid, h, hoff, hcols, hlen,
+          est, ctr + 2);
       if (!ok(hipGetLastError())) break;
     }
-    // which vertices a sweep recomputes: all in the first, then those with a
-    // neighbour lowered by the sweep before (two byte arrays, alternating)
-    if (!ok(dev_malloc_async(&dirty, sizeof(uint8_t) * 2 * std::max<int64_t>(h, 1), s))) {
-      st = ABCORE_ENOMEM;
-      break;
-    }
-    if (h > 0 && (!ok(hipMemsetAsync(dirty, 1, sizeof(uint8_t) * h, s)) ||
-                  !ok(hipMemsetAsync(dirty + h, 0, sizeof(uint8_t) * h, s))))
-      break;
-    // sweeps in place, checked every sweeps_per_check
+    // half sweeps: the upper layer first (all of it, no counts to keep yet),
+    // then the lower layer (all of it, decrementing the upper layer's
+    // counts), then the due vertices of each layer in turn; qlen[2t] and
+    // qlen[2t + 1] count half t's short and long rows
+    const int32_t hL = (int32_t)h - hU;
+    if (h > 0 && !ok(hipMemsetAsync(cntv, 0, sizeof(int32_t) * h, s))) break;
+    const int grid = std::max(1, std::min(g.cu_count, kMaxBlocks));
     int t = 0, fixed_at = -1;
-    std::vector<int32_t> hc(sweeps_per_check);
+    std::vector<int32_t> hq(2 * halves_per_check);
     bool failed = false;
-    while (t < max_sweeps && fixed_at < 0 && h > 0) {
+    while (t < max_halves && fixed_at < 0 && h > 0) {
       const int t0 = t;
-      for (int r = 0; r < sweeps_per_check && t < max_sweeps; ++r, ++t) {
-        hindex_sweep_kernel<<<grid_of(g, h * kWave, kBlock), kBlock, 0, s>>>(
-            hoff, hcols, h, k0, est, ctr, t, dirty + (t % 2) * h, dirty + ((t + 1) % 2) * h);
+      for (int r = 0; r < halves_per_check && t < max_halves; ++r, ++t) {
+        const bool upper = (t % 2) == 0;
+        const int32_t self_base = upper ? 0 : hU, self_cnt = upper ? hU : hL;
+        top_due_kernel<<<grid_of(g, self_cnt, kBlock), kBlock, 0, s>>>(
+            est, cntv, hlen, self_base, self_cnt, queue + self_base, qlen + 2 * t);
+        HalfArgs a{};
+        a.hoff = hoff;
+        a.hlen = hlen;
+        a.hcols = hcols;
+        a.est = est;
+        a.cnt = cntv;
+        a.k0 = k0;
+        a.tgt_base = upper ? hU : 0;
+        a.tgt_cnt = upper ? hL : hU;
+        a.q_in = queue + self_base;
+        a.len_in = qlen + 2 * t;
+        a.cap_in = self_cnt;
+        a.propagate = t >= 1;
+        hindex_half_kernel<<<grid, kHalfBlock, 0, s>>>(a);
       }
       if (!ok(hipGetLastError()) ||
-          !ok(hipMemcpyAsync(hc.data(), ctr + t0, sizeof(int32_t) * (t - t0),
+          !ok(hipMemcpyAsync(hq.data(), qlen + 2 * t0, sizeof(int32_t) * 2 * (t - t0),
                              hipMemcpyDeviceToHost, s)) ||
           !ok(hipStreamSynchronize(s))) {
         failed = true;
         break;
       }
-      for (int r = 0; r < t - t0; ++r)
-        if (hc[r] == 0) {
-          fixed_at = t0 + r;
-          break;
-        }
+      // a half with nothing due after the first two: the fixpoint
+      for (int r = 0; r < t - t0 && fixed_at < 0; ++r)
+        if (t0 + r >= 2 && hq[2 * r] + hq[2 * r + 1] == 0) fixed_at = t0 + r - 1;
     }
     if (failed) break;
+    int32_t flags[2] = {0, 0};
+    if (!ok(hipMemcpyAsync(flags, ctr + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s)) ||
+        !ok(hipStreamSynchronize(s)))
+      break;
+    if (flags[0] != 0) {
+      why = "core numbers: a row of the deep core exceeded its capacity";
+      break;
+    }
     if (h > 0 && fixed_at < 0) {
       st = ABCORE_OK;  // not converged: the caller continues level by level
       break;
@@ -425,12 +708,10 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
     g.top_stats[1] = h;
     g.top_stats[2] = eh;
     g.top_stats[3] = fixed_at + 1;
-    const int32_t *fin = est;
-    int32_t *dmax = ctr + nctr;
+    int32_t *dmax = ctr + 3;
     int32_t hmax = 0;
-    if (!ok(hipMemsetAsync(dmax, 0, sizeof(int32_t), s))) break;
     if (h > 0) {
-      top_write_kernel<<<grid_of(g, h, kBlock), kBlock, 0, s>>>(hv, fin, h, g.core, dmax);
+      top_write_kernel<<<grid_of(g, h, kBlock), kBlock, 0, s>>>(hv, est, h, g.core, dmax);
       if (!ok(hipGetLastError())) break;
     }
     if (!ok(hipMemcpyAsync(&hmax, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, s)) ||
@@ -441,9 +722,11 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
     st = ABCORE_OK;
   } while (0);
   for (void *p : {(void *)lid, (void *)hv, (void *)hcols, (void *)est, (void *)ctr, (void *)hlen,
-                  (void *)hoff, (void *)dirty, temp})
+                  (void *)hoff, (void *)cap, (void *)keys, (void *)keys2, (void *)cntv,
+                  (void *)queue, (void *)qlen, (void *)live, temp})
     if (p) (void)dev_free_async(p, s);
-  if (st != ABCORE_OK) set_error("core numbers: the h-index phase failed");
+  if (st == ABCORE_ENOMEM) set_error("core numbers: the h-index phase is out of memory");
+  else if (st != ABCORE_OK) set_error("%s", why);
   return st;
 }
 

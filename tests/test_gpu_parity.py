@@ -500,3 +500,24 @@ def test_core_numbers_level_and_hindex_phases(switch):
         assert np.array_equal(core.cpu().numpy(), want), (spec, switch, "after updates")
         say(f"core numbers switch {switch}: n={nU + nL}, max {mx}")
         g.destroy()
+
+
+def test_core_numbers_hindex_layers_past_the_lds_cache():
+    """The h-index phase keeps the first 63,488 values of the layer a half
+    reads in LDS and reads the rest from memory: started at the first check
+    on the 2x10^7-edge graph (about a million live vertices), both layers of
+    the deep core exceed that, long rows need more than one binned pass, and
+    the result still equals the oracle's core numbers (Definition 2)."""
+    spec = bigraph_gen.CONFIGS[2]
+    nU, nL = spec["n_upper"], spec["n_lower"]
+    eu, ev = bigraph_gen.make_graph(spec)
+    g, ref = _make(nU, nL, eu, ev)
+    want = oracle.core_numbers(ref)
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_KCORE_SWITCH, 1 << 22)
+    core, mx = pkg.abcore_core_numbers(g)
+    top = pkg.abcore_graph_report(g)["core_top"]
+    say(f"config 2 core numbers from the first check: {top}")
+    assert top["vertices"] > 2 * 63488, top
+    assert np.array_equal(core.cpu().numpy(), want)
+    assert mx == int(want.max())
+    g.destroy()
