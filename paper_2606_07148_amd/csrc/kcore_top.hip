@@ -60,6 +60,7 @@ constexpr int kRegSpan = 8;    // rows of at most 8 x 64 entries keep their valu
 constexpr int kUnroll = ABC_TOP_UNROLL;             // row entries in flight per lane
 constexpr int kLongRow = ABC_TOP_LONG_ROW;          // longer rows: walked by a whole workgroup
 constexpr int kUnrollBlock = ABC_TOP_UNROLL_BLOCK;  // the same for those walks
+constexpr int kAgg = (kHalfBlock / kWave - 1) * (kFine + kCoarse);  // summed decrement targets
 
 // Live vertices of the alive list (core < 0) into hv and their bits into
 // live; count[0] receives their number, count[1] the number in the upper
@@ -196,15 +197,34 @@ struct HalfArgs {
   const int32_t *len_in;
   int32_t cap_in;
   int propagate;  // lowered vertices decrement their neighbours' counts
+  int spec;       // every listed vertex is due (it drops): see hindex_wave
 };
 
 // x lowered from cur to h: its neighbour y with cur >= est(y) = v > h no
 // longer counts toward c(y).  No value is returned (nothing waits): which
 // vertices became due is read from the counts before the next half.
-__device__ __forceinline__ void uncount(const HalfArgs &a, int32_t w, int32_t v, int32_t cur,
+// Decrements of c(w).  Many rows that drop in one half share their most
+// referenced neighbours, whose counts would take every one of those
+// decrements on one address in turn; the long-row phase sums them per
+// workgroup in LDS (agg, for the first nagg local ids of the layer the
+// rows read) and adds each sum once.
+struct Dec {
+  int32_t *cnt;
+  int32_t base;
+  uint32_t *agg;
+  int nagg;
+  __device__ __forceinline__ void operator()(int32_t w) const {
+    const uint32_t r = (uint32_t)(w - base);
+    if (r < (uint32_t)nagg)
+      atomicAdd(&agg[r], 1u);
+    else
+      (void)__hip_atomic_fetch_add(&cnt[w], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+
+__device__ __forceinline__ void uncount(const Dec &dec, int32_t w, int32_t v, int32_t cur,
                                         int32_t h) {
-  if (v <= cur && v > h)
-    (void)__hip_atomic_fetch_add(&a.cnt[w], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (v <= cur && v > h) dec(w);
 }
 
 // One pass of the binned h-index search over [lo, hi]: values above hi are
@@ -290,25 +310,32 @@ __device__ bool scan_bins(const Pass &p, const uint32_t *bins, int64_t above, in
 
 // The search for a row walked by one wave, in passes that reread the row.
 // Two passes cover ranges up to kFine + kFine * kCoarse; more take more.
+// spec (a vertex known to drop, below cur = hi): the first pass already
+// takes it out of the counts of its neighbours valued exactly cur.
 template <class V>
 __device__ int32_t hindex_wave(const int32_t *__restrict__ hcols, int64_t b, int64_t e,
-                               int32_t lo, int32_t hi, uint32_t *bins, V val, int64_t *c) {
-  for (;;) {
+                               int32_t lo, int32_t hi, uint32_t *bins, V val, int64_t *c,
+                               const Dec *spec) {
+  const int32_t cur = hi;
+  for (bool first = true;; first = false) {
     const Pass p = pass_of(lo, hi);
     for (int i = lane_id(); i < kFine + kCoarse; i += kWave) bins[i] = 0;
     __builtin_amdgcn_wave_barrier();
     int64_t above = 0;
     for (int64_t k0i = b; k0i < e; k0i += (int64_t)kUnroll * kWave) {
-      int32_t v[kUnroll];
+      int32_t w[kUnroll], v[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int64_t k = k0i + u * kWave + lane_id();
-        v[u] = k < e ? val(hcols[k]) : INT32_MIN;
+        w[u] = k < e ? hcols[k] : -1;
       }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) v[u] = w[u] >= 0 ? val(w[u]) : INT32_MIN;
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         above += (int64_t)__popcll(__ballot(v[u] > p.hi));
         bin_value(p, v[u], bins);
+        if (first && spec != nullptr && v[u] == cur) (*spec)(w[u]);
       }
     }
     __builtin_amdgcn_wave_barrier();
@@ -329,28 +356,32 @@ struct BlockShared {
 };
 
 // The same search for a long row walked by the whole workgroup (bins shared
-// by its waves, scanned by wave 0).  Every thread calls it.
+// by its waves, scanned by wave 0; spec as above).  Every thread calls it.
 template <class V>
 __device__ int32_t hindex_block(const int32_t *__restrict__ hcols, int64_t b, int64_t e,
                                 int32_t lo, int32_t hi, uint32_t *bins, BlockShared &sh, V val,
-                                int64_t *c) {
-  for (;;) {
+                                int64_t *c, const Dec *spec) {
+  const int32_t cur = hi;
+  for (bool first = true;; first = false) {
     const Pass p = pass_of(lo, hi);
     for (int i = threadIdx.x; i < kFine + kCoarse; i += blockDim.x) bins[i] = 0;
     if (threadIdx.x == 0) sh.above = 0;
     __syncthreads();
     uint32_t above = 0;
     for (int64_t k0i = b; k0i < e; k0i += (int64_t)kUnrollBlock * kHalfBlock) {
-      int32_t v[kUnrollBlock];
+      int32_t w[kUnrollBlock], v[kUnrollBlock];
 #pragma unroll
       for (int u = 0; u < kUnrollBlock; ++u) {
         const int64_t k = k0i + u * kHalfBlock + threadIdx.x;
-        v[u] = k < e ? val(hcols[k]) : INT32_MIN;
+        w[u] = k < e ? hcols[k] : -1;
       }
+#pragma unroll
+      for (int u = 0; u < kUnrollBlock; ++u) v[u] = w[u] >= 0 ? val(w[u]) : INT32_MIN;
 #pragma unroll
       for (int u = 0; u < kUnrollBlock; ++u) {
         above += (uint32_t)__popcll(__ballot(v[u] > p.hi));
         bin_value(p, v[u], bins);
+        if (first && spec != nullptr && v[u] == cur) (*spec)(w[u]);
       }
     }
     if (lane_id() == 0 && above) atomicAdd(&sh.above, above);
@@ -403,14 +434,28 @@ __global__ __launch_bounds__(kHalfBlock) void hindex_half_kernel(HalfArgs a) {
       return r < (uint32_t)kcr ? (int32_t)cache[r] + k0 : a.est[w];
     };
   };
+  // long rows: decrements of the first kAgg ids summed in the bins of
+  // waves 1.. (wave 0's bins serve the search), flushed before the short rows
+  const bool have_long = blockIdx.x < n_long;
+  uint32_t *agg = s_bins[1];
+  const int nagg = min(kAgg, a.tgt_cnt);
+  if (have_long) {
+    for (int i = threadIdx.x; i < nagg; i += blockDim.x) agg[i] = 0;
+    __syncthreads();
+  }
+  const Dec dec_long{a.cnt, a.tgt_base, agg, nagg};
+  const Dec dec_short{a.cnt, a.tgt_base, nullptr, 0};
   for (int64_t i = blockIdx.x; i < n_long; i += gridDim.x) {
     const int32_t x = a.q_in[a.cap_in - 1 - i];
     const int32_t cur = a.est[x];
     const int64_t b = a.hoff[x], e = b + a.hlen[x];
     const auto val = make_val(cur);
     int64_t c = 0;
-    const int32_t h = hindex_block(a.hcols, b, e, k0, cur, s_bins[0], sh, val, &c);
-    if (a.propagate && h < cur) {
+    const Dec *spec = a.spec ? &dec_long : nullptr;
+    const int32_t h = hindex_block(a.hcols, b, e, k0, cur, s_bins[0], sh, val, &c, spec);
+    // the neighbours valued cur are done if the first pass took them out
+    const int32_t top = spec ? cur - 1 : cur;
+    if (a.propagate && h < top) {
       for (int64_t k0i = b; k0i < e; k0i += (int64_t)kUnrollBlock * kHalfBlock) {
         int32_t w[kUnrollBlock], v[kUnrollBlock];
 #pragma unroll
@@ -421,13 +466,21 @@ __global__ __launch_bounds__(kHalfBlock) void hindex_half_kernel(HalfArgs a) {
 #pragma unroll
         for (int u = 0; u < kUnrollBlock; ++u) v[u] = w[u] >= 0 ? val(w[u]) : INT32_MIN;
 #pragma unroll
-        for (int u = 0; u < kUnrollBlock; ++u) uncount(a, w[u], v[u], cur, h);
+        for (int u = 0; u < kUnrollBlock; ++u) uncount(dec_long, w[u], v[u], top, h);
       }
     }
     if (threadIdx.x == 0) {
       a.cnt[x] = (int32_t)min<int64_t>(c, 0x7FFFFFFF);
       if (h < cur) a.est[x] = h;
     }
+  }
+  if (have_long) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < nagg; i += blockDim.x)
+      if (agg[i] != 0)
+        (void)__hip_atomic_fetch_add(&a.cnt[a.tgt_base + i], -(int32_t)agg[i], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();  // the short rows' bins reuse the sums' words
   }
   uint32_t *bins = s_bins[wave_in_block()];
   const int64_t nw = (int64_t)gridDim.x * kHalfWaves;
@@ -469,13 +522,15 @@ __global__ __launch_bounds__(kHalfBlock) void hindex_half_kernel(HalfArgs a) {
       }
       if (a.propagate && h < cur) {
 #pragma unroll
-        for (int u = 0; u < kRegSpan; ++u) uncount(a, w[u], v[u], cur, h);
+        for (int u = 0; u < kRegSpan; ++u) uncount(dec_short, w[u], v[u], cur, h);
       }
     } else {
       // the first pass also settles a row that does not drop (its answer
       // is cur, among the unit bins)
-      h = hindex_wave(a.hcols, b, e, k0, cur, bins, val, &c);
-      if (a.propagate && h < cur) {
+      const Dec *spec = a.spec ? &dec_short : nullptr;
+      h = hindex_wave(a.hcols, b, e, k0, cur, bins, val, &c, spec);
+      const int32_t top = spec ? cur - 1 : cur;
+      if (a.propagate && h < top) {
         for (int64_t k0i = b; k0i < e; k0i += (int64_t)kUnroll * kWave) {
           int32_t w[kUnroll], v[kUnroll];
 #pragma unroll
@@ -486,7 +541,7 @@ __global__ __launch_bounds__(kHalfBlock) void hindex_half_kernel(HalfArgs a) {
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) v[u] = w[u] >= 0 ? val(w[u]) : INT32_MIN;
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) uncount(a, w[u], v[u], cur, h);
+          for (int u = 0; u < kUnroll; ++u) uncount(dec_short, w[u], v[u], top, h);
         }
       }
     }
@@ -678,6 +733,7 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
         a.len_in = qlen + 2 * t;
         a.cap_in = self_cnt;
         a.propagate = t >= 1;
+        a.spec = t >= 2;  // from the third half on, a listed vertex is due
         hindex_half_kernel<<<grid, kHalfBlock, 0, s>>>(a);
       }
       if (!ok(hipGetLastError()) ||
