@@ -60,7 +60,10 @@ constexpr int kRegSpan = 8;    // rows of at most 8 x 64 entries keep their valu
 constexpr int kUnroll = ABC_TOP_UNROLL;             // row entries in flight per lane
 constexpr int kLongRow = ABC_TOP_LONG_ROW;          // longer rows: walked by a whole workgroup
 constexpr int kUnrollBlock = ABC_TOP_UNROLL_BLOCK;  // the same for those walks
-constexpr int kAgg = (kHalfBlock / kWave - 1) * (kFine + kCoarse);  // summed decrement targets
+// summed decrement targets: 16-bit sums, two to a word, in the bins of
+// waves 1..15 (a sum counts rows of one workgroup: at most one decrement
+// of a target per row, far fewer rows than 65536 per workgroup and half)
+constexpr int kAgg = 2 * (kHalfBlock / kWave - 1) * (kFine + kCoarse);
 
 // Live vertices of the alive list (core < 0) into hv and their bits into
 // live; count[0] receives their number, count[1] the number in the upper
@@ -203,11 +206,27 @@ struct HalfArgs {
 // x lowered from cur to h: its neighbour y with cur >= est(y) = v > h no
 // longer counts toward c(y).  No value is returned (nothing waits): which
 // vertices became due is read from the counts before the next half.
+#ifndef ABC_TOP_LDS_BARRIER
+#define ABC_TOP_LDS_BARRIER 1
+#endif
+// A workgroup barrier that orders LDS only: the half kernel's barriers
+// guard LDS words, and its global writes (decrements, values) are read by
+// later kernels only, so no wave waits here for its global memory traffic.
+__device__ __forceinline__ void lds_barrier() {
+#if ABC_TOP_LDS_BARRIER
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+#else
+  __syncthreads();
+#endif
+}
+
 // Decrements of c(w).  Many rows that drop in one half share their most
 // referenced neighbours, whose counts would take every one of those
 // decrements on one address in turn; the long-row phase sums them per
-// workgroup in LDS (agg, for the first nagg local ids of the layer the
-// rows read) and adds each sum once.
+// workgroup in LDS (agg, 16-bit sums for the first nagg local ids of the
+// layer the rows read) and adds each sum once.
 struct Dec {
   int32_t *cnt;
   int32_t base;
@@ -216,7 +235,7 @@ struct Dec {
   __device__ __forceinline__ void operator()(int32_t w) const {
     const uint32_t r = (uint32_t)(w - base);
     if (r < (uint32_t)nagg)
-      atomicAdd(&agg[r], 1u);
+      atomicAdd(&agg[r >> 1], 1u << ((r & 1) * 16));
     else
       (void)__hip_atomic_fetch_add(&cnt[w], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -366,7 +385,7 @@ __device__ int32_t hindex_block(const int32_t *__restrict__ hcols, int64_t b, in
     const Pass p = pass_of(lo, hi);
     for (int i = threadIdx.x; i < kFine + kCoarse; i += blockDim.x) bins[i] = 0;
     if (threadIdx.x == 0) sh.above = 0;
-    __syncthreads();
+    lds_barrier();
     uint32_t above = 0;
     for (int64_t k0i = b; k0i < e; k0i += (int64_t)kUnrollBlock * kHalfBlock) {
       int32_t w[kUnrollBlock], v[kUnrollBlock];
@@ -385,7 +404,7 @@ __device__ int32_t hindex_block(const int32_t *__restrict__ hcols, int64_t b, in
       }
     }
     if (lane_id() == 0 && above) atomicAdd(&sh.above, above);
-    __syncthreads();
+    lds_barrier();
     if (wave_in_block() == 0) {
       int32_t res, nhi;
       int64_t cc;
@@ -397,11 +416,11 @@ __device__ int32_t hindex_block(const int32_t *__restrict__ hcols, int64_t b, in
         sh.c = cc;
       }
     }
-    __syncthreads();
+    lds_barrier();
     const bool exact = sh.exact != 0;
     const int32_t res = sh.res, nhi = sh.nhi;
     const int64_t cc = sh.c;
-    __syncthreads();  // the next pass rewrites the shared words
+    lds_barrier();  // the next pass rewrites the shared words
     if (exact) {
       *c = cc;
       return res;
@@ -423,7 +442,7 @@ __global__ __launch_bounds__(kHalfBlock) void hindex_half_kernel(HalfArgs a) {
   const int kc = min(kCache, a.tgt_cnt);
   for (int i = threadIdx.x; i < kc; i += blockDim.x)
     cache[i] = (uint16_t)min(a.est[a.tgt_base + i] - a.k0, 65535);
-  __syncthreads();
+  lds_barrier();
   const int32_t k0 = a.k0;
   // cached values are offsets from k0 saturated at 65535: exact for every
   // comparison with thresholds <= cur while cur - k0 < 65535
@@ -438,17 +457,30 @@ __global__ __launch_bounds__(kHalfBlock) void hindex_half_kernel(HalfArgs a) {
   // waves 1.. (wave 0's bins serve the search), flushed before the short rows
   const bool have_long = blockIdx.x < n_long;
   uint32_t *agg = s_bins[1];
-  const int nagg = min(kAgg, a.tgt_cnt);
+  // (a 16-bit sum cannot wrap: at most 65535 rows per workgroup, else no sums)
+  const int nagg = n_long <= (int64_t)65535 * gridDim.x ? min(kAgg, a.tgt_cnt) : 0;
   if (have_long) {
-    for (int i = threadIdx.x; i < nagg; i += blockDim.x) agg[i] = 0;
-    __syncthreads();
+    for (int i = threadIdx.x; i < (nagg + 1) / 2; i += blockDim.x) agg[i] = 0;
+    lds_barrier();
   }
   const Dec dec_long{a.cnt, a.tgt_base, agg, nagg};
   const Dec dec_short{a.cnt, a.tgt_base, nullptr, 0};
-  for (int64_t i = blockIdx.x; i < n_long; i += gridDim.x) {
-    const int32_t x = a.q_in[a.cap_in - 1 - i];
-    const int32_t cur = a.est[x];
-    const int64_t b = a.hoff[x], e = b + a.hlen[x];
+  // a row's vertex, value and extent are loaded one row ahead (the vertex
+  // two ahead), off the chain of dependent loads of the row in hand
+  auto long_vertex = [&](int64_t i) { return i < n_long ? a.q_in[a.cap_in - 1 - i] : 0; };
+  const int64_t step = gridDim.x;
+  int32_t x_next = long_vertex(blockIdx.x);
+  int32_t x_after = long_vertex(blockIdx.x + step);
+  int32_t cur_next = a.est[x_next];
+  int64_t b_next = a.hoff[x_next], d_next = a.hlen[x_next];
+  for (int64_t i = blockIdx.x; i < n_long; i += step) {
+    const int32_t x = x_next, cur = cur_next;
+    const int64_t b = b_next, e = b + d_next;
+    x_next = x_after;
+    x_after = long_vertex(i + 2 * step);
+    cur_next = a.est[x_next];
+    b_next = a.hoff[x_next];
+    d_next = a.hlen[x_next];
     const auto val = make_val(cur);
     int64_t c = 0;
     const Dec *spec = a.spec ? &dec_long : nullptr;
@@ -475,12 +507,14 @@ __global__ __launch_bounds__(kHalfBlock) void hindex_half_kernel(HalfArgs a) {
     }
   }
   if (have_long) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < nagg; i += blockDim.x)
-      if (agg[i] != 0)
-        (void)__hip_atomic_fetch_add(&a.cnt[a.tgt_base + i], -(int32_t)agg[i], __ATOMIC_RELAXED,
+    lds_barrier();
+    for (int i = threadIdx.x; i < nagg; i += blockDim.x) {
+      const uint32_t sum = (agg[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu;
+      if (sum != 0)
+        (void)__hip_atomic_fetch_add(&a.cnt[a.tgt_base + i], -(int32_t)sum, __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();  // the short rows' bins reuse the sums' words
+    }
+    lds_barrier();  // the short rows' bins reuse the sums' words
   }
   uint32_t *bins = s_bins[wave_in_block()];
   const int64_t nw = (int64_t)gridDim.x * kHalfWaves;
