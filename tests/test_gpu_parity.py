@@ -521,3 +521,37 @@ def test_core_numbers_hindex_layers_past_the_lds_cache():
     assert np.array_equal(core.cpu().numpy(), want)
     assert mx == int(want.max())
     g.destroy()
+
+
+def test_core_numbers_hindex_wide_ranges():
+    """Rows whose value range exceeds 16 bits in the h-index phase: ten
+    lower vertices adjacent to 80,000 upper vertices (degree 80,000, core
+    10) start at their degree, so their search spans [k0, 80,000]: more than
+    two binned passes, long rows walked by a whole workgroup, and values
+    past the LDS cache's 16-bit offsets (those rows read every value from
+    memory).  Random edges around them give the other vertices varied cores.
+    Core numbers equal the oracle's (Definition 2) with the h-index phase
+    from the first check and with levels only."""
+    rng = np.random.default_rng(77)
+    nU, nL = 100_000, 1_010
+    hub_u = np.repeat(np.arange(80_000, dtype=np.int32), 10)
+    hub_v = np.tile(np.arange(10, dtype=np.int32), 80_000)
+    ru = rng.integers(80_000, nU, 300_000, dtype=np.int32)
+    rv = rng.integers(10, nL, 300_000, dtype=np.int32)
+    pairs = np.unique(np.stack([np.concatenate([hub_u, ru]), np.concatenate([hub_v, rv])], 1), axis=0)
+    eu, ev = pairs[:, 0].copy(), pairs[:, 1].copy()
+    g, ref = _make(nU, nL, eu, ev)
+    want = oracle.core_numbers(ref)
+    for switch in (1 << 30, 1):
+        pkg.abcore_set_option(g, pkg.ABCORE_OPT_KCORE_SWITCH, switch)
+        core, mx = pkg.abcore_core_numbers(g)
+        top = pkg.abcore_graph_report(g)["core_top"]
+        say(f"wide ranges, switch {switch}: {top}, max core {mx}")
+        assert (top["vertices"] > 0) == (switch > 1), top
+        assert np.array_equal(core.cpu().numpy(), want), switch
+        assert mx == int(want.max())
+        # a changed option drops the cached core numbers only with the graph;
+        # rebuild for the second switch
+        g.destroy()
+        g, _ = _make(nU, nL, eu, ev)
+    g.destroy()
