@@ -2575,7 +2575,7 @@ hipError_t launch_kcore_persistent(Graph &g, hipStream_t s) {
 // Level k of the decomposition (Definition 2: core(x) = the largest k with x
 // in the k-core) as one scan and one asynchronous peel.  The scan takes the
 // live vertices of degree <= k (core k), queues them, and appends the others
-// to the next alive list (so the list only ever holds live vertices); the
+// to the next alive list (the vertices live when the scan ran); the
 // peel then gives core k to every vertex whose degree falls to k, in any
 // order (the k-core is unique).  A level that queues nothing jumps to the
 // smallest live degree.  No grid barrier: two launches per level.
@@ -2609,16 +2609,18 @@ __global__ __launch_bounds__(kScanBlock) void kcore_level_scan_kernel(PeelArgs a
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (i0 + j < cur) {
+          // the list held live vertices of degree > the previous level when
+          // that level's scan wrote it; its peel left the survivors at
+          // degree >= kn and the removed ones below, so the degree alone
+          // tells them apart (no read of core[])
           const int32_t x = A[i0 + j];
-          if (a.core[x] < 0) {
-            const int32_t d = a.deg[x];
-            if (d <= kn) {
-              a.core[x] = kn;
-              items[cnt++] = x;
-            } else {
-              kept[kc++] = x;
-              mn = min(mn, d);
-            }
+          const int32_t d = a.deg[x];
+          if (d == kn) {
+            a.core[x] = kn;
+            items[cnt++] = x;
+          } else if (d > kn) {
+            kept[kc++] = x;
+            mn = min(mn, d);
           }
         }
       }
