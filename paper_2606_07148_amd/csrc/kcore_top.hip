@@ -110,16 +110,42 @@ __global__ void top_keys_kernel(const int32_t *__restrict__ hv, int64_t h,
   }
 }
 
-// hv[j], lid[hv[j]] = j and the row capacity deg0 (the exclusive sum of
-// which places the rows) from the sorted keys.
+// Live vertices per 32-id word of the live bitmap (words entries; one more
+// zero for the exclusive sum).
+__global__ void top_word_count_kernel(const uint32_t *__restrict__ live, int64_t words,
+                                      int64_t *__restrict__ wcount) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= words; i += stride)
+    wcount[i] = i < words ? __popc(live[i]) : 0;
+}
+
+// rk[i] = {live bits of word i, live vertices in the words before it}: the
+// rank of a live vertex among the live ones in id order is a single 8-byte
+// read, next to its liveness bit.
+__global__ void top_word_pack_kernel(const uint32_t *__restrict__ live,
+                                     const int64_t *__restrict__ wpre, int64_t words,
+                                     uint2 *__restrict__ rk) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+    rk[i] = make_uint2(live[i], (uint32_t)wpre[i]);
+}
+
+__device__ __forceinline__ int32_t id_rank(const uint2 word, int32_t w) {
+  return (int32_t)(word.y + (uint32_t)__popc(word.x & ((1u << (w & 31)) - 1u)));
+}
+
+// hv[j], perm[rank of hv[j] in id order] = j (the local id), and the row
+// capacity deg0 (the exclusive sum of which places the rows) from the
+// sorted keys.
 __global__ void top_place_kernel(const uint64_t *__restrict__ keys, int64_t h,
-                                 const int32_t *__restrict__ deg0, int32_t *__restrict__ hv,
-                                 int32_t *__restrict__ lid, int64_t *__restrict__ cap) {
+                                 const int32_t *__restrict__ deg0, const uint2 *__restrict__ rk,
+                                 int32_t *__restrict__ hv, int32_t *__restrict__ perm,
+                                 int64_t *__restrict__ cap) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < h; j += stride) {
     const int32_t x = (int32_t)(uint32_t)keys[j];
     hv[j] = x;
-    lid[x] = (int32_t)j;
+    perm[id_rank(rk[x >> 5], x)] = (int32_t)j;
     cap[j] = deg0[x];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) cap[h] = 0;
@@ -133,13 +159,12 @@ __global__ void top_place_kernel(const uint64_t *__restrict__ keys, int64_t h,
 __global__ __launch_bounds__(kBlock) void top_fill_kernel(
     const int64_t *__restrict__ off, const int32_t *__restrict__ cols,
     const int32_t *__restrict__ ins_head, const int32_t *__restrict__ ins_next,
-    const int32_t *__restrict__ ins_other, const uint32_t *__restrict__ live,
-    const int32_t *__restrict__ hv, const int32_t *__restrict__ lid, int64_t h,
+    const int32_t *__restrict__ ins_other, const uint2 *__restrict__ rk,
+    const int32_t *__restrict__ hv, const int32_t *__restrict__ perm, int64_t h,
     const int64_t *__restrict__ hoff, int32_t *__restrict__ hcols, int32_t *__restrict__ hlen,
     int32_t *__restrict__ est, int32_t *overflow) {
   const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
   const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
-  auto is_live = [&](int32_t w) { return w >= 0 && ((live[w >> 5] >> (w & 31)) & 1u); };
   for (int64_t j = gw; j < h; j += nw) {
     const int32_t x = hv[j];
     const int64_t cap = hoff[j + 1] - hoff[j];
@@ -153,12 +178,15 @@ __global__ __launch_bounds__(kBlock) void top_fill_kernel(
         const int64_t k = j0 + u * kWave + lane_id();
         w[u] = k < e ? cols[k] : -1;
       }
+      uint2 word[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) word[u] = w[u] >= 0 ? rk[w[u] >> 5] : make_uint2(0, 0);
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        const bool on = is_live(w[u]);
+        const bool on = w[u] >= 0 && ((word[u].x >> (w[u] & 31)) & 1u);
         const uint64_t mask = __ballot(on);
         const int64_t r = done + (int64_t)__popcll(mask & lanemask_lt());
-        if (on && r < cap) row[r] = lid[w[u]];
+        if (on && r < cap) row[r] = perm[id_rank(word[u], w[u])];
         done += (int64_t)__popcll(mask);
       }
     }
@@ -168,8 +196,9 @@ __global__ __launch_bounds__(kBlock) void top_fill_kernel(
       if (lane_id() == 0) {
         for (int q = ins_head[x]; q >= 0; q = ins_next[q]) {
           const int32_t w = ins_other[q];
-          if (is_live(w)) {
-            if (done + extra < cap) row[done + extra] = lid[w];
+          const uint2 word = w >= 0 ? rk[w >> 5] : make_uint2(0, 0);
+          if (w >= 0 && ((word.x >> (w & 31)) & 1u)) {
+            if (done + extra < cap) row[done + extra] = perm[id_rank(word, w)];
             ++extra;
           }
         }
@@ -654,7 +683,9 @@ int grid_of(const Graph &g, int64_t items, int per_block) {
 abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
                         int max_halves, bool *finished, int32_t *top_max, hipStream_t s) {
   *finished = false;
-  int32_t *lid = nullptr, *hv = nullptr, *hcols = nullptr, *est = nullptr, *ctr = nullptr;
+  int32_t *perm = nullptr, *hv = nullptr, *hcols = nullptr, *est = nullptr, *ctr = nullptr;
+  int64_t *wcount = nullptr, *wpre = nullptr;
+  uint2 *rk = nullptr;
   int32_t *hlen = nullptr, *cntv = nullptr, *queue = nullptr, *qlen = nullptr;
   uint32_t *live = nullptr;
   uint64_t *keys = nullptr, *keys2 = nullptr;
@@ -671,7 +702,9 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
   auto ok = [](hipError_t e) { return e == hipSuccess; };
   do {
     // ctr: [0] live count, [1] upper-layer count, [2] overflow, [3] maximum
-    if (!ok(dev_malloc_async(&lid, sizeof(int32_t) * std::max<int64_t>(g.n, 1), s)) ||
+    if (!ok(dev_malloc_async(&wcount, sizeof(int64_t) * (words + 1), s)) ||
+        !ok(dev_malloc_async(&wpre, sizeof(int64_t) * (words + 1), s)) ||
+        !ok(dev_malloc_async(&rk, sizeof(uint2) * std::max<int64_t>(words, 1), s)) ||
         !ok(dev_malloc_async(&hv, sizeof(int32_t) * std::max<int64_t>(cnt, 1), s)) ||
         !ok(dev_malloc_async(&live, sizeof(uint32_t) * std::max<int64_t>(words, 1), s)) ||
         !ok(dev_malloc_async(&ctr, sizeof(int32_t) * 4, s)) ||
@@ -704,23 +737,39 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
       st = ABCORE_ENOMEM;
       break;
     }
+    if (!ok(dev_malloc_async(&perm, sizeof(int32_t) * std::max<int64_t>(h, 1), s))) {
+      st = ABCORE_ENOMEM;
+      break;
+    }
     // local ids: layer, then decreasing degree
     if (h > 0) {
       top_keys_kernel<<<grid_of(g, h, kBlock), kBlock, 0, s>>>(hv, h, g.deg0, g.nU, keys);
       if (!ok(hipGetLastError())) break;
     }
-    size_t sort_bytes = 0, scan_bytes = 0;
+    size_t sort_bytes = 0, scan_bytes = 0, wscan_bytes = 0;
     if (!ok(prim::sort_keys(nullptr, sort_bytes, keys, keys2, (size_t)h, 0, 64, s)) ||
-        !ok(prim::exclusive_sum(nullptr, scan_bytes, cap, hoff, (size_t)(h + 1), s)))
+        !ok(prim::exclusive_sum(nullptr, scan_bytes, cap, hoff, (size_t)(h + 1), s)) ||
+        !ok(prim::exclusive_sum(nullptr, wscan_bytes, wcount, wpre, (size_t)(words + 1), s)))
       break;
-    temp_bytes = std::max<size_t>({sort_bytes, scan_bytes, 16});
+    temp_bytes = std::max<size_t>({sort_bytes, scan_bytes, wscan_bytes, 16});
     if (!ok(dev_malloc_async(&temp, temp_bytes, s))) {
       st = ABCORE_ENOMEM;
       break;
     }
+    // ranks of the live vertices in id order, read next to their bits
+    top_word_count_kernel<<<grid_of(g, words + 1, kBlock), kBlock, 0, s>>>(live, words, wcount);
     size_t tb = temp_bytes;
+    if (!ok(hipGetLastError()) ||
+        !ok(prim::exclusive_sum(temp, tb, wcount, wpre, (size_t)(words + 1), s)))
+      break;
+    if (words > 0) {
+      top_word_pack_kernel<<<grid_of(g, words, kBlock), kBlock, 0, s>>>(live, wpre, words, rk);
+      if (!ok(hipGetLastError())) break;
+    }
+    tb = temp_bytes;
     if (h > 0 && !ok(prim::sort_keys(temp, tb, keys, keys2, (size_t)h, 0, 64, s))) break;
-    top_place_kernel<<<grid_of(g, h + 1, kBlock), kBlock, 0, s>>>(keys2, h, g.deg0, hv, lid, cap);
+    top_place_kernel<<<grid_of(g, h + 1, kBlock), kBlock, 0, s>>>(keys2, h, g.deg0, rk, hv, perm,
+                                                                   cap);
     if (!ok(hipGetLastError())) break;
     tb = temp_bytes;
     if (!ok(prim::exclusive_sum(temp, tb, cap, hoff, (size_t)(h + 1), s))) break;
@@ -733,7 +782,7 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
     }
     if (h > 0) {
       top_fill_kernel<<<grid_of(g, h * kWave, kBlock), kBlock, 0, s>>>(
-          g.off, g.cols, ih, g.delta.next, g.delta.other, live, hv, lid, h, hoff, hcols, hlen,
+          g.off, g.cols, ih, g.delta.next, g.delta.other, rk, hv, perm, h, hoff, hcols, hlen,
           est, ctr + 2);
       if (!ok(hipGetLastError())) break;
     }
@@ -811,7 +860,7 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
     *finished = true;
     st = ABCORE_OK;
   } while (0);
-  for (void *p : {(void *)lid, (void *)hv, (void *)hcols, (void *)est, (void *)ctr, (void *)hlen,
+  for (void *p : {(void *)perm, (void *)wcount, (void *)wpre, (void *)rk, (void *)hv, (void *)hcols, (void *)est, (void *)ctr, (void *)hlen,
                   (void *)hoff, (void *)cap, (void *)keys, (void *)keys2, (void *)cntv,
                   (void *)queue, (void *)qlen, (void *)live, temp})
     if (p) (void)dev_free_async(p, s);
