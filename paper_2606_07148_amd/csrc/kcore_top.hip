@@ -18,19 +18,20 @@
 // is recomputed only when its value must drop: c(x) counts the neighbours
 // whose value is >= est(x), and x is due exactly when c(x) < est(x).  A
 // vertex a half lowers from `old` to `new` decrements c(y) of each
-// neighbour y with old >= est(y) > new; the decrement that takes c(y) from
-// est(y) to est(y) - 1 queues y for the next half (at most once per half:
-// c(y) >= est(y) holds for every vertex when the half begins).  Past the
-// first few halves only a few thousand vertices drop per half, while a dense
-// core's every row has one of them as neighbour, so this does a fraction of
-// the work of sweeps that recompute every row with a changed neighbour.
+// neighbour y with old >= est(y) > new, and the next half lists the due
+// vertices of its layer from the counts.  Past the first few halves only a
+// few thousand vertices drop per half, while a dense core's every row has
+// one of them as neighbour, so this does a fraction of the work of sweeps
+// that recompute every row with a changed neighbour.
 //
 // Layout.  H's vertices get local ids by layer, then by decreasing degree,
 // so the most referenced values of a layer come first: each workgroup keeps
 // the first 63,488 values of the layer a half reads in LDS (16 bits each,
 // offsets from k0), and only entries past them read the values array.  Rows
 // are written at offsets given by the vertices' degrees in G (an upper
-// bound of their degrees in H), so the adjacency is built in one walk.
+// bound of their degrees in H), so the adjacency is built in one walk; a
+// neighbour's local id comes from its rank among the live vertices in id
+// order (a live bitmap with per-word prefix counts) through a permutation.
 #include <algorithm>
 #include <vector>
 
@@ -686,7 +687,7 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
   int32_t *perm = nullptr, *hv = nullptr, *hcols = nullptr, *est = nullptr, *ctr = nullptr;
   int64_t *wcount = nullptr, *wpre = nullptr;
   uint2 *rk = nullptr;
-  int32_t *hlen = nullptr, *cntv = nullptr, *queue = nullptr, *qlen = nullptr;
+  int32_t *hlen = nullptr, *cntv = nullptr, *lists = nullptr, *list_len = nullptr;
   uint32_t *live = nullptr;
   uint64_t *keys = nullptr, *keys2 = nullptr;
   int64_t *cap = nullptr, *hoff = nullptr;
@@ -708,12 +709,12 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
         !ok(dev_malloc_async(&hv, sizeof(int32_t) * std::max<int64_t>(cnt, 1), s)) ||
         !ok(dev_malloc_async(&live, sizeof(uint32_t) * std::max<int64_t>(words, 1), s)) ||
         !ok(dev_malloc_async(&ctr, sizeof(int32_t) * 4, s)) ||
-        !ok(dev_malloc_async(&qlen, sizeof(int32_t) * 2 * (max_halves + 2), s))) {
+        !ok(dev_malloc_async(&list_len, sizeof(int32_t) * 2 * (max_halves + 2), s))) {
       st = ABCORE_ENOMEM;
       break;
     }
     if (!ok(hipMemsetAsync(ctr, 0, sizeof(int32_t) * 4, s)) ||
-        !ok(hipMemsetAsync(qlen, 0, sizeof(int32_t) * 2 * (max_halves + 2), s)) ||
+        !ok(hipMemsetAsync(list_len, 0, sizeof(int32_t) * 2 * (max_halves + 2), s)) ||
         !ok(hipMemsetAsync(live, 0, sizeof(uint32_t) * std::max<int64_t>(words, 1), s)))
       break;
     if (cnt > 0) {
@@ -733,7 +734,7 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
         !ok(dev_malloc_async(&hlen, sizeof(int32_t) * std::max<int64_t>(h, 1), s)) ||
         !ok(dev_malloc_async(&est, sizeof(int32_t) * std::max<int64_t>(h, 1), s)) ||
         !ok(dev_malloc_async(&cntv, sizeof(int32_t) * std::max<int64_t>(h, 1), s)) ||
-        !ok(dev_malloc_async(&queue, sizeof(int32_t) * std::max<int64_t>(h, 1), s))) {
+        !ok(dev_malloc_async(&lists, sizeof(int32_t) * std::max<int64_t>(h, 1), s))) {
       st = ABCORE_ENOMEM;
       break;
     }
@@ -788,8 +789,8 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
     }
     // half sweeps: the upper layer first (all of it, no counts to keep yet),
     // then the lower layer (all of it, decrementing the upper layer's
-    // counts), then the due vertices of each layer in turn; qlen[2t] and
-    // qlen[2t + 1] count half t's short and long rows
+    // counts), then the due vertices of each layer in turn; list_len[2t] and
+    // list_len[2t + 1] count half t's short and long rows
     const int32_t hL = (int32_t)h - hU;
     if (h > 0 && !ok(hipMemsetAsync(cntv, 0, sizeof(int32_t) * h, s))) break;
     const int grid = std::max(1, std::min(g.cu_count, kMaxBlocks));
@@ -802,7 +803,7 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
         const bool upper = (t % 2) == 0;
         const int32_t self_base = upper ? 0 : hU, self_cnt = upper ? hU : hL;
         top_due_kernel<<<grid_of(g, self_cnt, kBlock), kBlock, 0, s>>>(
-            est, cntv, hlen, self_base, self_cnt, queue + self_base, qlen + 2 * t);
+            est, cntv, hlen, self_base, self_cnt, lists + self_base, list_len + 2 * t);
         HalfArgs a{};
         a.hoff = hoff;
         a.hlen = hlen;
@@ -812,15 +813,15 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
         a.k0 = k0;
         a.tgt_base = upper ? hU : 0;
         a.tgt_cnt = upper ? hL : hU;
-        a.q_in = queue + self_base;
-        a.len_in = qlen + 2 * t;
+        a.q_in = lists + self_base;
+        a.len_in = list_len + 2 * t;
         a.cap_in = self_cnt;
         a.propagate = t >= 1;
         a.spec = t >= 2;  // from the third half on, a listed vertex is due
         hindex_half_kernel<<<grid, kHalfBlock, 0, s>>>(a);
       }
       if (!ok(hipGetLastError()) ||
-          !ok(hipMemcpyAsync(hq.data(), qlen + 2 * t0, sizeof(int32_t) * 2 * (t - t0),
+          !ok(hipMemcpyAsync(hq.data(), list_len + 2 * t0, sizeof(int32_t) * 2 * (t - t0),
                              hipMemcpyDeviceToHost, s)) ||
           !ok(hipStreamSynchronize(s))) {
         failed = true;
@@ -862,7 +863,7 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
   } while (0);
   for (void *p : {(void *)perm, (void *)wcount, (void *)wpre, (void *)rk, (void *)hv, (void *)hcols, (void *)est, (void *)ctr, (void *)hlen,
                   (void *)hoff, (void *)cap, (void *)keys, (void *)keys2, (void *)cntv,
-                  (void *)queue, (void *)qlen, (void *)live, temp})
+                  (void *)lists, (void *)list_len, (void *)live, temp})
     if (p) (void)dev_free_async(p, s);
   if (st == ABCORE_ENOMEM) set_error("core numbers: the h-index phase is out of memory");
   else if (st != ABCORE_OK) set_error("%s", why);
