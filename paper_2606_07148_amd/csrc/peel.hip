@@ -23,6 +23,8 @@
 // slots, and round bookkeeping is done by a whole wave in parallel.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "abcore_internal.h"
 #include "wave.h"
 
@@ -1372,10 +1374,45 @@ struct PullShared {
 
 // Bit of neighbour v (0 for v < 0: padding or a deleted entry), branch-free
 // so that a group of lookups issues together.
-__device__ __forceinline__ uint32_t test_bit(const uint32_t *w, int64_t base_word, int32_t v) {
-  const int64_t idx = v >= 0 ? (int64_t)(v >> 5) - base_word : 0;
-  return (w[idx] >> (v & 31)) & (v >= 0 ? 1u : 0u);
-}
+// Entry tests in two steps, so that a batch issues all its word loads
+// before it uses any (one wait for the batch instead of one per entry):
+// word(v) loads what the test needs, pass(word, v) decides.  Deleted and
+// padding entries (negative) never pass.
+struct BitTest {  // v's bit in a bitmap of words from base_word (global)
+  const uint32_t *w;
+  int64_t base_word;
+  uint32_t zero;  // (unused)
+  __device__ __forceinline__ uint32_t word(int32_t v) const {
+    return w[v >= 0 ? (int64_t)(v >> 5) - base_word : 0];
+  }
+  __device__ __forceinline__ uint32_t pass(uint32_t wd, int32_t v) const {
+    return v >= 0 ? (wd >> (v & 31)) & 1u : 0u;
+  }
+};
+// The same for a bitmap staged in LDS with a zero word at index `zero`
+// (just past the staged words): a negative entry's word index, computed
+// signed, is negative and clamps (as unsigned) to the zero word, so neither
+// the index nor the result needs a test of the sign; ubfe takes the bit
+// position from the low five bits of v.
+struct BitTestLds {
+  const uint32_t *w;
+  int64_t base_word;
+  uint32_t zero;
+  __device__ __forceinline__ uint32_t word(int32_t v) const {
+    const uint32_t idx = (uint32_t)((v >> 5) - (int32_t)base_word);
+    return w[min(idx, zero)];
+  }
+  __device__ __forceinline__ uint32_t pass(uint32_t wd, int32_t v) const {
+    return __builtin_amdgcn_ubfe(wd, (uint32_t)v, 1u);
+  }
+};
+struct BelowTest {  // v below a bound (the rank copy's surviving prefix)
+  int32_t kb;
+  __device__ __forceinline__ uint32_t word(int32_t) const { return 0; }
+  __device__ __forceinline__ uint32_t pass(uint32_t, int32_t v) const {
+    return (uint32_t)(v >= 0 && v < kb);
+  }
+};
 
 // Row entries that pass `test` in [s, s+d) of `src` (the adjacency with the
 // bitmap test, deleted entries negative and never counting, or the rank
@@ -1390,9 +1427,12 @@ __device__ __forceinline__ int count_row_thread(const PeelArgs &a, const int32_t
 #pragma unroll
     for (int j = 0; j < kLightRow; ++j) w[j] = view_col(a, j < d, s + j, w[j]);
   }
+  uint32_t wd[kLightRow];
+#pragma unroll
+  for (int j = 0; j < kLightRow; ++j) wd[j] = test.word(w[j]);
   int c = 0;
 #pragma unroll
-  for (int j = 0; j < kLightRow; ++j) c += (int)test(w[j]);
+  for (int j = 0; j < kLightRow; ++j) c += (int)test.pass(wd[j], w[j]);
   return c;
 }
 
@@ -1440,11 +1480,16 @@ __device__ __forceinline__ void count_chunks(const PeelArgs &a, const int32_t *s
         for (int j = 0; j < 4; ++j)
           w[r][j] = view_col(a, l + 16 * j < cdn[r], cs[r] + l + 16 * j, w[r][j]);
     }
+    uint32_t wd[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) wd[r][j] = test.word(w[r][j]);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       int c = 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) c += (int)test(w[r][j]);
+      for (int j = 0; j < 4; ++j) c += (int)test.pass(wd[r][j], w[r][j]);
       c += __shfl_xor(c, 8, 16);
       c += __shfl_xor(c, 4, 16);
       c += __shfl_xor(c, 2, 16);
@@ -1528,7 +1573,15 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
             (__attribute__((address_space(3))) void *)(s_bits + 4 * cc * kWave), 16, 0, 0);
     }
     for (int64_t i = a0 + 4 * n4 + threadIdx.x; i <= w1; i += blockDim.x) s_bits[i - a0] = gbits[i];
+    // the zero word just past the staged ones (the dynamic size holds four
+    // words more than a layer's bitmap, and a0 lies at most three below it)
+    if (threadIdx.x == 0) s_bits[w1 + 1 - a0] = 0;
     __builtin_amdgcn_s_waitcnt(0);  // the loads have landed in LDS (the caller then syncs)
+  };
+  auto zero_word = [&](int phase) -> uint32_t {
+    const int64_t nb_lo = phase == 0 ? a.nU : 0, nb_hi = phase == 0 ? n : a.nU;
+    const int64_t w1 = nb_hi > nb_lo ? ((nb_hi - 1) >> 5) : (nb_lo >> 5);
+    return (uint32_t)(w1 + 1 - stage_base(phase));
   };
   if (threadIdx.x == 0) {
     sh.next_row = 0;
@@ -1624,10 +1677,13 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     if (lo >= hi) continue;
     const uint32_t *lk = gbits;
     int64_t lk_base = 0;
+    uint32_t lk_zero = 0;
     if (kLds) {
       lk = s_bits;
       lk_base = stage_base(phase);
+      lk_zero = zero_word(phase);
     }
+    using RowTest = typename std::conditional<kLds, BitTestLds, BitTest>::type;
     // This workgroup's rows (a range of equal weight, else an equal share)
     // and pieces; its waves claim 64 of them at a time through LDS.
     const int G = (int)gridDim.x, k = (int)blockIdx.x;
@@ -1649,7 +1705,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
       const int32_t kb = sh.k_alive[phase ^ 1] + (phase == 0 ? a.nU : 0);
       const int64_t nh = phase == 0 ? nheavy_upper : nheavy - nheavy_upper;
       const int64_t hend = base + min(nh, kself), lend = base + kself;
-      auto below = [kb](int32_t v) { return (uint32_t)(v >= 0 && v < kb); };
+      const BelowTest below{kb};
       for (;;) {
         int claim = 0;
         if (lane_id() == 0) claim = atomicAdd(&sh.next_row, 1);
@@ -1761,7 +1817,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
       b = bn;
       int c = 0;
       const bool grouped = alive && d > kLightRow;
-      auto bit = [&](int32_t v) { return test_bit(lk, lk_base, v); };
+      const RowTest bit{lk, lk_base, lk_zero};
       if (alive && d <= kLightRow) c = count_row_thread(a, a.cols, s, d, bit);
       count_chunks(a, a.cols, grouped, s, d, desc, cnt, bit);
       if (grouped) c = cnt[lane_id()];
@@ -1796,8 +1852,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
         d = (int)(min(s + kPiece, re) - s);
         first = s == rs;
       }
-      count_chunks(a, a.cols, alive, s, d, desc, cnt,
-                   [&](int32_t v) { return test_bit(lk, lk_base, v); });
+      count_chunks(a, a.cols, alive, s, d, desc, cnt, RowTest{lk, lk_base, lk_zero});
       int c = 0;
       if (alive) {
         entries += d;
