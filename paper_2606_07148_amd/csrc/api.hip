@@ -471,7 +471,10 @@ abcore_status compute_core(Graph &g, hipStream_t s) {
         const int32_t *L = g.h_state->alive_sel ? g.list2 : g.list;
         const auto t_top = std::chrono::steady_clock::now();
         g.top_ms[0] = std::chrono::duration<double, std::milli>(t_top - t_levels).count();
-        TRY(kcore_top(g, L, alive, g.h_state->next_k, 8192, &fin, &tmax, s));
+        // the h-index phase needs temporaries of the deep core's size; when
+        // they do not fit the memory budget the levels finish the job
+        const abcore_status ts = kcore_top(g, L, alive, g.h_state->next_k, 8192, &fin, &tmax, s);
+        if (ts != ABCORE_OK && ts != ABCORE_ENOMEM) return ts;
         g.top_ms[1] = std::chrono::duration<double, std::milli>(
                           std::chrono::steady_clock::now() - t_top).count();
         if (fin) {
