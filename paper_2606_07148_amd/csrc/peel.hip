@@ -1531,7 +1531,9 @@ __device__ __forceinline__ int delta_alive(const PeelArgs &a, const uint32_t *gb
 
 // kLds: the neighbour layer's bitmap is staged in LDS (a compile-time
 // choice, so that lookups are LDS reads and not generic-address loads).
-template <bool kLds>
+// kRank: the rank form (rows of the degree-rank copy, rcols non-null),
+// compiled apart from the vertex form (each form has its own tests).
+template <bool kLds, bool kRank>
 __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     PeelArgs a, const uint32_t *__restrict__ gbits, const int32_t *__restrict__ deg0, int64_t n,
     int scan_blocks, int mode, int use_lds, int64_t total_entries, int64_t npieces,
@@ -1541,6 +1543,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     int rest_part, const int32_t *__restrict__ written_snap, const int32_t *__restrict__ rcols,
     const int32_t *__restrict__ rank_vtx, const int64_t *__restrict__ roff, int64_t nheavy,
     int64_t nheavy_upper, int rspace, int64_t rk_u, int64_t rk_l, uint32_t *__restrict__ rs_bits) {
+  static_assert(!(kLds && kRank), "the rank form looks nothing up in a bitmap");
   extern __shared__ __align__(16) uint32_t s_bits[];
   __shared__ PullShared sh;
   if (rspace && a.rs_fail != nullptr && ld_agent(a.rs_fail) != 0) {
@@ -1601,7 +1604,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     // surviving row (a few per split row): worth it once the frontier's
     // atomics are about half as many as the survivors
     int64_t ku = 0, kl = 0;
-    if (rcols != nullptr) {
+    if (kRank) {
       // (known in advance for a query in rank order)
       ku = rk_u >= 0 ? rk_u : wave_sum_strided(a.part + kPartAliveU, scan_blocks, kPartFields);
       kl = rk_l >= 0 ? rk_l : wave_sum_strided(a.part + kPartAliveL, scan_blocks, kPartFields);
@@ -1613,7 +1616,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     const bool pull =
         mode == 2 ||
         (mode == 0 && f0deg > 0 &&
-         (rcols != nullptr ? f0deg * 2 >= ku + kl
+         (kRank ? f0deg * 2 >= ku + kl
                            : (use_lds ? f0deg * 16 >= rest : f0deg * 6 >= rest)));
     if (lane_id() == 0) sh.decide = pull ? 1 : 0;
   }
@@ -1691,7 +1694,7 @@ __global__ __launch_bounds__(kPullBlock) void pull_round_kernel(
     const int64_t r1 = bounds != nullptr ? bounds[phase * (G + 1) + k + 1]
                                          : lo + (hi - lo) * (k + 1) / G;
     const int64_t p0 = plo + (phi - plo) * k / G, p1 = plo + (phi - plo) * (k + 1) / G;
-    if (rcols != nullptr) {
+    if (kRank) {
       // Rank form: the surviving rows of this layer are its ranks below
       // kself, split rows (more than kPiece entries) first; a row's
       // surviving neighbours are its rank row's prefix below kb.  Chunks of
@@ -1955,7 +1958,7 @@ hipError_t prepare_pull_kernel(Graph &g) {
   // (256 bytes left for the alignment of the dynamic part)
   const int dyn = (int)std::max<int64_t>(
       0, (int64_t)g.lds_per_block - (int64_t)sizeof(PullShared) - 256);
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&pull_round_kernel<true>),
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&pull_round_kernel<true, false>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
 }
 
@@ -1985,16 +1988,22 @@ hipError_t launch_pull_round_args(Graph &g, const PeelArgs &a, const uint32_t *b
   const int32_t *bounds = g.pull_bounds_grid == grid ? g.pull_bounds : nullptr;
   const int32_t *rcols = rank ? g.rcols : nullptr;
   if (use_lds)
-    pull_round_kernel<true><<<grid, kPullBlock, dyn, s>>>(
+    pull_round_kernel<true, false><<<grid, kPullBlock, dyn, s>>>(
         a, bits, g.deg0, g.n, scan_grid(g), mode, 1, total_entries, g.npieces,
+        g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0,
+        rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr, nullptr, g.rank_vtx,
+        g.roff, g.nheavy, g.nheavy_upper, 0, -1, -1, nullptr);
+  else if (rcols != nullptr)
+    pull_round_kernel<false, true><<<grid, kPullBlock, dyn, s>>>(
+        a, bits, g.deg0, g.n, scan_grid(g), mode, 0, total_entries, g.npieces,
         g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0,
         rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr, rcols, g.rank_vtx,
         g.roff, g.nheavy, g.nheavy_upper, 0, -1, -1, nullptr);
   else
-    pull_round_kernel<false><<<grid, kPullBlock, dyn, s>>>(
+    pull_round_kernel<false, false><<<grid, kPullBlock, dyn, s>>>(
         a, bits, g.deg0, g.n, scan_grid(g), mode, 0, total_entries, g.npieces,
         g.npieces_upper, corr_x, corr_d, ncorr, advance ? 1 : 0, bounds, queue_f0 ? 1 : 0,
-        rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr, rcols, g.rank_vtx,
+        rowbits, rest_part ? 1 : 0, rest_part ? g.split_written : nullptr, nullptr, g.rank_vtx,
         g.roff, g.nheavy, g.nheavy_upper, 0, -1, -1, nullptr);
   return hipGetLastError();
 }
@@ -2023,7 +2032,7 @@ hipError_t launch_rank_query(Graph &g, int32_t thrU, int32_t thrL, int64_t ku, i
     a.rs_mask = g.rdeg_mask;
     a.rs_fail = g.rs_fail;
     const int grid = g.cu_count;
-    pull_round_kernel<false><<<grid, kPullBlock, 0, s>>>(
+    pull_round_kernel<false, true><<<grid, kPullBlock, 0, s>>>(
         a, g.alive_bits, g.deg0, g.n, scan_grid(g), 2, 0, 2 * g.m, g.npieces, g.npieces_upper,
         nullptr, nullptr, 0, 0, nullptr, 0, g.alive_bits, 0, nullptr, g.rcols, g.rank_vtx, g.roff,
         g.nheavy, g.nheavy_upper, 1, ku, kl, pack_bits);
