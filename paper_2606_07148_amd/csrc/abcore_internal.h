@@ -110,6 +110,8 @@ struct PeelState {
   int32_t aux0, aux1;   // small results (uncertain count, labels, answer bits)
   int32_t pulled;       // first round ran in pull form
   int32_t abort_flag;   // a grid barrier exceeded its spin limit
+  int32_t dead;         // core decomposition: alive-list entries found removed by a scan
+  int32_t live;         // core decomposition: live entries of the alive list after a scan
   int32_t pad0;
   int64_t launches;     // launches that did work
   // arrival counters of the workspace reset only (never zeroed: that kernel

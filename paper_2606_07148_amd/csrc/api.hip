@@ -463,7 +463,8 @@ abcore_status compute_core(Graph &g, hipStream_t s) {
       if (g.h_state->done) break;
       // the deep levels by the h-index fixpoint once the live part (the
       // next_k-core) is small: at most kcore_switch vertices
-      const int64_t alive = g.h_state->alive_cur;
+      // (the list may still hold removed entries: the live count decides)
+      const int64_t alive = g.h_state->live;
       if (!top_tried && g.h_state->next_k >= 1 && alive <= g.kcore_switch) {
         top_tried = true;
         bool fin = false;
@@ -473,7 +474,8 @@ abcore_status compute_core(Graph &g, hipStream_t s) {
         g.top_ms[0] = std::chrono::duration<double, std::milli>(t_top - t_levels).count();
         // the h-index phase needs temporaries of the deep core's size; when
         // they do not fit the memory budget the levels finish the job
-        const abcore_status ts = kcore_top(g, L, alive, g.h_state->next_k, 8192, &fin, &tmax, s);
+        const abcore_status ts =
+            kcore_top(g, L, g.h_state->alive_cur, g.h_state->next_k, 8192, &fin, &tmax, s);
         if (ts != ABCORE_OK && ts != ABCORE_ENOMEM) return ts;
         g.top_ms[1] = std::chrono::duration<double, std::milli>(
                           std::chrono::steady_clock::now() - t_top).count();

@@ -761,6 +761,9 @@ __device__ __forceinline__ bool peel_visit(const PeelArgs &a, int32_t w, int32_t
 #ifndef ABC_UNROLL
 #define ABC_UNROLL 4
 #endif
+#ifndef ABC_LEVEL_COMPACT_ALWAYS
+#define ABC_LEVEL_COMPACT_ALWAYS 0
+#endif
 constexpr int kUnroll = ABC_UNROLL;
 
 // Removes up to 64 queue items (vertices or pieces of split rows; -1 marks
@@ -2649,21 +2652,30 @@ __global__ __launch_bounds__(kScanBlock) void kcore_level_scan_kernel(PeelArgs a
   __shared__ ScanCollector col;   // queued vertices
   __shared__ ScanCollector keep;  // live vertices for the next level
   __shared__ int32_t s_min;
+  __shared__ int32_t s_kept, s_dead;
   PeelState *st = a.st;
   if (st->done) return;  // written by an earlier launch
   const int32_t kn = st->next_k;
   const int32_t cur = st->alive_cur;
   const int sel = st->alive_sel;
+  // the list is rewritten without its removed entries only when enough of
+  // it was found removed before (rewriting costs a write per kept entry;
+  // a removed entry left in place costs a read per scan, and the degree
+  // tells it apart at any later level too)
+  const bool compact = ABC_LEVEL_COMPACT_ALWAYS || st->compact != 0;
   const int32_t *A = sel ? list1 : list0;
   int32_t *N = sel ? list0 : list1;
   if (threadIdx.x == 0) {
     col.count = 0;
     keep.count = 0;
     s_min = 0x7FFFFFFF;
+    s_kept = 0;
+    s_dead = 0;
   }
   __syncthreads();
   const int sub = blockIdx.x % kSub;
   int32_t mn = 0x7FFFFFFF;
+  int kept_here = 0, dead_here = 0;
   for (int64_t cb = (int64_t)blockIdx.x * kScanChunk; cb < cur;
        cb += (int64_t)gridDim.x * kScanChunk) {
     for (int t = 0; t < kScanChunk; t += kScanBlock * 4) {
@@ -2685,18 +2697,30 @@ __global__ __launch_bounds__(kScanBlock) void kcore_level_scan_kernel(PeelArgs a
           } else if (d > kn) {
             kept[kc++] = x;
             mn = min(mn, d);
+          } else {
+            ++dead_here;
           }
         }
       }
       col.append(items, cnt);
-      keep.append(kept, kc);
+      kept_here += kc;
+      dead_here += cnt;  // queued now: removed for the next scan
+      if (compact) keep.append(kept, kc);
     }
     col.flush_queue(a, sub);
-    keep.flush(N, &a.st->kept);
+    if (compact) keep.flush(N, &a.st->kept);
   }
   mn = wave_min(mn);
-  if (lane_id() == 0) atomicMin(&s_min, mn);
+  kept_here = wave_sum(kept_here);
+  dead_here = wave_sum(dead_here);
+  if (lane_id() == 0) {
+    atomicMin(&s_min, mn);
+    atomicAdd(&s_kept, kept_here);
+    atomicAdd(&s_dead, dead_here);
+  }
   __syncthreads();
+  if (!compact && threadIdx.x == 0 && s_kept > 0) atomicAdd(&st->kept, s_kept);
+  if (threadIdx.x == 0 && s_dead > 0) atomicAdd(&st->dead, s_dead);
   if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * kPartFields + kPartMin] = s_min;
   if (last_block_done<false>(st)) {
     const int lane = lane_id();
@@ -2708,13 +2732,21 @@ __global__ __launch_bounds__(kScanBlock) void kcore_level_scan_kernel(PeelArgs a
     advance_round_wave(st, a.qcap);  // the queued vertices start the level's peel
     if (lane < kGroups) st->fin[lane][0] = 0;  // the level's peel detects its own end
     if (lane == 0) {
-      const int32_t kept_n = ld_agent(&st->kept);
+      const int32_t kept_n = ld_agent(&st->kept);  // live entries
+      const int32_t dead_n = ld_agent(&st->dead);
       st->k = kn;
       if (after > 0) st->max_core = kn;
       st->next_k = after > 0 ? kn + 1 : max(kn + 1, gmin);
-      st->alive_cur = kept_n;
-      st->alive_sel = sel ^ 1;
+      if (compact) {
+        st->alive_cur = kept_n;
+        st->alive_sel = sel ^ 1;
+      }
+      // the next scan rewrites the list once a quarter of it is removed
+      const int32_t len = compact ? kept_n : cur;
+      st->compact = (int64_t)(compact ? 0 : dead_n) * 4 > len ? 1 : 0;
+      st->live = kept_n;
       st->kept = 0;
+      st->dead = 0;
       if (kept_n == 0) st->done = 1;
       atomicAdd((unsigned long long *)&st->launches, 1ull);
     }
