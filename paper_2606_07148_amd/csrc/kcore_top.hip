@@ -233,9 +233,6 @@ struct HalfArgs {
   int spec;       // every listed vertex is due (it drops): see hindex_wave
 };
 
-// x lowered from cur to h: its neighbour y with cur >= est(y) = v > h no
-// longer counts toward c(y).  No value is returned (nothing waits): which
-// vertices became due is read from the counts before the next half.
 #ifndef ABC_TOP_LDS_BARRIER
 #define ABC_TOP_LDS_BARRIER 1
 #endif
@@ -271,6 +268,9 @@ struct Dec {
   }
 };
 
+// x lowered from cur to h: its neighbour w valued v with cur >= v > h no
+// longer counts toward c(w).  No value is returned (nothing waits): which
+// vertices became due is read from the counts before the next half.
 __device__ __forceinline__ void uncount(const Dec &dec, int32_t w, int32_t v, int32_t cur,
                                         int32_t h) {
   if (v <= cur && v > h) dec(w);
