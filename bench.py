@@ -357,6 +357,27 @@ def _gcc_bytes(n: int, q: dict) -> int:
     return 8 * n + n // 8 + 16 * q["removed"] + 4 * q["removed_degree_sum"] + 8 * q["m_peeled"]
 
 
+def _core_split(report) -> dict:
+    """Where a core decomposition spent its time: the levels peeled before
+    the switch to the h-index fixpoint, and that fixpoint (host wall clock
+    of each phase, both zero when the levels finished the job alone)."""
+    return {"levels_ms": report["core_levels_ms"], "hindex_ms": report["core_top_ms"],
+            "hindex": report["core_top"]}
+
+
+def _core_warm(pkg, torch, g):
+    """The core decomposition again on the same handle (the switch option
+    set to its default drops the cached numbers): the first call also pays
+    for the first use of its temporaries' memory, this one does not."""
+    pkg.abcore_set_option(g, pkg.ABCORE_OPT_KCORE_SWITCH, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pkg.abcore_core_numbers(g)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    return ms, _core_split(pkg.abcore_graph_report(g))
+
+
 def _sha_words(t) -> str:
     import hashlib
     return hashlib.sha256(t.cpu().numpy().astype("<u4").tobytes()).hexdigest()
@@ -394,6 +415,8 @@ def bench_sweep(args, pkg, torch, np, bigraph_gen) -> dict:
     _, max_core = pkg.abcore_core_numbers(g)
     torch.cuda.synchronize()
     prep_ms = (time.perf_counter() - t0) * 1e3
+    split = _core_split(pkg.abcore_graph_report(g))
+    warm_ms, warm_split = _core_warm(pkg, torch, g)
     out = torch.empty(g.nwords, dtype=torch.int32, device="cuda")
     ref = torch.empty(g.nwords, dtype=torch.int32, device="cuda")
     rows = []
@@ -434,7 +457,10 @@ def bench_sweep(args, pkg, torch, np, bigraph_gen) -> dict:
         "m": m, "core_preprocessing_ms": prep_ms,
         "core_preprocessing_edges_per_s": m / (prep_ms / 1e3),
         "core_preprocessing_frac": (20 * n + 16 * m) / (prep_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-        "max_core": max_core,
+        "max_core": max_core, "core_split": split,
+        "core_preprocessing_warm_ms": warm_ms, "core_split_warm": warm_split,
+        "core_preprocessing_warm_frac":
+            (20 * n + 16 * m) / (warm_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         "queries": rows, "gcc_plus_total_ms": total_plus,
         "gcc_total_ms": sum(r["gcc_ms"] for r in rows),
         "gcc_plus_pack_bytes": pack_bytes,
@@ -641,6 +667,8 @@ def main() -> int:
         _, max_core = pkg.abcore_core_numbers(g)
         torch.cuda.synchronize()
         prep_ms = (time.perf_counter() - t0) * 1e3
+        split = _core_split(pkg.abcore_graph_report(g))
+        warm_ms, warm_split = _core_warm(pkg, torch, g)
         for _ in range(args.warmup):
             pkg.abcore_compute(g, alpha, beta, pkg.ABCORE_GCC_PLUS, out=out)
         torch.cuda.synchronize()
@@ -658,6 +686,8 @@ def main() -> int:
                     "pack_GBs": pack_bytes / (plus_ms / 1e3) / 1e9,
                     "pack_frac": pack_bytes / (plus_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                     "core_preprocessing_ms": prep_ms, "max_core": max_core,
+                    "core_split": split,
+                    "core_preprocessing_warm_ms": warm_ms, "core_split_warm": warm_split,
                     "edges_peeled_per_s_incl_preprocessing":
                         m_peeled / ((prep_ms + plus_ms) / 1e3)}
         # Algorithm 2 with alpha != beta (uncertain vertices are peeled),

@@ -209,6 +209,10 @@ struct Graph {
   PeelState *h_state = nullptr;  // pinned host mirror
   int64_t *h_part = nullptr;     // pinned host mirror of part
   int32_t *core = nullptr;  // cached core numbers
+  uint32_t *kdead = nullptr;  // n bits: vertices the level peel has removed
+  // the h-index phase's buffers (hipMalloc), kept for the next decomposition
+  void *top_buf[20] = {};
+  size_t top_cap[20] = {};
   bool core_valid = false;
   int32_t max_core = 0;
   // Rows longer than kPiece entries are split into pieces of kPiece entries
@@ -344,6 +348,10 @@ struct PeelArgs {
   const int32_t *ins_next;
   const int32_t *ins_other;
   int32_t *core;            // kKCore: output core numbers
+  // kKCore (nullable): a bit per removed vertex, set when the peel takes it;
+  // decrements of a vertex found removed are skipped (a bit still clear
+  // only costs the decrement)
+  uint32_t *kdead;
   const int32_t *piece_row;
   const int64_t *piece_start;
   const int32_t *piece_first;
@@ -414,7 +422,7 @@ PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL);
 // the library-wide current and peak byte counts (abcore_device_memory) and
 // apply the budget (abcore_set_memory_budget).  Memory a handle keeps comes
 // from hipMalloc; temporaries of one call (sort keys, scan storage, the
-// compacted deep core) are stream-ordered on the caller's stream
+// deep core's rows) are stream-ordered on the caller's stream
 // (hipMallocAsync / hipFreeAsync), so freeing them waits for nothing.
 hipError_t dev_malloc_bytes(void **p, size_t bytes);
 template <class T>

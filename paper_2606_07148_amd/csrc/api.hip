@@ -261,8 +261,10 @@ void free_graph(Graph *g) {
                   g->rcols,       g->rank_vtx,    g->roff,        g->rp_row,
                   g->rp_start,    g->rp_first,    g->rdeg,        g->state_alt,
                   g->part_alt,    g->rs_fail,     g->aux,         g->probe_bits,
-                  g->dbg_enqueue};
+                  g->dbg_enqueue, g->kdead};
   for (void *p : bufs)
+    if (p) (void)dev_free(p);
+  for (void *p : g->top_buf)
     if (p) (void)dev_free(p);
   if (g->h_abort) (void)hipHostFree(g->h_abort);
   if (g->h_state) (void)hipHostFree(g->h_state);
@@ -446,6 +448,7 @@ abcore_status compute_core(Graph &g, hipStream_t s) {
   TRY(ensure(&g.core, g.n));
   TRY(ensure(&g.list, g.n));
   TRY(ensure(&g.list2, g.n));
+  TRY(ensure(&g.kdead, (g.n + 31) / 32));
   CHK(launch_kcore_init(g, s));
   g.kcore_top_used = false;
   for (int64_t &v : g.top_stats) v = 0;

@@ -1,9 +1,9 @@
 // Device construction of the unified CSR (Sec. III: CSR storage; Sec. IV-A:
 // contiguous ids, upper first).  Pairs are keyed (u*nL + v), radix-sorted
 // and deduplicated (E is a set); the sorted keys give the upper rows
-// directly, a second sort on (v*nU + u) gives the lower rows.  Both sorts use
-// rocPRIM's device radix sort through hipCUB; the build is preprocessing and
-// is not part of the timed peel.
+// directly, a second sort on (v*nU + u) gives the lower rows.  Both sorts are
+// rocPRIM's device radix sort, called directly (prim.h); the build is
+// preprocessing and is not part of the timed peel.
 #include "prim.h"
 
 #include <algorithm>

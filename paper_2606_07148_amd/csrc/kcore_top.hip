@@ -55,6 +55,9 @@ constexpr int kRegSpan = 8;    // rows of at most 8 x 64 entries keep their valu
 #ifndef ABC_TOP_LONG_ROW
 #define ABC_TOP_LONG_ROW 2048
 #endif
+#ifndef ABC_TOP_FILL_PARTS
+#define ABC_TOP_FILL_PARTS 1
+#endif
 #ifndef ABC_TOP_UNROLL_BLOCK
 #define ABC_TOP_UNROLL_BLOCK 4
 #endif
@@ -212,6 +215,114 @@ __global__ __launch_bounds__(kBlock) void top_fill_kernel(
       hlen[j] = d;
       est[j] = d;
     }
+  }
+}
+
+// The same rows built in id ranges of the other layer, one range per XCD.
+// A neighbour's rank word and local id are random reads; in one walk every
+// XCD reads all of rk and perm (17.5 MB and 3 MB at 10^9 edges), more than
+// its 4 MB L2, while a range's slice of each fits.  Workgroup b takes range
+// b % kParts (the dispatcher deals workgroups to the XCDs in turn; any
+// other placement is still correct, only slower).  Needs rows sorted by
+// neighbour id with no tombstones and no inserted edges: a graph unchanged
+// since the build.
+constexpr int kParts = 8;
+
+// pos[j * (kParts + 1) + p]: the CSR position of row j's first entry in
+// range p (ranges of span ids over the other layer; entry kParts is the
+// row's end).  One wave per row; lane p binary-searches range p's start.
+__global__ __launch_bounds__(kBlock) void top_bounds_kernel(
+    const int64_t *__restrict__ off, const int32_t *__restrict__ cols,
+    const int32_t *__restrict__ hv, int64_t h, int32_t nU, int32_t spanU, int32_t spanL,
+    int64_t *__restrict__ pos) {
+  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wave_in_block();
+  const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
+  const int lane = lane_id();
+  for (int64_t j = gw; j < h; j += nw) {
+    if (lane > kParts) continue;
+    const int32_t x = hv[j];
+    const int64_t b = off[x], e = off[x + 1];
+    int64_t lo = b;
+    if (lane == kParts) {
+      lo = e;
+    } else if (lane > 0) {
+      // upper rows hold lower ids [nU, n), lower rows upper ids [0, nU)
+      const int64_t first = x < nU ? (int64_t)nU + (int64_t)lane * spanL : (int64_t)lane * spanU;
+      int64_t hi = e;
+      while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if ((int64_t)cols[mid] < first)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+    }
+    pos[j * (kParts + 1) + lane] = lo;
+  }
+}
+
+// Row j's live neighbours in range p as local ids, appended to the row in
+// any order (the h-index phase reads a row as a set): one reservation on
+// hlen[j] per step of kUnroll x 64 entries.  hlen starts at zero; the
+// entries past the row's capacity are counted, not written.
+__global__ __launch_bounds__(kBlock) void top_fill_parts_kernel(
+    const int32_t *__restrict__ cols, const uint2 *__restrict__ rk,
+    const int32_t *__restrict__ perm, int64_t h, const int64_t *__restrict__ pos,
+    const int64_t *__restrict__ hoff, int32_t *__restrict__ hcols, int32_t *__restrict__ hlen) {
+  const int part = (int)(blockIdx.x % kParts);
+  const int64_t gw = (int64_t)(blockIdx.x / kParts) * kWavesPerBlock + wave_in_block();
+  const int64_t nw = (int64_t)(gridDim.x / kParts) * kWavesPerBlock;
+  for (int64_t j = gw; j < h; j += nw) {
+    const int64_t b = pos[j * (kParts + 1) + part], e = pos[j * (kParts + 1) + part + 1];
+    const int64_t r0 = hoff[j], cap = hoff[j + 1] - r0;
+    int32_t *row = hcols + r0;
+    for (int64_t j0 = b; j0 < e; j0 += (int64_t)kUnroll * kWave) {
+      int32_t w[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t k = j0 + u * kWave + lane_id();
+        w[u] = k < e ? cols[k] : -1;
+      }
+      uint2 word[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) word[u] = w[u] >= 0 ? rk[w[u] >> 5] : make_uint2(0, 0);
+      uint64_t mask[kUnroll];
+      int total = 0;
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        mask[u] = __ballot(w[u] >= 0 && ((word[u].x >> (w[u] & 31)) & 1u));
+        total += (int)__popcll(mask[u]);
+      }
+      if (total == 0) continue;
+      int at = 0;
+      if (lane_id() == 0) at = atomicAdd(&hlen[j], total);
+      int64_t r = __shfl(at, 0, kWave);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const bool on = (mask[u] >> lane_id()) & 1ull;
+        const int64_t q = r + (int64_t)__popcll(mask[u] & lanemask_lt());
+        if (on && q < cap) row[q] = perm[id_rank(word[u], w[u])];
+        r += (int64_t)__popcll(mask[u]);
+      }
+    }
+  }
+}
+
+// Row lengths after top_fill_parts_kernel: clamped to the capacity (a
+// longer row sets *overflow), and the starting values.
+__global__ void top_len_kernel(const int64_t *__restrict__ hoff, int64_t h,
+                               int32_t *__restrict__ hlen, int32_t *__restrict__ est,
+                               int32_t *overflow) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < h; j += stride) {
+    const int64_t cap = hoff[j + 1] - hoff[j];
+    int32_t d = hlen[j];
+    if (d > cap) {
+      atomicExch(overflow, 1);
+      d = (int32_t)cap;
+    }
+    hlen[j] = d;
+    est[j] = d;
   }
 }
 
@@ -674,6 +785,33 @@ int grid_of(const Graph &g, int64_t items, int per_block) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, std::min(g.cu_count * 8, kMaxBlocks)));
 }
 
+// The phase's buffers stay with the handle for the next decomposition and
+// grow when short, so a repeated decomposition allocates and frees nothing
+// (freeing the gigabytes of one call cost about 4 ms at 10^9 edges).  A
+// buffer that must grow is freed first; hipFree waits for the device.
+template <class T>
+hipError_t keep(Graph &g, int slot, T **p, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 16);
+  if (g.top_cap[slot] < bytes) {
+    if (g.top_buf[slot] != nullptr) {
+      (void)dev_free(g.top_buf[slot]);
+      g.top_buf[slot] = nullptr;
+      g.top_cap[slot] = 0;
+    }
+    void *q = nullptr;
+    const hipError_t e = dev_malloc_bytes(&q, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();  // the caller falls back; later checks must not see it
+      *p = nullptr;
+      return e;
+    }
+    g.top_buf[slot] = q;
+    g.top_cap[slot] = bytes;
+  }
+  *p = static_cast<T *>(g.top_buf[slot]);
+  return hipSuccess;
+}
+
 }  // namespace
 
 // After the levels below k0 (every vertex of core < k0 has its value; the
@@ -690,7 +828,7 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
   int32_t *hlen = nullptr, *cntv = nullptr, *lists = nullptr, *list_len = nullptr;
   uint32_t *live = nullptr;
   uint64_t *keys = nullptr, *keys2 = nullptr;
-  int64_t *cap = nullptr, *hoff = nullptr;
+  int64_t *cap = nullptr, *hoff = nullptr, *pos = nullptr;
   void *temp = nullptr;
   size_t temp_bytes = 0;
   int32_t hc[3] = {0, 0, 0};
@@ -703,13 +841,13 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
   auto ok = [](hipError_t e) { return e == hipSuccess; };
   do {
     // ctr: [0] live count, [1] upper-layer count, [2] overflow, [3] maximum
-    if (!ok(dev_malloc_async(&wcount, sizeof(int64_t) * (words + 1), s)) ||
-        !ok(dev_malloc_async(&wpre, sizeof(int64_t) * (words + 1), s)) ||
-        !ok(dev_malloc_async(&rk, sizeof(uint2) * std::max<int64_t>(words, 1), s)) ||
-        !ok(dev_malloc_async(&hv, sizeof(int32_t) * std::max<int64_t>(cnt, 1), s)) ||
-        !ok(dev_malloc_async(&live, sizeof(uint32_t) * std::max<int64_t>(words, 1), s)) ||
-        !ok(dev_malloc_async(&ctr, sizeof(int32_t) * 4, s)) ||
-        !ok(dev_malloc_async(&list_len, sizeof(int32_t) * 2 * (max_halves + 2), s))) {
+    if (!ok(keep(g, 0, &wcount, sizeof(int64_t) * (words + 1))) ||
+        !ok(keep(g, 1, &wpre, sizeof(int64_t) * (words + 1))) ||
+        !ok(keep(g, 2, &rk, sizeof(uint2) * std::max<int64_t>(words, 1))) ||
+        !ok(keep(g, 3, &hv, sizeof(int32_t) * std::max<int64_t>(cnt, 1))) ||
+        !ok(keep(g, 4, &live, sizeof(uint32_t) * std::max<int64_t>(words, 1))) ||
+        !ok(keep(g, 5, &ctr, sizeof(int32_t) * 4)) ||
+        !ok(keep(g, 6, &list_len, sizeof(int32_t) * 2 * (max_halves + 2)))) {
       st = ABCORE_ENOMEM;
       break;
     }
@@ -727,18 +865,18 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
       break;
     h = hc[0];
     const int32_t hU = hc[1];
-    if (!ok(dev_malloc_async(&keys, sizeof(uint64_t) * std::max<int64_t>(h, 1), s)) ||
-        !ok(dev_malloc_async(&keys2, sizeof(uint64_t) * std::max<int64_t>(h, 1), s)) ||
-        !ok(dev_malloc_async(&cap, sizeof(int64_t) * (h + 1), s)) ||
-        !ok(dev_malloc_async(&hoff, sizeof(int64_t) * (h + 1), s)) ||
-        !ok(dev_malloc_async(&hlen, sizeof(int32_t) * std::max<int64_t>(h, 1), s)) ||
-        !ok(dev_malloc_async(&est, sizeof(int32_t) * std::max<int64_t>(h, 1), s)) ||
-        !ok(dev_malloc_async(&cntv, sizeof(int32_t) * std::max<int64_t>(h, 1), s)) ||
-        !ok(dev_malloc_async(&lists, sizeof(int32_t) * std::max<int64_t>(h, 1), s))) {
+    if (!ok(keep(g, 7, &keys, sizeof(uint64_t) * std::max<int64_t>(h, 1))) ||
+        !ok(keep(g, 8, &keys2, sizeof(uint64_t) * std::max<int64_t>(h, 1))) ||
+        !ok(keep(g, 9, &cap, sizeof(int64_t) * (h + 1))) ||
+        !ok(keep(g, 10, &hoff, sizeof(int64_t) * (h + 1))) ||
+        !ok(keep(g, 11, &hlen, sizeof(int32_t) * std::max<int64_t>(h, 1))) ||
+        !ok(keep(g, 12, &est, sizeof(int32_t) * std::max<int64_t>(h, 1))) ||
+        !ok(keep(g, 13, &cntv, sizeof(int32_t) * std::max<int64_t>(h, 1))) ||
+        !ok(keep(g, 14, &lists, sizeof(int32_t) * std::max<int64_t>(h, 1)))) {
       st = ABCORE_ENOMEM;
       break;
     }
-    if (!ok(dev_malloc_async(&perm, sizeof(int32_t) * std::max<int64_t>(h, 1), s))) {
+    if (!ok(keep(g, 15, &perm, sizeof(int32_t) * std::max<int64_t>(h, 1)))) {
       st = ABCORE_ENOMEM;
       break;
     }
@@ -753,7 +891,7 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
         !ok(prim::exclusive_sum(nullptr, wscan_bytes, wcount, wpre, (size_t)(words + 1), s)))
       break;
     temp_bytes = std::max<size_t>({sort_bytes, scan_bytes, wscan_bytes, 16});
-    if (!ok(dev_malloc_async(&temp, temp_bytes, s))) {
+    if (!ok(keep(g, 16, &temp, temp_bytes))) {
       st = ABCORE_ENOMEM;
       break;
     }
@@ -777,11 +915,30 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
     if (!ok(hipMemcpyAsync(&eh, hoff + h, sizeof(int64_t), hipMemcpyDeviceToHost, s)) ||
         !ok(hipStreamSynchronize(s)))
       break;
-    if (!ok(dev_malloc_async(&hcols, sizeof(int32_t) * std::max<int64_t>(eh, 1), s))) {
+    if (!ok(keep(g, 17, &hcols, sizeof(int32_t) * std::max<int64_t>(eh, 1)))) {
       st = ABCORE_ENOMEM;
       break;
     }
-    if (h > 0) {
+    // rows by id ranges, one per XCD, on a graph unchanged since the build
+    // (sorted rows); otherwise, or without room for the range bounds, one
+    // walk per row
+    bool parts = false;
+    if (ABC_TOP_FILL_PARTS && h > 0 && g.version == 0 && g.delta.count == 0) {
+      parts = ok(keep(g, 18, &pos, sizeof(int64_t) * h * (kParts + 1)));
+      if (!parts) (void)hipGetLastError();  // the fallback needs no memory
+    }
+    if (parts) {
+      const int64_t nU = g.nU, nL = g.n - g.nU;
+      const int32_t spanU = (int32_t)(((nU + kParts - 1) / kParts + 31) / 32 * 32);
+      const int32_t spanL = (int32_t)(((nL + kParts - 1) / kParts + 31) / 32 * 32);
+      top_bounds_kernel<<<grid_of(g, h * kWave, kBlock), kBlock, 0, s>>>(
+          g.off, g.cols, hv, h, g.nU, spanU, spanL, pos);
+      if (!ok(hipGetLastError()) || !ok(hipMemsetAsync(hlen, 0, sizeof(int32_t) * h, s))) break;
+      const int pg = std::max(kParts, grid_of(g, h * kWave * kParts, kBlock) / kParts * kParts);
+      top_fill_parts_kernel<<<pg, kBlock, 0, s>>>(g.cols, rk, perm, h, pos, hoff, hcols, hlen);
+      top_len_kernel<<<grid_of(g, h, kBlock), kBlock, 0, s>>>(hoff, h, hlen, est, ctr + 2);
+      if (!ok(hipGetLastError())) break;
+    } else if (h > 0) {
       top_fill_kernel<<<grid_of(g, h * kWave, kBlock), kBlock, 0, s>>>(
           g.off, g.cols, ih, g.delta.next, g.delta.other, rk, hv, perm, h, hoff, hcols, hlen,
           est, ctr + 2);
@@ -861,10 +1018,6 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
     *finished = true;
     st = ABCORE_OK;
   } while (0);
-  for (void *p : {(void *)perm, (void *)wcount, (void *)wpre, (void *)rk, (void *)hv, (void *)hcols, (void *)est, (void *)ctr, (void *)hlen,
-                  (void *)hoff, (void *)cap, (void *)keys, (void *)keys2, (void *)cntv,
-                  (void *)lists, (void *)list_len, (void *)live, temp})
-    if (p) (void)dev_free_async(p, s);
   if (st == ABCORE_ENOMEM) set_error("core numbers: the h-index phase is out of memory");
   else if (st != ABCORE_OK) set_error("%s", why);
   return st;

@@ -132,6 +132,7 @@ PeelArgs make_args(Graph &g, int32_t thrU, int32_t thrL) {
   a.ins_next = g.delta.next;
   a.ins_other = g.delta.other;
   a.core = g.core;
+  a.kdead = nullptr;
   a.piece_row = g.piece_row;
   a.piece_start = g.piece_start;
   a.piece_first = g.piece_first;
@@ -780,6 +781,8 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
   int d;
   bool first;
   decode_item(a, x, row, s, d, first);
+  if (KIND == kKCore && a.kdead != nullptr && x >= 0)
+    atomicOr(&a.kdead[x >> 5], 1u << (x & 31));  // taken once: removed from here on
   if (LAZY && a.pack_vtx != nullptr && a.pack_bits != nullptr && x >= 0) {
     // rank order: the result bitmask holds the scan's survivors; a removed
     // vertex is taken here exactly once (its rank), so its bit is cleared
@@ -854,6 +857,15 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
       // one round trip instead of a load followed by an atomic
       dw[u] = w[u] >= 0 ? (KIND == kGCCPlus ? a.deg[w[u]] : kMaxThreshold) : -1;
     }
+    // core numbers: a neighbour removed before (at an earlier level, or
+    // taken already at this one) needs no decrement; its bit is read from a
+    // small bitmap, ahead of the atomics
+    uint32_t gone[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      gone[u] = (KIND == kKCore && a.kdead != nullptr && w[u] >= 0)
+                    ? (a.kdead[w[u] >> 5] >> (w[u] & 31)) & 1u
+                    : 0u;
     bool push[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
@@ -868,6 +880,7 @@ __device__ __forceinline__ void peel_batch(const PeelArgs &a, int32_t x, int32_t
       // in rank order the scan's survivors are a prefix of each layer
       if (KIND == kGCC && a.klim_u >= 0)
         live = live && (w[u] < a.nU ? w[u] < a.klim_u : w[u] - a.nU < a.klim_l);
+      if (KIND == kKCore) live = live && gone[u] == 0;
       push[u] = live && atomicSub(&a.deg[deg_slot(a, w[u])], 1) == t[u];
     }
 #pragma unroll
@@ -2403,12 +2416,17 @@ hipError_t launch_restricted_init(Graph &g, int32_t thrU, int32_t thrL, int32_t 
 
 __global__ void kcore_init_kernel(const int32_t *__restrict__ deg0, int32_t *__restrict__ deg,
                                   int32_t *__restrict__ core, int32_t *__restrict__ alive,
-                                  PeelState *st, int64_t n) {
+                                  uint32_t *__restrict__ dead, PeelState *st, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
     deg[x] = deg0[x];
     core[x] = -1;
     alive[x] = (int32_t)x;
+  }
+  if (dead != nullptr) {
+    const int64_t words = (n + 31) / 32;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+      dead[i] = 0;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->alive_cur = (int32_t)n;
@@ -2423,7 +2441,7 @@ hipError_t launch_kcore_init(Graph &g, hipStream_t s) {
   hipError_t e = launch_init_state(g, s);
   if (e != hipSuccess) return e;
   kcore_init_kernel<<<flat_grid(g, g.n, kBlock), kBlock, 0, s>>>(g.deg0, g.deg, g.core, g.list,
-                                                                 g.state, g.n);
+                                                                 g.kdead, g.state, g.n);
   return hipGetLastError();
 }
 
@@ -2753,8 +2771,12 @@ __global__ __launch_bounds__(kScanBlock) void kcore_level_scan_kernel(PeelArgs a
   }
 }
 
+#ifndef ABC_KCORE_DEAD_BITS
+#define ABC_KCORE_DEAD_BITS 1
+#endif
 hipError_t launch_kcore_levels(Graph &g, int levels, hipStream_t s) {
   PeelArgs a = make_args(g, 0, 0);
+  if (ABC_KCORE_DEAD_BITS) a.kdead = g.kdead;
   const int sgrid = std::min(g.cu_count * 4, kMaxBlocks);
   const int agrid = async_peel_grid(g);
   for (int l = 0; l < levels; ++l) {

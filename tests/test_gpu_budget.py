@@ -188,33 +188,41 @@ def test_deadline_drops_queries_but_applies_updates(deadline_us):
 
 
 def test_core_numbers_without_room_for_the_hindex_phase():
-    """The h-index phase of the core decomposition allocates temporaries of
-    the deep core's size; under a budget that leaves no room for them, the
-    level peel finishes the decomposition instead and the core numbers
-    still equal the oracle's (Definition 2)."""
+    """The h-index phase of the core decomposition needs buffers of the deep
+    core's size, which the handle keeps for later decompositions; under a
+    budget that leaves room for the per-vertex arrays only, the level peel
+    finishes the decomposition instead and the core numbers still equal the
+    oracle's (Definition 2).  Later, without the budget, the phase runs on
+    the updated graph and agrees with the oracle again."""
     spec = bigraph_gen.scaled(2, 0.05)
     nU, nL = spec["n_upper"], spec["n_lower"]
+    n = nU + nL
     eu, ev = bigraph_gen.make_graph(spec)
     g = pkg.abcore_build_csr(nU, nL, to_dev(eu), to_dev(ev))
     try:
         pkg.abcore_set_option(g, pkg.ABCORE_OPT_KCORE_SWITCH, 1 << 30)
-        # the first decomposition allocates the persistent arrays and uses
-        # the h-index phase
-        pkg.abcore_core_numbers(g)
-        assert pkg.abcore_graph_report(g)["core_top"]["vertices"] > 0
-        # an update changes the graph, so the next call decomposes again
+        # core numbers, two alive lists and the removed bitmap (the arrays
+        # every decomposition allocates on first use), and 1 KiB more
+        arrays = 3 * 4 * n + 4 * ((n + 31) // 32)
+        now, _ = pkg.abcore_device_memory()
+        pkg.abcore_set_memory_budget(now + arrays + 1024)
+        say("budget: core numbers with room for the per-vertex arrays only")
+        core, mx = pkg.abcore_core_numbers(g)
+        pkg.abcore_set_memory_budget(0)
+        assert pkg.abcore_graph_report(g)["core_top"]["vertices"] == 0
+        want = oracle.core_numbers(oracle.Graph(nU, nL, eu, ev))
+        assert np.array_equal(core.cpu().numpy(), want)
+        assert mx == int(want.max())
+        # an update changes the graph, so the next call decomposes again,
+        # now with the h-index phase
         u, v = 0, 0
         present = set(zip(eu.tolist(), ev.tolist()))
         while (u, v) in present:
             v += 1
         pkg.abcore_query(g, u, v, 1, 2, 2)
         present.add((u, v))
-        now, _ = pkg.abcore_device_memory()
-        pkg.abcore_set_memory_budget(now + 1024)
-        say("budget: core numbers with 1 KiB to spare")
         core, mx = pkg.abcore_core_numbers(g)
-        pkg.abcore_set_memory_budget(0)
-        assert pkg.abcore_graph_report(g)["core_top"]["vertices"] == 0
+        assert pkg.abcore_graph_report(g)["core_top"]["vertices"] > 0
         pe = np.array(sorted(present), np.int32)
         want = oracle.core_numbers(oracle.Graph(nU, nL, pe[:, 0], pe[:, 1]))
         assert np.array_equal(core.cpu().numpy(), want)
