@@ -219,6 +219,10 @@ abcore_status abcore_batch_plan(const uint32_t *h_alpha, const uint32_t *h_beta,
  * (delta,delta)-core, 0 for isolated vertices.  Computed once per graph
  * version and cached for GCC+.  d_core: DEVICE n int32, or NULL to only fill
  * the cache.  max_core (nullable): largest core number (delta of Table I).
+ * The handle keeps the buffers of the decomposition's deep part (the k0-core's
+ * rows, about 4 GB at 10^9 edges) for the next decomposition, until it is
+ * destroyed; they count in abcore_device_memory.  Under a memory budget
+ * that leaves no room for them the levels finish the decomposition alone.
  * Synchronous. */
 abcore_status abcore_core_numbers(abcore_graph g, int32_t *d_core, int32_t *max_core,
                                   void *stream);

@@ -227,6 +227,11 @@ __global__ __launch_bounds__(kBlock) void top_fill_kernel(
 // neighbour id with no tombstones and no inserted edges: a graph unchanged
 // since the build.
 constexpr int kParts = 8;
+// Rows of fewer entries on average are filled by one walk each: a range of
+// a short row is a few entries behind a chain of dependent loads (at 48
+// entries per row the ranges took 3.4 ms where the row walk took 0.6 ms;
+// at 1,190 they took 8.9 ms where it took 11.6 ms).
+constexpr int kPartsMinRow = 512;
 
 // pos[j * (kParts + 1) + p]: the CSR position of row j's first entry in
 // range p (ranges of span ids over the other layer; entry kParts is the
@@ -920,10 +925,11 @@ abcore_status kcore_top(Graph &g, const int32_t *alive, int64_t cnt, int32_t k0,
       break;
     }
     // rows by id ranges, one per XCD, on a graph unchanged since the build
-    // (sorted rows); otherwise, or without room for the range bounds, one
-    // walk per row
+    // (sorted rows) whose deep core's rows are long; otherwise, or without
+    // room for the range bounds, one walk per row
     bool parts = false;
-    if (ABC_TOP_FILL_PARTS && h > 0 && g.version == 0 && g.delta.count == 0) {
+    if (ABC_TOP_FILL_PARTS && h > 0 && g.version == 0 && g.delta.count == 0 &&
+        eh >= (int64_t)kPartsMinRow * h) {
       parts = ok(keep(g, 18, &pos, sizeof(int64_t) * h * (kParts + 1)));
       if (!parts) (void)hipGetLastError();  // the fallback needs no memory
     }

@@ -523,6 +523,42 @@ def test_core_numbers_hindex_layers_past_the_lds_cache():
     g.destroy()
 
 
+def test_core_numbers_hindex_long_rows_by_id_ranges():
+    """A dense graph whose deep core's rows average over 512 entries: on a
+    graph unchanged since the build the h-index phase fills those rows by
+    id ranges of the other layer, one range per XCD (ranges of 160 ids here,
+    the last ones ragged or empty, rows appended in any order).  Core
+    numbers equal the oracle's (Definition 2); after an update the same
+    graph takes the one-walk-per-row fill and agrees again."""
+    nU, nL = 1201, 1187
+    m = int(0.45 * nU * nL)
+    eu, ev = bigraph_gen.make_graph(dict(kind="uniform", n_upper=nU, n_lower=nL, m=m, seed=91))
+    g, ref = _make(nU, nL, eu, ev)
+    try:
+        pkg.abcore_set_option(g, pkg.ABCORE_OPT_KCORE_SWITCH, 1 << 30)
+        core, mx = pkg.abcore_core_numbers(g)
+        top = pkg.abcore_graph_report(g)["core_top"]
+        say(f"long rows: {top}, max core {mx}")
+        assert top["vertices"] > 0 and top["entries"] >= 512 * top["vertices"], top
+        want = oracle.core_numbers(ref)
+        assert np.array_equal(core.cpu().numpy(), want)
+        assert mx == int(want.max())
+        present = set(zip(eu.tolist(), ev.tolist()))
+        u, v = 0, 0
+        while (u, v) in present:
+            v += 1
+        pkg.abcore_query(g, u, v, 1, 2, 2)
+        present.add((u, v))
+        core, mx = pkg.abcore_core_numbers(g)
+        assert pkg.abcore_graph_report(g)["core_top"]["vertices"] > 0
+        pe = np.array(sorted(present), np.int32)
+        want = oracle.core_numbers(oracle.Graph(nU, nL, pe[:, 0], pe[:, 1]))
+        assert np.array_equal(core.cpu().numpy(), want)
+        assert mx == int(want.max())
+    finally:
+        g.destroy()
+
+
 def test_core_numbers_hindex_wide_ranges():
     """Rows whose value range exceeds 16 bits in the h-index phase: ten
     lower vertices adjacent to 80,000 upper vertices (degree 80,000, core
