@@ -29,9 +29,11 @@
 // the first 63,488 values of the layer a half reads in LDS (16 bits each,
 // offsets from k0), and only entries past them read the values array.  Rows
 // are written at offsets given by the vertices' degrees in G (an upper
-// bound of their degrees in H), so the adjacency is built in one walk; a
-// neighbour's local id comes from its rank among the live vertices in id
+// bound of their degrees in H), so the adjacency is built in one pass over
+// the rows (long rows by id ranges of the other layer, one range per XCD);
+// a neighbour's local id comes from its rank among the live vertices in id
 // order (a live bitmap with per-word prefix counts) through a permutation.
+// The phase's buffers stay with the handle for the next decomposition.
 #include <algorithm>
 #include <vector>
 
