@@ -523,6 +523,36 @@ def test_core_numbers_hindex_layers_past_the_lds_cache():
     g.destroy()
 
 
+def test_core_numbers_hindex_buffers_kept_and_grown():
+    """The handle keeps the h-index phase's buffers between decompositions:
+    switch points that give a small, a large, a small and again a large
+    deep core make them grow once and then serve smaller and equal deep
+    cores as they are.  Every decomposition equals the oracle's core numbers
+    (Definition 2), and destroying the handle returns every byte."""
+    spec = bigraph_gen.scaled(2, 0.05)
+    nU, nL = spec["n_upper"], spec["n_lower"]
+    eu, ev = bigraph_gen.make_graph(spec)
+    before, _ = pkg.abcore_device_memory()
+    g, ref = _make(nU, nL, eu, ev)
+    want = oracle.core_numbers(ref)
+    sizes = []
+    try:
+        for switch in (1 << 13, 1 << 30, 1 << 13, 1 << 30):
+            pkg.abcore_set_option(g, pkg.ABCORE_OPT_KCORE_SWITCH, switch)
+            core, mx = pkg.abcore_core_numbers(g)
+            top = pkg.abcore_graph_report(g)["core_top"]
+            say(f"kept buffers, switch {switch}: {top}, {pkg.abcore_device_memory()[0]} bytes")
+            assert np.array_equal(core.cpu().numpy(), want), switch
+            assert mx == int(want.max())
+            sizes.append((top["vertices"], pkg.abcore_device_memory()[0]))
+        assert 0 < sizes[0][0] < sizes[1][0], sizes
+        # the small deep core again fits the grown buffers: no allocation
+        assert sizes[2][1] == sizes[1][1] == sizes[3][1], sizes
+    finally:
+        g.destroy()
+    assert pkg.abcore_device_memory()[0] == before
+
+
 def test_core_numbers_hindex_long_rows_by_id_ranges():
     """A dense graph whose deep core's rows average over 512 entries: on a
     graph unchanged since the build the h-index phase fills those rows by
